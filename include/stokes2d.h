@@ -1,0 +1,152 @@
+/*
+ * stokes2d.h -- C ABI of libstokes2d.so: free-space 2D Stokes layer
+ * potentials with periodic near images on MI355X (gfx950).
+ *
+ * What is computed (Marple, Barnett, Gillman, Veerapaneni, "A fast algorithm
+ * for simulating multiphase flows through periodic geometries of arbitrary
+ * shape", arXiv 1510.05616):
+ *
+ *   single layer, Section 2.1 Eq. (S) summed as the imposed flow of
+ *   Section 3.1 Eq. (utotrep):
+ *     u(x) = 1/(4 pi mu) sum_{n=img_lo}^{img_hi} sum_j
+ *            [ -1/2 log|r|^2 I + r r^T / |r|^2 ] w_j f_j,  r = x - y_j - n d e1
+ *
+ *   double layer, Section 2.1 Eq. (D) summed as Eq. (Dnr):
+ *     u(x) = 1/pi sum_{n=img_lo}^{img_hi} sum_j r (r . n_j)(r . tau_j) w_j / |r|^4
+ *
+ * The source nodes carry periodic-trapezoid weights w_j (Section 2.3).  A
+ * target that is node i of source curve c (declared through on_curve and
+ * on_node) is treated as the paper's Nystrom discretisation does:
+ *   - single layer: the n = 0 interaction with its own curve c is replaced by
+ *     Kress's product quadrature for the logarithmic singularity (Section 3.2,
+ *     spectrally accurate Nystrom method with periodic Kress corrections);
+ *     curve c must have an even node count N = 2m with nodes equispaced in a
+ *     smooth parameter, w_k = (2 pi / N) |x'(t_k)|;
+ *   - double layer: the n = 0 term of node i itself is replaced by the
+ *     diagonal limit -(kappa_i / 2 pi) t_i t_i^T tau_i w_i (Section 2.3); the
+ *     result is the principal-value operator D_{Gamma,Gamma}; the caller adds
+ *     the -1/2 tau jump of Eq. (JR) if it wants the interior limit.
+ * With img_lo = -1, img_hi = 1 this is the |n| <= 1 near-image sum of the
+ * paper; img_lo = img_hi = +-1 gives the single far images of the
+ * periodicity blocks (Section 2.2, Eqs. (BIEgu) and (vesU)-(vesgT)).
+ *
+ * Conventions (the paper shows them only in a figure):
+ *   - signed curvature kappa = -(x'' . n) / |x'|^2 (positive on a convex curve
+ *     with outward normal);  normals are taken as given.
+ *
+ * Memory and ownership.  Every array argument is a DEVICE pointer to
+ * caller-owned memory, structure-of-arrays, FP64 (int32 for indices), in
+ * every mode; the mode selects only the internal arithmetic.  The library
+ * never allocates, frees or keeps user memory: scratch comes from the
+ * caller's workspace (size from stokes2d_workspace_size(), 256-byte aligned).
+ * Calls are asynchronous on `stream` (a hipStream_t, or NULL for the null
+ * stream); the caller synchronises.  Two calls that share a workspace must be
+ * ordered on one stream.
+ *
+ * Errors.  Every entry point returns an s2d_status.  Argument checks run on
+ * the host before any launch: a call that fails them launches nothing and
+ * leaves the outputs untouched.  Index contents of device arrays (curve_off,
+ * on_curve, on_node) are not read on the host; a target whose on_curve /
+ * on_node entry is out of range, or that sits on an odd-sized curve in a
+ * single-layer call, gets NaN outputs.  stokes2d_last_error() returns a
+ * message for the calling thread's last failure.
+ */
+#ifndef STOKES2D_H
+#define STOKES2D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define S2D_API __attribute__((visibility("default")))
+
+typedef enum {
+    S2D_OK = 0,
+    S2D_EINVAL = -1,      /* bad argument (NULL pointer, size, image range, mu <= 0, ...) */
+    S2D_EHIP = -2,        /* a HIP runtime call failed */
+    S2D_ENOTSUP = -3,     /* unsupported mode / device */
+    S2D_EWORKSPACE = -4,  /* workspace NULL, too small or misaligned */
+    S2D_ENOINIT = -5      /* stokes2d_init() was not called for the current device */
+} s2d_status;
+
+typedef enum {
+    S2D_FP64 = 0,         /* every pair term in FP64 */
+    S2D_FP32C = 1         /* pair terms in FP32, exact FP64 coordinate differences,
+                             FP32 sub-blocks merged into FP64 accumulators; the own-curve
+                             Kress quadrature and the diagonal limit stay FP64 */
+} s2d_mode;
+
+typedef enum { S2D_OP_SLP = 0, S2D_OP_DLP = 1 } s2d_op;
+
+/* A set of source curves (device pointers).  Curve c owns global nodes
+ * [curve_off[c], curve_off[c+1]). */
+typedef struct s2d_curves {
+    int64_t n_nodes;
+    int32_t n_curves;
+    const int32_t *curve_off;   /* [n_curves + 1], curve_off[0] = 0, curve_off[n_curves] = n_nodes */
+    const double *x, *y;        /* node coordinates */
+    const double *nx, *ny;      /* unit normals: DLP always; SLP only when targets sit on curves */
+    const double *w;            /* trapezoid weights */
+    const double *kappa;        /* signed curvature: DLP with on-curve targets only, else may be NULL */
+    const double *fx, *fy;      /* density: force f (SLP) or double-layer density tau (DLP) */
+} s2d_curves;
+
+/* Target points (device pointers).  on_curve / on_node are both NULL (no
+ * target sits on a source node) or both [n]: on_curve[i] = c >= 0 says target
+ * i IS global source node on_node[i] of curve c (its coordinates must equal
+ * that node's); -1 means a free target. */
+typedef struct s2d_targets {
+    int64_t n;
+    const double *x, *y;
+    const int32_t *on_curve, *on_node;
+} s2d_targets;
+
+/* Selects the device for the calling thread's later calls and sets up the
+ * library's per-device state (device properties, launch tuning table).
+ * Not capturable; call once per device before any evaluation. */
+S2D_API int stokes2d_init(int device);
+
+/* Bytes of workspace an evaluation with these arguments needs (0 on bad
+ * arguments).  op is an s2d_op; mode an s2d_mode. */
+S2D_API size_t stokes2d_workspace_size(int op, int mode, const s2d_curves *src,
+                                       const s2d_targets *trg);
+
+/* Single-layer potential (Stokeslet) of density src->fx, fy at the targets,
+ * summed over source images n = img_lo..img_hi shifted by n * d along x.
+ * Writes u, v ([trg->n] device FP64), or adds to them when accumulate != 0.
+ * Requires mu > 0, img_lo <= img_hi, |img| <= 64, d > 0 if any image is
+ * nonzero.  Pointers in src may be NULL only when their count is 0. */
+S2D_API int stokes2d_slp_eval(int mode, const s2d_curves *src, const s2d_targets *trg,
+                              double d, int32_t img_lo, int32_t img_hi, double mu,
+                              double *u, double *v, int accumulate,
+                              void *ws, size_t ws_bytes, void *stream);
+
+/* Double-layer potential (stresslet, principal value on source curves) of
+ * density src->fx, fy (the paper's tau).  The double-layer velocity kernel has
+ * no viscosity factor (Section 2.1, Eq. (D)). */
+S2D_API int stokes2d_dlp_eval(int mode, const s2d_curves *src, const s2d_targets *trg,
+                              double d, int32_t img_lo, int32_t img_hi,
+                              double *u, double *v, int accumulate,
+                              void *ws, size_t ws_bytes, void *stream);
+
+/* Benchmarking aid (not capturable, not for production loops): while
+ * enabled, each evaluation records a HIP event pair around its pair-sum
+ * kernel launch on the caller's stream.  stokes2d_profile_read() waits for
+ * the recorded events of operation `op` (an s2d_op), returns their summed
+ * elapsed milliseconds and launch count, and releases them. */
+S2D_API int stokes2d_profile_enable(int on);
+S2D_API int stokes2d_profile_read(int op, double *total_ms, int64_t *launches);
+
+/* Message describing the calling thread's last non-OK return. */
+S2D_API const char *stokes2d_last_error(void);
+
+/* Library version: major * 10000 + minor * 100 + patch. */
+S2D_API int stokes2d_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STOKES2D_H */

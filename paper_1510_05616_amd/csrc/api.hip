@@ -1,0 +1,305 @@
+// C ABI of libstokes2d: argument checks, launch planning, workspace carve-up
+// and the launch sequence for each evaluation.  No allocation happens here:
+// all scratch lives in the caller's workspace.
+#include "s2d_internal.h"
+
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+namespace {
+
+thread_local std::string g_err;
+
+struct DevState {
+    bool init = false;
+    int cus = 256;
+};
+constexpr int kMaxDev = 64;
+DevState g_dev[kMaxDev];
+std::mutex g_mu;
+
+// Optional timing of the pair kernels (benchmarking aid, not capturable):
+// while enabled, each evaluation records a start/stop event pair around its
+// pair-kernel launch on the caller's stream.
+struct ProfEvent {
+    int op;
+    hipEvent_t a, b;
+};
+bool g_prof_on = false;
+std::vector<ProfEvent> g_prof;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t rec_bytes(int op, int mode) {
+    if (op == S2D_OP_SLP) return mode == S2D_FP64 ? sizeof(s2d::RecSlp64) : sizeof(s2d::RecSlp32);
+    return mode == S2D_FP64 ? sizeof(s2d::RecDlp64) : sizeof(s2d::RecDlp32);
+}
+
+// Checks that do not depend on the device; returns S2D_OK or an error code
+// with g_err set.
+int check_args(int op, int mode, const s2d_curves *s, const s2d_targets *t, double d, int img_lo,
+               int img_hi, double mu) {
+    if (mode != S2D_FP64 && mode != S2D_FP32C) return fail(S2D_EINVAL, "mode must be S2D_FP64 or S2D_FP32C");
+    if (op != S2D_OP_SLP && op != S2D_OP_DLP) return fail(S2D_EINVAL, "op must be S2D_OP_SLP or S2D_OP_DLP");
+    if (!s || !t) return fail(S2D_EINVAL, "src and trg must not be NULL");
+    if (s->n_nodes < 0 || s->n_nodes > INT32_MAX - 2 * s2d::kSuperBlock)
+        return fail(S2D_EINVAL, "src->n_nodes out of range [0, 2^31 - 513]");
+    if (s->n_curves < 0) return fail(S2D_EINVAL, "src->n_curves < 0");
+    if (t->n < 0) return fail(S2D_EINVAL, "trg->n < 0");
+    if (s->n_nodes > 0) {
+        if (!s->x || !s->y || !s->w || !s->fx || !s->fy)
+            return fail(S2D_EINVAL, "src x, y, w, fx, fy must not be NULL when n_nodes > 0");
+        if (op == S2D_OP_DLP && (!s->nx || !s->ny)) return fail(S2D_EINVAL, "double layer needs src nx, ny");
+    }
+    if (t->n > 0 && (!t->x || !t->y)) return fail(S2D_EINVAL, "trg x, y must not be NULL when n > 0");
+    if ((t->on_curve == nullptr) != (t->on_node == nullptr))
+        return fail(S2D_EINVAL, "trg on_curve and on_node must both be NULL or both be set");
+    if (t->on_curve && t->n > 0) {
+        if (!s->curve_off) return fail(S2D_EINVAL, "on-curve targets need src->curve_off");
+        if (op == S2D_OP_SLP && s->n_nodes > 0 && (!s->nx || !s->ny))
+            return fail(S2D_EINVAL, "single layer with on-curve targets needs src nx, ny");
+        if (op == S2D_OP_DLP && s->n_nodes > 0 && !s->kappa)
+            return fail(S2D_EINVAL, "double layer with on-curve targets needs src kappa");
+    }
+    if (img_lo > img_hi) return fail(S2D_EINVAL, "img_lo > img_hi");
+    if (img_lo < -s2d::kMaxImages || img_hi > s2d::kMaxImages) return fail(S2D_EINVAL, "|image| > 64");
+    if ((img_lo != 0 || img_hi != 0) && !(std::isfinite(d) && d > 0.0))
+        return fail(S2D_EINVAL, "period d must be finite and > 0 when images are used");
+    if (op == S2D_OP_SLP && !(std::isfinite(mu) && mu > 0.0)) return fail(S2D_EINVAL, "mu must be finite and > 0");
+    return S2D_OK;
+}
+
+s2d::Plan make_plan(int op, int mode, const s2d_curves *s, const s2d_targets *t, int cus) {
+    using namespace s2d;
+    Plan p{};
+    p.op = op;
+    p.mode = mode;
+    p.tpt = mode == S2D_FP64 ? 1 : 2;
+    p.n_src = s->n_nodes;
+    p.n_trg = t->n;
+    p.n_sb = (p.n_src + kSuperBlock - 1) / kSuperBlock;
+    p.n_tiles = (p.n_trg + (int64_t)kWave * p.tpt - 1) / ((int64_t)kWave * p.tpt);
+    if (p.n_sb > 0 && p.n_tiles > 0) {
+        const int64_t want_waves = (int64_t)cus * 4 * 8;          // ~8 waves per SIMD
+        int64_t ns = (want_waves + p.n_tiles - 1) / p.n_tiles;
+        if (ns >= 8) ns = (ns + 7) / 8 * 8;                        // XCD-aligned split count
+        ns = std::max<int64_t>(1, std::min<int64_t>(ns, std::min<int64_t>(p.n_sb, 4096)));
+        p.sb_per_split = (p.n_sb + ns - 1) / ns;
+        p.n_splits = (int)((p.n_sb + p.sb_per_split - 1) / p.sb_per_split);
+        p.n_blocks = (int64_t)p.n_splits * ((p.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock);
+    } else {
+        p.sb_per_split = 0;
+        p.n_splits = 0;
+        p.n_blocks = 0;
+    }
+    p.self = false;    // set by the caller once images are known
+    size_t off = 0;
+    p.off_rec = off;
+    off = align256(off + (size_t)p.n_sb * kSuperBlock * rec_bytes(op, mode));
+    p.off_sbsum = off;
+    if (op == S2D_OP_SLP && mode == S2D_FP32C) off = align256(off + (size_t)p.n_sb * 2 * sizeof(double));
+    p.off_part = off;
+    off = align256(off + (size_t)p.n_splits * 2 * (size_t)p.n_trg * sizeof(double));
+    p.off_self = off;
+    p.off_kress = off;
+    if (op == S2D_OP_SLP && t->on_curve && p.n_trg > 0) {
+        off = align256(off + 2 * (size_t)p.n_trg * sizeof(double));
+        p.off_kress = off;
+        off = align256(off + (size_t)p.n_src * sizeof(double));
+    }
+    p.total = off;
+    return p;
+}
+
+int current_device(int *dev) {
+    if (hipGetDevice(dev) != hipSuccess) return fail(S2D_EHIP, "hipGetDevice failed");
+    if (*dev < 0 || *dev >= kMaxDev || !g_dev[*dev].init)
+        return fail(S2D_ENOINIT, "stokes2d_init() was not called for the current device");
+    return S2D_OK;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(S2D_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int eval(int op, int mode, const s2d_curves *src, const s2d_targets *trg, double d, int32_t img_lo,
+         int32_t img_hi, double mu, double *u, double *v, int accumulate, void *ws, size_t ws_bytes,
+         void *stream) {
+    using namespace s2d;
+    int rc = check_args(op, mode, src, trg, d, img_lo, img_hi, mu);
+    if (rc != S2D_OK) return rc;
+    int dev = 0;
+    rc = current_device(&dev);
+    if (rc != S2D_OK) return rc;
+    if (trg->n == 0) return S2D_OK;
+    if (!u || !v) return fail(S2D_EINVAL, "outputs u, v must not be NULL");
+    Plan p = make_plan(op, mode, src, trg, g_dev[dev].cus);
+    const bool img0 = img_lo <= 0 && img_hi >= 0;
+    p.self = op == S2D_OP_SLP && trg->on_curve != nullptr && img0;
+    if (p.total > 0) {
+        if (!ws) return fail(S2D_EWORKSPACE, "workspace is NULL");
+        if (ws_bytes < p.total)
+            return fail(S2D_EWORKSPACE, "workspace too small: need " + std::to_string(p.total) + " bytes");
+        if (((uintptr_t)ws & 255) != 0) return fail(S2D_EWORKSPACE, "workspace must be 256-byte aligned");
+    }
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    if (p.n_sb > 0) {
+        e = launch_prep(p, src, ws, st);
+        if (e != hipSuccess) return hip_fail(e, "prep launch");
+    }
+    if (p.self) {
+        e = launch_kress(p, src, trg, ws, st);
+        if (e != hipSuccess) return hip_fail(e, "kress launch");
+    }
+    PairArgs a{};
+    a.rec = (char *)ws + p.off_rec;
+    a.sbsum = (const double *)((char *)ws + p.off_sbsum);
+    a.n_src = p.n_src;
+    a.tx = trg->x;
+    a.ty = trg->y;
+    a.on_curve = img0 ? trg->on_curve : nullptr;
+    a.on_node = img0 ? trg->on_node : nullptr;
+    a.curve_off = src->curve_off;
+    a.n_curves = src->n_curves;
+    a.n_trg = p.n_trg;
+    a.n_tiles = p.n_tiles;
+    a.n_splits = p.n_splits;
+    a.sb_per_split = p.sb_per_split;
+    a.n_sb = p.n_sb;
+    a.d = d;
+    a.img_lo = img_lo;
+    a.img_hi = img_hi;
+    a.part = (double *)((char *)ws + p.off_part);
+    if (p.n_blocks > 0) {
+        ProfEvent pe{op, nullptr, nullptr};
+        if (g_prof_on) {
+            std::lock_guard<std::mutex> lk(g_mu);
+            if (hipEventCreate(&pe.a) == hipSuccess && hipEventCreate(&pe.b) == hipSuccess) {
+                hipEventRecord(pe.a, st);
+            } else {
+                pe.a = pe.b = nullptr;
+            }
+        }
+        e = launch_pair(p, a, st);
+        if (e != hipSuccess) return hip_fail(e, "pair launch");
+        if (pe.a) {
+            hipEventRecord(pe.b, st);
+            std::lock_guard<std::mutex> lk(g_mu);
+            g_prof.push_back(pe);
+        }
+    }
+    FinalArgs f{};
+    f.part = a.part;
+    f.self = p.self ? (const double *)((char *)ws + p.off_self) : nullptr;
+    f.n_splits = p.n_splits;
+    f.n_trg = p.n_trg;
+    f.n_src = p.n_src;
+    f.pref = op == S2D_OP_SLP ? 1.0 / (4.0 * M_PI * mu) : 1.0 / M_PI;
+    f.accumulate = accumulate ? 1 : 0;
+    f.u = u;
+    f.v = v;
+    // on-curve targets with an empty or inconsistent curve come out NaN
+    f.dlp_diag = op == S2D_OP_DLP && trg->on_curve != nullptr && img0;
+    f.on_curve = trg->on_curve;
+    f.on_node = trg->on_node;
+    f.curve_off = src->curve_off;
+    f.n_curves = src->n_curves;
+    f.nx = src->nx;
+    f.ny = src->ny;
+    f.w = src->w;
+    f.kappa = src->kappa;
+    f.fx = src->fx;
+    f.fy = src->fy;
+    e = launch_final(p, f, st);
+    if (e != hipSuccess) return hip_fail(e, "finalize launch");
+    return S2D_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+S2D_API int stokes2d_init(int device) {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return fail(S2D_EHIP, "no HIP device");
+    if (device < 0 || device >= n || device >= kMaxDev) return fail(S2D_EINVAL, "device index out of range");
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(S2D_ENOTSUP, std::string("libstokes2d is built for gfx950, device is ") + prop.gcnArchName);
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_dev[device].cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    g_dev[device].init = true;
+    return S2D_OK;
+}
+
+S2D_API size_t stokes2d_workspace_size(int op, int mode, const s2d_curves *src, const s2d_targets *trg) {
+    if (check_args(op, mode, src, trg, 1.0, 0, 0, 1.0) != S2D_OK) return 0;
+    int dev = 0;
+    int cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < kMaxDev && g_dev[dev].init) cus = g_dev[dev].cus;
+    s2d::Plan p = make_plan(op, mode, src, trg, cus);
+    return p.total > 0 ? p.total : 256;
+}
+
+S2D_API int stokes2d_slp_eval(int mode, const s2d_curves *src, const s2d_targets *trg, double d, int32_t img_lo,
+                              int32_t img_hi, double mu, double *u, double *v, int accumulate, void *ws,
+                              size_t ws_bytes, void *stream) {
+    return eval(S2D_OP_SLP, mode, src, trg, d, img_lo, img_hi, mu, u, v, accumulate, ws, ws_bytes, stream);
+}
+
+S2D_API int stokes2d_dlp_eval(int mode, const s2d_curves *src, const s2d_targets *trg, double d, int32_t img_lo,
+                              int32_t img_hi, double *u, double *v, int accumulate, void *ws, size_t ws_bytes,
+                              void *stream) {
+    return eval(S2D_OP_DLP, mode, src, trg, d, img_lo, img_hi, 1.0, u, v, accumulate, ws, ws_bytes, stream);
+}
+
+S2D_API int stokes2d_profile_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_prof_on = on != 0;
+    return S2D_OK;
+}
+
+S2D_API int stokes2d_profile_read(int op, double *total_ms, int64_t *launches) {
+    if (!total_ms || !launches) return fail(S2D_EINVAL, "total_ms and launches must not be NULL");
+    std::lock_guard<std::mutex> lk(g_mu);
+    double tot = 0.0;
+    int64_t n = 0;
+    std::vector<ProfEvent> keep;
+    for (auto &pe : g_prof) {
+        if (pe.op != op) {
+            keep.push_back(pe);
+            continue;
+        }
+        float ms = 0.f;
+        hipError_t e = hipEventSynchronize(pe.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, pe.a, pe.b);
+        if (e != hipSuccess) return hip_fail(e, "profile event");
+        tot += ms;
+        ++n;
+        hipEventDestroy(pe.a);
+        hipEventDestroy(pe.b);
+    }
+    g_prof.swap(keep);
+    *total_ms = tot;
+    *launches = n;
+    return S2D_OK;
+}
+
+S2D_API const char *stokes2d_last_error(void) { return g_err.c_str(); }
+
+S2D_API int stokes2d_version(void) { return 100; }
+
+}  // extern "C"

@@ -1,0 +1,80 @@
+// Internal declarations shared by the HIP translation units of libstokes2d.
+// Nothing here is part of the public ABI (include/stokes2d.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/stokes2d.h"
+
+namespace s2d {
+
+constexpr int kWave = 64;            // CDNA wavefront width
+constexpr int kWavesPerBlock = 4;    // pair kernels: 4 independent waves per workgroup
+constexpr int kBlock = kWave * kWavesPerBlock;
+constexpr int kSuperBlock = 256;     // sources per superblock (split granularity, FP32 log reference)
+constexpr int kSubBlock = 8;         // FP32 sub-block merged into the FP64 accumulators
+constexpr int kMaxImages = 64;
+
+// Source records written by the preparation kernels: one wave-uniform record
+// per source, read through the scalar data path by the pair kernels.
+struct alignas(32) RecSlp64 { double x, y, gx, gy; };                 // g = w f
+struct alignas(32) RecSlp32 { double x, y; float gx, gy, lx, ly; };    // l = -ln2/2 * g
+struct alignas(16) RecDlp64 { double x, y, nx, ny, tx, ty; };         // nu = w n, tau
+struct alignas(32) RecDlp32 { double x, y; float nx, ny, tx, ty; };
+
+// One launch's decomposition of (targets x sources).
+struct Plan {
+    int op, mode, tpt;
+    int64_t n_src, n_trg;
+    int64_t n_sb;            // superblocks (sources padded to kSuperBlock)
+    int64_t n_tiles;         // target tiles of kWave * tpt
+    int n_splits;            // source splits (each a whole number of superblocks)
+    int64_t sb_per_split;
+    int64_t n_blocks;        // workgroups of the pair kernel
+    bool self;               // targets carry on_curve/on_node and image 0 is in range
+    // workspace carve-out (byte offsets)
+    size_t off_rec, off_sbsum, off_part, off_self, off_kress, total;
+};
+
+struct PairArgs {
+    const void *rec;
+    const double *sbsum;      // FP32 SLP: per-superblock sum of g (2 doubles each)
+    int64_t n_src;
+    const double *tx, *ty;
+    const int32_t *on_curve, *on_node, *curve_off;
+    int32_t n_curves;
+    int64_t n_trg;
+    int64_t n_tiles;
+    int32_t n_splits;
+    int64_t sb_per_split;
+    int64_t n_sb;
+    double d;
+    int32_t img_lo, img_hi;
+    double *part;             // [n_splits][2][n_trg]
+};
+
+struct FinalArgs {
+    const double *part;
+    const double *self;       // SLP own-curve Kress sums [2][n_trg] or NULL
+    int32_t n_splits;
+    int64_t n_trg;
+    int64_t n_src;
+    double pref;
+    int accumulate;
+    double *u, *v;
+    // DLP diagonal limit
+    int dlp_diag;
+    const int32_t *on_curve, *on_node, *curve_off;
+    int32_t n_curves;
+    const double *nx, *ny, *w, *kappa, *fx, *fy;
+};
+
+// launchers (return hipError_t of the launch)
+hipError_t launch_prep(const Plan &p, const s2d_curves *src, void *ws, hipStream_t st);
+hipError_t launch_pair(const Plan &p, const PairArgs &a, hipStream_t st);
+hipError_t launch_kress(const Plan &p, const s2d_curves *src, const s2d_targets *trg,
+                        void *ws, hipStream_t st);
+hipError_t launch_final(const Plan &p, const FinalArgs &a, hipStream_t st);
+
+}  // namespace s2d

@@ -1,0 +1,71 @@
+"""Shared helpers for the tests: run the GPU path through the C ABI on a
+synthetic problem, run the oracle on the same inputs, and compare them with
+the paper's relative error (Section 4.1: max over targets of the velocity
+error norm divided by the max velocity norm), per target class."""
+from __future__ import annotations
+
+import numpy as np
+
+CLASS_NAMES = {0: "vesicle", 1: "wall", 2: "side"}
+
+
+def rel_err(u, v, ur, vr, sel=None):
+    """E = max_i |(u,v)_i - (ur,vr)_i| / max_i |(ur,vr)_i| over the index set sel."""
+    if sel is None:
+        sel = slice(None)
+    du = np.hypot(np.asarray(u)[sel] - ur[sel], np.asarray(v)[sel] - vr[sel])
+    sc = np.hypot(ur[sel], vr[sel]).max()
+    return float(du.max() / sc) if sc > 0 else float(du.max())
+
+
+def class_errors(kind, u, v, ur, vr):
+    out = {}
+    for k in np.unique(kind):
+        sel = np.where(kind == k)[0]
+        out[CLASS_NAMES.get(int(k), str(k))] = rel_err(u, v, ur, vr, sel)
+    return out
+
+
+def gpu_eval(prob, mode, img_lo=-1, img_hi=1, idx=None, parts=True):
+    """Evaluate SLP(vesicles) and DLP(walls) at every target of prob on the GPU.
+    Returns numpy (us, vs, ud, vd) (or only the targets idx)."""
+    import torch
+    import paper_1510_05616_amd as s2d
+    s2d.stokes2d_init(0)
+    t = prob.trg
+    ves, wall = s2d.Curves(prob.ves), s2d.Curves(prob.wall)
+    tv = s2d.Targets(t.x, t.y, t.ves_curve, t.ves_node)
+    tw = s2d.Targets(t.x, t.y, t.wall_curve, t.wall_node)
+    n = t.n
+    us = torch.zeros(n, dtype=torch.float64, device="cuda")
+    vs = torch.zeros_like(us)
+    ud = torch.zeros_like(us)
+    vd = torch.zeros_like(us)
+    s2d.stokes2d_slp_eval(mode, ves, tv, prob.d, img_lo, img_hi, prob.mu, us, vs)
+    s2d.stokes2d_dlp_eval(mode, wall, tw, prob.d, img_lo, img_hi, ud, vd)
+    torch.cuda.synchronize()
+    res = [a.cpu().numpy() for a in (us, vs, ud, vd)]
+    if idx is not None:
+        res = [a[idx] for a in res]
+    return res
+
+
+def oracle_eval(prob, img_lo=-1, img_hi=1, idx=None):
+    import oracle
+    t = prob.trg
+    sel = slice(None) if idx is None else idx
+    us, vs = oracle.slp(prob.ves, t.x[sel], t.y[sel], t.ves_curve[sel], t.ves_node[sel],
+                        prob.d, img_lo, img_hi, prob.mu)
+    ud, vd = oracle.dlp(prob.wall, t.x[sel], t.y[sel], t.wall_curve[sel], t.wall_node[sel],
+                        prob.d, img_lo, img_hi)
+    return us, vs, ud, vd
+
+
+def sample_targets(prob, per_class=256, seed=0):
+    rng = np.random.default_rng(seed)
+    kind = prob.trg.kind
+    idx = []
+    for k in np.unique(kind):
+        pool = np.where(kind == k)[0]
+        idx.append(np.sort(rng.choice(pool, min(per_class, pool.size), replace=False)))
+    return np.concatenate(idx)

@@ -1,0 +1,96 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every entry point declared in include/stokes2d.h, and rejects bad arguments
+(before touching the device) with the documented status codes."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = []
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", h)).read()
+            names += re.findall(r"S2D_API\s+[\w\s\*]+?\b(\w+)\s*\(", txt)
+    return names
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_1510_05616_amd as s2d
+    return s2d.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = _declared()
+    assert "stokes2d_slp_eval" in names and "stokes2d_dlp_eval" in names
+    for n in names:
+        assert hasattr(L, n), f"{n} declared in include/ but not exported"
+
+
+def test_version(L):
+    import paper_1510_05616_amd as s2d
+    assert s2d.stokes2d_version() >= 100
+
+
+def _structs(n_src=8, n_trg=4, on=False):
+    import paper_1510_05616_amd as s2d
+    fake = ctypes.c_void_p(0x1000)          # never dereferenced: validation fails first
+    cs = s2d._Curves(n_src, 1, fake, fake, fake, fake, fake, fake, fake, fake, fake)
+    ts = s2d._Targets(n_trg, fake, fake, fake if on else None, fake if on else None)
+    return cs, ts
+
+
+def test_bad_arguments_return_einval(L):
+    import paper_1510_05616_amd as s2d
+    cs, ts = _structs()
+    out = ctypes.c_void_p(0x2000)
+    ws = ctypes.c_void_p(0x3000)
+    by = ctypes.byref
+    # bad mode
+    assert L.stokes2d_slp_eval(7, by(cs), by(ts), 1.0, 0, 0, 1.0, out, out, 0, ws, 1 << 20, None) == s2d.S2D_EINVAL
+    # NULL structs
+    assert L.stokes2d_slp_eval(0, None, by(ts), 1.0, 0, 0, 1.0, out, out, 0, ws, 1 << 20, None) == s2d.S2D_EINVAL
+    # img_lo > img_hi
+    assert L.stokes2d_dlp_eval(0, by(cs), by(ts), 1.0, 1, 0, out, out, 0, ws, 1 << 20, None) == s2d.S2D_EINVAL
+    # images without a period
+    assert L.stokes2d_slp_eval(0, by(cs), by(ts), 0.0, -1, 1, 1.0, out, out, 0, ws, 1 << 20, None) == s2d.S2D_EINVAL
+    assert L.stokes2d_slp_eval(0, by(cs), by(ts), float("nan"), -1, 1, 1.0, out, out, 0, ws, 1 << 20, None) == s2d.S2D_EINVAL
+    # mu <= 0
+    assert L.stokes2d_slp_eval(0, by(cs), by(ts), 1.0, 0, 0, 0.0, out, out, 0, ws, 1 << 20, None) == s2d.S2D_EINVAL
+    # too many images
+    assert L.stokes2d_slp_eval(0, by(cs), by(ts), 1.0, -65, 0, 1.0, out, out, 0, ws, 1 << 20, None) == s2d.S2D_EINVAL
+    # on_curve without on_node
+    ts2 = s2d._Targets(4, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), None)
+    assert L.stokes2d_slp_eval(0, by(cs), by(ts2), 1.0, 0, 0, 1.0, out, out, 0, ws, 1 << 20, None) == s2d.S2D_EINVAL
+    # DLP with on-curve targets but no curvature
+    cs2, ts3 = _structs(on=True)
+    cs2.kappa = None
+    assert L.stokes2d_dlp_eval(0, by(cs2), by(ts3), 1.0, 0, 0, out, out, 0, ws, 1 << 20, None) == s2d.S2D_EINVAL
+    # negative sizes
+    cs3, _ = _structs(n_src=-1)
+    assert L.stokes2d_slp_eval(0, by(cs3), by(ts), 1.0, 0, 0, 1.0, out, out, 0, ws, 1 << 20, None) == s2d.S2D_EINVAL
+    assert "n_nodes" in s2d.stokes2d_last_error()
+
+
+def test_workspace_size_is_zero_on_bad_arguments(L):
+    import paper_1510_05616_amd as s2d
+    cs, ts = _structs()
+    assert L.stokes2d_workspace_size(5, 0, ctypes.byref(cs), ctypes.byref(ts)) == 0
+    assert L.stokes2d_workspace_size(0, 0, ctypes.byref(cs), ctypes.byref(ts)) > 0
+
+
+def test_workspace_grows_with_problem(L):
+    import paper_1510_05616_amd as s2d
+    small = _structs(100, 100)
+    big = _structs(100000, 100000)
+    for op in (0, 1):
+        for mode in (0, 1):
+            a = L.stokes2d_workspace_size(op, mode, ctypes.byref(small[0]), ctypes.byref(small[1]))
+            b = L.stokes2d_workspace_size(op, mode, ctypes.byref(big[0]), ctypes.byref(big[1]))
+            assert 0 < a < b

@@ -1,0 +1,202 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle, element
+by element on the same seeded inputs.
+
+Tolerances (relative error E of Section 4.1, per target class and per part):
+FP64 mode 1e-12, FP32C mode 1e-6.  Full-size (config 3, 128,064 targets x
+128,000 sources x 3 images) runs the GPU on every target in the same launch
+configuration the benchmark times, and checks a seeded sample of targets that
+the oracle computes one by one.
+"""
+import numpy as np
+import pytest
+
+import synth
+from _common import class_errors, gpu_eval, oracle_eval, rel_err, sample_targets
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-12, 1: 1e-6}
+MODES = [0, 1]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def device():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_1510_05616_amd as s2d
+    s2d.stokes2d_init(0)
+    yield
+
+
+def _check(prob, mode, idx=None, img=(-1, 1), tol=None):
+    tol = TOL[mode] if tol is None else tol
+    g = gpu_eval(prob, mode, *img, idx=idx)
+    o = oracle_eval(prob, *img, idx=idx)
+    kind = prob.trg.kind if idx is None else prob.trg.kind[idx]
+    errs = {}
+    for part, (gu, gv, ou, ov) in (("slp", (g[0], g[1], o[0], o[1])), ("dlp", (g[2], g[3], o[2], o[3]))):
+        for cls, e in class_errors(kind, gu, gv, ou, ov).items():
+            errs[f"{part}/{cls}"] = e
+    tot = class_errors(kind, g[0] + g[2], g[1] + g[3], o[0] + o[2], o[1] + o[3])
+    for cls, e in tot.items():
+        errs[f"total/{cls}"] = e
+    worst = max(errs.values())
+    print(f"mode={mode} worst E={worst:.3e} {errs}", flush=True)
+    assert worst <= tol, errs
+    return errs
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_config1_parity(mode):
+    _check(synth.make_config(1), mode)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_config2_parity(mode):
+    _check(synth.make_config(2), mode)
+
+
+@pytest.fixture(scope="module")
+def cfg3():
+    return synth.make_config(3)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_config3_full_size_sampled(cfg3, mode):
+    idx = sample_targets(cfg3, per_class=256, seed=5)
+    _check(cfg3, mode, idx=idx)
+
+
+@pytest.mark.parametrize("img", [(0, 0), (1, 1), (-1, -1), (-2, 2), (-3, 0)])
+@pytest.mark.parametrize("mode", MODES)
+def test_image_ranges(mode, img):
+    _check(synth.make_config(1), mode, img=img)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_ragged_sizes(mode):
+    # sizes that are not multiples of the wave (64), the target tile or the
+    # source superblock (256); odd wall node count
+    prob = synth.make_config(2, n_ves=7, ves_nodes=38, wall_nodes=1001)
+    _check(prob, mode)
+
+
+def test_single_node_sources_and_free_targets():
+    import torch
+    import oracle
+    import paper_1510_05616_amd as s2d
+    rng = np.random.default_rng(9)
+    src = synth.concat_curves([(rng.normal(size=1), rng.normal(size=1), np.ones(1), np.zeros(1),
+                                np.ones(1), np.zeros(1), rng.normal(size=1), rng.normal(size=1))
+                               for _ in range(3)])
+    tx, ty = rng.normal(size=5) + 5.0, rng.normal(size=5)
+    c, tg = s2d.Curves(src), s2d.Targets(tx, ty)
+    for mode in MODES:
+        u = torch.zeros(5, dtype=torch.float64, device="cuda")
+        v = torch.zeros_like(u)
+        s2d.stokes2d_slp_eval(mode, c, tg, 3.0, -1, 1, 0.7, u, v)
+        ou, ov = oracle.slp(src, tx, ty, d=3.0, img_lo=-1, img_hi=1, mu=0.7)
+        assert rel_err(u.cpu().numpy(), v.cpu().numpy(), ou, ov) < TOL[mode]
+        s2d.stokes2d_dlp_eval(mode, c, tg, 3.0, -1, 1, u, v)
+        ou, ov = oracle.dlp(src, tx, ty, d=3.0, img_lo=-1, img_hi=1)
+        assert rel_err(u.cpu().numpy(), v.cpu().numpy(), ou, ov) < TOL[mode]
+
+
+def test_empty_inputs_and_accumulate():
+    import torch
+    import paper_1510_05616_amd as s2d
+    prob = synth.make_config(1)
+    t = prob.trg
+    ves = s2d.Curves(prob.ves)
+    tv = s2d.Targets(t.x, t.y, t.ves_curve, t.ves_node)
+    # no targets: a no-op
+    e = s2d.Targets(np.zeros(0), np.zeros(0))
+    z = torch.zeros(0, dtype=torch.float64, device="cuda")
+    s2d.stokes2d_slp_eval(0, ves, e, prob.d, -1, 1, 1.0, z, z)
+    # no sources: zero output; with accumulate the outputs are unchanged
+    empty = synth.concat_curves([])
+    ec = s2d.Curves(empty)
+    tf = s2d.Targets(t.x, t.y)
+    u = torch.full((t.n,), 3.5, dtype=torch.float64, device="cuda")
+    v = torch.full((t.n,), -1.5, dtype=torch.float64, device="cuda")
+    s2d.stokes2d_slp_eval(0, ec, tf, prob.d, -1, 1, 1.0, u, v, accumulate=1)
+    torch.cuda.synchronize()
+    assert torch.all(u == 3.5) and torch.all(v == -1.5)
+    s2d.stokes2d_dlp_eval(1, ec, tf, prob.d, -1, 1, u, v)
+    torch.cuda.synchronize()
+    assert torch.all(u == 0) and torch.all(v == 0)
+    # accumulate adds exactly the non-accumulated result
+    for mode in MODES:
+        a = torch.zeros(t.n, dtype=torch.float64, device="cuda")
+        b = torch.zeros_like(a)
+        s2d.stokes2d_slp_eval(mode, ves, tv, prob.d, -1, 1, 1.0, a, b)
+        u = torch.full((t.n,), 0.25, dtype=torch.float64, device="cuda")
+        v = torch.full((t.n,), -0.5, dtype=torch.float64, device="cuda")
+        s2d.stokes2d_slp_eval(mode, ves, tv, prob.d, -1, 1, 1.0, u, v, accumulate=1)
+        torch.cuda.synchronize()
+        assert torch.equal(u, a + 0.25) and torch.equal(v, b - 0.5)
+
+
+def test_inconsistent_on_curve_entries_give_nan():
+    import torch
+    import paper_1510_05616_amd as s2d
+    prob = synth.make_config(1)
+    t = prob.trg
+    vc, vn = t.ves_curve.copy(), t.ves_node.copy()
+    vn[3] = vn[3] + 200                 # node outside its curve
+    vc[5] = 7                           # curve that does not exist
+    wc, wn = t.wall_curve.copy(), t.wall_node.copy()
+    j = int(np.where(wc >= 0)[0][0])
+    wn[j] = -5
+    ves, wall = s2d.Curves(prob.ves), s2d.Curves(prob.wall)
+    for mode in MODES:
+        u = torch.zeros(t.n, dtype=torch.float64, device="cuda")
+        v = torch.zeros_like(u)
+        s2d.stokes2d_slp_eval(mode, ves, s2d.Targets(t.x, t.y, vc, vn), prob.d, -1, 1, 1.0, u, v)
+        un = u.cpu().numpy()
+        assert np.isnan(un[3]) and np.isnan(un[5])
+        assert np.isfinite(np.delete(un, [3, 5])).all()
+        s2d.stokes2d_dlp_eval(mode, wall, s2d.Targets(t.x, t.y, wc, wn), prob.d, -1, 1, u, v)
+        un = u.cpu().numpy()
+        assert np.isnan(un[j]) and np.isfinite(np.delete(un, [j])).all()
+
+
+def test_odd_curve_with_self_target_gives_nan():
+    import torch
+    import paper_1510_05616_amd as s2d
+    c = synth.ellipse_curve(0.3, 0.2, 33, fx=np.cos, fy=np.sin)
+    oc = np.zeros(33, np.int32)
+    on = np.arange(33, dtype=np.int32)
+    u = torch.zeros(33, dtype=torch.float64, device="cuda")
+    v = torch.zeros_like(u)
+    s2d.stokes2d_slp_eval(0, s2d.Curves(c), s2d.Targets(c.x, c.y, oc, on), 0.0, 0, 0, 1.0, u, v)
+    assert torch.isnan(u).all()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_bitwise_deterministic(mode):
+    prob = synth.make_config(2)
+    a = gpu_eval(prob, mode)
+    b = gpu_eval(prob, mode)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_workspace_errors():
+    import torch
+    import paper_1510_05616_amd as s2d
+    prob = synth.make_config(1)
+    t = prob.trg
+    ves = s2d.Curves(prob.ves)
+    tv = s2d.Targets(t.x, t.y, t.ves_curve, t.ves_node)
+    u = torch.zeros(t.n, dtype=torch.float64, device="cuda")
+    v = torch.zeros_like(u)
+    need = s2d.stokes2d_workspace_size(0, 0, ves, tv)
+    small = torch.empty(need // 2, dtype=torch.uint8, device="cuda")
+    with pytest.raises(s2d.S2DError) as ei:
+        s2d.stokes2d_slp_eval(0, ves, tv, prob.d, -1, 1, 1.0, u, v, ws=small)
+    assert ei.value.code == s2d.S2D_EWORKSPACE
+    big = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
+    with pytest.raises(s2d.S2DError) as ei:   # misaligned pointer
+        s2d.stokes2d_slp_eval(0, ves, tv, prob.d, -1, 1, 1.0, u, v, ws=big[8:])
+    assert ei.value.code == s2d.S2D_EWORKSPACE
