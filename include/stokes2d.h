@@ -132,6 +132,43 @@ S2D_API int stokes2d_dlp_eval(int mode, const s2d_curves *src, const s2d_targets
                               double *u, double *v, int accumulate,
                               void *ws, size_t ws_bytes, void *stream);
 
+/* One independent channel instance of a batched evaluation: the single
+ * layer of the vesicles plus the double layer of the walls, images -1..1,
+ * at the same n target points (trg_ves and trg_wall describe the same points;
+ * their on_curve / on_node refer to ves and wall respectively). */
+typedef struct s2d_instance {
+    s2d_curves ves;
+    s2d_curves wall;
+    s2d_targets trg_ves;
+    s2d_targets trg_wall;
+    double d, mu;
+    double *u, *v;               /* [n] outputs (written, not accumulated) */
+} s2d_instance;
+
+/* Workspace bytes for stokes2d_batch_eval over the host array inst[n_inst]
+ * (0 on bad arguments).  The size covers every tile shape the tuner tries. */
+S2D_API size_t stokes2d_batch_workspace_size(int mode, int32_t n_inst, const s2d_instance *inst);
+
+/* Evaluates u = S(ves) f + D(wall) tau for every instance.  The work of all
+ * instances is cut into (instance, operator, target tile, source split)
+ * items, sorted longest first, and run by one persistent launch; the whole
+ * evaluation is recorded in a HIP graph.  The first call for a given argument
+ * set (mode, every pointer and size in inst[], d, mu, ws, ws_bytes) waits for
+ * `stream`, picks the tile shape (timing a few candidates on the real inputs
+ * unless a tuned choice for this size is cached; environment S2D_TUNE=0 keeps
+ * the default, S2D_TUNE_CACHE names the JSON cache file), records the graph
+ * and launches it; it is not capturable and may allocate (pinned table
+ * image, graph).  Later calls with the same argument set are one graph launch
+ * on `stream`: device data behind the pointers may change between calls, the
+ * pointers and sizes may not.  `inst` is read only during the call.  The
+ * workspace holds the call's tables and partial sums until the launched work
+ * completes. */
+S2D_API int stokes2d_batch_eval(int mode, int32_t n_inst, const s2d_instance *inst,
+                                void *ws, size_t ws_bytes, void *stream);
+
+/* Frees every cached batch plan and graph (waits for the device). */
+S2D_API int stokes2d_batch_release(void);
+
 /* Benchmarking aid (not capturable, not for production loops): while
  * enabled, each evaluation records a HIP event pair around its pair-sum
  * kernel launch on the caller's stream.  stokes2d_profile_read() waits for

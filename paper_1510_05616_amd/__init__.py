@@ -24,6 +24,7 @@ __all__ = [
     "Curves", "Targets", "lib", "library_path",
     "stokes2d_init", "stokes2d_workspace_size", "stokes2d_slp_eval", "stokes2d_dlp_eval",
     "stokes2d_last_error", "stokes2d_version", "stokes2d_profile_enable", "stokes2d_profile_read",
+    "BatchInstance", "stokes2d_batch_workspace_size", "stokes2d_batch_eval", "stokes2d_batch_release",
 ]
 
 S2D_OK, S2D_EINVAL, S2D_EHIP, S2D_ENOTSUP, S2D_EWORKSPACE, S2D_ENOINIT = 0, -1, -2, -3, -4, -5
@@ -54,6 +55,12 @@ class _Targets(ctypes.Structure):
                 ("on_curve", ctypes.c_void_p), ("on_node", ctypes.c_void_p)]
 
 
+class _Instance(ctypes.Structure):
+    _fields_ = [("ves", _Curves), ("wall", _Curves), ("trg_ves", _Targets), ("trg_wall", _Targets),
+                ("d", ctypes.c_double), ("mu", ctypes.c_double),
+                ("u", ctypes.c_void_p), ("v", ctypes.c_void_p)]
+
+
 _lib = None
 
 
@@ -79,6 +86,12 @@ def lib():
         L.stokes2d_last_error.restype = ctypes.c_char_p
         L.stokes2d_version.argtypes = []
         L.stokes2d_version.restype = I
+        L.stokes2d_batch_workspace_size.argtypes = [I, I32, P]
+        L.stokes2d_batch_workspace_size.restype = SZ
+        L.stokes2d_batch_eval.argtypes = [I, I32, P, P, SZ, P]
+        L.stokes2d_batch_eval.restype = I
+        L.stokes2d_batch_release.argtypes = []
+        L.stokes2d_batch_release.restype = I
         L.stokes2d_profile_enable.argtypes = [I]
         L.stokes2d_profile_enable.restype = I
         L.stokes2d_profile_read.argtypes = [I, P, P]
@@ -210,3 +223,40 @@ def stokes2d_dlp_eval(mode, src: Curves, trg: Targets, d, img_lo, img_hi, u, v,
     _check(lib().stokes2d_dlp_eval(int(mode), ctypes.byref(cs), ctypes.byref(ts), float(d),
                                    int(img_lo), int(img_hi), _ptr(u), _ptr(v),
                                    int(bool(accumulate)), _ptr(ws), ws.numel(), _stream(stream)))
+
+
+class BatchInstance:
+    """One channel instance of a batched evaluation: vesicle curves (single
+    layer), wall curves (double layer), the target points with their on-curve
+    references to each set, period d, viscosity mu and the outputs u, v."""
+
+    def __init__(self, ves: Curves, wall: Curves, trg_ves: Targets, trg_wall: Targets, d, mu, u, v):
+        self.ves, self.wall, self.trg_ves, self.trg_wall = ves, wall, trg_ves, trg_wall
+        self.d, self.mu, self.u, self.v = float(d), float(mu), u, v
+
+    def struct(self):
+        return _Instance(self.ves.struct(), self.wall.struct(), self.trg_ves.struct(), self.trg_wall.struct(),
+                         self.d, self.mu, _ptr(self.u), _ptr(self.v))
+
+
+def _inst_array(instances):
+    arr = (_Instance * max(len(instances), 1))()
+    for i, b in enumerate(instances):
+        arr[i] = b.struct()
+    return arr
+
+
+def stokes2d_batch_workspace_size(mode, instances) -> int:
+    arr = _inst_array(instances)
+    return int(lib().stokes2d_batch_workspace_size(int(mode), len(instances), arr))
+
+
+def stokes2d_batch_eval(mode, instances, ws, stream=None) -> None:
+    """ws: a device uint8 tensor of at least stokes2d_batch_workspace_size()
+    bytes; keep passing the same one so repeated calls replay the cached graph."""
+    arr = _inst_array(instances)
+    _check(lib().stokes2d_batch_eval(int(mode), len(instances), arr, _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def stokes2d_batch_release() -> None:
+    _check(lib().stokes2d_batch_release())

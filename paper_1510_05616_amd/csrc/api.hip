@@ -3,6 +3,7 @@
 // all scratch lives in the caller's workspace.
 #include "s2d_internal.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -117,6 +118,19 @@ s2d::Plan make_plan(int op, int mode, const s2d_curves *s, const s2d_targets *t,
     }
     p.total = off;
     return p;
+}
+
+int check_batch_inst(int mode, const s2d_instance &I, int32_t k) {
+    const std::string where = "instance " + std::to_string(k) + ": ";
+    int rc = check_args(S2D_OP_SLP, mode, &I.ves, &I.trg_ves, I.d, -1, 1, I.mu);
+    if (rc != S2D_OK) return fail(rc, where + g_err);
+    rc = check_args(S2D_OP_DLP, mode, &I.wall, &I.trg_wall, I.d, -1, 1, 1.0);
+    if (rc != S2D_OK) return fail(rc, where + g_err);
+    if (I.trg_ves.n != I.trg_wall.n) return fail(S2D_EINVAL, where + "trg_ves.n != trg_wall.n");
+    if (I.trg_ves.n > 0 && (!I.u || !I.v)) return fail(S2D_EINVAL, where + "outputs u, v must not be NULL");
+    if (I.ves.n_nodes > INT32_MAX / 4 || I.wall.n_nodes > INT32_MAX / 4 || I.trg_ves.n > INT32_MAX / 4)
+        return fail(S2D_EINVAL, where + "instance too large for the batched path");
+    return S2D_OK;
 }
 
 int current_device(int *dev) {
@@ -297,6 +311,35 @@ S2D_API int stokes2d_profile_read(int op, double *total_ms, int64_t *launches) {
     *launches = n;
     return S2D_OK;
 }
+
+S2D_API size_t stokes2d_batch_workspace_size(int mode, int32_t n_inst, const s2d_instance *inst) {
+    if (n_inst < 0 || (n_inst > 0 && !inst)) return 0;
+    for (int32_t k = 0; k < n_inst; ++k)
+        if (check_batch_inst(mode, inst[k], k) != S2D_OK) return 0;
+    return std::max<size_t>(s2d::batch_workspace_size(mode, n_inst, inst), 256);
+}
+
+S2D_API int stokes2d_batch_eval(int mode, int32_t n_inst, const s2d_instance *inst, void *ws, size_t ws_bytes,
+                                void *stream) {
+    if (n_inst < 0) return fail(S2D_EINVAL, "n_inst < 0");
+    if (n_inst > 0 && !inst) return fail(S2D_EINVAL, "inst must not be NULL");
+    for (int32_t k = 0; k < n_inst; ++k) {
+        const int rc = check_batch_inst(mode, inst[k], k);
+        if (rc != S2D_OK) return rc;
+    }
+    int dev = 0;
+    int rc = current_device(&dev);
+    if (rc != S2D_OK) return rc;
+    if (n_inst == 0) return S2D_OK;
+    if (!ws) return fail(S2D_EWORKSPACE, "workspace is NULL");
+    if (((uintptr_t)ws & 255) != 0) return fail(S2D_EWORKSPACE, "workspace must be 256-byte aligned");
+    std::string err;
+    rc = s2d::batch_eval(dev, g_dev[dev].cus, mode, n_inst, inst, ws, ws_bytes, (hipStream_t)stream, err);
+    if (rc != S2D_OK) return fail(rc, err);
+    return S2D_OK;
+}
+
+S2D_API int stokes2d_batch_release(void) { return s2d::batch_release(); }
 
 S2D_API const char *stokes2d_last_error(void) { return g_err.c_str(); }
 

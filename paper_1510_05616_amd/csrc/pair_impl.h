@@ -1,0 +1,328 @@
+#pragma once
+// Pair-sum kernels: Stokeslet single layer (Section 2.1 Eq. (S), summed over
+// the near images of Section 3.1 Eq. (utotrep)) and stresslet double layer
+// (Eq. (D), summed as Eq. (Dnr)), for every target against every source node
+// of a curve set and its images n = img_lo..img_hi.
+//
+// Work decomposition.  A wavefront owns kWave * TPT targets (TPT per lane,
+// lane-strided so target loads are coalesced) and one source split (a run of
+// superblocks of kSuperBlock sources).  Every lane of a wave walks the same
+// sources in the same order, so each source record is wave-uniform: it is
+// fetched through the scalar data path into SGPRs (no LDS staging, no
+// barriers) and used as the SGPR operand of the vector ALU instructions.  The
+// workgroup's split index is blockIdx % n_splits, so with a multiple of 8
+// splits all workgroups on one XCD (dispatch is round-robin over the 8 XCDs)
+// stream the same sources through that XCD's L2.  Each wave writes one FP64
+// partial per target and split; a second kernel reduces them in fixed order
+// (deterministic, no atomics).
+//
+// Exclusions.  For a target that is node i of source curve c, the single
+// layer skips curve c at n = 0 (Kress's rule covers it elsewhere) and the
+// double layer skips node i at n = 0 (the diagonal limit covers it).  A wave
+// folds its targets' excluded index ranges into one hull; a superblock that
+// meets the hull at n = 0, or the ragged last superblock, takes a masked path
+// with a per-pair select.  All other superblocks take the unmasked path.
+//
+// Precision.  FP64 mode evaluates each term in double.  FP32C mode forms the
+// coordinate difference in double and rounds it once to float (so r carries a
+// relative error of one rounding, also for near pairs), evaluates the term in
+// float with the hardware log2 and reciprocal, sums kSubBlock terms in float
+// and merges them into double accumulators.  For the single-layer log term a
+// per-(target, superblock, image) reference distance q_ref is divided out
+// before the float log2 and its log is added back in double against the
+// superblock's FP64 density sum, so the float logs stay O(1) in magnitude.
+#include "s2d_internal.h"
+
+#include <climits>
+
+namespace s2d {
+
+__device__ __forceinline__ double rcp64(double q) {
+    double y = __builtin_amdgcn_rcp(q);          // ~2^-26 relative
+    double e = __builtin_fma(-q, y, 1.0);
+    y = __builtin_fma(y, e, y);
+    e = __builtin_fma(-q, y, 1.0);
+    return __builtin_fma(y, e, y);
+}
+
+// Natural log of a positive, finite, normal double (q = |r|^2 here), from
+// the reduction x = 2^e m with m in [sqrt(1/2), sqrt(2)) and
+// log m = 2 atanh(s), s = (m - 1) / (m + 1), |s| <= 0.1716, summed as the
+// odd series 2 (s + s^3/3 + ... + s^23/23): the first omitted term is below
+// 1e-18 relative.  Error: a few ulp, from the rounding of m + 1 and of the
+// reciprocal.  Zero or negative input gives a finite meaningless value (the
+// callers mask those pairs out).
+__device__ __forceinline__ double log64(double x) {
+    int e = __builtin_amdgcn_frexp_exp(x);             // x = m 2^e, m in [0.5, 1)
+    double m = __builtin_amdgcn_frexp_mant(x);
+    const bool lo = m < 0.70710678118654752440;
+    m = lo ? m + m : m;
+    e = lo ? e - 1 : e;
+    const double f = m - 1.0;
+    const double s = f * rcp64(2.0 + f);
+    const double z = s * s;
+    double p = 2.0 / 23.0;
+    p = __builtin_fma(p, z, 2.0 / 21.0);
+    p = __builtin_fma(p, z, 2.0 / 19.0);
+    p = __builtin_fma(p, z, 2.0 / 17.0);
+    p = __builtin_fma(p, z, 2.0 / 15.0);
+    p = __builtin_fma(p, z, 2.0 / 13.0);
+    p = __builtin_fma(p, z, 2.0 / 11.0);
+    p = __builtin_fma(p, z, 2.0 / 9.0);
+    p = __builtin_fma(p, z, 2.0 / 7.0);
+    p = __builtin_fma(p, z, 2.0 / 5.0);
+    p = __builtin_fma(p, z, 2.0 / 3.0);
+    const double lm = __builtin_fma(s * z, p, s + s);  // log m
+    const double de = (double)e;
+    // ln 2 split so that de * kLn2Hi is exact for |e| < 2^11
+    constexpr double kLn2Hi = 6.93147180369123816490e-01;
+    constexpr double kLn2Lo = 1.90821492927058770002e-10;
+    return __builtin_fma(de, kLn2Hi, __builtin_fma(de, kLn2Lo, lm));
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = min(v, __shfl_xor(v, m, kWave));
+    return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = max(v, __shfl_xor(v, m, kWave));
+    return v;
+}
+
+
+// ---------------------------------------------------------------------------
+// per-pair terms
+// ---------------------------------------------------------------------------
+// FP64 single layer: accumulates A += g log q and B += r (r.g)/q.
+__device__ __forceinline__ void slp64_pair(double px, double py, const RecSlp64 &s,
+                                           double &ax, double &ay, double &bx, double &by) {
+    double rx = px - s.x, ry = py - s.y;
+    double q = __builtin_fma(rx, rx, ry * ry);
+    double lq = log64(q);
+    double iq = rcp64(q);
+    double t = __builtin_fma(rx, s.gx, ry * s.gy) * iq;
+    ax = __builtin_fma(s.gx, lq, ax);
+    ay = __builtin_fma(s.gy, lq, ay);
+    bx = __builtin_fma(rx, t, bx);
+    by = __builtin_fma(ry, t, by);
+}
+
+// FP32 single layer term added to (sx, sy); iqr scales q before the log.
+__device__ __forceinline__ void slp32_acc(double px, double py, const RecSlp32 &s, float iqr,
+                                          float &sx, float &sy) {
+    float rx = (float)(px - s.x), ry = (float)(py - s.y);
+    float q = __builtin_fmaf(rx, rx, ry * ry);
+    float lq = __builtin_amdgcn_logf(q * iqr);      // log2
+    float iq = __builtin_amdgcn_rcpf(q);
+    float t = __builtin_fmaf(rx, s.gx, ry * s.gy) * iq;
+    sx = __builtin_fmaf(s.lx, lq, sx);
+    sx = __builtin_fmaf(rx, t, sx);
+    sy = __builtin_fmaf(s.ly, lq, sy);
+    sy = __builtin_fmaf(ry, t, sy);
+}
+
+__device__ __forceinline__ void dlp64_pair(double px, double py, const RecDlp64 &s,
+                                           double &ux, double &uy) {
+    double rx = px - s.x, ry = py - s.y;
+    double q = __builtin_fma(rx, rx, ry * ry);
+    double iq = rcp64(q);
+    double rn = __builtin_fma(rx, s.nx, ry * s.ny);
+    double rt = __builtin_fma(rx, s.tx, ry * s.ty);
+    double f = (rn * rt) * (iq * iq);
+    ux = __builtin_fma(rx, f, ux);
+    uy = __builtin_fma(ry, f, uy);
+}
+
+__device__ __forceinline__ void dlp32_acc(double px, double py, const RecDlp32 &s,
+                                          float &sx, float &sy) {
+    float rx = (float)(px - s.x), ry = (float)(py - s.y);
+    float q = __builtin_fmaf(rx, rx, ry * ry);
+    float iq = __builtin_amdgcn_rcpf(q);
+    float rn = __builtin_fmaf(rx, s.nx, ry * s.ny);
+    float rt = __builtin_fmaf(rx, s.tx, ry * s.ty);
+    float f = (rn * rt) * (iq * iq);
+    sx = __builtin_fmaf(rx, f, sx);
+    sy = __builtin_fmaf(ry, f, sy);
+}
+
+// ---------------------------------------------------------------------------
+// the kernel
+// ---------------------------------------------------------------------------
+// One wave: targets [tile * kWave * TPT, +kWave * TPT) against source split
+// `split`, all images; writes the FP64 partials of that split.
+template <int OP, int PREC, int TPT>
+__device__ __forceinline__ void pair_tile(const PairArgs &a, int64_t tile, int split, int lane) {
+
+    double tx[TPT], ty[TPT];
+    int lo[TPT], hi[TPT];
+    int64_t ti[TPT];
+    int hlo = INT_MAX, hhi = INT_MIN;
+#pragma unroll
+    for (int k = 0; k < TPT; ++k) {
+        ti[k] = tile * (int64_t)(kWave * TPT) + k * kWave + lane;
+        const bool act = ti[k] < a.n_trg;
+        tx[k] = act ? a.tx[ti[k]] : 0.0;
+        ty[k] = act ? a.ty[ti[k]] : 0.0;
+        lo[k] = 0;
+        hi[k] = 0;
+        if (act && a.on_curve) {
+            const int c = a.on_curve[ti[k]];
+            if (c >= 0 && c < a.n_curves) {
+                if (OP == S2D_OP_SLP) {
+                    lo[k] = a.curve_off[c];
+                    hi[k] = a.curve_off[c + 1];
+                } else {
+                    const int j = a.on_node[ti[k]];
+                    if (j >= a.curve_off[c] && j < a.curve_off[c + 1]) { lo[k] = j; hi[k] = j + 1; }
+                }
+            }
+        }
+        if (lo[k] < hi[k]) { hlo = min(hlo, lo[k]); hhi = max(hhi, hi[k]); }
+    }
+    hlo = __builtin_amdgcn_readfirstlane(wave_min(hlo));
+    hhi = __builtin_amdgcn_readfirstlane(wave_max(hhi));
+
+    const int64_t sb0 = (int64_t)split * a.sb_per_split;
+    const int64_t sb1 = min(sb0 + a.sb_per_split, a.n_sb);
+
+    double ux[TPT], uy[TPT], vx[TPT], vy[TPT];     // vx, vy: FP64 SLP log accumulators
+#pragma unroll
+    for (int k = 0; k < TPT; ++k) { ux[k] = uy[k] = vx[k] = vy[k] = 0.0; }
+
+    for (int n = a.img_lo; n <= a.img_hi; ++n) {
+        double px[TPT], py[TPT];
+#pragma unroll
+        for (int k = 0; k < TPT; ++k) { px[k] = tx[k] - (double)n * a.d; py[k] = ty[k]; }
+
+        for (int64_t sb = sb0; sb < sb1; ++sb) {
+            const int64_t j0 = sb * kSuperBlock;
+            const int64_t j1 = min(j0 + (int64_t)kSuperBlock, a.n_src);
+            const bool masked = (j1 - j0 < kSuperBlock) ||
+                                (n == 0 && hlo < hhi && j0 < hhi && (int64_t)hlo < j0 + kSuperBlock);
+            if (!masked) {
+                // ---------------- unmasked superblock ----------------
+                if (PREC == S2D_FP64) {
+                    if (OP == S2D_OP_SLP) {
+                        const RecSlp64 *rec = (const RecSlp64 *)a.rec + j0;
+                        for (int u = 0; u < kSuperBlock; u += 4) {
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) {
+                                const RecSlp64 s = rec[u + q];
+#pragma unroll
+                                for (int k = 0; k < TPT; ++k) slp64_pair(px[k], py[k], s, vx[k], vy[k], ux[k], uy[k]);
+                            }
+                        }
+                    } else {
+                        const RecDlp64 *rec = (const RecDlp64 *)a.rec + j0;
+                        for (int u = 0; u < kSuperBlock; u += 4) {
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) {
+                                const RecDlp64 s = rec[u + q];
+#pragma unroll
+                                for (int k = 0; k < TPT; ++k) dlp64_pair(px[k], py[k], s, ux[k], uy[k]);
+                            }
+                        }
+                    }
+                } else {
+                    if (OP == S2D_OP_SLP) {
+                        const RecSlp32 *rec = (const RecSlp32 *)a.rec + j0;
+                        // log reference: the superblock's first source
+                        float iqr[TPT];
+                        const double gsx = a.sbsum[2 * sb], gsy = a.sbsum[2 * sb + 1];
+#pragma unroll
+                        for (int k = 0; k < TPT; ++k) {
+                            const double rx0 = px[k] - rec[0].x, ry0 = py[k] - rec[0].y;
+                            const double qr = __builtin_fma(rx0, rx0, ry0 * ry0);
+                            iqr[k] = (qr > 1e-20 && qr < 1e20) ? (float)rcp64(qr) : 1.0f;
+                            // -1/2 sum g ln q = sum (l log2(q iqr)) + 1/2 ln(iqr) sum g
+                            const double c = 0.5 * log64((double)iqr[k]);
+                            ux[k] = __builtin_fma(c, gsx, ux[k]);
+                            uy[k] = __builtin_fma(c, gsy, uy[k]);
+                        }
+                        for (int u = 0; u < kSuperBlock; u += kSubBlock) {
+                            float sx[TPT], sy[TPT];
+#pragma unroll
+                            for (int k = 0; k < TPT; ++k) { sx[k] = 0.f; sy[k] = 0.f; }
+#pragma unroll
+                            for (int q = 0; q < kSubBlock; ++q) {
+                                const RecSlp32 s = rec[u + q];
+#pragma unroll
+                                for (int k = 0; k < TPT; ++k) slp32_acc(px[k], py[k], s, iqr[k], sx[k], sy[k]);
+                            }
+#pragma unroll
+                            for (int k = 0; k < TPT; ++k) { ux[k] += (double)sx[k]; uy[k] += (double)sy[k]; }
+                        }
+                    } else {
+                        const RecDlp32 *rec = (const RecDlp32 *)a.rec + j0;
+                        for (int u = 0; u < kSuperBlock; u += kSubBlock) {
+                            float sx[TPT], sy[TPT];
+#pragma unroll
+                            for (int k = 0; k < TPT; ++k) { sx[k] = 0.f; sy[k] = 0.f; }
+#pragma unroll
+                            for (int q = 0; q < kSubBlock; ++q) {
+                                const RecDlp32 s = rec[u + q];
+#pragma unroll
+                                for (int k = 0; k < TPT; ++k) dlp32_acc(px[k], py[k], s, sx[k], sy[k]);
+                            }
+#pragma unroll
+                            for (int k = 0; k < TPT; ++k) { ux[k] += (double)sx[k]; uy[k] += (double)sy[k]; }
+                        }
+                    }
+                }
+            } else {
+                // ---------------- masked superblock (rare) ----------------
+                for (int64_t j = j0; j < j0 + kSuperBlock; ++j) {
+                    const bool inrange = j < j1;
+#pragma unroll
+                    for (int k = 0; k < TPT; ++k) {
+                        const bool ok = inrange && (n != 0 || j < lo[k] || j >= hi[k]);
+                        if (PREC == S2D_FP64) {
+                            if (OP == S2D_OP_SLP) {
+                                const RecSlp64 s = ((const RecSlp64 *)a.rec)[j];
+                                double ax = 0, ay = 0, bx = 0, by = 0;
+                                slp64_pair(px[k], py[k], s, ax, ay, bx, by);
+                                vx[k] += ok ? ax : 0.0; vy[k] += ok ? ay : 0.0;
+                                ux[k] += ok ? bx : 0.0; uy[k] += ok ? by : 0.0;
+                            } else {
+                                const RecDlp64 s = ((const RecDlp64 *)a.rec)[j];
+                                double ax = 0, ay = 0;
+                                dlp64_pair(px[k], py[k], s, ax, ay);
+                                ux[k] += ok ? ax : 0.0; uy[k] += ok ? ay : 0.0;
+                            }
+                        } else {
+                            float t0 = 0.f, t1 = 0.f;
+                            if (OP == S2D_OP_SLP) {
+                                const RecSlp32 s = ((const RecSlp32 *)a.rec)[j];
+                                slp32_acc(px[k], py[k], s, 1.0f, t0, t1);
+                            } else {
+                                const RecDlp32 s = ((const RecDlp32 *)a.rec)[j];
+                                dlp32_acc(px[k], py[k], s, t0, t1);
+                            }
+                            ux[k] += ok ? (double)t0 : 0.0;
+                            uy[k] += ok ? (double)t1 : 0.0;
+                        }
+                    }
+                }
+            }
+        }
+    }
+
+    const int64_t plane = a.n_trg;
+    double *out = a.part + (int64_t)split * 2 * plane;
+#pragma unroll
+    for (int k = 0; k < TPT; ++k) {
+        if (ti[k] < a.n_trg) {
+            double rx_ = ux[k], ry_ = uy[k];
+            if (PREC == S2D_FP64 && OP == S2D_OP_SLP) {
+                rx_ = __builtin_fma(-0.5, vx[k], rx_);
+                ry_ = __builtin_fma(-0.5, vy[k], ry_);
+            }
+            out[ti[k]] = rx_;
+            out[plane + ti[k]] = ry_;
+        }
+    }
+}
+
+}  // namespace s2d

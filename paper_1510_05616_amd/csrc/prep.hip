@@ -1,11 +1,6 @@
-// Source preparation (O(N)): turns the caller's FP64 structure-of-arrays
-// curve data into the per-source records the pair kernels stream, with the
-// trapezoid weight folded in (g = w f for the single layer, nu = w n for the
-// double layer; Section 2.3 Nystrom discretisation), zero records padding the
-// last superblock, and, for the FP32 single layer, each superblock's FP64
-// density sum (used to add back the log of the superblock's reference
-// distance).
-#include "s2d_internal.h"
+// Source preparation kernels of a single evaluation (device code in
+// prep_impl.h).
+#include "prep_impl.h"
 
 namespace s2d {
 
@@ -18,43 +13,16 @@ __global__ __launch_bounds__(256) void prep_records(int64_t n_src, int64_t n_pad
                                                     void *rec_out) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n_pad) return;
-    const bool v = j < n_src;
-    const double X = v ? x[j] : 0.0, Y = v ? y[j] : 0.0;
-    const double W = v ? w[j] : 0.0;
-    const double FX = v ? fx[j] : 0.0, FY = v ? fy[j] : 0.0;
-    if (OP == S2D_OP_SLP) {
-        const double gx = W * FX, gy = W * FY;
-        if (PREC == S2D_FP64) {
-            ((RecSlp64 *)rec_out)[j] = RecSlp64{X, Y, gx, gy};
-        } else {
-            const double c = -0.34657359027997264;   // -ln(2)/2: natural log from log2
-            ((RecSlp32 *)rec_out)[j] = RecSlp32{X, Y, (float)gx, (float)gy, (float)(c * gx), (float)(c * gy)};
-        }
-    } else {
-        const double NX = v ? W * nx[j] : 0.0, NY = v ? W * ny[j] : 0.0;
-        if (PREC == S2D_FP64) {
-            ((RecDlp64 *)rec_out)[j] = RecDlp64{X, Y, NX, NY, FX, FY};
-        } else {
-            ((RecDlp32 *)rec_out)[j] = RecDlp32{X, Y, (float)NX, (float)NY, (float)FX, (float)FY};
-        }
-    }
+    prep_one<OP, PREC>(j, n_src, x, y, nx, ny, w, fx, fy, rec_out);
 }
 
-// One thread per superblock: sequential FP64 sum of g = w f (fixed order).
 __global__ __launch_bounds__(256) void prep_sbsum(int64_t n_src, int64_t n_sb,
                                                   const double *__restrict__ w,
                                                   const double *__restrict__ fx, const double *__restrict__ fy,
                                                   double *sbsum) {
     const int64_t sb = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (sb >= n_sb) return;
-    double sx = 0.0, sy = 0.0;
-    const int64_t j0 = sb * kSuperBlock, j1 = min(j0 + (int64_t)kSuperBlock, n_src);
-    for (int64_t j = j0; j < j1; ++j) {
-        sx += w[j] * fx[j];
-        sy += w[j] * fy[j];
-    }
-    sbsum[2 * sb] = sx;
-    sbsum[2 * sb + 1] = sy;
+    sbsum_one(sb, n_src, w, fx, fy, sbsum);
 }
 
 template <int OP, int PREC>

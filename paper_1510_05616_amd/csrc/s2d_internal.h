@@ -5,6 +5,8 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <string>
+
 #include "../../include/stokes2d.h"
 
 namespace s2d {
@@ -76,5 +78,12 @@ hipError_t launch_pair(const Plan &p, const PairArgs &a, hipStream_t st);
 hipError_t launch_kress(const Plan &p, const s2d_curves *src, const s2d_targets *trg,
                         void *ws, hipStream_t st);
 hipError_t launch_final(const Plan &p, const FinalArgs &a, hipStream_t st);
+
+// batched evaluation (batch.hip)
+size_t batch_workspace_size(int mode, int32_t n_inst, const s2d_instance *inst);
+int batch_eval(int dev, int cus, int mode, int32_t n_inst, const s2d_instance *inst, void *ws, size_t ws_bytes,
+               hipStream_t stream, std::string &err);
+int batch_release();
+int batch_tuned(int mode, int32_t n_inst, const s2d_instance *inst, int *tpt, int *sbps, int *wpc);
 
 }  // namespace s2d
