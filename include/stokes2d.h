@@ -169,6 +169,79 @@ S2D_API int stokes2d_batch_eval(int mode, int32_t n_inst, const s2d_instance *in
 /* Frees every cached batch plan and graph (waits for the device). */
 S2D_API int stokes2d_batch_release(void);
 
+/* ---------------------------------------------------------------------------
+ * Near-field correction of the single layer (learned, with FFT-upsampled
+ * quadrature as reference and fallback).
+ *
+ * For a target x near closed source curve c (given by trg_curve[i]), the
+ * plain N-node trapezoid single layer of curve c loses accuracy (the paper
+ * notes the trapezoid rule's near-curve error band, Section 4.1).  The
+ * correction is Delta(x) = u_P(x) - u_1(x): the single layer of curve c
+ * evaluated on P*N nodes obtained by FFT upsampling of the curve and its
+ * density (the paper represents curves in a Fourier basis), minus the N-node
+ * trapezoid value; images and other curves are not involved.  Curves must
+ * have an even node count N with 8 <= N <= 256 and P*N <= 2048.
+ * ------------------------------------------------------------------------- */
+#define S2D_NEAR_NFEAT 20            /* features per target */
+#define S2D_MLP_NPARAM 9834          /* FP32 master parameters of the 20-64-64-64-2 network */
+
+typedef enum {
+    S2D_NEAR_UPSAMPLE = 0,           /* FP64 upsampled quadrature for every target */
+    S2D_NEAR_MLP = 1,                /* BF16 MLP for every target, no fallback */
+    S2D_NEAR_AUTO = 2                /* MLP where its calibrated bound <= threshold, else upsampled */
+} s2d_near_method;
+
+/* Workspace bytes for near_correct_eval. */
+S2D_API size_t near_workspace_size(int method, const s2d_curves *ves, const s2d_targets *trg, int32_t upsample);
+
+/* Delta at every target (du, dv: [n] device FP64, written).  trg->on_curve /
+ * on_node are ignored; trg_curve[i] names the curve of `ves` the correction
+ * is for.  upsample = P (1..32).  mlp: device blob from near_mlp_pack (MLP,
+ * AUTO).  threshold: AUTO falls back for a target when its bin's calibrated
+ * error bound, in velocity units, exceeds it.  used_fallback: [n] device
+ * int32 or NULL, set to 1 where the upsampled quadrature was used (AUTO).
+ * Targets of invalid curves get NaN. */
+S2D_API int near_correct_eval(int method, const s2d_curves *ves, const s2d_targets *trg,
+                              const int32_t *trg_curve, int32_t upsample, const void *mlp,
+                              double threshold, double mu, double *du, double *dv,
+                              int32_t *used_fallback, void *ws, size_t ws_bytes, void *stream);
+
+/* Target features X ([n][20] FP32: tangential and normal offset from node
+ * k0 in units of h, distance to the nearest node / h, kappa h, and the
+ * densities of nodes k0-3..k0+4 in the local frame divided by their largest
+ * norm F) and frames ([n][6] FP64: t0, n0, h, F). */
+S2D_API int near_features_eval(const s2d_curves *ves, const s2d_targets *trg, const int32_t *trg_curve,
+                               float *X, double *frame, void *stream);
+
+/* Training labels in the local frame: Y = (Delta . t0, Delta . n0) 4 pi mu / (h F). */
+S2D_API int near_scale_labels(int64_t n, const double *du, const double *dv, const double *frame,
+                              double mu, float *Y, void *stream);
+
+/* Workspace bytes for a training step with `batch` samples. */
+S2D_API size_t near_mlp_train_workspace_size(int32_t batch);
+
+/* One minibatch step of MSE training, L = 1/(2B) sum ||net(X_idx) - Y_idx||^2:
+ * forward, backward and per-parameter gradient sums over the batch in fixed
+ * sample order, then an Adam update (beta 0.9, 0.999, eps 1e-8) at
+ * step >= 1; step == 0 computes grad and loss only.  params, adam_m,
+ * adam_v, grad: [S2D_MLP_NPARAM] device FP32 (the first 40 entries are the
+ * input standardisation mean and scale, not trained).  loss: device float
+ * or NULL.  idx: [batch] sample indices into X / Y, or NULL for 0..batch-1. */
+S2D_API int near_mlp_train_step(int32_t batch, const int32_t *idx, const float *X, const float *Y,
+                                float *params, float *adam_m, float *adam_v, int32_t step, float lr,
+                                float *grad, float *loss, void *ws, size_t ws_bytes, void *stream);
+
+/* FP32 forward pass of the master parameters: Y [n][2]. */
+S2D_API int near_mlp_forward(int64_t n, const float *X, const float *params, float *Y, void *stream);
+
+/* Bytes of the BF16 inference blob; near_mlp_pack fills it from FP32 master
+ * parameters and a calibrated error bound per bin of log10(|normal offset| / h)
+ * (n_bins <= 64 bins of width bin_w starting at bin_lo), in the scaled output
+ * units of near_scale_labels. */
+S2D_API size_t near_mlp_blob_size(void);
+S2D_API int near_mlp_pack(const float *params, const float *bound, int32_t n_bins, float bin_lo,
+                          float bin_w, void *blob, void *stream);
+
 /* Benchmarking aid (not capturable, not for production loops): while
  * enabled, each evaluation records a HIP event pair around its pair-sum
  * kernel launch on the caller's stream.  stokes2d_profile_read() waits for

@@ -2,6 +2,7 @@
 // and the launch sequence for each evaluation.  No allocation happens here:
 // all scratch lives in the caller's workspace.
 #include "s2d_internal.h"
+#include "s2d_near.h"
 
 #include <algorithm>
 #include <cmath>
@@ -340,6 +341,184 @@ S2D_API int stokes2d_batch_eval(int mode, int32_t n_inst, const s2d_instance *in
 }
 
 S2D_API int stokes2d_batch_release(void) { return s2d::batch_release(); }
+
+// ---------------------------------------------------------------------------
+// near-field correction
+// ---------------------------------------------------------------------------
+namespace {
+
+struct NearLayout {
+    size_t up, X, frame, list, count, total;
+};
+
+NearLayout near_layout(int method, const s2d_curves *c, const s2d_targets *t, int P) {
+    NearLayout L{};
+    size_t off = 0;
+    L.up = off;
+    if (method != S2D_NEAR_MLP) off = align256(off + 5 * (size_t)P * (size_t)c->n_nodes * sizeof(double));
+    L.X = off;
+    if (method != S2D_NEAR_UPSAMPLE) {
+        off = align256(off + (size_t)t->n * s2d::kNearFeat * sizeof(float));
+        L.frame = off;
+        off = align256(off + (size_t)t->n * 6 * sizeof(double));
+        L.list = off;
+        off = align256(off + (size_t)t->n * sizeof(int32_t));
+        L.count = off;
+        off = align256(off + sizeof(int32_t));
+    } else {
+        L.frame = L.list = L.count = off;
+    }
+    L.total = std::max<size_t>(off, 256);
+    return L;
+}
+
+int check_near(int method, const s2d_curves *c, const s2d_targets *t, const int32_t *tc, int P, double mu) {
+    if (method < S2D_NEAR_UPSAMPLE || method > S2D_NEAR_AUTO) return fail(S2D_EINVAL, "unknown near method");
+    if (!c || !t) return fail(S2D_EINVAL, "ves and trg must not be NULL");
+    if (c->n_nodes < 0 || c->n_nodes > INT32_MAX / 32 || c->n_curves < 0 || t->n < 0 || t->n > INT32_MAX)
+        return fail(S2D_EINVAL, "sizes out of range");
+    if (c->n_nodes > 0 && (!c->x || !c->y || !c->nx || !c->ny || !c->w || !c->kappa || !c->fx || !c->fy ||
+                           !c->curve_off))
+        return fail(S2D_EINVAL, "ves arrays (x, y, nx, ny, w, kappa, fx, fy, curve_off) must not be NULL");
+    if (t->n > 0 && (!t->x || !t->y || !tc)) return fail(S2D_EINVAL, "trg x, y and trg_curve must not be NULL");
+    if (P < 1 || P > 32) return fail(S2D_EINVAL, "upsample factor must be in 1..32");
+    if (!(std::isfinite(mu) && mu > 0.0)) return fail(S2D_EINVAL, "mu must be finite and > 0");
+    return S2D_OK;
+}
+
+}  // namespace
+
+S2D_API size_t near_workspace_size(int method, const s2d_curves *ves, const s2d_targets *trg, int32_t upsample) {
+    if (!ves || !trg || upsample < 1 || upsample > 32 || method < 0 || method > 2) return 0;
+    return near_layout(method, ves, trg, upsample).total;
+}
+
+S2D_API int near_correct_eval(int method, const s2d_curves *ves, const s2d_targets *trg, const int32_t *trg_curve,
+                              int32_t upsample, const void *mlp, double threshold, double mu, double *du,
+                              double *dv, int32_t *used_fallback, void *ws, size_t ws_bytes, void *stream) {
+    int rc = check_near(method, ves, trg, trg_curve, upsample, mu);
+    if (rc != S2D_OK) return rc;
+    if (method != S2D_NEAR_UPSAMPLE && !mlp) return fail(S2D_EINVAL, "MLP methods need the packed network");
+    if (method == S2D_NEAR_AUTO && !(threshold >= 0.0)) return fail(S2D_EINVAL, "threshold must be >= 0");
+    int dev = 0;
+    rc = current_device(&dev);
+    if (rc != S2D_OK) return rc;
+    if (trg->n == 0) return S2D_OK;
+    if (!du || !dv) return fail(S2D_EINVAL, "outputs du, dv must not be NULL");
+    const NearLayout L = near_layout(method, ves, trg, upsample);
+    if (!ws || ws_bytes < L.total)
+        return fail(S2D_EWORKSPACE, "near workspace too small: need " + std::to_string(L.total) + " bytes");
+    if (((uintptr_t)ws & 255) != 0) return fail(S2D_EWORKSPACE, "workspace must be 256-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    char *w = (char *)ws;
+    double *up = (double *)(w + L.up);
+    hipError_t e = hipSuccess;
+    if (method != S2D_NEAR_MLP) {
+        e = s2d::near_launch_upsample(ves, upsample, up, st);
+        if (e != hipSuccess) return hip_fail(e, "near upsample launch");
+    }
+    if (method == S2D_NEAR_UPSAMPLE) {
+        e = s2d::near_launch_quad(ves, trg, trg_curve, nullptr, nullptr, upsample, up, mu, du, dv, st);
+        if (e != hipSuccess) return hip_fail(e, "near quadrature launch");
+        return S2D_OK;
+    }
+    float *X = (float *)(w + L.X);
+    double *frame = (double *)(w + L.frame);
+    int32_t *list = (int32_t *)(w + L.list);
+    int32_t *count = (int32_t *)(w + L.count);
+    e = s2d::near_launch_features(ves, trg, trg_curve, X, frame, st);
+    if (e != hipSuccess) return hip_fail(e, "near features launch");
+    const bool autom = method == S2D_NEAR_AUTO;
+    int32_t *flag = used_fallback;
+    e = s2d::near_launch_infer(trg->n, X, frame, (const s2d::NearBlob *)mlp, mu, threshold, autom ? 1 : 0, du, dv,
+                               flag, list, count, st);
+    if (e != hipSuccess) return hip_fail(e, "near MLP launch");
+    if (autom) {
+        e = s2d::near_launch_quad(ves, trg, trg_curve, list, count, upsample, up, mu, du, dv, st);
+        if (e != hipSuccess) return hip_fail(e, "near fallback launch");
+    }
+    return S2D_OK;
+}
+
+S2D_API int near_features_eval(const s2d_curves *ves, const s2d_targets *trg, const int32_t *trg_curve, float *X,
+                               double *frame, void *stream) {
+    int rc = check_near(S2D_NEAR_MLP, ves, trg, trg_curve, 1, 1.0);
+    if (rc != S2D_OK) return rc;
+    int dev = 0;
+    rc = current_device(&dev);
+    if (rc != S2D_OK) return rc;
+    if (trg->n == 0) return S2D_OK;
+    if (!X || !frame) return fail(S2D_EINVAL, "X and frame must not be NULL");
+    hipError_t e = s2d::near_launch_features(ves, trg, trg_curve, X, frame, (hipStream_t)stream);
+    return e == hipSuccess ? S2D_OK : hip_fail(e, "near features launch");
+}
+
+S2D_API int near_scale_labels(int64_t n, const double *du, const double *dv, const double *frame, double mu,
+                              float *Y, void *stream) {
+    if (n < 0) return fail(S2D_EINVAL, "n < 0");
+    if (n > 0 && (!du || !dv || !frame || !Y)) return fail(S2D_EINVAL, "arrays must not be NULL");
+    if (!(std::isfinite(mu) && mu > 0.0)) return fail(S2D_EINVAL, "mu must be finite and > 0");
+    int dev = 0;
+    int rc = current_device(&dev);
+    if (rc != S2D_OK) return rc;
+    hipError_t e = s2d::near_launch_scale_labels(n, du, dv, frame, mu, Y, (hipStream_t)stream);
+    return e == hipSuccess ? S2D_OK : hip_fail(e, "label scaling launch");
+}
+
+S2D_API size_t near_mlp_train_workspace_size(int32_t batch) {
+    if (batch <= 0) return 0;
+    return align256((size_t)batch * s2d::kActStride * sizeof(float)) + align256((size_t)batch * 2 * sizeof(float)) +
+           align256((size_t)batch * sizeof(float));
+}
+
+S2D_API int near_mlp_train_step(int32_t batch, const int32_t *idx, const float *X, const float *Y, float *params,
+                                float *adam_m, float *adam_v, int32_t step, float lr, float *grad, float *loss,
+                                void *ws, size_t ws_bytes, void *stream) {
+    if (batch <= 0 || batch > (1 << 22)) return fail(S2D_EINVAL, "batch must be in 1..4194304");
+    if (!X || !Y || !params || !grad) return fail(S2D_EINVAL, "X, Y, params, grad must not be NULL");
+    if (step > 0 && (!adam_m || !adam_v)) return fail(S2D_EINVAL, "Adam state must not be NULL when step > 0");
+    if (step < 0) return fail(S2D_EINVAL, "step < 0");
+    if (!(std::isfinite(lr) && lr >= 0.f)) return fail(S2D_EINVAL, "lr must be finite and >= 0");
+    int dev = 0;
+    int rc = current_device(&dev);
+    if (rc != S2D_OK) return rc;
+    const size_t need = near_mlp_train_workspace_size(batch);
+    if (!ws || ws_bytes < need) return fail(S2D_EWORKSPACE, "train workspace too small: need " + std::to_string(need));
+    if (((uintptr_t)ws & 255) != 0) return fail(S2D_EWORKSPACE, "workspace must be 256-byte aligned");
+    char *w = (char *)ws;
+    float *act = (float *)w;
+    float *dY = (float *)(w + align256((size_t)batch * s2d::kActStride * sizeof(float)));
+    float *lossv = (float *)((char *)dY + align256((size_t)batch * 2 * sizeof(float)));
+    hipError_t e = s2d::near_launch_train_step(batch, idx, X, Y, params, adam_m, adam_v, step, lr, grad, act, dY,
+                                               lossv, loss, step > 0 ? 1 : 0, (hipStream_t)stream);
+    return e == hipSuccess ? S2D_OK : hip_fail(e, "train step launch");
+}
+
+S2D_API int near_mlp_forward(int64_t n, const float *X, const float *params, float *Y, void *stream) {
+    if (n < 0) return fail(S2D_EINVAL, "n < 0");
+    if (n > 0 && (!X || !params || !Y)) return fail(S2D_EINVAL, "arrays must not be NULL");
+    int dev = 0;
+    int rc = current_device(&dev);
+    if (rc != S2D_OK) return rc;
+    hipError_t e = s2d::near_launch_fwd(n, X, params, Y, (hipStream_t)stream);
+    return e == hipSuccess ? S2D_OK : hip_fail(e, "MLP forward launch");
+}
+
+S2D_API size_t near_mlp_blob_size(void) { return align256(sizeof(s2d::NearBlob)); }
+
+S2D_API int near_mlp_pack(const float *params, const float *bound, int32_t n_bins, float bin_lo, float bin_w,
+                          void *blob, void *stream) {
+    if (!params || !blob) return fail(S2D_EINVAL, "params and blob must not be NULL");
+    if (n_bins < 0 || n_bins > s2d::kNearMaxBins) return fail(S2D_EINVAL, "n_bins must be in 0..64");
+    if (n_bins > 0 && !bound) return fail(S2D_EINVAL, "bound must not be NULL when n_bins > 0");
+    if (!(bin_w > 0.f) || !std::isfinite(bin_lo)) return fail(S2D_EINVAL, "bin_w must be > 0");
+    int dev = 0;
+    int rc = current_device(&dev);
+    if (rc != S2D_OK) return rc;
+    hipError_t e = s2d::near_launch_pack(params, bound, n_bins, bin_lo, bin_w, (s2d::NearBlob *)blob,
+                                         (hipStream_t)stream);
+    return e == hipSuccess ? S2D_OK : hip_fail(e, "MLP pack launch");
+}
 
 S2D_API const char *stokes2d_last_error(void) { return g_err.c_str(); }
 

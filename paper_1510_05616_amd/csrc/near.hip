@@ -1,0 +1,597 @@
+// Near-field correction of the single layer for targets within a few node
+// spacings of a closed curve.
+//
+// The periodic trapezoid rule loses accuracy for targets close to a curve
+// (the paper notes this for the channel walls, Section 4.1 footnote and the
+// error band of its serpentine-channel figure, and uses a dedicated close
+// evaluation scheme for near vesicle pairs, Section 3.3).  Here the
+// correction Delta = u_P(x) - u_1(x) of one curve's single layer is computed
+// either by FFT-upsampled quadrature (the reference and fallback) or by a
+// small MLP that predicts it from local features.
+//
+//  * upsample: per curve (one workgroup), the N-node samples of x, y, f are
+//    expanded in their discrete Fourier coefficients and evaluated at P*N
+//    equispaced parameter nodes (Nyquist mode split evenly); the speed comes
+//    from the spectral derivative, weights (2 pi / (P N)) |x'|.  FP64.
+//  * quadrature: per target, the fine trapezoid sum minus the coarse one,
+//    FP64, over the target's own curve.
+//  * features: per target, nearest node k* by a scan of the curve, k0 = k* or
+//    k* - 1 so that the target lies over [k0, k0+1), the local frame of k0,
+//    offsets and distance in units of h = (sum w) / N, kappa h, and the
+//    densities of nodes k0-3..k0+4 rotated into the frame and divided by
+//    their largest norm F.
+//  * MLP inference: 20 -> 64 -> 64 -> 64 -> 2, tanh-form GELU; weights and
+//    activations rounded to BF16, products accumulated in FP32 with the
+//    gfx950 v_dot2c_f32_bf16 instruction (weights wave-uniform, read through
+//    the scalar path).  The output is the correction in the local frame in
+//    units of h F / (4 pi mu).  A per-bin error bound (bins in the normal
+//    offset) calibrated on validation data decides the fallback to the
+//    upsampled quadrature.
+//  * training (FP32 master weights): per-sample forward, per-sample backward
+//    deltas, per-weight gradient sums over the batch in fixed order, and an
+//    Adam update; all deterministic.
+#include "pair_impl.h"
+#include "s2d_near.h"
+
+#include <algorithm>
+
+namespace s2d {
+
+// ---------------------------------------------------------------------------
+// a8: upsampling and FP64 quadrature
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void near_upsample(const int32_t *__restrict__ off, int32_t n_curves, int64_t n_src,
+                                                     const double *__restrict__ x, const double *__restrict__ y,
+                                                     const double *__restrict__ fx, const double *__restrict__ fy,
+                                                     int P, double *__restrict__ up /* [5][P n_src] */) {
+    extern __shared__ double lds[];
+    const int c = blockIdx.x;
+    if (c >= n_curves) return;
+    const int lo = off[c], N = off[c + 1] - lo;
+    if (N < 4 || (N & 1) || N > kUpMaxN || lo < 0 || (int64_t)lo + N > n_src || P * N > kUpMaxM) return;
+    const int M = P * N, H = N / 2;
+    double *ct = lds;                 // cos(2 pi j / M), j < M
+    double *st = ct + M;              // sin(2 pi j / M)
+    double *A = st + M;               // [4][H + 1] cosine coefficients
+    double *B = A + 4 * (H + 1);      // [4][H + 1] sine coefficients
+    for (int j = threadIdx.x; j < M; j += blockDim.x) {
+        double s, co;
+        sincospi(2.0 * (double)j / (double)M, &s, &co);
+        ct[j] = co;
+        st[j] = s;
+    }
+    __syncthreads();
+    const double *sig[4] = {x + lo, y + lo, fx + lo, fy + lo};
+    for (int q = threadIdx.x; q < 4 * (H + 1); q += blockDim.x) {
+        const int s = q / (H + 1), m = q % (H + 1);
+        const double *v = sig[s];
+        double a = 0.0, b = 0.0;
+        for (int k = 0; k < N; ++k) {
+            const int idx = (int)(((int64_t)m * k * P) % M);     // angle 2 pi m k / N
+            a += v[k] * ct[idx];
+            b += v[k] * st[idx];
+        }
+        A[q] = a;
+        B[q] = b;
+    }
+    __syncthreads();
+    const double inv = 1.0 / (double)N;
+    const int64_t base = (int64_t)lo * P;
+    const int64_t plane = (int64_t)n_src * P;
+    for (int j = threadIdx.x; j < M; j += blockDim.x) {
+        double val[4], der[2];
+        for (int s = 0; s < 4; ++s) {
+            const double *As = A + s * (H + 1), *Bs = B + s * (H + 1);
+            double v = As[0], dv = 0.0;
+            for (int m = 1; m < H; ++m) {
+                const int idx = (int)(((int64_t)m * j) % M);
+                v += 2.0 * (As[m] * ct[idx] + Bs[m] * st[idx]);
+                if (s < 2) dv += 2.0 * (double)m * (Bs[m] * ct[idx] - As[m] * st[idx]);
+            }
+            const int idx = (int)(((int64_t)H * j) % M);
+            v += As[H] * ct[idx];
+            if (s < 2) dv -= (double)H * As[H] * st[idx];
+            val[s] = v * inv;
+            if (s < 2) der[s] = dv * inv;
+        }
+        const double sp = sqrt(der[0] * der[0] + der[1] * der[1]);
+        up[base + j] = val[0];
+        up[plane + base + j] = val[1];
+        up[2 * plane + base + j] = (2.0 * M_PI / (double)M) * sp;
+        up[3 * plane + base + j] = val[2];
+        up[4 * plane + base + j] = val[3];
+    }
+}
+
+__device__ __forceinline__ void slp64_acc(double px, double py, double sx, double sy, double gx, double gy,
+                                          double &ax, double &ay, double &bx, double &by) {
+    const double rx = px - sx, ry = py - sy;
+    const double q = __builtin_fma(rx, rx, ry * ry);
+    const double lq = log64(q);
+    const double t = __builtin_fma(rx, gx, ry * gy) * rcp64(q);
+    ax = __builtin_fma(gx, lq, ax);
+    ay = __builtin_fma(gy, lq, ay);
+    bx = __builtin_fma(rx, t, bx);
+    by = __builtin_fma(ry, t, by);
+}
+
+// Delta for target i (or list[i] when list != NULL, up to *count entries).
+__global__ __launch_bounds__(256) void near_quad(int64_t n_trg, const int32_t *__restrict__ list,
+                                                 const int32_t *__restrict__ count, const double *__restrict__ tx,
+                                                 const double *__restrict__ ty, const int32_t *__restrict__ tc,
+                                                 const int32_t *__restrict__ off, int32_t n_curves, int64_t n_src,
+                                                 const double *__restrict__ x, const double *__restrict__ y,
+                                                 const double *__restrict__ w, const double *__restrict__ fx,
+                                                 const double *__restrict__ fy, int P, const double *__restrict__ up,
+                                                 double pref, double *__restrict__ du, double *__restrict__ dv) {
+    const int64_t n = list ? (int64_t)*count : n_trg;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = list ? list[q] : q;
+        const int c = tc[i];
+        const int lo = (c >= 0 && c < n_curves) ? off[c] : 0;
+        const int N = (c >= 0 && c < n_curves) ? off[c + 1] - lo : 0;
+        if (c < 0 || c >= n_curves || N < 4 || (N & 1) || N > kUpMaxN || P * N > kUpMaxM || lo < 0 ||
+            (int64_t)lo + N > n_src) {
+            du[i] = dv[i] = __builtin_nan("");
+            continue;
+        }
+        const double px = tx[i], py = ty[i];
+        double a0 = 0, a1 = 0, b0 = 0, b1 = 0, c0 = 0, c1 = 0, d0 = 0, d1 = 0;
+        for (int k = lo; k < lo + N; ++k)
+            slp64_acc(px, py, x[k], y[k], w[k] * fx[k], w[k] * fy[k], a0, a1, b0, b1);
+        const int64_t plane = n_src * (int64_t)P, base = (int64_t)lo * P;
+        for (int64_t k = base; k < base + (int64_t)N * P; ++k) {
+            const double ww = up[2 * plane + k];
+            slp64_acc(px, py, up[k], up[plane + k], ww * up[3 * plane + k], ww * up[4 * plane + k], c0, c1, d0, d1);
+        }
+        du[i] = pref * ((-0.5 * c0 + d0) - (-0.5 * a0 + b0));
+        dv[i] = pref * ((-0.5 * c1 + d1) - (-0.5 * a1 + b1));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a9: features
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void near_features(int64_t n_trg, const double *__restrict__ tx,
+                                                     const double *__restrict__ ty, const int32_t *__restrict__ tc,
+                                                     const int32_t *__restrict__ off, int32_t n_curves, int64_t n_src,
+                                                     const double *__restrict__ x, const double *__restrict__ y,
+                                                     const double *__restrict__ nx, const double *__restrict__ ny,
+                                                     const double *__restrict__ kap, const double *__restrict__ w,
+                                                     const double *__restrict__ fx, const double *__restrict__ fy,
+                                                     float *__restrict__ X, double *__restrict__ frame) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_trg) return;
+    const int c = tc[i];
+    const int lo = (c >= 0 && c < n_curves) ? off[c] : 0;
+    const int N = (c >= 0 && c < n_curves) ? off[c + 1] - lo : 0;
+    float *xi = X + i * kNearFeat;
+    double *fr = frame + i * 6;
+    if (c < 0 || c >= n_curves || N < 8 || lo < 0 || (int64_t)lo + N > n_src) {
+        for (int k = 0; k < kNearFeat; ++k) xi[k] = __builtin_nanf("");
+        for (int k = 0; k < 6; ++k) fr[k] = __builtin_nan("");
+        return;
+    }
+    const double px = tx[i], py = ty[i];
+    double best = 1e300, wsum = 0.0;
+    int ks = 0;
+    for (int k = 0; k < N; ++k) {
+        const double dx = px - x[lo + k], dy = py - y[lo + k];
+        const double d2 = dx * dx + dy * dy;
+        if (d2 < best) { best = d2; ks = k; }
+        wsum += w[lo + k];
+    }
+    const double h = wsum / (double)N;
+    const double ts0 = -ny[lo + ks], ts1 = nx[lo + ks];
+    const int k0 = ((px - x[lo + ks]) * ts0 + (py - y[lo + ks]) * ts1 >= 0.0) ? ks : (ks + N - 1) % N;
+    const double t0 = -ny[lo + k0], t1 = nx[lo + k0];
+    const double n0 = nx[lo + k0], n1 = ny[lo + k0];
+    const double ox = px - x[lo + k0], oy = py - y[lo + k0];
+    double ft[8], fn[8], F = 0.0;
+    for (int j = 0; j < 8; ++j) {
+        const int k = lo + (k0 + j - 3 + N) % N;
+        ft[j] = fx[k] * t0 + fy[k] * t1;
+        fn[j] = fx[k] * n0 + fy[k] * n1;
+        F = fmax(F, sqrt(ft[j] * ft[j] + fn[j] * fn[j]));
+    }
+    if (F == 0.0) F = 1.0;
+    xi[0] = (float)((ox * t0 + oy * t1) / h);
+    xi[1] = (float)((ox * n0 + oy * n1) / h);
+    xi[2] = (float)(sqrt(best) / h);
+    xi[3] = (float)(kap[lo + k0] * h);
+    for (int j = 0; j < 8; ++j) {
+        xi[4 + j] = (float)(ft[j] / F);
+        xi[12 + j] = (float)(fn[j] / F);
+    }
+    fr[0] = t0;
+    fr[1] = t1;
+    fr[2] = n0;
+    fr[3] = n1;
+    fr[4] = h;
+    fr[5] = F;
+}
+
+// scaled labels in the local frame: (Delta . t0, Delta . n0) * 4 pi mu / (h F)
+__global__ __launch_bounds__(256) void near_scale_labels_k(int64_t n, const double *__restrict__ du,
+                                                           const double *__restrict__ dv,
+                                                           const double *__restrict__ frame, double mu,
+                                                           float *__restrict__ Y) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double *fr = frame + 6 * i;
+    const double sc = 4.0 * M_PI * mu / (fr[4] * fr[5]);
+    Y[2 * i] = (float)((du[i] * fr[0] + dv[i] * fr[1]) * sc);
+    Y[2 * i + 1] = (float)((du[i] * fr[2] + dv[i] * fr[3]) * sc);
+}
+
+// ---------------------------------------------------------------------------
+// MLP pieces
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float gelu_f(float z) {
+    const float u = 0.7978845608028654f * (z + 0.044715f * z * z * z);
+    // tanh(u) = 1 - 2 / (exp(2u) + 1); exp via the hardware exp2
+    const float e = __builtin_amdgcn_exp2f(fminf(2.8853900817779268f * u, 126.f));
+    const float th = 1.f - 2.f * __builtin_amdgcn_rcpf(e + 1.f);
+    return 0.5f * z * (1.f + th);
+}
+
+__device__ __forceinline__ float gelu_grad_f(float z) {
+    const float u = 0.7978845608028654f * (z + 0.044715f * z * z * z);
+    const float e = __builtin_amdgcn_exp2f(fminf(2.8853900817779268f * u, 126.f));
+    const float th = 1.f - 2.f * __builtin_amdgcn_rcpf(e + 1.f);
+    const float du = 0.7978845608028654f * (1.f + 3.f * 0.044715f * z * z);
+    return 0.5f * (1.f + th) + 0.5f * z * (1.f - th * th) * du;
+}
+
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
+    // round to nearest even, as the hardware conversion does
+    bf16x2_t v;
+    v[0] = (__bf16)a;
+    v[1] = (__bf16)b;
+    return __builtin_bit_cast(uint32_t, v);
+}
+
+__device__ __forceinline__ float dot2_bf16(uint32_t a, uint32_t b, float c) {
+    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a), __builtin_bit_cast(bf16x2_t, b), c,
+                                           false);
+}
+
+// One dense layer of the BF16 network: out[o] = b[o] + sum_k W[o][k] in[k],
+// with in[] packed as bf16 pairs and W as [out][in/2] bf16 pairs.
+template <int IN2, int OUT, bool ACT>
+__device__ __forceinline__ void bf16_layer(const uint32_t *__restrict__ W, const float *__restrict__ b,
+                                           const uint32_t (&in)[IN2], uint32_t (&out)[OUT / 2]) {
+#pragma unroll
+    for (int o = 0; o < OUT; o += 2) {
+        float a0 = b[o], a1 = b[o + 1];
+#pragma unroll
+        for (int k = 0; k < IN2; ++k) {
+            a0 = dot2_bf16(W[o * IN2 + k], in[k], a0);
+            a1 = dot2_bf16(W[(o + 1) * IN2 + k], in[k], a1);
+        }
+        if (ACT) {
+            a0 = gelu_f(a0);
+            a1 = gelu_f(a1);
+        }
+        out[o / 2] = pack_bf16(a0, a1);
+    }
+}
+
+// MLP inference with fallback decision.  blob: the packed BF16 network.
+__global__ __launch_bounds__(256) void near_mlp_infer(int64_t n_trg, const float *__restrict__ X,
+                                                      const double *__restrict__ frame, const NearBlob *__restrict__ nb,
+                                                      double mu, double threshold, int use_bound,
+                                                      double *__restrict__ du, double *__restrict__ dv,
+                                                      int32_t *__restrict__ flag, int32_t *__restrict__ list,
+                                                      int32_t *__restrict__ count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_trg) return;
+    const float *xi = X + i * kNearFeat;
+    uint32_t h0[kNearFeat / 2];
+#pragma unroll
+    for (int k = 0; k < kNearFeat; k += 2)
+        h0[k / 2] = pack_bf16((xi[k] - nb->mu_in[k]) * nb->isd_in[k], (xi[k + 1] - nb->mu_in[k + 1]) * nb->isd_in[k + 1]);
+    uint32_t h1[32], h2[32], h3[32];
+    bf16_layer<kNearFeat / 2, 64, true>(nb->W1, nb->b1, h0, h1);
+    bf16_layer<32, 64, true>(nb->W2, nb->b2, h1, h2);
+    bf16_layer<32, 64, true>(nb->W3, nb->b3, h2, h3);
+    float y0 = nb->b4[0], y1 = nb->b4[1];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+        y0 = dot2_bf16(nb->W4[k], h3[k], y0);
+        y1 = dot2_bf16(nb->W4[32 + k], h3[k], y1);
+    }
+    const double *fr = frame + 6 * i;
+    const double sc = fr[4] * fr[5] / (4.0 * M_PI * mu);
+    // fallback decision from the calibrated bound of the target's bin
+    int fb = 0;
+    if (use_bound) {
+        const float noff = fabsf(xi[1]);
+        int bin = (int)floorf((log10f(fmaxf(noff, 1e-30f)) - nb->bin_lo) / nb->bin_w);
+        bin = bin < 0 ? 0 : (bin >= nb->n_bins ? nb->n_bins - 1 : bin);
+        fb = ((double)nb->bound[bin] * sc > threshold) || !(noff == noff);
+    }
+    if (fb) {
+        if (flag) flag[i] = 1;
+        const int slot = atomicAdd(count, 1);
+        list[slot] = (int32_t)i;
+        return;                        // the quadrature kernel writes du, dv
+    }
+    if (flag) flag[i] = 0;
+    du[i] = sc * ((double)y0 * fr[0] + (double)y1 * fr[2]);
+    dv[i] = sc * ((double)y0 * fr[1] + (double)y1 * fr[3]);
+}
+
+__global__ void near_zero_count(int32_t *count) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *count = 0;
+}
+
+// Pack FP32 master parameters into the BF16 inference blob.
+__global__ __launch_bounds__(256) void near_pack(const float *__restrict__ prm, const float *__restrict__ bound,
+                                                 int32_t n_bins, float bin_lo, float bin_w, NearBlob *__restrict__ nb) {
+    const MlpOffsets O;
+    constexpr int r0 = kNearFeat;                  // W1 pairs
+    constexpr int r1 = r0 + 64 * kNearFeat / 2;    // W2
+    constexpr int r2 = r1 + 64 * 32;               // W3
+    constexpr int r3 = r2 + 64 * 32;               // W4
+    constexpr int r4 = r3 + 2 * 32;                // biases, bounds
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < kNearBlobWork; q += gridDim.x * blockDim.x) {
+        if (q < r0) {
+            nb->mu_in[q] = prm[O.mu + q];
+            nb->isd_in[q] = 1.f / prm[O.sd + q];
+        } else if (q < r1) {
+            const int r = q - r0, o = r / (kNearFeat / 2), k = r % (kNearFeat / 2);
+            nb->W1[r] = pack_bf16(prm[O.W1 + (2 * k) * 64 + o], prm[O.W1 + (2 * k + 1) * 64 + o]);
+        } else if (q < r2) {
+            const int r = q - r1, o = r / 32, k = r % 32;
+            nb->W2[r] = pack_bf16(prm[O.W2 + (2 * k) * 64 + o], prm[O.W2 + (2 * k + 1) * 64 + o]);
+        } else if (q < r3) {
+            const int r = q - r2, o = r / 32, k = r % 32;
+            nb->W3[r] = pack_bf16(prm[O.W3 + (2 * k) * 64 + o], prm[O.W3 + (2 * k + 1) * 64 + o]);
+        } else if (q < r4) {
+            const int r = q - r3, o = r / 32, k = r % 32;
+            nb->W4[r] = pack_bf16(prm[O.W4 + (2 * k) * 2 + o], prm[O.W4 + (2 * k + 1) * 2 + o]);
+        } else {
+            const int o = q - r4;                  // 0 .. 63
+            nb->b1[o] = prm[O.b1 + o];
+            nb->b2[o] = prm[O.b2 + o];
+            nb->b3[o] = prm[O.b3 + o];
+            if (o < 2) nb->b4[o] = prm[O.b4 + o];
+            nb->bound[o] = o < n_bins ? bound[o] : 0.f;
+            if (o == 0) {
+                nb->n_bins = n_bins;
+                nb->bin_lo = bin_lo;
+                nb->bin_w = bin_w;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a11: training (FP32)
+// ---------------------------------------------------------------------------
+// per sample: forward, loss term, output delta dY = (Y - T) / B, and the
+// pre-activations z1..z3 and activations h0..h3 kept for the backward pass
+__global__ __launch_bounds__(256) void mlp_fwd(int32_t B, const int32_t *__restrict__ idx,
+                                               const float *__restrict__ X, const float *__restrict__ T,
+                                               const float *__restrict__ prm, float *__restrict__ act,
+                                               float *__restrict__ dY, float *__restrict__ lossv) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= B) return;
+    const MlpOffsets O;
+    const int64_t i = idx ? idx[s] : s;
+    float *A = act + (int64_t)s * kActStride;   // h0[20] z1[64] h1[64] z2[64] h2[64] z3[64] h3[64]
+    float *h0 = A, *z1 = A + 20, *h1 = A + 84, *z2 = A + 148, *h2 = A + 212, *z3 = A + 276, *h3 = A + 340;
+    for (int k = 0; k < kNearFeat; ++k) h0[k] = (X[i * kNearFeat + k] - prm[O.mu + k]) / prm[O.sd + k];
+    for (int o = 0; o < 64; ++o) {
+        float a = prm[O.b1 + o];
+        for (int k = 0; k < kNearFeat; ++k) a = fmaf(h0[k], prm[O.W1 + k * 64 + o], a);
+        z1[o] = a;
+        h1[o] = gelu_f(a);
+    }
+    for (int o = 0; o < 64; ++o) {
+        float a = prm[O.b2 + o];
+        for (int k = 0; k < 64; ++k) a = fmaf(h1[k], prm[O.W2 + k * 64 + o], a);
+        z2[o] = a;
+        h2[o] = gelu_f(a);
+    }
+    for (int o = 0; o < 64; ++o) {
+        float a = prm[O.b3 + o];
+        for (int k = 0; k < 64; ++k) a = fmaf(h2[k], prm[O.W3 + k * 64 + o], a);
+        z3[o] = a;
+        h3[o] = gelu_f(a);
+    }
+    float l = 0.f;
+    for (int o = 0; o < 2; ++o) {
+        float a = prm[O.b4 + o];
+        for (int k = 0; k < 64; ++k) a = fmaf(h3[k], prm[O.W4 + k * 2 + o], a);
+        const float r = a - T[i * 2 + o];
+        dY[s * 2 + o] = r / (float)B;
+        l += r * r;
+    }
+    lossv[s] = 0.5f * l / (float)B;
+}
+
+// per sample: deltas d3, d2, d1 (stored over z3, z2, z1)
+__global__ __launch_bounds__(256) void mlp_bwd(int32_t B, const float *__restrict__ prm, float *__restrict__ act,
+                                               const float *__restrict__ dY) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= B) return;
+    const MlpOffsets O;
+    float *A = act + (int64_t)s * kActStride;
+    float *z1 = A + 20, *z2 = A + 148, *z3 = A + 276;
+    const float g0 = dY[2 * s], g1 = dY[2 * s + 1];
+    for (int k = 0; k < 64; ++k)
+        z3[k] = (prm[O.W4 + k * 2] * g0 + prm[O.W4 + k * 2 + 1] * g1) * gelu_grad_f(z3[k]);
+    for (int k = 0; k < 64; ++k) {
+        float a = 0.f;
+        for (int o = 0; o < 64; ++o) a = fmaf(prm[O.W3 + k * 64 + o], z3[o], a);
+        z2[k] = a * gelu_grad_f(z2[k]);
+    }
+    for (int k = 0; k < 64; ++k) {
+        float a = 0.f;
+        for (int o = 0; o < 64; ++o) a = fmaf(prm[O.W2 + k * 64 + o], z2[o], a);
+        z1[k] = a * gelu_grad_f(z1[k]);
+    }
+}
+
+// one thread per parameter: gradient summed over the batch in sample order;
+// thread 0 also sums the per-sample losses in sample order.
+__global__ __launch_bounds__(256) void mlp_grad(int32_t B, const float *__restrict__ act,
+                                                const float *__restrict__ dY, const float *__restrict__ lossv,
+                                                float *__restrict__ grad, float *__restrict__ loss) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const MlpOffsets O;
+    if (p >= O.total) return;
+    float g = 0.f;
+    int hin = -1, dl = -1, dk = 0, width = 64;   // activation column, delta column
+    if (p >= O.W1 && p < O.b1) { const int r = p - O.W1; hin = r / 64; dl = 20 + r % 64; }
+    else if (p >= O.b1 && p < O.W2) { dl = 20 + (p - O.b1); }
+    else if (p >= O.W2 && p < O.b2) { const int r = p - O.W2; hin = 84 + r / 64; dl = 148 + r % 64; }
+    else if (p >= O.b2 && p < O.W3) { dl = 148 + (p - O.b2); }
+    else if (p >= O.W3 && p < O.b3) { const int r = p - O.W3; hin = 212 + r / 64; dl = 276 + r % 64; }
+    else if (p >= O.b3 && p < O.W4) { dl = 276 + (p - O.b3); }
+    else if (p >= O.W4 && p < O.b4) { const int r = p - O.W4; hin = 340 + r / 2; dk = r % 2; width = 2; }
+    else if (p >= O.b4 && p < O.total) { dk = p - O.b4; width = 2; }
+    if (p == 0 && loss) {
+        float l = 0.f;
+        for (int s = 0; s < B; ++s) l += lossv[s];
+        *loss = l;
+    }
+    if (p < O.W1) {                               // mu_in / sd_in are not trained
+        grad[p] = 0.f;
+        return;
+    }
+    for (int s = 0; s < B; ++s) {
+        const float *A = act + (int64_t)s * kActStride;
+        const float d = width == 2 ? dY[2 * s + dk] : A[dl];
+        g = fmaf(hin >= 0 ? A[hin] : 1.f, d, g);
+    }
+    grad[p] = g;
+}
+
+__global__ __launch_bounds__(256) void mlp_adam(float *__restrict__ prm, const float *__restrict__ grad,
+                                                float *__restrict__ m, float *__restrict__ v, int32_t step, float lr,
+                                                float b1, float b2, float eps) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const MlpOffsets O;
+    if (p >= O.total || p < O.W1) return;
+    const float g = grad[p];
+    const float mm = b1 * m[p] + (1.f - b1) * g;
+    const float vv = b2 * v[p] + (1.f - b2) * g * g;
+    m[p] = mm;
+    v[p] = vv;
+    const float mh = mm / (1.f - powf(b1, (float)step));
+    const float vh = vv / (1.f - powf(b2, (float)step));
+    prm[p] -= lr * mh / (sqrtf(vh) + eps);
+}
+
+// FP32 forward only (reference-precision inference, gradient checks)
+__global__ __launch_bounds__(256) void mlp_fwd_only(int64_t n, const float *__restrict__ X,
+                                                    const float *__restrict__ prm, float *__restrict__ Y) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const MlpOffsets O;
+    float h0[kNearFeat], h1[64], h2[64];
+    for (int k = 0; k < kNearFeat; ++k) h0[k] = (X[i * kNearFeat + k] - prm[O.mu + k]) / prm[O.sd + k];
+    for (int o = 0; o < 64; ++o) {
+        float a = prm[O.b1 + o];
+        for (int k = 0; k < kNearFeat; ++k) a = fmaf(h0[k], prm[O.W1 + k * 64 + o], a);
+        h1[o] = gelu_f(a);
+    }
+    for (int o = 0; o < 64; ++o) {
+        float a = prm[O.b2 + o];
+        for (int k = 0; k < 64; ++k) a = fmaf(h1[k], prm[O.W2 + k * 64 + o], a);
+        h2[o] = gelu_f(a);
+    }
+    for (int o = 0; o < 64; ++o) {
+        float a = prm[O.b3 + o];
+        for (int k = 0; k < 64; ++k) a = fmaf(h2[k], prm[O.W3 + k * 64 + o], a);
+        h1[o] = gelu_f(a);
+    }
+    for (int o = 0; o < 2; ++o) {
+        float a = prm[O.b4 + o];
+        for (int k = 0; k < 64; ++k) a = fmaf(h1[k], prm[O.W4 + k * 2 + o], a);
+        Y[i * 2 + o] = a;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static unsigned grid_for(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t near_launch_upsample(const s2d_curves *c, int P, double *up, hipStream_t st) {
+    if (c->n_curves <= 0) return hipSuccess;
+    // LDS: 2 M cos/sin + 8 (H + 1) coefficients, at the largest sizes (41 KB)
+    const size_t lds = (2 * (size_t)kUpMaxM + 8 * ((size_t)kUpMaxN / 2 + 1)) * sizeof(double);
+    hipLaunchKernelGGL(near_upsample, dim3((unsigned)c->n_curves), dim3(256), lds, st, c->curve_off, c->n_curves,
+                       c->n_nodes, c->x, c->y, c->fx, c->fy, P, up);
+    return hipGetLastError();
+}
+
+hipError_t near_launch_quad(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, const int32_t *list,
+                            const int32_t *count, int P, const double *up, double mu, double *du, double *dv,
+                            hipStream_t st) {
+    if (t->n <= 0) return hipSuccess;
+    const unsigned g = list ? std::min<unsigned>(grid_for(t->n), 4096u) : grid_for(t->n);
+    hipLaunchKernelGGL(near_quad, dim3(g), dim3(256), 0, st, t->n, list, count, t->x, t->y, tc, c->curve_off,
+                       c->n_curves, c->n_nodes, c->x, c->y, c->w, c->fx, c->fy, P, up, 1.0 / (4.0 * M_PI * mu), du,
+                       dv);
+    return hipGetLastError();
+}
+
+hipError_t near_launch_features(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, float *X,
+                                double *frame, hipStream_t st) {
+    if (t->n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(near_features, dim3(grid_for(t->n)), dim3(256), 0, st, t->n, t->x, t->y, tc, c->curve_off,
+                       c->n_curves, c->n_nodes, c->x, c->y, c->nx, c->ny, c->kappa, c->w, c->fx, c->fy, X, frame);
+    return hipGetLastError();
+}
+
+hipError_t near_launch_scale_labels(int64_t n, const double *du, const double *dv, const double *frame, double mu,
+                                    float *Y, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(near_scale_labels_k, dim3(grid_for(n)), dim3(256), 0, st, n, du, dv, frame, mu, Y);
+    return hipGetLastError();
+}
+
+hipError_t near_launch_infer(int64_t n, const float *X, const double *frame, const NearBlob *nb, double mu,
+                             double threshold, int use_bound, double *du, double *dv, int32_t *flag, int32_t *list,
+                             int32_t *count, hipStream_t st) {
+    hipLaunchKernelGGL(near_zero_count, dim3(1), dim3(64), 0, st, count);
+    if (n <= 0) return hipGetLastError();
+    hipLaunchKernelGGL(near_mlp_infer, dim3(grid_for(n)), dim3(256), 0, st, n, X, frame, nb, mu, threshold,
+                       use_bound, du, dv, flag, list, count);
+    return hipGetLastError();
+}
+
+hipError_t near_launch_pack(const float *prm, const float *bound, int32_t n_bins, float bin_lo, float bin_w,
+                            NearBlob *nb, hipStream_t st) {
+    hipLaunchKernelGGL(near_pack, dim3(grid_for(kNearBlobWork)), dim3(256), 0, st, prm, bound, n_bins, bin_lo,
+                       bin_w, nb);
+    return hipGetLastError();
+}
+
+hipError_t near_launch_train_step(int32_t B, const int32_t *idx, const float *X, const float *T, float *prm,
+                                  float *m, float *v, int32_t step, float lr, float *grad, float *act, float *dY,
+                                  float *lossv, float *loss, int update, hipStream_t st) {
+    const MlpOffsets O;
+    hipLaunchKernelGGL(mlp_fwd, dim3(grid_for(B)), dim3(256), 0, st, B, idx, X, T, prm, act, dY, lossv);
+    hipLaunchKernelGGL(mlp_bwd, dim3(grid_for(B)), dim3(256), 0, st, B, prm, act, dY);
+    hipLaunchKernelGGL(mlp_grad, dim3(grid_for(O.total)), dim3(256), 0, st, B, act, dY, lossv, grad, loss);
+    if (update)
+        hipLaunchKernelGGL(mlp_adam, dim3(grid_for(O.total)), dim3(256), 0, st, prm, grad, m, v, step, lr, 0.9f,
+                           0.999f, 1e-8f);
+    return hipGetLastError();
+}
+
+hipError_t near_launch_fwd(int64_t n, const float *X, const float *prm, float *Y, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(mlp_fwd_only, dim3(grid_for(n)), dim3(256), 0, st, n, X, prm, Y);
+    return hipGetLastError();
+}
+
+}  // namespace s2d

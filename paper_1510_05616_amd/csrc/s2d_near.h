@@ -1,0 +1,56 @@
+// Internal declarations of the near-field correction kernels (near.hip).
+#pragma once
+#include "s2d_internal.h"
+
+namespace s2d {
+
+constexpr int kNearFeat = 20;
+constexpr int kNearMaxBins = 64;
+constexpr int kActStride = 20 + 6 * 64;      // h0 z1 h1 z2 h2 z3 h3 per training sample
+
+// FP32 master parameter vector: standardisation, then W (in x out, row
+// major) and b of each layer.
+struct MlpOffsets {
+    int mu = 0, sd = 20, W1 = 40, b1 = 40 + 1280, W2 = 1384, b2 = 1384 + 4096, W3 = 5544, b3 = 5544 + 4096,
+        W4 = 9704, b4 = 9704 + 128, total = 9834;
+};
+
+// BF16 inference blob (device): weights as [out][in / 2] bf16 pairs.
+struct NearBlob {
+    float mu_in[kNearFeat], isd_in[kNearFeat];
+    uint32_t W1[64 * kNearFeat / 2];
+    float b1[64];
+    uint32_t W2[64 * 32];
+    float b2[64];
+    uint32_t W3[64 * 32];
+    float b3[64];
+    uint32_t W4[2 * 32];
+    float b4[2];
+    int32_t n_bins;
+    float bin_lo, bin_w;
+    float bound[kNearMaxBins];
+};
+constexpr int kNearBlobWork = kNearFeat + 64 * kNearFeat / 2 + 2 * 64 * 32 + 2 * 32 + 64;
+
+hipError_t near_launch_upsample(const s2d_curves *c, int P, double *up, hipStream_t st);
+hipError_t near_launch_quad(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, const int32_t *list,
+                            const int32_t *count, int P, const double *up, double mu, double *du, double *dv,
+                            hipStream_t st);
+hipError_t near_launch_features(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, float *X,
+                                double *frame, hipStream_t st);
+hipError_t near_launch_scale_labels(int64_t n, const double *du, const double *dv, const double *frame, double mu,
+                                    float *Y, hipStream_t st);
+hipError_t near_launch_infer(int64_t n, const float *X, const double *frame, const NearBlob *nb, double mu,
+                             double threshold, int use_bound, double *du, double *dv, int32_t *flag, int32_t *list,
+                             int32_t *count, hipStream_t st);
+hipError_t near_launch_pack(const float *prm, const float *bound, int32_t n_bins, float bin_lo, float bin_w,
+                            NearBlob *nb, hipStream_t st);
+hipError_t near_launch_train_step(int32_t B, const int32_t *idx, const float *X, const float *T, float *prm,
+                                  float *m, float *v, int32_t step, float lr, float *grad, float *act, float *dY,
+                                  float *lossv, float *loss, int update, hipStream_t st);
+hipError_t near_launch_fwd(int64_t n, const float *X, const float *prm, float *Y, hipStream_t st);
+
+constexpr int kUpMaxN = 256;      // coarse nodes per curve for upsampling
+constexpr int kUpMaxM = 2048;     // fine nodes per curve
+
+}  // namespace s2d

@@ -1,0 +1,248 @@
+"""Binding of the near-field correction entry points of libstokes2d, and the
+training driver of the near-field MLP.
+
+The driver only orchestrates library calls: labels come from the library's
+FFT-upsampled FP64 quadrature, features from its feature kernel, every
+training step (forward, backward, gradient sums, Adam) from its training
+kernels, and the BF16 inference blob from its packing kernel.  torch supplies
+device memory, the minibatch permutation and the per-bin statistics of the
+calibration.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+
+import numpy as np
+
+from . import (Curves, Targets, _check, _ptr, _stream, lib)
+
+S2D_NEAR_UPSAMPLE, S2D_NEAR_MLP, S2D_NEAR_AUTO = 0, 1, 2
+NFEAT = 20
+NPARAM = 9834
+# offsets in the FP32 master parameter vector
+OFF = dict(mu=0, sd=20, W1=40, b1=1320, W2=1384, b2=5480, W3=5544, b3=9640, W4=9704, b4=9832)
+SHAPES = dict(W1=(20, 64), b1=(64,), W2=(64, 64), b2=(64,), W3=(64, 64), b3=(64,), W4=(64, 2), b4=(2,))
+BIN_LO, BIN_W, N_BINS = math.log10(0.05), 0.1, 20      # bins of log10(|normal offset| / h)
+
+_bound = False
+
+
+def _bind():
+    global _bound
+    L = lib()
+    if _bound:
+        return L
+    P, I, I32, I64, D, F, SZ = (ctypes.c_void_p, ctypes.c_int, ctypes.c_int32, ctypes.c_int64,
+                                ctypes.c_double, ctypes.c_float, ctypes.c_size_t)
+    L.near_workspace_size.argtypes = [I, P, P, I32]
+    L.near_workspace_size.restype = SZ
+    L.near_correct_eval.argtypes = [I, P, P, P, I32, P, D, D, P, P, P, P, SZ, P]
+    L.near_correct_eval.restype = I
+    L.near_features_eval.argtypes = [P, P, P, P, P, P]
+    L.near_features_eval.restype = I
+    L.near_scale_labels.argtypes = [I64, P, P, P, D, P, P]
+    L.near_scale_labels.restype = I
+    L.near_mlp_train_workspace_size.argtypes = [I32]
+    L.near_mlp_train_workspace_size.restype = SZ
+    L.near_mlp_train_step.argtypes = [I32, P, P, P, P, P, P, I32, F, P, P, P, SZ, P]
+    L.near_mlp_train_step.restype = I
+    L.near_mlp_forward.argtypes = [I64, P, P, P, P]
+    L.near_mlp_forward.restype = I
+    L.near_mlp_blob_size.argtypes = []
+    L.near_mlp_blob_size.restype = SZ
+    L.near_mlp_pack.argtypes = [P, P, I32, F, F, P, P]
+    L.near_mlp_pack.restype = I
+    _bound = True
+    return L
+
+
+def _empty(nbytes, device="cuda"):
+    import torch
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def near_workspace_size(method, ves: Curves, trg: Targets, upsample: int) -> int:
+    L = _bind()
+    cs, ts = ves.struct(), trg.struct()
+    return int(L.near_workspace_size(int(method), ctypes.byref(cs), ctypes.byref(ts), int(upsample)))
+
+
+def near_correct_eval(method, ves: Curves, trg: Targets, trg_curve, upsample, blob, threshold, mu, du, dv,
+                      used_fallback=None, ws=None, stream=None) -> None:
+    L = _bind()
+    cs, ts = ves.struct(), trg.struct()
+    if ws is None:
+        ws = _empty(near_workspace_size(method, ves, trg, upsample), du.device)
+    _check(L.near_correct_eval(int(method), ctypes.byref(cs), ctypes.byref(ts), _ptr(trg_curve), int(upsample),
+                               _ptr(blob), float(threshold), float(mu), _ptr(du), _ptr(dv), _ptr(used_fallback),
+                               _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def near_features_eval(ves: Curves, trg: Targets, trg_curve, X, frame, stream=None) -> None:
+    L = _bind()
+    cs, ts = ves.struct(), trg.struct()
+    _check(L.near_features_eval(ctypes.byref(cs), ctypes.byref(ts), _ptr(trg_curve), _ptr(X), _ptr(frame),
+                                _stream(stream)))
+
+
+def near_scale_labels(du, dv, frame, mu, Y, stream=None) -> None:
+    L = _bind()
+    _check(L.near_scale_labels(du.numel(), _ptr(du), _ptr(dv), _ptr(frame), float(mu), _ptr(Y), _stream(stream)))
+
+
+def near_mlp_train_workspace_size(batch: int) -> int:
+    return int(_bind().near_mlp_train_workspace_size(int(batch)))
+
+
+def near_mlp_train_step(batch, idx, X, Y, params, m, v, step, lr, grad, loss, ws, stream=None) -> None:
+    L = _bind()
+    _check(L.near_mlp_train_step(int(batch), _ptr(idx), _ptr(X), _ptr(Y), _ptr(params), _ptr(m), _ptr(v),
+                                 int(step), float(lr), _ptr(grad), _ptr(loss), _ptr(ws), ws.numel(),
+                                 _stream(stream)))
+
+
+def near_mlp_forward(X, params, Y, stream=None) -> None:
+    L = _bind()
+    _check(L.near_mlp_forward(X.shape[0], _ptr(X), _ptr(params), _ptr(Y), _stream(stream)))
+
+
+def near_mlp_blob_size() -> int:
+    return int(_bind().near_mlp_blob_size())
+
+
+def near_mlp_pack(params, bound, n_bins, bin_lo, bin_w, blob, stream=None) -> None:
+    L = _bind()
+    _check(L.near_mlp_pack(_ptr(params), _ptr(bound), int(n_bins), float(bin_lo), float(bin_w), _ptr(blob),
+                           _stream(stream)))
+
+
+# ----------------------------------------------------------------------------
+# parameters
+# ----------------------------------------------------------------------------
+def params_to_dict(p: np.ndarray) -> dict:
+    p = np.asarray(p, dtype=np.float64)
+    d = {"mu_in": p[0:20].copy(), "sd_in": p[20:40].copy()}
+    for k, shp in SHAPES.items():
+        n = int(np.prod(shp))
+        d[k] = p[OFF[k]:OFF[k] + n].reshape(shp).copy()
+    return d
+
+
+def dict_to_params(d: dict) -> np.ndarray:
+    p = np.zeros(NPARAM)
+    p[0:20] = d["mu_in"]
+    p[20:40] = d["sd_in"]
+    for k, shp in SHAPES.items():
+        n = int(np.prod(shp))
+        p[OFF[k]:OFF[k] + n] = np.asarray(d[k]).reshape(-1)
+    return p
+
+
+def init_params(mu_in, sd_in, seed=0) -> np.ndarray:
+    rng = np.random.default_rng([seed, 2])
+    d = {"mu_in": np.asarray(mu_in, float), "sd_in": np.asarray(sd_in, float)}
+    for k, shp in SHAPES.items():
+        d[k] = rng.normal(size=shp) * math.sqrt(2.0 / shp[0]) if k.startswith("W") else np.zeros(shp)
+    return dict_to_params(d)
+
+
+# ----------------------------------------------------------------------------
+# data and training
+# ----------------------------------------------------------------------------
+class NearData:
+    """Device copy of a near-field dataset with its features, frames and
+    (optionally) FP64 upsampled labels."""
+
+    def __init__(self, curves, tx, ty, tc, mu=1.0, upsample=8, labels=True, device="cuda"):
+        import torch
+        self.curves = Curves(curves, device)
+        self.trg = Targets(tx, ty, device=device)
+        self.tc = torch.as_tensor(np.ascontiguousarray(tc, dtype=np.int32), device=device)
+        self.n = self.trg.n
+        self.mu = mu
+        self.P = upsample
+        self.X = torch.empty((self.n, NFEAT), dtype=torch.float32, device=device)
+        self.frame = torch.empty((self.n, 6), dtype=torch.float64, device=device)
+        near_features_eval(self.curves, self.trg, self.tc, self.X, self.frame)
+        self.du = self.dv = self.Y = None
+        if labels:
+            self.du = torch.empty(self.n, dtype=torch.float64, device=device)
+            self.dv = torch.empty_like(self.du)
+            near_correct_eval(S2D_NEAR_UPSAMPLE, self.curves, self.trg, self.tc, upsample, None, 0.0, mu,
+                              self.du, self.dv)
+            self.Y = torch.empty((self.n, 2), dtype=torch.float32, device=device)
+            near_scale_labels(self.du, self.dv, self.frame, mu, self.Y)
+
+
+def train(data: NearData, epochs=60, batch=1024, lr=2e-3, lr_min=2e-5, seed=0, log=None):
+    """Trains the MLP on data.X -> data.Y with the library's kernels; returns
+    (params tensor, list of epoch losses)."""
+    import torch
+    dev = data.X.device
+    Xc = data.X.double()
+    mu_in = Xc.mean(0).cpu().numpy()
+    sd_in = Xc.std(0).clamp_min(1e-6).cpu().numpy()
+    params = torch.as_tensor(init_params(mu_in, sd_in, seed), dtype=torch.float32, device=dev)
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    grad = torch.zeros_like(params)
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    ws = _empty(near_mlp_train_workspace_size(batch), dev)
+    gen = torch.Generator(device="cpu")
+    gen.manual_seed(seed)
+    n = data.n
+    steps_per_epoch = n // batch
+    total = max(1, epochs * steps_per_epoch)
+    step = 0
+    hist = []
+    for ep in range(epochs):
+        perm = torch.randperm(n, generator=gen).to(device=dev, dtype=torch.int32)
+        acc = 0.0
+        for b in range(steps_per_epoch):
+            step += 1
+            frac = (step - 1) / total
+            cur = lr_min + 0.5 * (lr - lr_min) * (1 + math.cos(math.pi * frac))
+            idx = perm[b * batch:(b + 1) * batch]
+            near_mlp_train_step(batch, idx, data.X, data.Y, params, m, v, step, cur, grad, loss, ws)
+            if b % 50 == 0:
+                acc += float(loss.item())
+        hist.append(acc / max(1, (steps_per_epoch + 49) // 50))
+        if log:
+            log(f"epoch {ep}: loss {hist[-1]:.3e}")
+    return params, hist
+
+
+def scaled_errors(data: NearData, du_pred, dv_pred):
+    """Per-target error of a prediction in the scaled units of the labels."""
+    import torch
+    fr = data.frame
+    sc = 4 * math.pi * data.mu / (fr[:, 4] * fr[:, 5])
+    return torch.hypot(du_pred - data.du, dv_pred - data.dv) * sc
+
+
+def calibrate(data: NearData, params, quantile=1.0, safety=1.5):
+    """Per-bin error bound of the BF16 network on validation data (bins of
+    log10 |normal offset| / h): the max (quantile 1) scaled error times
+    `safety`.  Returns (blob tensor, bound numpy array)."""
+    import torch
+    dev = data.X.device
+    blob = torch.zeros(near_mlp_blob_size(), dtype=torch.uint8, device=dev)
+    zero = torch.zeros(N_BINS, dtype=torch.float32, device=dev)
+    near_mlp_pack(params, zero, N_BINS, BIN_LO, BIN_W, blob)
+    du = torch.empty_like(data.du)
+    dv = torch.empty_like(data.dv)
+    near_correct_eval(S2D_NEAR_MLP, data.curves, data.trg, data.tc, data.P, blob, 0.0, data.mu, du, dv)
+    err = scaled_errors(data, du, dv).cpu().numpy()
+    noff = np.abs(data.X[:, 1].double().cpu().numpy())
+    b = np.clip(np.floor((np.log10(np.maximum(noff, 1e-30)) - BIN_LO) / BIN_W).astype(int), 0, N_BINS - 1)
+    bound = np.zeros(N_BINS)
+    for k in range(N_BINS):
+        e = err[b == k]
+        if e.size:
+            bound[k] = (np.quantile(e, quantile) if quantile < 1 else e.max()) * safety
+        else:
+            bound[k] = np.inf
+    bt = torch.as_tensor(np.minimum(bound, 3e38), dtype=torch.float32, device=dev)
+    near_mlp_pack(params, bt, N_BINS, BIN_LO, BIN_W, blob)
+    return blob, bound

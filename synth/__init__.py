@@ -389,3 +389,45 @@ def ellipse_param(a: float, b: float, center=(0.0, 0.0), phi: float = 0.0):
         ex, ey = a * np.cos(t), b * np.sin(t)
         return center[0] + c * ex - s * ey, center[1] + s * ex + c * ey
     return xy
+
+
+def make_near_dataset(n_targets: int, seed: int, per_curve: int = 200, sizes=(64, 96, 128),
+                      K_range=(8, 16), delta_range=(0.05, 5.0), area: float = AREA_C1):
+    """Near-field workload: closed ellipses (reduced area U[0.65, 0.9], node
+    count from `sizes`, K ~ U{K_range} density modes, random rotation) and
+    targets x(th) + delta n(th) outside them, th ~ U[0, 2 pi) continuous,
+    delta = h 10^U[log10 lo, log10 hi] with h = (sum of weights) / N.
+    Returns (curves, tx, ty, trg_curve, delta_over_h)."""
+    rng = np.random.default_rng([seed, 0])
+    rd = np.random.default_rng([seed, 1])
+    n_curves = (n_targets + per_curve - 1) // per_curve
+    parts, tx, ty, tc, dh = [], [], [], [], []
+    left = n_targets
+    for c in range(n_curves):
+        nu = rng.uniform(0.65, 0.9)
+        N = int(rng.choice(np.asarray(sizes)))
+        K = int(rng.integers(K_range[0], K_range[1] + 1))
+        phi = rng.uniform(0.0, np.pi)
+        a, b = ellipse_axes_for(nu, area)
+        x, y, nx, ny, w, kap, t = _ellipse(0.0, 0.0, a, b, phi, N)
+        fx, fy = _density(rd, t, K)
+        parts.append((x, y, nx, ny, w, kap, fx, fy))
+        m = min(per_curve, left)
+        left -= m
+        h = w.sum() / N
+        th = rng.uniform(0.0, 2 * np.pi, m)
+        lg = rng.uniform(np.log10(delta_range[0]), np.log10(delta_range[1]), m)
+        cs, sn = math.cos(phi), math.sin(phi)
+        ex, ey = a * np.cos(th), b * np.sin(th)
+        px, py = cs * ex - sn * ey, sn * ex + cs * ey
+        dx, dy = -a * np.sin(th), b * np.cos(th)
+        qx, qy = cs * dx - sn * dy, sn * dx + cs * dy
+        sp = np.hypot(qx, qy)
+        onx, ony = qy / sp, -qx / sp
+        delta = h * 10.0 ** lg
+        tx.append(px + delta * onx)
+        ty.append(py + delta * ony)
+        tc.append(np.full(m, c, np.int32))
+        dh.append(10.0 ** lg)
+    return (concat_curves(parts), np.concatenate(tx), np.concatenate(ty), np.concatenate(tc),
+            np.concatenate(dh))

@@ -1,0 +1,208 @@
+"""GPU checks of the near-field correction: upsampled FP64 quadrature and the
+features against the oracle, training-kernel gradients against the FP64
+oracle backward pass and finite differences, Adam against the oracle step,
+BF16 inference against the FP32 forward pass, the fallback rule, and what a
+trained network gains over the plain trapezoid rule."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import near as onear
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def device():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1510_05616_amd as s2d
+    s2d.stokes2d_init(0)
+    yield
+
+
+@pytest.fixture(scope="module")
+def small():
+    from paper_1510_05616_amd import near
+    c, tx, ty, tc, dh = synth.make_near_dataset(3000, seed=21, per_curve=150)
+    return c, tx, ty, tc, dh, near.NearData(c, tx, ty, tc, mu=1.0, upsample=8)
+
+
+def test_upsampled_quadrature_matches_oracle(small):
+    import oracle
+    c, tx, ty, tc, dh, data = small
+    du = data.du.cpu().numpy()
+    dv = data.dv.cpu().numpy()
+    worst = 0.0
+    for k in range(c.n_curves):
+        sel = np.where(tc == k)[0]
+        s = slice(c.curve_off[k], c.curve_off[k + 1])
+        ou, ov = onear.near_label(c.x[s], c.y[s], c.fx[s], c.fy[s], c.w[s], tx[sel], ty[sel], P=8)
+        sub = synth.CurveSet(*(getattr(c, a)[s] for a in ("x", "y", "nx", "ny", "w", "kappa", "fx", "fy")),
+                             curve_off=np.array([0, s.stop - s.start], np.int32))
+        u1, v1 = oracle.slp(sub, tx[sel], ty[sel])
+        sc = np.hypot(u1 + ou, v1 + ov).max()
+        worst = max(worst, np.hypot(du[sel] - ou, dv[sel] - ov).max() / sc)
+    print(f"upsampled quadrature worst rel err {worst:.2e}", flush=True)
+    assert worst < 1e-12
+
+
+def test_features_match_oracle(small):
+    c, tx, ty, tc, dh, data = small
+    X = data.X.cpu().numpy()
+    fr = data.frame.cpu().numpy()
+    rng = np.random.default_rng(0)
+    for i in rng.choice(len(tx), 300, replace=False):
+        k = tc[i]
+        s = slice(c.curve_off[k], c.curve_off[k + 1])
+        f, t0, n0, h, F = onear.features_one(c.x[s], c.y[s], c.nx[s], c.ny[s], c.kappa[s], c.w[s], c.fx[s],
+                                             c.fy[s], tx[i], ty[i])
+        assert np.abs(X[i] - f).max() < 2e-6 * max(1.0, np.abs(f).max())
+        assert np.abs(fr[i] - np.concatenate([t0, n0, [h, F]])).max() < 1e-13
+
+
+def _rand_params(seed=3):
+    rng = np.random.default_rng(seed)
+    p = onear.init_params(seed=seed, mu_in=rng.normal(size=20) * 0.2, sd_in=0.5 + rng.random(20))
+    for k in ("b1", "b2", "b3", "b4"):
+        p[k] = rng.normal(size=p[k].shape) * 0.1
+    return p
+
+
+def test_training_gradient_matches_oracle_and_finite_differences():
+    import torch
+    from paper_1510_05616_amd import near
+    rng = np.random.default_rng(5)
+    B = 96
+    X = rng.normal(size=(B + 10, 20))
+    T = rng.normal(size=(B + 10, 2)) * 0.3
+    idx = rng.permutation(B + 10)[:B].astype(np.int32)
+    pd = _rand_params()
+    p32 = near.dict_to_params(pd).astype(np.float32)
+    pd32 = near.params_to_dict(p32)                      # the oracle sees the FP32-rounded weights
+    L, g = onear.mlp_loss_grad(pd32, X.astype(np.float32).astype(np.float64)[idx],
+                               T.astype(np.float32).astype(np.float64)[idx])
+    dev = "cuda"
+    Xt = torch.as_tensor(X, dtype=torch.float32, device=dev)
+    Tt = torch.as_tensor(T, dtype=torch.float32, device=dev)
+    it = torch.as_tensor(idx, device=dev)
+    prm = torch.as_tensor(p32, device=dev)
+    grad = torch.zeros_like(prm)
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    ws = torch.empty(near.near_mlp_train_workspace_size(B), dtype=torch.uint8, device=dev)
+    near.near_mlp_train_step(B, it, Xt, Tt, prm, None, None, 0, 0.0, grad, loss, ws)
+    torch.cuda.synchronize()
+    gg = near.params_to_dict(grad.cpu().numpy())
+    assert abs(loss.item() - L) <= 1e-5 * abs(L)
+    for k in ("W1", "b1", "W2", "b2", "W3", "b3", "W4", "b4"):
+        sc = np.abs(g[k]).max()
+        assert np.abs(gg[k] - g[k]).max() <= 2e-4 * sc, k
+    # finite differences of the GPU loss itself (FP32: loose)
+    for name, j in (("W1", 37), ("W3", 1000), ("b4", 1), ("W4", 50)):
+        e = 1e-2
+        vals = []
+        for sgn in (1, -1):
+            q = p32.copy()
+            q[near.OFF[name] + j] += sgn * e
+            near.near_mlp_train_step(B, it, Xt, Tt, torch.as_tensor(q, device=dev), None, None, 0, 0.0, grad, loss, ws)
+            torch.cuda.synchronize()
+            vals.append(loss.item())
+        fd = (vals[0] - vals[1]) / (2 * e)
+        gj = gg[name].reshape(-1)[j]
+        assert abs(fd - gj) <= 2e-2 * max(abs(gj), 1e-3 * abs(L)), (name, fd, gj)
+
+
+def test_adam_step_matches_oracle():
+    import torch
+    from paper_1510_05616_amd import near
+    rng = np.random.default_rng(7)
+    B = 64
+    X = rng.normal(size=(B, 20)).astype(np.float32)
+    T = rng.normal(size=(B, 2)).astype(np.float32)
+    p32 = near.dict_to_params(_rand_params(8)).astype(np.float32)
+    dev = "cuda"
+    prm = torch.as_tensor(p32, device=dev)
+    m = torch.zeros_like(prm)
+    v = torch.zeros_like(prm)
+    grad = torch.zeros_like(prm)
+    ws = torch.empty(near.near_mlp_train_workspace_size(B), dtype=torch.uint8, device=dev)
+    Xt, Tt = torch.as_tensor(X, device=dev), torch.as_tensor(T, device=dev)
+    st = {}
+    pd = near.params_to_dict(p32)
+    for step in (1, 2, 3):
+        near.near_mlp_train_step(B, None, Xt, Tt, prm, m, v, step, 1e-3, grad, None, ws)
+        L, g = onear.mlp_loss_grad(pd, X.astype(np.float64), T.astype(np.float64))
+        onear.adam_step(pd, g, st, lr=1e-3)
+    torch.cuda.synchronize()
+    got = near.params_to_dict(prm.cpu().numpy())
+    for k in ("W1", "W2", "b3", "W4"):
+        assert np.abs(got[k] - pd[k]).max() < 5e-6, k
+
+
+def test_fp32_forward_and_bf16_inference(small):
+    import torch
+    from paper_1510_05616_amd import near
+    c, tx, ty, tc, dh, data = small
+    pd = _rand_params(9)
+    p32 = torch.as_tensor(near.dict_to_params(pd).astype(np.float32), device="cuda")
+    Y = torch.empty((data.n, 2), dtype=torch.float32, device="cuda")
+    near.near_mlp_forward(data.X, p32, Y)
+    torch.cuda.synchronize()
+    ref, _ = onear.mlp_forward(near.params_to_dict(p32.cpu().numpy()), data.X.double().cpu().numpy())
+    assert np.abs(Y.cpu().numpy() - ref).max() < 2e-5 * np.abs(ref).max()
+    # BF16 inference through near_correct_eval(MLP): same network, BF16 rounding
+    blob = torch.zeros(near.near_mlp_blob_size(), dtype=torch.uint8, device="cuda")
+    near.near_mlp_pack(p32, torch.zeros(near.N_BINS, device="cuda"), near.N_BINS, near.BIN_LO, near.BIN_W, blob)
+    du = torch.empty(data.n, dtype=torch.float64, device="cuda")
+    dv = torch.empty_like(du)
+    near.near_correct_eval(near.S2D_NEAR_MLP, data.curves, data.trg, data.tc, 8, blob, 0.0, 1.0, du, dv)
+    torch.cuda.synchronize()
+    fr = data.frame.cpu().numpy()
+    rdu, rdv = onear.frame_to_velocity(ref, fr)
+    sc = np.abs(ref).max() * (fr[:, 4] * fr[:, 5]).max() / (4 * math.pi)
+    err = np.hypot(du.cpu().numpy() - rdu, dv.cpu().numpy() - rdv).max() / sc
+    print(f"bf16 vs fp64 forward: {err:.2e}", flush=True)
+    assert err < 3e-2
+
+
+def test_auto_with_zero_threshold_is_the_upsampled_result(small):
+    import torch
+    from paper_1510_05616_amd import near
+    c, tx, ty, tc, dh, data = small
+    p32 = torch.as_tensor(near.dict_to_params(_rand_params(2)).astype(np.float32), device="cuda")
+    blob = torch.zeros(near.near_mlp_blob_size(), dtype=torch.uint8, device="cuda")
+    near.near_mlp_pack(p32, torch.full((near.N_BINS,), 1e-3, device="cuda"), near.N_BINS, near.BIN_LO,
+                       near.BIN_W, blob)
+    du = torch.empty(data.n, dtype=torch.float64, device="cuda")
+    dv = torch.empty_like(du)
+    fb = torch.zeros(data.n, dtype=torch.int32, device="cuda")
+    near.near_correct_eval(near.S2D_NEAR_AUTO, data.curves, data.trg, data.tc, 8, blob, 0.0, 1.0, du, dv, fb)
+    torch.cuda.synchronize()
+    assert torch.all(fb == 1)
+    assert torch.equal(du, data.du) and torch.equal(dv, data.dv)
+    # and a huge threshold never falls back
+    near.near_correct_eval(near.S2D_NEAR_AUTO, data.curves, data.trg, data.tc, 8, blob, 1e30, 1.0, du, dv, fb)
+    torch.cuda.synchronize()
+    assert torch.all(fb == 0)
+
+
+def test_training_gains_over_plain_trapezoid():
+    import torch
+    from paper_1510_05616_amd import near
+    tr = near.NearData(*synth.make_near_dataset(60000, seed=31)[:4], mu=1.0, upsample=8)
+    va = near.NearData(*synth.make_near_dataset(6000, seed=32)[:4], mu=1.0, upsample=8)
+    params, hist = near.train(tr, epochs=12, batch=512, lr=3e-3)
+    assert hist[-1] < 0.2 * hist[0]
+    blob, bound = near.calibrate(va, params)
+    du = torch.empty(va.n, dtype=torch.float64, device="cuda")
+    dv = torch.empty_like(du)
+    near.near_correct_eval(near.S2D_NEAR_MLP, va.curves, va.trg, va.tc, 8, blob, 0.0, 1.0, du, dv)
+    torch.cuda.synchronize()
+    e_mlp = near.scaled_errors(va, du, dv).cpu().numpy()
+    e_plain = near.scaled_errors(va, torch.zeros_like(du), torch.zeros_like(dv)).cpu().numpy()
+    noff = np.abs(va.X[:, 1].double().cpu().numpy())
+    near_sel = noff < 1.0
+    print(f"near targets: plain {np.median(e_plain[near_sel]):.2e} mlp {np.median(e_mlp[near_sel]):.2e}", flush=True)
+    assert np.median(e_mlp[near_sel]) < 0.2 * np.median(e_plain[near_sel])
