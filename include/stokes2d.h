@@ -206,6 +206,14 @@ S2D_API int near_correct_eval(int method, const s2d_curves *ves, const s2d_targe
                               double threshold, double mu, double *du, double *dv,
                               int32_t *used_fallback, void *ws, size_t ws_bytes, void *stream);
 
+/* The single layer of each target's own curve by the P-times upsampled
+ * trapezoid rule (u_up, v_up) and by the plain N-node rule (u_trap, v_trap),
+ * FP64 (their difference is Delta).  For normalising near-field errors. */
+S2D_API size_t near_upsampled_slp_workspace_size(const s2d_curves *ves, const s2d_targets *trg, int32_t upsample);
+S2D_API int near_upsampled_slp(const s2d_curves *ves, const s2d_targets *trg, const int32_t *trg_curve,
+                               int32_t upsample, double mu, double *u_up, double *v_up, double *u_trap,
+                               double *v_trap, void *ws, size_t ws_bytes, void *stream);
+
 /* Target features X ([n][20] FP32: tangential and normal offset from node
  * k0 in units of h, distance to the nearest node / h, kappa h, and the
  * densities of nodes k0-3..k0+4 in the local frame divided by their largest

@@ -440,6 +440,36 @@ S2D_API int near_correct_eval(int method, const s2d_curves *ves, const s2d_targe
     return S2D_OK;
 }
 
+S2D_API int near_upsampled_slp(const s2d_curves *ves, const s2d_targets *trg, const int32_t *trg_curve,
+                               int32_t upsample, double mu, double *u_up, double *v_up, double *u_trap,
+                               double *v_trap, void *ws, size_t ws_bytes, void *stream) {
+    int rc = check_near(S2D_NEAR_UPSAMPLE, ves, trg, trg_curve, upsample, mu);
+    if (rc != S2D_OK) return rc;
+    int dev = 0;
+    rc = current_device(&dev);
+    if (rc != S2D_OK) return rc;
+    if (trg->n == 0) return S2D_OK;
+    if (!u_up || !v_up || !u_trap || !v_trap) return fail(S2D_EINVAL, "outputs must not be NULL");
+    const NearLayout L = near_layout(S2D_NEAR_UPSAMPLE, ves, trg, upsample);
+    const size_t need = L.total + align256(2 * (size_t)trg->n * sizeof(double));
+    if (!ws || ws_bytes < need)
+        return fail(S2D_EWORKSPACE, "near workspace too small: need " + std::to_string(need) + " bytes");
+    if (((uintptr_t)ws & 255) != 0) return fail(S2D_EWORKSPACE, "workspace must be 256-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    double *up = (double *)((char *)ws + L.up);
+    double *d = (double *)((char *)ws + L.total);
+    hipError_t e = s2d::near_launch_upsample(ves, upsample, up, st);
+    if (e != hipSuccess) return hip_fail(e, "near upsample launch");
+    e = s2d::near_launch_quad(ves, trg, trg_curve, nullptr, nullptr, upsample, up, mu, d, d + trg->n, st, u_up, v_up,
+                              u_trap, v_trap);
+    return e == hipSuccess ? S2D_OK : hip_fail(e, "near quadrature launch");
+}
+
+S2D_API size_t near_upsampled_slp_workspace_size(const s2d_curves *ves, const s2d_targets *trg, int32_t upsample) {
+    if (!ves || !trg || upsample < 1 || upsample > 32) return 0;
+    return near_layout(S2D_NEAR_UPSAMPLE, ves, trg, upsample).total + align256(2 * (size_t)trg->n * sizeof(double));
+}
+
 S2D_API int near_features_eval(const s2d_curves *ves, const s2d_targets *trg, const int32_t *trg_curve, float *X,
                                double *frame, void *stream) {
     int rc = check_near(S2D_NEAR_MLP, ves, trg, trg_curve, 1, 1.0);

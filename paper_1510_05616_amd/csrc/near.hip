@@ -123,7 +123,9 @@ __global__ __launch_bounds__(256) void near_quad(int64_t n_trg, const int32_t *_
                                                  const double *__restrict__ x, const double *__restrict__ y,
                                                  const double *__restrict__ w, const double *__restrict__ fx,
                                                  const double *__restrict__ fy, int P, const double *__restrict__ up,
-                                                 double pref, double *__restrict__ du, double *__restrict__ dv) {
+                                                 double pref, double *__restrict__ du, double *__restrict__ dv,
+                                                 double *__restrict__ uf, double *__restrict__ vf,
+                                                 double *__restrict__ uc, double *__restrict__ vc) {
     const int64_t n = list ? (int64_t)*count : n_trg;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = list ? list[q] : q;
@@ -133,6 +135,7 @@ __global__ __launch_bounds__(256) void near_quad(int64_t n_trg, const int32_t *_
         if (c < 0 || c >= n_curves || N < 4 || (N & 1) || N > kUpMaxN || P * N > kUpMaxM || lo < 0 ||
             (int64_t)lo + N > n_src) {
             du[i] = dv[i] = __builtin_nan("");
+            if (uf) uf[i] = vf[i] = uc[i] = vc[i] = __builtin_nan("");
             continue;
         }
         const double px = tx[i], py = ty[i];
@@ -146,6 +149,12 @@ __global__ __launch_bounds__(256) void near_quad(int64_t n_trg, const int32_t *_
         }
         du[i] = pref * ((-0.5 * c0 + d0) - (-0.5 * a0 + b0));
         dv[i] = pref * ((-0.5 * c1 + d1) - (-0.5 * a1 + b1));
+        if (uf) {
+            uf[i] = pref * (-0.5 * c0 + d0);
+            vf[i] = pref * (-0.5 * c1 + d1);
+            uc[i] = pref * (-0.5 * a0 + b0);
+            vc[i] = pref * (-0.5 * a1 + b1);
+        }
     }
 }
 
@@ -534,12 +543,12 @@ hipError_t near_launch_upsample(const s2d_curves *c, int P, double *up, hipStrea
 
 hipError_t near_launch_quad(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, const int32_t *list,
                             const int32_t *count, int P, const double *up, double mu, double *du, double *dv,
-                            hipStream_t st) {
+                            hipStream_t st, double *uf, double *vf, double *uc, double *vc) {
     if (t->n <= 0) return hipSuccess;
     const unsigned g = list ? std::min<unsigned>(grid_for(t->n), 4096u) : grid_for(t->n);
     hipLaunchKernelGGL(near_quad, dim3(g), dim3(256), 0, st, t->n, list, count, t->x, t->y, tc, c->curve_off,
                        c->n_curves, c->n_nodes, c->x, c->y, c->w, c->fx, c->fy, P, up, 1.0 / (4.0 * M_PI * mu), du,
-                       dv);
+                       dv, uf, vf, uc, vc);
     return hipGetLastError();
 }
 

@@ -35,7 +35,8 @@ constexpr int kNearBlobWork = kNearFeat + 64 * kNearFeat / 2 + 2 * 64 * 32 + 2 *
 hipError_t near_launch_upsample(const s2d_curves *c, int P, double *up, hipStream_t st);
 hipError_t near_launch_quad(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, const int32_t *list,
                             const int32_t *count, int P, const double *up, double mu, double *du, double *dv,
-                            hipStream_t st);
+                            hipStream_t st, double *uf = nullptr, double *vf = nullptr, double *uc = nullptr,
+                            double *vc = nullptr);
 hipError_t near_launch_features(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, float *X,
                                 double *frame, hipStream_t st);
 hipError_t near_launch_scale_labels(int64_t n, const double *du, const double *dv, const double *frame, double mu,

@@ -39,6 +39,10 @@ def _bind():
     L.near_workspace_size.restype = SZ
     L.near_correct_eval.argtypes = [I, P, P, P, I32, P, D, D, P, P, P, P, SZ, P]
     L.near_correct_eval.restype = I
+    L.near_upsampled_slp_workspace_size.argtypes = [P, P, I32]
+    L.near_upsampled_slp_workspace_size.restype = SZ
+    L.near_upsampled_slp.argtypes = [P, P, P, I32, D, P, P, P, P, P, SZ, P]
+    L.near_upsampled_slp.restype = I
     L.near_features_eval.argtypes = [P, P, P, P, P, P]
     L.near_features_eval.restype = I
     L.near_scale_labels.argtypes = [I64, P, P, P, D, P, P]
@@ -77,6 +81,18 @@ def near_correct_eval(method, ves: Curves, trg: Targets, trg_curve, upsample, bl
     _check(L.near_correct_eval(int(method), ctypes.byref(cs), ctypes.byref(ts), _ptr(trg_curve), int(upsample),
                                _ptr(blob), float(threshold), float(mu), _ptr(du), _ptr(dv), _ptr(used_fallback),
                                _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def near_upsampled_slp(ves: Curves, trg: Targets, trg_curve, upsample, mu, u_up, v_up, u_trap, v_trap,
+                       ws=None, stream=None) -> None:
+    L = _bind()
+    cs, ts = ves.struct(), trg.struct()
+    if ws is None:
+        ws = _empty(L.near_upsampled_slp_workspace_size(ctypes.byref(cs), ctypes.byref(ts), int(upsample)),
+                    u_up.device)
+    _check(L.near_upsampled_slp(ctypes.byref(cs), ctypes.byref(ts), _ptr(trg_curve), int(upsample), float(mu),
+                                _ptr(u_up), _ptr(v_up), _ptr(u_trap), _ptr(v_trap), _ptr(ws), ws.numel(),
+                                _stream(stream)))
 
 
 def near_features_eval(ves: Curves, trg: Targets, trg_curve, X, frame, stream=None) -> None:
