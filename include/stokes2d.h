@@ -197,9 +197,11 @@ S2D_API size_t near_workspace_size(int method, const s2d_curves *ves, const s2d_
 /* Delta at every target (du, dv: [n] device FP64, written).  trg->on_curve /
  * on_node are ignored; trg_curve[i] names the curve of `ves` the correction
  * is for.  upsample = P (1..32).  mlp: device blob from near_mlp_pack (MLP,
- * AUTO).  threshold: AUTO falls back for a target when its bin's calibrated
- * error bound, in velocity units, exceeds it.  used_fallback: [n] device
- * int32 or NULL, set to 1 where the upsampled quadrature was used (AUTO).
+ * AUTO).  AUTO decides per target from the calibrated bounds of its bin
+ * (scaled by h F / (4 pi mu) into velocity units): Delta = 0 where the plain
+ * rule's bound is <= threshold, the network where its bound is, the
+ * upsampled quadrature otherwise.  used_fallback: [n] device int32 or NULL,
+ * set (AUTO) to 0 network, 1 upsampled quadrature, 2 no correction.
  * Targets of invalid curves get NaN. */
 S2D_API int near_correct_eval(int method, const s2d_curves *ves, const s2d_targets *trg,
                               const int32_t *trg_curve, int32_t upsample, const void *mlp,
@@ -243,12 +245,13 @@ S2D_API int near_mlp_train_step(int32_t batch, const int32_t *idx, const float *
 S2D_API int near_mlp_forward(int64_t n, const float *X, const float *params, float *Y, void *stream);
 
 /* Bytes of the BF16 inference blob; near_mlp_pack fills it from FP32 master
- * parameters and a calibrated error bound per bin of log10(|normal offset| / h)
- * (n_bins <= 64 bins of width bin_w starting at bin_lo), in the scaled output
- * units of near_scale_labels. */
+ * parameters and two calibrated error bounds per bin of
+ * log10(|normal offset| / h) (n_bins <= 64 bins of width bin_w starting at
+ * bin_lo), in the scaled output units of near_scale_labels: `bound` for the
+ * network and `bound_zero` for no correction at all (NULL: never skip). */
 S2D_API size_t near_mlp_blob_size(void);
-S2D_API int near_mlp_pack(const float *params, const float *bound, int32_t n_bins, float bin_lo,
-                          float bin_w, void *blob, void *stream);
+S2D_API int near_mlp_pack(const float *params, const float *bound, const float *bound_zero, int32_t n_bins,
+                          float bin_lo, float bin_w, void *blob, void *stream);
 
 /* Benchmarking aid (not capturable, not for production loops): while
  * enabled, each evaluation records a HIP event pair around its pair-sum

@@ -95,9 +95,9 @@ def features_one(x, y, nx, ny, kappa, w, fx, fy, px, py):
     tangential offset from k* is >= 0, else k* - 1, so the target lies over
     the interval [k0, k0+1).  Features: [s, n_off, dist, kappa h,
     f_t(k0-3..k0+4) / F, f_n(k0-3..k0+4) / F] with s, n_off the tangential
-    and normal offsets from node k0 and dist the distance to node k*, all in
-    units of h, t0 = (-n_y, n_x) at k0 and F the largest density norm in the
-    window (1 if zero)."""
+    and normal offsets from node k0 in units of h, dist = ln(|p - x_k*| / h),
+    t0 = (-n_y, n_x) at k0 and F the largest density norm in the window (1 if
+    zero)."""
     N = x.shape[0]
     h = w.sum() / N
     d2 = (px - x) ** 2 + (py - y) ** 2
@@ -112,7 +112,7 @@ def features_one(x, y, nx, ny, kappa, w, fx, fy, px, py):
     ox, oy = px - x[k0], py - y[k0]
     s = (ox * t0[0] + oy * t0[1]) / h
     no = (ox * n0[0] + oy * n0[1]) / h
-    dist = math.sqrt(d2[ks]) / h
+    dist = math.log(math.sqrt(d2[ks]) / h)
     idx = [(k0 + j) % N for j in range(WINDOW[0], WINDOW[1] + 1)]
     ft = np.array([fx[j] * t0[0] + fy[j] * t0[1] for j in idx])
     fn = np.array([fx[j] * n0[0] + fy[j] * n0[1] for j in idx])

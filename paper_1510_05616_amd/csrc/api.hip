@@ -536,8 +536,8 @@ S2D_API int near_mlp_forward(int64_t n, const float *X, const float *params, flo
 
 S2D_API size_t near_mlp_blob_size(void) { return align256(sizeof(s2d::NearBlob)); }
 
-S2D_API int near_mlp_pack(const float *params, const float *bound, int32_t n_bins, float bin_lo, float bin_w,
-                          void *blob, void *stream) {
+S2D_API int near_mlp_pack(const float *params, const float *bound, const float *bound_zero, int32_t n_bins,
+                          float bin_lo, float bin_w, void *blob, void *stream) {
     if (!params || !blob) return fail(S2D_EINVAL, "params and blob must not be NULL");
     if (n_bins < 0 || n_bins > s2d::kNearMaxBins) return fail(S2D_EINVAL, "n_bins must be in 0..64");
     if (n_bins > 0 && !bound) return fail(S2D_EINVAL, "bound must not be NULL when n_bins > 0");
@@ -545,7 +545,7 @@ S2D_API int near_mlp_pack(const float *params, const float *bound, int32_t n_bin
     int dev = 0;
     int rc = current_device(&dev);
     if (rc != S2D_OK) return rc;
-    hipError_t e = s2d::near_launch_pack(params, bound, n_bins, bin_lo, bin_w, (s2d::NearBlob *)blob,
+    hipError_t e = s2d::near_launch_pack(params, bound, bound_zero, n_bins, bin_lo, bin_w, (s2d::NearBlob *)blob,
                                          (hipStream_t)stream);
     return e == hipSuccess ? S2D_OK : hip_fail(e, "MLP pack launch");
 }

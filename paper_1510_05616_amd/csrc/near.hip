@@ -17,7 +17,7 @@
 //    FP64, over the target's own curve.
 //  * features: per target, nearest node k* by a scan of the curve, k0 = k* or
 //    k* - 1 so that the target lies over [k0, k0+1), the local frame of k0,
-//    offsets and distance in units of h = (sum w) / N, kappa h, and the
+//    offsets in units of h = (sum w) / N, ln(distance / h), kappa h, and the
 //    densities of nodes k0-3..k0+4 rotated into the frame and divided by
 //    their largest norm F.
 //  * MLP inference: 20 -> 64 -> 64 -> 64 -> 2, tanh-form GELU; weights and
@@ -206,7 +206,7 @@ __global__ __launch_bounds__(256) void near_features(int64_t n_trg, const double
     if (F == 0.0) F = 1.0;
     xi[0] = (float)((ox * t0 + oy * t1) / h);
     xi[1] = (float)((ox * n0 + oy * n1) / h);
-    xi[2] = (float)(sqrt(best) / h);
+    xi[2] = (float)log(sqrt(best) / h);
     xi[3] = (float)(kap[lo + k0] * h);
     for (int j = 0; j < 8; ++j) {
         xi[4 + j] = (float)(ft[j] / F);
@@ -314,19 +314,26 @@ __global__ __launch_bounds__(256) void near_mlp_infer(int64_t n_trg, const float
     }
     const double *fr = frame + 6 * i;
     const double sc = fr[4] * fr[5] / (4.0 * M_PI * mu);
-    // fallback decision from the calibrated bound of the target's bin
-    int fb = 0;
+    // decision from the calibrated bounds of the target's bin: no correction
+    // when the plain rule is already within the threshold, the network when
+    // its bound is, the upsampled quadrature otherwise
     if (use_bound) {
         const float noff = fabsf(xi[1]);
         int bin = (int)floorf((log10f(fmaxf(noff, 1e-30f)) - nb->bin_lo) / nb->bin_w);
         bin = bin < 0 ? 0 : (bin >= nb->n_bins ? nb->n_bins - 1 : bin);
-        fb = ((double)nb->bound[bin] * sc > threshold) || !(noff == noff);
-    }
-    if (fb) {
-        if (flag) flag[i] = 1;
-        const int slot = atomicAdd(count, 1);
-        list[slot] = (int32_t)i;
-        return;                        // the quadrature kernel writes du, dv
+        const bool bad = !(noff == noff);
+        if (!bad && (double)nb->bound_zero[bin] * sc <= threshold) {
+            if (flag) flag[i] = 2;
+            du[i] = 0.0;
+            dv[i] = 0.0;
+            return;
+        }
+        if (bad || (double)nb->bound[bin] * sc > threshold) {
+            if (flag) flag[i] = 1;
+            const int slot = atomicAdd(count, 1);
+            list[slot] = (int32_t)i;
+            return;                    // the quadrature kernel writes du, dv
+        }
     }
     if (flag) flag[i] = 0;
     du[i] = sc * ((double)y0 * fr[0] + (double)y1 * fr[2]);
@@ -339,7 +346,8 @@ __global__ void near_zero_count(int32_t *count) {
 
 // Pack FP32 master parameters into the BF16 inference blob.
 __global__ __launch_bounds__(256) void near_pack(const float *__restrict__ prm, const float *__restrict__ bound,
-                                                 int32_t n_bins, float bin_lo, float bin_w, NearBlob *__restrict__ nb) {
+                                                 const float *__restrict__ bound_zero, int32_t n_bins, float bin_lo,
+                                                 float bin_w, NearBlob *__restrict__ nb) {
     const MlpOffsets O;
     constexpr int r0 = kNearFeat;                  // W1 pairs
     constexpr int r1 = r0 + 64 * kNearFeat / 2;    // W2
@@ -368,7 +376,8 @@ __global__ __launch_bounds__(256) void near_pack(const float *__restrict__ prm, 
             nb->b2[o] = prm[O.b2 + o];
             nb->b3[o] = prm[O.b3 + o];
             if (o < 2) nb->b4[o] = prm[O.b4 + o];
-            nb->bound[o] = o < n_bins ? bound[o] : 0.f;
+            nb->bound[o] = o < n_bins ? bound[o] : 3e38f;
+            nb->bound_zero[o] = (o < n_bins && bound_zero) ? bound_zero[o] : 3e38f;
             if (o == 0) {
                 nb->n_bins = n_bins;
                 nb->bin_lo = bin_lo;
@@ -577,10 +586,10 @@ hipError_t near_launch_infer(int64_t n, const float *X, const double *frame, con
     return hipGetLastError();
 }
 
-hipError_t near_launch_pack(const float *prm, const float *bound, int32_t n_bins, float bin_lo, float bin_w,
-                            NearBlob *nb, hipStream_t st) {
-    hipLaunchKernelGGL(near_pack, dim3(grid_for(kNearBlobWork)), dim3(256), 0, st, prm, bound, n_bins, bin_lo,
-                       bin_w, nb);
+hipError_t near_launch_pack(const float *prm, const float *bound, const float *bound_zero, int32_t n_bins,
+                            float bin_lo, float bin_w, NearBlob *nb, hipStream_t st) {
+    hipLaunchKernelGGL(near_pack, dim3(grid_for(kNearBlobWork)), dim3(256), 0, st, prm, bound, bound_zero, n_bins,
+                       bin_lo, bin_w, nb);
     return hipGetLastError();
 }
 

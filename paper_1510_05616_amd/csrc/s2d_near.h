@@ -28,7 +28,8 @@ struct NearBlob {
     float b4[2];
     int32_t n_bins;
     float bin_lo, bin_w;
-    float bound[kNearMaxBins];
+    float bound[kNearMaxBins];        // network error bound per bin (scaled units)
+    float bound_zero[kNearMaxBins];   // plain-rule error bound per bin (scaled units)
 };
 constexpr int kNearBlobWork = kNearFeat + 64 * kNearFeat / 2 + 2 * 64 * 32 + 2 * 32 + 64;
 
@@ -44,8 +45,8 @@ hipError_t near_launch_scale_labels(int64_t n, const double *du, const double *d
 hipError_t near_launch_infer(int64_t n, const float *X, const double *frame, const NearBlob *nb, double mu,
                              double threshold, int use_bound, double *du, double *dv, int32_t *flag, int32_t *list,
                              int32_t *count, hipStream_t st);
-hipError_t near_launch_pack(const float *prm, const float *bound, int32_t n_bins, float bin_lo, float bin_w,
-                            NearBlob *nb, hipStream_t st);
+hipError_t near_launch_pack(const float *prm, const float *bound, const float *bound_zero, int32_t n_bins,
+                            float bin_lo, float bin_w, NearBlob *nb, hipStream_t st);
 hipError_t near_launch_train_step(int32_t B, const int32_t *idx, const float *X, const float *T, float *prm,
                                   float *m, float *v, int32_t step, float lr, float *grad, float *act, float *dY,
                                   float *lossv, float *loss, int update, hipStream_t st);

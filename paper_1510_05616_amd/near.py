@@ -55,7 +55,7 @@ def _bind():
     L.near_mlp_forward.restype = I
     L.near_mlp_blob_size.argtypes = []
     L.near_mlp_blob_size.restype = SZ
-    L.near_mlp_pack.argtypes = [P, P, I32, F, F, P, P]
+    L.near_mlp_pack.argtypes = [P, P, P, I32, F, F, P, P]
     L.near_mlp_pack.restype = I
     _bound = True
     return L
@@ -127,10 +127,10 @@ def near_mlp_blob_size() -> int:
     return int(_bind().near_mlp_blob_size())
 
 
-def near_mlp_pack(params, bound, n_bins, bin_lo, bin_w, blob, stream=None) -> None:
+def near_mlp_pack(params, bound, n_bins, bin_lo, bin_w, blob, bound_zero=None, stream=None) -> None:
     L = _bind()
-    _check(L.near_mlp_pack(_ptr(params), _ptr(bound), int(n_bins), float(bin_lo), float(bin_w), _ptr(blob),
-                           _stream(stream)))
+    _check(L.near_mlp_pack(_ptr(params), _ptr(bound), _ptr(bound_zero), int(n_bins), float(bin_lo), float(bin_w),
+                           _ptr(blob), _stream(stream)))
 
 
 # ----------------------------------------------------------------------------
@@ -238,9 +238,10 @@ def scaled_errors(data: NearData, du_pred, dv_pred):
 
 
 def calibrate(data: NearData, params, quantile=1.0, safety=1.5):
-    """Per-bin error bound of the BF16 network on validation data (bins of
-    log10 |normal offset| / h): the max (quantile 1) scaled error times
-    `safety`.  Returns (blob tensor, bound numpy array)."""
+    """Per-bin error bounds on validation data (bins of log10 |normal
+    offset| / h), in scaled units: the max (quantile 1) error of the BF16
+    network and of no correction at all, times `safety`.  Returns (blob
+    tensor, network bound, no-correction bound) (numpy arrays)."""
     import torch
     dev = data.X.device
     blob = torch.zeros(near_mlp_blob_size(), dtype=torch.uint8, device=dev)
@@ -250,15 +251,17 @@ def calibrate(data: NearData, params, quantile=1.0, safety=1.5):
     dv = torch.empty_like(data.dv)
     near_correct_eval(S2D_NEAR_MLP, data.curves, data.trg, data.tc, data.P, blob, 0.0, data.mu, du, dv)
     err = scaled_errors(data, du, dv).cpu().numpy()
+    err0 = scaled_errors(data, torch.zeros_like(du), torch.zeros_like(dv)).cpu().numpy()
     noff = np.abs(data.X[:, 1].double().cpu().numpy())
     b = np.clip(np.floor((np.log10(np.maximum(noff, 1e-30)) - BIN_LO) / BIN_W).astype(int), 0, N_BINS - 1)
-    bound = np.zeros(N_BINS)
+    bound = np.full(N_BINS, np.inf)
+    bound0 = np.full(N_BINS, np.inf)
     for k in range(N_BINS):
-        e = err[b == k]
-        if e.size:
-            bound[k] = (np.quantile(e, quantile) if quantile < 1 else e.max()) * safety
-        else:
-            bound[k] = np.inf
-    bt = torch.as_tensor(np.minimum(bound, 3e38), dtype=torch.float32, device=dev)
-    near_mlp_pack(params, bt, N_BINS, BIN_LO, BIN_W, blob)
-    return blob, bound
+        sel = b == k
+        if sel.any():
+            q = (lambda e: np.quantile(e, quantile)) if quantile < 1 else np.max
+            bound[k] = q(err[sel]) * safety
+            bound0[k] = q(err0[sel]) * safety
+    cap = lambda a: torch.as_tensor(np.minimum(a, 3e38), dtype=torch.float32, device=dev)
+    near_mlp_pack(params, cap(bound), N_BINS, BIN_LO, BIN_W, blob, bound_zero=cap(bound0))
+    return blob, bound, bound0

@@ -100,7 +100,7 @@ def test_features_reconstruct_target_and_window():
         assert abs(hh - h) < 1e-15
         d2 = (px - c.x) ** 2 + (py - c.y) ** 2
         ks = int(np.argmin(d2))
-        assert abs(f[2] - math.sqrt(d2[ks]) / h) < 1e-12          # distance to the nearest node
+        assert abs(f[2] - math.log(math.sqrt(d2[ks]) / h)) < 1e-12   # log distance to the nearest node
         # the target is x_k0 + h (s t0 + n_off n0) for the node k0 whose frame it uses
         k0 = [j for j in range(N) if abs(-c.ny[j] - t0[0]) < 1e-15 and abs(c.nx[j] - t0[1]) < 1e-15][0]
         assert k0 in (ks, (ks - 1) % N) and f[0] >= 0.0 or k0 == (ks - 1) % N
