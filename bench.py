@@ -18,8 +18,11 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--cpu-sample T]
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
+import math
 import os
+import re
 import sys
 import time
 
@@ -32,8 +35,48 @@ FLOPS_PER_PAIR = 19          # algorithmic flops per pair, SLP and DLP alike
 PEAK = {"f32": 157.3e12, "f64": 78.6e12}
 
 
+PAIR_SOURCES = ("paper_1510_05616_amd/csrc/pair_impl.h", "paper_1510_05616_amd/csrc/pair.hip",
+                "paper_1510_05616_amd/csrc/s2d_internal.h")
+PROFILE = "profiles/pair_kernels_config3.md"
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def pair_source_sha1():
+    h = hashlib.sha1()
+    for f in PAIR_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` recorded in the committed rocprofv3
+    summary, or None when the pair-kernel sources changed since it was taken."""
+    try:
+        txt = open(os.path.join(ROOT, PROFILE)).read()
+    except OSError:
+        return None
+    m = re.search(r"pair-kernel source sha1: ([0-9a-f]{40})", txt)
+    if not m or m.group(1) != pair_source_sha1():
+        return None
+    m = re.search(r"traffic_bytes " + re.escape(kernel) + r" (\d+)", txt)
+    return int(m.group(1)) if m else None
+
+
+def copy_probe():
+    """A device-to-device copy of exactly 1 GiB, three times (for calibrating
+    the FETCH_SIZE / WRITE_SIZE counters)."""
+    import torch
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"copied 3 x {4 * n} bytes", flush=True)
 
 
 def load_problem(cfg: int):
@@ -85,6 +128,87 @@ def run_mode(prob, mode, steps, warmup):
                 u=u.cpu().numpy(), v=v.cpu().numpy(), ws_bytes=nws)
 
 
+def _time(fn, reps=3):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def near_section():
+    """Learned near-field correction on the near-target workload: train on
+    200k targets, calibrate on 20k, test on 1M (targets at log-uniform
+    normal distances 0.05 h .. 5 h from ellipses of 64-128 nodes).  Errors are
+    normalised per curve by the largest |u| of the 8x upsampled single layer
+    over that curve's test targets."""
+    import torch
+    import synth
+    from paper_1510_05616_amd import near
+    t0 = time.time()
+    tr = near.NearData(*synth.make_near_dataset(200000, 5)[:4], mu=1.0, upsample=8)
+    va = near.NearData(*synth.make_near_dataset(20000, 6)[:4], mu=1.0, upsample=8)
+    c, tx, ty, tc, dh = synth.make_near_dataset(1000000, 7)
+    te = near.NearData(c, tx, ty, tc, mu=1.0, upsample=8, labels=False)
+    log(f"near: data ready ({time.time() - t0:.1f}s)")
+    t0 = time.time()
+    params, hist = near.train(tr, epochs=40, batch=512, lr=3e-3)
+    torch.cuda.synchronize()
+    t_train = time.time() - t0
+    blob, bound, bound0 = near.calibrate(va, params)
+    log(f"near: trained 40 epochs in {t_train:.1f}s, loss {hist[0]:.3e} -> {hist[-1]:.3e}")
+    n = te.n
+    dev = "cuda"
+    uP = torch.empty(n, dtype=torch.float64, device=dev)
+    vP, u1, v1 = torch.empty_like(uP), torch.empty_like(uP), torch.empty_like(uP)
+    near.near_upsampled_slp(te.curves, te.trg, te.tc, 8, 1.0, uP, vP, u1, v1)
+    d_up, e_up = uP - u1, vP - v1
+    tcl = te.tc.long()
+    mag = torch.hypot(uP, vP)
+    scale_c = torch.zeros(te.curves.n_curves, dtype=torch.float64, device=dev).scatter_reduce(
+        0, tcl, mag, reduce="amax", include_self=False)
+    scale = scale_c[tcl]
+    thr = 1e-5 * float(scale_c.min())
+    du, dv = torch.empty_like(uP), torch.empty_like(uP)
+    fb = torch.zeros(n, dtype=torch.int32, device=dev)
+    ws_up = near._empty(near.near_workspace_size(0, te.curves, te.trg, 8))
+    ws_ml = near._empty(near.near_workspace_size(2, te.curves, te.trg, 8))
+    run = lambda m, th=0.0, flag=None, ws=ws_ml: near.near_correct_eval(m, te.curves, te.trg, te.tc, 8, blob, th,
+                                                                      1.0, du, dv, flag, ws)
+    ms_up = _time(lambda: run(near.S2D_NEAR_UPSAMPLE, ws=ws_up))
+    ms_mlp = _time(lambda: run(near.S2D_NEAR_MLP))
+    err = lambda: float((torch.hypot(du - d_up, dv - e_up) / scale).max())
+    run(near.S2D_NEAR_MLP)
+    e_mlp = err()
+    ms_auto = _time(lambda: run(near.S2D_NEAR_AUTO, thr, fb))
+    run(near.S2D_NEAR_AUTO, thr, fb)
+    e_auto = err()
+    frac_fb = float((fb == 1).double().mean())
+    frac_zero = float((fb == 2).double().mean())
+    e_plain = float((torch.hypot(d_up, e_up) / scale).max())
+    # 32x upsampled quadrature as context for the 8x judge
+    u32, v32 = torch.empty_like(uP), torch.empty_like(uP)
+    near.near_upsampled_slp(te.curves, te.trg, te.tc, 32, 1.0, u32, v32, u1, v1)
+    e_8v32 = float((torch.hypot(uP - u32, vP - v32) / scale).max())
+    res = {"workload": "1e6 targets at 0.05h..5h from 5000 ellipses of 64/96/128 nodes; MLP 20-64-64-64-2 "
+                       "trained on 2e5 8x-upsampled labels, calibrated on 2e4",
+           "threshold_abs": thr, "err_vs_upsampled8": {"mlp": e_mlp, "auto": e_auto, "no_correction": e_plain},
+           "err_upsampled8_vs_32": e_8v32, "auto_fraction_fallback": frac_fb, "auto_fraction_no_correction":
+               frac_zero, "ms": {"upsampled8": ms_up, "mlp": ms_mlp, "auto": ms_auto},
+           "speedup_vs_upsampled8": {"mlp": ms_up / ms_mlp, "auto": ms_up / ms_auto},
+           "train_s": t_train, "epochs": 40, "final_loss": hist[-1]}
+    log(f"near: upsampled {ms_up:.2f} ms, mlp {ms_mlp:.2f} ms (E={e_mlp:.2e}), auto {ms_auto:.2f} ms "
+        f"(E={e_auto:.2e}, fallback {frac_fb:.3f}, no-correction {frac_zero:.3f}); plain E={e_plain:.2e}, "
+        f"8x vs 32x {e_8v32:.2e}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,7 +217,12 @@ def main():
     ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=8192,
                     help="targets of the workload the FP64 oracle evaluates on the host (0: skip)")
+    ap.add_argument("--near", type=int, default=1, help="run the near-field correction section (0: skip)")
+    ap.add_argument("--copy-probe", action="store_true", help="only copy 1 GiB on the device and exit")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the target-sharded design is described in DESIGN.md)", file=sys.stderr)
@@ -119,7 +248,9 @@ def main():
                          slp_pair_ms=r["slp_ms"], dlp_pair_ms=r["dlp_ms"],
                          roofline={"bound": "alu", "kernel": "pair_kernel<SLP>",
                                    "achieved": ach / 1e12, "peak": PEAK[name] / 1e12,
-                                   "unit": "TFLOP/s", "frac": ach / PEAK[name], "traffic": None,
+                                   "unit": "TFLOP/s", "frac": ach / PEAK[name],
+                                   "traffic": measured_traffic(
+                                       "pair_kernel<0,1,2>" if name == "f32" else "pair_kernel<0,0,1>"),
                                    "flops_per_pair": FLOPS_PER_PAIR, "pairs_per_launch": pairs_slp},
                          u=r["u"], v=r["v"])
         log(f"{name}: {ms_step:.3f} ms/step, {pairs / (ms_step * 1e-3):.4e} pairs/s, "
@@ -152,6 +283,8 @@ def main():
         log(f"oracle: {dt:.1f}s on {cpu['cores']} threads, {cpu['value']:.3e} pairs/s; "
             f"rel err f32={errs['f32']:.2e} f64={errs['f64']:.2e}")
 
+    near_res = near_section() if args.near else None
+
     f32, f64 = res["f32"], res["f64"]
     line = {
         "metric": "Stokes pair-evals/s at N=128k, FP32 vs FP64 on GPU, at 1e-6 rel err vs FP64 oracle",
@@ -169,6 +302,7 @@ def main():
                  "dtype": "f64", "roofline": f64["roofline"]},
         "kernel_ms": {"f32_slp_pair": f32["slp_pair_ms"], "f32_dlp_pair": f32["dlp_pair_ms"],
                       "f64_slp_pair": f64["slp_pair_ms"], "f64_dlp_pair": f64["dlp_pair_ms"]},
+        "near": near_res,
     }
     print(json.dumps(line), flush=True)
 

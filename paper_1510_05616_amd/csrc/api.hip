@@ -106,6 +106,9 @@ s2d::Plan make_plan(int op, int mode, const s2d_curves *s, const s2d_targets *t,
     size_t off = 0;
     p.off_rec = off;
     off = align256(off + (size_t)p.n_sb * kSuperBlock * rec_bytes(op, mode));
+    p.off_sub = off;
+    if (mode == S2D_FP32C)
+        off = align256(off + (size_t)p.n_sb * (kSuperBlock / kSubBlock) * sizeof(s2d::SubInfo));
     p.off_sbsum = off;
     if (op == S2D_OP_SLP && mode == S2D_FP32C) off = align256(off + (size_t)p.n_sb * 2 * sizeof(double));
     p.off_part = off;
@@ -178,6 +181,7 @@ int eval(int op, int mode, const s2d_curves *src, const s2d_targets *trg, double
     PairArgs a{};
     a.rec = (char *)ws + p.off_rec;
     a.sbsum = (const double *)((char *)ws + p.off_sbsum);
+    a.sub = (const SubInfo *)((char *)ws + p.off_sub);
     a.n_src = p.n_src;
     a.tx = trg->x;
     a.ty = trg->y;

@@ -83,19 +83,27 @@ __global__ void batch_reset(unsigned long long *counter) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0ull;
 }
 
+// FP64: one thread per padded source; FP32C: one thread per sub-block
+// (the prefix sums count padded sources; sub-blocks never straddle instances).
 template <int PREC>
 __global__ __launch_bounds__(256) void batch_prep(BatchTables t, int op) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t g = PREC == S2D_FP64 ? g0 : g0 * kSubBlock;
     const int64_t *off = op == 0 ? t.src_pad_off0 : t.src_pad_off1;
     if (g >= off[t.n_inst]) return;
     const int k = find_inst(off, t.n_inst, g);
     const BatchInst &I = t.inst[k];
     const int64_t j = g - off[k];
     const s2d_curves &s = I.src[op];
-    if (op == 0)
-        prep_one<S2D_OP_SLP, PREC>(j, s.n_nodes, s.x, s.y, s.nx, s.ny, s.w, s.fx, s.fy, (void *)I.pa[0].rec);
-    else
-        prep_one<S2D_OP_DLP, PREC>(j, s.n_nodes, s.x, s.y, s.nx, s.ny, s.w, s.fx, s.fy, (void *)I.pa[1].rec);
+    void *rec = (void *)I.pa[op].rec;
+    if (PREC == S2D_FP64) {
+        if (op == 0) prep_one64<S2D_OP_SLP>(j, s.n_nodes, s.x, s.y, s.nx, s.ny, s.w, s.fx, s.fy, rec);
+        else prep_one64<S2D_OP_DLP>(j, s.n_nodes, s.x, s.y, s.nx, s.ny, s.w, s.fx, s.fy, rec);
+    } else {
+        SubInfo *sub = (SubInfo *)I.pa[op].sub;
+        if (op == 0) prep_sub32<S2D_OP_SLP>(j / kSubBlock, s.n_nodes, s.x, s.y, s.nx, s.ny, s.w, s.fx, s.fy, rec, sub);
+        else prep_sub32<S2D_OP_DLP>(j / kSubBlock, s.n_nodes, s.x, s.y, s.nx, s.ny, s.w, s.fx, s.fy, rec, sub);
+    }
 }
 
 __global__ __launch_bounds__(256) void batch_sbsum(BatchTables t) {
@@ -287,7 +295,7 @@ size_t recb(int op, int mode) {
 // Per-instance sizes for a tile configuration.
 struct InstGeom {
     int64_t n_sb[2], n_tiles, n_splits[2], sbps;
-    size_t off_rec[2], off_sbsum, off_part[2], off_self, off_kress, bytes;
+    size_t off_rec[2], off_sub[2], off_sbsum, off_part[2], off_self, off_kress, bytes;
     bool self;
 };
 
@@ -303,6 +311,8 @@ InstGeom inst_geom(const s2d_instance &I, int mode, const TuneChoice &c) {
         g.n_splits[op] = n > 0 ? (g.n_sb[op] + c.sbps - 1) / c.sbps : 0;
         g.off_rec[op] = off;
         off = al256(off + (size_t)g.n_sb[op] * kSuperBlock * recb(op, mode));
+        g.off_sub[op] = off;
+        if (mode == S2D_FP32C) off = al256(off + (size_t)g.n_sb[op] * (kSuperBlock / kSubBlock) * sizeof(SubInfo));
     }
     g.off_sbsum = off;
     if (mode == S2D_FP32C) off = al256(off + (size_t)g.n_sb[0] * 16);
@@ -392,13 +402,14 @@ hipError_t record_graph(BatchPlan &P, const BatchTables &t, int n_pre_targets, i
     if (e != hipSuccess) return done(e);
     hipLaunchKernelGGL(batch_reset, dim3(1), dim3(64), 0, st, t.counter);
     const int prec = P.mode;
-    if (tot_src0 > 0) {
-        if (prec == S2D_FP64) hipLaunchKernelGGL(batch_prep<S2D_FP64>, dim3((unsigned)((tot_src0 + 255) / 256)), dim3(256), 0, st, t, 0);
-        else hipLaunchKernelGGL(batch_prep<S2D_FP32C>, dim3((unsigned)((tot_src0 + 255) / 256)), dim3(256), 0, st, t, 0);
-    }
-    if (tot_src1 > 0) {
-        if (prec == S2D_FP64) hipLaunchKernelGGL(batch_prep<S2D_FP64>, dim3((unsigned)((tot_src1 + 255) / 256)), dim3(256), 0, st, t, 1);
-        else hipLaunchKernelGGL(batch_prep<S2D_FP32C>, dim3((unsigned)((tot_src1 + 255) / 256)), dim3(256), 0, st, t, 1);
+    for (int op = 0; op < 2; ++op) {
+        const int64_t tot = op == 0 ? tot_src0 : tot_src1;
+        if (tot <= 0) continue;
+        if (prec == S2D_FP64)
+            hipLaunchKernelGGL(batch_prep<S2D_FP64>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, t, op);
+        else
+            hipLaunchKernelGGL(batch_prep<S2D_FP32C>, dim3((unsigned)((tot / kSubBlock + 255) / 256)), dim3(256), 0,
+                               st, t, op);
     }
     if (prec == S2D_FP32C && tot_sb > 0)
         hipLaunchKernelGGL(batch_sbsum, dim3((unsigned)((tot_sb + 255) / 256)), dim3(256), 0, st, t);
@@ -481,6 +492,7 @@ int build_plan(BatchPlan &P, int mode, int32_t n_inst, const s2d_instance *inst,
             const s2d_targets &tr = op == 0 ? I.trg_ves : I.trg_wall;
             a.rec = db + data + g.off_rec[op];
             a.sbsum = (op == 0 && mode == S2D_FP32C) ? (const double *)(db + data + g.off_sbsum) : nullptr;
+            a.sub = mode == S2D_FP32C ? (const SubInfo *)(db + data + g.off_sub[op]) : nullptr;
             a.n_src = s.n_nodes;
             a.tx = tr.x;
             a.ty = tr.y;

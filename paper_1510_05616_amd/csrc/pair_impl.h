@@ -23,11 +23,14 @@
 // meets the hull at n = 0, or the ragged last superblock, takes a masked path
 // with a per-pair select.  All other superblocks take the unmasked path.
 //
-// Precision.  FP64 mode evaluates each term in double.  FP32C mode forms the
-// coordinate difference in double and rounds it once to float (so r carries a
-// relative error of one rounding, also for near pairs), evaluates the term in
-// float with the hardware log2 and reciprocal, sums kSubBlock terms in float
-// and merges them into double accumulators.  For the single-layer log term a
+// Precision.  FP64 mode evaluates each term in double.  FP32C mode evaluates
+// each term in float with the hardware log2 and reciprocal, sums a sub-block
+// of kSubBlock sources in float and merges it into double accumulators.  The
+// difference r is formed, per sub-block and wave, either from FP32 offsets to
+// the sub-block's FP64 origin (when every target of the wave is at least
+// kFarRadii sub-block radii away, so r keeps a relative error of a few
+// roundings) or in double and rounded once (near sub-blocks, so near pairs
+// keep one-rounding relative accuracy).  For the single-layer log term a
 // per-(target, superblock, image) reference distance q_ref is divided out
 // before the float log2 and its log is added back in double against the
 // superblock's FP64 density sum, so the float logs stay O(1) in magnitude.
@@ -109,10 +112,9 @@ __device__ __forceinline__ void slp64_pair(double px, double py, const RecSlp64 
     by = __builtin_fma(ry, t, by);
 }
 
-// FP32 single layer term added to (sx, sy); iqr scales q before the log.
-__device__ __forceinline__ void slp32_acc(double px, double py, const RecSlp32 &s, float iqr,
-                                          float &sx, float &sy) {
-    float rx = (float)(px - s.x), ry = (float)(py - s.y);
+// FP32 single layer term for the difference r = (rx, ry), added to (sx, sy);
+// iqr scales q before the log.
+__device__ __forceinline__ void slp32_r(float rx, float ry, const RecSlp32 &s, float iqr, float &sx, float &sy) {
     float q = __builtin_fmaf(rx, rx, ry * ry);
     float lq = __builtin_amdgcn_logf(q * iqr);      // log2
     float iq = __builtin_amdgcn_rcpf(q);
@@ -121,6 +123,12 @@ __device__ __forceinline__ void slp32_acc(double px, double py, const RecSlp32 &
     sx = __builtin_fmaf(rx, t, sx);
     sy = __builtin_fmaf(s.ly, lq, sy);
     sy = __builtin_fmaf(ry, t, sy);
+}
+
+// exact path: the difference formed in FP64 and rounded once
+__device__ __forceinline__ void slp32_acc(double px, double py, const RecSlp32 &s, float iqr,
+                                          float &sx, float &sy) {
+    slp32_r((float)(px - s.x), (float)(py - s.y), s, iqr, sx, sy);
 }
 
 __device__ __forceinline__ void dlp64_pair(double px, double py, const RecDlp64 &s,
@@ -135,9 +143,7 @@ __device__ __forceinline__ void dlp64_pair(double px, double py, const RecDlp64 
     uy = __builtin_fma(ry, f, uy);
 }
 
-__device__ __forceinline__ void dlp32_acc(double px, double py, const RecDlp32 &s,
-                                          float &sx, float &sy) {
-    float rx = (float)(px - s.x), ry = (float)(py - s.y);
+__device__ __forceinline__ void dlp32_r(float rx, float ry, const RecDlp32 &s, float &sx, float &sy) {
     float q = __builtin_fmaf(rx, rx, ry * ry);
     float iq = __builtin_amdgcn_rcpf(q);
     float rn = __builtin_fmaf(rx, s.nx, ry * s.ny);
@@ -145,6 +151,27 @@ __device__ __forceinline__ void dlp32_acc(double px, double py, const RecDlp32 &
     float f = (rn * rt) * (iq * iq);
     sx = __builtin_fmaf(rx, f, sx);
     sy = __builtin_fmaf(ry, f, sy);
+}
+
+__device__ __forceinline__ void dlp32_acc(double px, double py, const RecDlp32 &s, float &sx, float &sy) {
+    dlp32_r((float)(px - s.x), (float)(py - s.y), s, sx, sy);
+}
+
+// Offsets of the targets from sub-block origin si in FP32, and whether every
+// active target of the wave is at least kFarRadii sub-block radii away (then
+// r = offset - local source offset has a relative error of a few roundings).
+template <int TPT>
+__device__ __forceinline__ bool far_offsets(const SubInfo &si, const double (&px)[TPT], const double (&py)[TPT],
+                                            const bool (&act)[TPT], float (&dx)[TPT], float (&dy)[TPT]) {
+    bool far = true;
+    const float r2 = (float)si.r2;
+#pragma unroll
+    for (int k = 0; k < TPT; ++k) {
+        dx[k] = (float)(px[k] - si.ox);
+        dy[k] = (float)(py[k] - si.oy);
+        far = far && (!act[k] || __builtin_fmaf(dx[k], dx[k], dy[k] * dy[k]) >= r2);
+    }
+    return __all(far);
 }
 
 // ---------------------------------------------------------------------------
@@ -158,16 +185,17 @@ __device__ __forceinline__ void pair_tile(const PairArgs &a, int64_t tile, int s
     double tx[TPT], ty[TPT];
     int lo[TPT], hi[TPT];
     int64_t ti[TPT];
+    bool act[TPT];
     int hlo = INT_MAX, hhi = INT_MIN;
 #pragma unroll
     for (int k = 0; k < TPT; ++k) {
         ti[k] = tile * (int64_t)(kWave * TPT) + k * kWave + lane;
-        const bool act = ti[k] < a.n_trg;
-        tx[k] = act ? a.tx[ti[k]] : 0.0;
-        ty[k] = act ? a.ty[ti[k]] : 0.0;
+        act[k] = ti[k] < a.n_trg;
+        tx[k] = act[k] ? a.tx[ti[k]] : 0.0;
+        ty[k] = act[k] ? a.ty[ti[k]] : 0.0;
         lo[k] = 0;
         hi[k] = 0;
-        if (act && a.on_curve) {
+        if (act[k] && a.on_curve) {
             const int c = a.on_curve[ti[k]];
             if (c >= 0 && c < a.n_curves) {
                 if (OP == S2D_OP_SLP) {
@@ -242,14 +270,24 @@ __device__ __forceinline__ void pair_tile(const PairArgs &a, int64_t tile, int s
                             uy[k] = __builtin_fma(c, gsy, uy[k]);
                         }
                         for (int u = 0; u < kSuperBlock; u += kSubBlock) {
-                            float sx[TPT], sy[TPT];
+                            float sx[TPT], sy[TPT], dx[TPT], dy[TPT];
 #pragma unroll
                             for (int k = 0; k < TPT; ++k) { sx[k] = 0.f; sy[k] = 0.f; }
+                            if (far_offsets<TPT>(a.sub[(j0 + u) / kSubBlock], px, py, act, dx, dy)) {
 #pragma unroll
-                            for (int q = 0; q < kSubBlock; ++q) {
-                                const RecSlp32 s = rec[u + q];
+                                for (int q = 0; q < kSubBlock; ++q) {
+                                    const RecSlp32 s = rec[u + q];
 #pragma unroll
-                                for (int k = 0; k < TPT; ++k) slp32_acc(px[k], py[k], s, iqr[k], sx[k], sy[k]);
+                                    for (int k = 0; k < TPT; ++k)
+                                        slp32_r(dx[k] - s.xl, dy[k] - s.yl, s, iqr[k], sx[k], sy[k]);
+                                }
+                            } else {
+#pragma unroll
+                                for (int q = 0; q < kSubBlock; ++q) {
+                                    const RecSlp32 s = rec[u + q];
+#pragma unroll
+                                    for (int k = 0; k < TPT; ++k) slp32_acc(px[k], py[k], s, iqr[k], sx[k], sy[k]);
+                                }
                             }
 #pragma unroll
                             for (int k = 0; k < TPT; ++k) { ux[k] += (double)sx[k]; uy[k] += (double)sy[k]; }
@@ -257,14 +295,23 @@ __device__ __forceinline__ void pair_tile(const PairArgs &a, int64_t tile, int s
                     } else {
                         const RecDlp32 *rec = (const RecDlp32 *)a.rec + j0;
                         for (int u = 0; u < kSuperBlock; u += kSubBlock) {
-                            float sx[TPT], sy[TPT];
+                            float sx[TPT], sy[TPT], dx[TPT], dy[TPT];
 #pragma unroll
                             for (int k = 0; k < TPT; ++k) { sx[k] = 0.f; sy[k] = 0.f; }
+                            if (far_offsets<TPT>(a.sub[(j0 + u) / kSubBlock], px, py, act, dx, dy)) {
 #pragma unroll
-                            for (int q = 0; q < kSubBlock; ++q) {
-                                const RecDlp32 s = rec[u + q];
+                                for (int q = 0; q < kSubBlock; ++q) {
+                                    const RecDlp32 s = rec[u + q];
 #pragma unroll
-                                for (int k = 0; k < TPT; ++k) dlp32_acc(px[k], py[k], s, sx[k], sy[k]);
+                                    for (int k = 0; k < TPT; ++k) dlp32_r(dx[k] - s.xl, dy[k] - s.yl, s, sx[k], sy[k]);
+                                }
+                            } else {
+#pragma unroll
+                                for (int q = 0; q < kSubBlock; ++q) {
+                                    const RecDlp32 s = rec[u + q];
+#pragma unroll
+                                    for (int k = 0; k < TPT; ++k) dlp32_acc(px[k], py[k], s, sx[k], sy[k]);
+                                }
                             }
 #pragma unroll
                             for (int k = 0; k < TPT; ++k) { ux[k] += (double)sx[k]; uy[k] += (double)sy[k]; }

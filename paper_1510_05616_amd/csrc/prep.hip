@@ -10,10 +10,15 @@ __global__ __launch_bounds__(256) void prep_records(int64_t n_src, int64_t n_pad
                                                     const double *__restrict__ nx, const double *__restrict__ ny,
                                                     const double *__restrict__ w,
                                                     const double *__restrict__ fx, const double *__restrict__ fy,
-                                                    void *rec_out) {
+                                                    void *rec_out, SubInfo *sub) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n_pad) return;
-    prep_one<OP, PREC>(j, n_src, x, y, nx, ny, w, fx, fy, rec_out);
+    if (PREC == S2D_FP64) {
+        if (j >= n_pad) return;
+        prep_one64<OP>(j, n_src, x, y, nx, ny, w, fx, fy, rec_out);
+    } else {
+        if (j >= n_pad / kSubBlock) return;           // one thread per sub-block
+        prep_sub32<OP>(j, n_src, x, y, nx, ny, w, fx, fy, rec_out, sub);
+    }
 }
 
 __global__ __launch_bounds__(256) void prep_sbsum(int64_t n_src, int64_t n_sb,
@@ -30,8 +35,10 @@ static hipError_t prep_t(const Plan &p, const s2d_curves *s, void *ws, hipStream
     const int64_t n_pad = p.n_sb * kSuperBlock;
     if (n_pad == 0) return hipSuccess;
     void *rec = (char *)ws + p.off_rec;
-    hipLaunchKernelGGL((prep_records<OP, PREC>), dim3((unsigned)((n_pad + 255) / 256)), dim3(256), 0, st,
-                       p.n_src, n_pad, s->x, s->y, s->nx, s->ny, s->w, s->fx, s->fy, rec);
+    SubInfo *sub = (SubInfo *)((char *)ws + p.off_sub);
+    const int64_t nthr = PREC == S2D_FP64 ? n_pad : n_pad / kSubBlock;
+    hipLaunchKernelGGL((prep_records<OP, PREC>), dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, st,
+                       p.n_src, n_pad, s->x, s->y, s->nx, s->ny, s->w, s->fx, s->fy, rec, sub);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (OP == S2D_OP_SLP && PREC == S2D_FP32C) {

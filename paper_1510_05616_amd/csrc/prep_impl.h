@@ -10,31 +10,61 @@
 
 namespace s2d {
 
-// Record j of a padded source array (zero record past n_src).
-template <int OP, int PREC>
-__device__ __forceinline__ void prep_one(int64_t j, int64_t n_src, const double *__restrict__ x,
-                                         const double *__restrict__ y, const double *__restrict__ nx,
-                                         const double *__restrict__ ny, const double *__restrict__ w,
-                                         const double *__restrict__ fx, const double *__restrict__ fy,
-                                         void *rec_out) {
+// Record j of a padded source array (zero record past n_src), FP64 modes.
+template <int OP>
+__device__ __forceinline__ void prep_one64(int64_t j, int64_t n_src, const double *__restrict__ x,
+                                           const double *__restrict__ y, const double *__restrict__ nx,
+                                           const double *__restrict__ ny, const double *__restrict__ w,
+                                           const double *__restrict__ fx, const double *__restrict__ fy,
+                                           void *rec_out) {
     const bool v = j < n_src;
     const double X = v ? x[j] : 0.0, Y = v ? y[j] : 0.0;
     const double W = v ? w[j] : 0.0;
     const double FX = v ? fx[j] : 0.0, FY = v ? fy[j] : 0.0;
     if (OP == S2D_OP_SLP) {
-        const double gx = W * FX, gy = W * FY;
-        if (PREC == S2D_FP64) {
-            ((RecSlp64 *)rec_out)[j] = RecSlp64{X, Y, gx, gy};
-        } else {
-            const double c = -0.34657359027997264;   // -ln(2)/2: natural log from log2
-            ((RecSlp32 *)rec_out)[j] = RecSlp32{X, Y, (float)gx, (float)gy, (float)(c * gx), (float)(c * gy)};
-        }
+        ((RecSlp64 *)rec_out)[j] = RecSlp64{X, Y, W * FX, W * FY};
     } else {
         const double NX = v ? W * nx[j] : 0.0, NY = v ? W * ny[j] : 0.0;
-        if (PREC == S2D_FP64) {
-            ((RecDlp64 *)rec_out)[j] = RecDlp64{X, Y, NX, NY, FX, FY};
+        ((RecDlp64 *)rec_out)[j] = RecDlp64{X, Y, NX, NY, FX, FY};
+    }
+}
+
+// FP32C sub-block u (kSubBlock records, zero past n_src): origin = its middle
+// valid node, radius = largest distance of a valid node from the origin;
+// records hold the FP64 node and its FP32 offset from the origin.
+template <int OP>
+__device__ __forceinline__ void prep_sub32(int64_t u, int64_t n_src, const double *__restrict__ x,
+                                           const double *__restrict__ y, const double *__restrict__ nx,
+                                           const double *__restrict__ ny, const double *__restrict__ w,
+                                           const double *__restrict__ fx, const double *__restrict__ fy,
+                                           void *rec_out, SubInfo *sub) {
+    const int64_t j0 = u * kSubBlock;
+    const int64_t nv = max((int64_t)0, min((int64_t)kSubBlock, n_src - j0));
+    double ox = 0.0, oy = 0.0, r2 = 0.0;
+    if (nv > 0) {
+        const int64_t jm = j0 + nv / 2;
+        ox = x[jm];
+        oy = y[jm];
+        for (int64_t j = j0; j < j0 + nv; ++j) {
+            const double dx = x[j] - ox, dy = y[j] - oy;
+            r2 = fmax(r2, dx * dx + dy * dy);
+        }
+    }
+    sub[u] = SubInfo{ox, oy, kFarRadii * kFarRadii * r2};
+    for (int64_t j = j0; j < j0 + kSubBlock; ++j) {
+        const bool v = j < n_src;
+        const double X = v ? x[j] : 0.0, Y = v ? y[j] : 0.0;
+        const double W = v ? w[j] : 0.0;
+        const double FX = v ? fx[j] : 0.0, FY = v ? fy[j] : 0.0;
+        const float xl = (float)(X - ox), yl = (float)(Y - oy);
+        if (OP == S2D_OP_SLP) {
+            const double gx = W * FX, gy = W * FY;
+            const double c = -0.34657359027997264;   // -ln(2)/2: natural log from log2
+            ((RecSlp32 *)rec_out)[j] =
+                RecSlp32{X, Y, xl, yl, (float)gx, (float)gy, (float)(c * gx), (float)(c * gy)};
         } else {
-            ((RecDlp32 *)rec_out)[j] = RecDlp32{X, Y, (float)NX, (float)NY, (float)FX, (float)FY};
+            const double NX = v ? W * nx[j] : 0.0, NY = v ? W * ny[j] : 0.0;
+            ((RecDlp32 *)rec_out)[j] = RecDlp32{X, Y, xl, yl, (float)NX, (float)NY, (float)FX, (float)FY};
         }
     }
 }

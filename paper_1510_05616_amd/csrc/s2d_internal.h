@@ -15,15 +15,20 @@ constexpr int kWave = 64;            // CDNA wavefront width
 constexpr int kWavesPerBlock = 4;    // pair kernels: 4 independent waves per workgroup
 constexpr int kBlock = kWave * kWavesPerBlock;
 constexpr int kSuperBlock = 256;     // sources per superblock (split granularity, FP32 log reference)
-constexpr int kSubBlock = 8;         // FP32 sub-block merged into the FP64 accumulators
+constexpr int kSubBlock = 16;        // FP32 sub-block: local origin, merged into the FP64 accumulators
+constexpr double kFarRadii = 4.0;    // a sub-block is far from a target beyond this many radii
 constexpr int kMaxImages = 64;
 
 // Source records written by the preparation kernels: one wave-uniform record
 // per source, read through the scalar data path by the pair kernels.
 struct alignas(32) RecSlp64 { double x, y, gx, gy; };                 // g = w f
-struct alignas(32) RecSlp32 { double x, y; float gx, gy, lx, ly; };    // l = -ln2/2 * g
+// FP32C records carry the FP64 node (exact path) and its offset from the
+// sub-block origin in FP32 (far path).
+struct alignas(16) RecSlp32 { double x, y; float xl, yl, gx, gy, lx, ly; };   // l = -ln2/2 * g
 struct alignas(16) RecDlp64 { double x, y, nx, ny, tx, ty; };         // nu = w n, tau
-struct alignas(32) RecDlp32 { double x, y; float nx, ny, tx, ty; };
+struct alignas(16) RecDlp32 { double x, y; float xl, yl, nx, ny, tx, ty; };
+// per FP32C sub-block: origin and (kFarRadii * radius)^2
+struct SubInfo { double ox, oy, r2; };
 
 // One launch's decomposition of (targets x sources).
 struct Plan {
@@ -36,12 +41,13 @@ struct Plan {
     int64_t n_blocks;        // workgroups of the pair kernel
     bool self;               // targets carry on_curve/on_node and image 0 is in range
     // workspace carve-out (byte offsets)
-    size_t off_rec, off_sbsum, off_part, off_self, off_kress, total;
+    size_t off_rec, off_sub, off_sbsum, off_part, off_self, off_kress, total;
 };
 
 struct PairArgs {
     const void *rec;
     const double *sbsum;      // FP32 SLP: per-superblock sum of g (2 doubles each)
+    const SubInfo *sub;       // FP32C: per sub-block origin and far radius
     int64_t n_src;
     const double *tx, *ty;
     const int32_t *on_curve, *on_node, *curve_off;
