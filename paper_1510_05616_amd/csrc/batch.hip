@@ -142,6 +142,8 @@ __global__ __launch_bounds__(256) void batch_kress_self(BatchTables t) {
 
 template <int PREC, int TPT>
 __global__ __launch_bounds__(kBlock) void batch_pair(BatchTables t) {
+    __shared__ double ltab[3 * kLogTab];
+    if (PREC == S2D_FP64) fill_log_table(ltab);
     const int lane = threadIdx.x & (kWave - 1);
     for (;;) {
         int it = 0;
@@ -151,9 +153,9 @@ __global__ __launch_bounds__(kBlock) void batch_pair(BatchTables t) {
         const BatchItem w = t.items[item];
         const PairArgs a = t.inst[w.inst].pa[w.op];
         if (w.op == 0)
-            pair_tile<S2D_OP_SLP, PREC, TPT>(a, w.tile, w.split, lane);
+            pair_tile<S2D_OP_SLP, PREC, TPT>(a, w.tile, w.split, lane, ltab);
         else
-            pair_tile<S2D_OP_DLP, PREC, TPT>(a, w.tile, w.split, lane);
+            pair_tile<S2D_OP_DLP, PREC, TPT>(a, w.tile, w.split, lane, ltab);
     }
 }
 

@@ -6,13 +6,15 @@ namespace s2d {
 
 template <int OP, int PREC, int TPT>
 __global__ __launch_bounds__(kBlock) void pair_kernel(PairArgs a) {
+    __shared__ double ltab[3 * kLogTab];
+    if (PREC == S2D_FP64 && OP == S2D_OP_SLP) fill_log_table(ltab);   // before any wave returns
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;
     const int64_t blk = blockIdx.x;
     const int split = (int)(blk % a.n_splits);
     const int64_t tile = (blk / a.n_splits) * kWavesPerBlock + wid;
     if (tile >= a.n_tiles) return;                  // wave-uniform
-    pair_tile<OP, PREC, TPT>(a, tile, split, lane);
+    pair_tile<OP, PREC, TPT>(a, tile, split, lane, ltab);
 }
 
 template <int OP, int PREC, int TPT>

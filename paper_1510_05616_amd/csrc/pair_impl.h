@@ -25,7 +25,9 @@
 //
 // Precision.  FP64 mode evaluates each term in double.  FP32C mode evaluates
 // each term in float with the hardware log2 and reciprocal, sums a sub-block
-// of kSubBlock sources in float and merges it into double accumulators.  The
+// of kSubBlock sources in float (single-layer log and rational parts and odd
+// and even sources in separate accumulators, halving the length of each
+// float sum) and merges it into double accumulators.  The
 // difference r is formed, per sub-block and wave, either from FP32 offsets to
 // the sub-block's FP64 origin (when every target of the wave is at least
 // kFarRadii sub-block radii away, so r keeps a relative error of a few
@@ -40,11 +42,11 @@
 
 namespace s2d {
 
+// 1/q: the hardware seed (measured relative error below 5e-8) and one
+// Newton step, relative error about 2e-15.
 __device__ __forceinline__ double rcp64(double q) {
-    double y = __builtin_amdgcn_rcp(q);          // ~2^-26 relative
+    double y = __builtin_amdgcn_rcp(q);
     double e = __builtin_fma(-q, y, 1.0);
-    y = __builtin_fma(y, e, y);
-    e = __builtin_fma(-q, y, 1.0);
     return __builtin_fma(y, e, y);
 }
 
@@ -83,6 +85,43 @@ __device__ __forceinline__ double log64(double x) {
     return __builtin_fma(de, kLn2Hi, __builtin_fma(de, kLn2Lo, lm));
 }
 
+// Table-driven natural log (Tang's method) of a positive, finite, normal
+// double: x = 2^e m, m in [1/2, 1); the top 8 mantissa bits pick the
+// breakpoint F_k = 1/2 + (k + 1/2) / 512, f = m - F_k is exact, and
+// log m = log F_k + log1p(u), u = f / F_k, |u| <= 2^-9, with log1p summed to
+// u^6 (first omitted term below 1e-20).  tab holds F_k, 1/F_k, log F_k
+// (3 x kLogTab doubles, staged in LDS by fill_log_table).
+constexpr int kLogTab = 256;
+
+__device__ __forceinline__ double log64_tab(double x, const double *tab) {
+    const int e = __builtin_amdgcn_frexp_exp(x);
+    const double m = __builtin_amdgcn_frexp_mant(x);
+    const uint32_t hi = (uint32_t)(__builtin_bit_cast(uint64_t, x) >> 32);
+    const int k = (hi >> 12) & (kLogTab - 1);
+    const double u = (m - tab[k]) * tab[kLogTab + k];
+    double p = -1.0 / 6.0;
+    p = __builtin_fma(p, u, 1.0 / 5.0);
+    p = __builtin_fma(p, u, -1.0 / 4.0);
+    p = __builtin_fma(p, u, 1.0 / 3.0);
+    p = __builtin_fma(p, u, -1.0 / 2.0);
+    const double l1p = __builtin_fma(p * u, u, u);
+    const double de = (double)e;
+    constexpr double kLn2Hi = 6.93147180369123816490e-01;
+    constexpr double kLn2Lo = 1.90821492927058770002e-10;
+    return __builtin_fma(de, kLn2Hi, tab[2 * kLogTab + k] + __builtin_fma(de, kLn2Lo, l1p));
+}
+
+// Called by every thread of a workgroup before any of them uses the table.
+__device__ __forceinline__ void fill_log_table(double *tab) {
+    for (int k = threadIdx.x; k < kLogTab; k += blockDim.x) {
+        const double F = 0.5 + ((double)k + 0.5) / (2.0 * kLogTab);
+        tab[k] = F;
+        tab[kLogTab + k] = 1.0 / F;
+        tab[2 * kLogTab + k] = log64(F);
+    }
+    __syncthreads();
+}
+
 __device__ __forceinline__ int wave_min(int v) {
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) v = min(v, __shfl_xor(v, m, kWave));
@@ -99,11 +138,11 @@ __device__ __forceinline__ int wave_max(int v) {
 // per-pair terms
 // ---------------------------------------------------------------------------
 // FP64 single layer: accumulates A += g log q and B += r (r.g)/q.
-__device__ __forceinline__ void slp64_pair(double px, double py, const RecSlp64 &s,
+__device__ __forceinline__ void slp64_pair(double px, double py, const RecSlp64 &s, const double *ltab,
                                            double &ax, double &ay, double &bx, double &by) {
     double rx = px - s.x, ry = py - s.y;
     double q = __builtin_fma(rx, rx, ry * ry);
-    double lq = log64(q);
+    double lq = log64_tab(q, ltab);
     double iq = rcp64(q);
     double t = __builtin_fma(rx, s.gx, ry * s.gy) * iq;
     ax = __builtin_fma(s.gx, lq, ax);
@@ -112,23 +151,23 @@ __device__ __forceinline__ void slp64_pair(double px, double py, const RecSlp64 
     by = __builtin_fma(ry, t, by);
 }
 
-// FP32 single layer term for the difference r = (rx, ry), added to (sx, sy);
-// iqr scales q before the log.
-__device__ __forceinline__ void slp32_r(float rx, float ry, const RecSlp32 &s, float iqr, float &sx, float &sy) {
+// FP32 single layer term for the difference r = (rx, ry); the log and the
+// rational parts go to separate accumulators a = {log x, log y, rat x, rat y}
+// (iqr scales q before the log).
+__device__ __forceinline__ void slp32_r(float rx, float ry, const RecSlp32 &s, float iqr, float (&a)[4]) {
     float q = __builtin_fmaf(rx, rx, ry * ry);
     float lq = __builtin_amdgcn_logf(q * iqr);      // log2
     float iq = __builtin_amdgcn_rcpf(q);
     float t = __builtin_fmaf(rx, s.gx, ry * s.gy) * iq;
-    sx = __builtin_fmaf(s.lx, lq, sx);
-    sx = __builtin_fmaf(rx, t, sx);
-    sy = __builtin_fmaf(s.ly, lq, sy);
-    sy = __builtin_fmaf(ry, t, sy);
+    a[0] = __builtin_fmaf(s.lx, lq, a[0]);
+    a[1] = __builtin_fmaf(s.ly, lq, a[1]);
+    a[2] = __builtin_fmaf(rx, t, a[2]);
+    a[3] = __builtin_fmaf(ry, t, a[3]);
 }
 
 // exact path: the difference formed in FP64 and rounded once
-__device__ __forceinline__ void slp32_acc(double px, double py, const RecSlp32 &s, float iqr,
-                                          float &sx, float &sy) {
-    slp32_r((float)(px - s.x), (float)(py - s.y), s, iqr, sx, sy);
+__device__ __forceinline__ void slp32_acc(double px, double py, const RecSlp32 &s, float iqr, float (&a)[4]) {
+    slp32_r((float)(px - s.x), (float)(py - s.y), s, iqr, a);
 }
 
 __device__ __forceinline__ void dlp64_pair(double px, double py, const RecDlp64 &s,
@@ -143,18 +182,19 @@ __device__ __forceinline__ void dlp64_pair(double px, double py, const RecDlp64 
     uy = __builtin_fma(ry, f, uy);
 }
 
-__device__ __forceinline__ void dlp32_r(float rx, float ry, const RecDlp32 &s, float &sx, float &sy) {
+// FP32 double layer term, accumulators a = {x, y}
+__device__ __forceinline__ void dlp32_r(float rx, float ry, const RecDlp32 &s, float (&a)[2]) {
     float q = __builtin_fmaf(rx, rx, ry * ry);
     float iq = __builtin_amdgcn_rcpf(q);
     float rn = __builtin_fmaf(rx, s.nx, ry * s.ny);
     float rt = __builtin_fmaf(rx, s.tx, ry * s.ty);
     float f = (rn * rt) * (iq * iq);
-    sx = __builtin_fmaf(rx, f, sx);
-    sy = __builtin_fmaf(ry, f, sy);
+    a[0] = __builtin_fmaf(rx, f, a[0]);
+    a[1] = __builtin_fmaf(ry, f, a[1]);
 }
 
-__device__ __forceinline__ void dlp32_acc(double px, double py, const RecDlp32 &s, float &sx, float &sy) {
-    dlp32_r((float)(px - s.x), (float)(py - s.y), s, sx, sy);
+__device__ __forceinline__ void dlp32_acc(double px, double py, const RecDlp32 &s, float (&a)[2]) {
+    dlp32_r((float)(px - s.x), (float)(py - s.y), s, a);
 }
 
 // Offsets of the targets from sub-block origin si in FP32, and whether every
@@ -180,7 +220,7 @@ __device__ __forceinline__ bool far_offsets(const SubInfo &si, const double (&px
 // One wave: targets [tile * kWave * TPT, +kWave * TPT) against source split
 // `split`, all images; writes the FP64 partials of that split.
 template <int OP, int PREC, int TPT>
-__device__ __forceinline__ void pair_tile(const PairArgs &a, int64_t tile, int split, int lane) {
+__device__ __forceinline__ void pair_tile(const PairArgs &a, int64_t tile, int split, int lane, const double *ltab) {
 
     double tx[TPT], ty[TPT];
     int lo[TPT], hi[TPT];
@@ -239,7 +279,7 @@ __device__ __forceinline__ void pair_tile(const PairArgs &a, int64_t tile, int s
                             for (int q = 0; q < 4; ++q) {
                                 const RecSlp64 s = rec[u + q];
 #pragma unroll
-                                for (int k = 0; k < TPT; ++k) slp64_pair(px[k], py[k], s, vx[k], vy[k], ux[k], uy[k]);
+                                for (int k = 0; k < TPT; ++k) slp64_pair(px[k], py[k], s, ltab, vx[k], vy[k], ux[k], uy[k]);
                             }
                         }
                     } else {
@@ -270,51 +310,62 @@ __device__ __forceinline__ void pair_tile(const PairArgs &a, int64_t tile, int s
                             uy[k] = __builtin_fma(c, gsy, uy[k]);
                         }
                         for (int u = 0; u < kSuperBlock; u += kSubBlock) {
-                            float sx[TPT], sy[TPT], dx[TPT], dy[TPT];
+                            // per target: [source parity][log x, log y, rat x, rat y]
+                            float ac[TPT][2][4], dx[TPT], dy[TPT];
 #pragma unroll
-                            for (int k = 0; k < TPT; ++k) { sx[k] = 0.f; sy[k] = 0.f; }
+                            for (int k = 0; k < TPT; ++k)
+#pragma unroll
+                                for (int e = 0; e < 8; ++e) ac[k][e / 4][e % 4] = 0.f;
                             if (far_offsets<TPT>(a.sub[(j0 + u) / kSubBlock], px, py, act, dx, dy)) {
 #pragma unroll
                                 for (int q = 0; q < kSubBlock; ++q) {
                                     const RecSlp32 s = rec[u + q];
 #pragma unroll
                                     for (int k = 0; k < TPT; ++k)
-                                        slp32_r(dx[k] - s.xl, dy[k] - s.yl, s, iqr[k], sx[k], sy[k]);
+                                        slp32_r(dx[k] - s.xl, dy[k] - s.yl, s, iqr[k], ac[k][q & 1]);
                                 }
                             } else {
 #pragma unroll
                                 for (int q = 0; q < kSubBlock; ++q) {
                                     const RecSlp32 s = rec[u + q];
 #pragma unroll
-                                    for (int k = 0; k < TPT; ++k) slp32_acc(px[k], py[k], s, iqr[k], sx[k], sy[k]);
+                                    for (int k = 0; k < TPT; ++k) slp32_acc(px[k], py[k], s, iqr[k], ac[k][q & 1]);
                                 }
                             }
 #pragma unroll
-                            for (int k = 0; k < TPT; ++k) { ux[k] += (double)sx[k]; uy[k] += (double)sy[k]; }
+                            for (int k = 0; k < TPT; ++k) {
+                                ux[k] += (double)((ac[k][0][0] + ac[k][1][0]) + (ac[k][0][2] + ac[k][1][2]));
+                                uy[k] += (double)((ac[k][0][1] + ac[k][1][1]) + (ac[k][0][3] + ac[k][1][3]));
+                            }
                         }
                     } else {
                         const RecDlp32 *rec = (const RecDlp32 *)a.rec + j0;
                         for (int u = 0; u < kSuperBlock; u += kSubBlock) {
-                            float sx[TPT], sy[TPT], dx[TPT], dy[TPT];
+                            float ac[TPT][2][2], dx[TPT], dy[TPT];     // [source parity][x, y]
 #pragma unroll
-                            for (int k = 0; k < TPT; ++k) { sx[k] = 0.f; sy[k] = 0.f; }
+                            for (int k = 0; k < TPT; ++k)
+#pragma unroll
+                                for (int e = 0; e < 4; ++e) ac[k][e / 2][e % 2] = 0.f;
                             if (far_offsets<TPT>(a.sub[(j0 + u) / kSubBlock], px, py, act, dx, dy)) {
 #pragma unroll
                                 for (int q = 0; q < kSubBlock; ++q) {
                                     const RecDlp32 s = rec[u + q];
 #pragma unroll
-                                    for (int k = 0; k < TPT; ++k) dlp32_r(dx[k] - s.xl, dy[k] - s.yl, s, sx[k], sy[k]);
+                                    for (int k = 0; k < TPT; ++k) dlp32_r(dx[k] - s.xl, dy[k] - s.yl, s, ac[k][q & 1]);
                                 }
                             } else {
 #pragma unroll
                                 for (int q = 0; q < kSubBlock; ++q) {
                                     const RecDlp32 s = rec[u + q];
 #pragma unroll
-                                    for (int k = 0; k < TPT; ++k) dlp32_acc(px[k], py[k], s, sx[k], sy[k]);
+                                    for (int k = 0; k < TPT; ++k) dlp32_acc(px[k], py[k], s, ac[k][q & 1]);
                                 }
                             }
 #pragma unroll
-                            for (int k = 0; k < TPT; ++k) { ux[k] += (double)sx[k]; uy[k] += (double)sy[k]; }
+                            for (int k = 0; k < TPT; ++k) {
+                                ux[k] += (double)(ac[k][0][0] + ac[k][1][0]);
+                                uy[k] += (double)(ac[k][0][1] + ac[k][1][1]);
+                            }
                         }
                     }
                 }
@@ -329,7 +380,7 @@ __device__ __forceinline__ void pair_tile(const PairArgs &a, int64_t tile, int s
                             if (OP == S2D_OP_SLP) {
                                 const RecSlp64 s = ((const RecSlp64 *)a.rec)[j];
                                 double ax = 0, ay = 0, bx = 0, by = 0;
-                                slp64_pair(px[k], py[k], s, ax, ay, bx, by);
+                                slp64_pair(px[k], py[k], s, ltab, ax, ay, bx, by);
                                 vx[k] += ok ? ax : 0.0; vy[k] += ok ? ay : 0.0;
                                 ux[k] += ok ? bx : 0.0; uy[k] += ok ? by : 0.0;
                             } else {
@@ -342,10 +393,16 @@ __device__ __forceinline__ void pair_tile(const PairArgs &a, int64_t tile, int s
                             float t0 = 0.f, t1 = 0.f;
                             if (OP == S2D_OP_SLP) {
                                 const RecSlp32 s = ((const RecSlp32 *)a.rec)[j];
-                                slp32_acc(px[k], py[k], s, 1.0f, t0, t1);
+                                float t4[4] = {0.f, 0.f, 0.f, 0.f};
+                                slp32_acc(px[k], py[k], s, 1.0f, t4);
+                                t0 = t4[0] + t4[2];
+                                t1 = t4[1] + t4[3];
                             } else {
                                 const RecDlp32 s = ((const RecDlp32 *)a.rec)[j];
-                                dlp32_acc(px[k], py[k], s, t0, t1);
+                                float t2[2] = {0.f, 0.f};
+                                dlp32_acc(px[k], py[k], s, t2);
+                                t0 = t2[0];
+                                t1 = t2[1];
                             }
                             ux[k] += ok ? (double)t0 : 0.0;
                             uy[k] += ok ? (double)t1 : 0.0;
