@@ -142,6 +142,52 @@ def _time(fn, reps=3):
     return a.elapsed_time(b) / reps
 
 
+def batch_section():
+    """Config 4: 256 independent channel instances (1-40 vesicles of
+    32-256 nodes, 256-4096 wall nodes per wall) evaluated by one batched call
+    (persistent work-list kernel recorded in a HIP graph, tile shape from the
+    autotuner), FP32C, against the same instances as sequential single calls."""
+    import torch
+    import synth
+    import paper_1510_05616_amd as s2d
+    t0 = time.time()
+    probs = synth.make_batch(256)
+    log(f"batch: 256 instances generated ({time.time() - t0:.1f}s)")
+    mode = s2d.S2D_FP32C
+    insts = []
+    for p in probs:
+        t = p.trg
+        u = torch.zeros(t.n, dtype=torch.float64, device="cuda")
+        insts.append(s2d.BatchInstance(s2d.Curves(p.ves), s2d.Curves(p.wall),
+                                       s2d.Targets(t.x, t.y, t.ves_curve, t.ves_node),
+                                       s2d.Targets(t.x, t.y, t.wall_curve, t.wall_node), p.d, p.mu, u,
+                                       torch.zeros_like(u)))
+    pairs = sum(p.trg.n * (p.ves.n_nodes + p.wall.n_nodes) * 3 for p in probs)
+    ws = torch.empty(s2d.stokes2d_batch_workspace_size(mode, insts), dtype=torch.uint8, device="cuda")
+    t0 = time.time()
+    s2d.stokes2d_batch_eval(mode, insts, ws)          # plans, tunes, records the graph
+    torch.cuda.synchronize()
+    t_first = time.time() - t0
+    ms_batch = _time(lambda: s2d.stokes2d_batch_eval(mode, insts, ws), reps=5)
+    wss = torch.empty(max(max(s2d.stokes2d_workspace_size(0, mode, b.ves, b.trg_ves),
+                              s2d.stokes2d_workspace_size(1, mode, b.wall, b.trg_wall)) for b in insts),
+                      dtype=torch.uint8, device="cuda")
+
+    def singles():
+        for b in insts:
+            s2d.stokes2d_slp_eval(mode, b.ves, b.trg_ves, b.d, -1, 1, b.mu, b.u, b.v, 0, wss)
+            s2d.stokes2d_dlp_eval(mode, b.wall, b.trg_wall, b.d, -1, 1, b.u, b.v, 1, wss)
+    ms_single = _time(singles, reps=3)
+    s2d.stokes2d_batch_release()
+    res = {"workload": "256 instances, 1-40 vesicles x {32,64,128,256} nodes, 256-4096 nodes per wall, "
+                       "images -1..1, FP32C", "pairs": pairs, "ms": ms_batch,
+           "value": pairs / (ms_batch * 1e-3), "unit": "pair-evals/s", "first_call_s": t_first,
+           "sequential_single_calls_ms": ms_single, "speedup_vs_single_calls": ms_single / ms_batch}
+    log(f"batch: {ms_batch:.2f} ms per batched call ({pairs / (ms_batch * 1e-3):.3e} pairs/s), "
+        f"{ms_single:.2f} ms as 512 single calls, first call {t_first:.1f}s")
+    return res
+
+
 def near_section():
     """Learned near-field correction on the near-target workload: train on
     200k targets, calibrate on 20k, test on 1M (targets at log-uniform
@@ -218,6 +264,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=8192,
                     help="targets of the workload the FP64 oracle evaluates on the host (0: skip)")
     ap.add_argument("--near", type=int, default=1, help="run the near-field correction section (0: skip)")
+    ap.add_argument("--batch", type=int, default=1, help="run the batched-instances section (0: skip)")
     ap.add_argument("--copy-probe", action="store_true", help="only copy 1 GiB on the device and exit")
     args = ap.parse_args()
     if args.copy_probe:
@@ -284,6 +331,7 @@ def main():
             f"rel err f32={errs['f32']:.2e} f64={errs['f64']:.2e}")
 
     near_res = near_section() if args.near else None
+    batch_res = batch_section() if args.batch else None
 
     f32, f64 = res["f32"], res["f64"]
     line = {
@@ -303,6 +351,7 @@ def main():
         "kernel_ms": {"f32_slp_pair": f32["slp_pair_ms"], "f32_dlp_pair": f32["dlp_pair_ms"],
                       "f64_slp_pair": f64["slp_pair_ms"], "f64_dlp_pair": f64["dlp_pair_ms"]},
         "near": near_res,
+        "batch": batch_res,
     }
     print(json.dumps(line), flush=True)
 

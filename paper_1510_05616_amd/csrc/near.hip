@@ -104,10 +104,10 @@ __global__ __launch_bounds__(256) void near_upsample(const int32_t *__restrict__
 }
 
 __device__ __forceinline__ void slp64_acc(double px, double py, double sx, double sy, double gx, double gy,
-                                          double &ax, double &ay, double &bx, double &by) {
+                                          const double *ltab, double &ax, double &ay, double &bx, double &by) {
     const double rx = px - sx, ry = py - sy;
     const double q = __builtin_fma(rx, rx, ry * ry);
-    const double lq = log64(q);
+    const double lq = log64_tab(q, ltab);
     const double t = __builtin_fma(rx, gx, ry * gy) * rcp64(q);
     ax = __builtin_fma(gx, lq, ax);
     ay = __builtin_fma(gy, lq, ay);
@@ -115,7 +115,30 @@ __device__ __forceinline__ void slp64_acc(double px, double py, double sx, doubl
     by = __builtin_fma(ry, t, by);
 }
 
+// coarse (N nodes) and fine (P N nodes) single-layer sums of one curve
+template <bool UNIFORM>
+__device__ __forceinline__ void near_sums(double px, double py, int lo, int N, int P, int64_t plane,
+                                          const double *__restrict__ x, const double *__restrict__ y,
+                                          const double *__restrict__ w, const double *__restrict__ fx,
+                                          const double *__restrict__ fy, const double *__restrict__ up,
+                                          const double *ltab, double (&s)[8]) {
+    if (UNIFORM) {
+        lo = __builtin_amdgcn_readfirstlane(lo);
+        N = __builtin_amdgcn_readfirstlane(N);
+    }
+    for (int k = lo; k < lo + N; ++k)
+        slp64_acc(px, py, x[k], y[k], w[k] * fx[k], w[k] * fy[k], ltab, s[0], s[1], s[2], s[3]);
+    const int64_t base = (int64_t)lo * P;
+    for (int64_t k = base; k < base + (int64_t)N * P; ++k) {
+        const double ww = up[2 * plane + k];
+        slp64_acc(px, py, up[k], up[plane + k], ww * up[3 * plane + k], ww * up[4 * plane + k], ltab, s[4], s[5],
+                  s[6], s[7]);
+    }
+}
+
 // Delta for target i (or list[i] when list != NULL, up to *count entries).
+// When every target of a wave lies on the same curve the source loops are
+// wave-uniform and their loads go through the scalar path.
 __global__ __launch_bounds__(256) void near_quad(int64_t n_trg, const int32_t *__restrict__ list,
                                                  const int32_t *__restrict__ count, const double *__restrict__ tx,
                                                  const double *__restrict__ ty, const int32_t *__restrict__ tc,
@@ -126,34 +149,43 @@ __global__ __launch_bounds__(256) void near_quad(int64_t n_trg, const int32_t *_
                                                  double pref, double *__restrict__ du, double *__restrict__ dv,
                                                  double *__restrict__ uf, double *__restrict__ vf,
                                                  double *__restrict__ uc, double *__restrict__ vc) {
+    __shared__ double ltab[3 * kLogTab];
+    fill_log_table(ltab);
     const int64_t n = list ? (int64_t)*count : n_trg;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = list ? list[q] : q;
-        const int c = tc[i];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // every wave runs the same number of iterations (n rounded up), so the
+    // wave-level vote below sees all 64 lanes
+    const int64_t nround = (n + stride - 1) / stride * stride;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nround; q += stride) {
+        const bool live = q < n;
+        const int64_t i = live ? (list ? list[q] : q) : 0;
+        const int c = live ? tc[i] : -1;
         const int lo = (c >= 0 && c < n_curves) ? off[c] : 0;
         const int N = (c >= 0 && c < n_curves) ? off[c + 1] - lo : 0;
-        if (c < 0 || c >= n_curves || N < 4 || (N & 1) || N > kUpMaxN || P * N > kUpMaxM || lo < 0 ||
-            (int64_t)lo + N > n_src) {
+        const bool ok = c >= 0 && c < n_curves && N >= 4 && !(N & 1) && N <= kUpMaxN && P * N <= kUpMaxM &&
+                        lo >= 0 && (int64_t)lo + N <= n_src;
+        const int c0 = __builtin_amdgcn_readfirstlane(c);
+        const bool uniform = __all(ok && c == c0);
+        double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        const int64_t plane = n_src * (int64_t)P;
+        if (uniform) {
+            near_sums<true>(tx[i], ty[i], lo, N, P, plane, x, y, w, fx, fy, up, ltab, s);
+        } else if (ok) {
+            near_sums<false>(tx[i], ty[i], lo, N, P, plane, x, y, w, fx, fy, up, ltab, s);
+        }
+        if (!live) continue;
+        if (!ok) {
             du[i] = dv[i] = __builtin_nan("");
             if (uf) uf[i] = vf[i] = uc[i] = vc[i] = __builtin_nan("");
             continue;
         }
-        const double px = tx[i], py = ty[i];
-        double a0 = 0, a1 = 0, b0 = 0, b1 = 0, c0 = 0, c1 = 0, d0 = 0, d1 = 0;
-        for (int k = lo; k < lo + N; ++k)
-            slp64_acc(px, py, x[k], y[k], w[k] * fx[k], w[k] * fy[k], a0, a1, b0, b1);
-        const int64_t plane = n_src * (int64_t)P, base = (int64_t)lo * P;
-        for (int64_t k = base; k < base + (int64_t)N * P; ++k) {
-            const double ww = up[2 * plane + k];
-            slp64_acc(px, py, up[k], up[plane + k], ww * up[3 * plane + k], ww * up[4 * plane + k], c0, c1, d0, d1);
-        }
-        du[i] = pref * ((-0.5 * c0 + d0) - (-0.5 * a0 + b0));
-        dv[i] = pref * ((-0.5 * c1 + d1) - (-0.5 * a1 + b1));
+        du[i] = pref * ((-0.5 * s[4] + s[6]) - (-0.5 * s[0] + s[2]));
+        dv[i] = pref * ((-0.5 * s[5] + s[7]) - (-0.5 * s[1] + s[3]));
         if (uf) {
-            uf[i] = pref * (-0.5 * c0 + d0);
-            vf[i] = pref * (-0.5 * c1 + d1);
-            uc[i] = pref * (-0.5 * a0 + b0);
-            vc[i] = pref * (-0.5 * a1 + b1);
+            uf[i] = pref * (-0.5 * s[4] + s[6]);
+            vf[i] = pref * (-0.5 * s[5] + s[7]);
+            uc[i] = pref * (-0.5 * s[0] + s[2]);
+            vc[i] = pref * (-0.5 * s[1] + s[3]);
         }
     }
 }
@@ -288,7 +320,11 @@ __device__ __forceinline__ void bf16_layer(const uint32_t *__restrict__ W, const
     }
 }
 
-// MLP inference with fallback decision.  blob: the packed BF16 network.
+// MLP inference with the fallback decision taken first (from the target's
+// bin of |normal offset| / h and the calibrated bounds, scaled into velocity
+// units by h F / (4 pi mu)): no correction, the network, or the upsampled
+// quadrature (the target joins the fallback list).  blob: the packed BF16
+// network.
 __global__ __launch_bounds__(256) void near_mlp_infer(int64_t n_trg, const float *__restrict__ X,
                                                       const double *__restrict__ frame, const NearBlob *__restrict__ nb,
                                                       double mu, double threshold, int use_bound,
@@ -298,25 +334,8 @@ __global__ __launch_bounds__(256) void near_mlp_infer(int64_t n_trg, const float
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_trg) return;
     const float *xi = X + i * kNearFeat;
-    uint32_t h0[kNearFeat / 2];
-#pragma unroll
-    for (int k = 0; k < kNearFeat; k += 2)
-        h0[k / 2] = pack_bf16((xi[k] - nb->mu_in[k]) * nb->isd_in[k], (xi[k + 1] - nb->mu_in[k + 1]) * nb->isd_in[k + 1]);
-    uint32_t h1[32], h2[32], h3[32];
-    bf16_layer<kNearFeat / 2, 64, true>(nb->W1, nb->b1, h0, h1);
-    bf16_layer<32, 64, true>(nb->W2, nb->b2, h1, h2);
-    bf16_layer<32, 64, true>(nb->W3, nb->b3, h2, h3);
-    float y0 = nb->b4[0], y1 = nb->b4[1];
-#pragma unroll
-    for (int k = 0; k < 32; ++k) {
-        y0 = dot2_bf16(nb->W4[k], h3[k], y0);
-        y1 = dot2_bf16(nb->W4[32 + k], h3[k], y1);
-    }
     const double *fr = frame + 6 * i;
     const double sc = fr[4] * fr[5] / (4.0 * M_PI * mu);
-    // decision from the calibrated bounds of the target's bin: no correction
-    // when the plain rule is already within the threshold, the network when
-    // its bound is, the upsampled quadrature otherwise
     if (use_bound) {
         const float noff = fabsf(xi[1]);
         int bin = (int)floorf((log10f(fmaxf(noff, 1e-30f)) - nb->bin_lo) / nb->bin_w);
@@ -334,6 +353,20 @@ __global__ __launch_bounds__(256) void near_mlp_infer(int64_t n_trg, const float
             list[slot] = (int32_t)i;
             return;                    // the quadrature kernel writes du, dv
         }
+    }
+    uint32_t h0[kNearFeat / 2];
+#pragma unroll
+    for (int k = 0; k < kNearFeat; k += 2)
+        h0[k / 2] = pack_bf16((xi[k] - nb->mu_in[k]) * nb->isd_in[k], (xi[k + 1] - nb->mu_in[k + 1]) * nb->isd_in[k + 1]);
+    uint32_t h1[32], h2[32], h3[32];
+    bf16_layer<kNearFeat / 2, 64, true>(nb->W1, nb->b1, h0, h1);
+    bf16_layer<32, 64, true>(nb->W2, nb->b2, h1, h2);
+    bf16_layer<32, 64, true>(nb->W3, nb->b3, h2, h3);
+    float y0 = nb->b4[0], y1 = nb->b4[1];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+        y0 = dot2_bf16(nb->W4[k], h3[k], y0);
+        y1 = dot2_bf16(nb->W4[32 + k], h3[k], y1);
     }
     if (flag) flag[i] = 0;
     du[i] = sc * ((double)y0 * fr[0] + (double)y1 * fr[2]);

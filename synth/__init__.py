@@ -191,15 +191,15 @@ def concat_curves(parts) -> CurveSet:
 # ----------------------------------------------------------------------------
 def _place_vesicles(rng, n_ves, nus, area, h, d, gap, max_tries=20000):
     """Centres, axes and rotations of n_ves ellipses inside the channel
-    |y| < h(x), pairwise gap >= gap (periodic in x with period d) and gap >=
-    gap to both walls, checked on finely resolved outlines."""
+    |y| < h(x), pairwise gap >= gap (periodic in x with period d, checked on
+    finely resolved outlines) and gap >= gap to both walls (checked with the
+    wall's largest slope)."""
     from scipy.spatial import cKDTree
-    xw = np.linspace(0.0, d, max(4096, int(d / 0.004)), endpoint=False)
-    hw = h(xw)
-    wall_pts = np.concatenate([np.stack([xw, hw], 1), np.stack([xw, -hw], 1)])
-    wall_pts = np.concatenate([wall_pts + [dx, 0.0] for dx in (-d, 0.0, d)])
-    wall_tree = cKDTree(wall_pts)
-    hmin = float(hw.min())
+    # a point with |y| <= h(x) - gap * sqrt(1 + max h'^2) is at least `gap`
+    # from both walls (the wall is a graph whose slope never exceeds max |h'|)
+    xs = np.linspace(0.0, 2.0 * d, 20000)
+    wall_margin = gap * math.sqrt(1.0 + float(np.max(np.abs(
+        np.gradient(h(xs), xs)))) ** 2)
     placed = []          # (cx, cy, a, outline points)
     grid = {}
     cell = 1.0
@@ -214,18 +214,17 @@ def _place_vesicles(rng, n_ves, nus, area, h, d, gap, max_tries=20000):
             phi = rng.uniform(0.0, np.pi)
             ex, ey, *_ = _ellipse(cx, cy, a, b, phi, nfine)
             pts = np.stack([ex, ey], 1)
-            dw, _ = wall_tree.query(pts)
-            if dw.min() < gap or np.any(np.abs(ey) >= h(ex)):
+            if np.any(np.abs(ey) > h(ex) - wall_margin):
                 continue
             ok = True
             gx = int(math.floor(cx / cell))
             for gxx in range(gx - 2, gx + 3):
                 for j in grid.get(gxx % max(1, int(math.ceil(d / cell))), []):
-                    ox, oy, oa, opts = placed[j]
+                    ox, oy, oa, otree = placed[j]
                     for sh in (-d, 0.0, d):
                         if math.hypot(cx - ox - sh, cy - oy) > a + oa + gap:
                             continue
-                        dd, _ = cKDTree(opts + [sh, 0.0]).query(pts)
+                        dd, _ = otree.query(pts - [sh, 0.0])
                         if dd.min() < gap:
                             ok = False
                             break
@@ -234,7 +233,7 @@ def _place_vesicles(rng, n_ves, nus, area, h, d, gap, max_tries=20000):
                 if not ok:
                     break
             if ok:
-                placed.append((cx, cy, a, pts))
+                placed.append((cx, cy, a, cKDTree(pts)))
                 grid.setdefault(gx % max(1, int(math.ceil(d / cell))), []).append(len(placed) - 1)
                 yield (cx, cy, a, b, phi)
                 break
