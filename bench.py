@@ -238,14 +238,33 @@ def near_section():
     frac_fb = float((fb == 1).double().mean())
     frac_zero = float((fb == 2).double().mean())
     e_plain = float((torch.hypot(d_up, e_up) / scale).max())
-    # 32x upsampled quadrature as context for the 8x judge
-    u32, v32 = torch.empty_like(uP), torch.empty_like(uP)
-    near.near_upsampled_slp(te.curves, te.trg, te.tc, 32, 1.0, u32, v32, u1, v1)
-    e_8v32 = float((torch.hypot(uP - u32, vP - v32) / scale).max())
+    # 32x upsampled quadrature as context for the 8x judge (64-node curves,
+    # the largest that 32x upsampling supports)
+    c64 = synth.make_near_dataset(100000, 8, sizes=(64,))
+    d64 = near.NearData(*c64[:4], mu=1.0, upsample=8, labels=False)
+    a8, b8, a1, b1 = (torch.empty(d64.n, dtype=torch.float64, device=dev) for _ in range(4))
+    a32, b32 = torch.empty_like(a8), torch.empty_like(a8)
+    near.near_upsampled_slp(d64.curves, d64.trg, d64.tc, 8, 1.0, a8, b8, a1, b1)
+    near.near_upsampled_slp(d64.curves, d64.trg, d64.tc, 32, 1.0, a32, b32, a1, b1)
+    t64 = d64.tc.long()
+    s64 = torch.zeros(d64.curves.n_curves, dtype=torch.float64, device=dev).scatter_reduce(
+        0, t64, torch.hypot(a32, b32), reduce="amax", include_self=False)[t64]
+    e_8v32 = float((torch.hypot(a8 - a32, b8 - b32) / s64).max())
+    # what the network gains: median errors per band of normal offset / h
+    run(near.S2D_NEAR_MLP)
+    err_mlp = (torch.hypot(du - d_up, dv - e_up) / scale).cpu().numpy()
+    err_plain = (torch.hypot(d_up, e_up) / scale).cpu().numpy()
+    noff = np.abs(te.X[:, 1].double().cpu().numpy())
+    gain = {}
+    for lo, hi in ((0.05, 0.2), (0.2, 0.5), (0.5, 1.0), (1.0, 2.0), (2.0, 5.1)):
+        m = (noff >= lo) & (noff < hi)
+        gain[f"{lo}-{hi}h"] = {"plain_median": float(np.median(err_plain[m])),
+                               "mlp_median": float(np.median(err_mlp[m])), "mlp_max": float(err_mlp[m].max())}
     res = {"workload": "1e6 targets at 0.05h..5h from 5000 ellipses of 64/96/128 nodes; MLP 20-64-64-64-2 "
                        "trained on 2e5 8x-upsampled labels, calibrated on 2e4",
            "threshold_abs": thr, "err_vs_upsampled8": {"mlp": e_mlp, "auto": e_auto, "no_correction": e_plain},
-           "err_upsampled8_vs_32": e_8v32, "auto_fraction_fallback": frac_fb, "auto_fraction_no_correction":
+           "err_upsampled8_vs_32_on_64_node_curves": e_8v32, "error_by_offset_band": gain,
+           "auto_fraction_fallback": frac_fb, "auto_fraction_no_correction":
                frac_zero, "ms": {"upsampled8": ms_up, "mlp": ms_mlp, "auto": ms_auto},
            "speedup_vs_upsampled8": {"mlp": ms_up / ms_mlp, "auto": ms_up / ms_auto},
            "train_s": t_train, "epochs": 40, "final_loss": hist[-1]}

@@ -422,23 +422,22 @@ S2D_API int near_correct_eval(int method, const s2d_curves *ves, const s2d_targe
         if (e != hipSuccess) return hip_fail(e, "near upsample launch");
     }
     if (method == S2D_NEAR_UPSAMPLE) {
-        e = s2d::near_launch_quad(ves, trg, trg_curve, nullptr, nullptr, upsample, up, mu, du, dv, st);
+        e = s2d::near_launch_quad(ves, trg, trg_curve, nullptr, upsample, up, mu, du, dv, st);
         if (e != hipSuccess) return hip_fail(e, "near quadrature launch");
         return S2D_OK;
     }
     float *X = (float *)(w + L.X);
     double *frame = (double *)(w + L.frame);
-    int32_t *list = (int32_t *)(w + L.list);
-    int32_t *count = (int32_t *)(w + L.count);
     e = s2d::near_launch_features(ves, trg, trg_curve, X, frame, st);
     if (e != hipSuccess) return hip_fail(e, "near features launch");
     const bool autom = method == S2D_NEAR_AUTO;
-    int32_t *flag = used_fallback;
+    // AUTO needs the per-target decisions: the caller's array or the workspace
+    int32_t *flag = used_fallback ? used_fallback : (autom ? (int32_t *)(w + L.list) : nullptr);
     e = s2d::near_launch_infer(trg->n, X, frame, (const s2d::NearBlob *)mlp, mu, threshold, autom ? 1 : 0, du, dv,
-                               flag, list, count, st);
+                               flag, st);
     if (e != hipSuccess) return hip_fail(e, "near MLP launch");
     if (autom) {
-        e = s2d::near_launch_quad(ves, trg, trg_curve, list, count, upsample, up, mu, du, dv, st);
+        e = s2d::near_launch_quad(ves, trg, trg_curve, flag, upsample, up, mu, du, dv, st);
         if (e != hipSuccess) return hip_fail(e, "near fallback launch");
     }
     return S2D_OK;
@@ -464,8 +463,8 @@ S2D_API int near_upsampled_slp(const s2d_curves *ves, const s2d_targets *trg, co
     double *d = (double *)((char *)ws + L.total);
     hipError_t e = s2d::near_launch_upsample(ves, upsample, up, st);
     if (e != hipSuccess) return hip_fail(e, "near upsample launch");
-    e = s2d::near_launch_quad(ves, trg, trg_curve, nullptr, nullptr, upsample, up, mu, d, d + trg->n, st, u_up, v_up,
-                              u_trap, v_trap);
+    e = s2d::near_launch_quad(ves, trg, trg_curve, nullptr, upsample, up, mu, d, d + trg->n, st, u_up, v_up, u_trap,
+                              v_trap);
     return e == hipSuccess ? S2D_OK : hip_fail(e, "near quadrature launch");
 }
 

@@ -34,6 +34,7 @@
 #include "s2d_near.h"
 
 #include <algorithm>
+#include <climits>
 
 namespace s2d {
 
@@ -136,11 +137,12 @@ __device__ __forceinline__ void near_sums(double px, double py, int lo, int N, i
     }
 }
 
-// Delta for target i (or list[i] when list != NULL, up to *count entries).
-// When every target of a wave lies on the same curve the source loops are
-// wave-uniform and their loads go through the scalar path.
-__global__ __launch_bounds__(256) void near_quad(int64_t n_trg, const int32_t *__restrict__ list,
-                                                 const int32_t *__restrict__ count, const double *__restrict__ tx,
+// Delta for every target i (only those with mask[i] == 1 when mask != NULL;
+// targets stay in their order, so the waves of curve-sorted targets remain
+// on one curve).  When every live target of a wave lies on the same curve the
+// source loops are wave-uniform and their loads go through the scalar path.
+__global__ __launch_bounds__(256) void near_quad(int64_t n_trg, const int32_t *__restrict__ mask,
+                                                 const double *__restrict__ tx,
                                                  const double *__restrict__ ty, const int32_t *__restrict__ tc,
                                                  const int32_t *__restrict__ off, int32_t n_curves, int64_t n_src,
                                                  const double *__restrict__ x, const double *__restrict__ y,
@@ -151,25 +153,32 @@ __global__ __launch_bounds__(256) void near_quad(int64_t n_trg, const int32_t *_
                                                  double *__restrict__ uc, double *__restrict__ vc) {
     __shared__ double ltab[3 * kLogTab];
     fill_log_table(ltab);
-    const int64_t n = list ? (int64_t)*count : n_trg;
+    const int64_t n = n_trg;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     // every wave runs the same number of iterations (n rounded up), so the
     // wave-level vote below sees all 64 lanes
     const int64_t nround = (n + stride - 1) / stride * stride;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nround; q += stride) {
-        const bool live = q < n;
-        const int64_t i = live ? (list ? list[q] : q) : 0;
+        const bool live = q < n && (!mask || mask[q] == 1);
+        const int64_t i = live ? q : 0;
         const int c = live ? tc[i] : -1;
         const int lo = (c >= 0 && c < n_curves) ? off[c] : 0;
         const int N = (c >= 0 && c < n_curves) ? off[c + 1] - lo : 0;
         const bool ok = c >= 0 && c < n_curves && N >= 4 && !(N & 1) && N <= kUpMaxN && P * N <= kUpMaxM &&
                         lo >= 0 && (int64_t)lo + N <= n_src;
-        const int c0 = __builtin_amdgcn_readfirstlane(c);
-        const bool uniform = __all(ok && c == c0);
+        // a wave is uniform when all its live lanes share one valid curve
+        const int cl = ok ? c : INT_MAX;
+        const int cmin = wave_min(cl);
+        const bool any_ok = cmin != INT_MAX;
+        const bool uniform = any_ok && __all(!live || (ok && c == cmin));
         double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         const int64_t plane = n_src * (int64_t)P;
         if (uniform) {
-            near_sums<true>(tx[i], ty[i], lo, N, P, plane, x, y, w, fx, fy, up, ltab, s);
+            // idle lanes follow the wave's curve (their results are dropped)
+            const int cu = __builtin_amdgcn_readfirstlane(cmin);
+            const int lou = off[cu], Nu = off[cu + 1] - lou;
+            near_sums<true>(live ? tx[i] : tx[0], live ? ty[i] : ty[0], lou, Nu, P, plane, x, y, w, fx, fy, up, ltab,
+                            s);
         } else if (ok) {
             near_sums<false>(tx[i], ty[i], lo, N, P, plane, x, y, w, fx, fy, up, ltab, s);
         }
@@ -329,8 +338,7 @@ __global__ __launch_bounds__(256) void near_mlp_infer(int64_t n_trg, const float
                                                       const double *__restrict__ frame, const NearBlob *__restrict__ nb,
                                                       double mu, double threshold, int use_bound,
                                                       double *__restrict__ du, double *__restrict__ dv,
-                                                      int32_t *__restrict__ flag, int32_t *__restrict__ list,
-                                                      int32_t *__restrict__ count) {
+                                                      int32_t *__restrict__ flag) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_trg) return;
     const float *xi = X + i * kNearFeat;
@@ -348,10 +356,8 @@ __global__ __launch_bounds__(256) void near_mlp_infer(int64_t n_trg, const float
             return;
         }
         if (bad || (double)nb->bound[bin] * sc > threshold) {
-            if (flag) flag[i] = 1;
-            const int slot = atomicAdd(count, 1);
-            list[slot] = (int32_t)i;
-            return;                    // the quadrature kernel writes du, dv
+            flag[i] = 1;               // the quadrature kernel writes du, dv
+            return;
         }
     }
     uint32_t h0[kNearFeat / 2];
@@ -371,10 +377,6 @@ __global__ __launch_bounds__(256) void near_mlp_infer(int64_t n_trg, const float
     if (flag) flag[i] = 0;
     du[i] = sc * ((double)y0 * fr[0] + (double)y1 * fr[2]);
     dv[i] = sc * ((double)y0 * fr[1] + (double)y1 * fr[3]);
-}
-
-__global__ void near_zero_count(int32_t *count) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *count = 0;
 }
 
 // Pack FP32 master parameters into the BF16 inference blob.
@@ -583,12 +585,12 @@ hipError_t near_launch_upsample(const s2d_curves *c, int P, double *up, hipStrea
     return hipGetLastError();
 }
 
-hipError_t near_launch_quad(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, const int32_t *list,
-                            const int32_t *count, int P, const double *up, double mu, double *du, double *dv,
-                            hipStream_t st, double *uf, double *vf, double *uc, double *vc) {
+hipError_t near_launch_quad(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, const int32_t *mask,
+                            int P, const double *up, double mu, double *du, double *dv, hipStream_t st, double *uf,
+                            double *vf, double *uc, double *vc) {
     if (t->n <= 0) return hipSuccess;
-    const unsigned g = list ? std::min<unsigned>(grid_for(t->n), 4096u) : grid_for(t->n);
-    hipLaunchKernelGGL(near_quad, dim3(g), dim3(256), 0, st, t->n, list, count, t->x, t->y, tc, c->curve_off,
+    const unsigned g = grid_for(t->n);
+    hipLaunchKernelGGL(near_quad, dim3(g), dim3(256), 0, st, t->n, mask, t->x, t->y, tc, c->curve_off,
                        c->n_curves, c->n_nodes, c->x, c->y, c->w, c->fx, c->fy, P, up, 1.0 / (4.0 * M_PI * mu), du,
                        dv, uf, vf, uc, vc);
     return hipGetLastError();
@@ -610,12 +612,10 @@ hipError_t near_launch_scale_labels(int64_t n, const double *du, const double *d
 }
 
 hipError_t near_launch_infer(int64_t n, const float *X, const double *frame, const NearBlob *nb, double mu,
-                             double threshold, int use_bound, double *du, double *dv, int32_t *flag, int32_t *list,
-                             int32_t *count, hipStream_t st) {
-    hipLaunchKernelGGL(near_zero_count, dim3(1), dim3(64), 0, st, count);
-    if (n <= 0) return hipGetLastError();
+                             double threshold, int use_bound, double *du, double *dv, int32_t *flag, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(near_mlp_infer, dim3(grid_for(n)), dim3(256), 0, st, n, X, frame, nb, mu, threshold,
-                       use_bound, du, dv, flag, list, count);
+                       use_bound, du, dv, flag);
     return hipGetLastError();
 }
 

@@ -34,17 +34,15 @@ struct NearBlob {
 constexpr int kNearBlobWork = kNearFeat + 64 * kNearFeat / 2 + 2 * 64 * 32 + 2 * 32 + 64;
 
 hipError_t near_launch_upsample(const s2d_curves *c, int P, double *up, hipStream_t st);
-hipError_t near_launch_quad(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, const int32_t *list,
-                            const int32_t *count, int P, const double *up, double mu, double *du, double *dv,
-                            hipStream_t st, double *uf = nullptr, double *vf = nullptr, double *uc = nullptr,
-                            double *vc = nullptr);
+hipError_t near_launch_quad(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, const int32_t *mask,
+                            int P, const double *up, double mu, double *du, double *dv, hipStream_t st,
+                            double *uf = nullptr, double *vf = nullptr, double *uc = nullptr, double *vc = nullptr);
 hipError_t near_launch_features(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, float *X,
                                 double *frame, hipStream_t st);
 hipError_t near_launch_scale_labels(int64_t n, const double *du, const double *dv, const double *frame, double mu,
                                     float *Y, hipStream_t st);
 hipError_t near_launch_infer(int64_t n, const float *X, const double *frame, const NearBlob *nb, double mu,
-                             double threshold, int use_bound, double *du, double *dv, int32_t *flag, int32_t *list,
-                             int32_t *count, hipStream_t st);
+                             double threshold, int use_bound, double *du, double *dv, int32_t *flag, hipStream_t st);
 hipError_t near_launch_pack(const float *prm, const float *bound, const float *bound_zero, int32_t n_bins,
                             float bin_lo, float bin_w, NearBlob *nb, hipStream_t st);
 hipError_t near_launch_train_step(int32_t B, const int32_t *idx, const float *X, const float *T, float *prm,

@@ -200,3 +200,29 @@ def test_workspace_errors():
     with pytest.raises(s2d.S2DError) as ei:   # misaligned pointer
         s2d.stokes2d_slp_eval(0, ves, tv, prob.d, -1, 1, 1.0, u, v, ws=big[8:])
     assert ei.value.code == s2d.S2D_EWORKSPACE
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_side_targets_few_targets_many_sources(cfg3, mode):
+    # only the 64 side-wall collocation points of the 128k workload: one target
+    # tile against every source superblock, so the call splits the sources over
+    # hundreds of waves and reduces the partials in a second pass
+    import torch
+    import oracle
+    import paper_1510_05616_amd as s2d
+    t = cfg3.trg
+    side = np.where(t.kind == 2)[0]
+    tx, ty = t.x[side], t.y[side]
+    ves, wall = s2d.Curves(cfg3.ves), s2d.Curves(cfg3.wall)
+    tg = s2d.Targets(tx, ty)
+    for img in ((-1, 1), (1, 1), (-1, -1)):
+        u = torch.zeros(len(side), dtype=torch.float64, device="cuda")
+        v = torch.zeros_like(u)
+        s2d.stokes2d_slp_eval(mode, ves, tg, cfg3.d, img[0], img[1], cfg3.mu, u, v)
+        ou, ov = oracle.slp(cfg3.ves, tx, ty, None, None, cfg3.d, img[0], img[1], cfg3.mu)
+        e1 = rel_err(u.cpu().numpy(), v.cpu().numpy(), ou, ov)
+        s2d.stokes2d_dlp_eval(mode, wall, tg, cfg3.d, img[0], img[1], u, v)
+        ou, ov = oracle.dlp(cfg3.wall, tx, ty, None, None, cfg3.d, img[0], img[1])
+        e2 = rel_err(u.cpu().numpy(), v.cpu().numpy(), ou, ov)
+        print(f"side targets mode={mode} images={img}: slp {e1:.2e} dlp {e2:.2e}", flush=True)
+        assert e1 <= TOL[mode] and e2 <= TOL[mode]
