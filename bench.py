@@ -36,7 +36,7 @@ PEAK = {"f32": 157.3e12, "f64": 78.6e12}
 
 
 PAIR_SOURCES = ("paper_1510_05616_amd/csrc/pair_impl.h", "paper_1510_05616_amd/csrc/pair.hip",
-                "paper_1510_05616_amd/csrc/s2d_internal.h")
+                "paper_1510_05616_amd/csrc/s2d_internal.h", "paper_1510_05616_amd/csrc/api.hip")
 PROFILE = "profiles/pair_kernels_config3.md"
 
 
@@ -316,7 +316,7 @@ def main():
                                    "achieved": ach / 1e12, "peak": PEAK[name] / 1e12,
                                    "unit": "TFLOP/s", "frac": ach / PEAK[name],
                                    "traffic": measured_traffic(
-                                       "pair_kernel<0,1,2>" if name == "f32" else "pair_kernel<0,0,1>"),
+                                       "pair_kernel<0,1,1>" if name == "f32" else "pair_kernel<0,0,1>"),
                                    "flops_per_pair": FLOPS_PER_PAIR, "pairs_per_launch": pairs_slp},
                          u=r["u"], v=r["v"])
         log(f"{name}: {ms_step:.3f} ms/step, {pairs / (ms_step * 1e-3):.4e} pairs/s, "

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -84,18 +85,40 @@ s2d::Plan make_plan(int op, int mode, const s2d_curves *s, const s2d_targets *t,
     Plan p{};
     p.op = op;
     p.mode = mode;
-    p.tpt = mode == S2D_FP64 ? 1 : 2;
+    // One target per lane in both modes; the grid over-decomposes the work
+    // to about 128 waves per SIMD (16x the resident waves of the FP32C
+    // kernel) so that tiles of unequal cost even out.  S2D_TPT (1, 2 or 4)
+    // and S2D_SPLITS override the shape for tuning sweeps.
+    static const int env_tpt = [] {
+        const char *e = std::getenv("S2D_TPT");
+        const int v = e ? std::atoi(e) : 0;
+        return (v == 1 || v == 2 || v == 4) ? v : 0;
+    }();
+    static const int env_splits = [] {
+        const char *e = std::getenv("S2D_SPLITS");
+        return e ? std::max(0, std::atoi(e)) : 0;
+    }();
+    p.tpt = env_tpt ? env_tpt : 1;
+    constexpr int64_t kWavesPerSimd = 128;
     p.n_src = s->n_nodes;
     p.n_trg = t->n;
     p.n_sb = (p.n_src + kSuperBlock - 1) / kSuperBlock;
     p.n_tiles = (p.n_trg + (int64_t)kWave * p.tpt - 1) / ((int64_t)kWave * p.tpt);
     if (p.n_sb > 0 && p.n_tiles > 0) {
-        const int64_t want_waves = (int64_t)cus * 4 * 8;          // ~8 waves per SIMD
-        int64_t ns = (want_waves + p.n_tiles - 1) / p.n_tiles;
-        if (ns >= 8) ns = (ns + 7) / 8 * 8;                        // XCD-aligned split count
-        ns = std::max<int64_t>(1, std::min<int64_t>(ns, std::min<int64_t>(p.n_sb, 4096)));
-        p.sb_per_split = (p.n_sb + ns - 1) / ns;
-        p.n_splits = (int)((p.n_sb + p.sb_per_split - 1) / p.sb_per_split);
+        const int64_t want_waves = (int64_t)cus * 4 * kWavesPerSimd;
+        int64_t ns = env_splits ? env_splits : (want_waves + p.n_tiles - 1) / p.n_tiles;
+        if (ns >= 8 && p.n_sb >= 8) {
+            // XCD-aligned: a multiple of 8 splits keeps every XCD on its own
+            // eighth of the source records; trailing splits may be short or
+            // empty (an empty split writes zero partials)
+            ns = std::min<int64_t>((ns + 7) / 8 * 8, std::min<int64_t>(p.n_sb / 8 * 8, 4096));
+            p.sb_per_split = (p.n_sb + ns - 1) / ns;
+            p.n_splits = (int)ns;
+        } else {
+            ns = std::max<int64_t>(1, std::min<int64_t>(ns, p.n_sb));
+            p.sb_per_split = (p.n_sb + ns - 1) / ns;
+            p.n_splits = (int)((p.n_sb + p.sb_per_split - 1) / p.sb_per_split);
+        }
         p.n_blocks = (int64_t)p.n_splits * ((p.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock);
     } else {
         p.sb_per_split = 0;

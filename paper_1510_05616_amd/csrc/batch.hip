@@ -356,8 +356,8 @@ Layout layout(int32_t n_inst, const s2d_instance *inst, int mode, const TuneChoi
 }
 
 const TuneChoice kCandidates64[] = {{1, 2, 16, 0}, {1, 4, 16, 0}, {1, 8, 16, 0}, {2, 4, 16, 0}, {1, 4, 24, 0}};
-const TuneChoice kCandidates32[] = {{2, 2, 16, 0}, {2, 4, 16, 0}, {2, 8, 16, 0}, {1, 4, 16, 0},
-                                    {4, 4, 16, 0}, {2, 4, 24, 0}};
+const TuneChoice kCandidates32[] = {{2, 2, 16, 0}, {2, 4, 16, 0}, {2, 8, 16, 0}, {1, 2, 16, 0},
+                                    {1, 4, 16, 0}, {1, 8, 16, 0}, {4, 4, 16, 0}, {2, 4, 24, 0}};
 
 void candidates(int mode, std::vector<TuneChoice> &out) {
     out.clear();
