@@ -178,13 +178,15 @@ def batch_section():
             s2d.stokes2d_slp_eval(mode, b.ves, b.trg_ves, b.d, -1, 1, b.mu, b.u, b.v, 0, wss)
             s2d.stokes2d_dlp_eval(mode, b.wall, b.trg_wall, b.d, -1, 1, b.u, b.v, 1, wss)
     ms_single = _time(singles, reps=3)
+    shape = s2d.stokes2d_batch_tuned(mode, insts)
     s2d.stokes2d_batch_release()
     res = {"workload": "256 instances, 1-40 vesicles x {32,64,128,256} nodes, 256-4096 nodes per wall, "
                        "images -1..1, FP32C", "pairs": pairs, "ms": ms_batch,
            "value": pairs / (ms_batch * 1e-3), "unit": "pair-evals/s", "first_call_s": t_first,
-           "sequential_single_calls_ms": ms_single, "speedup_vs_single_calls": ms_single / ms_batch}
+           "sequential_single_calls_ms": ms_single, "speedup_vs_single_calls": ms_single / ms_batch,
+           "tile_shape": shape}
     log(f"batch: {ms_batch:.2f} ms per batched call ({pairs / (ms_batch * 1e-3):.3e} pairs/s), "
-        f"{ms_single:.2f} ms as 512 single calls, first call {t_first:.1f}s")
+        f"{ms_single:.2f} ms as 512 single calls, first call {t_first:.2f}s, shape {shape}")
     return res
 
 

@@ -151,8 +151,8 @@ S2D_API size_t stokes2d_batch_workspace_size(int mode, int32_t n_inst, const s2d
 
 /* Evaluates u = S(ves) f + D(wall) tau for every instance.  The work of all
  * instances is cut into (instance, operator, target tile, source split)
- * items, sorted longest first, and run by one persistent launch; the whole
- * evaluation is recorded in a HIP graph.  The first call for a given argument
+ * items, sorted longest first per operator, and run by one persistent launch
+ * per operator; the whole evaluation is recorded in a HIP graph.  The first call for a given argument
  * set (mode, every pointer and size in inst[], d, mu, ws, ws_bytes) waits for
  * `stream`, picks the tile shape (timing a few candidates on the real inputs
  * unless a tuned choice for this size is cached; environment S2D_TUNE=0 keeps
@@ -168,6 +168,15 @@ S2D_API int stokes2d_batch_eval(int mode, int32_t n_inst, const s2d_instance *in
 
 /* Frees every cached batch plan and graph (waits for the device). */
 S2D_API int stokes2d_batch_release(void);
+
+/* The tile shape stokes2d_batch_eval uses for this instance set's size
+ * bucket: targets per lane (*tpt: 1, 2 or 4), 256-source superblocks per
+ * source split (*sbps) and resident waves per compute unit of the persistent
+ * grid (*wpc).  Returns 1 when the shape comes from the tuner (this process
+ * or the cache file), 0 when it is the built-in default, or a negative
+ * s2d_status.  Host only; launches nothing. */
+S2D_API int stokes2d_batch_tuned(int mode, int32_t n_inst, const s2d_instance *inst, int32_t *tpt,
+                                 int32_t *sbps, int32_t *wpc);
 
 /* ---------------------------------------------------------------------------
  * Near-field correction of the single layer (learned, with FFT-upsampled

@@ -25,6 +25,7 @@ __all__ = [
     "stokes2d_init", "stokes2d_workspace_size", "stokes2d_slp_eval", "stokes2d_dlp_eval",
     "stokes2d_last_error", "stokes2d_version", "stokes2d_profile_enable", "stokes2d_profile_read",
     "BatchInstance", "stokes2d_batch_workspace_size", "stokes2d_batch_eval", "stokes2d_batch_release",
+    "stokes2d_batch_tuned",
 ]
 
 S2D_OK, S2D_EINVAL, S2D_EHIP, S2D_ENOTSUP, S2D_EWORKSPACE, S2D_ENOINIT = 0, -1, -2, -3, -4, -5
@@ -92,6 +93,8 @@ def lib():
         L.stokes2d_batch_eval.restype = I
         L.stokes2d_batch_release.argtypes = []
         L.stokes2d_batch_release.restype = I
+        L.stokes2d_batch_tuned.argtypes = [I, I32, P, P, P, P]
+        L.stokes2d_batch_tuned.restype = I
         L.stokes2d_profile_enable.argtypes = [I]
         L.stokes2d_profile_enable.restype = I
         L.stokes2d_profile_read.argtypes = [I, P, P]
@@ -260,3 +263,16 @@ def stokes2d_batch_eval(mode, instances, ws, stream=None) -> None:
 
 def stokes2d_batch_release() -> None:
     _check(lib().stokes2d_batch_release())
+
+
+def stokes2d_batch_tuned(mode, instances) -> dict:
+    """The tile shape the batched call uses for these instances' size bucket
+    and whether it came from the tuner (True) or is the default (False)."""
+    arr = _inst_array(instances)
+    t, b, w = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    rc = lib().stokes2d_batch_tuned(int(mode), len(instances), arr, ctypes.byref(t), ctypes.byref(b),
+                                    ctypes.byref(w))
+    if rc < 0:
+        _check(rc)
+    return {"targets_per_lane": t.value, "superblocks_per_split": b.value, "waves_per_cu": w.value,
+            "tuned": rc == 1}

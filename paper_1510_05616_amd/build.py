@@ -29,7 +29,11 @@ def sources():
 
 
 def build(verbose: bool = False, jobs: int = 8) -> str:
-    """Compile each source to an object in parallel, then link the .so."""
+    """Compile each source to an object in parallel, then link the .so.  The
+    previous library is removed first, so a failed build leaves none behind
+    (loaders then fail loudly instead of running stale code)."""
+    if os.path.exists(LIB):
+        os.remove(LIB)
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     procs = []

@@ -369,6 +369,24 @@ S2D_API int stokes2d_batch_eval(int mode, int32_t n_inst, const s2d_instance *in
 
 S2D_API int stokes2d_batch_release(void) { return s2d::batch_release(); }
 
+S2D_API int stokes2d_batch_tuned(int mode, int32_t n_inst, const s2d_instance *inst, int32_t *tpt, int32_t *sbps,
+                                 int32_t *wpc) {
+    if (!tpt || !sbps || !wpc) return fail(S2D_EINVAL, "tpt, sbps and wpc must not be NULL");
+    if (mode != S2D_FP64 && mode != S2D_FP32C) return fail(S2D_EINVAL, "mode must be S2D_FP64 or S2D_FP32C");
+    if (n_inst < 0) return fail(S2D_EINVAL, "n_inst < 0");
+    if (n_inst > 0 && !inst) return fail(S2D_EINVAL, "inst must not be NULL");
+    for (int32_t k = 0; k < n_inst; ++k) {
+        const int rc = check_batch_inst(mode, inst[k], k);
+        if (rc != S2D_OK) return rc;
+    }
+    int a = 0, b = 0, c = 0;
+    const int tuned = s2d::batch_tuned(mode, n_inst, inst, &a, &b, &c);
+    *tpt = a;
+    *sbps = b;
+    *wpc = c;
+    return tuned;
+}
+
 // ---------------------------------------------------------------------------
 // near-field correction
 // ---------------------------------------------------------------------------

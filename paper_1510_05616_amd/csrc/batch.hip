@@ -4,10 +4,11 @@
 //
 // Work list.  The host cuts every instance's single layer (vesicle sources)
 // and double layer (wall sources) into items (instance, op, target tile,
-// source split) and sorts them by estimated cost, longest first.  A
-// persistent grid of independent waves pops items from a device counter
-// (one vector atomic per item) until the list is exhausted; every wave
-// reaches the exit because the counter only grows.  Each item writes its own
+// source split) and sorts each operator's items by estimated cost, longest
+// first.  One persistent grid of independent waves per operator pops items
+// from that operator's device counter (one vector atomic per item) until its
+// list is exhausted; every wave reaches the exit because the counter only
+// grows.  Each item writes its own
 // FP64 partial slot, and a final per-target pass adds the slots in fixed
 // order, so the result is bitwise deterministic whatever order the items ran
 // in.  Uneven vesicle sizes are absorbed because items tile over nodes, not
@@ -59,9 +60,10 @@ struct BatchItem {
 
 struct BatchTables {
     const BatchInst *inst;
-    const BatchItem *items;
+    const BatchItem *items;                        // single-layer items, then double-layer items
     int64_t n_items;
-    unsigned long long *counter;
+    int64_t n_items_op[2];                         // items per op
+    unsigned long long *counter;                   // [2]: next item per op
     const int64_t *src_pad_off0, *src_pad_off1;   // prefix sums of padded sources per op
     const int64_t *sb_off;                         // prefix sums of single-layer superblocks
     const int64_t *curve_pre;                      // prefix sums of vesicle curve counts
@@ -80,7 +82,7 @@ __device__ __forceinline__ int find_inst(const int64_t *__restrict__ off, int n,
 }
 
 __global__ void batch_reset(unsigned long long *counter) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0ull;
+    if (threadIdx.x < 2 && blockIdx.x == 0) counter[threadIdx.x] = 0ull;
 }
 
 // FP64: one thread per padded source; FP32C: one thread per sub-block
@@ -140,22 +142,25 @@ __global__ __launch_bounds__(256) void batch_kress_self(BatchTables t) {
     I.self[I.trg[0].n + i] = sy;
 }
 
-template <int PREC, int TPT>
+// One persistent grid per operator, so that each body gets its own register
+// allocation (the single layer needs about twice the registers of the double
+// layer); each drains its own contiguous range of the work list.
+template <int OP, int PREC, int TPT>
 __global__ __launch_bounds__(kBlock) void batch_pair(BatchTables t) {
     __shared__ double ltab[3 * kLogTab];
-    if (PREC == S2D_FP64) fill_log_table(ltab);
+    if (PREC == S2D_FP64 && OP == S2D_OP_SLP) fill_log_table(ltab);
     const int lane = threadIdx.x & (kWave - 1);
+    const int64_t first = OP == S2D_OP_SLP ? 0 : t.n_items_op[0];
+    const int64_t count = t.n_items_op[OP];
     for (;;) {
         int it = 0;
-        if (lane == 0) it = (int)atomicAdd(t.counter, 1ull);
-        const int64_t item = __builtin_amdgcn_readfirstlane(it);   // lane 0's value, wave-uniform
-        if (item >= t.n_items) break;                          // every wave gets here
-        const BatchItem w = t.items[item];
-        const PairArgs a = t.inst[w.inst].pa[w.op];
-        if (w.op == 0)
-            pair_tile<S2D_OP_SLP, PREC, TPT>(a, w.tile, w.split, lane, ltab);
-        else
-            pair_tile<S2D_OP_DLP, PREC, TPT>(a, w.tile, w.split, lane, ltab);
+        if (lane == 0) it = (int)atomicAdd(t.counter + OP, 1ull);
+        const int64_t k = __builtin_amdgcn_readfirstlane(it);      // lane 0's value, wave-uniform
+        if (k >= count) break;                                     // every wave gets here
+        // the tables were uploaded before the launch: read them as invariant
+        const BatchItem w = load_ro<BatchItem>(t.items, first + k);
+        const PairArgs a = load_ro<PairArgs>(&t.inst[w.inst].pa[OP], 0);
+        pair_tile<OP, PREC, TPT>(a, w.tile, w.split, lane, ltab);
     }
 }
 
@@ -350,14 +355,14 @@ Layout layout(int32_t n_inst, const s2d_instance *inst, int mode, const TuneChoi
     L.off_items = al256(sizeof(BatchInst) * (size_t)n_inst);
     L.off_pre = al256(L.off_items + sizeof(BatchItem) * (size_t)n_items);
     L.off_counter = al256(L.off_pre + sizeof(int64_t) * 5 * ((size_t)n_inst + 1));
-    L.off_data = al256(L.off_counter + 8);
+    L.off_data = al256(L.off_counter + 16);
     L.total = L.off_data + data;
     return L;
 }
 
 const TuneChoice kCandidates64[] = {{1, 2, 16, 0}, {1, 4, 16, 0}, {1, 8, 16, 0}, {2, 4, 16, 0}, {1, 4, 24, 0}};
-const TuneChoice kCandidates32[] = {{2, 2, 16, 0}, {2, 4, 16, 0}, {2, 8, 16, 0}, {1, 2, 16, 0},
-                                    {1, 4, 16, 0}, {1, 8, 16, 0}, {4, 4, 16, 0}, {2, 4, 24, 0}};
+const TuneChoice kCandidates32[] = {{1, 2, 24, 0}, {1, 4, 24, 0}, {1, 8, 24, 0}, {1, 4, 32, 0},
+                                    {1, 4, 16, 0}, {2, 4, 16, 0}, {2, 4, 24, 0}, {2, 8, 24, 0}};
 
 void candidates(int mode, std::vector<TuneChoice> &out) {
     out.clear();
@@ -367,7 +372,7 @@ void candidates(int mode, std::vector<TuneChoice> &out) {
         out.assign(std::begin(kCandidates32), std::end(kCandidates32));
 }
 
-TuneChoice default_choice(int mode) { return mode == S2D_FP64 ? TuneChoice{1, 4, 16, 0} : TuneChoice{2, 4, 16, 0}; }
+TuneChoice default_choice(int mode) { return mode == S2D_FP64 ? TuneChoice{1, 4, 16, 0} : TuneChoice{1, 4, 24, 0}; }
 
 std::string bucket_key(int mode, int32_t n_inst, const s2d_instance *inst) {
     double pairs = 0;
@@ -379,7 +384,10 @@ std::string bucket_key(int mode, int32_t n_inst, const s2d_instance *inst) {
 
 template <int PREC, int TPT>
 hipError_t launch_batch_pair(const BatchTables &t, int blocks, hipStream_t st) {
-    hipLaunchKernelGGL((batch_pair<PREC, TPT>), dim3(blocks), dim3(kBlock), 0, st, t);
+    if (t.n_items_op[0] > 0)
+        hipLaunchKernelGGL((batch_pair<S2D_OP_SLP, PREC, TPT>), dim3(blocks), dim3(kBlock), 0, st, t);
+    if (t.n_items_op[1] > 0)
+        hipLaunchKernelGGL((batch_pair<S2D_OP_DLP, PREC, TPT>), dim3(blocks), dim3(kBlock), 0, st, t);
     return hipGetLastError();
 }
 
@@ -531,13 +539,22 @@ int build_plan(BatchPlan &P, int mode, int32_t n_inst, const s2d_instance *inst,
         p_trg[k + 1] = p_trg[k] + n;
         data += g.bytes;
     }
-    std::stable_sort(work.begin(), work.end(), [](const Cost &a, const Cost &b) { return a.cost > b.cost; });
-    for (size_t i = 0; i < work.size(); ++i) items[i] = work[i].it;
+    // per op, longest first
+    std::stable_sort(work.begin(), work.end(), [](const Cost &a, const Cost &b) {
+        return a.it.op != b.it.op ? a.it.op < b.it.op : a.cost > b.cost;
+    });
+    int64_t n_op[2] = {0, 0};
+    for (size_t i = 0; i < work.size(); ++i) {
+        items[i] = work[i].it;
+        ++n_op[work[i].it.op];
+    }
 
     BatchTables t{};
     t.inst = (const BatchInst *)(db + L.off_inst);
     t.items = (const BatchItem *)(db + L.off_items);
     t.n_items = (int64_t)work.size();
+    t.n_items_op[0] = n_op[0];
+    t.n_items_op[1] = n_op[1];
     t.counter = (unsigned long long *)(db + L.off_counter);
     const int64_t *dpre = (const int64_t *)(db + L.off_pre);
     t.src_pad_off0 = dpre;

@@ -42,6 +42,32 @@
 
 namespace s2d {
 
+// Read-only view of a workspace array that the reading kernel never writes
+// (source records, sub-block descriptors, superblock sums; all written by an
+// earlier launch).  Reads through the constant address space are invariant
+// for the kernel, so wave-uniform ones use scalar loads also where they
+// follow the kernel's own stores (the persistent batched loop), not only
+// before them.
+template <class T>
+using cview = const __attribute__((address_space(4))) T *;
+
+// Element i of an array of T (trivially copyable, a whole number of dwords)
+// read through such a view, one dword at a time (adjacent scalar loads are
+// merged into wide ones) and reassembled.
+template <class T>
+__device__ __forceinline__ T load_ro(const void *base, int64_t i) {
+    static_assert(sizeof(T) % 4 == 0, "whole dwords only");
+    constexpr int n = (int)(sizeof(T) / 4);
+    const cview<uint32_t> p = (cview<uint32_t>)((const char *)base + i * (int64_t)sizeof(T));
+    struct Words {
+        uint32_t w[n];
+    } t;
+#pragma unroll
+    for (int k = 0; k < n; ++k) t.w[k] = p[k];
+    return __builtin_bit_cast(T, t);
+}
+
+
 // 1/q: the hardware seed (measured relative error below 5e-8) and one
 // Newton step, relative error about 2e-15.
 __device__ __forceinline__ double rcp64(double q) {
@@ -277,7 +303,7 @@ __device__ __forceinline__ void pair_tile(const PairArgs &a, int64_t tile, int s
                         for (int u = 0; u < kSuperBlock; u += 4) {
 #pragma unroll
                             for (int q = 0; q < 4; ++q) {
-                                const RecSlp64 s = rec[u + q];
+                                const RecSlp64 s = load_ro<RecSlp64>(rec, u + q);
 #pragma unroll
                                 for (int k = 0; k < TPT; ++k) slp64_pair(px[k], py[k], s, ltab, vx[k], vy[k], ux[k], uy[k]);
                             }
@@ -287,7 +313,7 @@ __device__ __forceinline__ void pair_tile(const PairArgs &a, int64_t tile, int s
                         for (int u = 0; u < kSuperBlock; u += 4) {
 #pragma unroll
                             for (int q = 0; q < 4; ++q) {
-                                const RecDlp64 s = rec[u + q];
+                                const RecDlp64 s = load_ro<RecDlp64>(rec, u + q);
 #pragma unroll
                                 for (int k = 0; k < TPT; ++k) dlp64_pair(px[k], py[k], s, ux[k], uy[k]);
                             }
@@ -298,10 +324,11 @@ __device__ __forceinline__ void pair_tile(const PairArgs &a, int64_t tile, int s
                         const RecSlp32 *rec = (const RecSlp32 *)a.rec + j0;
                         // log reference: the superblock's first source
                         float iqr[TPT];
-                        const double gsx = a.sbsum[2 * sb], gsy = a.sbsum[2 * sb + 1];
+                        const double gsx = load_ro<double>(a.sbsum, 2 * sb), gsy = load_ro<double>(a.sbsum, 2 * sb + 1);
+                        const RecSlp32 r0 = load_ro<RecSlp32>(rec, 0);
 #pragma unroll
                         for (int k = 0; k < TPT; ++k) {
-                            const double rx0 = px[k] - rec[0].x, ry0 = py[k] - rec[0].y;
+                            const double rx0 = px[k] - r0.x, ry0 = py[k] - r0.y;
                             const double qr = __builtin_fma(rx0, rx0, ry0 * ry0);
                             iqr[k] = (qr > 1e-20 && qr < 1e20) ? (float)rcp64(qr) : 1.0f;
                             // -1/2 sum g ln q = sum (l log2(q iqr)) + 1/2 ln(iqr) sum g
@@ -316,10 +343,11 @@ __device__ __forceinline__ void pair_tile(const PairArgs &a, int64_t tile, int s
                             for (int k = 0; k < TPT; ++k)
 #pragma unroll
                                 for (int e = 0; e < 8; ++e) ac[k][e / 4][e % 4] = 0.f;
-                            if (far_offsets<TPT>(a.sub[(j0 + u) / kSubBlock], px, py, act, dx, dy)) {
+                            const SubInfo si = load_ro<SubInfo>(a.sub, (j0 + u) / kSubBlock);
+                            if (far_offsets<TPT>(si, px, py, act, dx, dy)) {
 #pragma unroll
                                 for (int q = 0; q < kSubBlock; ++q) {
-                                    const RecSlp32 s = rec[u + q];
+                                    const RecSlp32 s = load_ro<RecSlp32>(rec, u + q);
 #pragma unroll
                                     for (int k = 0; k < TPT; ++k)
                                         slp32_r(dx[k] - s.xl, dy[k] - s.yl, s, iqr[k], ac[k][q & 1]);
@@ -327,7 +355,7 @@ __device__ __forceinline__ void pair_tile(const PairArgs &a, int64_t tile, int s
                             } else {
 #pragma unroll
                                 for (int q = 0; q < kSubBlock; ++q) {
-                                    const RecSlp32 s = rec[u + q];
+                                    const RecSlp32 s = load_ro<RecSlp32>(rec, u + q);
 #pragma unroll
                                     for (int k = 0; k < TPT; ++k) slp32_acc(px[k], py[k], s, iqr[k], ac[k][q & 1]);
                                 }
@@ -346,17 +374,18 @@ __device__ __forceinline__ void pair_tile(const PairArgs &a, int64_t tile, int s
                             for (int k = 0; k < TPT; ++k)
 #pragma unroll
                                 for (int e = 0; e < 4; ++e) ac[k][e / 2][e % 2] = 0.f;
-                            if (far_offsets<TPT>(a.sub[(j0 + u) / kSubBlock], px, py, act, dx, dy)) {
+                            const SubInfo si = load_ro<SubInfo>(a.sub, (j0 + u) / kSubBlock);
+                            if (far_offsets<TPT>(si, px, py, act, dx, dy)) {
 #pragma unroll
                                 for (int q = 0; q < kSubBlock; ++q) {
-                                    const RecDlp32 s = rec[u + q];
+                                    const RecDlp32 s = load_ro<RecDlp32>(rec, u + q);
 #pragma unroll
                                     for (int k = 0; k < TPT; ++k) dlp32_r(dx[k] - s.xl, dy[k] - s.yl, s, ac[k][q & 1]);
                                 }
                             } else {
 #pragma unroll
                                 for (int q = 0; q < kSubBlock; ++q) {
-                                    const RecDlp32 s = rec[u + q];
+                                    const RecDlp32 s = load_ro<RecDlp32>(rec, u + q);
 #pragma unroll
                                     for (int k = 0; k < TPT; ++k) dlp32_acc(px[k], py[k], s, ac[k][q & 1]);
                                 }
@@ -378,13 +407,13 @@ __device__ __forceinline__ void pair_tile(const PairArgs &a, int64_t tile, int s
                         const bool ok = inrange && (n != 0 || j < lo[k] || j >= hi[k]);
                         if (PREC == S2D_FP64) {
                             if (OP == S2D_OP_SLP) {
-                                const RecSlp64 s = ((const RecSlp64 *)a.rec)[j];
+                                const RecSlp64 s = load_ro<RecSlp64>(a.rec, j);
                                 double ax = 0, ay = 0, bx = 0, by = 0;
                                 slp64_pair(px[k], py[k], s, ltab, ax, ay, bx, by);
                                 vx[k] += ok ? ax : 0.0; vy[k] += ok ? ay : 0.0;
                                 ux[k] += ok ? bx : 0.0; uy[k] += ok ? by : 0.0;
                             } else {
-                                const RecDlp64 s = ((const RecDlp64 *)a.rec)[j];
+                                const RecDlp64 s = load_ro<RecDlp64>(a.rec, j);
                                 double ax = 0, ay = 0;
                                 dlp64_pair(px[k], py[k], s, ax, ay);
                                 ux[k] += ok ? ax : 0.0; uy[k] += ok ? ay : 0.0;
@@ -392,13 +421,13 @@ __device__ __forceinline__ void pair_tile(const PairArgs &a, int64_t tile, int s
                         } else {
                             float t0 = 0.f, t1 = 0.f;
                             if (OP == S2D_OP_SLP) {
-                                const RecSlp32 s = ((const RecSlp32 *)a.rec)[j];
+                                const RecSlp32 s = load_ro<RecSlp32>(a.rec, j);
                                 float t4[4] = {0.f, 0.f, 0.f, 0.f};
                                 slp32_acc(px[k], py[k], s, 1.0f, t4);
                                 t0 = t4[0] + t4[2];
                                 t1 = t4[1] + t4[3];
                             } else {
-                                const RecDlp32 s = ((const RecDlp32 *)a.rec)[j];
+                                const RecDlp32 s = load_ro<RecDlp32>(a.rec, j);
                                 float t2[2] = {0.f, 0.f};
                                 dlp32_acc(px[k], py[k], s, t2);
                                 t0 = t2[0];

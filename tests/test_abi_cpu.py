@@ -94,3 +94,18 @@ def test_workspace_grows_with_problem(L):
             a = L.stokes2d_workspace_size(op, mode, ctypes.byref(small[0]), ctypes.byref(small[1]))
             b = L.stokes2d_workspace_size(op, mode, ctypes.byref(big[0]), ctypes.byref(big[1]))
             assert 0 < a < b
+
+
+def test_batch_tuned_is_host_only_and_reports_the_default(L, tmp_path, monkeypatch):
+    import paper_1510_05616_amd as s2d
+    monkeypatch.setenv("S2D_TUNE_CACHE", str(tmp_path / "absent.json"))
+    t = ctypes.c_int32()
+    by = ctypes.byref
+    assert L.stokes2d_batch_tuned(1, 0, None, None, by(t), by(t)) == s2d.S2D_EINVAL
+    assert L.stokes2d_batch_tuned(3, 0, None, by(t), by(t), by(t)) == s2d.S2D_EINVAL
+    assert L.stokes2d_batch_tuned(1, -1, None, by(t), by(t), by(t)) == s2d.S2D_EINVAL
+    for mode in (s2d.S2D_FP64, s2d.S2D_FP32C):
+        shape = s2d.stokes2d_batch_tuned(mode, [])
+        assert shape["tuned"] is False
+        assert shape["targets_per_lane"] in (1, 2, 4)
+        assert shape["superblocks_per_split"] > 0 and shape["waves_per_cu"] > 0
