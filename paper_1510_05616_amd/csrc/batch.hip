@@ -147,7 +147,7 @@ __global__ __launch_bounds__(256) void batch_kress_self(BatchTables t) {
 // layer); each drains its own contiguous range of the work list.
 template <int OP, int PREC, int TPT>
 __global__ __launch_bounds__(kBlock) void batch_pair(BatchTables t) {
-    __shared__ double ltab[3 * kLogTab];
+    __shared__ __attribute__((aligned(16))) double ltab[kLogTabWords];
     if (PREC == S2D_FP64 && OP == S2D_OP_SLP) fill_log_table(ltab);
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t first = OP == S2D_OP_SLP ? 0 : t.n_items_op[0];

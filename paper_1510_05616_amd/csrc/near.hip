@@ -151,7 +151,7 @@ __global__ __launch_bounds__(256) void near_quad(int64_t n_trg, const int32_t *_
                                                  double pref, double *__restrict__ du, double *__restrict__ dv,
                                                  double *__restrict__ uf, double *__restrict__ vf,
                                                  double *__restrict__ uc, double *__restrict__ vc) {
-    __shared__ double ltab[3 * kLogTab];
+    __shared__ __attribute__((aligned(16))) double ltab[kLogTabWords];
     fill_log_table(ltab);
     const int64_t n = n_trg;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;

@@ -6,7 +6,7 @@ namespace s2d {
 
 template <int OP, int PREC, int TPT>
 __global__ __launch_bounds__(kBlock) void pair_kernel(PairArgs a) {
-    __shared__ double ltab[3 * kLogTab];
+    __shared__ __attribute__((aligned(16))) double ltab[kLogTabWords];
     if (PREC == S2D_FP64 && OP == S2D_OP_SLP) fill_log_table(ltab);   // before any wave returns
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;

@@ -113,37 +113,41 @@ __device__ __forceinline__ double log64(double x) {
 
 // Table-driven natural log (Tang's method) of a positive, finite, normal
 // double: x = 2^e m, m in [1/2, 1); the top 8 mantissa bits pick the
-// breakpoint F_k = 1/2 + (k + 1/2) / 512, f = m - F_k is exact, and
-// log m = log F_k + log1p(u), u = f / F_k, |u| <= 2^-9, with log1p summed to
-// u^6 (first omitted term below 1e-20).  tab holds F_k, 1/F_k, log F_k
-// (3 x kLogTab doubles, staged in LDS by fill_log_table).
+// breakpoint F_k = 1/2 + (k + 1/2) / 512, and
+// log x = e ln 2 + log F_k + log1p(u), u = m / F_k - 1, |u| <= 2^-9.
+// u is formed as one FMA m (1/F_k) - 1 (error below 2^-52 from the rounding
+// of 1/F_k), log1p is summed to u^5 (first omitted term below 2e-17), and
+// e ln 2 is one rounded product: absolute error a few 1e-16 for the |e| of
+// squared distances, far inside the FP64 path's 1e-12 budget.  tab holds the
+// pairs {1/F_k, log F_k} (2 x kLogTab doubles, staged in LDS by
+// fill_log_table; one 16-byte LDS read per call).
 constexpr int kLogTab = 256;
+constexpr int kLogTabWords = 2 * kLogTab;
 
 __device__ __forceinline__ double log64_tab(double x, const double *tab) {
     const int e = __builtin_amdgcn_frexp_exp(x);
     const double m = __builtin_amdgcn_frexp_mant(x);
     const uint32_t hi = (uint32_t)(__builtin_bit_cast(uint64_t, x) >> 32);
     const int k = (hi >> 12) & (kLogTab - 1);
-    const double u = (m - tab[k]) * tab[kLogTab + k];
-    double p = -1.0 / 6.0;
-    p = __builtin_fma(p, u, 1.0 / 5.0);
+    typedef double double2_t __attribute__((ext_vector_type(2)));
+    const double2_t t = ((const double2_t *)tab)[k];     // {1/F_k, log F_k}
+    const double u = __builtin_fma(m, t.x, -1.0);
+    double p = 1.0 / 5.0;
     p = __builtin_fma(p, u, -1.0 / 4.0);
     p = __builtin_fma(p, u, 1.0 / 3.0);
     p = __builtin_fma(p, u, -1.0 / 2.0);
     const double l1p = __builtin_fma(p * u, u, u);
-    const double de = (double)e;
-    constexpr double kLn2Hi = 6.93147180369123816490e-01;
-    constexpr double kLn2Lo = 1.90821492927058770002e-10;
-    return __builtin_fma(de, kLn2Hi, tab[2 * kLogTab + k] + __builtin_fma(de, kLn2Lo, l1p));
+    constexpr double kLn2 = 6.93147180559945286227e-01;
+    return __builtin_fma((double)e, kLn2, t.y + l1p);
 }
 
-// Called by every thread of a workgroup before any of them uses the table.
+// Called by every thread of a workgroup before any of them uses the table
+// (a __shared__ array of kLogTabWords doubles, 16-byte aligned).
 __device__ __forceinline__ void fill_log_table(double *tab) {
     for (int k = threadIdx.x; k < kLogTab; k += blockDim.x) {
         const double F = 0.5 + ((double)k + 0.5) / (2.0 * kLogTab);
-        tab[k] = F;
-        tab[kLogTab + k] = 1.0 / F;
-        tab[2 * kLogTab + k] = log64(F);
+        tab[2 * k] = 1.0 / F;
+        tab[2 * k + 1] = log64(F);
     }
     __syncthreads();
 }
