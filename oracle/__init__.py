@@ -15,7 +15,11 @@ Pins (tests/test_oracle_*.py): Kress weights exact on cos(m t) and summing to
 zero; the circle of constant density; the double-layer translation identity
 (-c inside, 0 outside, -c/2 on the curve); reproduction of an exterior point
 Stokeslet by Green's identity with spectral convergence; Stokeslet symmetry;
-50-digit brute force on tiny curves; explicit image replication.
+50-digit brute force on tiny curves; explicit image replication.  Pressures
+and traction: the single-layer pressure of a circle of constant density in
+closed form; the pressure form of Green's identity, with the traction data
+taken from the oracle's own traction kernel; the traction equals the stress
+of the single-layer velocity and pressure fields (finite differences).
 """
 from __future__ import annotations
 
@@ -30,7 +34,7 @@ _SRC = os.path.join(_HERE, "stokes_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "_liboracle.so")
 _lib = None
 
-__all__ = ["build", "slp", "dlp", "kress_weights", "num_threads"]
+__all__ = ["build", "slp", "dlp", "slp_pressure", "dlp_pressure", "slp_traction", "kress_weights", "num_threads"]
 
 
 def build(force: bool = True) -> str:
@@ -59,6 +63,13 @@ def _load():
         lib.oracle_dlp.argtypes = [ctypes.c_int64, ctypes.c_int32, P, P, P, P, P, P, P, P, P,
                                    ctypes.c_int64, P, P, P, P, ctypes.c_double,
                                    ctypes.c_int32, ctypes.c_int32, P, P]
+        I64, I32, D = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+        lib.oracle_slp_pressure.restype = ctypes.c_int
+        lib.oracle_slp_pressure.argtypes = [I64, P, P, P, P, P, I64, P, P, D, I32, I32, P]
+        lib.oracle_dlp_pressure.restype = ctypes.c_int
+        lib.oracle_dlp_pressure.argtypes = [I64, P, P, P, P, P, P, P, I64, P, P, D, I32, I32, D, P]
+        lib.oracle_slp_traction.restype = ctypes.c_int
+        lib.oracle_slp_traction.argtypes = [I64, P, P, P, P, P, I64, P, P, P, P, D, I32, I32, P, P]
         lib.oracle_kress_weights.argtypes = [ctypes.c_int, P]
         lib.oracle_kress_weights.restype = ctypes.c_int
         lib.oracle_num_threads.restype = ctypes.c_int
@@ -114,6 +125,44 @@ def dlp(src, tx, ty, on_curve=None, on_node=None, d=0.0, img_lo=0, img_hi=0):
     if rc != 0:
         raise ValueError("oracle_dlp: invalid arguments")
     return u, v
+
+
+def slp_pressure(src, tx, ty, d=0.0, img_lo=0, img_hi=0):
+    """Pressure of the single layer (density src.fx, src.fy, weights src.w) at
+    free targets, summed over images img_lo..img_hi of period d."""
+    lib = _load()
+    x, y, w, fx, fy = (_f64(getattr(src, k)) for k in ("x", "y", "w", "fx", "fy"))
+    tx, ty = _f64(tx), _f64(ty)
+    p = np.zeros(tx.shape[0])
+    if lib.oracle_slp_pressure(x.shape[0], _p(x), _p(y), _p(w), _p(fx), _p(fy), tx.shape[0], _p(tx), _p(ty),
+                               float(d), int(img_lo), int(img_hi), _p(p)) != 0:
+        raise ValueError("oracle_slp_pressure: invalid arguments")
+    return p
+
+
+def dlp_pressure(src, tx, ty, d=0.0, img_lo=0, img_hi=0, mu=1.0):
+    """Pressure of the double layer (density src.fx, src.fy, source normals
+    src.nx, src.ny, weights src.w) at free targets."""
+    lib = _load()
+    x, y, nx, ny, w, fx, fy = (_f64(getattr(src, k)) for k in ("x", "y", "nx", "ny", "w", "fx", "fy"))
+    tx, ty = _f64(tx), _f64(ty)
+    p = np.zeros(tx.shape[0])
+    if lib.oracle_dlp_pressure(x.shape[0], _p(x), _p(y), _p(nx), _p(ny), _p(w), _p(fx), _p(fy), tx.shape[0],
+                               _p(tx), _p(ty), float(d), int(img_lo), int(img_hi), float(mu), _p(p)) != 0:
+        raise ValueError("oracle_dlp_pressure: invalid arguments")
+    return p
+
+
+def slp_traction(src, tx, ty, mx, my, d=0.0, img_lo=0, img_hi=0):
+    """Traction of the single layer at free targets with unit normals (mx, my)."""
+    lib = _load()
+    x, y, w, fx, fy = (_f64(getattr(src, k)) for k in ("x", "y", "w", "fx", "fy"))
+    tx, ty, mx, my = _f64(tx), _f64(ty), _f64(mx), _f64(my)
+    ox, oy = np.zeros(tx.shape[0]), np.zeros(tx.shape[0])
+    if lib.oracle_slp_traction(x.shape[0], _p(x), _p(y), _p(w), _p(fx), _p(fy), tx.shape[0], _p(tx), _p(ty),
+                               _p(mx), _p(my), float(d), int(img_lo), int(img_hi), _p(ox), _p(oy)) != 0:
+        raise ValueError("oracle_slp_traction: invalid arguments")
+    return ox, oy
 
 
 def kress_weights(N: int) -> np.ndarray:

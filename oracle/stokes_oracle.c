@@ -204,6 +204,96 @@ int oracle_dlp(int64_t n_src, int32_t n_curves, const int32_t *curve_off,
     return 0;
 }
 
+/*
+ * Pressures and traction at free targets (no target coincides with a source
+ * node; a coincident pair gives an infinite or NaN term, as the kernels are
+ * singular there).  Sums over the images n = img_lo..img_hi as above.
+ *
+ * Single-layer pressure (Section 2.1, Eq. (Q)):
+ *   p(x) = 1/(2 pi) sum_n sum_j (r . g_j) / |r|^2,  g_j = w_j f_j.
+ * Double-layer pressure (Section 2.1, Eq. (P)):
+ *   p(x) = mu/pi sum_n sum_j [ -(nu_j . tau_j) / |r|^2
+ *                              + 2 (r . nu_j)(r . tau_j) / |r|^4 ],  nu_j = w_j n_j.
+ * Single-layer traction at a target with unit normal m (Section 2.1, Eq. (K)):
+ *   t(x) = -1/pi sum_n sum_j r (r . g_j)(r . m) / |r|^4.
+ */
+int oracle_slp_pressure(int64_t n_src, const double *x, const double *y, const double *w,
+                        const double *fx, const double *fy, int64_t n_trg,
+                        const double *tx, const double *ty, double d, int32_t img_lo,
+                        int32_t img_hi, double *out_p)
+{
+    if (img_lo > img_hi) return -1;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n_trg; ++i) {
+        nsum sp = {0, 0};
+        for (int n = img_lo; n <= img_hi; ++n) {
+            double px = tx[i] - (double)n * d, py = ty[i];
+            for (int64_t j = 0; j < n_src; ++j) {
+                double rx = px - x[j], ry = py - y[j];
+                double q = rx * rx + ry * ry;
+                double rg = rx * (w[j] * fx[j]) + ry * (w[j] * fy[j]);
+                nadd(&sp, rg / q);
+            }
+        }
+        out_p[i] = nval(&sp) / (2.0 * M_PI);
+    }
+    return 0;
+}
+
+int oracle_dlp_pressure(int64_t n_src, const double *x, const double *y, const double *nx,
+                        const double *ny, const double *w, const double *tx_d,
+                        const double *ty_d, int64_t n_trg, const double *tx, const double *ty,
+                        double d, int32_t img_lo, int32_t img_hi, double mu, double *out_p)
+{
+    if (img_lo > img_hi) return -1;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n_trg; ++i) {
+        nsum sp = {0, 0};
+        for (int n = img_lo; n <= img_hi; ++n) {
+            double px = tx[i] - (double)n * d, py = ty[i];
+            for (int64_t j = 0; j < n_src; ++j) {
+                double rx = px - x[j], ry = py - y[j];
+                double q = rx * rx + ry * ry;
+                double vx = w[j] * nx[j], vy = w[j] * ny[j];
+                double rn = rx * vx + ry * vy;
+                double rt = rx * tx_d[j] + ry * ty_d[j];
+                double nt = vx * tx_d[j] + vy * ty_d[j];
+                nadd(&sp, -nt / q);
+                nadd(&sp, 2.0 * rn * rt / (q * q));
+            }
+        }
+        out_p[i] = mu / M_PI * nval(&sp);
+    }
+    return 0;
+}
+
+int oracle_slp_traction(int64_t n_src, const double *x, const double *y, const double *w,
+                        const double *fx, const double *fy, int64_t n_trg,
+                        const double *tx, const double *ty, const double *mx, const double *my,
+                        double d, int32_t img_lo, int32_t img_hi, double *out_x, double *out_y)
+{
+    if (img_lo > img_hi) return -1;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n_trg; ++i) {
+        nsum sx = {0, 0}, sy = {0, 0};
+        for (int n = img_lo; n <= img_hi; ++n) {
+            double px = tx[i] - (double)n * d, py = ty[i];
+            for (int64_t j = 0; j < n_src; ++j) {
+                double rx = px - x[j], ry = py - y[j];
+                double q = rx * rx + ry * ry;
+                double rg = rx * (w[j] * fx[j]) + ry * (w[j] * fy[j]);
+                double rm = rx * mx[i] + ry * my[i];
+                double s = rg * rm / (q * q);
+                nadd(&sx, rx * s);
+                nadd(&sy, ry * s);
+            }
+        }
+        out_x[i] = -nval(&sx) / M_PI;
+        out_y[i] = -nval(&sy) / M_PI;
+    }
+    return 0;
+}
+
 /* Kress weights for a curve of N nodes (exposed for the tests' pins). */
 int oracle_kress_weights(int N, double *R) {
     if (N < 2 || N % 2) return -1;
