@@ -79,7 +79,13 @@ typedef enum {
                              Kress quadrature and the diagonal limit stay FP64 */
 } s2d_mode;
 
-typedef enum { S2D_OP_SLP = 0, S2D_OP_DLP = 1 } s2d_op;
+typedef enum {
+    S2D_OP_SLP = 0,               /* single-layer velocity */
+    S2D_OP_DLP = 1,               /* double-layer velocity */
+    S2D_OP_SLP_PRESSURE = 2,      /* single-layer pressure (free targets) */
+    S2D_OP_DLP_PRESSURE = 3,      /* double-layer pressure (free targets) */
+    S2D_OP_SLP_TRACTION = 4       /* single-layer traction (free targets with normals) */
+} s2d_op;
 
 /* A set of source curves (device pointers).  Curve c owns global nodes
  * [curve_off[c], curve_off[c+1]). */
@@ -131,6 +137,45 @@ S2D_API int stokes2d_dlp_eval(int mode, const s2d_curves *src, const s2d_targets
                               double d, int32_t img_lo, int32_t img_hi,
                               double *u, double *v, int accumulate,
                               void *ws, size_t ws_bytes, void *stream);
+
+/* Pressure and traction of the layer potentials at free targets (the
+ * pressure representation and the traction data of the periodicity
+ * conditions).  The kernels are singular where a target meets a source node,
+ * so trg->on_curve / on_node must be NULL (S2D_EINVAL otherwise); targets are
+ * assumed off the source curves.  Sums over source images n = img_lo..img_hi
+ * as for the velocities; the same modes (FP64, FP32C with FP32 pair terms from
+ * exact FP64 coordinate differences).  Output arrays are [trg->n] device FP64,
+ * written, or added to when accumulate != 0.
+ *
+ * Single-layer pressure (Section 2.1, Eq. (Q)) of force density src->fx, fy:
+ *   p(x) = 1/(2 pi) sum_n sum_j (r . w_j f_j) / |r|^2,  r = x - y_j - n d e1
+ * (no viscosity factor). */
+S2D_API int stokes2d_slp_pressure_eval(int mode, const s2d_curves *src, const s2d_targets *trg,
+                                       double d, int32_t img_lo, int32_t img_hi,
+                                       double *p, int accumulate,
+                                       void *ws, size_t ws_bytes, void *stream);
+
+/* Double-layer pressure (Section 2.1, Eq. (P)) of density src->fx, fy (tau),
+ * source normals src->nx, ny:
+ *   p(x) = mu/pi sum_n sum_j [ -(nu_j . tau_j) / |r|^2
+ *                              + 2 (r . nu_j)(r . tau_j) / |r|^4 ],  nu_j = w_j n_j.
+ * Requires mu > 0. */
+S2D_API int stokes2d_dlp_pressure_eval(int mode, const s2d_curves *src, const s2d_targets *trg,
+                                       double d, int32_t img_lo, int32_t img_hi, double mu,
+                                       double *p, int accumulate,
+                                       void *ws, size_t ws_bytes, void *stream);
+
+/* Single-layer traction (Section 2.1, Eq. (K)) at targets with unit normals
+ * (trg_nx[i], trg_ny[i]) (device FP64 [trg->n]):
+ *   t(x) = -1/pi sum_n sum_j r (r . w_j f_j)(r . m) / |r|^4,  m the target normal
+ * (no viscosity factor).  With single images n = -1 and n = +1 at the side
+ * walls this gives the traction discrepancy data of the periodicity
+ * conditions (Section 3.1, Eq. (vesgT)). */
+S2D_API int stokes2d_slp_traction_eval(int mode, const s2d_curves *src, const s2d_targets *trg,
+                                       const double *trg_nx, const double *trg_ny,
+                                       double d, int32_t img_lo, int32_t img_hi,
+                                       double *tx, double *ty, int accumulate,
+                                       void *ws, size_t ws_bytes, void *stream);
 
 /* One independent channel instance of a batched evaluation: the single
  * layer of the vesicles plus the double layer of the walls, images -1..1,

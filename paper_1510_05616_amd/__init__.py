@@ -25,12 +25,13 @@ __all__ = [
     "stokes2d_init", "stokes2d_workspace_size", "stokes2d_slp_eval", "stokes2d_dlp_eval",
     "stokes2d_last_error", "stokes2d_version", "stokes2d_profile_enable", "stokes2d_profile_read",
     "BatchInstance", "stokes2d_batch_workspace_size", "stokes2d_batch_eval", "stokes2d_batch_release",
-    "stokes2d_batch_tuned",
+    "stokes2d_batch_tuned", "S2D_OP_SLP_PRESSURE", "S2D_OP_DLP_PRESSURE", "S2D_OP_SLP_TRACTION",
+    "stokes2d_slp_pressure_eval", "stokes2d_dlp_pressure_eval", "stokes2d_slp_traction_eval",
 ]
 
 S2D_OK, S2D_EINVAL, S2D_EHIP, S2D_ENOTSUP, S2D_EWORKSPACE, S2D_ENOINIT = 0, -1, -2, -3, -4, -5
 S2D_FP64, S2D_FP32C = 0, 1
-S2D_OP_SLP, S2D_OP_DLP = 0, 1
+S2D_OP_SLP, S2D_OP_DLP, S2D_OP_SLP_PRESSURE, S2D_OP_DLP_PRESSURE, S2D_OP_SLP_TRACTION = 0, 1, 2, 3, 4
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "libstokes2d.so")
@@ -83,6 +84,12 @@ def lib():
         L.stokes2d_slp_eval.restype = I
         L.stokes2d_dlp_eval.argtypes = [I, P, P, D, I32, I32, P, P, I, P, SZ, P]
         L.stokes2d_dlp_eval.restype = I
+        L.stokes2d_slp_pressure_eval.argtypes = [I, P, P, D, I32, I32, P, I, P, SZ, P]
+        L.stokes2d_slp_pressure_eval.restype = I
+        L.stokes2d_dlp_pressure_eval.argtypes = [I, P, P, D, I32, I32, D, P, I, P, SZ, P]
+        L.stokes2d_dlp_pressure_eval.restype = I
+        L.stokes2d_slp_traction_eval.argtypes = [I, P, P, P, P, D, I32, I32, P, P, I, P, SZ, P]
+        L.stokes2d_slp_traction_eval.restype = I
         L.stokes2d_last_error.argtypes = []
         L.stokes2d_last_error.restype = ctypes.c_char_p
         L.stokes2d_version.argtypes = []
@@ -226,6 +233,38 @@ def stokes2d_dlp_eval(mode, src: Curves, trg: Targets, d, img_lo, img_hi, u, v,
     _check(lib().stokes2d_dlp_eval(int(mode), ctypes.byref(cs), ctypes.byref(ts), float(d),
                                    int(img_lo), int(img_hi), _ptr(u), _ptr(v),
                                    int(bool(accumulate)), _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def stokes2d_slp_pressure_eval(mode, src: Curves, trg: Targets, d, img_lo, img_hi, p,
+                               accumulate=0, ws=None, stream=None) -> None:
+    """Single-layer pressure at free targets (trg without on-curve
+    references); p: device float64 tensor of length trg.n."""
+    cs, ts = src.struct(), trg.struct()
+    ws = _workspace(stokes2d_workspace_size(S2D_OP_SLP_PRESSURE, mode, src, trg), p.device, ws)
+    _check(lib().stokes2d_slp_pressure_eval(int(mode), ctypes.byref(cs), ctypes.byref(ts), float(d), int(img_lo),
+                                            int(img_hi), _ptr(p), int(bool(accumulate)), _ptr(ws), ws.numel(),
+                                            _stream(stream)))
+
+
+def stokes2d_dlp_pressure_eval(mode, src: Curves, trg: Targets, d, img_lo, img_hi, mu, p,
+                               accumulate=0, ws=None, stream=None) -> None:
+    """Double-layer pressure at free targets."""
+    cs, ts = src.struct(), trg.struct()
+    ws = _workspace(stokes2d_workspace_size(S2D_OP_DLP_PRESSURE, mode, src, trg), p.device, ws)
+    _check(lib().stokes2d_dlp_pressure_eval(int(mode), ctypes.byref(cs), ctypes.byref(ts), float(d), int(img_lo),
+                                            int(img_hi), float(mu), _ptr(p), int(bool(accumulate)), _ptr(ws),
+                                            ws.numel(), _stream(stream)))
+
+
+def stokes2d_slp_traction_eval(mode, src: Curves, trg: Targets, nx, ny, d, img_lo, img_hi, tx, ty,
+                               accumulate=0, ws=None, stream=None) -> None:
+    """Single-layer traction at free targets with unit normals nx, ny
+    (device float64 tensors of length trg.n)."""
+    cs, ts = src.struct(), trg.struct()
+    ws = _workspace(stokes2d_workspace_size(S2D_OP_SLP_TRACTION, mode, src, trg), tx.device, ws)
+    _check(lib().stokes2d_slp_traction_eval(int(mode), ctypes.byref(cs), ctypes.byref(ts), _ptr(nx), _ptr(ny),
+                                            float(d), int(img_lo), int(img_hi), _ptr(tx), _ptr(ty),
+                                            int(bool(accumulate)), _ptr(ws), ws.numel(), _stream(stream)))
 
 
 class BatchInstance:

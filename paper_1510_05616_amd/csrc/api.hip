@@ -42,7 +42,7 @@ int fail(int code, const std::string &msg) {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 size_t rec_bytes(int op, int mode) {
-    if (op == S2D_OP_SLP) return mode == S2D_FP64 ? sizeof(s2d::RecSlp64) : sizeof(s2d::RecSlp32);
+    if (s2d::slp_sources(op)) return mode == S2D_FP64 ? sizeof(s2d::RecSlp64) : sizeof(s2d::RecSlp32);
     return mode == S2D_FP64 ? sizeof(s2d::RecDlp64) : sizeof(s2d::RecDlp32);
 }
 
@@ -51,7 +51,7 @@ size_t rec_bytes(int op, int mode) {
 int check_args(int op, int mode, const s2d_curves *s, const s2d_targets *t, double d, int img_lo,
                int img_hi, double mu) {
     if (mode != S2D_FP64 && mode != S2D_FP32C) return fail(S2D_EINVAL, "mode must be S2D_FP64 or S2D_FP32C");
-    if (op != S2D_OP_SLP && op != S2D_OP_DLP) return fail(S2D_EINVAL, "op must be S2D_OP_SLP or S2D_OP_DLP");
+    if (op < S2D_OP_SLP || op > S2D_OP_SLP_TRACTION) return fail(S2D_EINVAL, "op must be an s2d_op");
     if (!s || !t) return fail(S2D_EINVAL, "src and trg must not be NULL");
     if (s->n_nodes < 0 || s->n_nodes > INT32_MAX - 2 * s2d::kSuperBlock)
         return fail(S2D_EINVAL, "src->n_nodes out of range [0, 2^31 - 513]");
@@ -60,11 +60,13 @@ int check_args(int op, int mode, const s2d_curves *s, const s2d_targets *t, doub
     if (s->n_nodes > 0) {
         if (!s->x || !s->y || !s->w || !s->fx || !s->fy)
             return fail(S2D_EINVAL, "src x, y, w, fx, fy must not be NULL when n_nodes > 0");
-        if (op == S2D_OP_DLP && (!s->nx || !s->ny)) return fail(S2D_EINVAL, "double layer needs src nx, ny");
+        if (!s2d::slp_sources(op) && (!s->nx || !s->ny)) return fail(S2D_EINVAL, "double layer needs src nx, ny");
     }
     if (t->n > 0 && (!t->x || !t->y)) return fail(S2D_EINVAL, "trg x, y must not be NULL when n > 0");
     if ((t->on_curve == nullptr) != (t->on_node == nullptr))
         return fail(S2D_EINVAL, "trg on_curve and on_node must both be NULL or both be set");
+    if (op > S2D_OP_DLP && t->on_curve)
+        return fail(S2D_EINVAL, "pressure and traction are evaluated at free targets: trg on_curve must be NULL");
     if (t->on_curve && t->n > 0) {
         if (!s->curve_off) return fail(S2D_EINVAL, "on-curve targets need src->curve_off");
         if (op == S2D_OP_SLP && s->n_nodes > 0 && (!s->nx || !s->ny))
@@ -76,7 +78,8 @@ int check_args(int op, int mode, const s2d_curves *s, const s2d_targets *t, doub
     if (img_lo < -s2d::kMaxImages || img_hi > s2d::kMaxImages) return fail(S2D_EINVAL, "|image| > 64");
     if ((img_lo != 0 || img_hi != 0) && !(std::isfinite(d) && d > 0.0))
         return fail(S2D_EINVAL, "period d must be finite and > 0 when images are used");
-    if (op == S2D_OP_SLP && !(std::isfinite(mu) && mu > 0.0)) return fail(S2D_EINVAL, "mu must be finite and > 0");
+    if ((op == S2D_OP_SLP || op == S2D_OP_DLP_PRESSURE) && !(std::isfinite(mu) && mu > 0.0))
+        return fail(S2D_EINVAL, "mu must be finite and > 0");
     return S2D_OK;
 }
 
@@ -98,7 +101,7 @@ s2d::Plan make_plan(int op, int mode, const s2d_curves *s, const s2d_targets *t,
         const char *e = std::getenv("S2D_SPLITS");
         return e ? std::max(0, std::atoi(e)) : 0;
     }();
-    p.tpt = env_tpt ? env_tpt : 1;
+    p.tpt = (env_tpt && op <= S2D_OP_DLP) ? env_tpt : 1;      // pressures and traction: one target per lane
     constexpr int64_t kWavesPerSimd = 128;
     p.n_src = s->n_nodes;
     p.n_trg = t->n;
@@ -129,6 +132,9 @@ s2d::Plan make_plan(int op, int mode, const s2d_curves *s, const s2d_targets *t,
     size_t off = 0;
     p.off_rec = off;
     off = align256(off + (size_t)p.n_sb * kSuperBlock * rec_bytes(op, mode));
+    p.off_rec64 = off;
+    if (mode == S2D_FP32C && s2d::near_fp64(op))
+        off = align256(off + (size_t)p.n_sb * kSuperBlock * rec_bytes(op, S2D_FP64));
     p.off_sub = off;
     if (mode == S2D_FP32C)
         off = align256(off + (size_t)p.n_sb * (kSuperBlock / kSubBlock) * sizeof(s2d::SubInfo));
@@ -173,15 +179,19 @@ int hip_fail(hipError_t e, const char *what) {
 
 int eval(int op, int mode, const s2d_curves *src, const s2d_targets *trg, double d, int32_t img_lo,
          int32_t img_hi, double mu, double *u, double *v, int accumulate, void *ws, size_t ws_bytes,
-         void *stream) {
+         void *stream, const double *tnx = nullptr, const double *tny = nullptr) {
     using namespace s2d;
     int rc = check_args(op, mode, src, trg, d, img_lo, img_hi, mu);
     if (rc != S2D_OK) return rc;
+    const int ncomp = (op == S2D_OP_SLP_PRESSURE || op == S2D_OP_DLP_PRESSURE) ? 1 : 2;
+    if (trg->n > 0) {
+        if (!u || (ncomp == 2 && !v)) return fail(S2D_EINVAL, "output arrays must not be NULL");
+        if (op == S2D_OP_SLP_TRACTION && (!tnx || !tny)) return fail(S2D_EINVAL, "traction needs target normals");
+    }
     int dev = 0;
     rc = current_device(&dev);
     if (rc != S2D_OK) return rc;
     if (trg->n == 0) return S2D_OK;
-    if (!u || !v) return fail(S2D_EINVAL, "outputs u, v must not be NULL");
     Plan p = make_plan(op, mode, src, trg, g_dev[dev].cus);
     const bool img0 = img_lo <= 0 && img_hi >= 0;
     p.self = op == S2D_OP_SLP && trg->on_curve != nullptr && img0;
@@ -221,6 +231,9 @@ int eval(int op, int mode, const s2d_curves *src, const s2d_targets *trg, double
     a.img_lo = img_lo;
     a.img_hi = img_hi;
     a.part = (double *)((char *)ws + p.off_part);
+    a.tnx = tnx;
+    a.tny = tny;
+    a.rec64 = (char *)ws + p.off_rec64;
     if (p.n_blocks > 0) {
         ProfEvent pe{op, nullptr, nullptr};
         if (g_prof_on) {
@@ -245,8 +258,15 @@ int eval(int op, int mode, const s2d_curves *src, const s2d_targets *trg, double
     f.n_splits = p.n_splits;
     f.n_trg = p.n_trg;
     f.n_src = p.n_src;
-    f.pref = op == S2D_OP_SLP ? 1.0 / (4.0 * M_PI * mu) : 1.0 / M_PI;
+    switch (op) {
+    case S2D_OP_SLP: f.pref = 1.0 / (4.0 * M_PI * mu); break;             // Eq. (S)
+    case S2D_OP_DLP: f.pref = 1.0 / M_PI; break;                          // Eq. (D)
+    case S2D_OP_SLP_PRESSURE: f.pref = 1.0 / (2.0 * M_PI); break;         // Eq. (Q)
+    case S2D_OP_DLP_PRESSURE: f.pref = mu / M_PI; break;                  // Eq. (P)
+    default: f.pref = -1.0 / M_PI; break;                                 // Eq. (K)
+    }
     f.accumulate = accumulate ? 1 : 0;
+    f.ncomp = ncomp;
     f.u = u;
     f.v = v;
     // on-curve targets with an empty or inconsistent curve come out NaN
@@ -306,6 +326,28 @@ S2D_API int stokes2d_dlp_eval(int mode, const s2d_curves *src, const s2d_targets
                               int32_t img_hi, double *u, double *v, int accumulate, void *ws, size_t ws_bytes,
                               void *stream) {
     return eval(S2D_OP_DLP, mode, src, trg, d, img_lo, img_hi, 1.0, u, v, accumulate, ws, ws_bytes, stream);
+}
+
+S2D_API int stokes2d_slp_pressure_eval(int mode, const s2d_curves *src, const s2d_targets *trg, double d,
+                                       int32_t img_lo, int32_t img_hi, double *p, int accumulate, void *ws,
+                                       size_t ws_bytes, void *stream) {
+    return eval(S2D_OP_SLP_PRESSURE, mode, src, trg, d, img_lo, img_hi, 1.0, p, nullptr, accumulate, ws, ws_bytes,
+                stream);
+}
+
+S2D_API int stokes2d_dlp_pressure_eval(int mode, const s2d_curves *src, const s2d_targets *trg, double d,
+                                       int32_t img_lo, int32_t img_hi, double mu, double *p, int accumulate,
+                                       void *ws, size_t ws_bytes, void *stream) {
+    return eval(S2D_OP_DLP_PRESSURE, mode, src, trg, d, img_lo, img_hi, mu, p, nullptr, accumulate, ws, ws_bytes,
+                stream);
+}
+
+S2D_API int stokes2d_slp_traction_eval(int mode, const s2d_curves *src, const s2d_targets *trg,
+                                       const double *trg_nx, const double *trg_ny, double d, int32_t img_lo,
+                                       int32_t img_hi, double *tx, double *ty, int accumulate, void *ws,
+                                       size_t ws_bytes, void *stream) {
+    return eval(S2D_OP_SLP_TRACTION, mode, src, trg, d, img_lo, img_hi, 1.0, tx, ty, accumulate, ws, ws_bytes,
+                stream, trg_nx, trg_ny);
 }
 
 S2D_API int stokes2d_profile_enable(int on) {

@@ -25,7 +25,22 @@ static hipError_t launch_t(const Plan &p, const PairArgs &a, hipStream_t st) {
 
 hipError_t launch_pair(const Plan &p, const PairArgs &a, hipStream_t st) {
     if (p.n_blocks <= 0) return hipSuccess;
-    const bool slp = p.op == S2D_OP_SLP, f64 = p.mode == S2D_FP64;
+    const bool f64 = p.mode == S2D_FP64;
+    // pressures and traction: one target per lane
+    switch (p.op) {
+    case S2D_OP_SLP_PRESSURE:
+        return f64 ? launch_t<S2D_OP_SLP_PRESSURE, S2D_FP64, 1>(p, a, st)
+                   : launch_t<S2D_OP_SLP_PRESSURE, S2D_FP32C, 1>(p, a, st);
+    case S2D_OP_DLP_PRESSURE:
+        return f64 ? launch_t<S2D_OP_DLP_PRESSURE, S2D_FP64, 1>(p, a, st)
+                   : launch_t<S2D_OP_DLP_PRESSURE, S2D_FP32C, 1>(p, a, st);
+    case S2D_OP_SLP_TRACTION:
+        return f64 ? launch_t<S2D_OP_SLP_TRACTION, S2D_FP64, 1>(p, a, st)
+                   : launch_t<S2D_OP_SLP_TRACTION, S2D_FP32C, 1>(p, a, st);
+    default:
+        break;
+    }
+    const bool slp = p.op == S2D_OP_SLP;
     switch (p.tpt) {
     case 1:
         if (slp) return f64 ? launch_t<S2D_OP_SLP, S2D_FP64, 1>(p, a, st) : launch_t<S2D_OP_SLP, S2D_FP32C, 1>(p, a, st);

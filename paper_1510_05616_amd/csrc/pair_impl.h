@@ -2,7 +2,9 @@
 // Pair-sum kernels: Stokeslet single layer (Section 2.1 Eq. (S), summed over
 // the near images of Section 3.1 Eq. (utotrep)) and stresslet double layer
 // (Eq. (D), summed as Eq. (Dnr)), for every target against every source node
-// of a curve set and its images n = img_lo..img_hi.
+// of a curve set and its images n = img_lo..img_hi; and, at free targets, the
+// pressures of both layers (Section 2.1 Eqs. (Q), (P)) and the single-layer
+// traction (Eq. (K)), which share the double layer's rational-term paths.
 //
 // Work decomposition.  A wavefront owns kWave * TPT targets (TPT per lane,
 // lane-strided so target loads are coalesced) and one source split (a run of
@@ -37,6 +39,8 @@
 // before the float log2 and its log is added back in double against the
 // superblock's FP64 density sum, so the float logs stay O(1) in magnitude.
 #include "s2d_internal.h"
+
+#include <type_traits>
 
 #include <climits>
 
@@ -227,6 +231,71 @@ __device__ __forceinline__ void dlp32_acc(double px, double py, const RecDlp32 &
     dlp32_r((float)(px - s.x), (float)(py - s.y), s, a);
 }
 
+// ---------------------------------------------------------------------------
+// rational operators (no logarithm): the double-layer velocity, the
+// pressures of both layers and the single-layer traction.  Each adds its
+// term for r = (rx, ry) to the accumulators (ax, ay); the pressures use ax
+// only.  m = (mx, my) is the target normal (traction only).
+// ---------------------------------------------------------------------------
+template <int OP>
+using Rec64Of = typename std::conditional<slp_sources(OP), RecSlp64, RecDlp64>::type;
+template <int OP>
+using Rec32Of = typename std::conditional<slp_sources(OP), RecSlp32, RecDlp32>::type;
+
+template <int OP>
+__device__ __forceinline__ void rat64(double px, double py, const Rec64Of<OP> &s, double mx, double my,
+                                      double &ax, double &ay) {
+    if constexpr (OP == S2D_OP_DLP) {
+        dlp64_pair(px, py, s, ax, ay);
+    } else {
+        const double rx = px - s.x, ry = py - s.y;
+        const double q = __builtin_fma(rx, rx, ry * ry);
+        const double iq = rcp64(q);
+        if constexpr (OP == S2D_OP_DLP_PRESSURE) {
+            // -(nu . tau) / q + 2 (r . nu)(r . tau) / q^2
+            const double rn = __builtin_fma(rx, s.nx, ry * s.ny);
+            const double rt = __builtin_fma(rx, s.tx, ry * s.ty);
+            const double nt = __builtin_fma(s.nx, s.tx, s.ny * s.ty);
+            ax = __builtin_fma(iq, __builtin_fma(2.0 * rn * rt, iq, -nt), ax);
+        } else if constexpr (OP == S2D_OP_SLP_PRESSURE) {
+            // (r . g) / q
+            ax = __builtin_fma(__builtin_fma(rx, s.gx, ry * s.gy), iq, ax);
+        } else {
+            // traction: r (r . g)(r . m) / q^2
+            const double rg = __builtin_fma(rx, s.gx, ry * s.gy);
+            const double rm = __builtin_fma(rx, mx, ry * my);
+            const double f = (rg * rm) * (iq * iq);
+            ax = __builtin_fma(rx, f, ax);
+            ay = __builtin_fma(ry, f, ay);
+        }
+    }
+}
+
+template <int OP>
+__device__ __forceinline__ void rat32(float rx, float ry, const Rec32Of<OP> &s, float mx, float my,
+                                      float (&a)[2]) {
+    if constexpr (OP == S2D_OP_DLP) {
+        dlp32_r(rx, ry, s, a);
+    } else {
+        const float q = __builtin_fmaf(rx, rx, ry * ry);
+        const float iq = __builtin_amdgcn_rcpf(q);
+        if constexpr (OP == S2D_OP_DLP_PRESSURE) {
+            const float rn = __builtin_fmaf(rx, s.nx, ry * s.ny);
+            const float rt = __builtin_fmaf(rx, s.tx, ry * s.ty);
+            const float nt = __builtin_fmaf(s.nx, s.tx, s.ny * s.ty);
+            a[0] = __builtin_fmaf(iq, __builtin_fmaf(2.0f * rn * rt, iq, -nt), a[0]);
+        } else if constexpr (OP == S2D_OP_SLP_PRESSURE) {
+            a[0] = __builtin_fmaf(__builtin_fmaf(rx, s.gx, ry * s.gy), iq, a[0]);
+        } else {
+            const float rg = __builtin_fmaf(rx, s.gx, ry * s.gy);
+            const float rm = __builtin_fmaf(rx, mx, ry * my);
+            const float f = (rg * rm) * (iq * iq);
+            a[0] = __builtin_fmaf(rx, f, a[0]);
+            a[1] = __builtin_fmaf(ry, f, a[1]);
+        }
+    }
+}
+
 // Offsets of the targets from sub-block origin si in FP32, and whether every
 // active target of the wave is at least kFarRadii sub-block radii away (then
 // r = offset - local source offset has a relative error of a few roundings).
@@ -281,6 +350,13 @@ __device__ __forceinline__ void pair_tile(const PairArgs &a, int64_t tile, int s
     }
     hlo = __builtin_amdgcn_readfirstlane(wave_min(hlo));
     hhi = __builtin_amdgcn_readfirstlane(wave_max(hhi));
+    double mx[TPT], my[TPT];                        // target normals (traction only)
+#pragma unroll
+    for (int k = 0; k < TPT; ++k) {
+        const bool tr = OP == S2D_OP_SLP_TRACTION && act[k];
+        mx[k] = tr ? a.tnx[ti[k]] : 0.0;
+        my[k] = tr ? a.tny[ti[k]] : 0.0;
+    }
 
     const int64_t sb0 = (int64_t)split * a.sb_per_split;
     const int64_t sb1 = min(sb0 + a.sb_per_split, a.n_sb);
@@ -313,13 +389,14 @@ __device__ __forceinline__ void pair_tile(const PairArgs &a, int64_t tile, int s
                             }
                         }
                     } else {
-                        const RecDlp64 *rec = (const RecDlp64 *)a.rec + j0;
+                        using R = Rec64Of<OP>;
+                        const R *rec = (const R *)a.rec + j0;
                         for (int u = 0; u < kSuperBlock; u += 4) {
 #pragma unroll
                             for (int q = 0; q < 4; ++q) {
-                                const RecDlp64 s = load_ro<RecDlp64>(rec, u + q);
+                                const R s = load_ro<R>(rec, u + q);
 #pragma unroll
-                                for (int k = 0; k < TPT; ++k) dlp64_pair(px[k], py[k], s, ux[k], uy[k]);
+                                for (int k = 0; k < TPT; ++k) rat64<OP>(px[k], py[k], s, mx[k], my[k], ux[k], uy[k]);
                             }
                         }
                     }
@@ -371,7 +448,8 @@ __device__ __forceinline__ void pair_tile(const PairArgs &a, int64_t tile, int s
                             }
                         }
                     } else {
-                        const RecDlp32 *rec = (const RecDlp32 *)a.rec + j0;
+                        using R = Rec32Of<OP>;
+                        const R *rec = (const R *)a.rec + j0;
                         for (int u = 0; u < kSuperBlock; u += kSubBlock) {
                             float ac[TPT][2][2], dx[TPT], dy[TPT];     // [source parity][x, y]
 #pragma unroll
@@ -382,16 +460,30 @@ __device__ __forceinline__ void pair_tile(const PairArgs &a, int64_t tile, int s
                             if (far_offsets<TPT>(si, px, py, act, dx, dy)) {
 #pragma unroll
                                 for (int q = 0; q < kSubBlock; ++q) {
-                                    const RecDlp32 s = load_ro<RecDlp32>(rec, u + q);
+                                    const R s = load_ro<R>(rec, u + q);
 #pragma unroll
-                                    for (int k = 0; k < TPT; ++k) dlp32_r(dx[k] - s.xl, dy[k] - s.yl, s, ac[k][q & 1]);
+                                    for (int k = 0; k < TPT; ++k)
+                                        rat32<OP>(dx[k] - s.xl, dy[k] - s.yl, s, (float)mx[k], (float)my[k], ac[k][q & 1]);
+                                }
+                            } else if constexpr (near_fp64(OP)) {
+                                // pressures and traction: near terms in FP64 (their sum can be
+                                // much smaller than the terms, so FP32 terms would lose digits)
+                                using R64 = Rec64Of<OP>;
+                                const R64 *rec64 = (const R64 *)a.rec64 + j0;
+#pragma unroll 4
+                                for (int q = 0; q < kSubBlock; ++q) {
+                                    const R64 s = load_ro<R64>(rec64, u + q);
+#pragma unroll
+                                    for (int k = 0; k < TPT; ++k) rat64<OP>(px[k], py[k], s, mx[k], my[k], ux[k], uy[k]);
                                 }
                             } else {
 #pragma unroll
                                 for (int q = 0; q < kSubBlock; ++q) {
-                                    const RecDlp32 s = load_ro<RecDlp32>(rec, u + q);
+                                    const R s = load_ro<R>(rec, u + q);
 #pragma unroll
-                                    for (int k = 0; k < TPT; ++k) dlp32_acc(px[k], py[k], s, ac[k][q & 1]);
+                                    for (int k = 0; k < TPT; ++k)
+                                        rat32<OP>((float)(px[k] - s.x), (float)(py[k] - s.y), s, (float)mx[k], (float)my[k],
+                                                  ac[k][q & 1]);
                                 }
                             }
 #pragma unroll
@@ -417,9 +509,9 @@ __device__ __forceinline__ void pair_tile(const PairArgs &a, int64_t tile, int s
                                 vx[k] += ok ? ax : 0.0; vy[k] += ok ? ay : 0.0;
                                 ux[k] += ok ? bx : 0.0; uy[k] += ok ? by : 0.0;
                             } else {
-                                const RecDlp64 s = load_ro<RecDlp64>(a.rec, j);
+                                const Rec64Of<OP> s = load_ro<Rec64Of<OP>>(a.rec, j);
                                 double ax = 0, ay = 0;
-                                dlp64_pair(px[k], py[k], s, ax, ay);
+                                rat64<OP>(px[k], py[k], s, mx[k], my[k], ax, ay);
                                 ux[k] += ok ? ax : 0.0; uy[k] += ok ? ay : 0.0;
                             }
                         } else {
@@ -430,10 +522,17 @@ __device__ __forceinline__ void pair_tile(const PairArgs &a, int64_t tile, int s
                                 slp32_acc(px[k], py[k], s, 1.0f, t4);
                                 t0 = t4[0] + t4[2];
                                 t1 = t4[1] + t4[3];
+                            } else if constexpr (near_fp64(OP)) {
+                                const Rec64Of<OP> s = load_ro<Rec64Of<OP>>(a.rec64, j);
+                                double ax = 0, ay = 0;
+                                rat64<OP>(px[k], py[k], s, mx[k], my[k], ax, ay);
+                                ux[k] += ok ? ax : 0.0;
+                                uy[k] += ok ? ay : 0.0;
+                                continue;
                             } else {
-                                const RecDlp32 s = load_ro<RecDlp32>(a.rec, j);
+                                const Rec32Of<OP> s = load_ro<Rec32Of<OP>>(a.rec, j);
                                 float t2[2] = {0.f, 0.f};
-                                dlp32_acc(px[k], py[k], s, t2);
+                                rat32<OP>((float)(px[k] - s.x), (float)(py[k] - s.y), s, (float)mx[k], (float)my[k], t2);
                                 t0 = t2[0];
                                 t1 = t2[1];
                             }

@@ -49,9 +49,28 @@ static hipError_t prep_t(const Plan &p, const s2d_curves *s, void *ws, hipStream
     return e;
 }
 
+// FP64 records of the sources at p.off_rec64 (FP32C pressures and traction)
+template <int OP>
+static hipError_t prep_rec64(const Plan &p, const s2d_curves *s, void *ws, hipStream_t st) {
+    const int64_t n_pad = p.n_sb * kSuperBlock;
+    if (n_pad == 0) return hipSuccess;
+    hipLaunchKernelGGL((prep_records<OP, S2D_FP64>), dim3((unsigned)((n_pad + 255) / 256)), dim3(256), 0, st,
+                       p.n_src, n_pad, s->x, s->y, s->nx, s->ny, s->w, s->fx, s->fy, (char *)ws + p.off_rec64,
+                       (SubInfo *)nullptr);
+    return hipGetLastError();
+}
+
 hipError_t launch_prep(const Plan &p, const s2d_curves *s, void *ws, hipStream_t st) {
+    if (p.mode == S2D_FP32C && near_fp64(p.op)) {
+        const hipError_t e = slp_sources(p.op) ? prep_rec64<S2D_OP_SLP_PRESSURE>(p, s, ws, st)
+                                               : prep_rec64<S2D_OP_DLP>(p, s, ws, st);
+        if (e != hipSuccess) return e;
+    }
     if (p.op == S2D_OP_SLP)
         return p.mode == S2D_FP64 ? prep_t<S2D_OP_SLP, S2D_FP64>(p, s, ws, st) : prep_t<S2D_OP_SLP, S2D_FP32C>(p, s, ws, st);
+    if (slp_sources(p.op))       // pressure and traction of the single layer: same records, no log sums
+        return p.mode == S2D_FP64 ? prep_t<S2D_OP_SLP_PRESSURE, S2D_FP64>(p, s, ws, st)
+                                  : prep_t<S2D_OP_SLP_PRESSURE, S2D_FP32C>(p, s, ws, st);
     return p.mode == S2D_FP64 ? prep_t<S2D_OP_DLP, S2D_FP64>(p, s, ws, st) : prep_t<S2D_OP_DLP, S2D_FP32C>(p, s, ws, st);
 }
 

@@ -21,7 +21,7 @@ __device__ __forceinline__ void prep_one64(int64_t j, int64_t n_src, const doubl
     const double X = v ? x[j] : 0.0, Y = v ? y[j] : 0.0;
     const double W = v ? w[j] : 0.0;
     const double FX = v ? fx[j] : 0.0, FY = v ? fy[j] : 0.0;
-    if (OP == S2D_OP_SLP) {
+    if (slp_sources(OP)) {
         ((RecSlp64 *)rec_out)[j] = RecSlp64{X, Y, W * FX, W * FY};
     } else {
         const double NX = v ? W * nx[j] : 0.0, NY = v ? W * ny[j] : 0.0;
@@ -57,7 +57,7 @@ __device__ __forceinline__ void prep_sub32(int64_t u, int64_t n_src, const doubl
         const double W = v ? w[j] : 0.0;
         const double FX = v ? fx[j] : 0.0, FY = v ? fy[j] : 0.0;
         const float xl = (float)(X - ox), yl = (float)(Y - oy);
-        if (OP == S2D_OP_SLP) {
+        if (slp_sources(OP)) {
             const double gx = W * FX, gy = W * FY;
             const double c = -0.34657359027997264;   // -ln(2)/2: natural log from log2
             ((RecSlp32 *)rec_out)[j] =

@@ -41,7 +41,7 @@ struct Plan {
     int64_t n_blocks;        // workgroups of the pair kernel
     bool self;               // targets carry on_curve/on_node and image 0 is in range
     // workspace carve-out (byte offsets)
-    size_t off_rec, off_sub, off_sbsum, off_part, off_self, off_kress, total;
+    size_t off_rec, off_rec64, off_sub, off_sbsum, off_part, off_self, off_kress, total;
 };
 
 struct PairArgs {
@@ -60,7 +60,18 @@ struct PairArgs {
     double d;
     int32_t img_lo, img_hi;
     double *part;             // [n_splits][2][n_trg]
+    const double *tnx, *tny;  // target unit normals (single-layer traction) or NULL
+    const void *rec64;        // FP32C pressures and traction: FP64 records for near sub-blocks
 };
+
+// FP32C pressures and traction evaluate near sub-blocks from FP64 records.
+constexpr bool near_fp64(int op) { return op > S2D_OP_DLP; }
+
+// Operators whose sources are force densities g = w f (single-layer records)
+// rather than double-layer densities (nu = w n, tau).
+constexpr bool slp_sources(int op) {
+    return op == S2D_OP_SLP || op == S2D_OP_SLP_PRESSURE || op == S2D_OP_SLP_TRACTION;
+}
 
 struct FinalArgs {
     const double *part;
@@ -70,6 +81,7 @@ struct FinalArgs {
     int64_t n_src;
     double pref;
     int accumulate;
+    int ncomp;                // 2: (u, v); 1: a scalar (pressure) written to u only
     double *u, *v;
     // DLP diagonal limit
     int dlp_diag;

@@ -45,7 +45,7 @@ __global__ __launch_bounds__(256) void finalize(FinalArgs a) {
                      a.fx, a.fy, sx, sy);
     const double ux = a.pref * sx, uy = a.pref * sy;
     a.u[i] = a.accumulate ? a.u[i] + ux : ux;
-    a.v[i] = a.accumulate ? a.v[i] + uy : uy;
+    if (a.ncomp == 2) a.v[i] = a.accumulate ? a.v[i] + uy : uy;
 }
 hipError_t launch_kress(const Plan &p, const s2d_curves *src, const s2d_targets *trg, void *ws,
                         hipStream_t st) {

@@ -293,6 +293,35 @@ def _vesicle_parts(rng_geom, rng_dens, n_ves, sizes, nus, area, h, d, K, gap=0.1
     return parts
 
 
+def fluid_points(prob: Problem, n: int, seed: int, gap: float = 0.02):
+    """n seeded free target points in one period of the channel (between the
+    walls, x in [0, d)), none within `gap` of a vesicle or wall node, e.g. for
+    evaluating pressures.  Returns (x, y)."""
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(seed)
+    w = prob.wall
+    lo_hi = []
+    for c in range(w.n_curves):
+        s = slice(w.curve_off[c], w.curve_off[c + 1])
+        order = np.argsort(w.x[s])
+        lo_hi.append((w.x[s][order], w.y[s][order]))
+    nodes = np.concatenate([np.stack([prob.ves.x, prob.ves.y], 1), np.stack([w.x, w.y], 1)])
+    tree = cKDTree(nodes)
+    xs, ys = [], []
+    got = 0
+    while got < n:
+        m = 2 * (n - got) + 64
+        x = rng.uniform(0.0, prob.d, m)
+        walls = [np.interp(x, cx, cy, period=prob.d) for cx, cy in lo_hi]
+        y0, y1 = np.minimum(*walls), np.maximum(*walls)
+        y = y0 + rng.uniform(0.0, 1.0, m) * (y1 - y0)
+        keep = tree.query(np.stack([x, y], 1))[0] > gap
+        xs.append(x[keep])
+        ys.append(y[keep])
+        got += int(keep.sum())
+    return np.concatenate(xs)[:n], np.concatenate(ys)[:n]
+
+
 AREA_C1 = math.pi * 0.3 * 0.17          # the config-1 vesicle area, 0.160221
 
 

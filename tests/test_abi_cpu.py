@@ -109,3 +109,25 @@ def test_batch_tuned_is_host_only_and_reports_the_default(L, tmp_path, monkeypat
         assert shape["tuned"] is False
         assert shape["targets_per_lane"] in (1, 2, 4)
         assert shape["superblocks_per_split"] > 0 and shape["waves_per_cu"] > 0
+
+
+def test_pressure_and_traction_argument_checks(L):
+    import paper_1510_05616_amd as s2d
+    cs, ts = _structs()
+    cs_on, ts_on = _structs(on=True)
+    out = ctypes.c_void_p(0x2000)
+    ws = ctypes.c_void_p(0x3000)
+    by = ctypes.byref
+    # on-curve targets are not supported for the singular kernels
+    assert L.stokes2d_slp_pressure_eval(0, by(cs), by(ts_on), 1.0, 0, 0, out, 0, ws, 1 << 20, None) == s2d.S2D_EINVAL
+    assert "free targets" in s2d.stokes2d_last_error()
+    # double-layer pressure needs mu > 0
+    assert L.stokes2d_dlp_pressure_eval(0, by(cs), by(ts), 1.0, 0, 0, 0.0, out, 0, ws, 1 << 20, None) == s2d.S2D_EINVAL
+    # traction needs the target normals
+    assert L.stokes2d_slp_traction_eval(0, by(cs), by(ts), None, out, 1.0, 0, 0, out, out, 0, ws, 1 << 20,
+                                        None) == s2d.S2D_EINVAL
+    # unknown op code
+    assert L.stokes2d_workspace_size(5, 0, by(cs), by(ts)) == 0
+    for op in (s2d.S2D_OP_SLP_PRESSURE, s2d.S2D_OP_DLP_PRESSURE, s2d.S2D_OP_SLP_TRACTION):
+        assert L.stokes2d_workspace_size(op, 1, by(cs), by(ts)) > 0
+        assert L.stokes2d_workspace_size(op, 1, by(cs_on), by(ts_on)) == 0
