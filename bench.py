@@ -142,6 +142,88 @@ def _time(fn, reps=3):
     return a.elapsed_time(b) / reps
 
 
+# algorithmic flops per pair (FMA = 2, reciprocal = 1) of the pressure and
+# traction terms: r (2), |r|^2 (3), 1/|r|^2 (1), then
+#   single-layer pressure: r.g (3), accumulate (2)                          = 11
+#   double-layer pressure: r.nu, r.tau (6), 2 (r.nu)(r.tau) (2), two FMAs (4) = 18
+#   single-layer traction: r.g, r.m (6), products (3), accumulate (4)       = 19
+F1_FLOPS = {"slp_pressure": 11, "dlp_pressure": 18, "slp_traction": 19}
+
+
+def f1_section(prob, reps=5):
+    """Pressure and traction at the free targets of the 128k channel: 128,000
+    seeded fluid points plus the 64 side-wall points (single-layer pressure
+    and traction from the 96,000 vesicle nodes, double-layer pressure from
+    the 32,000 wall nodes, images -1..1), FP32C and FP64, with the FP64 oracle
+    on a seeded sample of 256 targets."""
+    import torch
+    import oracle
+    import synth
+    import paper_1510_05616_amd as s2d
+    fx, fy = synth.fluid_points(prob, 128000, seed=11)
+    side = prob.trg.kind == 2
+    x = np.concatenate([fx, prob.trg.x[side]])
+    y = np.concatenate([fy, prob.trg.y[side]])
+    n = x.shape[0]
+    th = np.random.default_rng(12).uniform(0.0, 2 * np.pi, n)
+    mxn, myn = np.cos(th), np.sin(th)
+    f64 = dict(dtype=torch.float64, device="cuda")
+    tg = s2d.Targets(x, y)
+    ves, wall = s2d.Curves(prob.ves), s2d.Curves(prob.wall)
+    mx, my = torch.as_tensor(mxn, **f64), torch.as_tensor(myn, **f64)
+    o1, o2 = torch.zeros(n, **f64), torch.zeros(n, **f64)
+    nws = max(s2d.stokes2d_workspace_size(op, mode, src, tg) for mode in (0, 1)
+              for op, src in ((s2d.S2D_OP_SLP_PRESSURE, ves), (s2d.S2D_OP_DLP_PRESSURE, wall),
+                              (s2d.S2D_OP_SLP_TRACTION, ves)))
+    ws = torch.empty(nws, dtype=torch.uint8, device="cuda")
+    nv, nw = prob.ves.n_nodes, prob.wall.n_nodes
+    ops = {
+        "slp_pressure": (s2d.S2D_OP_SLP_PRESSURE, n * nv * 3,
+                         lambda m: s2d.stokes2d_slp_pressure_eval(m, ves, tg, prob.d, -1, 1, o1, 0, ws)),
+        "dlp_pressure": (s2d.S2D_OP_DLP_PRESSURE, n * nw * 3,
+                         lambda m: s2d.stokes2d_dlp_pressure_eval(m, wall, tg, prob.d, -1, 1, prob.mu, o1, 0, ws)),
+        "slp_traction": (s2d.S2D_OP_SLP_TRACTION, n * nv * 3,
+                         lambda m: s2d.stokes2d_slp_traction_eval(m, ves, tg, mx, my, prob.d, -1, 1, o1, o2, 0, ws)),
+    }
+    idx = np.random.default_rng(13).choice(n, 256, replace=False)
+    xs, ys = x[idx], y[idx]
+    t0 = time.time()
+    ref = {"slp_pressure": (oracle.slp_pressure(prob.ves, xs, ys, prob.d, -1, 1),),
+           "dlp_pressure": (oracle.dlp_pressure(prob.wall, xs, ys, prob.d, -1, 1, prob.mu),),
+           "slp_traction": oracle.slp_traction(prob.ves, xs, ys, mxn[idx], myn[idx], prob.d, -1, 1)}
+    t_oracle = time.time() - t0
+    res = {"workload": "128,000 fluid points + 64 side-wall points of the 128k channel (free targets), "
+                       "vesicle single-layer pressure and traction, wall double-layer pressure, images -1..1",
+           "n_targets": n, "flops_per_pair": F1_FLOPS,
+           "oracle_sample": {"targets": 256, "seconds": t_oracle, "threads": oracle.num_threads()}}
+    for name, mode in (("f32", s2d.S2D_FP32C), ("f64", s2d.S2D_FP64)):
+        out = {}
+        for op, (code, pairs, fn) in ops.items():
+            fn(mode)
+            torch.cuda.synchronize()
+            s2d.stokes2d_profile_read(code)
+            s2d.stokes2d_profile_enable(True)
+            ms = _time(lambda: fn(mode), reps=reps)
+            s2d.stokes2d_profile_enable(False)
+            kms, kn = s2d.stokes2d_profile_read(code)
+            kms /= max(kn, 1)
+            got = [o1.cpu().numpy()[idx]] + ([o2.cpu().numpy()[idx]] if op == "slp_traction" else [])
+            e = max(float(np.abs(g - r).max()) for g, r in zip(got, ref[op])) / \
+                max(float(np.abs(r).max()) for r in ref[op])
+            tf = F1_FLOPS[op] * pairs / (kms * 1e-3) / 1e12
+            out[op] = {"ms": ms, "kernel_ms": kms, "pairs": pairs, "value": pairs / (ms * 1e-3),
+                       "unit": "pair-evals/s", "achieved_tflops": tf, "peak_tflops": PEAK[name] / 1e12,
+                       "frac": tf * 1e12 / PEAK[name], "rel_err_vs_oracle": e}
+            log(f"f1 {name} {op}: {ms:.3f} ms ({pairs / (ms * 1e-3):.3e} pairs/s), kernel {kms:.3f} ms, "
+                f"{tf:.1f} TFLOP/s, E={e:.2e}")
+        res[name] = out
+    pairs_sample = 256 * (2 * nv + nw) * 3
+    res["cpu_baseline"] = {"value": pairs_sample / t_oracle, "unit": "pair-evals/s", "kind": "oracle",
+                           "cores": oracle.num_threads(), "sample": "256 seeded targets x the three operators "
+                           "x all sources x 3 images (FP64)"}
+    return res
+
+
 def batch_section():
     """Config 4: 256 independent channel instances (1-40 vesicles of
     32-256 nodes, 256-4096 wall nodes per wall) evaluated by one batched call
@@ -286,6 +368,7 @@ def main():
                     help="targets of the workload the FP64 oracle evaluates on the host (0: skip)")
     ap.add_argument("--near", type=int, default=1, help="run the near-field correction section (0: skip)")
     ap.add_argument("--batch", type=int, default=1, help="run the batched-instances section (0: skip)")
+    ap.add_argument("--f1", type=int, default=1, help="run the pressure/traction section (0: skip)")
     ap.add_argument("--copy-probe", action="store_true", help="only copy 1 GiB on the device and exit")
     args = ap.parse_args()
     if args.copy_probe:
@@ -351,6 +434,7 @@ def main():
         log(f"oracle: {dt:.1f}s on {cpu['cores']} threads, {cpu['value']:.3e} pairs/s; "
             f"rel err f32={errs['f32']:.2e} f64={errs['f64']:.2e}")
 
+    f1_res = f1_section(prob) if args.f1 and args.config == 3 else None
     near_res = near_section() if args.near else None
     batch_res = batch_section() if args.batch else None
 
@@ -371,6 +455,7 @@ def main():
                  "dtype": "f64", "roofline": f64["roofline"]},
         "kernel_ms": {"f32_slp_pair": f32["slp_pair_ms"], "f32_dlp_pair": f32["dlp_pair_ms"],
                       "f64_slp_pair": f64["slp_pair_ms"], "f64_dlp_pair": f64["dlp_pair_ms"]},
+        "pressure_traction": f1_res,
         "near": near_res,
         "batch": batch_res,
     }
