@@ -9,7 +9,9 @@ The pair sums and Kress's self quadrature are plain C (`stokes_oracle.c`,
 OpenMP over targets, IEEE double, Neumaier summation); this module compiles
 that file with gcc and marshals numpy arrays into it.  `near.py` holds the
 numpy FP64 references for the near-field extension (FFT-upsampled trapezoid
-quadrature, target features, and the MLP forward/backward pass).
+quadrature, target features, and the MLP forward/backward pass); `els.py`
+the dense assembly and Schur-complement solve of the periodization system of
+an empty channel cell.
 
 Pins (tests/test_oracle_*.py): Kress weights exact on cos(m t) and summing to
 zero; the circle of constant density; the double-layer translation identity

@@ -157,7 +157,7 @@ def _wall(h, hp, hpp, d, n, upper: bool):
         nx, ny = -yp / sp, 1.0 / sp
     else:                     # normal pointing down (out of the fluid)
         nx, ny = yp / sp, -1.0 / sp
-    kappa = -(ypp * ny) / sp ** 3          # x'' = (0, y'')
+    kappa = -(ypp * ny) / sp ** 2          # -(x'' . n) / |x'|^2 with x'' = (0, y'')
     w = (d / n) * sp
     th = 2.0 * np.pi * xs / d
     return xs, y, nx, ny, w, kappa, th
@@ -291,6 +291,19 @@ def _vesicle_parts(rng_geom, rng_dens, n_ves, sizes, nus, area, h, d, K, gap=0.1
         fx, fy = _density(rng_dens, t, K)
         parts.append((x, y, nx, ny, w, kap, fx, fy))
     return parts
+
+
+def make_channel(n_wall: int, n_side: int, profile: str = "sin1", d: float = 2 * np.pi):
+    """One period of an empty symmetric channel for the periodization system:
+    walls U (y = h(x), normal up) and D (y = -h(x), normal down) with n_wall
+    trapezoid nodes each on x in [0, d) (zero densities), and the n_side
+    Gauss-Legendre heights of the side walls L (x = 0) and R (x = d).
+    Returns (walls, side_y, d)."""
+    h, hp, hpp = wall_profile(profile)
+    walls = concat_curves([(*_wall(h, hp, hpp, d, n_wall, up)[:6], np.zeros(n_wall), np.zeros(n_wall))
+                           for up in (True, False)])
+    xs, ys = _side_targets(h, d, n_side)
+    return walls, ys[:n_side].copy(), float(d)
 
 
 def fluid_points(prob: Problem, n: int, seed: int, gap: float = 0.02):
