@@ -177,6 +177,58 @@ S2D_API int stokes2d_slp_traction_eval(int mode, const s2d_curves *src, const s2
                                        double *tx, double *ty, int accumulate,
                                        void *ws, size_t ws_bytes, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Periodization system of one channel cell (Section 2.2, Eqs. (urep)-(bsys);
+ * Nystrom discretisation, Section 2.3; block solve, Section 5.1).
+ *
+ * The velocity in the cell is the wall double layer of density tau summed
+ * over the images |n| <= 1 plus M Stokeslets c_m at proxy points on a circle
+ * around the cell; the pressure correspondingly.  Rows: the velocity data v
+ * at the N wall nodes (the n = 0 term with the -1/2 jump and the diagonal
+ * limit), then at the K side heights the velocity difference u(R) - u(L) and
+ * the traction difference T(R) - T(L) for the side normal (1, 0), R = L + d:
+ *     [A B; C Q] [tau; c] = [v; g],
+ * solved as S = Q - C A^-1 B, c = S^+ (g - C A^-1 v), tau = A^-1 (v - B c),
+ * S^+ the pseudo-inverse over the singular values above rcond * s_max.
+ * Every 2-vector is interleaved (x, y) per node: v, tau [2N], g [4K] (the K
+ * velocity differences, then the K traction differences), c [2M].  Matrices
+ * are column-major with leading dimension = rows: A 2N x 2N, B 2N x 2M,
+ * C 4K x 2N, Q 4K x 2M.  The pair kernels of Eqs. (D), (S), (K) and the
+ * double-layer traction of Eq. (T) fill them on the GPU; LU, GEMM and SVD run
+ * in rocSOLVER / rocBLAS, which may allocate their own device scratch.
+ * ------------------------------------------------------------------------- */
+typedef struct s2d_cell {
+    s2d_curves walls;             /* the wall nodes of one period (x, y, nx, ny, w, kappa; the
+                                     densities are not used); normals point out of the fluid */
+    int32_t n_side;               /* K >= 1 collocation heights on each side wall */
+    const double *side_y;         /* [K] device */
+    double x_left;                /* L at x = x_left, R at x = x_left + d */
+    int32_t n_proxy;              /* M >= 1 proxy Stokeslets, equispaced from angle 0 */
+    double proxy_cx, proxy_cy, proxy_r;
+    double d, mu;                 /* period > 0, viscosity > 0 */
+} s2d_cell;
+
+/* Workspace bytes of a factored cell (0 on bad arguments): the LU of A,
+ * A^-1 B, C, the pseudo-inverse of S and scratch, about (2N)^2 * 8 bytes. */
+S2D_API size_t stokes2d_cell_workspace_size(const s2d_cell *cell);
+
+/* Fills the four blocks into caller buffers (any may be NULL to skip). */
+S2D_API int stokes2d_cell_assemble(const s2d_cell *cell, double *A, double *B, double *C, double *Q,
+                                   void *stream);
+
+/* Assembles and factors the system into ws; waits for `stream` (it reads
+ * the LU and SVD status).  Not capturable.  rcond: relative cut-off of S^+
+ * (the paper gives none; 1e-8 is about the square root of the noise level
+ * of S).  S2D_EHIP with a message if A is singular or the SVD fails. */
+S2D_API int stokes2d_cell_factor(const s2d_cell *cell, double rcond, void *ws, size_t ws_bytes,
+                                 void *stream);
+
+/* Solves for one right-hand side with a workspace factored by
+ * stokes2d_cell_factor (same cell): v [2N], g [4K] in; tau [2N], c [2M]
+ * out (device FP64).  Asynchronous on `stream`. */
+S2D_API int stokes2d_cell_solve(const s2d_cell *cell, const double *v, const double *g, double *tau,
+                                double *c, void *ws, size_t ws_bytes, void *stream);
+
 /* One independent channel instance of a batched evaluation: the single
  * layer of the vesicles plus the double layer of the walls, images -1..1,
  * at the same n target points (trg_ves and trg_wall describe the same points;

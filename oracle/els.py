@@ -203,29 +203,3 @@ def field(walls, tau, px, py, c, d, mu, X, Y):
     u += np.einsum("tsab,sb->ta", stokeslet(X, Y, px, py, mu), np.stack([cx, cy], 1))
     p += np.einsum("tsb,sb->t", stokeslet_pressure(X, Y, px, py), np.stack([cx, cy], 1))
     return u, p
-
-
-def poiseuille(X, Y, alpha, mu):
-    """u = (alpha y^2, 0), p = 2 alpha mu x: a Stokes solution with pressure
-    gain 2 alpha mu d per period (Section 4.1 writes p = alpha mu x, which
-    does not satisfy -mu Lap u + grad p = 0; the factor 2 is restored)."""
-    return np.stack([alpha * np.asarray(Y) ** 2, np.zeros_like(Y)], -1), 2 * alpha * mu * np.asarray(X)
-
-
-def poiseuille_data(walls, side_y, d, alpha, mu, x_left=0.0):
-    """Right-hand sides (v, g) for which the Poiseuille flow solves the cell
-    problem: v = u_e on the walls; g = [u_e(R) - u_e(L); T(u_e, p_e)(R) -
-    T(u_e, p_e)(L)] with the side normal (1, 0)."""
-    ue, _ = poiseuille(walls.x, walls.y, alpha, mu)
-    v = ue.reshape(-1)
-    K = len(side_y)
-    gu = np.zeros(2 * K)                          # u_e does not depend on x
-
-    def traction(X, Y):
-        # grad u: du1/dy = 2 alpha y, all else 0; T = -p n + mu (grad u + grad u^T) n, n = (1, 0)
-        _, p = poiseuille(X, Y, alpha, mu)
-        return np.stack([-p, mu * 2 * alpha * np.asarray(Y)], -1)
-
-    xl = np.full(K, x_left)
-    gt = (traction(xl + d, side_y) - traction(xl, side_y)).reshape(-1)
-    return v, np.concatenate([gu, gt])

@@ -50,7 +50,8 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     for p in procs:
         _wait(p)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs,
+           "-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocsolver", "-lrocblas"]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     return LIB

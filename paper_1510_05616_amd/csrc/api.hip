@@ -350,6 +350,99 @@ S2D_API int stokes2d_slp_traction_eval(int mode, const s2d_curves *src, const s2
                 stream, trg_nx, trg_ny);
 }
 
+// ---------------------------------------------------------------------------
+// periodization system of one channel cell
+// ---------------------------------------------------------------------------
+namespace {
+
+int check_cell(const s2d_cell *c, s2d::CellArgs *g) {
+    if (!c) return fail(S2D_EINVAL, "cell must not be NULL");
+    const s2d_curves &w = c->walls;
+    if (w.n_nodes < 1 || 2 * w.n_nodes > INT32_MAX / 2) return fail(S2D_EINVAL, "cell walls: n_nodes out of range");
+    if (!w.x || !w.y || !w.nx || !w.ny || !w.w || !w.kappa)
+        return fail(S2D_EINVAL, "cell walls need x, y, nx, ny, w and kappa");
+    if (c->n_side < 1 || c->n_side > 4096 || !c->side_y) return fail(S2D_EINVAL, "cell: n_side in 1..4096 and side_y set");
+    if (c->n_proxy < 1 || c->n_proxy > 8192) return fail(S2D_EINVAL, "cell: n_proxy in 1..8192");
+    if (!(std::isfinite(c->d) && c->d > 0.0)) return fail(S2D_EINVAL, "cell: d must be finite and > 0");
+    if (!(std::isfinite(c->mu) && c->mu > 0.0)) return fail(S2D_EINVAL, "cell: mu must be finite and > 0");
+    if (!(std::isfinite(c->proxy_r) && c->proxy_r > 0.0) || !std::isfinite(c->proxy_cx) ||
+        !std::isfinite(c->proxy_cy) || !std::isfinite(c->x_left))
+        return fail(S2D_EINVAL, "cell: proxy circle and x_left must be finite, proxy_r > 0");
+    g->n_wall = w.n_nodes;
+    g->x = w.x;
+    g->y = w.y;
+    g->nx = w.nx;
+    g->ny = w.ny;
+    g->w = w.w;
+    g->kap = w.kappa;
+    g->K = c->n_side;
+    g->side_y = c->side_y;
+    g->xl = c->x_left;
+    g->M = c->n_proxy;
+    g->cx = c->proxy_cx;
+    g->cy = c->proxy_cy;
+    g->R = c->proxy_r;
+    g->d = c->d;
+    g->mu = c->mu;
+    return S2D_OK;
+}
+
+int check_cell_ws(const s2d::CellArgs &g, void *ws, size_t ws_bytes) {
+    const size_t need = s2d::cell_layout(g).total;
+    if (!ws) return fail(S2D_EWORKSPACE, "workspace is NULL");
+    if (ws_bytes < need) return fail(S2D_EWORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+    if (((uintptr_t)ws & 255) != 0) return fail(S2D_EWORKSPACE, "workspace must be 256-byte aligned");
+    return S2D_OK;
+}
+
+}  // namespace
+
+S2D_API size_t stokes2d_cell_workspace_size(const s2d_cell *cell) {
+    s2d::CellArgs g{};
+    if (check_cell(cell, &g) != S2D_OK) return 0;
+    return s2d::cell_layout(g).total;
+}
+
+S2D_API int stokes2d_cell_assemble(const s2d_cell *cell, double *A, double *B, double *C, double *Q, void *stream) {
+    s2d::CellArgs g{};
+    int rc = check_cell(cell, &g);
+    if (rc != S2D_OK) return rc;
+    int dev = 0;
+    rc = current_device(&dev);
+    if (rc != S2D_OK) return rc;
+    const hipError_t e = s2d::cell_fill(g, A, B, C, Q, (hipStream_t)stream);
+    return e == hipSuccess ? S2D_OK : hip_fail(e, "cell assemble");
+}
+
+S2D_API int stokes2d_cell_factor(const s2d_cell *cell, double rcond, void *ws, size_t ws_bytes, void *stream) {
+    s2d::CellArgs g{};
+    int rc = check_cell(cell, &g);
+    if (rc != S2D_OK) return rc;
+    if (!(std::isfinite(rcond) && rcond >= 0.0 && rcond < 1.0)) return fail(S2D_EINVAL, "rcond must be in [0, 1)");
+    rc = check_cell_ws(g, ws, ws_bytes);
+    if (rc != S2D_OK) return rc;
+    int dev = 0;
+    rc = current_device(&dev);
+    if (rc != S2D_OK) return rc;
+    const std::string err = s2d::cell_factor(g, rcond, ws, (hipStream_t)stream);
+    return err.empty() ? S2D_OK : fail(S2D_EHIP, err);
+}
+
+S2D_API int stokes2d_cell_solve(const s2d_cell *cell, const double *v, const double *gv, double *tau, double *c,
+                                void *ws, size_t ws_bytes, void *stream) {
+    s2d::CellArgs g{};
+    int rc = check_cell(cell, &g);
+    if (rc != S2D_OK) return rc;
+    if (!v || !gv || !tau || !c) return fail(S2D_EINVAL, "v, g, tau and c must not be NULL");
+    rc = check_cell_ws(g, ws, ws_bytes);
+    if (rc != S2D_OK) return rc;
+    int dev = 0;
+    rc = current_device(&dev);
+    if (rc != S2D_OK) return rc;
+    const std::string err = s2d::cell_solve(g, v, gv, tau, c, ws, (hipStream_t)stream);
+    return err.empty() ? S2D_OK : fail(S2D_EHIP, err);
+}
+
 S2D_API int stokes2d_profile_enable(int on) {
     std::lock_guard<std::mutex> lk(g_mu);
     g_prof_on = on != 0;

@@ -1,0 +1,345 @@
+// Periodization system of one channel cell on the GPU (Section 2.2,
+// Eqs. (urep)-(bsys); Nystrom discretisation, Section 2.3; block solve,
+// Section 5.1).
+//
+// Unknowns: the double-layer density tau at the N wall nodes (interleaved
+// (x, y) per node) and the coefficients c of M proxy Stokeslets on a circle
+// around the cell.  Rows: the wall velocity data at the N wall nodes
+// (-1/2 tau + the double layer over the images |n| <= 1, the n = 0 self term
+// by the diagonal limit), then at K side heights the velocity difference
+// R - L and the traction difference R - L (side normal (1, 0)), where only
+// the far wall copies (R against the walls shifted by -d, L against +d) and
+// the proxies remain after the near interactions cancel (Eqs. (BIEgu),
+// (BIEgT)).
+//
+// The four blocks are filled by one kernel each (one thread per 2 x 2 node
+// block, column-major for the solver).  Factor: LU of A (rocSOLVER), X =
+// A^-1 B, S = Q - C X (rocBLAS GEMM), SVD of the small S and its truncated
+// pseudo-inverse.  Solve: y = A^-1 v, c = S^+ (g - C y), tau = y - X c.
+#include "s2d_internal.h"
+
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cmath>
+#include <mutex>
+#include <string>
+
+namespace s2d {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// 2 x 2 kernel blocks, o[2 a + b] = K_ab, r = target - source
+
+__device__ __forceinline__ void stresslet_blk(double rx, double ry, double nx, double ny, double (&o)[4]) {
+    const double q = rx * rx + ry * ry;
+    const double f = (rx * nx + ry * ny) / (q * q * kPi);
+    o[0] = rx * rx * f;
+    o[1] = rx * ry * f;
+    o[2] = o[1];
+    o[3] = ry * ry * f;
+}
+
+__device__ __forceinline__ void stokeslet_blk(double rx, double ry, double mu, double (&o)[4]) {
+    const double q = rx * rx + ry * ry;
+    const double s = 1.0 / (4.0 * kPi * mu);
+    const double l = -0.5 * log(q);
+    o[0] = s * (l + rx * rx / q);
+    o[1] = s * (rx * ry / q);
+    o[2] = o[1];
+    o[3] = s * (l + ry * ry / q);
+}
+
+// traction of the Stokeslet at a target with normal m (Eq. (K))
+__device__ __forceinline__ void stokeslet_traction_blk(double rx, double ry, double mx, double my, double (&o)[4]) {
+    const double q = rx * rx + ry * ry;
+    const double f = -(rx * mx + ry * my) / (q * q * kPi);
+    o[0] = rx * rx * f;
+    o[1] = rx * ry * f;
+    o[2] = o[1];
+    o[3] = ry * ry * f;
+}
+
+// traction of the double-layer velocity and pressure pair (Eqs. (D), (P)) of
+// a source with normal n at a target with normal m (Eq. (T), its dipole
+// functions paired as the stress of the pair: a = r.n/r^2 goes with the
+// target-normal term, b = r.m/r^2 with the source-normal term)
+__device__ __forceinline__ void stresslet_traction_blk(double rx, double ry, double mx, double my, double nx,
+                                                       double ny, double mu, double (&o)[4]) {
+    const double q = rx * rx + ry * ry;
+    const double a = (rx * nx + ry * ny) / q;
+    const double b = (rx * mx + ry * my) / q;
+    const double c1 = ((nx * mx + ny * my) / q - 8.0 * a * b) / q;
+    const double r[2] = {rx, ry}, m[2] = {mx, my}, n[2] = {nx, ny};
+    const double s = mu / kPi;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+            o[2 * i + k] = s * (c1 * r[i] * r[k] + (i == k ? a * b : 0.0) + m[i] * n[k] / q + b * n[i] * r[k] / q +
+                                a * r[i] * m[k] / q);
+}
+
+__device__ __forceinline__ void proxy_point(const CellArgs &g, int m, double &px, double &py) {
+    const double th = 2.0 * kPi * (double)m / (double)g.M;
+    px = g.cx + g.R * cos(th);
+    py = g.cy + g.R * sin(th);
+}
+
+__device__ __forceinline__ void put(double *A, int64_t ld, int64_t row0, int64_t col0, const double (&o)[4]) {
+    A[row0 + col0 * ld] = o[0];
+    A[row0 + 1 + col0 * ld] = o[2];
+    A[row0 + (col0 + 1) * ld] = o[1];
+    A[row0 + 1 + (col0 + 1) * ld] = o[3];
+}
+
+// A: -1/2 I + sum_{|n| <= 1} D(x_i, y_j + n d) w_j, diagonal limit at n = 0
+__global__ __launch_bounds__(256) void cell_fill_A(CellArgs g, double *A) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t N = g.n_wall;
+    if (t >= N * N) return;
+    const int64_t i = t % N, j = t / N;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const double nx = g.nx[j], ny = g.ny[j], w = g.w[j];
+    for (int n = -1; n <= 1; ++n) {
+        double o[4];
+        if (n == 0 && i == j) {
+            // -(kappa / 2 pi) t t^T, t t^T = I - n n^T
+            const double k = -g.kap[j] / (2.0 * kPi);
+            o[0] = k * (1.0 - nx * nx);
+            o[1] = k * (-nx * ny);
+            o[2] = o[1];
+            o[3] = k * (1.0 - ny * ny);
+        } else {
+            stresslet_blk(g.x[i] - g.x[j] - n * g.d, g.y[i] - g.y[j], nx, ny, o);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[e] += o[e] * w;
+    }
+    if (i == j) {
+        acc[0] -= 0.5;
+        acc[3] -= 0.5;
+    }
+    put(A, 2 * N, 2 * i, 2 * j, acc);
+}
+
+// B: the proxy Stokeslets at the wall nodes
+__global__ __launch_bounds__(256) void cell_fill_B(CellArgs g, double *B) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t N = g.n_wall;
+    if (t >= N * g.M) return;
+    const int64_t i = t % N;
+    const int m = (int)(t / N);
+    double px, py, o[4];
+    proxy_point(g, m, px, py);
+    stokeslet_blk(g.x[i] - px, g.y[i] - py, g.mu, o);
+    put(B, 2 * N, 2 * i, 2 * m, o);
+}
+
+// C: velocity (rows 2k + a) and traction (rows 2K + 2k + a) differences of
+// the far wall copies, R against the walls shifted by -d, L by +d
+__global__ __launch_bounds__(256) void cell_fill_C(CellArgs g, double *C) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t K = g.K;
+    if (t >= K * g.n_wall) return;
+    const int64_t k = t % K, j = t / K;
+    const double yk = g.side_y[k], w = g.w[j], nx = g.nx[j], ny = g.ny[j];
+    const double rxR = g.xl + g.d - (g.x[j] - g.d), rxL = g.xl - (g.x[j] + g.d), ry = yk - g.y[j];
+    double a[4], b[4], o[4];
+    stresslet_blk(rxR, ry, nx, ny, a);
+    stresslet_blk(rxL, ry, nx, ny, b);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) o[e] = (a[e] - b[e]) * w;
+    put(C, 4 * K, 2 * k, 2 * j, o);
+    stresslet_traction_blk(rxR, ry, 1.0, 0.0, nx, ny, g.mu, a);
+    stresslet_traction_blk(rxL, ry, 1.0, 0.0, nx, ny, g.mu, b);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) o[e] = (a[e] - b[e]) * w;
+    put(C, 4 * K, 2 * K + 2 * k, 2 * j, o);
+}
+
+// Q: the same differences of the proxy Stokeslets
+__global__ __launch_bounds__(256) void cell_fill_Q(CellArgs g, double *Q) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t K = g.K;
+    if (t >= K * g.M) return;
+    const int64_t k = t % K;
+    const int m = (int)(t / K);
+    double px, py, a[4], b[4], o[4];
+    proxy_point(g, m, px, py);
+    const double yk = g.side_y[k];
+    stokeslet_blk(g.xl + g.d - px, yk - py, g.mu, a);
+    stokeslet_blk(g.xl - px, yk - py, g.mu, b);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) o[e] = a[e] - b[e];
+    put(Q, 4 * K, 2 * k, 2 * m, o);
+    stokeslet_traction_blk(g.xl + g.d - px, yk - py, 1.0, 0.0, a);
+    stokeslet_traction_blk(g.xl - px, yk - py, 1.0, 0.0, b);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) o[e] = a[e] - b[e];
+    put(Q, 4 * K, 2 * K + 2 * k, 2 * m, o);
+}
+
+// P (n x m) = V diag(1/s) U^T over the singular values above rcond * s_0,
+// from U (m x r, ld m) and V^T (r x n, ld r), r = min(m, n)
+__global__ __launch_bounds__(256) void cell_pinv(int m, int n, int r, const double *sv, const double *U,
+                                                 const double *Vt, double rcond, double *P) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)m * n) return;
+    const int j = (int)(t % n), i = (int)(t / n);
+    const double cut = rcond * sv[0];
+    double acc = 0.0;
+    for (int l = 0; l < r; ++l)
+        if (sv[l] > cut) acc += Vt[l + (int64_t)j * r] * U[i + (int64_t)l * m] / sv[l];
+    P[j + (int64_t)i * n] = acc;
+}
+
+unsigned grid(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+CellLayout cell_layout(const CellArgs &g) {
+    CellLayout L{};
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const int64_t n = 2 * g.n_wall, nc = 2 * (int64_t)g.M, mr = 4 * (int64_t)g.K;
+    const int64_t r = std::min(mr, nc);
+    size_t off = 0;
+    L.A = off;    off = al(off + (size_t)n * n * 8);
+    L.X = off;    off = al(off + (size_t)n * nc * 8);
+    L.C = off;    off = al(off + (size_t)mr * n * 8);
+    L.S = off;    off = al(off + (size_t)mr * nc * 8);
+    L.U = off;    off = al(off + (size_t)mr * r * 8);
+    L.Vt = off;   off = al(off + (size_t)r * nc * 8);
+    L.sv = off;   off = al(off + (size_t)r * 8);
+    L.E = off;    off = al(off + (size_t)r * 8);
+    L.P = off;    off = al(off + (size_t)nc * mr * 8);
+    L.y = off;    off = al(off + (size_t)n * 8);
+    L.rr = off;   off = al(off + (size_t)mr * 8);
+    L.ipiv = off; off = al(off + (size_t)n * 4);
+    L.info = off; off = al(off + 2 * 4);
+    L.total = off;
+    return L;
+}
+
+hipError_t cell_fill(const CellArgs &g, double *A, double *B, double *C, double *Q, hipStream_t st) {
+    const int64_t N = g.n_wall;
+    if (A && N > 0) hipLaunchKernelGGL(cell_fill_A, dim3(grid(N * N)), dim3(256), 0, st, g, A);
+    if (B && N > 0 && g.M > 0) hipLaunchKernelGGL(cell_fill_B, dim3(grid(N * g.M)), dim3(256), 0, st, g, B);
+    if (C && N > 0 && g.K > 0) hipLaunchKernelGGL(cell_fill_C, dim3(grid(g.K * N)), dim3(256), 0, st, g, C);
+    if (Q && g.K > 0 && g.M > 0) hipLaunchKernelGGL(cell_fill_Q, dim3(grid((int64_t)g.K * g.M)), dim3(256), 0, st, g, Q);
+    return hipGetLastError();
+}
+
+hipError_t cell_pinv_launch(int m, int n, const double *sv, const double *U, const double *Vt, double rcond, double *P,
+                            hipStream_t st) {
+    const int r = std::min(m, n);
+    hipLaunchKernelGGL(cell_pinv, dim3(grid((int64_t)m * n)), dim3(256), 0, st, m, n, r, sv, U, Vt, rcond, P);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// factor and solve (rocSOLVER / rocBLAS on the caller's stream)
+// ---------------------------------------------------------------------------
+namespace {
+
+std::mutex g_hmu;
+rocblas_handle g_handle[64] = {};
+
+std::string rb_err(const char *what, rocblas_status s) {
+    return std::string(what) + ": " + rocblas_status_to_string(s);
+}
+
+// one handle per device, created on first use; the caller holds g_hmu
+rocblas_handle handle_for(hipStream_t st, std::string &err) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        err = "no current HIP device";
+        return nullptr;
+    }
+    if (!g_handle[dev]) {
+        const rocblas_status s = rocblas_create_handle(&g_handle[dev]);
+        if (s != rocblas_status_success) {
+            err = rb_err("rocblas_create_handle", s);
+            g_handle[dev] = nullptr;
+            return nullptr;
+        }
+    }
+    const rocblas_status s = rocblas_set_stream(g_handle[dev], st);
+    if (s != rocblas_status_success) {
+        err = rb_err("rocblas_set_stream", s);
+        return nullptr;
+    }
+    return g_handle[dev];
+}
+
+}  // namespace
+
+std::string cell_factor(const CellArgs &g, double rcond, void *ws, hipStream_t st) {
+    const CellLayout L = cell_layout(g);
+    char *b = (char *)ws;
+    double *A = (double *)(b + L.A), *X = (double *)(b + L.X), *C = (double *)(b + L.C), *S = (double *)(b + L.S);
+    double *U = (double *)(b + L.U), *Vt = (double *)(b + L.Vt), *sv = (double *)(b + L.sv), *E = (double *)(b + L.E);
+    double *P = (double *)(b + L.P);
+    rocblas_int *ipiv = (rocblas_int *)(b + L.ipiv), *info = (rocblas_int *)(b + L.info);
+    const rocblas_int n = (rocblas_int)(2 * g.n_wall), nc = 2 * g.M, mr = 4 * g.K, r = std::min(mr, nc);
+    hipError_t e = cell_fill(g, A, X, C, S, st);          // B into X, Q into S
+    if (e != hipSuccess) return std::string("cell fill: ") + hipGetErrorString(e);
+    std::lock_guard<std::mutex> lk(g_hmu);
+    std::string err;
+    rocblas_handle h = handle_for(st, err);
+    if (!h) return err;
+    rocblas_status s = rocsolver_dgetrf(h, n, n, A, n, ipiv, info);
+    if (s != rocblas_status_success) return rb_err("rocsolver_dgetrf", s);
+    s = rocsolver_dgetrs(h, rocblas_operation_none, n, nc, A, n, ipiv, X, n);       // X = A^-1 B
+    if (s != rocblas_status_success) return rb_err("rocsolver_dgetrs", s);
+    const double one = 1.0, minus_one = -1.0;
+    s = rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, mr, nc, n, &minus_one, C, mr, X, n, &one, S,
+                      mr);                                                            // S = Q - C X
+    if (s != rocblas_status_success) return rb_err("rocblas_dgemm", s);
+    s = rocsolver_dgesvd(h, rocblas_svect_singular, rocblas_svect_singular, mr, nc, S, mr, sv, U, mr, Vt, r, E,
+                         rocblas_outofplace, info + 1);
+    if (s != rocblas_status_success) return rb_err("rocsolver_dgesvd", s);
+    e = cell_pinv_launch(mr, nc, sv, U, Vt, rcond, P, st);
+    if (e != hipSuccess) return std::string("cell pinv: ") + hipGetErrorString(e);
+    rocblas_int hinfo[2] = {0, 0};
+    e = hipMemcpyAsync(hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return std::string("cell factor: ") + hipGetErrorString(e);
+    if (hinfo[0] != 0) return "the wall block A is singular (LU pivot " + std::to_string(hinfo[0]) + " is zero)";
+    if (hinfo[1] != 0) return "the SVD of the Schur complement did not converge";
+    return "";
+}
+
+std::string cell_solve(const CellArgs &g, const double *v, const double *gv, double *tau, double *c, void *ws,
+                       hipStream_t st) {
+    const CellLayout L = cell_layout(g);
+    char *b = (char *)ws;
+    double *A = (double *)(b + L.A), *X = (double *)(b + L.X), *C = (double *)(b + L.C), *P = (double *)(b + L.P);
+    double *y = (double *)(b + L.y), *rr = (double *)(b + L.rr);
+    const rocblas_int *ipiv = (const rocblas_int *)(b + L.ipiv);
+    const rocblas_int n = (rocblas_int)(2 * g.n_wall), nc = 2 * g.M, mr = 4 * g.K;
+    hipError_t e = hipMemcpyAsync(y, v, (size_t)n * 8, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(rr, gv, (size_t)mr * 8, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return std::string("cell solve: ") + hipGetErrorString(e);
+    std::lock_guard<std::mutex> lk(g_hmu);
+    std::string err;
+    rocblas_handle h = handle_for(st, err);
+    if (!h) return err;
+    const double one = 1.0, minus_one = -1.0, zero = 0.0;
+    rocblas_status s = rocsolver_dgetrs(h, rocblas_operation_none, n, 1, A, n, ipiv, y, n);       // y = A^-1 v
+    if (s != rocblas_status_success) return rb_err("rocsolver_dgetrs", s);
+    s = rocblas_dgemv(h, rocblas_operation_none, mr, n, &minus_one, C, mr, y, 1, &one, rr, 1);     // g - C y
+    if (s != rocblas_status_success) return rb_err("rocblas_dgemv", s);
+    s = rocblas_dgemv(h, rocblas_operation_none, nc, mr, &one, P, nc, rr, 1, &zero, c, 1);         // c = S^+ (.)
+    if (s != rocblas_status_success) return rb_err("rocblas_dgemv", s);
+    e = hipMemcpyAsync(tau, y, (size_t)n * 8, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return std::string("cell solve: ") + hipGetErrorString(e);
+    s = rocblas_dgemv(h, rocblas_operation_none, n, nc, &minus_one, X, n, c, 1, &one, tau, 1);     // y - X c
+    if (s != rocblas_status_success) return rb_err("rocblas_dgemv", s);
+    return "";
+}
+
+}  // namespace s2d

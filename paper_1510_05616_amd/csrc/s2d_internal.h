@@ -30,6 +30,30 @@ struct alignas(16) RecDlp32 { double x, y; float xl, yl, nx, ny, tx, ty; };
 // per FP32C sub-block: origin and (kFarRadii * radius)^2
 struct SubInfo { double ox, oy, r2; };
 
+// Periodization system of one channel cell (device-passable by value).
+struct CellArgs {
+    int64_t n_wall;                                   // wall nodes N (both walls)
+    const double *x, *y, *nx, *ny, *w, *kap;
+    int32_t K;                                        // side collocation heights
+    const double *side_y;
+    double xl;                                        // x of the left side wall
+    int32_t M;                                        // proxy Stokeslets
+    double cx, cy, R;                                 // proxy circle
+    double d, mu;
+};
+// workspace of a factored cell (byte offsets)
+struct CellLayout {
+    size_t A, X, C, S, U, Vt, sv, E, P, y, rr, ipiv, info, total;
+};
+CellLayout cell_layout(const CellArgs &g);
+hipError_t cell_fill(const CellArgs &g, double *A, double *B, double *C, double *Q, hipStream_t st);
+hipError_t cell_pinv_launch(int m, int n, const double *sv, const double *U, const double *Vt, double rcond,
+                            double *P, hipStream_t st);
+// "" on success, else a message; factor waits for the stream
+std::string cell_factor(const CellArgs &g, double rcond, void *ws, hipStream_t st);
+std::string cell_solve(const CellArgs &g, const double *v, const double *gv, double *tau, double *c, void *ws,
+                       hipStream_t st);
+
 // One launch's decomposition of (targets x sources).
 struct Plan {
     int op, mode, tpt;

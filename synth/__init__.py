@@ -306,6 +306,35 @@ def make_channel(n_wall: int, n_side: int, profile: str = "sin1", d: float = 2 *
     return walls, ys[:n_side].copy(), float(d)
 
 
+def poiseuille(X, Y, alpha, mu):
+    """Manufactured Stokes flow u = (alpha y^2, 0), p = 2 alpha mu x, with a
+    pressure gain of 2 alpha mu d per period d (the paper's periodization
+    test, Section 4.1, writes p = alpha mu x, which does not satisfy
+    -mu Lap u + grad p = 0; the factor 2 is restored)."""
+    return np.stack([alpha * np.asarray(Y) ** 2, np.zeros_like(np.asarray(Y, float))], -1), \
+        2 * alpha * mu * np.asarray(X)
+
+
+def poiseuille_cell_data(walls, side_y, d, alpha, mu, x_left=0.0):
+    """Right-hand sides (v, g) of the periodization system for which the
+    Poiseuille flow solves the cell problem: v = u_e at the wall nodes
+    (interleaved x, y); g = [u_e(R) - u_e(L) at the K side heights; the
+    traction difference T(R) - T(L) for the side normal (1, 0)]."""
+    ue, _ = poiseuille(walls.x, walls.y, alpha, mu)
+    v = ue.reshape(-1)
+    K = len(side_y)
+    gu = np.zeros(2 * K)                          # u_e does not depend on x
+
+    def traction(X, Y):
+        # grad u: du1/dy = 2 alpha y, all else 0; T = -p n + mu (grad u + grad u^T) n, n = (1, 0)
+        _, p = poiseuille(X, Y, alpha, mu)
+        return np.stack([-p, mu * 2 * alpha * np.asarray(Y)], -1)
+
+    xl = np.full(K, x_left)
+    gt = (traction(xl + d, side_y) - traction(xl, side_y)).reshape(-1)
+    return v, np.concatenate([gu, gt])
+
+
 def fluid_points(prob: Problem, n: int, seed: int, gap: float = 0.02):
     """n seeded free target points in one period of the channel (between the
     walls, x in [0, d)), none within `gap` of a vesicle or wall node, e.g. for

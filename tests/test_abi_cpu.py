@@ -131,3 +131,25 @@ def test_pressure_and_traction_argument_checks(L):
     for op in (s2d.S2D_OP_SLP_PRESSURE, s2d.S2D_OP_DLP_PRESSURE, s2d.S2D_OP_SLP_TRACTION):
         assert L.stokes2d_workspace_size(op, 1, by(cs), by(ts)) > 0
         assert L.stokes2d_workspace_size(op, 1, by(cs_on), by(ts_on)) == 0
+
+
+def test_cell_argument_checks(L):
+    import paper_1510_05616_amd as s2d
+    from paper_1510_05616_amd import cell as pc
+    pc._bind()
+    fake = ctypes.c_void_p(0x1000)
+    walls = s2d._Curves(64, 2, fake, fake, fake, fake, fake, fake, fake, fake, fake)
+    good = pc._Cell(walls, 8, fake, 0.0, 32, 3.0, 0.0, 6.0, 6.0, 0.7)
+    by = ctypes.byref
+    assert L.stokes2d_cell_workspace_size(None) == 0
+    assert L.stokes2d_cell_workspace_size(by(good)) > (2 * 64) ** 2 * 8
+    for field, value in (("n_side", 0), ("n_proxy", 0), ("d", 0.0), ("mu", -1.0), ("proxy_r", 0.0)):
+        bad = pc._Cell(walls, 8, fake, 0.0, 32, 3.0, 0.0, 6.0, 6.0, 0.7)
+        setattr(bad, field, value)
+        assert L.stokes2d_cell_workspace_size(by(bad)) == 0, field
+        assert L.stokes2d_cell_factor(by(bad), 1e-8, fake, 1 << 30, None) == s2d.S2D_EINVAL, field
+    nok = s2d._Curves(64, 2, fake, fake, fake, fake, fake, fake, None, fake, fake)     # no kappa
+    assert L.stokes2d_cell_workspace_size(by(pc._Cell(nok, 8, fake, 0.0, 32, 3.0, 0.0, 6.0, 6.0, 0.7))) == 0
+    assert L.stokes2d_cell_factor(by(good), 1.5, fake, 1 << 30, None) == s2d.S2D_EINVAL     # rcond
+    assert L.stokes2d_cell_factor(by(good), 1e-8, fake, 16, None) == s2d.S2D_EWORKSPACE
+    assert L.stokes2d_cell_solve(by(good), None, fake, fake, fake, fake, 1 << 30, None) == s2d.S2D_EINVAL

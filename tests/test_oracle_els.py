@@ -81,11 +81,11 @@ def test_blocks_act_as_the_pair_sums(oracle_lib):
 def _poiseuille_error(Nw, K, M, alpha=0.2, mu=0.7):
     walls, sy, d = synth.make_channel(Nw, K)
     A, B, C, Q, (px, py) = els.assemble(walls, sy, d, M, mu)
-    v, g = els.poiseuille_data(walls, sy, d, alpha, mu)
+    v, g = synth.poiseuille_cell_data(walls, sy, d, alpha, mu)
     tau, c = els.solve(A, B, C, Q, v, g)
     X, Y = np.array([0.8, 3.2, 4.8]), np.zeros(3)
     u, p = els.field(walls, tau, px, py, c, d, mu, X, Y)
-    ue, pe = els.poiseuille(X, Y, alpha, mu)
+    ue, pe = synth.poiseuille(X, Y, alpha, mu)
     eu = np.abs(u - ue).max() / (alpha * 1.3 ** 2)            # max |u_e| over the cell
     # the pressure is fixed up to a constant: compare differences
     ep = np.abs((p - p[0]) - (pe - pe[0])).max() / (2 * alpha * mu * d)
@@ -108,7 +108,7 @@ def test_poiseuille_data_is_the_exact_traction_jump():
     # the traction jump of u = (a y^2, 0), p = 2 a mu x across one period is
     # -(p(R) - p(L)) n = -2 a mu d n at every height
     walls, sy, d = synth.make_channel(16, 8)
-    v, g = els.poiseuille_data(walls, sy, d, 0.2, 0.7)
+    v, g = synth.poiseuille_cell_data(walls, sy, d, 0.2, 0.7)
     K = len(sy)
     assert np.allclose(g[:2 * K], 0.0)
     assert np.allclose(g[2 * K::2], -2 * 0.2 * 0.7 * d) and np.allclose(g[2 * K + 1::2], 0.0)
