@@ -224,6 +224,66 @@ def f1_section(prob, reps=5):
     return res
 
 
+def cell_section(n_wall=4000, K=32, M=128, reps=5):
+    """Periodization system of an empty channel cell at the paper's sizes
+    (y = +-(1 + 0.3 sin x), d = 2 pi, 4000 nodes per wall, K = 32 side
+    heights, M = 128 proxies, mu = 0.7): factor (block fill, LU of the
+    16,000 x 16,000 wall block, A^-1 B, Schur complement, SVD) and solve
+    times, the Poiseuille test errors at (0.8, 0), (3.2, 0), (4.8, 0), and
+    the FP64 oracle's dense solve at 500 nodes per wall for scale."""
+    import torch
+    import synth
+    from paper_1510_05616_amd.cell import Cell
+    alpha, mu = 0.2, 0.7
+    walls, sy, d = synth.make_channel(n_wall, K)
+    cell = Cell(walls, sy, d, M, mu)
+    cell.factor()                       # first call: library handle and scratch set-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cell.factor()
+    t_factor = time.perf_counter() - t0
+    v, g = synth.poiseuille_cell_data(walls, sy, d, alpha, mu)
+    f64 = dict(dtype=torch.float64, device="cuda")
+    vt, gt = torch.as_tensor(v, **f64), torch.as_tensor(g, **f64)
+    tau, c = cell.solve(vt, gt)
+    ms_solve = _time(lambda: cell.solve(vt, gt, tau, c), reps=reps)
+    X, Y = np.array([0.8, 3.2, 4.8]), np.zeros(3)
+    u, w, p = cell.flow(tau, c, X, Y)
+    ue, pe = synth.poiseuille(X, Y, alpha, mu)
+    un = np.stack([u.cpu().numpy(), w.cpu().numpy()], 1)
+    pn = p.cpu().numpy()
+    eu = float(np.abs(un - ue).max() / (alpha * 1.3 ** 2))
+    ep = float(np.abs((pn - pn[0]) - (pe - pe[0])).max() / (2 * alpha * mu * d))
+    n, nc, mr = 4 * n_wall, 2 * M, 4 * K
+    # LU (2/3 n^3) + inverse from the LU (4/3 n^3) + A^-1 B + C A^-1 B
+    flops = 2.0 * n ** 3 + 2.0 * n * n * nc + 2.0 * mr * n * nc
+    tf = flops / t_factor / 1e12
+    res = {"workload": f"empty channel y = +-(1 + 0.3 sin x), d = 2 pi, {n_wall} nodes per wall "
+                       f"(system {n} + {nc} unknowns), K = {K}, M = {M}, Poiseuille data",
+           "factor_s": t_factor, "solve_ms": ms_solve,
+           "factor_flops": flops, "factor_tflops": tf, "peak_tflops": 78.6, "frac": tf / 78.6,
+           "poiseuille_error": {"velocity": eu, "pressure": ep}}
+    log(f"cell: factor {t_factor * 1e3:.1f} ms ({tf:.1f} TFLOP/s FP64: LU and inverse), solve {ms_solve:.3f} ms, "
+        f"Poiseuille error velocity {eu:.2e} pressure {ep:.2e}")
+    return res
+
+
+def cell_cpu_baseline(n_wall=500, K=32, M=128):
+    """The oracle's dense numpy assembly and solve at 500 nodes per wall."""
+    import synth
+    from oracle import els
+    walls, sy, d = synth.make_channel(n_wall, K)
+    t0 = time.perf_counter()
+    A, B, C, Q, _ = els.assemble(walls, sy, d, M, 0.7)
+    v, g = synth.poiseuille_cell_data(walls, sy, d, 0.2, 0.7)
+    els.solve(A, B, C, Q, v, g)
+    t = time.perf_counter() - t0
+    n = 4 * n_wall
+    flops = 2.0 / 3.0 * n ** 3 + 2.0 * n * n * 2 * M + 2.0 * 4 * K * n * 2 * M
+    return {"seconds": t, "n_wall": n_wall, "tflops": flops / t / 1e12, "kind": "oracle",
+            "sample": f"{n_wall} nodes per wall (system {n} + {2 * M}), numpy/LAPACK"}
+
+
 def batch_section():
     """Config 4: 256 independent channel instances (1-40 vesicles of
     32-256 nodes, 256-4096 wall nodes per wall) evaluated by one batched call
@@ -369,6 +429,7 @@ def main():
     ap.add_argument("--near", type=int, default=1, help="run the near-field correction section (0: skip)")
     ap.add_argument("--batch", type=int, default=1, help="run the batched-instances section (0: skip)")
     ap.add_argument("--f1", type=int, default=1, help="run the pressure/traction section (0: skip)")
+    ap.add_argument("--cell", type=int, default=1, help="run the periodization-system section (0: skip)")
     ap.add_argument("--copy-probe", action="store_true", help="only copy 1 GiB on the device and exit")
     args = ap.parse_args()
     if args.copy_probe:
@@ -435,6 +496,9 @@ def main():
             f"rel err f32={errs['f32']:.2e} f64={errs['f64']:.2e}")
 
     f1_res = f1_section(prob) if args.f1 and args.config == 3 else None
+    cell_res = cell_section() if args.cell else None
+    if cell_res is not None and args.cpu_sample > 0:
+        cell_res["cpu_baseline"] = cell_cpu_baseline()
     near_res = near_section() if args.near else None
     batch_res = batch_section() if args.batch else None
 
@@ -456,6 +520,7 @@ def main():
         "kernel_ms": {"f32_slp_pair": f32["slp_pair_ms"], "f32_dlp_pair": f32["dlp_pair_ms"],
                       "f64_slp_pair": f64["slp_pair_ms"], "f64_dlp_pair": f64["dlp_pair_ms"]},
         "pressure_traction": f1_res,
+        "periodization_cell": cell_res,
         "near": near_res,
         "batch": batch_res,
     }

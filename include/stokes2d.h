@@ -195,7 +195,8 @@ S2D_API int stokes2d_slp_traction_eval(int mode, const s2d_curves *src, const s2
  * are column-major with leading dimension = rows: A 2N x 2N, B 2N x 2M,
  * C 4K x 2N, Q 4K x 2M.  The pair kernels of Eqs. (D), (S), (K) and the
  * double-layer traction of Eq. (T) fill them on the GPU; LU, GEMM and SVD run
- * in rocSOLVER / rocBLAS, which may allocate their own device scratch.
+ * in rocSOLVER / rocBLAS (LU, explicit inverse, GEMM, SVD), which may
+ * allocate their own device scratch.
  * ------------------------------------------------------------------------- */
 typedef struct s2d_cell {
     s2d_curves walls;             /* the wall nodes of one period (x, y, nx, ny, w, kappa; the
@@ -208,8 +209,9 @@ typedef struct s2d_cell {
     double d, mu;                 /* period > 0, viscosity > 0 */
 } s2d_cell;
 
-/* Workspace bytes of a factored cell (0 on bad arguments): the LU of A,
- * A^-1 B, C, the pseudo-inverse of S and scratch, about (2N)^2 * 8 bytes. */
+/* Workspace bytes of a factored cell (0 on bad arguments): A^-1 (formed
+ * once, so that each solve is matrix-vector products), B, A^-1 B, C, the
+ * pseudo-inverse of S and scratch, about (2N)^2 * 8 bytes. */
 S2D_API size_t stokes2d_cell_workspace_size(const s2d_cell *cell);
 
 /* Fills the four blocks into caller buffers (any may be NULL to skip). */

@@ -13,9 +13,10 @@
 // (BIEgT)).
 //
 // The four blocks are filled by one kernel each (one thread per 2 x 2 node
-// block, column-major for the solver).  Factor: LU of A (rocSOLVER), X =
-// A^-1 B, S = Q - C X (rocBLAS GEMM), SVD of the small S and its truncated
-// pseudo-inverse.  Solve: y = A^-1 v, c = S^+ (g - C y), tau = y - X c.
+// block, column-major for the solver).  Factor: LU of A^T and the explicit
+// inverse (A^-1)^T (rocSOLVER), X = A^-1 B, S = Q - C X (rocBLAS GEMM), SVD of the
+// small S and its truncated pseudo-inverse.  Solve (matrix-vector products
+// only): y = A^-1 v, c = S^+ (g - C y), tau = y - X c.
 #include "s2d_internal.h"
 
 #include <rocblas/rocblas.h>
@@ -97,7 +98,7 @@ __device__ __forceinline__ void put(double *A, int64_t ld, int64_t row0, int64_t
 }
 
 // A: -1/2 I + sum_{|n| <= 1} D(x_i, y_j + n d) w_j, diagonal limit at n = 0
-__global__ __launch_bounds__(256) void cell_fill_A(CellArgs g, double *A) {
+__global__ __launch_bounds__(256) void cell_fill_A(CellArgs g, double *A, int transpose) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t N = g.n_wall;
     if (t >= N * N) return;
@@ -123,7 +124,12 @@ __global__ __launch_bounds__(256) void cell_fill_A(CellArgs g, double *A) {
         acc[0] -= 0.5;
         acc[3] -= 0.5;
     }
-    put(A, 2 * N, 2 * i, 2 * j, acc);
+    if (transpose) {
+        const double tr[4] = {acc[0], acc[2], acc[1], acc[3]};
+        put(A, 2 * N, 2 * j, 2 * i, tr);
+    } else {
+        put(A, 2 * N, 2 * i, 2 * j, acc);
+    }
 }
 
 // B: the proxy Stokeslets at the wall nodes
@@ -208,6 +214,7 @@ CellLayout cell_layout(const CellArgs &g) {
     const int64_t r = std::min(mr, nc);
     size_t off = 0;
     L.A = off;    off = al(off + (size_t)n * n * 8);
+    L.B = off;    off = al(off + (size_t)n * nc * 8);
     L.X = off;    off = al(off + (size_t)n * nc * 8);
     L.C = off;    off = al(off + (size_t)mr * n * 8);
     L.S = off;    off = al(off + (size_t)mr * nc * 8);
@@ -219,14 +226,14 @@ CellLayout cell_layout(const CellArgs &g) {
     L.y = off;    off = al(off + (size_t)n * 8);
     L.rr = off;   off = al(off + (size_t)mr * 8);
     L.ipiv = off; off = al(off + (size_t)n * 4);
-    L.info = off; off = al(off + 2 * 4);
+    L.info = off; off = al(off + 3 * 4);
     L.total = off;
     return L;
 }
 
-hipError_t cell_fill(const CellArgs &g, double *A, double *B, double *C, double *Q, hipStream_t st) {
+hipError_t cell_fill(const CellArgs &g, double *A, double *B, double *C, double *Q, hipStream_t st, bool a_transposed) {
     const int64_t N = g.n_wall;
-    if (A && N > 0) hipLaunchKernelGGL(cell_fill_A, dim3(grid(N * N)), dim3(256), 0, st, g, A);
+    if (A && N > 0) hipLaunchKernelGGL(cell_fill_A, dim3(grid(N * N)), dim3(256), 0, st, g, A, a_transposed ? 1 : 0);
     if (B && N > 0 && g.M > 0) hipLaunchKernelGGL(cell_fill_B, dim3(grid(N * g.M)), dim3(256), 0, st, g, B);
     if (C && N > 0 && g.K > 0) hipLaunchKernelGGL(cell_fill_C, dim3(grid(g.K * N)), dim3(256), 0, st, g, C);
     if (Q && g.K > 0 && g.M > 0) hipLaunchKernelGGL(cell_fill_Q, dim3(grid((int64_t)g.K * g.M)), dim3(256), 0, st, g, Q);
@@ -280,22 +287,30 @@ rocblas_handle handle_for(hipStream_t st, std::string &err) {
 std::string cell_factor(const CellArgs &g, double rcond, void *ws, hipStream_t st) {
     const CellLayout L = cell_layout(g);
     char *b = (char *)ws;
-    double *A = (double *)(b + L.A), *X = (double *)(b + L.X), *C = (double *)(b + L.C), *S = (double *)(b + L.S);
+    double *A = (double *)(b + L.A), *B = (double *)(b + L.B), *X = (double *)(b + L.X), *C = (double *)(b + L.C);
+    double *S = (double *)(b + L.S);
     double *U = (double *)(b + L.U), *Vt = (double *)(b + L.Vt), *sv = (double *)(b + L.sv), *E = (double *)(b + L.E);
     double *P = (double *)(b + L.P);
     rocblas_int *ipiv = (rocblas_int *)(b + L.ipiv), *info = (rocblas_int *)(b + L.info);
     const rocblas_int n = (rocblas_int)(2 * g.n_wall), nc = 2 * g.M, mr = 4 * g.K, r = std::min(mr, nc);
-    hipError_t e = cell_fill(g, A, X, C, S, st);          // B into X, Q into S
+    hipError_t e = cell_fill(g, A, B, C, S, st, true);    // A^T, and Q into S
     if (e != hipSuccess) return std::string("cell fill: ") + hipGetErrorString(e);
     std::lock_guard<std::mutex> lk(g_hmu);
     std::string err;
     rocblas_handle h = handle_for(st, err);
     if (!h) return err;
+    // (A^T)^-1 = (A^-1)^T is formed once from the LU of A^T: every later
+    // solve is then matrix-vector products, and with the inverse stored
+    // transposed they read its rows contiguously (a triangular solve per
+    // right-hand side is latency-bound at this size)
     rocblas_status s = rocsolver_dgetrf(h, n, n, A, n, ipiv, info);
     if (s != rocblas_status_success) return rb_err("rocsolver_dgetrf", s);
-    s = rocsolver_dgetrs(h, rocblas_operation_none, n, nc, A, n, ipiv, X, n);       // X = A^-1 B
-    if (s != rocblas_status_success) return rb_err("rocsolver_dgetrs", s);
-    const double one = 1.0, minus_one = -1.0;
+    s = rocsolver_dgetri(h, n, A, n, ipiv, info + 2);
+    if (s != rocblas_status_success) return rb_err("rocsolver_dgetri", s);
+    const double one = 1.0, minus_one = -1.0, zero = 0.0;
+    s = rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, n, nc, n, &one, A, n, B, n, &zero, X,
+                      n);                                                             // X = A^-1 B
+    if (s != rocblas_status_success) return rb_err("rocblas_dgemm", s);
     s = rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, mr, nc, n, &minus_one, C, mr, X, n, &one, S,
                       mr);                                                            // S = Q - C X
     if (s != rocblas_status_success) return rb_err("rocblas_dgemm", s);
@@ -304,11 +319,12 @@ std::string cell_factor(const CellArgs &g, double rcond, void *ws, hipStream_t s
     if (s != rocblas_status_success) return rb_err("rocsolver_dgesvd", s);
     e = cell_pinv_launch(mr, nc, sv, U, Vt, rcond, P, st);
     if (e != hipSuccess) return std::string("cell pinv: ") + hipGetErrorString(e);
-    rocblas_int hinfo[2] = {0, 0};
+    rocblas_int hinfo[3] = {0, 0, 0};
     e = hipMemcpyAsync(hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return std::string("cell factor: ") + hipGetErrorString(e);
-    if (hinfo[0] != 0) return "the wall block A is singular (LU pivot " + std::to_string(hinfo[0]) + " is zero)";
+    if (hinfo[0] != 0 || hinfo[2] != 0)
+        return "the wall block A is singular (LU pivot " + std::to_string(std::max(hinfo[0], hinfo[2])) + " is zero)";
     if (hinfo[1] != 0) return "the SVD of the Schur complement did not converge";
     return "";
 }
@@ -319,18 +335,16 @@ std::string cell_solve(const CellArgs &g, const double *v, const double *gv, dou
     char *b = (char *)ws;
     double *A = (double *)(b + L.A), *X = (double *)(b + L.X), *C = (double *)(b + L.C), *P = (double *)(b + L.P);
     double *y = (double *)(b + L.y), *rr = (double *)(b + L.rr);
-    const rocblas_int *ipiv = (const rocblas_int *)(b + L.ipiv);
     const rocblas_int n = (rocblas_int)(2 * g.n_wall), nc = 2 * g.M, mr = 4 * g.K;
-    hipError_t e = hipMemcpyAsync(y, v, (size_t)n * 8, hipMemcpyDeviceToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(rr, gv, (size_t)mr * 8, hipMemcpyDeviceToDevice, st);
+    hipError_t e = hipMemcpyAsync(rr, gv, (size_t)mr * 8, hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return std::string("cell solve: ") + hipGetErrorString(e);
     std::lock_guard<std::mutex> lk(g_hmu);
     std::string err;
     rocblas_handle h = handle_for(st, err);
     if (!h) return err;
     const double one = 1.0, minus_one = -1.0, zero = 0.0;
-    rocblas_status s = rocsolver_dgetrs(h, rocblas_operation_none, n, 1, A, n, ipiv, y, n);       // y = A^-1 v
-    if (s != rocblas_status_success) return rb_err("rocsolver_dgetrs", s);
+    rocblas_status s = rocblas_dgemv(h, rocblas_operation_transpose, n, n, &one, A, n, v, 1, &zero, y, 1);  // A^-1 v
+    if (s != rocblas_status_success) return rb_err("rocblas_dgemv", s);
     s = rocblas_dgemv(h, rocblas_operation_none, mr, n, &minus_one, C, mr, y, 1, &one, rr, 1);     // g - C y
     if (s != rocblas_status_success) return rb_err("rocblas_dgemv", s);
     s = rocblas_dgemv(h, rocblas_operation_none, nc, mr, &one, P, nc, rr, 1, &zero, c, 1);         // c = S^+ (.)

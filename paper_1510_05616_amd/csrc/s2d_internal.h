@@ -43,10 +43,11 @@ struct CellArgs {
 };
 // workspace of a factored cell (byte offsets)
 struct CellLayout {
-    size_t A, X, C, S, U, Vt, sv, E, P, y, rr, ipiv, info, total;
+    size_t A, B, X, C, S, U, Vt, sv, E, P, y, rr, ipiv, info, total;
 };
 CellLayout cell_layout(const CellArgs &g);
-hipError_t cell_fill(const CellArgs &g, double *A, double *B, double *C, double *Q, hipStream_t st);
+hipError_t cell_fill(const CellArgs &g, double *A, double *B, double *C, double *Q, hipStream_t st,
+                     bool a_transposed = false);
 hipError_t cell_pinv_launch(int m, int n, const double *sv, const double *U, const double *Vt, double rcond,
                             double *P, hipStream_t st);
 // "" on success, else a message; factor waits for the stream
