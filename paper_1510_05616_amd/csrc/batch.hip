@@ -99,12 +99,14 @@ __global__ __launch_bounds__(256) void batch_prep(BatchTables t, int op) {
     const s2d_curves &s = I.src[op];
     void *rec = (void *)I.pa[op].rec;
     if (PREC == S2D_FP64) {
-        if (op == 0) prep_one64<S2D_OP_SLP>(j, s.n_nodes, s.x, s.y, s.nx, s.ny, s.w, s.fx, s.fy, rec);
-        else prep_one64<S2D_OP_DLP>(j, s.n_nodes, s.x, s.y, s.nx, s.ny, s.w, s.fx, s.fy, rec);
+        if (op == 0) prep_one64<S2D_OP_SLP>(j, s.n_nodes, s.x, s.y, s.nx, s.ny, s.w, s.fx, s.fy, rec, kFarPad);
+        else prep_one64<S2D_OP_DLP>(j, s.n_nodes, s.x, s.y, s.nx, s.ny, s.w, s.fx, s.fy, rec, kFarPad);
     } else {
         SubInfo *sub = (SubInfo *)I.pa[op].sub;
-        if (op == 0) prep_sub32<S2D_OP_SLP>(j / kSubBlock, s.n_nodes, s.x, s.y, s.nx, s.ny, s.w, s.fx, s.fy, rec, sub);
-        else prep_sub32<S2D_OP_DLP>(j / kSubBlock, s.n_nodes, s.x, s.y, s.nx, s.ny, s.w, s.fx, s.fy, rec, sub);
+        if (op == 0)
+            prep_sub32<S2D_OP_SLP>(j / kSubBlock, s.n_nodes, s.x, s.y, s.nx, s.ny, s.w, s.fx, s.fy, rec, sub, kFarPad);
+        else
+            prep_sub32<S2D_OP_DLP>(j / kSubBlock, s.n_nodes, s.x, s.y, s.nx, s.ny, s.w, s.fx, s.fy, rec, sub, kFarPad);
     }
 }
 
@@ -519,6 +521,7 @@ int build_plan(BatchPlan &P, int mode, int32_t n_inst, const s2d_instance *inst,
             a.img_lo = -1;
             a.img_hi = 1;
             a.part = (double *)(db + data + g.off_part[op]);
+            a.pad_far = 1;
             for (int64_t tl = 0; tl < g.n_tiles; ++tl) {
                 const int64_t act = std::min<int64_t>((int64_t)kWave * c.tpt, n - tl * kWave * c.tpt);
                 for (int64_t sp = 0; sp < g.n_splits[op]; ++sp) {

@@ -373,7 +373,7 @@ __device__ __forceinline__ void pair_tile(const PairArgs &a, int64_t tile, int s
         for (int64_t sb = sb0; sb < sb1; ++sb) {
             const int64_t j0 = sb * kSuperBlock;
             const int64_t j1 = min(j0 + (int64_t)kSuperBlock, a.n_src);
-            const bool masked = (j1 - j0 < kSuperBlock) ||
+            const bool masked = (j1 - j0 < kSuperBlock && !a.pad_far) ||
                                 (n == 0 && hlo < hhi && j0 < hhi && (int64_t)hlo < j0 + kSuperBlock);
             if (!masked) {
                 // ---------------- unmasked superblock ----------------

@@ -2,8 +2,10 @@
 // Source preparation (O(N)): turns the caller's FP64 structure-of-arrays
 // curve data into the per-source records the pair kernels stream, with the
 // trapezoid weight folded in (g = w f for the single layer, nu = w n for the
-// double layer; Section 2.3 Nystrom discretisation), zero records padding the
-// last superblock, and, for the FP32 single layer, each superblock's FP64
+// double layer; Section 2.3 Nystrom discretisation), zero-density records
+// padding the last superblock (at coordinate `pad`: the batched path puts them
+// at kFarPad so that they can be summed like real sources, contributing
+// exactly zero), and, for the FP32 single layer, each superblock's FP64
 // density sum (used to add back the log of the superblock's reference
 // distance).
 #include "s2d_internal.h"
@@ -16,9 +18,9 @@ __device__ __forceinline__ void prep_one64(int64_t j, int64_t n_src, const doubl
                                            const double *__restrict__ y, const double *__restrict__ nx,
                                            const double *__restrict__ ny, const double *__restrict__ w,
                                            const double *__restrict__ fx, const double *__restrict__ fy,
-                                           void *rec_out) {
+                                           void *rec_out, double pad = 0.0) {
     const bool v = j < n_src;
-    const double X = v ? x[j] : 0.0, Y = v ? y[j] : 0.0;
+    const double X = v ? x[j] : pad, Y = v ? y[j] : pad;
     const double W = v ? w[j] : 0.0;
     const double FX = v ? fx[j] : 0.0, FY = v ? fy[j] : 0.0;
     if (slp_sources(OP)) {
@@ -37,7 +39,7 @@ __device__ __forceinline__ void prep_sub32(int64_t u, int64_t n_src, const doubl
                                            const double *__restrict__ y, const double *__restrict__ nx,
                                            const double *__restrict__ ny, const double *__restrict__ w,
                                            const double *__restrict__ fx, const double *__restrict__ fy,
-                                           void *rec_out, SubInfo *sub) {
+                                           void *rec_out, SubInfo *sub, double pad = 0.0) {
     const int64_t j0 = u * kSubBlock;
     const int64_t nv = max((int64_t)0, min((int64_t)kSubBlock, n_src - j0));
     double ox = 0.0, oy = 0.0, r2 = 0.0;
@@ -53,7 +55,7 @@ __device__ __forceinline__ void prep_sub32(int64_t u, int64_t n_src, const doubl
     sub[u] = SubInfo{ox, oy, kFarRadii * kFarRadii * r2};
     for (int64_t j = j0; j < j0 + kSubBlock; ++j) {
         const bool v = j < n_src;
-        const double X = v ? x[j] : 0.0, Y = v ? y[j] : 0.0;
+        const double X = v ? x[j] : pad, Y = v ? y[j] : pad;
         const double W = v ? w[j] : 0.0;
         const double FX = v ? fx[j] : 0.0, FY = v ? fy[j] : 0.0;
         const float xl = (float)(X - ox), yl = (float)(Y - oy);

@@ -87,7 +87,13 @@ struct PairArgs {
     double *part;             // [n_splits][2][n_trg]
     const double *tnx, *tny;  // target unit normals (single-layer traction) or NULL
     const void *rec64;        // FP32C pressures and traction: FP64 records for near sub-blocks
+    int32_t pad_far;          // padding records sit at kFarPad: the ragged superblock needs no mask
 };
+
+// Position of the zero-density padding records of the batched path: far
+// from every target (coordinates below 1e6 in magnitude), so that a padded
+// pair has a finite, large |r| and contributes exactly zero.
+constexpr double kFarPad = 1.0e7;
 
 // FP32C pressures and traction evaluate near sub-blocks from FP64 records.
 constexpr bool near_fp64(int op) { return op > S2D_OP_DLP; }
