@@ -12,6 +12,11 @@ TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
   the plain N-node trapezoid rule (no images, no self term).  The paper
   notes that the trapezoid rule loses accuracy for targets near a curve
   (Section 4.1 footnote and the error band of its serpentine-channel figure).
+* Spectral upsampling of one period of a periodic channel wall (the same
+  trigonometric interpolation applied to the wall's periodic parts), for the
+  near-wall correction of the double layer: Delta = D_P - D_1 with both sums
+  over the whole wall and its images, the close evaluation the paper names as
+  future work for the walls (Section 4.1 footnote, Conclusions).
 * Target features and the MLP (3 hidden layers of width 64, tanh-form GELU)
   forward and backward passes, written out plainly.
 """
@@ -82,6 +87,36 @@ def near_label(x, y, fx, fy, w, tx, ty, P=8, mu=1.0):
     u1, v1 = slp_trap(x, y, w, fx, fy, tx, ty, mu)
     uP, vP = slp_trap(xu, yu, wu, fxu, fyu, tx, ty, mu)
     return uP - u1, vP - v1
+
+
+# ----------------------------------------------------------------------------
+# walls: spectral upsampling of one period of a periodic wall
+# ----------------------------------------------------------------------------
+def wall_upsample(x, y, nx, ny, fx, fy, d, P):
+    """One period of a wall with N nodes equispaced in its parameter t in
+    [0, 2 pi), advancing by d (or -d) in x per period: the periodic parts
+    x - s d t / (2 pi) (s = +-1) and y, and the density, interpolated onto P N
+    nodes (trigonometric interpolation, Nyquist mode split evenly); the speed
+    |x'(t)| from spectral derivatives, weights (2 pi / (P N)) |x'|, unit
+    normals perpendicular to the tangent and oriented like the given ones.
+    Returns (x, y, nx, ny, w, fx, fy) on P N nodes."""
+    N = x.shape[0]
+    s = 1.0 if x[1] > x[0] else -1.0
+    t = 2 * np.pi * np.arange(N) / N
+    xp = x - s * d * t / (2 * np.pi)
+    M = P * N
+    tf = 2 * np.pi * np.arange(M) / M
+    xu = upsample_periodic(xp, P) + s * d * tf / (2 * np.pi)
+    yu = upsample_periodic(y, P)
+    dx = spectral_derivative(upsample_periodic(xp, P)) + s * d / (2 * np.pi)
+    dy = spectral_derivative(yu)
+    sp = np.hypot(dx, dy)
+    # orientation of the given normals relative to the left normal (-y', x')
+    tx0 = spectral_derivative(xp)[0] + s * d / (2 * np.pi)
+    ty0 = spectral_derivative(y)[0]
+    o = 1.0 if (-ty0 * nx[0] + tx0 * ny[0]) > 0 else -1.0
+    return (xu, yu, o * -dy / sp, o * dx / sp, (2 * np.pi / M) * sp,
+            upsample_periodic(fx, P), upsample_periodic(fy, P))
 
 
 # ----------------------------------------------------------------------------
