@@ -224,6 +224,90 @@ def f1_section(prob, reps=5):
     return res
 
 
+# algorithmic flops of the wall upsampling sums: per (fine point, mode k) the
+# four values Re(V_k e^{ik th}) (4 each), the two derivatives Re(i k V_k
+# e^{ik th}) (5 each) and the twiddle rotation (6); per (mode, node) of the
+# coefficient sums 4 complex-by-real products (16), the shift of x (2) and
+# the rotation (6)
+WALL_SYNTH_FLOPS, WALL_DFT_FLOPS = 32, 24
+
+
+def wall_section(prob, n_trg=20000, P=8, reps=5):
+    """Near-wall correction of the walls' double layer on the 128k channel:
+    its two walls of 16,000 nodes (smooth seeded densities) refined P = 8
+    times by the library, Delta = D_P - D_1 over images -1..1 at 20,000
+    seeded points 0.05..3 node spacings inside the fluid; FP64.  The dominant
+    kernel is the double-layer pair kernel over the 256,000 refined nodes."""
+    import torch
+    import oracle
+    import synth
+    import paper_1510_05616_amd as s2d
+    from oracle import near as onear
+    from paper_1510_05616_amd import near as pn
+    walls_np = synth.wall_densities(prob.wall, 21)
+    tx, ty = synth.near_wall_points(walls_np, n_trg, seed=22)
+    walls, tg = s2d.Curves(walls_np), s2d.Targets(tx, ty)
+    f64 = dict(dtype=torch.float64, device="cuda")
+    du, dv = torch.zeros(n_trg, **f64), torch.zeros(n_trg, **f64)
+    ws = torch.empty(pn.near_wall_workspace_size(walls, tg, P), dtype=torch.uint8, device="cuda")
+    corr = lambda: pn.near_wall_correct_eval(walls, tg, prob.d, -1, 1, P, du, dv, 0, ws)
+    ms_corr = _time(corr, reps)
+    fine = pn.stokes2d_wall_upsample(walls, prob.d, P)
+    ms_up = _time(lambda: pn.stokes2d_wall_upsample(walls, prob.d, P), reps)
+    u, v = torch.zeros(n_trg, **f64), torch.zeros(n_trg, **f64)
+    pws = torch.empty(s2d.stokes2d_workspace_size(s2d.S2D_OP_DLP, s2d.S2D_FP64, fine, tg), dtype=torch.uint8,
+                      device="cuda")
+    dlp = lambda: s2d.stokes2d_dlp_eval(s2d.S2D_FP64, fine, tg, prob.d, -1, 1, u, v, 0, pws)
+    dlp()
+    torch.cuda.synchronize()
+    s2d.stokes2d_profile_read(s2d.S2D_OP_DLP)
+    s2d.stokes2d_profile_enable(True)
+    _time(dlp, reps)
+    s2d.stokes2d_profile_enable(False)
+    kms, kn = s2d.stokes2d_profile_read(s2d.S2D_OP_DLP)
+    kms /= max(kn, 1)
+    corr()
+    torch.cuda.synchronize()
+    gu, gv = du.cpu().numpy(), dv.cpu().numpy()
+    nw, nf = prob.wall.n_nodes, P * prob.wall.n_nodes
+    pairs_fine = n_trg * nf * 3
+    tf = FLOPS_PER_PAIR * pairs_fine / (kms * 1e-3) / 1e12
+    half = nw // 2                                  # nodes per wall
+    up_flops = 2 * (P * half * (half // 2 - 1) * WALL_SYNTH_FLOPS + (half // 2 + 1) * half * WALL_DFT_FLOPS)
+
+    # the oracle: refined walls by FFT, both double layers by direct sums,
+    # on a seeded sample of the targets
+    ns = 200
+    idx = np.random.default_rng(23).choice(n_trg, ns, replace=False)
+    t0 = time.time()
+    parts = []
+    for c in range(walls_np.n_curves):
+        sl = slice(walls_np.curve_off[c], walls_np.curve_off[c + 1])
+        r = onear.wall_upsample(walls_np.x[sl], walls_np.y[sl], walls_np.nx[sl], walls_np.ny[sl],
+                                walls_np.fx[sl], walls_np.fy[sl], prob.d, P)
+        parts.append((r[0], r[1], r[2], r[3], r[4], np.zeros_like(r[0]), r[5], r[6]))
+    fine_np = synth.concat_curves(parts)
+    uP, vP = oracle.dlp(fine_np, tx[idx], ty[idx], None, None, prob.d, -1, 1)
+    u1, v1 = oracle.dlp(walls_np, tx[idx], ty[idx], None, None, prob.d, -1, 1)
+    t_or = time.time() - t0
+    e = max(np.abs(gu[idx] - (uP - u1)).max(), np.abs(gv[idx] - (vP - v1)).max()) / np.hypot(uP, vP).max()
+    log(f"walls: correction {ms_corr:.3f} ms for {n_trg} targets (upsampling {ms_up:.3f} ms, refined DLP pair "
+        f"kernel {kms:.3f} ms = {tf:.1f} TFLOP/s), E={e:.2e}; oracle {t_or:.1f}s for {ns} targets")
+    return {"workload": "2 walls x 16,000 nodes of the 128k channel refined 8x, Delta = D_P - D_1 at 20,000 "
+                        "near-wall points (0.05..3 spacings), images -1..1, FP64",
+            "ms": ms_corr, "value": n_trg / (ms_corr * 1e-3), "unit": "corrected targets/s",
+            "upsample_ms": ms_up, "upsample_tflops": up_flops / (ms_up * 1e-3) / 1e12,
+            "roofline": {"bound": "alu", "kernel": "pair_kernel<DLP> over the refined walls", "achieved": tf,
+                         "peak": PEAK["f64"] / 1e12, "unit": "TFLOP/s", "frac": tf * 1e12 / PEAK["f64"],
+                         "traffic": None, "flops_per_pair": FLOPS_PER_PAIR, "pairs_per_launch": pairs_fine,
+                         "kernel_ms": kms},
+            "rel_err_vs_oracle": float(e),
+            "cpu_baseline": {"value": ns / t_or, "unit": "corrected targets/s", "kind": "oracle",
+                             "cores": oracle.num_threads(),
+                             "sample": f"{ns} seeded targets: FFT refinement of both walls plus the refined and "
+                                       "given double layers by direct FP64 sums"}}
+
+
 def cell_section(n_wall=4000, K=32, M=128, reps=5):
     """Periodization system of an empty channel cell at the paper's sizes
     (y = +-(1 + 0.3 sin x), d = 2 pi, 4000 nodes per wall, K = 32 side
@@ -430,6 +514,7 @@ def main():
     ap.add_argument("--batch", type=int, default=1, help="run the batched-instances section (0: skip)")
     ap.add_argument("--f1", type=int, default=1, help="run the pressure/traction section (0: skip)")
     ap.add_argument("--cell", type=int, default=1, help="run the periodization-system section (0: skip)")
+    ap.add_argument("--walls", type=int, default=1, help="run the near-wall correction section (0: skip)")
     ap.add_argument("--copy-probe", action="store_true", help="only copy 1 GiB on the device and exit")
     args = ap.parse_args()
     if args.copy_probe:
@@ -496,6 +581,7 @@ def main():
             f"rel err f32={errs['f32']:.2e} f64={errs['f64']:.2e}")
 
     f1_res = f1_section(prob) if args.f1 and args.config == 3 else None
+    wall_res = wall_section(prob) if args.walls and args.config == 3 else None
     cell_res = cell_section() if args.cell else None
     if cell_res is not None and args.cpu_sample > 0:
         cell_res["cpu_baseline"] = cell_cpu_baseline()
@@ -521,6 +607,7 @@ def main():
                       "f64_slp_pair": f64["slp_pair_ms"], "f64_dlp_pair": f64["dlp_pair_ms"]},
         "pressure_traction": f1_res,
         "periodization_cell": cell_res,
+        "near_wall": wall_res,
         "near": near_res,
         "batch": batch_res,
     }

@@ -364,6 +364,51 @@ S2D_API size_t near_mlp_blob_size(void);
 S2D_API int near_mlp_pack(const float *params, const float *bound, const float *bound_zero, int32_t n_bins,
                           float bin_lo, float bin_w, void *blob, void *stream);
 
+/* ---- walls: spectral upsampling and the near-wall correction ------------
+ *
+ * The paper evaluates the wall double layer at vesicles near a wall by the
+ * plain trapezoid rule and leaves its close evaluation to future work
+ * (Section 4.1 footnote, Conclusions).  These entry points supply the
+ * upsampled-quadrature correction for it, in the form the vesicles' near
+ * field uses: Delta = D_P - D_1, the double layer of the P-times refined
+ * wall minus that of the given one.
+ *
+ * Wall curves: each curve of `walls` is one period of a d-periodic wall, N
+ * nodes (even, >= 4) equispaced in a parameter t in [0, 2 pi), advancing by
+ * +d or -d in x per period (the sign from its first two nodes), normals nx,
+ * ny, density fx, fy (w and kappa are not read).  A curve that is odd, has
+ * fewer than 4 nodes or is inconsistent with curve_off gets NaN outputs. */
+
+/* Workspace bytes for stokes2d_wall_upsample (0 on bad arguments). */
+S2D_API size_t stokes2d_wall_upsample_workspace_size(const s2d_curves *walls, int32_t upsample);
+
+/* The P N-node refinement of every wall curve (upsample = P in 1..32) by
+ * trigonometric interpolation of x - s d t / (2 pi), y, fx and fy (the
+ * Nyquist mode split evenly), with the speed |x'(t)| from spectral
+ * derivatives: outputs [P * walls->n_nodes] device FP64 nodes x, y, unit
+ * normals nx, ny (oriented like the given normal of the coarse node at or
+ * before each fine one), trapezoid weights w = (2 pi / (P N)) |x'|, density
+ * fx, fy; curve_off [n_curves + 1] device int32 = P * walls->curve_off.
+ * FP64, direct DFT per curve (O(P N^2) work). */
+S2D_API int stokes2d_wall_upsample(const s2d_curves *walls, double d, int32_t upsample,
+                                   double *x, double *y, double *nx, double *ny, double *w,
+                                   double *fx, double *fy, int32_t *curve_off,
+                                   void *ws, size_t ws_bytes, void *stream);
+
+/* Workspace bytes for near_wall_correct_eval (0 on bad arguments). */
+S2D_API size_t near_wall_workspace_size(const s2d_curves *walls, const s2d_targets *trg,
+                                        int32_t upsample);
+
+/* Delta = D_P - D_1 of the wall double layer (Section 2.1 Eq. (D)) summed over
+ * images img_lo..img_hi, at free targets (trg->on_curve must be NULL), FP64:
+ * du, dv ([trg->n] device) are written, or Delta is added to them when
+ * accumulate != 0 (so a caller adds it to the plain double layer it holds).
+ * Same image and period rules as stokes2d_dlp_eval. */
+S2D_API int near_wall_correct_eval(const s2d_curves *walls, const s2d_targets *trg, double d,
+                                   int32_t img_lo, int32_t img_hi, int32_t upsample,
+                                   double *du, double *dv, int accumulate,
+                                   void *ws, size_t ws_bytes, void *stream);
+
 /* Benchmarking aid (not capturable, not for production loops): while
  * enabled, each evaluation records a HIP event pair around its pair-sum
  * kernel launch on the caller's stream.  stokes2d_profile_read() waits for

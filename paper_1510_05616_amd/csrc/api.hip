@@ -729,6 +729,183 @@ S2D_API int near_mlp_pack(const float *params, const float *bound, const float *
     return e == hipSuccess ? S2D_OK : hip_fail(e, "MLP pack launch");
 }
 
+// ---------------------------------------------------------------------------
+// walls: spectral upsampling and the near-wall double-layer correction
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int64_t kWallMaxNodes = (INT32_MAX - 4 * s2d::kSuperBlock) / 32;
+
+int check_walls(const s2d_curves *w, double d, int P) {
+    if (!w) return fail(S2D_EINVAL, "walls must not be NULL");
+    if (w->n_nodes < 0 || w->n_nodes > kWallMaxNodes || w->n_curves < 0)
+        return fail(S2D_EINVAL, "walls sizes out of range");
+    if (w->n_nodes > 0 && w->n_curves < 1) return fail(S2D_EINVAL, "walls with nodes need n_curves >= 1");
+    if (w->n_nodes > 0 && (!w->x || !w->y || !w->nx || !w->ny || !w->fx || !w->fy || !w->curve_off))
+        return fail(S2D_EINVAL, "walls x, y, nx, ny, fx, fy, curve_off must not be NULL");
+    if (P < 1 || P > 32) return fail(S2D_EINVAL, "upsample factor must be in 1..32");
+    if (!(std::isfinite(d) && d > 0.0)) return fail(S2D_EINVAL, "period d must be finite and > 0");
+    return S2D_OK;
+}
+
+// fine curves, then the coefficients, in one workspace
+struct WallLayout {
+    size_t fine, foff, coef, total;
+};
+
+WallLayout wall_layout(const s2d_curves *w, int P) {
+    WallLayout L{};
+    const size_t nf = (size_t)P * (size_t)w->n_nodes;
+    L.fine = 0;
+    L.foff = align256(7 * nf * sizeof(double));
+    L.coef = L.foff + align256(((size_t)w->n_curves + 1) * sizeof(int32_t));
+    L.total = L.coef + align256(s2d::wall_scratch(w->n_nodes, P).total);
+    return L;
+}
+
+s2d::WallArgs wall_args(const s2d_curves *w, double d, int P, void *scratch, double *const out[7], int32_t *ooff) {
+    s2d::WallArgs a{};
+    const s2d::WallScratch sc = s2d::wall_scratch(w->n_nodes, P);
+    a.s1 = sc.s1;
+    a.s2 = sc.s2;
+    a.coef = (double *)((char *)scratch + sc.coef);
+    a.part1 = (double *)((char *)scratch + sc.part1);
+    a.part2 = (double *)((char *)scratch + sc.part2);
+    a.n_nodes = w->n_nodes;
+    a.n_curves = w->n_curves;
+    a.P = P;
+    a.off = w->curve_off;
+    a.x = w->x;
+    a.y = w->y;
+    a.nx = w->nx;
+    a.ny = w->ny;
+    a.fx = w->fx;
+    a.fy = w->fy;
+    a.d = d;
+    a.ox = out[0];
+    a.oy = out[1];
+    a.onx = out[2];
+    a.ony = out[3];
+    a.ow = out[4];
+    a.ofx = out[5];
+    a.ofy = out[6];
+    a.ooff = ooff;
+    return a;
+}
+
+// workspace of near_wall_correct_eval: upsampling, two outputs, pair sums
+struct NearWallLayout {
+    WallLayout up;
+    size_t tmp, pair, pair_bytes, total;
+};
+
+NearWallLayout near_wall_layout(const s2d_curves *w, const s2d_targets *t, int P, s2d_curves *fine_shape) {
+    NearWallLayout L{};
+    L.up = wall_layout(w, P);
+    L.tmp = L.up.total;
+    L.pair = L.tmp + align256(4 * (size_t)t->n * sizeof(double));
+    s2d_curves f = *w;
+    f.n_nodes = (int64_t)P * w->n_nodes;
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < kMaxDev && g_dev[dev].init) cus = g_dev[dev].cus;
+    const size_t a = make_plan(S2D_OP_DLP, S2D_FP64, &f, t, cus).total;
+    const size_t b = make_plan(S2D_OP_DLP, S2D_FP64, w, t, cus).total;
+    L.pair_bytes = std::max<size_t>(std::max(a, b), 256);
+    L.total = L.pair + L.pair_bytes;
+    if (fine_shape) *fine_shape = f;
+    return L;
+}
+
+}  // namespace
+
+S2D_API size_t stokes2d_wall_upsample_workspace_size(const s2d_curves *walls, int32_t upsample) {
+    if (!walls || walls->n_nodes < 0 || walls->n_nodes > kWallMaxNodes || upsample < 1 || upsample > 32) return 0;
+    return std::max<size_t>(s2d::wall_scratch(walls->n_nodes, upsample).total, 256);
+}
+
+S2D_API int stokes2d_wall_upsample(const s2d_curves *walls, double d, int32_t upsample, double *x, double *y,
+                                   double *nx, double *ny, double *w, double *fx, double *fy, int32_t *curve_off,
+                                   void *ws, size_t ws_bytes, void *stream) {
+    int rc = check_walls(walls, d, upsample);
+    if (rc != S2D_OK) return rc;
+    if (walls->n_nodes > 0 && (!x || !y || !nx || !ny || !w || !fx || !fy))
+        return fail(S2D_EINVAL, "outputs x, y, nx, ny, w, fx, fy must not be NULL");
+    if (walls->n_curves > 0 && !curve_off) return fail(S2D_EINVAL, "output curve_off must not be NULL");
+    int dev = 0;
+    rc = current_device(&dev);
+    if (rc != S2D_OK) return rc;
+    const size_t need = stokes2d_wall_upsample_workspace_size(walls, upsample);
+    if (!ws || ws_bytes < need)
+        return fail(S2D_EWORKSPACE, "wall workspace too small: need " + std::to_string(need) + " bytes");
+    if (((uintptr_t)ws & 255) != 0) return fail(S2D_EWORKSPACE, "workspace must be 256-byte aligned");
+    double *const out[7] = {x, y, nx, ny, w, fx, fy};
+    const s2d::WallArgs a = wall_args(walls, d, upsample, ws, out, walls->n_curves > 0 ? curve_off : nullptr);
+    if (walls->n_curves == 0) return S2D_OK;
+    const hipError_t e = s2d::wall_upsample_launch(a, (hipStream_t)stream);
+    return e == hipSuccess ? S2D_OK : hip_fail(e, "wall upsample launch");
+}
+
+S2D_API size_t near_wall_workspace_size(const s2d_curves *walls, const s2d_targets *trg, int32_t upsample) {
+    if (!walls || !trg || trg->n < 0 || walls->n_nodes < 0 || walls->n_nodes > kWallMaxNodes ||
+        walls->n_curves < 0 || upsample < 1 || upsample > 32)
+        return 0;
+    return near_wall_layout(walls, trg, upsample, nullptr).total;
+}
+
+S2D_API int near_wall_correct_eval(const s2d_curves *walls, const s2d_targets *trg, double d, int32_t img_lo,
+                                   int32_t img_hi, int32_t upsample, double *du, double *dv, int accumulate,
+                                   void *ws, size_t ws_bytes, void *stream) {
+    int rc = check_walls(walls, d, upsample);
+    if (rc != S2D_OK) return rc;
+    rc = check_args(S2D_OP_DLP, S2D_FP64, walls, trg, d, img_lo, img_hi, 1.0);
+    if (rc != S2D_OK) return rc;
+    if (trg->on_curve) return fail(S2D_EINVAL, "the near-wall correction is for free targets: on_curve must be NULL");
+    if (trg->n > 0 && (!du || !dv)) return fail(S2D_EINVAL, "outputs du, dv must not be NULL");
+    int dev = 0;
+    rc = current_device(&dev);
+    if (rc != S2D_OK) return rc;
+    if (trg->n == 0) return S2D_OK;
+    s2d_curves fine{};
+    const NearWallLayout L = near_wall_layout(walls, trg, upsample, &fine);
+    if (!ws || ws_bytes < L.total)
+        return fail(S2D_EWORKSPACE, "near-wall workspace too small: need " + std::to_string(L.total) + " bytes");
+    if (((uintptr_t)ws & 255) != 0) return fail(S2D_EWORKSPACE, "workspace must be 256-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    char *base = (char *)ws;
+    double *t4 = (double *)(base + L.tmp);     // D_P (u, v), then D_1 (u, v)
+    if (walls->n_nodes == 0) {
+        // no wall: the correction is zero
+        rc = eval(S2D_OP_DLP, S2D_FP64, walls, trg, d, img_lo, img_hi, 1.0, du, dv, accumulate, base + L.pair,
+                  L.pair_bytes, stream);
+        return rc;
+    }
+    const size_t nf = (size_t)fine.n_nodes;
+    double *fp = (double *)(base + L.up.fine);
+    double *const out[7] = {fp, fp + nf, fp + 2 * nf, fp + 3 * nf, fp + 4 * nf, fp + 5 * nf, fp + 6 * nf};
+    int32_t *foff = (int32_t *)(base + L.up.foff);
+    const s2d::WallArgs a = wall_args(walls, d, upsample, base + L.up.coef, out, foff);
+    hipError_t e = s2d::wall_upsample_launch(a, st);
+    if (e != hipSuccess) return hip_fail(e, "wall upsample launch");
+    fine.curve_off = foff;
+    fine.x = out[0];
+    fine.y = out[1];
+    fine.nx = out[2];
+    fine.ny = out[3];
+    fine.w = out[4];
+    fine.kappa = nullptr;
+    fine.fx = out[5];
+    fine.fy = out[6];
+    const int64_t n = trg->n;
+    rc = eval(S2D_OP_DLP, S2D_FP64, &fine, trg, d, img_lo, img_hi, 1.0, t4, t4 + n, 0, base + L.pair,
+              L.pair_bytes, stream);
+    if (rc != S2D_OK) return rc;
+    rc = eval(S2D_OP_DLP, S2D_FP64, walls, trg, d, img_lo, img_hi, 1.0, t4 + 2 * n, t4 + 3 * n, 0, base + L.pair,
+              L.pair_bytes, stream);
+    if (rc != S2D_OK) return rc;
+    e = s2d::delta_combine_launch(n, accumulate, du, dv, t4, st);
+    return e == hipSuccess ? S2D_OK : hip_fail(e, "near-wall combine launch");
+}
+
 S2D_API const char *stokes2d_last_error(void) { return g_err.c_str(); }
 
 S2D_API int stokes2d_version(void) { return 100; }

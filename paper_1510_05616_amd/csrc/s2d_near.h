@@ -53,4 +53,28 @@ hipError_t near_launch_fwd(int64_t n, const float *X, const float *prm, float *Y
 constexpr int kUpMaxN = 256;      // coarse nodes per curve for upsampling
 constexpr int kUpMaxM = 2048;     // fine nodes per curve
 
+// Spectral upsampling of periodic wall curves (wall.hip).
+struct WallArgs {
+    int64_t n_nodes;                                    // coarse nodes, all curves
+    int32_t n_curves, P;
+    const int32_t *off;                                 // [n_curves + 1]
+    const double *x, *y, *nx, *ny, *fx, *fy;
+    double d;
+    int32_t s1, s2;                                     // chunks of the two sums
+    double *coef, *part1, *part2;                       // scratch, WallScratch layout
+    double *ox, *oy, *onx, *ony, *ow, *ofx, *ofy;       // [P n_nodes]
+    int32_t *ooff;                                      // [n_curves + 1] = P off
+};
+// scratch of the upsampling: coefficients [n_nodes] x 8, partial
+// coefficients [s1][n_nodes] x 8, partial fine sums [s2][6][P n_nodes]
+// (byte offsets from the scratch base)
+struct WallScratch {
+    int s1, s2;
+    size_t coef, part1, part2, total;
+};
+WallScratch wall_scratch(int64_t n_nodes, int P);
+hipError_t wall_upsample_launch(const WallArgs &a, hipStream_t st);
+// t = [uf | vf | uc | vc], each [n]: u (+)= uf - uc, v (+)= vf - vc
+hipError_t delta_combine_launch(int64_t n, int accumulate, double *u, double *v, const double *t, hipStream_t st);
+
 }  // namespace s2d

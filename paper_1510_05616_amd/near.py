@@ -57,6 +57,14 @@ def _bind():
     L.near_mlp_blob_size.restype = SZ
     L.near_mlp_pack.argtypes = [P, P, P, I32, F, F, P, P]
     L.near_mlp_pack.restype = I
+    L.stokes2d_wall_upsample_workspace_size.argtypes = [P, I32]
+    L.stokes2d_wall_upsample_workspace_size.restype = SZ
+    L.stokes2d_wall_upsample.argtypes = [P, D, I32, P, P, P, P, P, P, P, P, P, SZ, P]
+    L.stokes2d_wall_upsample.restype = I
+    L.near_wall_workspace_size.argtypes = [P, P, I32]
+    L.near_wall_workspace_size.restype = SZ
+    L.near_wall_correct_eval.argtypes = [P, P, D, I32, I32, I32, P, P, I, P, SZ, P]
+    L.near_wall_correct_eval.restype = I
     _bound = True
     return L
 
@@ -93,6 +101,43 @@ def near_upsampled_slp(ves: Curves, trg: Targets, trg_curve, upsample, mu, u_up,
     _check(L.near_upsampled_slp(ctypes.byref(cs), ctypes.byref(ts), _ptr(trg_curve), int(upsample), float(mu),
                                 _ptr(u_up), _ptr(v_up), _ptr(u_trap), _ptr(v_trap), _ptr(ws), ws.numel(),
                                 _stream(stream)))
+
+
+def stokes2d_wall_upsample(walls: Curves, d, upsample, ws=None, stream=None) -> Curves:
+    """The P-times refined wall curves (nodes, normals, weights, density and
+    curve offsets computed by the library); kappa is left unset."""
+    import types
+    import torch
+    L = _bind()
+    cs = walls.struct()
+    nf = int(upsample) * walls.n_nodes
+    f64 = dict(dtype=torch.float64, device=walls.device)
+    out = {k: torch.empty(nf, **f64) for k in ("x", "y", "nx", "ny", "w", "fx", "fy")}
+    off = torch.empty(walls.n_curves + 1, dtype=torch.int32, device=walls.device)
+    if ws is None:
+        ws = _empty(L.stokes2d_wall_upsample_workspace_size(ctypes.byref(cs), int(upsample)), walls.device)
+    _check(L.stokes2d_wall_upsample(ctypes.byref(cs), float(d), int(upsample), *(_ptr(out[k]) for k in
+                                    ("x", "y", "nx", "ny", "w", "fx", "fy")), _ptr(off), _ptr(ws), ws.numel(),
+                                    _stream(stream)))
+    return Curves(types.SimpleNamespace(kappa=None, curve_off=off, **out), walls.device)
+
+
+def near_wall_workspace_size(walls: Curves, trg: Targets, upsample: int) -> int:
+    L = _bind()
+    cs, ts = walls.struct(), trg.struct()
+    return int(L.near_wall_workspace_size(ctypes.byref(cs), ctypes.byref(ts), int(upsample)))
+
+
+def near_wall_correct_eval(walls: Curves, trg: Targets, d, img_lo, img_hi, upsample, du, dv, accumulate=0,
+                           ws=None, stream=None) -> None:
+    """du, dv (device float64, [trg.n]) = (or +=) D_P - D_1 of the walls."""
+    L = _bind()
+    cs, ts = walls.struct(), trg.struct()
+    if ws is None:
+        ws = _empty(near_wall_workspace_size(walls, trg, upsample), du.device)
+    _check(L.near_wall_correct_eval(ctypes.byref(cs), ctypes.byref(ts), float(d), int(img_lo), int(img_hi),
+                                    int(upsample), _ptr(du), _ptr(dv), int(accumulate), _ptr(ws), ws.numel(),
+                                    _stream(stream)))
 
 
 def near_features_eval(ves: Curves, trg: Targets, trg_curve, X, frame, stream=None) -> None:

@@ -364,6 +364,36 @@ def fluid_points(prob: Problem, n: int, seed: int, gap: float = 0.02):
     return np.concatenate(xs)[:n], np.concatenate(ys)[:n]
 
 
+def near_wall_points(walls: CurveSet, n: int, seed: int, lo: float = 0.05, hi: float = 3.0):
+    """n seeded points near the wall curves, inside the fluid: at a random
+    node i, moved against its normal (normals point out of the fluid) by
+    delta_i = U(lo, hi) node spacings and along the wall by U(-1/2, 1/2)
+    spacings, the spacing taken as the node's weight w_i.  Returns (x, y)."""
+    rng = np.random.default_rng(seed)
+    i = rng.integers(0, walls.x.shape[0], n)
+    a = rng.uniform(lo, hi, n) * walls.w[i]
+    b = rng.uniform(-0.5, 0.5, n) * walls.w[i]
+    nx, ny = walls.nx[i], walls.ny[i]
+    return walls.x[i] - a * nx - b * ny, walls.y[i] - a * ny + b * nx
+
+
+def wall_densities(walls: CurveSet, seed: int, modes: int = 5) -> CurveSet:
+    """The wall curves with a smooth seeded density on each: a random
+    trigonometric polynomial of degree `modes` in the node parameter
+    t = 2 pi j / N, mode-k amplitudes standard normal / k^2."""
+    rng = np.random.default_rng(seed)
+    fx, fy = np.zeros(walls.n_nodes), np.zeros(walls.n_nodes)
+    for c in range(walls.n_curves):
+        s = slice(walls.curve_off[c], walls.curve_off[c + 1])
+        n = s.stop - s.start
+        t = 2 * math.pi * np.arange(n) / n
+        for k in range(1, modes + 1):
+            a = rng.standard_normal(4) / k ** 2
+            fx[s] += a[0] * np.cos(k * t) + a[1] * np.sin(k * t)
+            fy[s] += a[2] * np.cos(k * t) + a[3] * np.sin(k * t)
+    return CurveSet(walls.x, walls.y, walls.nx, walls.ny, walls.w, walls.kappa, fx, fy, walls.curve_off)
+
+
 AREA_C1 = math.pi * 0.3 * 0.17          # the config-1 vesicle area, 0.160221
 
 

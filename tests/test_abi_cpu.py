@@ -153,3 +153,35 @@ def test_cell_argument_checks(L):
     assert L.stokes2d_cell_factor(by(good), 1.5, fake, 1 << 30, None) == s2d.S2D_EINVAL     # rcond
     assert L.stokes2d_cell_factor(by(good), 1e-8, fake, 16, None) == s2d.S2D_EWORKSPACE
     assert L.stokes2d_cell_solve(by(good), None, fake, fake, fake, fake, 1 << 30, None) == s2d.S2D_EINVAL
+
+
+def test_wall_argument_checks(L):
+    import paper_1510_05616_amd as s2d
+    from paper_1510_05616_amd import near as pn
+    pn._bind()
+    fake = ctypes.c_void_p(0x1000)
+    by = ctypes.byref
+    walls = s2d._Curves(64, 2, fake, fake, fake, fake, fake, None, None, fake, fake)    # w, kappa unused
+    _, ts = _structs()
+    _, ts_on = _structs(on=True)
+    o = [fake] * 8
+    assert L.stokes2d_wall_upsample_workspace_size(None, 8) == 0
+    assert L.stokes2d_wall_upsample_workspace_size(by(walls), 0) == 0
+    assert L.stokes2d_wall_upsample_workspace_size(by(walls), 8) >= 64 * 64
+    assert L.near_wall_workspace_size(by(walls), by(ts), 8) > 8 * 64 * 7 * 8
+    assert L.near_wall_workspace_size(by(walls), by(ts), 33) == 0
+    # upsample factor, period, missing normals, missing outputs
+    assert L.stokes2d_wall_upsample(by(walls), 1.0, 0, *o, fake, 1 << 20, None) == s2d.S2D_EINVAL
+    assert L.stokes2d_wall_upsample(by(walls), 0.0, 4, *o, fake, 1 << 20, None) == s2d.S2D_EINVAL
+    non = s2d._Curves(64, 2, fake, fake, fake, None, fake, None, None, fake, fake)
+    assert L.stokes2d_wall_upsample(by(non), 1.0, 4, *o, fake, 1 << 20, None) == s2d.S2D_EINVAL
+    assert L.stokes2d_wall_upsample(by(walls), 1.0, 4, None, *o[1:], fake, 1 << 20, None) == s2d.S2D_EINVAL
+    none = s2d._Curves(64, 0, fake, fake, fake, fake, fake, None, None, fake, fake)     # nodes but no curves
+    assert L.stokes2d_wall_upsample(by(none), 1.0, 4, *o, fake, 1 << 20, None) == s2d.S2D_EINVAL
+    # the correction: free targets only, outputs, images
+    assert L.near_wall_correct_eval(by(walls), by(ts_on), 1.0, -1, 1, 8, fake, fake, 0, fake, 1 << 30,
+                                    None) == s2d.S2D_EINVAL
+    assert L.near_wall_correct_eval(by(walls), by(ts), 1.0, -1, 1, 8, None, fake, 0, fake, 1 << 30,
+                                    None) == s2d.S2D_EINVAL
+    assert L.near_wall_correct_eval(by(walls), by(ts), 1.0, 1, -1, 8, fake, fake, 0, fake, 1 << 30,
+                                    None) == s2d.S2D_EINVAL
