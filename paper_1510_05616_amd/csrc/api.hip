@@ -288,6 +288,11 @@ int eval(int op, int mode, const s2d_curves *src, const s2d_targets *trg, double
 
 }  // namespace
 
+namespace s2d {
+int set_error(int code, const std::string &msg) { return fail(code, msg); }
+int device_ready(int *dev) { return current_device(dev); }
+}  // namespace s2d
+
 extern "C" {
 
 S2D_API int stokes2d_init(int device) {

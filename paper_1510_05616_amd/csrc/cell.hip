@@ -284,6 +284,10 @@ rocblas_handle handle_for(hipStream_t st, std::string &err) {
 
 }  // namespace
 
+std::mutex &blas_mutex() { return g_hmu; }
+
+void *blas_handle(hipStream_t st, std::string &err) { return (void *)handle_for(st, err); }
+
 std::string cell_factor(const CellArgs &g, double rcond, void *ws, hipStream_t st) {
     const CellLayout L = cell_layout(g);
     char *b = (char *)ws;

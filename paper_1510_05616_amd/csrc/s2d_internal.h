@@ -5,6 +5,7 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <mutex>
 #include <string>
 
 #include "../../include/stokes2d.h"
@@ -127,6 +128,18 @@ hipError_t launch_pair(const Plan &p, const PairArgs &a, hipStream_t st);
 hipError_t launch_kress(const Plan &p, const s2d_curves *src, const s2d_targets *trg,
                         void *ws, hipStream_t st);
 hipError_t launch_final(const Plan &p, const FinalArgs &a, hipStream_t st);
+
+// the rocBLAS handle of the current device bound to stream st (a
+// rocblas_handle; cell.hip), created on first use; hold blas_mutex() while
+// using it
+std::mutex &blas_mutex();
+void *blas_handle(hipStream_t st, std::string &err);
+
+// error state and device checks shared by the entry points (api.hip):
+// set_error records the calling thread's message and returns code;
+// device_ready fails unless stokes2d_init ran for the current device
+int set_error(int code, const std::string &msg);
+int device_ready(int *dev);
 
 // batched evaluation (batch.hip)
 size_t batch_workspace_size(int mode, int32_t n_inst, const s2d_instance *inst);

@@ -185,3 +185,30 @@ def test_wall_argument_checks(L):
                                     None) == s2d.S2D_EINVAL
     assert L.near_wall_correct_eval(by(walls), by(ts), 1.0, 1, -1, 8, fake, fake, 0, fake, 1 << 30,
                                     None) == s2d.S2D_EINVAL
+
+
+def test_vesicle_argument_checks(L):
+    import paper_1510_05616_amd as s2d
+    from paper_1510_05616_amd import vesicle as pv
+    pv._bind()
+    fake = ctypes.c_void_p(0x1000)
+    by = ctypes.byref
+    good = pv.params(dt=1e-3)
+    assert L.ves_step_workspace_size(96, 1, by(good)) > 0
+    assert L.ves_step_workspace_size(96, 1, None) == 0
+    for field, value in (("dt", 0.0), ("mu", -1.0), ("restart", 0), ("restart", 129), ("max_iter", 0),
+                         ("mode", 3), ("kappa_b", -1.0), ("precond", 1), ("nmax", 600)):
+        bad = pv.params(dt=1e-3)
+        setattr(bad, field, value)
+        assert L.ves_step_solve(96, 1, fake, fake, fake, by(bad), fake, None, None, fake, 1 << 30,
+                                None) == s2d.S2D_EINVAL, field
+    img = pv.params(dt=1e-3, img_lo=-1, img_hi=1)          # images need d > 0
+    assert L.ves_step_solve(96, 1, fake, fake, fake, by(img), fake, None, None, fake, 1 << 30,
+                            None) == s2d.S2D_EINVAL
+    half = pv.params(dt=1e-3)
+    half.u_resp_x = 0x2000                                  # u_resp comes in pairs
+    assert L.ves_step_apply(96, 1, fake, fake, fake, by(half), fake, fake, None, fake, 1 << 30,
+                            None) == s2d.S2D_EINVAL
+    assert L.ves_forces(96, 1, fake, fake, fake, None, 1.0, fake, None, None, None, None) == s2d.S2D_EINVAL
+    assert L.ves_area_correct(96, 1, fake, fake, fake, None, None) == s2d.S2D_EINVAL
+    assert L.ves_measure(96, 0, fake, fake, fake, fake, fake, None) == s2d.S2D_EINVAL
