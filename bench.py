@@ -308,6 +308,74 @@ def wall_section(prob, n_trg=20000, P=8, reps=5):
                                        "given double layers by direct FP64 sums"}}
 
 
+def step_section(prob, steps=3, dt=1e-4, kappa_b=1.0):
+    """Vesicle time steps (Algorithm 1, steps 6-9) of the 128k channel's
+    1,000 vesicles x 96 nodes in the periodic free-space setting (single
+    layer over images -1..1, d = 64 pi; no wall response): the step system
+    solved by GMRES (right-preconditioned by the factored per-vesicle self
+    blocks), update, area correction, reparameterization; FP64 solve to
+    1e-10 (with FP32C single-layer sums GMRES stalls near 1.5e-5: the
+    operator amplifies their rounding through D_s^4).  The oracle times one
+    step of 4 of the vesicles on the host."""
+    import torch
+    import oracle
+    import paper_1510_05616_amd as s2d
+    from oracle import vesicle as ov
+    from paper_1510_05616_amd import vesicle as pv
+    ves = prob.ves
+    n = ves.n_nodes
+    out = {"workload": "1,000 vesicles x 96 nodes of the 128k channel, images -1..1 (d = 64 pi), "
+                       f"dt = {dt}, kappa_B = {kappa_b}, mu = {prob.mu}: one step = GMRES solve of the "
+                       "288,000-unknown step system + update + area correction + reparameterization",
+           "n_nodes": n}
+    for name, mode, tol in (("f64", s2d.S2D_FP64, 1e-10),):
+        V = pv.Vesicles(ves.x, ves.y, ves.curve_off)
+        L0, A0 = V.measure()
+        p = pv.params(mode=mode, dt=dt, kappa_b=kappa_b, mu=prob.mu, d=prob.d, img_lo=-1, img_hi=1, L0=L0,
+                      tol=tol, restart=64, max_iter=500, nmax=96)
+        ws = V.workspace(p)
+        V.time_step(p, A0=A0, ws=ws)                     # warm-up
+        torch.cuda.synchronize()
+        s2d.stokes2d_profile_read(s2d.S2D_OP_SLP)
+        s2d.stokes2d_profile_enable(True)
+        its = []
+        t0 = time.time()
+        for _ in range(steps):
+            it, res = V.time_step(p, A0=A0, ws=ws)
+            its.append((it, res))
+        torch.cuda.synchronize()
+        ms = (time.time() - t0) * 1e3 / steps
+        s2d.stokes2d_profile_enable(False)
+        kms, kn = s2d.stokes2d_profile_read(s2d.S2D_OP_SLP)
+        pairs = n * n * 3
+        avg = kms / max(kn, 1)
+        tf = FLOPS_PER_PAIR * pairs / (avg * 1e-3) / 1e12
+        peak = PEAK[name]
+        out[name] = {"ms_per_step": ms, "value": 1e3 / ms, "unit": "time steps/s", "gmres": its,
+                     "single_layer_launches_per_step": kn / steps, "slp_ms_per_step": kms / steps,
+                     "roofline": {"bound": "alu", "kernel": "pair_kernel<SLP> (on-curve, Kress self terms)",
+                                  "achieved": tf, "peak": peak / 1e12, "unit": "TFLOP/s", "frac": tf * 1e12 / peak,
+                                  "flops_per_pair": FLOPS_PER_PAIR, "pairs_per_launch": pairs,
+                                  "kernel_ms": avg, "traffic": None}}
+        log(f"step {name}: {ms:.1f} ms per time step, GMRES {its}, {kn / steps:.1f} single-layer launches per "
+            f"step ({kms / steps:.1f} ms), pair kernel {avg:.2f} ms = {tf:.1f} TFLOP/s")
+    # the oracle: one step of 4 vesicles (dense solve of the 1,152-unknown system)
+    off = ves.curve_off
+    s = slice(0, int(off[4]))
+    sub_off = off[:5] - off[0]
+    x, y = ves.x[s].copy(), ves.y[s].copy()
+    g = ov.geometry(x, y, sub_off)
+    t0 = time.time()
+    ov.time_step(x, y, np.zeros(x.shape[0]), sub_off, dt, kappa_b, prob.mu, L0=ov.arc_lengths(g),
+                 A0=ov.areas(x, y, sub_off), d=prob.d, img_lo=-1, img_hi=1)
+    t_or = time.time() - t0
+    out["cpu_baseline"] = {"value": 1.0 / t_or, "unit": "time steps/s", "kind": "oracle",
+                           "cores": oracle.num_threads(),
+                           "sample": "one step of 4 of the 1,000 vesicles (384 nodes, dense FP64 solve)"}
+    log(f"step oracle: {t_or:.2f} s for one step of 4 vesicles")
+    return out
+
+
 def cell_section(n_wall=4000, K=32, M=128, reps=5):
     """Periodization system of an empty channel cell at the paper's sizes
     (y = +-(1 + 0.3 sin x), d = 2 pi, 4000 nodes per wall, K = 32 side
@@ -515,6 +583,7 @@ def main():
     ap.add_argument("--f1", type=int, default=1, help="run the pressure/traction section (0: skip)")
     ap.add_argument("--cell", type=int, default=1, help="run the periodization-system section (0: skip)")
     ap.add_argument("--walls", type=int, default=1, help="run the near-wall correction section (0: skip)")
+    ap.add_argument("--step", type=int, default=1, help="run the vesicle time-step section (0: skip)")
     ap.add_argument("--copy-probe", action="store_true", help="only copy 1 GiB on the device and exit")
     args = ap.parse_args()
     if args.copy_probe:
@@ -582,6 +651,7 @@ def main():
 
     f1_res = f1_section(prob) if args.f1 and args.config == 3 else None
     wall_res = wall_section(prob) if args.walls and args.config == 3 else None
+    step_res = step_section(prob) if args.step and args.config == 3 else None
     cell_res = cell_section() if args.cell else None
     if cell_res is not None and args.cpu_sample > 0:
         cell_res["cpu_baseline"] = cell_cpu_baseline()
@@ -608,6 +678,7 @@ def main():
         "pressure_traction": f1_res,
         "periodization_cell": cell_res,
         "near_wall": wall_res,
+        "time_step": step_res,
         "near": near_res,
         "batch": batch_res,
     }
