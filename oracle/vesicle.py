@@ -269,3 +269,56 @@ def bending_energy(x, y, off, kappa_b=1.0):
     xss, yss = d_s(xs, g), d_s(ys, g)
     k = xs * yss - ys * xss
     return np.array([0.5 * kappa_b * np.dot(k[s] ** 2, g.w[s]) for s in _curves(off)])
+
+
+# ---------------------------------------------------------------------------
+# the channel's response to the vesicles (Algorithm 1, steps 3-5)
+# ---------------------------------------------------------------------------
+def _vesicle_source(x, y, off, fx, fy):
+    g = geometry(x, y, off)
+    return SimpleNamespace(x=x, y=y, nx=g.nx, ny=g.ny, w=g.w, kappa=g.kappa, fx=fx, fy=fy,
+                           curve_off=np.asarray(off, np.int32))
+
+
+def channel_response(walls, side_y, d, M, mu, x, y, off, fx, fy, p_drive, x_left=0.0, radius=None, tx=None,
+                     ty=None):
+    """Steps 3-5 of Algorithm 1 for vesicles with force density f:
+      v_U, v_D = -S^near f on the walls (Eq. (vesU)),
+      g_u = -S_{gamma-d} f|_R + S_{gamma+d} f|_L,
+      g_T = -T(S_{gamma-d} f, Q_{gamma-d} f)|_R + T(S_{gamma+d} f, Q_{gamma+d} f)|_L + p_drive n
+    (Eq. (vesgT), n = (1, 0); p_drive is the pressure drop p(L) - p(R) per
+    period), the cell system (Eq. (bsys)) for tau and c, and
+    u_resp = D^near tau + sum_m c_m phi_m (Eq. (urep)) at the vesicle nodes,
+    or at the points (tx, ty) when given.  Returns (u_resp (n, 2), p_resp
+    (n,), tau, c, (px, py))."""
+    import oracle
+    from . import els
+    src = _vesicle_source(x, y, off, fx, fy)
+    A, B, C, Q, (px, py) = els.assemble(walls, side_y, d, M, mu, x_left, radius)
+    vx, vy = oracle.slp(src, walls.x, walls.y, None, None, d, -1, 1, mu)
+    v = -np.stack([vx, vy], 1).reshape(-1)
+    K = len(side_y)
+    xl = np.full(K, x_left)
+    xr = xl + d
+    ones, zeros = np.ones(K), np.zeros(K)
+    rx, ry = oracle.slp(src, xr, side_y, None, None, d, -1, -1, mu)
+    lx, ly = oracle.slp(src, xl, side_y, None, None, d, 1, 1, mu)
+    gu = np.stack([lx - rx, ly - ry], 1).reshape(-1)
+    trx, try_ = oracle.slp_traction(src, xr, side_y, ones, zeros, d, -1, -1)
+    tlx, tly = oracle.slp_traction(src, xl, side_y, ones, zeros, d, 1, 1)
+    gt = np.stack([tlx - trx + p_drive, tly - try_], 1).reshape(-1)
+    tau, c = els.solve(A, B, C, Q, v, np.concatenate([gu, gt]))
+    X = x if tx is None else tx
+    Y = y if ty is None else ty
+    u, p = els.field(walls, tau, px, py, c, d, mu, X, Y)
+    return u, p, tau, c, (px, py)
+
+
+def imposed_field(x, y, off, fx, fy, d, mu, tx, ty):
+    """The vesicles' imposed flow S^near f and pressure Q^near f (images
+    -1..1, Eq. (utotrep)) at free points."""
+    import oracle
+    src = _vesicle_source(x, y, off, fx, fy)
+    u, v = oracle.slp(src, tx, ty, None, None, d, -1, 1, mu)
+    p = oracle.slp_pressure(src, tx, ty, d, -1, 1)
+    return np.stack([u, v], 1), p

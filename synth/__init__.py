@@ -139,6 +139,10 @@ def wall_profile(kind: str):
         return (lambda x: 1.0 + 0.3 * np.sin(x),
                 lambda x: 0.3 * np.cos(x),
                 lambda x: -0.3 * np.sin(x))
+    if kind == "flat":        # y = +-1 (the straight channel)
+        return (lambda x: np.ones_like(np.asarray(x, float)),
+                lambda x: np.zeros_like(np.asarray(x, float)),
+                lambda x: np.zeros_like(np.asarray(x, float)))
     if kind == "sin13":       # y = +-(1.5 + 0.4 sin x + 0.2 sin 3x)
         return (lambda x: 1.5 + 0.4 * np.sin(x) + 0.2 * np.sin(3 * x),
                 lambda x: 0.4 * np.cos(x) + 0.6 * np.cos(3 * x),

@@ -200,3 +200,43 @@ def test_table4_convergence_orders(corrections):
         assert all(1.5 < r < 2.5 for r in rL), rL
         eA = [out[M][3] for M in Ms]
         assert all(1.5 < eA[i] / eA[i + 1] < 2.5 for i in range(2)), eA
+
+
+# ---------------------------------------------------------------------------
+# the channel's response (Algorithm 1, steps 3-5)
+# ---------------------------------------------------------------------------
+def _two_in_channel():
+    x1, y1 = _ellipse(0.3, 0.15, 32, phi=0.3, cx=math.pi, cy=0.1)
+    x2, y2 = _ellipse(0.25, 0.15, 32, phi=-0.4, cx=1.5, cy=-0.3)
+    return np.r_[x1, x2], np.r_[y1, y2], np.array([0, 32, 64])
+
+
+def test_channel_response_flat_channel_is_poiseuille():
+    # no vesicle force and a pressure drop p_drive per period d in the straight
+    # channel |y| < 1: u = p_drive / (2 mu d) (1 - y^2), v = 0
+    walls, sy, d = synth.make_channel(128, 16, profile="flat")
+    x, y, off = _two_in_channel()
+    mu, pd = 0.7, 0.9
+    u, p, _, _, _ = ov.channel_response(walls, sy, d, 64, mu, x, y, off, np.zeros(64), np.zeros(64), pd)
+    ex = pd / (2 * mu * d) * (1 - y ** 2)
+    assert np.abs(u[:, 0] - ex).max() < 1e-10 and np.abs(u[:, 1]).max() < 1e-10
+
+
+def test_channel_response_periodic_with_the_pressure_drop():
+    # vesicle bending forces in the channel y = +-(1 + 0.3 sin x): the total
+    # flow S^near f + u_resp is periodic between L and R at heights that are
+    # not collocation heights, and the pressure falls by p_drive per period
+    walls, sy, d = synth.make_channel(256, 16)
+    x, y, off = _two_in_channel()
+    g = ov.geometry(x, y, off)
+    fbx, fby, _, _ = ov.forces(g, np.zeros(64), 1.0)
+    mu, pd = 0.7, 0.9
+    ys = np.linspace(-0.7, 0.7, 12)
+    X, Y = np.r_[np.zeros(12), np.full(12, d)], np.r_[ys, ys]
+    ur, pr, _, _, _ = ov.channel_response(walls, sy, d, 64, mu, x, y, off, fbx, fby, pd, tx=X, ty=Y)
+    ui, pi = ov.imposed_field(x, y, off, fbx, fby, d, mu, X, Y)
+    ut, pt = ur + ui, pr + pi
+    assert np.abs(ut[:12] - ut[12:]).max() < 1e-8 * np.abs(ut).max()
+    assert np.abs((pt[:12] - pt[12:]) - pd).max() < 1e-7
+    # the response alone is not periodic (the imposed near-image flow is not)
+    assert np.abs(ur[:12] - ur[12:]).max() > 1e-3 * np.abs(ur).max()
