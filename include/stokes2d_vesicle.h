@@ -47,6 +47,12 @@ S2D_API int ves_forces(int64_t n_nodes, int32_t n_curves, const int32_t *curve_o
                        const double *x, const double *y, const double *sigma, double kappa_b,
                        double *fbx, double *fby, double *fsx, double *fsy, void *stream);
 
+/* The total membrane force f = f_b + f_sigma (Algorithm 1, step 2) into
+ * fx, fy; sigma may be NULL (bending only). */
+S2D_API int ves_total_force(int64_t n_nodes, int32_t n_curves, const int32_t *curve_off,
+                            const double *x, const double *y, const double *sigma, double kappa_b,
+                            double *fx, double *fy, void *stream);
+
 /* Perimeter (sum of weights) and enclosed area (integral of x y_alpha
  * d alpha, Appendix B) of every curve: [n_curves] each; either may be NULL. */
 S2D_API int ves_measure(int64_t n_nodes, int32_t n_curves, const int32_t *curve_off,
@@ -122,6 +128,28 @@ S2D_API int ves_time_step(int64_t n_nodes, int32_t n_curves, const int32_t *curv
                           const double *A0, int reparam, double *u, double *v,
                           int32_t *iters, double *rel_res,
                           void *ws, size_t ws_bytes, void *stream);
+
+/* The channel's response to the vesicles, Algorithm 1 steps 3-5 (Section
+ * 3.1), for the force density (fx, fy) on the vesicles (e.g. f_b + f_sigma
+ * from ves_forces) and a cell factored by stokes2d_cell_factor (cell_ws):
+ *   v_U, v_D = -S^near f on the walls (Eq. (vesU)),
+ *   g_u = -S_{gamma-d} f|_R + S_{gamma+d} f|_L,
+ *   g_T = -T(S_{gamma-d} f, Q_{gamma-d} f)|_R + T(S_{gamma+d} f, Q_{gamma+d} f)|_L
+ *         + p_drive (1, 0)                   (Eq. (vesgT); p_drive is the
+ *                                           pressure drop p(L) - p(R) per period),
+ * the cell system for tau and c, and u_resp = D^near tau + sum_m c_m phi_m
+ * (Eq. (urep)) at the vesicle nodes: u_resp_x, u_resp_y [n_nodes] (written),
+ * the input u_resp of ves_step_params.  mode: the s2d_mode of the layer
+ * sums; the wall double layer at the vesicles uses the plain trapezoid rule
+ * (close evaluation: near_wall_correct_eval).  cell_ws also serves as the
+ * solve's scratch: calls sharing it must be ordered on one stream. */
+S2D_API size_t ves_response_workspace_size(const s2d_cell *cell, int64_t n_nodes, int32_t n_curves,
+                                           int mode);
+S2D_API int ves_channel_response(const s2d_cell *cell, void *cell_ws, size_t cell_ws_bytes,
+                                 int64_t n_nodes, int32_t n_curves, const int32_t *curve_off,
+                                 const double *x, const double *y, const double *fx,
+                                 const double *fy, double p_drive, int mode, double *u_resp_x,
+                                 double *u_resp_y, void *ws, size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -3,6 +3,7 @@
 // all scratch lives in the caller's workspace.
 #include "s2d_internal.h"
 #include "s2d_near.h"
+#include "../../include/stokes2d_vesicle.h"
 
 #include <algorithm>
 #include <cmath>
@@ -446,6 +447,154 @@ S2D_API int stokes2d_cell_solve(const s2d_cell *cell, const double *v, const dou
     if (rc != S2D_OK) return rc;
     const std::string err = s2d::cell_solve(g, v, gv, tau, c, ws, (hipStream_t)stream);
     return err.empty() ? S2D_OK : fail(S2D_EHIP, err);
+}
+
+// ---------------------------------------------------------------------------
+// the channel's response to vesicles (Algorithm 1, steps 3-5)
+// ---------------------------------------------------------------------------
+namespace {
+
+struct RespLayout {
+    size_t v, g, tau, c, vw, side, s, tauxy, cxy, prox, poff, geo, eval, eval_bytes, total;
+};
+
+RespLayout resp_layout(const s2d_cell *cell, int64_t n, int32_t nc, int mode) {
+    const size_t d = sizeof(double);
+    const int64_t nw = cell->walls.n_nodes;
+    const size_t K = (size_t)cell->n_side, M = (size_t)cell->n_proxy;
+    RespLayout L{};
+    size_t o = 0;
+    L.v = o;
+    o += align256(2 * nw * d);
+    L.g = o;
+    o += align256(4 * K * d);
+    L.tau = o;
+    o += align256(2 * nw * d);
+    L.c = o;
+    o += align256(2 * M * d);
+    L.vw = o;
+    o += align256(2 * nw * d);
+    L.side = o;
+    o += align256(4 * K * d);
+    L.s = o;
+    o += align256(8 * K * d);
+    L.tauxy = o;
+    o += align256(2 * nw * d);
+    L.cxy = o;
+    o += align256(2 * M * d);
+    L.prox = o;
+    o += align256(3 * M * d);
+    L.poff = o;
+    o += align256(2 * sizeof(int32_t));
+    L.geo = o;
+    o += align256(3 * (size_t)n * d);
+    // the evaluations run in turn on one stream and share one workspace;
+    // the shapes below carry placeholders for the arrays (only sizes are read)
+    const double *a = (const double *)1;
+    const int32_t *ia = (const int32_t *)1;
+    const s2d_curves ves{n, nc, ia, a, a, a, a, a, nullptr, a, a};
+    const s2d_curves wal{nw, cell->walls.n_curves, ia, a, a, a, a, a, nullptr, a, a};
+    const s2d_curves prx{(int64_t)M, 1, ia, a, a, a, a, a, nullptr, a, a};
+    const s2d_targets tw{nw, a, a, nullptr, nullptr}, ts{(int64_t)K, a, a, nullptr, nullptr},
+        tv{n, a, a, nullptr, nullptr};
+    size_t e = 256;
+    e = std::max(e, stokes2d_workspace_size(S2D_OP_SLP, mode, &ves, &tw));
+    e = std::max(e, stokes2d_workspace_size(S2D_OP_SLP, mode, &ves, &ts));
+    e = std::max(e, stokes2d_workspace_size(S2D_OP_SLP_TRACTION, mode, &ves, &ts));
+    e = std::max(e, stokes2d_workspace_size(S2D_OP_DLP, mode, &wal, &tv));
+    e = std::max(e, stokes2d_workspace_size(S2D_OP_SLP, mode, &prx, &tv));
+    L.eval = o;
+    L.eval_bytes = e;
+    o += align256(e);
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+S2D_API size_t ves_response_workspace_size(const s2d_cell *cell, int64_t n_nodes, int32_t n_curves, int mode) {
+    s2d::CellArgs g{};
+    if (check_cell(cell, &g) != S2D_OK || n_nodes < 0 || n_curves < 0 || (mode != S2D_FP64 && mode != S2D_FP32C))
+        return 0;
+    return resp_layout(cell, n_nodes, n_curves, mode).total;
+}
+
+S2D_API int ves_channel_response(const s2d_cell *cell, void *cell_ws, size_t cell_ws_bytes, int64_t n_nodes,
+                                 int32_t n_curves, const int32_t *curve_off, const double *x, const double *y,
+                                 const double *fx, const double *fy, double p_drive, int mode, double *u_resp_x,
+                                 double *u_resp_y, void *ws, size_t ws_bytes, void *stream) {
+    using namespace s2d;
+    CellArgs g{};
+    int rc = check_cell(cell, &g);
+    if (rc != S2D_OK) return rc;
+    rc = check_cell_ws(g, cell_ws, cell_ws_bytes);
+    if (rc != S2D_OK) return rc;
+    if (mode != S2D_FP64 && mode != S2D_FP32C) return fail(S2D_EINVAL, "mode must be an s2d_mode");
+    if (n_nodes < 0 || n_curves < 0) return fail(S2D_EINVAL, "vesicle sizes out of range");
+    if (n_nodes > 0 && (n_curves < 1 || !curve_off || !x || !y || !fx || !fy || !u_resp_x || !u_resp_y))
+        return fail(S2D_EINVAL, "curve_off, x, y, fx, fy and the outputs must not be NULL");
+    if (!std::isfinite(p_drive)) return fail(S2D_EINVAL, "p_drive must be finite");
+    int dev = 0;
+    rc = current_device(&dev);
+    if (rc != S2D_OK) return rc;
+    const RespLayout L = resp_layout(cell, n_nodes, n_curves, mode);
+    if (!ws || ws_bytes < L.total)
+        return fail(S2D_EWORKSPACE, "response workspace too small: need " + std::to_string(L.total) + " bytes");
+    if (((uintptr_t)ws & 255) != 0) return fail(S2D_EWORKSPACE, "workspace must be 256-byte aligned");
+    if (n_nodes == 0) return S2D_OK;
+    char *b = (char *)ws;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n = n_nodes, nw = cell->walls.n_nodes;
+    const int K = cell->n_side, M = cell->n_proxy;
+    const double d = cell->d, mu = cell->mu;
+    void *ew = b + L.eval;
+    const size_t eb = L.eval_bytes;
+    // the vesicles as single-layer sources of f
+    double *geo = (double *)(b + L.geo);
+    rc = ves_geometry(n, n_curves, curve_off, x, y, nullptr, geo, geo + n, geo + 2 * n, nullptr, nullptr, stream);
+    if (rc != S2D_OK) return rc;
+    const s2d_curves ves{n, n_curves, curve_off, x, y, geo + n, geo + 2 * n, geo, nullptr, fx, fy};
+    // step 3: -S^near f on the walls; S and T of the single far images at R and L
+    double *vw = (double *)(b + L.vw);
+    const s2d_targets tw{nw, cell->walls.x, cell->walls.y, nullptr, nullptr};
+    rc = eval(S2D_OP_SLP, mode, &ves, &tw, d, -1, 1, mu, vw, vw + nw, 0, ew, eb, stream);
+    if (rc != S2D_OK) return rc;
+    double *side = (double *)(b + L.side), *sxl = side, *sxr = side + K, *mx = side + 2 * K, *my = side + 3 * K;
+    hipError_t e = resp_side_launch(K, cell->side_y, cell->x_left, d, sxl, sxr, mx, my, st);
+    if (e != hipSuccess) return hip_fail(e, "response side targets");
+    double *s = (double *)(b + L.s);
+    const s2d_targets tR{K, sxr, cell->side_y, nullptr, nullptr}, tL{K, sxl, cell->side_y, nullptr, nullptr};
+    if ((rc = eval(S2D_OP_SLP, mode, &ves, &tR, d, -1, -1, mu, s, s + K, 0, ew, eb, stream)) != S2D_OK) return rc;
+    if ((rc = eval(S2D_OP_SLP, mode, &ves, &tL, d, 1, 1, mu, s + 2 * K, s + 3 * K, 0, ew, eb, stream)) != S2D_OK)
+        return rc;
+    if ((rc = eval(S2D_OP_SLP_TRACTION, mode, &ves, &tR, d, -1, -1, mu, s + 4 * K, s + 5 * K, 0, ew, eb, stream,
+                   mx, my)) != S2D_OK)
+        return rc;
+    if ((rc = eval(S2D_OP_SLP_TRACTION, mode, &ves, &tL, d, 1, 1, mu, s + 6 * K, s + 7 * K, 0, ew, eb, stream, mx,
+                   my)) != S2D_OK)
+        return rc;
+    double *v = (double *)(b + L.v), *gv = (double *)(b + L.g);
+    e = resp_pack_launch(nw, vw, vw + nw, K, s, p_drive, v, gv, st);
+    if (e != hipSuccess) return hip_fail(e, "response data");
+    // step 4: the cell system
+    double *tau = (double *)(b + L.tau), *c = (double *)(b + L.c);
+    const std::string err = cell_solve(g, v, gv, tau, c, cell_ws, st);
+    if (!err.empty()) return fail(S2D_EHIP, err);
+    // step 5: D^near tau + sum c_m phi_m at the vesicle nodes
+    double *tx = (double *)(b + L.tauxy), *ty = tx + nw, *cx = (double *)(b + L.cxy), *cy = cx + M;
+    double *px = (double *)(b + L.prox), *py = px + M, *pw = px + 2 * M;
+    int32_t *poff = (int32_t *)(b + L.poff);
+    e = resp_unpack_launch(nw, tau, tx, ty, M, c, cell->proxy_cx, cell->proxy_cy, cell->proxy_r, cx, cy, px, py, pw,
+                           poff, st);
+    if (e != hipSuccess) return hip_fail(e, "response densities");
+    s2d_curves wal = cell->walls;
+    wal.fx = tx;
+    wal.fy = ty;
+    const s2d_targets tv{n, x, y, nullptr, nullptr};
+    if ((rc = eval(S2D_OP_DLP, mode, &wal, &tv, d, -1, 1, 1.0, u_resp_x, u_resp_y, 0, ew, eb, stream)) != S2D_OK)
+        return rc;
+    const s2d_curves prx{(int64_t)M, 1, poff, px, py, nullptr, nullptr, pw, nullptr, cx, cy};
+    return eval(S2D_OP_SLP, mode, &prx, &tv, d, 0, 0, mu, u_resp_x, u_resp_y, 1, ew, eb, stream);
 }
 
 S2D_API int stokes2d_profile_enable(int on) {

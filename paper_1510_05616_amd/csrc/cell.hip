@@ -248,6 +248,90 @@ hipError_t cell_pinv_launch(int m, int n, const double *sv, const double *U, con
 }
 
 // ---------------------------------------------------------------------------
+// data of the channel's response to vesicles (Algorithm 1, steps 3-5)
+// ---------------------------------------------------------------------------
+namespace {
+
+// side-wall targets: L = (xl, side_y), R = (xl + d, side_y), normal (1, 0)
+__global__ __launch_bounds__(256) void resp_side(int K, const double *side_y, double xl, double d, double *sxl,
+                                                 double *sxr, double *mx, double *my) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    sxl[k] = xl;
+    sxr[k] = xl + d;
+    mx[k] = 1.0;
+    my[k] = 0.0;
+}
+
+// v = -(S^near f on the walls), interleaved per node
+__global__ __launch_bounds__(256) void resp_pack_v(int64_t nw, const double *vwx, const double *vwy, double *v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nw) return;
+    v[2 * i] = -vwx[i];
+    v[2 * i + 1] = -vwy[i];
+}
+
+// g = [L - R velocity ; L - R traction + p_drive (1, 0)], interleaved per height;
+// s = [rx | ry | lx | ly | trx | try | tlx | tly], K each
+__global__ __launch_bounds__(256) void resp_pack_g(int K, const double *s, double p_drive, double *g) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    g[2 * k] = s[2 * K + k] - s[k];
+    g[2 * k + 1] = s[3 * K + k] - s[K + k];
+    g[2 * K + 2 * k] = s[6 * K + k] - s[4 * K + k] + p_drive;
+    g[2 * K + 2 * k + 1] = s[7 * K + k] - s[5 * K + k];
+}
+
+// tau, c de-interleaved; proxy points on their circle, unit weights
+__global__ __launch_bounds__(256) void resp_unpack(int64_t nw, const double *tau, double *tx, double *ty, int M,
+                                                   const double *c, double pcx, double pcy, double R, double *cx,
+                                                   double *cy, double *px, double *py, double *pw, int32_t *poff) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nw) {
+        tx[i] = tau[2 * i];
+        ty[i] = tau[2 * i + 1];
+    }
+    if (i < M) {
+        cx[i] = c[2 * i];
+        cy[i] = c[2 * i + 1];
+        double sn, cs;
+        sincospi(2.0 * (double)i / (double)M, &sn, &cs);
+        px[i] = pcx + R * cs;
+        py[i] = pcy + R * sn;
+        pw[i] = 1.0;
+    }
+    if (i == 0) {
+        poff[0] = 0;
+        poff[1] = M;
+    }
+}
+
+}  // namespace
+
+hipError_t resp_side_launch(int K, const double *side_y, double xl, double d, double *sxl, double *sxr, double *mx,
+                            double *my, hipStream_t st) {
+    hipLaunchKernelGGL(resp_side, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, st, K, side_y, xl, d, sxl, sxr,
+                       mx, my);
+    return hipGetLastError();
+}
+
+hipError_t resp_pack_launch(int64_t nw, const double *vwx, const double *vwy, int K, const double *s, double p_drive,
+                            double *v, double *g, hipStream_t st) {
+    if (nw > 0) hipLaunchKernelGGL(resp_pack_v, dim3(grid(nw)), dim3(256), 0, st, nw, vwx, vwy, v);
+    hipLaunchKernelGGL(resp_pack_g, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, st, K, s, p_drive, g);
+    return hipGetLastError();
+}
+
+hipError_t resp_unpack_launch(int64_t nw, const double *tau, double *tx, double *ty, int M, const double *c,
+                              double pcx, double pcy, double R, double *cx, double *cy, double *px, double *py,
+                              double *pw, int32_t *poff, hipStream_t st) {
+    const int64_t n = std::max<int64_t>(std::max<int64_t>(nw, M), 1);
+    hipLaunchKernelGGL(resp_unpack, dim3(grid(n)), dim3(256), 0, st, nw, tau, tx, ty, M, c, pcx, pcy, R, cx, cy, px,
+                       py, pw, poff);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // factor and solve (rocSOLVER / rocBLAS on the caller's stream)
 // ---------------------------------------------------------------------------
 namespace {

@@ -51,6 +51,14 @@ hipError_t cell_fill(const CellArgs &g, double *A, double *B, double *C, double 
                      bool a_transposed = false);
 hipError_t cell_pinv_launch(int m, int n, const double *sv, const double *U, const double *Vt, double rcond,
                             double *P, hipStream_t st);
+// data of the channel's response to vesicles (cell.hip)
+hipError_t resp_side_launch(int K, const double *side_y, double xl, double d, double *sxl, double *sxr, double *mx,
+                            double *my, hipStream_t st);
+hipError_t resp_pack_launch(int64_t nw, const double *vwx, const double *vwy, int K, const double *s, double p_drive,
+                            double *v, double *g, hipStream_t st);
+hipError_t resp_unpack_launch(int64_t nw, const double *tau, double *tx, double *ty, int M, const double *c,
+                              double pcx, double pcy, double R, double *cx, double *cy, double *px, double *py,
+                              double *pw, int32_t *poff, hipStream_t st);
 // "" on success, else a message; factor waits for the stream
 std::string cell_factor(const CellArgs &g, double rcond, void *ws, hipStream_t st);
 std::string cell_solve(const CellArgs &g, const double *v, const double *gv, double *tau, double *c, void *ws,

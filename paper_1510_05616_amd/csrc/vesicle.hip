@@ -164,11 +164,11 @@ __global__ __launch_bounds__(kVesBlock) void ves_geom_kernel(int64_t n, const in
     }
 }
 
-// f_b = -kappa_B D_s^4 x, f_sigma = D_s(sigma x_s)
+// f_b = -kappa_B D_s^4 x, f_sigma = D_s(sigma x_s); total: fb receives f_b + f_sigma
 __global__ __launch_bounds__(kVesBlock) void ves_forces_kernel(int64_t n, const int32_t *off, const double *x,
                                                                const double *y, const double *sigma, double kb,
                                                                double *fbx, double *fby, double *fsx,
-                                                               double *fsy) {
+                                                               double *fsy, int total) {
     __shared__ double dtab[kVesMaxN], lx[kVesMaxN], ly[kVesMaxN], xa[kVesMaxN], ya[kVesMaxN], sp[kVesMaxN],
         tx[kVesMaxN], ty[kVesMaxN];
     const CurveRange r = curve_range(off, n);
@@ -196,7 +196,7 @@ __global__ __launch_bounds__(kVesBlock) void ves_forces_kernel(int64_t n, const 
         }
         __syncthreads();
     }
-    if (fsx) {
+    if (fsx || total) {
         // xa, ya <- sigma x_s; lx, ly <- D_s of it
         for (int m = threadIdx.x; m < r.N; m += blockDim.x) {
             const double s = sigma ? sigma[r.lo + m] : 0.0;
@@ -208,8 +208,13 @@ __global__ __launch_bounds__(kVesBlock) void ves_forces_kernel(int64_t n, const 
         dsv(ya, ly, dtab, sp, r.N);
         __syncthreads();
         for (int m = threadIdx.x; m < r.N; m += blockDim.x) {
-            fsx[r.lo + m] = lx[m];
-            fsy[r.lo + m] = ly[m];
+            if (total) {
+                fbx[r.lo + m] += lx[m];
+                fby[r.lo + m] += ly[m];
+            } else {
+                fsx[r.lo + m] = lx[m];
+                fsy[r.lo + m] = ly[m];
+            }
         }
     }
 }
@@ -1197,9 +1202,25 @@ S2D_API int ves_forces(int64_t n_nodes, int32_t n_curves, const int32_t *curve_o
     rc = device_ready(&dev);
     if (rc != S2D_OK || n_nodes == 0) return rc;
     hipLaunchKernelGGL(ves_forces_kernel, dim3(n_curves), dim3(kVesBlock), 0, (hipStream_t)stream, n_nodes,
-                       curve_off, x, y, sigma, kappa_b, fbx, fby, fsx, fsy);
+                       curve_off, x, y, sigma, kappa_b, fbx, fby, fsx, fsy, 0);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? S2D_OK : hipf(e, "ves_forces launch");
+}
+
+S2D_API int ves_total_force(int64_t n_nodes, int32_t n_curves, const int32_t *curve_off, const double *x,
+                            const double *y, const double *sigma, double kappa_b, double *fx, double *fy,
+                            void *stream) {
+    int rc = check_set(n_nodes, n_curves, curve_off, x, y);
+    if (rc != S2D_OK) return rc;
+    if (n_nodes > 0 && (!fx || !fy)) return ves_fail(S2D_EINVAL, "fx and fy must not be NULL");
+    if (!std::isfinite(kappa_b)) return ves_fail(S2D_EINVAL, "kappa_b must be finite");
+    int dev = 0;
+    rc = device_ready(&dev);
+    if (rc != S2D_OK || n_nodes == 0) return rc;
+    hipLaunchKernelGGL(ves_forces_kernel, dim3(n_curves), dim3(kVesBlock), 0, (hipStream_t)stream, n_nodes,
+                       curve_off, x, y, sigma, kappa_b, fx, fy, nullptr, nullptr, 1);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? S2D_OK : hipf(e, "ves_total_force launch");
 }
 
 S2D_API int ves_measure(int64_t n_nodes, int32_t n_curves, const int32_t *curve_off, const double *x,

@@ -43,6 +43,12 @@ def _bind():
     L.ves_reparameterize.restype = I
     L.ves_time_step.argtypes = [I64, I32, P, P, P, P, P, P, I, P, P, P, P, P, SZ, P]
     L.ves_time_step.restype = I
+    L.ves_total_force.argtypes = [I64, I32, P, P, P, P, D, P, P, P]
+    L.ves_total_force.restype = I
+    L.ves_response_workspace_size.argtypes = [P, I64, I32, I]
+    L.ves_response_workspace_size.restype = SZ
+    L.ves_channel_response.argtypes = [P, P, SZ, I64, I32, P, P, P, P, P, D, I, P, P, P, SZ, P]
+    L.ves_channel_response.restype = I
     _bound = True
     return L
 
@@ -93,6 +99,34 @@ class Vesicles:
         _check(_bind().ves_forces(*self._a(), _ptr(sigma), float(kappa_b), *(_ptr(o) for o in out),
                                   _stream(stream)))
         return out
+
+    def total_force(self, kappa_b, stream=None):
+        """f = f_b + f_sigma with the current tension."""
+        import torch
+        fx = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        fy = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        _check(_bind().ves_total_force(*self._a(), _ptr(self.sigma), float(kappa_b), _ptr(fx), _ptr(fy),
+                                       _stream(stream)))
+        return fx, fy
+
+    def channel_response(self, cell, fx, fy, p_drive, mode=0, ws=None, stream=None):
+        """u_resp at the nodes for the force density (fx, fy), from a
+        factored cell (paper_1510_05616_amd.cell.Cell)."""
+        import torch
+        if cell.ws is None:
+            raise RuntimeError("factor() the cell first")
+        L = _bind()
+        cs = cell.struct()
+        if ws is None:
+            nb = int(L.ves_response_workspace_size(ctypes.byref(cs), self.n, self.nc, int(mode)))
+            ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=self.device)
+        ux = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        uy = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        _check(L.ves_channel_response(ctypes.byref(cs), _ptr(cell.ws), cell.ws.numel(), self.n, self.nc,
+                                      _ptr(self.off), _ptr(self.x), _ptr(self.y), _ptr(fx), _ptr(fy),
+                                      float(p_drive), int(mode), _ptr(ux), _ptr(uy), _ptr(ws), ws.numel(),
+                                      _stream(stream)))
+        return ux, uy
 
     def measure(self, stream=None):
         import torch

@@ -261,3 +261,77 @@ def test_channel_vesicle_set_one_step():
           f"{dA:.2e}", flush=True)
     assert dA < 1e-7
     assert np.isfinite(_np(V.x)).all() and np.isfinite(_np(V.sigma)).all()
+
+
+# ---------------------------------------------------------------------------
+# in the channel: Algorithm 1 with the response (steps 2-9)
+# ---------------------------------------------------------------------------
+def _channel_setup():
+    walls, sy, d = synth.make_channel(256, 16)
+    x1, y1 = synth._ellipse(math.pi, 0.1, 0.3, 0.15, 0.3, 32)[:2]
+    x2, y2 = synth._ellipse(1.5, -0.3, 0.25, 0.15, -0.4, 32)[:2]
+    return walls, sy, d, np.r_[x1, x2], np.r_[y1, y2], np.array([0, 32, 64], np.int32)
+
+
+def test_total_force_and_channel_response():
+    from oracle import vesicle as ov
+    from paper_1510_05616_amd import vesicle as pv
+    from paper_1510_05616_amd.cell import Cell
+    import torch
+    walls, sy, d, x, y, off = _channel_setup()
+    mu, pd, M = 0.7, 0.9, 64
+    sig = 0.3 * np.cos(np.arange(64) * 2 * math.pi / 32) + 1.0
+    V = pv.Vesicles(x, y, off, sigma=sig)
+    fx, fy = V.total_force(1.0)
+    g = ov.geometry(x, y, off)
+    o = ov.forces(g, sig, 1.0)
+    ofx, ofy = o[0] + o[2], o[1] + o[3]
+    torch.cuda.synchronize()
+    assert _rel(_np(fx), ofx) < 1e-9 and _rel(_np(fy), ofy) < 1e-9
+    cell = Cell(walls, sy, d, M, mu)
+    cell.factor()
+    u_o = ov.channel_response(walls, sy, d, M, mu, x, y, off, ofx, ofy, pd)[0]
+    # FP32C: the data v, g carry the FP32C sums' ~1e-7; the cell system's
+    # solve amplifies it (measured 7e-6 on u_resp)
+    for mode, tol in ((0, 1e-9), (1, 2e-5)):
+        ux, uy = V.channel_response(cell, fx, fy, pd, mode=mode)
+        torch.cuda.synchronize()
+        e = max(_rel(_np(ux), u_o[:, 0]), _rel(_np(uy), u_o[:, 1]))
+        print(f"mode={mode} response rel error {e:.2e}", flush=True)
+        assert e < tol
+
+
+def test_channel_time_steps_match_the_oracle():
+    # two steps of Algorithm 1 in the channel: forces with the current
+    # tension, the channel's response, the preconditioned step, update, area
+    # correction, reparameterization
+    from oracle import vesicle as ov
+    from paper_1510_05616_amd import vesicle as pv
+    from paper_1510_05616_amd.cell import Cell
+    import torch
+    walls, sy, d, x, y, off = _channel_setup()
+    mu, pd, M, dt, kb = 0.7, 0.9, 64, 0.005, 1.0
+    g = ov.geometry(x, y, off)
+    L0, A0 = ov.arc_lengths(g), ov.areas(x, y, off)
+    f64 = dict(dtype=torch.float64, device="cuda")
+    cell = Cell(walls, sy, d, M, mu)
+    cell.factor()
+    V = pv.Vesicles(x, y, off)
+    L0d, A0d = torch.as_tensor(L0, **f64), torch.as_tensor(A0, **f64)
+    xo, yo, so = x.copy(), y.copy(), np.zeros(64)
+    for k in range(2):
+        fx, fy = V.total_force(kb)
+        ur = V.channel_response(cell, fx, fy, pd)
+        p = pv.params(dt=dt, kappa_b=kb, mu=mu, d=d, img_lo=-1, img_hi=1, L0=L0d, u_resp=ur, tol=1e-13,
+                      nmax=32)
+        it, res = V.time_step(p, A0=A0d)
+        go = ov.geometry(xo, yo, off)
+        o = ov.forces(go, so, kb)
+        uo = ov.channel_response(walls, sy, d, M, mu, xo, yo, off, o[0] + o[2], o[1] + o[3], pd)[0]
+        xo, yo, so, _, _ = ov.time_step(xo, yo, so, off, dt, kb, mu, L0=L0, A0=A0, u_resp=(uo[:, 0], uo[:, 1]),
+                                        d=d, img_lo=-1, img_hi=1)
+        torch.cuda.synchronize()
+        ex = max(_rel(_np(V.x), xo), _rel(_np(V.y), yo))
+        es = _rel(_np(V.sigma), so)
+        print(f"channel step {k}: {it} iterations, residual {res:.1e}, x {ex:.2e}, sigma {es:.2e}", flush=True)
+        assert res <= 1e-13 and ex < 1e-11 and es < 1e-8
