@@ -376,6 +376,62 @@ def step_section(prob, steps=3, dt=1e-4, kappa_b=1.0):
     return out
 
 
+def channel_section(prob, steps=2, dt=1e-4, kappa_b=1.0, p_drive=10.0, n_proxy=128, wall_nodes=8000):
+    """Algorithm 1 in the 128k channel: its walls at 2 x 8,000 nodes (the
+    dense cell system is limited to (2N)^2 < 2^31 elements; 8,000 per wall
+    still resolves every vesicle, all at least 3 wall spacings away)
+    with the 32 Gauss-Legendre side heights and 128 proxies factored once
+    (step 1, the dense 32,256-unknown periodization system), then time steps of the
+    1,000 vesicles: total membrane force (step 2), the channel's response
+    (steps 3-5: single layer on the walls and side walls, cell solve, wall
+    double layer and proxies at the 96,000 vesicle nodes), the preconditioned
+    step, update, area correction and reparameterization (steps 6-9); FP64."""
+    import torch
+    import synth
+    from paper_1510_05616_amd import vesicle as pv
+    from paper_1510_05616_amd.cell import Cell
+    h, hp, hpp = synth.wall_profile("sin13")
+    side_y = synth._side_targets(h, prob.d, 32)[1][:32]
+    walls = synth.concat_curves([(*synth._wall(h, hp, hpp, prob.d, wall_nodes, up)[:6], np.zeros(wall_nodes),
+                                  np.zeros(wall_nodes)) for up in (True, False)])
+    cell = Cell(walls, side_y, prob.d, n_proxy, prob.mu)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    cell.factor()
+    torch.cuda.synchronize()
+    t_factor = time.time() - t0
+    ves = prob.ves
+    V = pv.Vesicles(ves.x, ves.y, ves.curve_off)
+    L0, A0 = V.measure()
+    ws = None
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    resp_ms, step_ms, its = [], [], []
+    for k in range(steps + 1):                       # step 0 is the warm-up
+        torch.cuda.synchronize()
+        t0 = time.time()
+        fx, fy = V.total_force(kappa_b)
+        ev[0].record()
+        ur = V.channel_response(cell, fx, fy, p_drive)
+        ev[1].record()
+        p = pv.params(dt=dt, kappa_b=kappa_b, mu=prob.mu, d=prob.d, img_lo=-1, img_hi=1, L0=L0, u_resp=ur,
+                      tol=1e-10, nmax=96)
+        ws = V.workspace(p) if ws is None else ws
+        it, res = V.time_step(p, A0=A0, ws=ws)
+        torch.cuda.synchronize()
+        if k > 0:
+            step_ms.append((time.time() - t0) * 1e3)
+            resp_ms.append(ev[0].elapsed_time(ev[1]))
+            its.append((it, res))
+    ms = sum(step_ms) / len(step_ms)
+    log(f"channel: cell factor {t_factor:.1f} s (32,256 unknowns); Algorithm 1 step {ms:.1f} ms "
+        f"(response {sum(resp_ms) / len(resp_ms):.1f} ms), GMRES {its}")
+    return {"workload": "Algorithm 1 in the 128k channel: walls at 2 x 8,000 nodes, K = 32, M = 128 (cell factored "
+                        "once), 1,000 vesicles x 96 nodes, dt = %g, kappa_B = %g, p_drive = %g per period, FP64"
+                        % (dt, kappa_b, p_drive),
+            "cell_factor_s": t_factor, "ms_per_step": ms, "value": 1e3 / ms, "unit": "time steps/s",
+            "response_ms": sum(resp_ms) / len(resp_ms), "gmres": its}
+
+
 def cell_section(n_wall=4000, K=32, M=128, reps=5):
     """Periodization system of an empty channel cell at the paper's sizes
     (y = +-(1 + 0.3 sin x), d = 2 pi, 4000 nodes per wall, K = 32 side
@@ -584,6 +640,8 @@ def main():
     ap.add_argument("--cell", type=int, default=1, help="run the periodization-system section (0: skip)")
     ap.add_argument("--walls", type=int, default=1, help="run the near-wall correction section (0: skip)")
     ap.add_argument("--step", type=int, default=1, help="run the vesicle time-step section (0: skip)")
+    ap.add_argument("--channel", type=int, default=1,
+                    help="run Algorithm 1 in the channel, with the cell factored once (0: skip)")
     ap.add_argument("--copy-probe", action="store_true", help="only copy 1 GiB on the device and exit")
     args = ap.parse_args()
     if args.copy_probe:
@@ -652,6 +710,7 @@ def main():
     f1_res = f1_section(prob) if args.f1 and args.config == 3 else None
     wall_res = wall_section(prob) if args.walls and args.config == 3 else None
     step_res = step_section(prob) if args.step and args.config == 3 else None
+    chan_res = channel_section(prob) if args.channel and args.config == 3 else None
     cell_res = cell_section() if args.cell else None
     if cell_res is not None and args.cpu_sample > 0:
         cell_res["cpu_baseline"] = cell_cpu_baseline()
@@ -679,6 +738,7 @@ def main():
         "periodization_cell": cell_res,
         "near_wall": wall_res,
         "time_step": step_res,
+        "algorithm1_channel": chan_res,
         "near": near_res,
         "batch": batch_res,
     }

@@ -209,7 +209,11 @@ typedef struct s2d_cell {
     double d, mu;                 /* period > 0, viscosity > 0 */
 } s2d_cell;
 
-/* Workspace bytes of a factored cell (0 on bad arguments): A^-1 (formed
+/* The walls may hold at most 23,170 nodes: the dense (2N)^2 system is
+ * factored through 32-bit solver interfaces whose offsets stay below 2^31
+ * elements (S2D_EINVAL beyond).
+ *
+ * Workspace bytes of a factored cell (0 on bad arguments): A^-1 (formed
  * once, so that each solve is matrix-vector products), B, A^-1 B, C, the
  * pseudo-inverse of S and scratch, about (2N)^2 * 8 bytes. */
 S2D_API size_t stokes2d_cell_workspace_size(const s2d_cell *cell);

@@ -364,7 +364,12 @@ namespace {
 int check_cell(const s2d_cell *c, s2d::CellArgs *g) {
     if (!c) return fail(S2D_EINVAL, "cell must not be NULL");
     const s2d_curves &w = c->walls;
-    if (w.n_nodes < 1 || 2 * w.n_nodes > INT32_MAX / 2) return fail(S2D_EINVAL, "cell walls: n_nodes out of range");
+    // the dense factor and solve go through rocSOLVER's and rocBLAS's 32-bit
+    // (rocblas_int) interfaces, whose matrix offsets must stay below 2^31
+    // elements: (2N)^2 < 2^31, N <= 23,170 wall nodes
+    if (w.n_nodes < 1 || w.n_nodes > 23170)
+        return fail(S2D_EINVAL, "cell walls: n_nodes must be in 1..23170 (the dense (2N)^2 system must stay below "
+                                "2^31 elements for the 32-bit solver interface)");
     if (!w.x || !w.y || !w.nx || !w.ny || !w.w || !w.kappa)
         return fail(S2D_EINVAL, "cell walls need x, y, nx, ny, w and kappa");
     if (c->n_side < 1 || c->n_side > 4096 || !c->side_y) return fail(S2D_EINVAL, "cell: n_side in 1..4096 and side_y set");

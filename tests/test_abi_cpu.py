@@ -148,6 +148,11 @@ def test_cell_argument_checks(L):
         setattr(bad, field, value)
         assert L.stokes2d_cell_workspace_size(by(bad)) == 0, field
         assert L.stokes2d_cell_factor(by(bad), 1e-8, fake, 1 << 30, None) == s2d.S2D_EINVAL, field
+    big = s2d._Curves(23171, 2, fake, fake, fake, fake, fake, fake, fake, fake, fake)   # (2N)^2 >= 2^31
+    assert L.stokes2d_cell_workspace_size(by(pc._Cell(big, 8, fake, 0.0, 32, 3.0, 0.0, 6.0, 6.0, 0.7))) == 0
+    assert L.stokes2d_cell_factor(by(pc._Cell(big, 8, fake, 0.0, 32, 3.0, 0.0, 6.0, 6.0, 0.7)), 1e-8, fake,
+                                  1 << 40, None) == s2d.S2D_EINVAL
+    assert "23170" in s2d.stokes2d_last_error()
     nok = s2d._Curves(64, 2, fake, fake, fake, fake, fake, fake, None, fake, fake)     # no kappa
     assert L.stokes2d_cell_workspace_size(by(pc._Cell(nok, 8, fake, 0.0, 32, 3.0, 0.0, 6.0, 6.0, 0.7))) == 0
     assert L.stokes2d_cell_factor(by(good), 1.5, fake, 1 << 30, None) == s2d.S2D_EINVAL     # rcond
