@@ -335,3 +335,40 @@ def test_channel_time_steps_match_the_oracle():
         es = _rel(_np(V.sigma), so)
         print(f"channel step {k}: {it} iterations, residual {res:.1e}, x {ex:.2e}, sigma {es:.2e}", flush=True)
         assert res <= 1e-13 and ex < 1e-11 and es < 1e-8
+
+
+def _gpu_relax(dt, t_end, corrections):
+    from oracle import vesicle as ov
+    from paper_1510_05616_amd import vesicle as pv
+    import torch
+    x, y = synth._ellipse(0.0, 0.0, 1.0, 0.4, 0.2, 32)[:2]
+    off = np.array([0, 32], np.int32)
+    V = pv.Vesicles(x, y, off)
+    L0, A0 = V.measure()
+    p = pv.params(dt=dt, kappa_b=1.0, mu=1.0, L0=L0 if corrections else None, tol=1e-13, nmax=32)
+    ws = V.workspace(p)
+    for _ in range(int(round(t_end / dt))):
+        V.time_step(p, A0=A0 if corrections else None, reparam=False, ws=ws)
+    L1, A1 = V.measure()
+    torch.cuda.synchronize()
+    return (_np(V.x), _np(V.y), abs(float(_np(L1)[0] / _np(L0)[0]) - 1), abs(float(_np(A1)[0] / _np(A0)[0]) - 1))
+
+
+@pytest.mark.parametrize("corrections", [True, False])
+def test_table4_convergence_orders_on_the_gpu(corrections):
+    # Table 4's experiment with the GPU time step (the oracle's pin of the
+    # same orders is in test_oracle_vesicle): t = 0.1, dt = 0.01 / M
+    Ms = (2, 4, 8)
+    ref = _gpu_relax(0.01 / 64, 0.1, corrections)
+    out = {M: _gpu_relax(0.01 / M, 0.1, corrections) for M in Ms}
+    eL = [out[M][2] for M in Ms]
+    ex = [np.abs(np.r_[out[M][0] - ref[0], out[M][1] - ref[1]]).max() for M in Ms]
+    rL = [eL[i] / eL[i + 1] for i in range(2)]
+    rx = [ex[i] / ex[i + 1] for i in range(2)]
+    print(f"GPU corrections={corrections}: L errors {eL} ratios {rL}; x ratios {rx}", flush=True)
+    assert all(1.6 < r < 2.5 for r in rx), rx
+    if corrections:
+        assert all(3.5 < r < 5.5 for r in rL), rL
+        assert max(out[M][3] for M in Ms) < 1e-12
+    else:
+        assert all(1.5 < r < 2.5 for r in rL), rL
