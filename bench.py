@@ -321,10 +321,10 @@ def step_section(prob, steps=3, dt=1e-4, kappa_b=1.0):
     1,000 vesicles x 96 nodes in the periodic free-space setting (single
     layer over images -1..1, d = 64 pi; no wall response): the step system
     solved by GMRES (right-preconditioned by the factored per-vesicle self
-    blocks), update, area correction, reparameterization; FP64 solve to
-    1e-10 (with FP32C single-layer sums GMRES stalls near 1.5e-5: the
-    operator amplifies their rounding through D_s^4).  The oracle times one
-    step of 4 of the vesicles on the host."""
+    blocks), update, area correction, reparameterization; solved to 1e-10
+    with FP64 single-layer sums, and by iterative refinement with FP32C sums
+    (FP64 right-hand side and residuals, FP32C corrections).  The oracle
+    times one step of 4 of the vesicles on the host."""
     import torch
     import oracle
     import paper_1510_05616_amd as s2d
@@ -336,7 +336,7 @@ def step_section(prob, steps=3, dt=1e-4, kappa_b=1.0):
                        f"dt = {dt}, kappa_B = {kappa_b}, mu = {prob.mu}: one step = GMRES solve of the "
                        "288,000-unknown step system + update + area correction + reparameterization",
            "n_nodes": n}
-    for name, mode, tol in (("f64", s2d.S2D_FP64, 1e-10),):
+    for name, mode, tol in (("f64", s2d.S2D_FP64, 1e-10), ("f32", s2d.S2D_FP32C, 1e-10)):
         V = pv.Vesicles(ves.x, ves.y, ves.curve_off)
         L0, A0 = V.measure()
         p = pv.params(mode=mode, dt=dt, kappa_b=kappa_b, mu=prob.mu, d=prob.d, img_lo=-1, img_hi=1, L0=L0,
@@ -360,13 +360,19 @@ def step_section(prob, steps=3, dt=1e-4, kappa_b=1.0):
         tf = FLOPS_PER_PAIR * pairs / (avg * 1e-3) / 1e12
         peak = PEAK[name]
         out[name] = {"ms_per_step": ms, "value": 1e3 / ms, "unit": "time steps/s", "gmres": its,
-                     "single_layer_launches_per_step": kn / steps, "slp_ms_per_step": kms / steps,
-                     "roofline": {"bound": "alu", "kernel": "pair_kernel<SLP> (on-curve, Kress self terms)",
-                                  "achieved": tf, "peak": peak / 1e12, "unit": "TFLOP/s", "frac": tf * 1e12 / peak,
-                                  "flops_per_pair": FLOPS_PER_PAIR, "pairs_per_launch": pairs,
-                                  "kernel_ms": avg, "traffic": None}}
-        log(f"step {name}: {ms:.1f} ms per time step, GMRES {its}, {kn / steps:.1f} single-layer launches per "
-            f"step ({kms / steps:.1f} ms), pair kernel {avg:.2f} ms = {tf:.1f} TFLOP/s")
+                     "single_layer_launches_per_step": kn / steps, "slp_ms_per_step": kms / steps}
+        if name == "f64":
+            out[name]["roofline"] = {"bound": "alu", "kernel": "pair_kernel<SLP> (on-curve, Kress self terms)",
+                                     "achieved": tf, "peak": peak / 1e12, "unit": "TFLOP/s",
+                                     "frac": tf * 1e12 / peak, "flops_per_pair": FLOPS_PER_PAIR,
+                                     "pairs_per_launch": pairs, "kernel_ms": avg, "traffic": None}
+            log(f"step {name}: {ms:.1f} ms per time step, GMRES {its}, {kn / steps:.1f} single-layer launches per "
+                f"step ({kms / steps:.1f} ms, {avg:.2f} ms each = {tf:.1f} TFLOP/s)")
+        else:
+            # FP64 right-hand side and residuals, FP32C corrections: the
+            # launches are of both precisions
+            log(f"step {name} (FP32C corrections, FP64 residuals): {ms:.1f} ms per time step, GMRES {its}, "
+                f"{kn / steps:.1f} single-layer launches per step ({kms / steps:.1f} ms)")
     # the oracle: one step of 4 vesicles (dense solve of the 1,152-unknown system)
     off = ves.curve_off
     s = slice(0, int(off[4]))
@@ -409,35 +415,39 @@ def channel_section(prob, steps=2, dt=1e-4, kappa_b=1.0, p_drive=10.0, n_proxy=1
     torch.cuda.synchronize()
     t_factor = time.time() - t0
     ves = prob.ves
-    V = pv.Vesicles(ves.x, ves.y, ves.curve_off)
-    L0, A0 = V.measure()
-    ws = None
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    resp_ms, step_ms, its = [], [], []
-    for k in range(steps + 1):                       # step 0 is the warm-up
-        torch.cuda.synchronize()
-        t0 = time.time()
-        fx, fy = V.total_force(kappa_b)
-        ev[0].record()
-        ur = V.channel_response(cell, fx, fy, p_drive)
-        ev[1].record()
-        p = pv.params(dt=dt, kappa_b=kappa_b, mu=prob.mu, d=prob.d, img_lo=-1, img_hi=1, L0=L0, u_resp=ur,
-                      tol=1e-10, nmax=96)
-        ws = V.workspace(p) if ws is None else ws
-        it, res = V.time_step(p, A0=A0, ws=ws)
-        torch.cuda.synchronize()
-        if k > 0:
-            step_ms.append((time.time() - t0) * 1e3)
-            resp_ms.append(ev[0].elapsed_time(ev[1]))
-            its.append((it, res))
-    ms = sum(step_ms) / len(step_ms)
-    log(f"channel: cell factor {t_factor:.1f} s (32,256 unknowns); Algorithm 1 step {ms:.1f} ms "
-        f"(response {sum(resp_ms) / len(resp_ms):.1f} ms), GMRES {its}")
-    return {"workload": "Algorithm 1 in the 128k channel: walls at 2 x 8,000 nodes, K = 32, M = 128 (cell factored "
-                        "once), 1,000 vesicles x 96 nodes, dt = %g, kappa_B = %g, p_drive = %g per period, FP64"
-                        % (dt, kappa_b, p_drive),
-            "cell_factor_s": t_factor, "ms_per_step": ms, "value": 1e3 / ms, "unit": "time steps/s",
-            "response_ms": sum(resp_ms) / len(resp_ms), "gmres": its}
+    out = {"workload": "Algorithm 1 in the 128k channel: walls at 2 x 8,000 nodes, K = 32, M = 128 (cell factored "
+                       "once), 1,000 vesicles x 96 nodes, dt = %g, kappa_B = %g, p_drive = %g per period; "
+                       "response in FP64, the step solved to 1e-10 with FP64 sums (f64) or by FP32C corrections "
+                       "with FP64 residuals (f32)" % (dt, kappa_b, p_drive),
+           "cell_factor_s": t_factor}
+    for name, mode in (("f64", 0), ("f32", 1)):
+        V = pv.Vesicles(ves.x, ves.y, ves.curve_off)
+        L0, A0 = V.measure()
+        ws = None
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        resp_ms, step_ms, its = [], [], []
+        for k in range(steps + 1):                   # step 0 is the warm-up
+            torch.cuda.synchronize()
+            t0 = time.time()
+            fx, fy = V.total_force(kappa_b)
+            ev[0].record()
+            ur = V.channel_response(cell, fx, fy, p_drive)
+            ev[1].record()
+            p = pv.params(mode=mode, dt=dt, kappa_b=kappa_b, mu=prob.mu, d=prob.d, img_lo=-1, img_hi=1, L0=L0,
+                          u_resp=ur, tol=1e-10, nmax=96)
+            ws = V.workspace(p) if ws is None else ws
+            it, res = V.time_step(p, A0=A0, ws=ws)
+            torch.cuda.synchronize()
+            if k > 0:
+                step_ms.append((time.time() - t0) * 1e3)
+                resp_ms.append(ev[0].elapsed_time(ev[1]))
+                its.append((it, res))
+        ms = sum(step_ms) / len(step_ms)
+        log(f"channel {name}: cell factor {t_factor:.1f} s (32,256 unknowns); Algorithm 1 step {ms:.1f} ms "
+            f"(response {sum(resp_ms) / len(resp_ms):.1f} ms), GMRES {its}")
+        out[name] = {"ms_per_step": ms, "value": 1e3 / ms, "unit": "time steps/s",
+                     "response_ms": sum(resp_ms) / len(resp_ms), "gmres": its}
+    return out
 
 
 def cell_section(n_wall=4000, K=32, M=128, reps=5):

@@ -68,7 +68,12 @@ S2D_API int ves_measure(int64_t n_nodes, int32_t n_curves, const int32_t *curve_
  * row is Eq. (ALC) with L0 [n_curves] the reference perimeters; L0 = NULL
  * gives x_s . u_s = 0.  u_resp_x, u_resp_y: the channel's response velocity
  * at the nodes ([n_nodes] each) or NULL (none, e.g. free space).  mode: the
- * s2d_mode of the single-layer sums. */
+ * s2d_mode of the single-layer sums in ves_step_apply.  The solves
+ * (ves_step_solve, ves_time_step) with S2D_FP32C refine iteratively: the
+ * right-hand side and every residual b - A z in FP64, each correction
+ * A dz = r by GMRES with FP32C sums to a relative 1e-4 (FP32C sums alone
+ * stall GMRES near 1e-5: D_s^4 amplifies their rounding); they reach the
+ * same tolerance as S2D_FP64. */
 typedef struct ves_step_params {
     int32_t mode;
     double dt, kappa_b, mu;
@@ -101,7 +106,8 @@ S2D_API int ves_step_apply(int64_t n_nodes, int32_t n_curves, const int32_t *cur
  * Gram-Schmidt applied twice, fixed-order reductions: bitwise
  * reproducible).  z: [3 n_nodes] solution.  iters, rel_res: host pointers
  * (may be NULL) for the iteration count and the final ||b - A z|| / ||b||.
- * Returns S2D_OK also when max_iter is reached; check rel_res. */
+ * Returns S2D_OK also when max_iter is reached; check rel_res.  iters
+ * counts the GMRES iterations of all corrections in S2D_FP32C mode. */
 S2D_API int ves_step_solve(int64_t n_nodes, int32_t n_curves, const int32_t *curve_off,
                            const double *x, const double *y, const ves_step_params *p,
                            double *z, int32_t *iters, double *rel_res,

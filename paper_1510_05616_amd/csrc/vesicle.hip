@@ -722,7 +722,7 @@ namespace {
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct StepLayout {
-    size_t geo, dens, tgt, b, r, w, V, z, part, dots, slp, slp_bytes;
+    size_t geo, dens, tgt, b, r, w, dz, ri, V, z, part, dots, slp, slp_bytes;
     // preconditioner (precond != 0): Kress table, per-curve D_s, D_s^2, D_s^4,
     // S_cc, B, S_cc B, P (LU), pivots, info, padded right-hand sides, two
     // [3n] vectors
@@ -758,6 +758,10 @@ StepLayout step_layout(int64_t n, int32_t nc, const ves_step_params *p) {
     o += al256(n3 * d);
     L.w = o;
     o += al256(n3 * d);
+    L.dz = o;
+    o += al256(n3 * d);
+    L.ri = o;
+    o += al256(n3 * d);
     L.V = o;
     o += al256((size_t)(m + 1) * n3 * d);
     L.z = o;
@@ -774,7 +778,9 @@ StepLayout step_layout(int64_t n, int32_t nc, const ves_step_params *p) {
     t.n = n;
     t.x = t.y = (const double *)1;
     t.on_curve = t.on_node = (const int32_t *)1;
-    const size_t sz = stokes2d_workspace_size(S2D_OP_SLP, p->mode, &c, &t);
+    // FP64 sums always run (right-hand side and residuals); FP32C ones too in that mode
+    const size_t sz = std::max(stokes2d_workspace_size(S2D_OP_SLP, S2D_FP64, &c, &t),
+                               p->mode == S2D_FP32C ? stokes2d_workspace_size(S2D_OP_SLP, S2D_FP32C, &c, &t) : 0);
     L.slp = o;
     L.slp_bytes = std::max<size_t>(sz, 256);
     o += al256(L.slp_bytes);
@@ -899,9 +905,10 @@ int setup_ctx(StepCtx &C, int64_t n, int32_t nc, const int32_t *off, const doubl
     return S2D_OK;
 }
 
-// out = A z (RHS = false) or out = b (RHS = true, z unused)
+// out = A z (RHS = false) or out = b (RHS = true, z unused), single-layer
+// sums in `mode`
 template <bool RHS>
-int apply(StepCtx &C, const double *z, double *out) {
+int apply(StepCtx &C, const double *z, double *out, int mode) {
     OpArgs a{};
     a.n = C.n;
     a.off = C.off;
@@ -919,7 +926,7 @@ int apply(StepCtx &C, const double *z, double *out) {
     hipLaunchKernelGGL(ves_op_kernel<RHS>, dim3(C.nc), dim3(kVesBlock), 0, C.st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hipf(e, "vesicle operator launch");
-    return stokes2d_slp_eval(C.p->mode, &C.src, &C.trg, C.p->d, C.p->img_lo, C.p->img_hi, C.p->mu, out,
+    return stokes2d_slp_eval(mode, &C.src, &C.trg, C.p->d, C.p->img_lo, C.p->img_hi, C.p->mu, out,
                              out + C.n, 1, C.ws + C.L.slp, C.L.slp_bytes, C.st);
 }
 
@@ -1056,44 +1063,28 @@ int pc_apply(StepCtx &C, const double *v, double *out) {
     return e == hipSuccess ? S2D_OK : hipf(e, "preconditioner scatter");
 }
 
-int gmres_run(StepCtx &C, double *z, int32_t *iters_out, double *res_out);
-
-// restarted GMRES from z = 0 on A z = b, right-preconditioned when asked
-int gmres(StepCtx &C, double *z, int32_t *iters_out, double *res_out) {
-    C.pc = C.p->precond != 0;
-    if (!C.pc) return gmres_run(C, z, iters_out, res_out);
-    std::lock_guard<std::mutex> lk(blas_mutex());
-    std::string err;
-    C.h = (rocblas_handle)blas_handle(C.st, err);
-    if (!C.h) return ves_fail(S2D_EHIP, err);
-    S2D_TRY(pc_build(C));
-    return gmres_run(C, z, iters_out, res_out);
-}
-
-int gmres_run(StepCtx &C, double *z, int32_t *iters_out, double *res_out) {
+// Restarted GMRES on A x = rhs from x = 0 (single-layer sums in `mode`),
+// right-preconditioned when C.pc; stops at ||rhs - A x|| <= tol ||rhs||
+// (explicit residual at every restart) or after max_iter iterations.
+int krylov(StepCtx &C, const double *rhs, double rhs_norm, double *x, double tol, int mode, int max_iter,
+           int &iters, double &rel) {
     const int64_t len = 3 * C.n;
     const int m = C.p->restart;
-    double *b = (double *)(C.ws + C.L.b), *r = (double *)(C.ws + C.L.r), *w = (double *)(C.ws + C.L.w);
+    double *r = (double *)(C.ws + C.L.ri), *w = (double *)(C.ws + C.L.w);
     double *V = (double *)(C.ws + C.L.V);
-    S2D_TRY(apply<true>(C, nullptr, b));
-    double nb2 = 0.0;
-    S2D_TRY(dots(C, 1, b, b, &nb2));
-    const double bnorm = std::sqrt(nb2);
-    S2D_TRY(axpby(C, 0.0, b, 0.0, nullptr, z));
-    int iters = 0;
-    double rel = 0.0;
-    if (bnorm == 0.0 || !std::isfinite(bnorm)) {
-        if (iters_out) *iters_out = 0;
-        if (res_out) *res_out = bnorm == 0.0 ? 0.0 : bnorm;
+    S2D_TRY(axpby(C, 0.0, rhs, 0.0, nullptr, x));
+    iters = 0;
+    rel = 0.0;
+    if (rhs_norm == 0.0 || !std::isfinite(rhs_norm)) {
+        rel = rhs_norm == 0.0 ? 0.0 : rhs_norm;
         return S2D_OK;
     }
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hc(m + 2), h2(m + 2), y(m);
-    // r = b (z = 0)
-    S2D_TRY(axpby(C, 1.0, b, 0.0, nullptr, r));
-    double beta = bnorm;
+    S2D_TRY(axpby(C, 1.0, rhs, 0.0, nullptr, r));
+    double beta = rhs_norm;
     while (true) {
-        rel = beta / bnorm;
-        if (rel <= C.p->tol || iters >= C.p->max_iter) break;
+        rel = beta / rhs_norm;
+        if (rel <= tol || iters >= max_iter) break;
         S2D_TRY(axpby(C, 1.0 / beta, r, 0.0, nullptr, V));
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
@@ -1103,9 +1094,9 @@ int gmres_run(StepCtx &C, double *z, int32_t *iters_out, double *res_out) {
             if (C.pc) {
                 double *t1 = (double *)(C.ws + C.L.t1);
                 S2D_TRY(pc_apply(C, vj, t1));
-                S2D_TRY(apply<false>(C, t1, w));
+                S2D_TRY(apply<false>(C, t1, w, mode));
             } else {
-                S2D_TRY(apply<false>(C, vj, w));
+                S2D_TRY(apply<false>(C, vj, w, mode));
             }
             // classical Gram-Schmidt, twice
             S2D_TRY(dots(C, j + 1, V, w, hc.data()));
@@ -1134,37 +1125,95 @@ int gmres_run(StepCtx &C, double *z, int32_t *iters_out, double *res_out) {
             g[j] = cs[j] * g[j];
             ++iters;
             k = j + 1;
-            const double res = std::fabs(g[j + 1]) / bnorm;
-            if (hn == 0.0 || res <= C.p->tol || iters >= C.p->max_iter) break;
+            const double res = std::fabs(g[j + 1]) / rhs_norm;
+            if (hn == 0.0 || res <= tol || iters >= max_iter) break;
             S2D_TRY(axpby(C, 1.0 / hn, w, 0.0, nullptr, vn));
         }
-        // y = H^-1 g (upper triangular k x k), z += V y
+        // y = H^-1 g (upper triangular k x k), x += V y
         for (int i = k - 1; i >= 0; --i) {
             double s = g[i];
             for (int l = i + 1; l < k; ++l) s -= H[(size_t)i * m + l] * y[l];
             y[i] = s / H[(size_t)i * m + i];
         }
         if (C.pc) {
-            // z += P^-1 (V y)
+            // x += P^-1 (V y)
             double *t1 = (double *)(C.ws + C.L.t1), *t2 = (double *)(C.ws + C.L.t2);
             S2D_TRY(combo(C, k, V, y.data(), 0.0, t2));
             S2D_TRY(pc_apply(C, t2, t1));
-            S2D_TRY(axpby(C, 1.0, z, 1.0, t1, z));
+            S2D_TRY(axpby(C, 1.0, x, 1.0, t1, x));
         } else {
-            S2D_TRY(combo(C, k, V, y.data(), 1.0, z));
+            S2D_TRY(combo(C, k, V, y.data(), 1.0, x));
         }
-        // explicit residual r = b - A z
-        S2D_TRY(apply<false>(C, z, w));
-        S2D_TRY(axpby(C, 1.0, b, -1.0, w, r));
+        // explicit residual r = rhs - A x
+        S2D_TRY(apply<false>(C, x, w, mode));
+        S2D_TRY(axpby(C, 1.0, rhs, -1.0, w, r));
         double rr2 = 0.0;
         S2D_TRY(dots(C, 1, r, r, &rr2));
         beta = std::sqrt(rr2);
         if (!std::isfinite(beta)) break;
     }
-    rel = beta / bnorm;
+    rel = beta / rhs_norm;
+    return S2D_OK;
+}
+
+// a correction solve of the refinement needs to gain at least this factor
+constexpr double kInnerTol = 1e-4;
+constexpr int kMaxRefine = 30;
+
+// The step system A z = b.  FP64: GMRES with FP64 single-layer sums.
+// FP32C: iterative refinement; b and every residual b - A z in FP64, each
+// correction A dz = r solved by GMRES with FP32C sums to a relative
+// kInnerTol (or to what the tolerance still asks), z += dz.
+int gmres_run(StepCtx &C, double *z, int32_t *iters_out, double *res_out) {
+    double *b = (double *)(C.ws + C.L.b), *r = (double *)(C.ws + C.L.r), *w = (double *)(C.ws + C.L.w);
+    double *dz = (double *)(C.ws + C.L.dz);
+    S2D_TRY(apply<true>(C, nullptr, b, S2D_FP64));
+    double nb2 = 0.0;
+    S2D_TRY(dots(C, 1, b, b, &nb2));
+    const double bnorm = std::sqrt(nb2);
+    int iters = 0;
+    double rel = 0.0;
+    if (C.p->mode == S2D_FP64) {
+        S2D_TRY(krylov(C, b, bnorm, z, C.p->tol, S2D_FP64, C.p->max_iter, iters, rel));
+    } else {
+        S2D_TRY(axpby(C, 0.0, b, 0.0, nullptr, z));
+        S2D_TRY(axpby(C, 1.0, b, 0.0, nullptr, r));
+        double rnorm = bnorm;
+        rel = bnorm == 0.0 ? 0.0 : 1.0;
+        for (int o = 0; o < kMaxRefine && bnorm > 0.0 && std::isfinite(rnorm); ++o) {
+            if (rel <= C.p->tol || iters >= C.p->max_iter) break;
+            const double itol = std::max(C.p->tol * bnorm / rnorm, kInnerTol);
+            int it = 0;
+            double irel = 0.0;
+            S2D_TRY(krylov(C, r, rnorm, dz, itol, S2D_FP32C, C.p->max_iter - iters, it, irel));
+            iters += it;
+            S2D_TRY(axpby(C, 1.0, z, 1.0, dz, z));
+            S2D_TRY(apply<false>(C, z, w, S2D_FP64));
+            S2D_TRY(axpby(C, 1.0, b, -1.0, w, r));
+            double rr2 = 0.0;
+            S2D_TRY(dots(C, 1, r, r, &rr2));
+            const double next = std::sqrt(rr2);
+            const bool stalled = !(next < 0.5 * rnorm);
+            rnorm = next;
+            rel = rnorm / bnorm;
+            if (stalled) break;
+        }
+    }
     if (iters_out) *iters_out = iters;
     if (res_out) *res_out = rel;
     return S2D_OK;
+}
+
+// the step system, right-preconditioned when asked
+int gmres(StepCtx &C, double *z, int32_t *iters_out, double *res_out) {
+    C.pc = C.p->precond != 0;
+    if (!C.pc) return gmres_run(C, z, iters_out, res_out);
+    std::lock_guard<std::mutex> lk(blas_mutex());
+    std::string err;
+    C.h = (rocblas_handle)blas_handle(C.st, err);
+    if (!C.h) return ves_fail(S2D_EHIP, err);
+    S2D_TRY(pc_build(C));
+    return gmres_run(C, z, iters_out, res_out);
 }
 
 }  // namespace
@@ -1255,8 +1304,8 @@ S2D_API int ves_step_apply(int64_t n_nodes, int32_t n_curves, const int32_t *cur
     if (rc != S2D_OK || n_nodes == 0) return rc;
     StepCtx C{};
     S2D_TRY(setup_ctx(C, n_nodes, n_curves, curve_off, x, y, p, ws, ws_bytes, stream));
-    S2D_TRY(apply<false>(C, z, out));
-    if (b) S2D_TRY(apply<true>(C, nullptr, b));
+    S2D_TRY(apply<false>(C, z, out, p->mode));
+    if (b) S2D_TRY(apply<true>(C, nullptr, b, p->mode));
     return S2D_OK;
 }
 
