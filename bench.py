@@ -258,7 +258,7 @@ def wall_section(prob, n_trg=20000, P=8, reps=5):
     f64 = dict(dtype=torch.float64, device="cuda")
     du, dv = torch.zeros(n_trg, **f64), torch.zeros(n_trg, **f64)
     ws = torch.empty(pn.near_wall_workspace_size(walls, tg, P), dtype=torch.uint8, device="cuda")
-    corr = lambda: pn.near_wall_correct_eval(walls, tg, prob.d, -1, 1, P, du, dv, 0, ws)
+    corr = lambda: pn.near_wall_correct_eval(walls, tg, prob.d, -1, 1, P, du, dv, ws=ws)
     ms_corr = _time(corr, reps)
     fine = pn.stokes2d_wall_upsample(walls, prob.d, P)
     ms_up = _time(lambda: pn.stokes2d_wall_upsample(walls, prob.d, P), reps)
@@ -314,6 +314,68 @@ def wall_section(prob, n_trg=20000, P=8, reps=5):
                              "cores": oracle.num_threads(),
                              "sample": f"{ns} seeded targets: FFT refinement of both walls plus the refined and "
                                        "given double layers by direct FP64 sums"}}
+
+
+def wall_learned_section(prob, n_train=200000, n_test=1000000, epochs=40):
+    """The learned route for the walls on the 128k channel's walls (2 x
+    16,000 nodes, smooth densities, images -1..1): the network trained on
+    200,000 targets at log-uniform distances 0.05..5 spacings (labels from
+    the 8x refined walls), calibrated on 20,000, then on 1,000,000 test
+    targets the refined quadrature (every target against all 256,000 refined
+    nodes), the network alone, and AUTO at a threshold of 1e-3 of the
+    largest correction.  Errors in the labels' units (Delta pi / F)."""
+    import torch
+    import synth
+    from paper_1510_05616_amd import near as pn
+    walls = synth.wall_densities(prob.wall, 41)
+    d = prob.d
+    t0 = time.time()
+    tr = pn.WallNearData(walls, d, *synth.near_wall_dataset(walls, n_train, 42))
+    va = pn.WallNearData(walls, d, *synth.near_wall_dataset(walls, 20000, 43))
+    te = pn.WallNearData(walls, d, *synth.near_wall_dataset(walls, n_test, 44))
+    torch.cuda.synchronize()
+    t_data = time.time() - t0
+    t0 = time.time()
+    params, hist = pn.train(tr, epochs=epochs, batch=512, lr=3e-3)
+    torch.cuda.synchronize()
+    t_train = time.time() - t0
+    blob, bound, bound0 = pn.calibrate(va, params)
+    du = torch.empty(te.n, dtype=torch.float64, device="cuda")
+    dv = torch.empty_like(du)
+    fb = torch.zeros(te.n, dtype=torch.int32, device="cuda")
+    thr = 1e-3 * te.du.abs().max().item()
+    ws = {m: torch.empty(pn.near_wall_workspace_size(te.curves, te.trg, 8, m), dtype=torch.uint8, device="cuda")
+          for m in (pn.S2D_NEAR_UPSAMPLE, pn.S2D_NEAR_MLP, pn.S2D_NEAR_AUTO)}
+    run = {
+        "upsampled": lambda: pn.near_wall_correct_eval(te.curves, te.trg, d, -1, 1, 8, du, dv,
+                                                       ws=ws[pn.S2D_NEAR_UPSAMPLE]),
+        "mlp": lambda: pn.near_wall_correct_eval(te.curves, te.trg, d, -1, 1, 8, du, dv, method=pn.S2D_NEAR_MLP,
+                                                 trg_curve=te.tc, blob=blob, ws=ws[pn.S2D_NEAR_MLP]),
+        "auto": lambda: pn.near_wall_correct_eval(te.curves, te.trg, d, -1, 1, 8, du, dv, method=pn.S2D_NEAR_AUTO,
+                                                  trg_curve=te.tc, blob=blob, threshold=thr, used_fallback=fb,
+                                                  ws=ws[pn.S2D_NEAR_AUTO]),
+    }
+    out = {"workload": "learned wall correction: 128k channel walls (2 x 16,000 nodes), 1,000,000 test targets "
+                       "at 0.05..5 spacings, images -1..1, refined 8x",
+           "train_s": t_train, "data_s": t_data, "loss": [hist[0], hist[-1]]}
+    for name, fn in run.items():
+        ms = _time(fn, reps=2)
+        torch.cuda.synchronize()
+        e = (torch.hypot(du - te.du, dv - te.dv) * math.pi / te.frame[:, 5]).max().item()
+        out[name] = {"ms": ms, "max_scaled_error": e}
+        if name == "auto":
+            out[name]["threshold"] = thr
+            out[name]["fractions_network_quadrature_none"] = [(fb == k).float().mean().item() for k in range(3)]
+            out[name]["max_error"] = torch.hypot(du - te.du, dv - te.dv).max().item()
+    base = out["upsampled"]["ms"]
+    for name in ("mlp", "auto"):
+        out[name]["speedup_vs_upsampled"] = base / out[name]["ms"]
+    log(f"walls learned: train {t_train:.1f}s (loss {hist[0]:.3e} -> {hist[-1]:.3e}); upsampled {base:.1f} ms, "
+        f"mlp {out['mlp']['ms']:.2f} ms ({out['mlp']['speedup_vs_upsampled']:.0f}x, max scaled error "
+        f"{out['mlp']['max_scaled_error']:.2e}), auto {out['auto']['ms']:.1f} ms "
+        f"({out['auto']['speedup_vs_upsampled']:.2f}x, max error {out['auto']['max_error']:.2e} <= {thr:.2e}, "
+        f"fractions {out['auto']['fractions_network_quadrature_none']})")
+    return out
 
 
 def step_section(prob, steps=3, dt=1e-4, kappa_b=1.0):
@@ -656,7 +718,7 @@ def main():
     ap.add_argument("--batch", type=int, default=1, help="run the batched-instances section (0: skip)")
     ap.add_argument("--f1", type=int, default=1, help="run the pressure/traction section (0: skip)")
     ap.add_argument("--cell", type=int, default=1, help="run the periodization-system section (0: skip)")
-    ap.add_argument("--walls", type=int, default=1, help="run the near-wall correction section (0: skip)")
+    ap.add_argument("--walls", type=int, default=1, help="run the near-wall correction sections (0: skip)")
     ap.add_argument("--step", type=int, default=1, help="run the vesicle time-step section (0: skip)")
     ap.add_argument("--channel", type=int, default=1,
                     help="run Algorithm 1 in the channel, with the cell factored once (0: skip)")
@@ -727,6 +789,7 @@ def main():
 
     f1_res = f1_section(prob) if args.f1 and args.config == 3 else None
     wall_res = wall_section(prob) if args.walls and args.config == 3 else None
+    wall_learned = wall_learned_section(prob) if args.walls and args.config == 3 else None
     step_res = step_section(prob) if args.step and args.config == 3 else None
     chan_res = channel_section(prob) if args.channel and args.config == 3 else None
     cell_res = cell_section() if args.cell else None
@@ -755,6 +818,7 @@ def main():
         "pressure_traction": f1_res,
         "periodization_cell": cell_res,
         "near_wall": wall_res,
+        "near_wall_learned": wall_learned,
         "time_step": step_res,
         "algorithm1_channel": chan_res,
         "near": near_res,

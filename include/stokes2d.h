@@ -399,19 +399,49 @@ S2D_API int stokes2d_wall_upsample(const s2d_curves *walls, double d, int32_t up
                                    double *fx, double *fy, int32_t *curve_off,
                                    void *ws, size_t ws_bytes, void *stream);
 
-/* Workspace bytes for near_wall_correct_eval (0 on bad arguments). */
-S2D_API size_t near_wall_workspace_size(const s2d_curves *walls, const s2d_targets *trg,
+/* Workspace bytes for near_wall_correct_eval with `method` (0 on bad
+ * arguments). */
+S2D_API size_t near_wall_workspace_size(int method, const s2d_curves *walls, const s2d_targets *trg,
                                         int32_t upsample);
+
+/* The learned route for the walls (the vesicles' near-field network applied
+ * to the double layer).  Features of target i relative to wall curve
+ * trg_curve[i], the wall unrolled over three periods so that the nearest
+ * node and the 8-node density window may lie across the period boundary:
+ * X [n][20] FP32 as for near_features_eval (offsets in units of
+ * h = sum w / N, log distance, kappa h, the window's densities in the local
+ * frame over their largest norm F); frame [n][6] FP64 = (t0, n0, 1, F).
+ * Needs the walls' w and kappa; curves with fewer than 8 nodes give NaN. */
+S2D_API int near_wall_features_eval(const s2d_curves *walls, const s2d_targets *trg,
+                                    const int32_t *trg_curve, double d, float *X, double *frame,
+                                    void *stream);
+
+/* Training labels for the walls: Y = (Delta . t0, Delta . n0) pi / F (the
+ * double layer's correction scales with F / pi). */
+S2D_API int near_wall_scale_labels(int64_t n, const double *du, const double *dv,
+                                   const double *frame, float *Y, void *stream);
 
 /* Delta = D_P - D_1 of the wall double layer (Section 2.1 Eq. (D)) summed over
  * images img_lo..img_hi, at free targets (trg->on_curve must be NULL), FP64:
  * du, dv ([trg->n] device) are written, or Delta is added to them when
  * accumulate != 0 (so a caller adds it to the plain double layer it holds).
- * Same image and period rules as stokes2d_dlp_eval. */
-S2D_API int near_wall_correct_eval(const s2d_curves *walls, const s2d_targets *trg, double d,
-                                   int32_t img_lo, int32_t img_hi, int32_t upsample,
-                                   double *du, double *dv, int accumulate,
-                                   void *ws, size_t ws_bytes, void *stream);
+ * method (s2d_near_method as for near_correct_eval):
+ *   UPSAMPLE: the refined-wall quadrature at every target;
+ *   MLP:      the network (mlp: a blob from near_mlp_pack trained on wall
+ *             labels) at every target, relative to wall trg_curve[i];
+ *   AUTO:     per target as near_correct_eval decides (no correction, the
+ *             network, or the refined quadrature, against threshold), the
+ *             quadrature only at the fallback targets.  AUTO reads the
+ *             fallback count back to the host (it waits for `stream`).
+ * used_fallback: [n] device int32 or NULL, set (MLP, AUTO) to 0 network,
+ * 1 quadrature, 2 no correction.  Same image and period rules as
+ * stokes2d_dlp_eval. */
+S2D_API int near_wall_correct_eval(int method, const s2d_curves *walls, const s2d_targets *trg,
+                                   const int32_t *trg_curve, double d, int32_t img_lo,
+                                   int32_t img_hi, int32_t upsample, const void *mlp,
+                                   double threshold, double *du, double *dv,
+                                   int32_t *used_fallback, int accumulate, void *ws,
+                                   size_t ws_bytes, void *stream);
 
 /* Benchmarking aid (not capturable, not for production loops): while
  * enabled, each evaluation records a HIP event pair around its pair-sum

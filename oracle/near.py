@@ -184,6 +184,63 @@ def frame_to_velocity(yt, frames, mu=1.0):
 
 
 # ----------------------------------------------------------------------------
+# walls: features of targets near a periodic wall (the learned correction of
+# the walls' double layer)
+# ----------------------------------------------------------------------------
+def wall_features_one(x, y, nx, ny, kappa, w, fx, fy, d, px, py):
+    """Feature vector (20) of target p relative to one period of a wall
+    (N nodes advancing by s d in x, s = +-1 from its first two nodes), with
+    the frame (t0, n0), the scale length 1 and the density scale F.  The
+    wall is unrolled over three periods: node K in [-N, 2N) sits at
+    (x_{K mod N} + s d floor(K / N), y_{K mod N}).  K* is the nearest
+    unrolled node (smallest K on ties), K0 = K* or K* - 1 as for closed
+    curves, and the window holds the densities of K0-3 .. K0+4; s, n_off
+    and dist as for closed curves (units h = sum w / N), kappa of node
+    K0 mod N."""
+    N = x.shape[0]
+    sg = 1.0 if x[1] > x[0] else -1.0
+    h = w.sum() / N
+    K = np.arange(-N, 2 * N)
+    kk = K % N
+    X = x[kk] + sg * d * np.floor_divide(K, N)
+    Y = y[kk]
+    d2 = (px - X) ** 2 + (py - Y) ** 2
+    i = int(np.argmin(d2))
+    ks = K[i]
+    ts = np.array([-ny[ks % N], nx[ks % N]])
+    k0 = ks if (px - X[i]) * ts[0] + (py - Y[i]) * ts[1] >= 0.0 else ks - 1
+    m0 = k0 % N
+    t0 = np.array([-ny[m0], nx[m0]])
+    n0 = np.array([nx[m0], ny[m0]])
+    ox, oy = px - (x[m0] + sg * d * (k0 // N)), py - y[m0]
+    s = (ox * t0[0] + oy * t0[1]) / h
+    no = (ox * n0[0] + oy * n0[1]) / h
+    dist = math.log(math.sqrt(d2[i]) / h)
+    idx = [(k0 + j) % N for j in range(WINDOW[0], WINDOW[1] + 1)]
+    ft = np.array([fx[j] * t0[0] + fy[j] * t0[1] for j in idx])
+    fn = np.array([fx[j] * n0[0] + fy[j] * n0[1] for j in idx])
+    F = max(np.hypot(ft, fn).max(), 0.0)
+    if F == 0.0:
+        F = 1.0
+    feat = np.concatenate([[s, no, dist, kappa[m0] * h], ft / F, fn / F])
+    return feat, t0, n0, 1.0, F
+
+
+def wall_features(walls, d, px, py, tc):
+    """Features and frames (t0, n0, 1, F) of targets (px, py) relative to
+    wall curve tc[i] of `walls`."""
+    out = np.zeros((len(px), N_FEAT))
+    frames = np.zeros((len(px), 6))
+    for i in range(len(px)):
+        s = slice(walls.curve_off[tc[i]], walls.curve_off[tc[i] + 1])
+        f, t0, n0, h, F = wall_features_one(walls.x[s], walls.y[s], walls.nx[s], walls.ny[s], walls.kappa[s],
+                                            walls.w[s], walls.fx[s], walls.fy[s], d, px[i], py[i])
+        out[i] = f
+        frames[i] = [t0[0], t0[1], n0[0], n0[1], h, F]
+    return out, frames
+
+
+# ----------------------------------------------------------------------------
 # MLP: x (n, 20) -> standardise -> [64 GELU] x 3 -> 2
 # ----------------------------------------------------------------------------
 SQRT_2_OVER_PI = math.sqrt(2.0 / math.pi)

@@ -952,25 +952,61 @@ s2d::WallArgs wall_args(const s2d_curves *w, double d, int P, void *scratch, dou
     return a;
 }
 
-// workspace of near_wall_correct_eval: upsampling, two outputs, pair sums
+// workspace of near_wall_correct_eval: upsampling, outputs, features and
+// the fallback list (MLP, AUTO), pair sums
 struct NearWallLayout {
     WallLayout up;
-    size_t tmp, pair, pair_bytes, total;
+    size_t t4, X, frame, flag, list, count, cxy, pair, pair_bytes, total;
 };
 
-NearWallLayout near_wall_layout(const s2d_curves *w, const s2d_targets *t, int P, s2d_curves *fine_shape) {
+NearWallLayout near_wall_layout(int method, const s2d_curves *w, const s2d_targets *t, int P,
+                                s2d_curves *fine_shape) {
     NearWallLayout L{};
-    L.up = wall_layout(w, P);
-    L.tmp = L.up.total;
-    L.pair = L.tmp + align256(4 * (size_t)t->n * sizeof(double));
+    size_t o = 0;
+    if (method != S2D_NEAR_MLP) {
+        L.up = wall_layout(w, P);
+        o = L.up.total;
+    }
+    const size_t n = (size_t)t->n;
+    L.t4 = o;
+    o += align256(4 * n * sizeof(double));
+    if (method != S2D_NEAR_UPSAMPLE) {
+        L.X = o;
+        o += align256(n * s2d::kNearFeat * sizeof(float));
+        L.frame = o;
+        o += align256(n * 6 * sizeof(double));
+        L.flag = o;
+        o += align256(n * sizeof(int32_t));
+        L.list = o;
+        o += align256(n * sizeof(int32_t));
+        L.count = o;
+        o += 256;
+        L.cxy = o;
+        o += align256(2 * n * sizeof(double));
+    }
     s2d_curves f = *w;
     f.n_nodes = (int64_t)P * w->n_nodes;
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < kMaxDev && g_dev[dev].init) cus = g_dev[dev].cus;
-    const size_t a = make_plan(S2D_OP_DLP, S2D_FP64, &f, t, cus).total;
-    const size_t b = make_plan(S2D_OP_DLP, S2D_FP64, w, t, cus).total;
-    L.pair_bytes = std::max<size_t>(std::max(a, b), 256);
-    L.total = L.pair + L.pair_bytes;
+    size_t pb = 256;
+    if (method == S2D_NEAR_UPSAMPLE) {
+        pb = std::max(pb, make_plan(S2D_OP_DLP, S2D_FP64, &f, t, cus).total);
+        pb = std::max(pb, make_plan(S2D_OP_DLP, S2D_FP64, w, t, cus).total);
+    } else if (method == S2D_NEAR_AUTO) {
+        // the fallback targets are known only at run time: the largest plan
+        // over every tile count up to all targets (the plan depends on the
+        // target count through its tiles)
+        s2d_targets tm = *t;
+        const int64_t tiles = ((int64_t)n + s2d::kWave - 1) / s2d::kWave;
+        for (int64_t k = 1; k <= tiles; ++k) {
+            tm.n = std::min<int64_t>(k * s2d::kWave, (int64_t)n);
+            pb = std::max(pb, make_plan(S2D_OP_DLP, S2D_FP64, &f, &tm, cus).total);
+            pb = std::max(pb, make_plan(S2D_OP_DLP, S2D_FP64, w, &tm, cus).total);
+        }
+    }
+    L.pair = o;
+    L.pair_bytes = pb;
+    L.total = o + align256(pb);
     if (fine_shape) *fine_shape = f;
     return L;
 }
@@ -1004,65 +1040,150 @@ S2D_API int stokes2d_wall_upsample(const s2d_curves *walls, double d, int32_t up
     return e == hipSuccess ? S2D_OK : hip_fail(e, "wall upsample launch");
 }
 
-S2D_API size_t near_wall_workspace_size(const s2d_curves *walls, const s2d_targets *trg, int32_t upsample) {
+S2D_API size_t near_wall_workspace_size(int method, const s2d_curves *walls, const s2d_targets *trg,
+                                        int32_t upsample) {
     if (!walls || !trg || trg->n < 0 || walls->n_nodes < 0 || walls->n_nodes > kWallMaxNodes ||
-        walls->n_curves < 0 || upsample < 1 || upsample > 32)
+        walls->n_curves < 0 || upsample < 1 || upsample > 32 || method < S2D_NEAR_UPSAMPLE || method > S2D_NEAR_AUTO)
         return 0;
-    return near_wall_layout(walls, trg, upsample, nullptr).total;
+    return near_wall_layout(method, walls, trg, upsample, nullptr).total;
 }
 
-S2D_API int near_wall_correct_eval(const s2d_curves *walls, const s2d_targets *trg, double d, int32_t img_lo,
-                                   int32_t img_hi, int32_t upsample, double *du, double *dv, int accumulate,
-                                   void *ws, size_t ws_bytes, void *stream) {
+S2D_API int near_wall_features_eval(const s2d_curves *walls, const s2d_targets *trg, const int32_t *trg_curve,
+                                    double d, float *X, double *frame, void *stream) {
+    int rc = check_walls(walls, d, 1);
+    if (rc != S2D_OK) return rc;
+    if (!trg || trg->n < 0 || (trg->n > 0 && (!trg->x || !trg->y || !trg_curve)))
+        return fail(S2D_EINVAL, "trg x, y and trg_curve must not be NULL");
+    if (walls->n_nodes > 0 && (!walls->w || !walls->kappa))
+        return fail(S2D_EINVAL, "the features need the walls' w and kappa");
+    if (trg->n > 0 && (!X || !frame)) return fail(S2D_EINVAL, "X and frame must not be NULL");
+    int dev = 0;
+    rc = current_device(&dev);
+    if (rc != S2D_OK || trg->n == 0) return rc;
+    const hipError_t e = s2d::near_launch_wall_features(walls, trg, trg_curve, d, X, frame, (hipStream_t)stream);
+    return e == hipSuccess ? S2D_OK : hip_fail(e, "near-wall features launch");
+}
+
+S2D_API int near_wall_scale_labels(int64_t n, const double *du, const double *dv, const double *frame, float *Y,
+                                   void *stream) {
+    if (n < 0 || (n > 0 && (!du || !dv || !frame || !Y))) return fail(S2D_EINVAL, "bad label arguments");
+    int dev = 0;
+    int rc = current_device(&dev);
+    if (rc != S2D_OK || n == 0) return rc;
+    const hipError_t e =
+        s2d::near_launch_scale_labels(n, du, dv, frame, s2d::kWallMuScale, Y, (hipStream_t)stream);
+    return e == hipSuccess ? S2D_OK : hip_fail(e, "near-wall labels launch");
+}
+
+S2D_API int near_wall_correct_eval(int method, const s2d_curves *walls, const s2d_targets *trg,
+                                   const int32_t *trg_curve, double d, int32_t img_lo, int32_t img_hi,
+                                   int32_t upsample, const void *mlp, double threshold, double *du, double *dv,
+                                   int32_t *used_fallback, int accumulate, void *ws, size_t ws_bytes,
+                                   void *stream) {
+    if (method < S2D_NEAR_UPSAMPLE || method > S2D_NEAR_AUTO) return fail(S2D_EINVAL, "unknown near method");
     int rc = check_walls(walls, d, upsample);
     if (rc != S2D_OK) return rc;
     rc = check_args(S2D_OP_DLP, S2D_FP64, walls, trg, d, img_lo, img_hi, 1.0);
     if (rc != S2D_OK) return rc;
     if (trg->on_curve) return fail(S2D_EINVAL, "the near-wall correction is for free targets: on_curve must be NULL");
     if (trg->n > 0 && (!du || !dv)) return fail(S2D_EINVAL, "outputs du, dv must not be NULL");
+    if (method != S2D_NEAR_UPSAMPLE) {
+        if (!mlp) return fail(S2D_EINVAL, "MLP methods need the packed network");
+        if (trg->n > 0 && !trg_curve) return fail(S2D_EINVAL, "MLP methods need trg_curve");
+        if (walls->n_nodes > 0 && (!walls->w || !walls->kappa))
+            return fail(S2D_EINVAL, "MLP methods need the walls' w and kappa");
+    }
+    if (method == S2D_NEAR_AUTO && !(threshold >= 0.0)) return fail(S2D_EINVAL, "threshold must be >= 0");
     int dev = 0;
     rc = current_device(&dev);
     if (rc != S2D_OK) return rc;
     if (trg->n == 0) return S2D_OK;
     s2d_curves fine{};
-    const NearWallLayout L = near_wall_layout(walls, trg, upsample, &fine);
+    const NearWallLayout L = near_wall_layout(method, walls, trg, upsample, &fine);
     if (!ws || ws_bytes < L.total)
         return fail(S2D_EWORKSPACE, "near-wall workspace too small: need " + std::to_string(L.total) + " bytes");
     if (((uintptr_t)ws & 255) != 0) return fail(S2D_EWORKSPACE, "workspace must be 256-byte aligned");
     hipStream_t st = (hipStream_t)stream;
     char *base = (char *)ws;
-    double *t4 = (double *)(base + L.tmp);     // D_P (u, v), then D_1 (u, v)
+    const int64_t n = trg->n;
+    double *t4 = (double *)(base + L.t4);     // D_P (u, v), then D_1 (u, v); or the result (u, v)
+    hipError_t e = hipSuccess;
     if (walls->n_nodes == 0) {
         // no wall: the correction is zero
-        rc = eval(S2D_OP_DLP, S2D_FP64, walls, trg, d, img_lo, img_hi, 1.0, du, dv, accumulate, base + L.pair,
-                  L.pair_bytes, stream);
-        return rc;
+        return eval(S2D_OP_DLP, S2D_FP64, walls, trg, d, img_lo, img_hi, 1.0, du, dv, accumulate,
+                    base + L.pair, L.pair_bytes, stream);
     }
-    const size_t nf = (size_t)fine.n_nodes;
-    double *fp = (double *)(base + L.up.fine);
-    double *const out[7] = {fp, fp + nf, fp + 2 * nf, fp + 3 * nf, fp + 4 * nf, fp + 5 * nf, fp + 6 * nf};
-    int32_t *foff = (int32_t *)(base + L.up.foff);
-    const s2d::WallArgs a = wall_args(walls, d, upsample, base + L.up.coef, out, foff);
-    hipError_t e = s2d::wall_upsample_launch(a, st);
-    if (e != hipSuccess) return hip_fail(e, "wall upsample launch");
-    fine.curve_off = foff;
-    fine.x = out[0];
-    fine.y = out[1];
-    fine.nx = out[2];
-    fine.ny = out[3];
-    fine.w = out[4];
-    fine.kappa = nullptr;
-    fine.fx = out[5];
-    fine.fy = out[6];
-    const int64_t n = trg->n;
-    rc = eval(S2D_OP_DLP, S2D_FP64, &fine, trg, d, img_lo, img_hi, 1.0, t4, t4 + n, 0, base + L.pair,
-              L.pair_bytes, stream);
-    if (rc != S2D_OK) return rc;
-    rc = eval(S2D_OP_DLP, S2D_FP64, walls, trg, d, img_lo, img_hi, 1.0, t4 + 2 * n, t4 + 3 * n, 0, base + L.pair,
-              L.pair_bytes, stream);
-    if (rc != S2D_OK) return rc;
-    e = s2d::delta_combine_launch(n, accumulate, du, dv, t4, st);
-    return e == hipSuccess ? S2D_OK : hip_fail(e, "near-wall combine launch");
+    // the refined walls (UPSAMPLE; AUTO when some target falls back)
+    const auto refine = [&]() -> int {
+        const size_t nf = (size_t)fine.n_nodes;
+        double *fp = (double *)(base + L.up.fine);
+        double *const out[7] = {fp, fp + nf, fp + 2 * nf, fp + 3 * nf, fp + 4 * nf, fp + 5 * nf, fp + 6 * nf};
+        int32_t *foff = (int32_t *)(base + L.up.foff);
+        const s2d::WallArgs a = wall_args(walls, d, upsample, base + L.up.coef, out, foff);
+        const hipError_t ee = s2d::wall_upsample_launch(a, st);
+        if (ee != hipSuccess) return hip_fail(ee, "wall upsample launch");
+        fine.curve_off = foff;
+        fine.x = out[0];
+        fine.y = out[1];
+        fine.nx = out[2];
+        fine.ny = out[3];
+        fine.w = out[4];
+        fine.kappa = nullptr;
+        fine.fx = out[5];
+        fine.fy = out[6];
+        return S2D_OK;
+    };
+    if (method == S2D_NEAR_UPSAMPLE) {
+        if ((rc = refine()) != S2D_OK) return rc;
+        rc = eval(S2D_OP_DLP, S2D_FP64, &fine, trg, d, img_lo, img_hi, 1.0, t4, t4 + n, 0, base + L.pair,
+                  L.pair_bytes, stream);
+        if (rc != S2D_OK) return rc;
+        rc = eval(S2D_OP_DLP, S2D_FP64, walls, trg, d, img_lo, img_hi, 1.0, t4 + 2 * n, t4 + 3 * n, 0,
+                  base + L.pair, L.pair_bytes, stream);
+        if (rc != S2D_OK) return rc;
+        e = s2d::delta_combine_launch(n, accumulate, du, dv, t4, st);
+        return e == hipSuccess ? S2D_OK : hip_fail(e, "near-wall combine launch");
+    }
+    // MLP, AUTO: features, then the network (AUTO: with the per-bin decision)
+    float *X = (float *)(base + L.X);
+    double *frame = (double *)(base + L.frame);
+    e = s2d::near_launch_wall_features(walls, trg, trg_curve, d, X, frame, st);
+    if (e != hipSuccess) return hip_fail(e, "near-wall features launch");
+    const bool autom = method == S2D_NEAR_AUTO;
+    int32_t *flag = used_fallback ? used_fallback : (autom ? (int32_t *)(base + L.flag) : nullptr);
+    double *tu = t4, *tv = t4 + n;
+    e = s2d::near_launch_infer(n, X, frame, (const s2d::NearBlob *)mlp, s2d::kWallMuScale, threshold, autom ? 1 : 0,
+                               tu, tv, flag, st);
+    if (e != hipSuccess) return hip_fail(e, "near-wall MLP launch");
+    if (autom) {
+        // the fallback targets: the refined quadrature at a compacted list
+        int32_t *list = (int32_t *)(base + L.list), *count = (int32_t *)(base + L.count);
+        double *cx = (double *)(base + L.cxy), *cy = cx + n;
+        e = s2d::zero_int_launch(count, 1, st);
+        if (e == hipSuccess) e = s2d::fallback_compact_launch(n, flag, trg->x, trg->y, list, count, cx, cy, st);
+        int32_t m = 0;
+        if (e == hipSuccess) e = hipMemcpyAsync(&m, count, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "near-wall fallback list");
+        if (m > 0) {
+            if ((rc = refine()) != S2D_OK) return rc;
+            // fine and coarse sums of the m targets into the feature area
+            // (the features are no longer needed)
+            static_assert(s2d::kNearFeat * sizeof(float) >= 4 * sizeof(double), "four doubles per target fit in X");
+            double *f4 = (double *)(base + L.X);
+            const s2d_targets tl{m, cx, cy, nullptr, nullptr};
+            rc = eval(S2D_OP_DLP, S2D_FP64, &fine, &tl, d, img_lo, img_hi, 1.0, f4, f4 + m, 0, base + L.pair,
+                      L.pair_bytes, stream);
+            if (rc != S2D_OK) return rc;
+            rc = eval(S2D_OP_DLP, S2D_FP64, walls, &tl, d, img_lo, img_hi, 1.0, f4 + 2 * m, f4 + 3 * m, 0,
+                      base + L.pair, L.pair_bytes, stream);
+            if (rc != S2D_OK) return rc;
+            e = s2d::fallback_scatter_launch(m, list, f4, tu, tv, st);
+            if (e != hipSuccess) return hip_fail(e, "near-wall fallback scatter");
+        }
+    }
+    e = s2d::add_or_write_launch(n, accumulate, du, dv, tu, tv, st);
+    return e == hipSuccess ? S2D_OK : hip_fail(e, "near-wall output launch");
 }
 
 S2D_API const char *stokes2d_last_error(void) { return g_err.c_str(); }

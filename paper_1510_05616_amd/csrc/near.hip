@@ -261,6 +261,85 @@ __global__ __launch_bounds__(256) void near_features(int64_t n_trg, const double
     fr[5] = F;
 }
 
+// a9 for the walls: target i near one period of wall curve tc[i] (N >= 8
+// nodes advancing by sg d in x), the wall unrolled over three periods (node
+// K in [-N, 2N) at (x_{K mod N} + sg d floor(K / N), y_{K mod N})); nearest
+// unrolled node with the smallest K on ties, then the same features as for
+// closed curves; frame (t0, n0, 1, F): the double layer's correction scales
+// with F alone
+__global__ __launch_bounds__(256) void near_wall_features(int64_t n_trg, const double *__restrict__ tx,
+                                                          const double *__restrict__ ty,
+                                                          const int32_t *__restrict__ tc,
+                                                          const int32_t *__restrict__ off, int32_t n_curves,
+                                                          int64_t n_src, const double *__restrict__ x,
+                                                          const double *__restrict__ y,
+                                                          const double *__restrict__ nx,
+                                                          const double *__restrict__ ny,
+                                                          const double *__restrict__ kap,
+                                                          const double *__restrict__ w,
+                                                          const double *__restrict__ fx,
+                                                          const double *__restrict__ fy, double d,
+                                                          float *__restrict__ X, double *__restrict__ frame) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_trg) return;
+    const int c = tc[i];
+    const int lo = (c >= 0 && c < n_curves) ? off[c] : 0;
+    const int N = (c >= 0 && c < n_curves) ? off[c + 1] - lo : 0;
+    float *xi = X + i * kNearFeat;
+    double *fr = frame + i * 6;
+    if (c < 0 || c >= n_curves || N < 8 || lo < 0 || (int64_t)lo + N > n_src) {
+        for (int k = 0; k < kNearFeat; ++k) xi[k] = __builtin_nanf("");
+        for (int k = 0; k < 6; ++k) fr[k] = __builtin_nan("");
+        return;
+    }
+    const double sg = x[lo + 1] > x[lo] ? 1.0 : -1.0;
+    const double px = tx[i], py = ty[i];
+    double best = 1e300, wsum = 0.0;
+    int ks = 0;
+    for (int k = 0; k < N; ++k) wsum += w[lo + k];
+    for (int m = -1; m <= 1; ++m) {
+        const double sh = sg * d * (double)m;
+        for (int k = 0; k < N; ++k) {
+            const double dx = px - (x[lo + k] + sh), dy = py - y[lo + k];
+            const double d2 = dx * dx + dy * dy;
+            if (d2 < best) { best = d2; ks = m * N + k; }
+        }
+    }
+    const double h = wsum / (double)N;
+    const auto md = [N](int K) { return ((K % N) + N) % N; };
+    const auto fl = [N](int K) { return K >= 0 ? K / N : -((-K + N - 1) / N); };
+    const int ms = md(ks);
+    const double xs = x[lo + ms] + sg * d * (double)fl(ks), ys = y[lo + ms];
+    const double ts0 = -ny[lo + ms], ts1 = nx[lo + ms];
+    const int k0 = ((px - xs) * ts0 + (py - ys) * ts1 >= 0.0) ? ks : ks - 1;
+    const int m0 = md(k0);
+    const double t0 = -ny[lo + m0], t1 = nx[lo + m0];
+    const double n0 = nx[lo + m0], n1 = ny[lo + m0];
+    const double ox = px - (x[lo + m0] + sg * d * (double)fl(k0)), oy = py - y[lo + m0];
+    double ft[8], fn[8], F = 0.0;
+    for (int j = 0; j < 8; ++j) {
+        const int k = lo + md(k0 + j - 3);
+        ft[j] = fx[k] * t0 + fy[k] * t1;
+        fn[j] = fx[k] * n0 + fy[k] * n1;
+        F = fmax(F, sqrt(ft[j] * ft[j] + fn[j] * fn[j]));
+    }
+    if (F == 0.0) F = 1.0;
+    xi[0] = (float)((ox * t0 + oy * t1) / h);
+    xi[1] = (float)((ox * n0 + oy * n1) / h);
+    xi[2] = (float)log(sqrt(best) / h);
+    xi[3] = (float)(kap[lo + m0] * h);
+    for (int j = 0; j < 8; ++j) {
+        xi[4 + j] = (float)(ft[j] / F);
+        xi[12 + j] = (float)(fn[j] / F);
+    }
+    fr[0] = t0;
+    fr[1] = t1;
+    fr[2] = n0;
+    fr[3] = n1;
+    fr[4] = 1.0;
+    fr[5] = F;
+}
+
 // scaled labels in the local frame: (Delta . t0, Delta . n0) * 4 pi mu / (h F)
 __global__ __launch_bounds__(256) void near_scale_labels_k(int64_t n, const double *__restrict__ du,
                                                            const double *__restrict__ dv,
@@ -601,6 +680,15 @@ hipError_t near_launch_features(const s2d_curves *c, const s2d_targets *t, const
     if (t->n <= 0) return hipSuccess;
     hipLaunchKernelGGL(near_features, dim3(grid_for(t->n)), dim3(256), 0, st, t->n, t->x, t->y, tc, c->curve_off,
                        c->n_curves, c->n_nodes, c->x, c->y, c->nx, c->ny, c->kappa, c->w, c->fx, c->fy, X, frame);
+    return hipGetLastError();
+}
+
+hipError_t near_launch_wall_features(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, double d,
+                                     float *X, double *frame, hipStream_t st) {
+    if (t->n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(near_wall_features, dim3((unsigned)((t->n + 255) / 256)), dim3(256), 0, st, t->n, t->x, t->y,
+                       tc, c->curve_off, c->n_curves, c->n_nodes, c->x, c->y, c->nx, c->ny, c->kappa, c->w, c->fx,
+                       c->fy, d, X, frame);
     return hipGetLastError();
 }
 

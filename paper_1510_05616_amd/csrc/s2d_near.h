@@ -41,6 +41,12 @@ hipError_t near_launch_features(const s2d_curves *c, const s2d_targets *t, const
                                 double *frame, hipStream_t st);
 hipError_t near_launch_scale_labels(int64_t n, const double *du, const double *dv, const double *frame, double mu,
                                     float *Y, hipStream_t st);
+hipError_t near_launch_wall_features(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, double d,
+                                     float *X, double *frame, hipStream_t st);
+// The walls' labels and inference reuse the single layer's scale
+// h F / (4 pi mu): with the frame's length factor 1 and mu = 1/4 it is the
+// double layer's F / pi.
+constexpr double kWallMuScale = 0.25;
 hipError_t near_launch_infer(int64_t n, const float *X, const double *frame, const NearBlob *nb, double mu,
                              double threshold, int use_bound, double *du, double *dv, int32_t *flag, hipStream_t st);
 hipError_t near_launch_pack(const float *prm, const float *bound, const float *bound_zero, int32_t n_bins,
@@ -76,5 +82,16 @@ WallScratch wall_scratch(int64_t n_nodes, int P);
 hipError_t wall_upsample_launch(const WallArgs &a, hipStream_t st);
 // t = [uf | vf | uc | vc], each [n]: u (+)= uf - uc, v (+)= vf - vc
 hipError_t delta_combine_launch(int64_t n, int accumulate, double *u, double *v, const double *t, hipStream_t st);
+// u (+)= tu, v (+)= tv
+hipError_t add_or_write_launch(int64_t n, int accumulate, double *u, double *v, const double *tu, const double *tv,
+                               hipStream_t st);
+// the targets with flag 1 into a list (order unspecified): count[0] = how
+// many, list, and their coordinates cx, cy; count must be zero on entry
+hipError_t fallback_compact_launch(int64_t n, const int32_t *flag, const double *tx, const double *ty, int32_t *list,
+                                   int32_t *count, double *cx, double *cy, hipStream_t st);
+// tu[list[j]] = uf[j] - uc[j], tv[list[j]] = vf[j] - vc[j], t4 = [uf|vf|uc|vc] of m
+hipError_t fallback_scatter_launch(int64_t m, const int32_t *list, const double *t4, double *tu, double *tv,
+                                   hipStream_t st);
+hipError_t zero_int_launch(int32_t *p, int n, hipStream_t st);
 
 }  // namespace s2d

@@ -258,6 +258,43 @@ __global__ __launch_bounds__(256) void delta_combine(int64_t n, int acc, double 
     v[i] = acc ? v[i] + dv : dv;
 }
 
+__global__ __launch_bounds__(256) void add_or_write(int64_t n, int acc, double *__restrict__ u,
+                                                    double *__restrict__ v, const double *__restrict__ tu,
+                                                    const double *__restrict__ tv) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    u[i] = acc ? u[i] + tu[i] : tu[i];
+    v[i] = acc ? v[i] + tv[i] : tv[i];
+}
+
+// one vector atomic per fallback target
+__global__ __launch_bounds__(256) void fallback_compact(int64_t n, const int32_t *__restrict__ flag,
+                                                        const double *__restrict__ tx, const double *__restrict__ ty,
+                                                        int32_t *__restrict__ list, int32_t *__restrict__ count,
+                                                        double *__restrict__ cx, double *__restrict__ cy) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || flag[i] != 1) return;
+    const int32_t j = atomicAdd(count, 1);
+    list[j] = (int32_t)i;
+    cx[j] = tx[i];
+    cy[j] = ty[i];
+}
+
+__global__ __launch_bounds__(256) void fallback_scatter(int64_t m, const int32_t *__restrict__ list,
+                                                        const double *__restrict__ t4, double *__restrict__ tu,
+                                                        double *__restrict__ tv) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    const int32_t i = list[j];
+    tu[i] = t4[j] - t4[2 * m + j];
+    tv[i] = t4[m + j] - t4[3 * m + j];
+}
+
+__global__ void zero_int(int32_t *p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
 unsigned grid(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
@@ -294,6 +331,32 @@ hipError_t wall_upsample_launch(const WallArgs &a, hipStream_t st) {
         hipLaunchKernelGGL(wall_synth_part, dim3(g2, (unsigned)a.s2), dim3(256), 0, st, a);
         hipLaunchKernelGGL(wall_synth_fin, dim3(g2), dim3(256), 0, st, a);
     }
+    return hipGetLastError();
+}
+
+hipError_t add_or_write_launch(int64_t n, int accumulate, double *u, double *v, const double *tu, const double *tv,
+                               hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(add_or_write, dim3(grid(n)), dim3(256), 0, st, n, accumulate ? 1 : 0, u, v, tu, tv);
+    return hipGetLastError();
+}
+
+hipError_t fallback_compact_launch(int64_t n, const int32_t *flag, const double *tx, const double *ty, int32_t *list,
+                                   int32_t *count, double *cx, double *cy, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fallback_compact, dim3(grid(n)), dim3(256), 0, st, n, flag, tx, ty, list, count, cx, cy);
+    return hipGetLastError();
+}
+
+hipError_t fallback_scatter_launch(int64_t m, const int32_t *list, const double *t4, double *tu, double *tv,
+                                   hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fallback_scatter, dim3(grid(m)), dim3(256), 0, st, m, list, t4, tu, tv);
+    return hipGetLastError();
+}
+
+hipError_t zero_int_launch(int32_t *p, int n, hipStream_t st) {
+    hipLaunchKernelGGL(zero_int, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n);
     return hipGetLastError();
 }
 

@@ -61,10 +61,14 @@ def _bind():
     L.stokes2d_wall_upsample_workspace_size.restype = SZ
     L.stokes2d_wall_upsample.argtypes = [P, D, I32, P, P, P, P, P, P, P, P, P, SZ, P]
     L.stokes2d_wall_upsample.restype = I
-    L.near_wall_workspace_size.argtypes = [P, P, I32]
+    L.near_wall_workspace_size.argtypes = [I, P, P, I32]
     L.near_wall_workspace_size.restype = SZ
-    L.near_wall_correct_eval.argtypes = [P, P, D, I32, I32, I32, P, P, I, P, SZ, P]
+    L.near_wall_correct_eval.argtypes = [I, P, P, P, D, I32, I32, I32, P, D, P, P, P, I, P, SZ, P]
     L.near_wall_correct_eval.restype = I
+    L.near_wall_features_eval.argtypes = [P, P, P, D, P, P, P]
+    L.near_wall_features_eval.restype = I
+    L.near_wall_scale_labels.argtypes = [I64, P, P, P, P, P]
+    L.near_wall_scale_labels.restype = I
     _bound = True
     return L
 
@@ -122,22 +126,38 @@ def stokes2d_wall_upsample(walls: Curves, d, upsample, ws=None, stream=None) -> 
     return Curves(types.SimpleNamespace(kappa=None, curve_off=off, **out), walls.device)
 
 
-def near_wall_workspace_size(walls: Curves, trg: Targets, upsample: int) -> int:
+def near_wall_workspace_size(walls: Curves, trg: Targets, upsample: int, method=S2D_NEAR_UPSAMPLE) -> int:
     L = _bind()
     cs, ts = walls.struct(), trg.struct()
-    return int(L.near_wall_workspace_size(ctypes.byref(cs), ctypes.byref(ts), int(upsample)))
+    return int(L.near_wall_workspace_size(int(method), ctypes.byref(cs), ctypes.byref(ts), int(upsample)))
 
 
 def near_wall_correct_eval(walls: Curves, trg: Targets, d, img_lo, img_hi, upsample, du, dv, accumulate=0,
+                           method=S2D_NEAR_UPSAMPLE, trg_curve=None, blob=None, threshold=0.0, used_fallback=None,
                            ws=None, stream=None) -> None:
-    """du, dv (device float64, [trg.n]) = (or +=) D_P - D_1 of the walls."""
+    """du, dv (device float64, [trg.n]) = (or +=) D_P - D_1 of the walls:
+    by the refined walls (UPSAMPLE), the network (MLP) or per target
+    (AUTO; trg_curve names each target's wall)."""
     L = _bind()
     cs, ts = walls.struct(), trg.struct()
     if ws is None:
-        ws = _empty(near_wall_workspace_size(walls, trg, upsample), du.device)
-    _check(L.near_wall_correct_eval(ctypes.byref(cs), ctypes.byref(ts), float(d), int(img_lo), int(img_hi),
-                                    int(upsample), _ptr(du), _ptr(dv), int(accumulate), _ptr(ws), ws.numel(),
+        ws = _empty(near_wall_workspace_size(walls, trg, upsample, method), du.device)
+    _check(L.near_wall_correct_eval(int(method), ctypes.byref(cs), ctypes.byref(ts), _ptr(trg_curve), float(d),
+                                    int(img_lo), int(img_hi), int(upsample), _ptr(blob), float(threshold), _ptr(du),
+                                    _ptr(dv), _ptr(used_fallback), int(accumulate), _ptr(ws), ws.numel(),
                                     _stream(stream)))
+
+
+def near_wall_features_eval(walls: Curves, trg: Targets, trg_curve, d, X, frame, stream=None) -> None:
+    L = _bind()
+    cs, ts = walls.struct(), trg.struct()
+    _check(L.near_wall_features_eval(ctypes.byref(cs), ctypes.byref(ts), _ptr(trg_curve), float(d), _ptr(X),
+                                     _ptr(frame), _stream(stream)))
+
+
+def near_wall_scale_labels(du, dv, frame, Y, stream=None) -> None:
+    _check(_bind().near_wall_scale_labels(int(du.shape[0]), _ptr(du), _ptr(dv), _ptr(frame), _ptr(Y),
+                                          _stream(stream)))
 
 
 def near_features_eval(ves: Curves, trg: Targets, trg_curve, X, frame, stream=None) -> None:
@@ -235,6 +255,47 @@ class NearData:
             self.Y = torch.empty((self.n, 2), dtype=torch.float32, device=device)
             near_scale_labels(self.du, self.dv, self.frame, mu, self.Y)
 
+    def correct(self, method, blob, threshold, du, dv, used_fallback=None):
+        near_correct_eval(method, self.curves, self.trg, self.tc, self.P, blob, threshold, self.mu, du, dv,
+                          used_fallback)
+
+
+# the walls' labels are scaled by pi / F; with the frame's length factor 1
+# this is the single layer's 4 pi mu / (h F) at mu = 1/4, so the training,
+# error and calibration helpers serve both
+WALL_MU = 0.25
+
+
+class WallNearData:
+    """Near-wall dataset: targets near periodic walls (trg_curve naming each
+    one's wall), their features and frames, and (optionally) FP64 labels from
+    the refined-wall quadrature (images img_lo..img_hi of period d)."""
+
+    def __init__(self, walls, d, tx, ty, tc, upsample=8, img=(-1, 1), labels=True, device="cuda"):
+        import torch
+        self.curves = Curves(walls, device)
+        self.trg = Targets(tx, ty, device=device)
+        self.tc = torch.as_tensor(np.ascontiguousarray(tc, dtype=np.int32), device=device)
+        self.n = self.trg.n
+        self.d, self.img = float(d), img
+        self.mu = WALL_MU
+        self.P = upsample
+        self.X = torch.empty((self.n, NFEAT), dtype=torch.float32, device=device)
+        self.frame = torch.empty((self.n, 6), dtype=torch.float64, device=device)
+        near_wall_features_eval(self.curves, self.trg, self.tc, self.d, self.X, self.frame)
+        self.du = self.dv = self.Y = None
+        if labels:
+            self.du = torch.empty(self.n, dtype=torch.float64, device=device)
+            self.dv = torch.empty_like(self.du)
+            near_wall_correct_eval(self.curves, self.trg, self.d, img[0], img[1], upsample, self.du, self.dv)
+            self.Y = torch.empty((self.n, 2), dtype=torch.float32, device=device)
+            near_wall_scale_labels(self.du, self.dv, self.frame, self.Y)
+
+    def correct(self, method, blob, threshold, du, dv, used_fallback=None):
+        near_wall_correct_eval(self.curves, self.trg, self.d, self.img[0], self.img[1], self.P, du, dv,
+                               method=method, trg_curve=self.tc, blob=blob, threshold=threshold,
+                               used_fallback=used_fallback)
+
 
 def train(data: NearData, epochs=60, batch=1024, lr=2e-3, lr_min=2e-5, seed=0, log=None):
     """Trains the MLP on data.X -> data.Y with the library's kernels; returns
@@ -294,7 +355,7 @@ def calibrate(data: NearData, params, quantile=1.0, safety=1.5):
     near_mlp_pack(params, zero, N_BINS, BIN_LO, BIN_W, blob)
     du = torch.empty_like(data.du)
     dv = torch.empty_like(data.dv)
-    near_correct_eval(S2D_NEAR_MLP, data.curves, data.trg, data.tc, data.P, blob, 0.0, data.mu, du, dv)
+    data.correct(S2D_NEAR_MLP, blob, 0.0, du, dv)
     err = scaled_errors(data, du, dv).cpu().numpy()
     err0 = scaled_errors(data, torch.zeros_like(du), torch.zeros_like(dv)).cpu().numpy()
     noff = np.abs(data.X[:, 1].double().cpu().numpy())

@@ -381,6 +381,20 @@ def near_wall_points(walls: CurveSet, n: int, seed: int, lo: float = 0.05, hi: f
     return walls.x[i] - a * nx - b * ny, walls.y[i] - a * ny + b * nx
 
 
+def near_wall_dataset(walls: CurveSet, n: int, seed: int, lo: float = 0.05, hi: float = 5.0):
+    """n seeded targets near the wall curves for the learned wall correction:
+    at a uniformly drawn node i, moved into the fluid by delta = h_i
+    10^U(log10 lo, log10 hi) along the normal (h_i the node's weight) and by
+    U(-1/2, 1/2) h_i along the wall.  Returns (x, y, wall curve of each)."""
+    rng = np.random.default_rng(seed)
+    i = rng.integers(0, walls.x.shape[0], n)
+    a = 10.0 ** rng.uniform(math.log10(lo), math.log10(hi), n) * walls.w[i]
+    b = rng.uniform(-0.5, 0.5, n) * walls.w[i]
+    nx, ny = walls.nx[i], walls.ny[i]
+    curve = (np.searchsorted(walls.curve_off, i, side="right") - 1).astype(np.int32)
+    return walls.x[i] - a * nx - b * ny, walls.y[i] - a * ny + b * nx, curve
+
+
 def wall_densities(walls: CurveSet, seed: int, modes: int = 5) -> CurveSet:
     """The wall curves with a smooth seeded density on each: a random
     trigonometric polynomial of degree `modes` in the node parameter

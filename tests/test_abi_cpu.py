@@ -173,8 +173,10 @@ def test_wall_argument_checks(L):
     assert L.stokes2d_wall_upsample_workspace_size(None, 8) == 0
     assert L.stokes2d_wall_upsample_workspace_size(by(walls), 0) == 0
     assert L.stokes2d_wall_upsample_workspace_size(by(walls), 8) >= 64 * 64
-    assert L.near_wall_workspace_size(by(walls), by(ts), 8) > 8 * 64 * 7 * 8
-    assert L.near_wall_workspace_size(by(walls), by(ts), 33) == 0
+    assert L.near_wall_workspace_size(0, by(walls), by(ts), 8) > 8 * 64 * 7 * 8
+    assert L.near_wall_workspace_size(0, by(walls), by(ts), 33) == 0
+    assert L.near_wall_workspace_size(3, by(walls), by(ts), 8) == 0
+    assert L.near_wall_workspace_size(1, by(walls), by(ts), 8) > 0
     # upsample factor, period, missing normals, missing outputs
     assert L.stokes2d_wall_upsample(by(walls), 1.0, 0, *o, fake, 1 << 20, None) == s2d.S2D_EINVAL
     assert L.stokes2d_wall_upsample(by(walls), 0.0, 4, *o, fake, 1 << 20, None) == s2d.S2D_EINVAL
@@ -183,13 +185,18 @@ def test_wall_argument_checks(L):
     assert L.stokes2d_wall_upsample(by(walls), 1.0, 4, None, *o[1:], fake, 1 << 20, None) == s2d.S2D_EINVAL
     none = s2d._Curves(64, 0, fake, fake, fake, fake, fake, None, None, fake, fake)     # nodes but no curves
     assert L.stokes2d_wall_upsample(by(none), 1.0, 4, *o, fake, 1 << 20, None) == s2d.S2D_EINVAL
-    # the correction: free targets only, outputs, images
-    assert L.near_wall_correct_eval(by(walls), by(ts_on), 1.0, -1, 1, 8, fake, fake, 0, fake, 1 << 30,
-                                    None) == s2d.S2D_EINVAL
-    assert L.near_wall_correct_eval(by(walls), by(ts), 1.0, -1, 1, 8, None, fake, 0, fake, 1 << 30,
-                                    None) == s2d.S2D_EINVAL
-    assert L.near_wall_correct_eval(by(walls), by(ts), 1.0, 1, -1, 8, fake, fake, 0, fake, 1 << 30,
-                                    None) == s2d.S2D_EINVAL
+    # the correction: free targets only, outputs, images, method, network
+    def corr(method, trg, lo, hi, du, mlp=None, tc=fake):
+        return L.near_wall_correct_eval(method, by(walls), by(trg), tc, 1.0, lo, hi, 8, mlp, 0.0, du, fake, None,
+                                        0, fake, 1 << 30, None)
+    assert corr(0, ts_on, -1, 1, fake) == s2d.S2D_EINVAL
+    assert corr(0, ts, -1, 1, None) == s2d.S2D_EINVAL
+    assert corr(0, ts, 1, -1, fake) == s2d.S2D_EINVAL
+    assert corr(5, ts, -1, 1, fake) == s2d.S2D_EINVAL
+    assert corr(1, ts, -1, 1, fake, mlp=None) == s2d.S2D_EINVAL            # MLP needs the network
+    assert corr(2, ts, -1, 1, fake, mlp=fake, tc=None) == s2d.S2D_EINVAL   # and trg_curve
+    assert corr(1, ts, -1, 1, fake, mlp=fake) == s2d.S2D_EINVAL            # and the walls' w, kappa
+    assert L.near_wall_features_eval(by(walls), by(ts), None, 1.0, fake, fake, None) == s2d.S2D_EINVAL
 
 
 def test_vesicle_argument_checks(L):

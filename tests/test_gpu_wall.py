@@ -218,3 +218,89 @@ def test_delta_accumulate_and_edges():
     near_wall_correct_eval(e, Targets(tx, ty), prob.d, -1, 1, 4, a, b)
     torch.cuda.synchronize()
     assert torch.all(a == 0) and torch.all(b == 0)
+
+
+# ---------------------------------------------------------------------------
+# the learned route for the walls (features, network, AUTO)
+# ---------------------------------------------------------------------------
+def _wall_learning_set(n, seed):
+    prob = synth.make_config(2)
+    walls = synth.wall_densities(prob.wall, 31)
+    tx, ty, tc = synth.near_wall_dataset(walls, n, seed)
+    return walls, prob.d, tx, ty, tc
+
+
+def test_wall_features_match_the_oracle():
+    import torch
+    from oracle import near as onear
+    from paper_1510_05616_amd import Curves, Targets
+    from paper_1510_05616_amd import near as pn
+    walls, d, tx, ty, tc = _wall_learning_set(3000, 33)
+    # and targets across the period boundary of each wall
+    h = walls.w[:2048].mean()
+    tx = np.r_[tx, [-0.4 * h, d + 0.3 * h, 0.1 * h, d - 0.2 * h]]
+    ty = np.r_[ty, [0.95, -0.97, 0.9, -0.9]]
+    tc = np.r_[tc, [0, 1, 0, 1]].astype(np.int32)
+    n = tx.shape[0]
+    X = torch.empty((n, 20), dtype=torch.float32, device="cuda")
+    fr = torch.empty((n, 6), dtype=torch.float64, device="cuda")
+    pn.near_wall_features_eval(Curves(walls), Targets(tx, ty), torch.as_tensor(tc, device="cuda"), d, X, fr)
+    torch.cuda.synchronize()
+    ox, ofr = onear.wall_features(walls, d, tx, ty, tc)
+    gx = X.cpu().numpy()
+    err_x = np.abs(gx - ox.astype(np.float32)) / np.maximum(np.abs(ox), 1.0)
+    print(f"wall features: max rel diff {err_x.max():.2e}, frame {np.abs(fr.cpu().numpy() - ofr).max():.2e}",
+          flush=True)
+    assert err_x.max() < 4e-7 and np.abs(fr.cpu().numpy() - ofr).max() < 1e-13
+
+
+def test_wall_auto_extremes_and_network_gain():
+    import torch
+    from paper_1510_05616_amd import near as pn
+    walls, d, tx, ty, tc = _wall_learning_set(60000, 34)
+    tr = pn.WallNearData(walls, d, tx, ty, tc)
+    params, hist = pn.train(tr, epochs=20, batch=512, lr=3e-3)
+    assert hist[-1] < 0.2 * hist[0]
+    va = pn.WallNearData(walls, d, *_wall_learning_set(10000, 35)[2:])
+    blob, bound, bound0 = pn.calibrate(va, params)
+    te = pn.WallNearData(walls, d, *_wall_learning_set(10000, 36)[2:])
+    du = torch.empty(te.n, dtype=torch.float64, device="cuda")
+    dv = torch.empty_like(du)
+    fb = torch.zeros(te.n, dtype=torch.int32, device="cuda")
+    # the network gains over no correction near the walls
+    te.correct(pn.S2D_NEAR_MLP, blob, 0.0, du, dv, fb)
+    torch.cuda.synchronize()
+    e_mlp = pn.scaled_errors(te, du, dv).cpu().numpy()
+    e_plain = pn.scaled_errors(te, torch.zeros_like(du), torch.zeros_like(dv)).cpu().numpy()
+    noff = np.abs(te.X[:, 1].double().cpu().numpy())
+    sel = noff < 0.5
+    print(f"walls, targets within h/2: plain {np.median(e_plain[sel]):.2e} mlp {np.median(e_mlp[sel]):.2e}",
+          flush=True)
+    assert np.median(e_mlp[sel]) < 0.3 * np.median(e_plain[sel])
+    assert torch.all(fb == 0)
+    # AUTO: threshold 0 is the refined quadrature everywhere; a huge one no
+    # correction; in between every target within the threshold of it
+    te.correct(pn.S2D_NEAR_AUTO, blob, 0.0, du, dv, fb)
+    torch.cuda.synchronize()
+    assert torch.all(fb == 1)
+    e = max((du - te.du).abs().max().item(), (dv - te.dv).abs().max().item())
+    assert e <= 1e-12 * max(te.du.abs().max().item(), te.dv.abs().max().item()), e
+    te.correct(pn.S2D_NEAR_AUTO, blob, 1e30, du, dv, fb)
+    torch.cuda.synchronize()
+    assert torch.all(fb == 2) and torch.all(du == 0) and torch.all(dv == 0)
+    thr = 1e-3 * te.du.abs().max().item()
+    te.correct(pn.S2D_NEAR_AUTO, blob, thr, du, dv, fb)
+    torch.cuda.synchronize()
+    err = torch.hypot(du - te.du, dv - te.dv).max().item()
+    used = [(fb == k).float().mean().item() for k in range(3)]
+    print(f"walls AUTO at {thr:.2e}: max error {err:.2e}, network/quadrature/none {used}", flush=True)
+    assert err <= thr
+    # a looser threshold hands the network the bins whose calibrated bound
+    # it meets; the result still holds the threshold
+    thr = 0.3 * te.du.abs().max().item()
+    te.correct(pn.S2D_NEAR_AUTO, blob, thr, du, dv, fb)
+    torch.cuda.synchronize()
+    err = torch.hypot(du - te.du, dv - te.dv).max().item()
+    used = [(fb == k).float().mean().item() for k in range(3)]
+    print(f"walls AUTO at {thr:.2e}: max error {err:.2e}, network/quadrature/none {used}", flush=True)
+    assert err <= thr and used[0] > 0

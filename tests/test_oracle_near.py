@@ -200,3 +200,36 @@ def test_wall_correction_converges_to_the_integral(oracle_lib):
     e1 = np.hypot(vals[1][0] - vals[32][0], vals[1][1] - vals[32][1])[0] / ref
     e8 = np.hypot(vals[8][0] - vals[32][0], vals[8][1] - vals[32][1])[0] / ref
     assert e1 > 1e-3 and e8 < 1e-3 * e1, (e1, e8)
+
+
+def test_wall_features_reconstruct_target_and_window():
+    # from the features and the frame, the target is node K0 (unrolled over
+    # the period) plus h (s t0 + n_off n0), also for targets across the
+    # period boundary; the window is the wall density in the local frame
+    import math
+    from oracle import near as onear
+    walls, sy, d = synth.make_channel(64, 4)
+    w = synth.wall_densities(walls, 3)
+    rng = np.random.default_rng(4)
+    N = 64
+    s = slice(0, N)                     # the upper wall, x from 0 to d
+    h = w.w[s].sum() / N
+    for px, py in ((0.01, 0.9), (d - 0.02, 0.95), (-0.05, 0.92), (d + 0.03, 0.9), (2.0, 1.1)):
+        f, t0, n0, one, F = onear.wall_features_one(w.x[s], w.y[s], w.nx[s], w.ny[s], w.kappa[s], w.w[s],
+                                                    w.fx[s], w.fy[s], d, px, py)
+        assert one == 1.0
+        # candidate K0 positions: the node whose unrolled position + offsets gives p
+        ox, oy = h * (f[0] * t0[0] + f[1] * n0[0]), h * (f[0] * t0[1] + f[1] * n0[1])
+        qx, qy = px - ox, py - oy
+        K = np.arange(-N, 2 * N)
+        X = w.x[s][K % N] + d * np.floor_divide(K, N)
+        j = int(np.argmin((X - qx) ** 2 + (w.y[s][K % N] - qy) ** 2))
+        assert math.hypot(X[j] - qx, w.y[s][K[j] % N] - qy) < 1e-12
+        k0 = int(K[j])
+        # k0 is the nearest node or its predecessor
+        d2 = (X - px) ** 2 + (w.y[s][K % N] - py) ** 2
+        assert k0 in (int(K[np.argmin(d2)]), int(K[np.argmin(d2)]) - 1)
+        win = [(k0 + jj) % N for jj in range(-3, 5)]
+        ft = (w.fx[s][win] * t0[0] + w.fy[s][win] * t0[1]) / F
+        assert np.abs(f[4:12] - ft).max() < 1e-14
+        assert abs(f[2] - math.log(math.sqrt(d2.min()) / h)) < 1e-12
