@@ -719,6 +719,8 @@ def main():
     ap.add_argument("--f1", type=int, default=1, help="run the pressure/traction section (0: skip)")
     ap.add_argument("--cell", type=int, default=1, help="run the periodization-system section (0: skip)")
     ap.add_argument("--walls", type=int, default=1, help="run the near-wall correction sections (0: skip)")
+    ap.add_argument("--walls-learned", type=int, default=1,
+                    help="with --walls, also run the learned near-wall section (0: skip)")
     ap.add_argument("--step", type=int, default=1, help="run the vesicle time-step section (0: skip)")
     ap.add_argument("--channel", type=int, default=1,
                     help="run Algorithm 1 in the channel, with the cell factored once (0: skip)")
@@ -789,7 +791,8 @@ def main():
 
     f1_res = f1_section(prob) if args.f1 and args.config == 3 else None
     wall_res = wall_section(prob) if args.walls and args.config == 3 else None
-    wall_learned = wall_learned_section(prob) if args.walls and args.config == 3 else None
+    wall_learned = (wall_learned_section(prob) if args.walls and args.walls_learned and args.config == 3
+                    else None)
     step_res = step_section(prob) if args.step and args.config == 3 else None
     chan_res = channel_section(prob) if args.channel and args.config == 3 else None
     cell_res = cell_section() if args.cell else None
