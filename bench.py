@@ -46,6 +46,7 @@ PEAK = {"f32": 157.3e12, "f64": 78.6e12}
 PAIR_SOURCES = ("paper_1510_05616_amd/csrc/pair_impl.h", "paper_1510_05616_amd/csrc/pair.hip",
                 "paper_1510_05616_amd/csrc/s2d_internal.h", "paper_1510_05616_amd/csrc/api.hip")
 PROFILE = "profiles/pair_kernels_config3.md"
+VALU_PROFILE = "profiles/pair_kernels_valu_config3.md"
 
 
 def log(msg):
@@ -71,6 +72,25 @@ def measured_traffic(kernel):
         return None
     m = re.search(r"traffic_bytes " + re.escape(kernel) + r" (\d+)", txt)
     return int(m.group(1)) if m else None
+
+
+def measured_valu(kernel):
+    """VALU issue counters of `kernel` from the committed rocprofv3 summary
+    (VALUBusy %, share of SIMD quad-cycles issuing VALU work, share issuing two
+    VALU instructions, clock), or None when the pair-kernel sources changed
+    since they were taken."""
+    try:
+        txt = open(os.path.join(ROOT, VALU_PROFILE)).read()
+    except OSError:
+        return None
+    m = re.search(r"pair-kernel source sha1: ([0-9a-f]{40})", txt)
+    if not m or m.group(1) != pair_source_sha1():
+        return None
+    m = re.search(r"valu_busy " + re.escape(kernel) + r" ([\d.]+) issuing ([\d.]+) dual ([\d.]+) ghz ([\d.]+)", txt)
+    if not m:
+        return None
+    return {"valu_busy_pct": float(m.group(1)), "valu_issuing_pct": float(m.group(2)),
+            "dual_issue_pct": float(m.group(3)), "clock_ghz": float(m.group(4)), "source": VALU_PROFILE}
 
 
 def copy_probe():
@@ -756,6 +776,8 @@ def main():
                                    "achieved": ach / 1e12, "peak": PEAK[name] / 1e12,
                                    "unit": "TFLOP/s", "frac": ach / PEAK[name],
                                    "traffic": measured_traffic(
+                                       "pair_kernel<0,1,1>" if name == "f32" else "pair_kernel<0,0,1>"),
+                                   "valu_counters": measured_valu(
                                        "pair_kernel<0,1,1>" if name == "f32" else "pair_kernel<0,0,1>"),
                                    "flops_per_pair": FLOPS_PER_PAIR, "pairs_per_launch": pairs_slp},
                          u=r["u"], v=r["v"])
