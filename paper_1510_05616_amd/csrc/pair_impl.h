@@ -116,31 +116,32 @@ __device__ __forceinline__ double log64(double x) {
 }
 
 // Table-driven natural log (Tang's method) of a positive, finite, normal
-// double: x = 2^e m, m in [1/2, 1); the top 8 mantissa bits pick the
-// breakpoint F_k = 1/2 + (k + 1/2) / 512, and
-// log x = e ln 2 + log F_k + log1p(u), u = m / F_k - 1, |u| <= 2^-9.
+// double: x = 2^e m, m in [1/2, 1); the top 9 mantissa bits pick the
+// breakpoint F_k = 1/2 + (k + 1/2) / 1024, and
+// log x = e ln 2 + log F_k + log1p(u), u = m / F_k - 1, |u| <= 2^-10.
 // u is formed as one FMA m (1/F_k) - 1 (error below 2^-52 from the rounding
-// of 1/F_k), log1p is summed to u^5 (first omitted term below 2e-17), and
-// e ln 2 is one rounded product: absolute error a few 1e-16 for the |e| of
+// of 1/F_k), log1p is summed to u^4 (first omitted term below 1.8e-16), and
+// e ln 2 is one rounded product: absolute error below 1e-15 for the |e| of
 // squared distances, far inside the FP64 path's 1e-12 budget.  tab holds the
 // pairs {1/F_k, log F_k} (2 x kLogTab doubles, staged in LDS by
 // fill_log_table; one 16-byte LDS read per call).
-constexpr int kLogTab = 256;
+constexpr int kLogTab = 512;
 constexpr int kLogTabWords = 2 * kLogTab;
 
 __device__ __forceinline__ double log64_tab(double x, const double *tab) {
     const int e = __builtin_amdgcn_frexp_exp(x);
     const double m = __builtin_amdgcn_frexp_mant(x);
     const uint32_t hi = (uint32_t)(__builtin_bit_cast(uint64_t, x) >> 32);
-    const int k = (hi >> 12) & (kLogTab - 1);
+    const int k = (hi >> 11) & (kLogTab - 1);
     typedef double double2_t __attribute__((ext_vector_type(2)));
     const double2_t t = ((const double2_t *)tab)[k];     // {1/F_k, log F_k}
     const double u = __builtin_fma(m, t.x, -1.0);
-    double p = 1.0 / 5.0;
-    p = __builtin_fma(p, u, -1.0 / 4.0);
-    p = __builtin_fma(p, u, 1.0 / 3.0);
-    p = __builtin_fma(p, u, -1.0 / 2.0);
-    const double l1p = __builtin_fma(p * u, u, u);
+    // log1p(u) = u + u^2 (-1/2 + u/3 - u^2/4): each FMA takes at most one
+    // non-inline constant
+    const double v = u * u;
+    double c = __builtin_fma(u, 1.0 / 3.0, -0.5);
+    c = __builtin_fma(v, -0.25, c);
+    const double l1p = __builtin_fma(v, c, u);
     constexpr double kLn2 = 6.93147180559945286227e-01;
     return __builtin_fma((double)e, kLn2, t.y + l1p);
 }
