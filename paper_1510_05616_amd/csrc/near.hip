@@ -267,6 +267,153 @@ __global__ __launch_bounds__(256) void near_features(int64_t n_trg, const double
 // unrolled node with the smallest K on ties, then the same features as for
 // closed curves; frame (t0, n0, 1, F): the double layer's correction scales
 // with F alone
+// Nearest-node search over the three periods of a wall.  Nodes are grouped in
+// cells of kWallCell consecutive nodes; a cell's centre is its middle node and
+// its radius the largest distance of its nodes from that centre.  The search is
+// exact: a cell can hold a node closer than B only if |p - centre| <= B +
+// radius.  Pass 1 takes B from the cell centres (actual nodes); pass 2 scans,
+// in ascending (period, cell) order, every cell that passes the test, node by
+// node in ascending order with a strict comparison.  So the smallest unrolled
+// index among equal distances wins, as in a plain scan.  Each lane collects
+// its own list of cells to scan (up to kWallScan; a lane with more scans every
+// passing cell in order instead), so the lanes of a wave do not scan each
+// other's cells.
+constexpr int kWallCell = 128;
+constexpr int kWallMaxCells = 1024;
+constexpr int kWallMaxCurves = 64;
+constexpr int kWallScan = 10;            // two words of five 12-bit cell codes
+
+struct WallCells {
+    double cx[kWallMaxCells], cy[kWallMaxCells], rad[kWallMaxCells];
+    double h[kWallMaxCurves];            // mean weight of each curve
+    int coff[kWallMaxCurves + 1];
+    int ok;
+};
+
+__device__ __forceinline__ int wall_curve_nodes(const int32_t *off, int c, int64_t n_src) {
+    const int lo = off[c], hi = off[c + 1];
+    return (lo >= 0 && hi >= lo + 8 && (int64_t)hi <= n_src) ? hi - lo : 0;
+}
+
+// every thread of the block calls this (it synchronises)
+__device__ void wall_cells_build(WallCells &W, const int32_t *off, int n_curves, int64_t n_src, const double *x,
+                                 const double *y, const double *w) {
+    __shared__ double red[256];
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        bool ok = n_curves <= kWallMaxCurves;
+        for (int c = 0; ok && c < n_curves; ++c) {
+            W.coff[c] = acc;
+            acc += (wall_curve_nodes(off, c, n_src) + kWallCell - 1) / kWallCell;
+            ok = acc <= kWallMaxCells;
+        }
+        if (ok) W.coff[n_curves] = acc;
+        W.ok = ok ? 1 : 0;
+    }
+    __syncthreads();
+    if (!W.ok) return;                  // block-uniform
+    const int total = W.coff[n_curves];
+    for (int cell = threadIdx.x; cell < total; cell += blockDim.x) {
+        int c = 0;
+        while (W.coff[c + 1] <= cell) ++c;
+        const int lo = off[c], N = wall_curve_nodes(off, c, n_src);
+        const int k0 = (cell - W.coff[c]) * kWallCell, len = min(kWallCell, N - k0);
+        const double cx = x[lo + k0 + len / 2], cy = y[lo + k0 + len / 2];
+        double r2 = 0.0;
+        for (int j = k0; j < k0 + len; ++j) {
+            const double ex = x[lo + j] - cx, ey = y[lo + j] - cy;
+            r2 = fmax(r2, ex * ex + ey * ey);
+        }
+        W.cx[cell] = cx;
+        W.cy[cell] = cy;
+        W.rad[cell] = sqrt(r2) * (1.0 + 1e-12);
+    }
+    // mean weight per curve, in a fixed order (strided partial sums, then a tree)
+    for (int c = 0; c < n_curves; ++c) {
+        const int lo = off[c], N = wall_curve_nodes(off, c, n_src);
+        double sacc = 0.0;
+        for (int k = threadIdx.x; k < N; k += blockDim.x) sacc += w[lo + k];
+        red[threadIdx.x] = sacc;
+        __syncthreads();
+        for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+            if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) W.h[c] = N > 0 ? red[0] / (double)N : 0.0;
+        __syncthreads();
+    }
+}
+
+// nearest unrolled node K = m N + k (m = -1, 0, 1) of curve c to (px, py):
+// returns K and writes its squared distance to best
+__device__ int wall_nearest(const WallCells &W, bool cells, int c, int lo, int N, double sg, double d, double px,
+                            double py, const double *x, const double *y, double &best) {
+    best = 1e300;
+    int ks = 0;
+    const auto scan = [&](int m, int k0, int k1) {
+        const double sh = sg * d * (double)m;
+        for (int k = k0; k < k1; ++k) {
+            const double dx = px - (x[lo + k] + sh), dy = py - y[lo + k];
+            const double d2 = dx * dx + dy * dy;
+            if (d2 < best) { best = d2; ks = m * N + k; }
+        }
+    };
+    if (!cells) {
+        for (int m = -1; m <= 1; ++m) scan(m, 0, N);
+        return ks;
+    }
+    const int cb = W.coff[c], ce = W.coff[c + 1];
+    double ub = 1e300;
+    for (int m = -1; m <= 1; ++m) {
+        const double sh = sg * d * (double)m;
+        for (int q = cb; q < ce; ++q) {
+            const double dx = px - (W.cx[q] + sh), dy = py - W.cy[q];
+            ub = fmin(ub, dx * dx + dy * dy);
+        }
+    }
+    const double bound = sqrt(ub) * (1.0 + 1e-9);
+    // passing cells, as 12-bit codes (m + 1) * kWallMaxCells + (q - cb)
+    uint64_t wd[2] = {0, 0};
+    int nl = 0;
+    for (int m = -1; m <= 1; ++m) {
+        const double sh = sg * d * (double)m;
+        for (int q = cb; q < ce; ++q) {
+            const double dx = px - (W.cx[q] + sh), dy = py - W.cy[q];
+            const double lim = bound + W.rad[q];
+            if (dx * dx + dy * dy <= lim * lim) {
+                if (nl < kWallScan) {
+                    const uint64_t code = (uint64_t)((m + 1) * kWallMaxCells + (q - cb));
+                    if (nl < 5) wd[0] |= code << (12 * nl);
+                    else wd[1] |= code << (12 * (nl - 5));
+                }
+                ++nl;
+            }
+        }
+    }
+    if (nl <= kWallScan) {
+        for (int t = 0; t < nl; ++t) {
+            const int code = (int)(((t < 5 ? wd[0] : wd[1]) >> (12 * (t < 5 ? t : t - 5))) & 0xfff);
+            const int k0 = (code % kWallMaxCells) * kWallCell;
+            scan(code / kWallMaxCells - 1, k0, min(N, k0 + kWallCell));
+        }
+    } else {
+        for (int m = -1; m <= 1; ++m) {
+            const double sh = sg * d * (double)m;
+            for (int q = cb; q < ce; ++q) {
+                const double dx = px - (W.cx[q] + sh), dy = py - W.cy[q];
+                const double lim = bound + W.rad[q];
+                if (dx * dx + dy * dy <= lim * lim) {
+                    const int k0 = (q - cb) * kWallCell;
+                    scan(m, k0, min(N, k0 + kWallCell));
+                }
+            }
+        }
+    }
+    return ks;
+}
+
+// Features of targets near periodic walls (grid-stride over targets; the cell
+// table is built once per block in LDS).
 __global__ __launch_bounds__(256) void near_wall_features(int64_t n_trg, const double *__restrict__ tx,
                                                           const double *__restrict__ ty,
                                                           const int32_t *__restrict__ tc,
@@ -280,64 +427,63 @@ __global__ __launch_bounds__(256) void near_wall_features(int64_t n_trg, const d
                                                           const double *__restrict__ fx,
                                                           const double *__restrict__ fy, double d,
                                                           float *__restrict__ X, double *__restrict__ frame) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_trg) return;
-    const int c = tc[i];
-    const int lo = (c >= 0 && c < n_curves) ? off[c] : 0;
-    const int N = (c >= 0 && c < n_curves) ? off[c + 1] - lo : 0;
-    float *xi = X + i * kNearFeat;
-    double *fr = frame + i * 6;
-    if (c < 0 || c >= n_curves || N < 8 || lo < 0 || (int64_t)lo + N > n_src) {
-        for (int k = 0; k < kNearFeat; ++k) xi[k] = __builtin_nanf("");
-        for (int k = 0; k < 6; ++k) fr[k] = __builtin_nan("");
-        return;
-    }
-    const double sg = x[lo + 1] > x[lo] ? 1.0 : -1.0;
-    const double px = tx[i], py = ty[i];
-    double best = 1e300, wsum = 0.0;
-    int ks = 0;
-    for (int k = 0; k < N; ++k) wsum += w[lo + k];
-    for (int m = -1; m <= 1; ++m) {
-        const double sh = sg * d * (double)m;
-        for (int k = 0; k < N; ++k) {
-            const double dx = px - (x[lo + k] + sh), dy = py - y[lo + k];
-            const double d2 = dx * dx + dy * dy;
-            if (d2 < best) { best = d2; ks = m * N + k; }
+    __shared__ WallCells W;
+    wall_cells_build(W, off, n_curves, n_src, x, y, w);
+    const bool cells = W.ok != 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_trg; i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = tc[i];
+        const int lo = (c >= 0 && c < n_curves) ? off[c] : 0;
+        const int N = (c >= 0 && c < n_curves) ? off[c + 1] - lo : 0;
+        float *xi = X + i * kNearFeat;
+        double *fr = frame + i * 6;
+        if (c < 0 || c >= n_curves || N < 8 || lo < 0 || (int64_t)lo + N > n_src) {
+            for (int k = 0; k < kNearFeat; ++k) xi[k] = __builtin_nanf("");
+            for (int k = 0; k < 6; ++k) fr[k] = __builtin_nan("");
+            continue;
         }
+        const double sg = x[lo + 1] > x[lo] ? 1.0 : -1.0;
+        const double px = tx[i], py = ty[i];
+        double best = 0.0, h = 0.0;
+        if (cells) {
+            h = W.h[c];
+        } else {
+            for (int k = 0; k < N; ++k) h += w[lo + k];
+            h /= (double)N;
+        }
+        const int ks = wall_nearest(W, cells, c, lo, N, sg, d, px, py, x, y, best);
+        const auto md = [N](int K) { return ((K % N) + N) % N; };
+        const auto fl = [N](int K) { return K >= 0 ? K / N : -((-K + N - 1) / N); };
+        const int ms = md(ks);
+        const double xs = x[lo + ms] + sg * d * (double)fl(ks), ys = y[lo + ms];
+        const double ts0 = -ny[lo + ms], ts1 = nx[lo + ms];
+        const int k0 = ((px - xs) * ts0 + (py - ys) * ts1 >= 0.0) ? ks : ks - 1;
+        const int m0 = md(k0);
+        const double t0 = -ny[lo + m0], t1 = nx[lo + m0];
+        const double n0 = nx[lo + m0], n1 = ny[lo + m0];
+        const double ox = px - (x[lo + m0] + sg * d * (double)fl(k0)), oy = py - y[lo + m0];
+        double ft[8], fn[8], F = 0.0;
+        for (int j = 0; j < 8; ++j) {
+            const int k = lo + md(k0 + j - 3);
+            ft[j] = fx[k] * t0 + fy[k] * t1;
+            fn[j] = fx[k] * n0 + fy[k] * n1;
+            F = fmax(F, sqrt(ft[j] * ft[j] + fn[j] * fn[j]));
+        }
+        if (F == 0.0) F = 1.0;
+        xi[0] = (float)((ox * t0 + oy * t1) / h);
+        xi[1] = (float)((ox * n0 + oy * n1) / h);
+        xi[2] = (float)log(sqrt(best) / h);
+        xi[3] = (float)(kap[lo + m0] * h);
+        for (int j = 0; j < 8; ++j) {
+            xi[4 + j] = (float)(ft[j] / F);
+            xi[12 + j] = (float)(fn[j] / F);
+        }
+        fr[0] = t0;
+        fr[1] = t1;
+        fr[2] = n0;
+        fr[3] = n1;
+        fr[4] = 1.0;
+        fr[5] = F;
     }
-    const double h = wsum / (double)N;
-    const auto md = [N](int K) { return ((K % N) + N) % N; };
-    const auto fl = [N](int K) { return K >= 0 ? K / N : -((-K + N - 1) / N); };
-    const int ms = md(ks);
-    const double xs = x[lo + ms] + sg * d * (double)fl(ks), ys = y[lo + ms];
-    const double ts0 = -ny[lo + ms], ts1 = nx[lo + ms];
-    const int k0 = ((px - xs) * ts0 + (py - ys) * ts1 >= 0.0) ? ks : ks - 1;
-    const int m0 = md(k0);
-    const double t0 = -ny[lo + m0], t1 = nx[lo + m0];
-    const double n0 = nx[lo + m0], n1 = ny[lo + m0];
-    const double ox = px - (x[lo + m0] + sg * d * (double)fl(k0)), oy = py - y[lo + m0];
-    double ft[8], fn[8], F = 0.0;
-    for (int j = 0; j < 8; ++j) {
-        const int k = lo + md(k0 + j - 3);
-        ft[j] = fx[k] * t0 + fy[k] * t1;
-        fn[j] = fx[k] * n0 + fy[k] * n1;
-        F = fmax(F, sqrt(ft[j] * ft[j] + fn[j] * fn[j]));
-    }
-    if (F == 0.0) F = 1.0;
-    xi[0] = (float)((ox * t0 + oy * t1) / h);
-    xi[1] = (float)((ox * n0 + oy * n1) / h);
-    xi[2] = (float)log(sqrt(best) / h);
-    xi[3] = (float)(kap[lo + m0] * h);
-    for (int j = 0; j < 8; ++j) {
-        xi[4 + j] = (float)(ft[j] / F);
-        xi[12 + j] = (float)(fn[j] / F);
-    }
-    fr[0] = t0;
-    fr[1] = t1;
-    fr[2] = n0;
-    fr[3] = n1;
-    fr[4] = 1.0;
-    fr[5] = F;
 }
 
 // scaled labels in the local frame: (Delta . t0, Delta . n0) * 4 pi mu / (h F)
@@ -686,7 +832,10 @@ hipError_t near_launch_features(const s2d_curves *c, const s2d_targets *t, const
 hipError_t near_launch_wall_features(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, double d,
                                      float *X, double *frame, hipStream_t st) {
     if (t->n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(near_wall_features, dim3((unsigned)((t->n + 255) / 256)), dim3(256), 0, st, t->n, t->x, t->y,
+    // grid-stride: each block builds the cell table once for up to a few
+    // thousand targets
+    const int64_t blocks = std::min<int64_t>((t->n + 255) / 256, 1024);
+    hipLaunchKernelGGL(near_wall_features, dim3((unsigned)blocks), dim3(256), 0, st, t->n, t->x, t->y,
                        tc, c->curve_off, c->n_curves, c->n_nodes, c->x, c->y, c->nx, c->ny, c->kappa, c->w, c->fx,
                        c->fy, d, X, frame);
     return hipGetLastError();

@@ -254,6 +254,46 @@ def test_wall_features_match_the_oracle():
     assert err_x.max() < 4e-7 and np.abs(fr.cpu().numpy() - ofr).max() < 1e-13
 
 
+def _features_vs_oracle(walls, d, tx, ty, tc):
+    import torch
+    from oracle import near as onear
+    from paper_1510_05616_amd import Curves, Targets
+    from paper_1510_05616_amd import near as pn
+    n = tx.shape[0]
+    X = torch.empty((n, 20), dtype=torch.float32, device="cuda")
+    fr = torch.empty((n, 6), dtype=torch.float64, device="cuda")
+    pn.near_wall_features_eval(Curves(walls), Targets(tx, ty), torch.as_tensor(tc, device="cuda"), d, X, fr)
+    torch.cuda.synchronize()
+    ox, ofr = onear.wall_features(walls, d, tx, ty, tc)
+    err_x = np.abs(X.cpu().numpy() - ox.astype(np.float32)) / np.maximum(np.abs(ox), 1.0)
+    return err_x.max(), np.abs(fr.cpu().numpy() - ofr).max()
+
+
+def test_wall_features_interior_targets_and_large_walls():
+    """The nearest-node search prunes by cells of wall nodes.  Targets deep in
+    the channel (many cells pass the bound, so a lane scans every passing cell
+    in order), and walls with more cells than the search's table holds (plain
+    scan), match the oracle as the near-wall targets do."""
+    rng = np.random.default_rng(37)
+    walls, d, tx, ty, tc = _wall_learning_set(200, 38)
+    m = 60
+    tx = np.r_[tx, rng.uniform(0.0, d, m)]
+    ty = np.r_[ty, rng.uniform(-0.6, 0.6, m)]
+    tc = np.r_[tc, rng.integers(0, 2, m)].astype(np.int32)
+    ex, ef = _features_vs_oracle(walls, d, tx, ty, tc)
+    print(f"interior targets: features {ex:.2e}, frame {ef:.2e}", flush=True)
+    assert ex < 4e-7 and ef < 1e-13
+    big, _, dbig = synth.make_channel(66000, 4)        # 2 x 516 cells of 128: over the table
+    big = synth.wall_densities(big, 39)
+    bx, by, bc = synth.near_wall_dataset(big, 40, 40)
+    bx = np.r_[bx, rng.uniform(0.0, dbig, 8)]
+    by = np.r_[by, rng.uniform(-0.5, 0.5, 8)]
+    bc = np.r_[bc, rng.integers(0, 2, 8)].astype(np.int32)
+    ex, ef = _features_vs_oracle(big, dbig, bx, by, bc)
+    print(f"large walls: features {ex:.2e}, frame {ef:.2e}", flush=True)
+    assert ex < 4e-7 and ef < 1e-13
+
+
 def test_wall_auto_extremes_and_network_gain():
     import torch
     from paper_1510_05616_amd import near as pn
