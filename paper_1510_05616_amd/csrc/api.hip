@@ -194,6 +194,9 @@ int eval(int op, int mode, const s2d_curves *src, const s2d_targets *trg, double
     if (rc != S2D_OK) return rc;
     if (trg->n == 0) return S2D_OK;
     Plan p = make_plan(op, mode, src, trg, g_dev[dev].cus);
+    if (p.n_blocks > (int64_t)INT32_MAX)
+        return fail(S2D_EINVAL, "too many target tiles x source splits for one launch (" +
+                                    std::to_string(p.n_blocks) + " workgroups)");
     const bool img0 = img_lo <= 0 && img_hi >= 0;
     p.self = op == S2D_OP_SLP && trg->on_curve != nullptr && img0;
     if (p.total > 0) {
