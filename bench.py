@@ -690,7 +690,7 @@ def near_section():
     frac_fb = float((fb == 1).double().mean())
     frac_zero = float((fb == 2).double().mean())
     e_plain = float((torch.hypot(d_up, e_up) / scale).max())
-    # 32x upsampled quadrature as context for the 8x judge (64-node curves,
+    # 32x upsampled quadrature as context for the 8x reference (64-node curves,
     # the largest that 32x upsampling supports)
     c64 = synth.make_near_dataset(100000, 8, sizes=(64,))
     d64 = near.NearData(*c64[:4], mu=1.0, upsample=8, labels=False)
@@ -750,8 +750,8 @@ def main():
         copy_probe()
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the target-sharded design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path; a single-GPU run "
+              "measures one GPU's share of a target-sharded evaluation", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -1,7 +1,7 @@
 """Binding of the near-field correction entry points of libstokes2d, and the
-training driver of the near-field MLP.
+training loop of the near-field MLP.
 
-The driver only orchestrates library calls: labels come from the library's
+This module only orchestrates library calls: labels come from the library's
 FFT-upsampled FP64 quadrature, features from its feature kernel, every
 training step (forward, backward, gradient sums, Adam) from its training
 kernels, and the BF16 inference blob from its packing kernel.  torch supplies
