@@ -364,7 +364,8 @@ Layout layout(int32_t n_inst, const s2d_instance *inst, int mode, const TuneChoi
 
 const TuneChoice kCandidates64[] = {{1, 2, 16, 0}, {1, 4, 16, 0}, {1, 8, 16, 0}, {2, 4, 16, 0}, {1, 4, 24, 0}};
 const TuneChoice kCandidates32[] = {{1, 2, 24, 0}, {1, 4, 24, 0}, {1, 8, 24, 0}, {1, 4, 32, 0},
-                                    {1, 4, 16, 0}, {2, 4, 16, 0}, {2, 4, 24, 0}, {2, 8, 24, 0}};
+                                    {2, 4, 16, 0}, {2, 4, 24, 0}, {2, 8, 24, 0}, {2, 4, 32, 0},
+                                    {2, 8, 32, 0}};
 
 void candidates(int mode, std::vector<TuneChoice> &out) {
     out.clear();
