@@ -533,75 +533,137 @@ __device__ __forceinline__ float dot2_bf16(uint32_t a, uint32_t b, float c) {
                                            false);
 }
 
-// One dense layer of the BF16 network: out[o] = b[o] + sum_k W[o][k] in[k],
-// with in[] packed as bf16 pairs and W as [out][in/2] bf16 pairs.
-template <int IN2, int OUT, bool ACT>
-__device__ __forceinline__ void bf16_layer(const uint32_t *__restrict__ W, const float *__restrict__ b,
-                                           const uint32_t (&in)[IN2], uint32_t (&out)[OUT / 2]) {
+// MLP inference, with the fallback decision taken first (from the target's
+// bin of |normal offset| / h and the calibrated bounds, scaled into velocity
+// units by h F / (4 pi mu)): no correction, the network, or the upsampled
+// quadrature (the target joins the fallback list).  nb: the packed BF16
+// network.  The network runs on the matrix cores: a wave takes one group of
+// 32 targets and evaluates each layer as out^T = W in^T with
+// v_mfma_f32_32x32x8_bf16: A = 32 output features x 8 inputs of W (read from
+// the blob's [out][in/2] pairs), B = 8 inputs x the 32 targets, C = 32
+// features x 32 targets in FP32, started at the bias.  Lane l holds target
+// l % 32; in C it holds features 8 (r / 4) + 4 (l / 32) + r % 4 of each
+// 32-feature tile (r = 0..15), which are exactly the inputs 8 s + 4 (l / 32) +
+// 0..3 of K-step s of the next layer's B: the activations stay in their
+// lanes between layers.  GELU in FP32 and rounding to BF16 between layers; the
+// last 64 -> 2 layer is a dot2 over the lane's 32 features plus the partner
+// lane's half.
+typedef short bf16x4v_t __attribute__((ext_vector_type(4)));
+typedef float f32x16v_t __attribute__((ext_vector_type(16)));
+
+// 4 bf16 of row `row` of a [out][in2] pair array, inputs k0..k0+3 (k0 % 4 == 0)
+__device__ __forceinline__ bf16x4v_t mfma_wrow(const uint32_t *W, int in2, int row, int k0) {
+    const uint32_t *q = W + row * in2 + k0 / 2;
+    const uint32_t lo = q[0], hi = q[1];
+    return __builtin_bit_cast(bf16x4v_t, ((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ bf16x4v_t mfma_pack4(float a, float b, float c, float d) {
+    return __builtin_bit_cast(bf16x4v_t, ((uint64_t)pack_bf16(c, d) << 32) | pack_bf16(a, b));
+}
+
+template <int KSTEPS, int IN2>
+__device__ __forceinline__ void mfma_layer(const uint32_t *W, const float *b, const bf16x4v_t (&in)[KSTEPS],
+                                           int c, int h, f32x16v_t (&acc)[2]) {
 #pragma unroll
-    for (int o = 0; o < OUT; o += 2) {
-        float a0 = b[o], a1 = b[o + 1];
+    for (int T = 0; T < 2; ++T) {
 #pragma unroll
-        for (int k = 0; k < IN2; ++k) {
-            a0 = dot2_bf16(W[o * IN2 + k], in[k], a0);
-            a1 = dot2_bf16(W[(o + 1) * IN2 + k], in[k], a1);
+        for (int r = 0; r < 16; ++r) acc[T][r] = b[32 * T + 8 * (r / 4) + 4 * h + (r % 4)];
+#pragma unroll
+        for (int s = 0; s < KSTEPS; ++s) {
+            const int k0 = 8 * s + 4 * h;
+            const bf16x4v_t a = (2 * IN2 > k0) ? mfma_wrow(W, IN2, 32 * T + c, k0) : bf16x4v_t{0, 0, 0, 0};
+            acc[T] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, in[s], acc[T], 0, 0, 0);
         }
-        if (ACT) {
-            a0 = gelu_f(a0);
-            a1 = gelu_f(a1);
-        }
-        out[o / 2] = pack_bf16(a0, a1);
     }
 }
 
-// MLP inference with the fallback decision taken first (from the target's
-// bin of |normal offset| / h and the calibrated bounds, scaled into velocity
-// units by h F / (4 pi mu)): no correction, the network, or the upsampled
-// quadrature (the target joins the fallback list).  blob: the packed BF16
-// network.
-__global__ __launch_bounds__(256) void near_mlp_infer(int64_t n_trg, const float *__restrict__ X,
-                                                      const double *__restrict__ frame, const NearBlob *__restrict__ nb,
-                                                      double mu, double threshold, int use_bound,
-                                                      double *__restrict__ du, double *__restrict__ dv,
-                                                      int32_t *__restrict__ flag) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_trg) return;
-    const float *xi = X + i * kNearFeat;
-    const double *fr = frame + 6 * i;
-    const double sc = fr[4] * fr[5] / (4.0 * M_PI * mu);
-    if (use_bound) {
-        const float noff = fabsf(xi[1]);
-        int bin = (int)floorf((log10f(fmaxf(noff, 1e-30f)) - nb->bin_lo) / nb->bin_w);
-        bin = bin < 0 ? 0 : (bin >= nb->n_bins ? nb->n_bins - 1 : bin);
-        const bool bad = !(noff == noff);
-        if (!bad && (double)nb->bound_zero[bin] * sc <= threshold) {
-            if (flag) flag[i] = 2;
-            du[i] = 0.0;
-            dv[i] = 0.0;
-            return;
+// GELU of a layer's output, rounded to the next layer's B operands
+__device__ __forceinline__ void mfma_act(const f32x16v_t (&acc)[2], bf16x4v_t (&out)[8]) {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        const int T = s / 4, r = 4 * (s % 4);
+        out[s] = mfma_pack4(gelu_f(acc[T][r]), gelu_f(acc[T][r + 1]), gelu_f(acc[T][r + 2]), gelu_f(acc[T][r + 3]));
+    }
+}
+
+__global__ __launch_bounds__(256) void near_mlp_infer_mfma(int64_t n_trg, const float *__restrict__ X,
+                                                           const double *__restrict__ frame,
+                                                           const NearBlob *__restrict__ nb, double mu,
+                                                           double threshold, int use_bound,
+                                                           double *__restrict__ du, double *__restrict__ dv,
+                                                           int32_t *__restrict__ flag) {
+    static_assert(kNearFeat <= 24, "three K-steps of the first layer");
+    const int lane = threadIdx.x & (kWave - 1), h = lane >> 5, c = lane & 31;
+    const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;   // this wave's group
+    if (g * 32 < n_trg) {                                            // wave-uniform
+        const int64_t i = g * 32 + c;
+        const bool valid = i < n_trg;
+        const float *xi = X + (valid ? i : 0) * kNearFeat;
+        const double *fr = frame + 6 * (valid ? i : 0);
+        int dec = 0;                                                 // 0 network, 1 quadrature, 2 none
+        double sc = 0.0;
+        if (valid) {
+            sc = fr[4] * fr[5] / (4.0 * M_PI * mu);
+            if (use_bound) {
+                const float noff = fabsf(xi[1]);
+                int bin = (int)floorf((log10f(fmaxf(noff, 1e-30f)) - nb->bin_lo) / nb->bin_w);
+                bin = bin < 0 ? 0 : (bin >= nb->n_bins ? nb->n_bins - 1 : bin);
+                const bool bad = !(noff == noff);
+                if (!bad && (double)nb->bound_zero[bin] * sc <= threshold) dec = 2;
+                else if (bad || (double)nb->bound[bin] * sc > threshold) dec = 1;
+            }
         }
-        if (bad || (double)nb->bound[bin] * sc > threshold) {
-            flag[i] = 1;               // the quadrature kernel writes du, dv
-            return;
+        // the network runs only if some target of the group needs it
+        float y0 = 0.f, y1 = 0.f;
+        if (__any(valid && dec == 0)) {                              // wave-uniform
+            // first layer: the standardised features of the lane's target
+            bf16x4v_t in1[3];
+#pragma unroll
+            for (int s = 0; s < 3; ++s) {
+                float v[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int k = 8 * s + 4 * h + e;
+                    v[e] = (valid && k < kNearFeat) ? (xi[k] - nb->mu_in[k]) * nb->isd_in[k] : 0.f;
+                }
+                in1[s] = mfma_pack4(v[0], v[1], v[2], v[3]);
+            }
+            f32x16v_t acc[2];
+            bf16x4v_t hb[8];
+            mfma_layer<3, kNearFeat / 2>(nb->W1, nb->b1, in1, c, h, acc);
+            mfma_act(acc, hb);
+            mfma_layer<8, 32>(nb->W2, nb->b2, hb, c, h, acc);
+            mfma_act(acc, hb);
+            mfma_layer<8, 32>(nb->W3, nb->b3, hb, c, h, acc);
+#pragma unroll
+            for (int T = 0; T < 2; ++T) {
+#pragma unroll
+                for (int r = 0; r < 16; r += 2) {
+                    const int f = 32 * T + 8 * (r / 4) + 4 * h + (r % 4);
+                    const uint32_t p = pack_bf16(gelu_f(acc[T][r]), gelu_f(acc[T][r + 1]));
+                    y0 = dot2_bf16(nb->W4[f / 2], p, y0);
+                    y1 = dot2_bf16(nb->W4[32 + f / 2], p, y1);
+                }
+            }
+            y0 += __shfl_xor(y0, 32, kWave);
+            y1 += __shfl_xor(y1, 32, kWave);
+            y0 += nb->b4[0];
+            y1 += nb->b4[1];
+        }
+        if (valid && h == 0) {
+            if (dec == 2) {
+                if (flag) flag[i] = 2;
+                du[i] = 0.0;
+                dv[i] = 0.0;
+            } else if (dec == 1) {
+                flag[i] = 1;               // the quadrature kernel writes du, dv
+            } else {
+                if (flag) flag[i] = 0;
+                du[i] = sc * ((double)y0 * fr[0] + (double)y1 * fr[2]);
+                dv[i] = sc * ((double)y0 * fr[1] + (double)y1 * fr[3]);
+            }
         }
     }
-    uint32_t h0[kNearFeat / 2];
-#pragma unroll
-    for (int k = 0; k < kNearFeat; k += 2)
-        h0[k / 2] = pack_bf16((xi[k] - nb->mu_in[k]) * nb->isd_in[k], (xi[k + 1] - nb->mu_in[k + 1]) * nb->isd_in[k + 1]);
-    uint32_t h1[32], h2[32], h3[32];
-    bf16_layer<kNearFeat / 2, 64, true>(nb->W1, nb->b1, h0, h1);
-    bf16_layer<32, 64, true>(nb->W2, nb->b2, h1, h2);
-    bf16_layer<32, 64, true>(nb->W3, nb->b3, h2, h3);
-    float y0 = nb->b4[0], y1 = nb->b4[1];
-#pragma unroll
-    for (int k = 0; k < 32; ++k) {
-        y0 = dot2_bf16(nb->W4[k], h3[k], y0);
-        y1 = dot2_bf16(nb->W4[32 + k], h3[k], y1);
-    }
-    if (flag) flag[i] = 0;
-    du[i] = sc * ((double)y0 * fr[0] + (double)y1 * fr[2]);
-    dv[i] = sc * ((double)y0 * fr[1] + (double)y1 * fr[3]);
 }
 
 // Pack FP32 master parameters into the BF16 inference blob.
@@ -851,7 +913,10 @@ hipError_t near_launch_scale_labels(int64_t n, const double *du, const double *d
 hipError_t near_launch_infer(int64_t n, const float *X, const double *frame, const NearBlob *nb, double mu,
                              double threshold, int use_bound, double *du, double *dv, int32_t *flag, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(near_mlp_infer, dim3(grid_for(n)), dim3(256), 0, st, n, X, frame, nb, mu, threshold,
+    // 32 targets per wave, 4 waves per block
+    const int64_t groups = (n + 31) / 32;
+    const int64_t blocks = (groups + 3) / 4;
+    hipLaunchKernelGGL(near_mlp_infer_mfma, dim3((unsigned)blocks), dim3(256), 0, st, n, X, frame, nb, mu, threshold,
                        use_bound, du, dv, flag);
     return hipGetLastError();
 }
