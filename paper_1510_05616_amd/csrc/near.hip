@@ -712,80 +712,109 @@ __global__ __launch_bounds__(256) void near_pack(const float *__restrict__ prm, 
 // ---------------------------------------------------------------------------
 // a11: training (FP32)
 // ---------------------------------------------------------------------------
+// The training kernels give each sample a wave and each neuron a lane (the
+// batch of a step is a few hundred samples: one thread per sample would leave
+// most of the chip idle).  A neuron's sum runs over its inputs in the same
+// order as a plain per-sample loop.  The wave passes a layer's activations to
+// the next layer through its own row of LDS; the fences keep the compiler from
+// moving the LDS accesses across the hand-over (LDS instructions of one wave
+// complete in issue order).
+__device__ __forceinline__ void mlp_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// one 64-neuron layer of sample's forward pass: lane o; in: the wave's LDS row
+// (n_in values), written over by the layer's activations on return
+__device__ __forceinline__ void mlp_fwd_layer(int n_in, const float *__restrict__ W, const float *__restrict__ b,
+                                              float *row, int o, float *z, float *h) {
+    float a = b[o];
+    for (int k = 0; k < n_in; ++k) a = fmaf(row[k], W[k * 64 + o], a);
+    const float hv = gelu_f(a);
+    z[o] = a;
+    h[o] = hv;
+    mlp_wave_sync();                     // every lane has read the inputs
+    row[o] = hv;
+    mlp_wave_sync();
+}
+
 // per sample: forward, loss term, output delta dY = (Y - T) / B, and the
 // pre-activations z1..z3 and activations h0..h3 kept for the backward pass
 __global__ __launch_bounds__(256) void mlp_fwd(int32_t B, const int32_t *__restrict__ idx,
                                                const float *__restrict__ X, const float *__restrict__ T,
                                                const float *__restrict__ prm, float *__restrict__ act,
                                                float *__restrict__ dY, float *__restrict__ lossv) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= B) return;
+    __shared__ float rows[kBlock / kWave][64];
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int s = blockIdx.x * (kBlock / kWave) + wv;
+    if (s >= B) return;                  // wave-uniform; no block barrier below
+    float *row = rows[wv];
     const MlpOffsets O;
     const int64_t i = idx ? idx[s] : s;
     float *A = act + (int64_t)s * kActStride;   // h0[20] z1[64] h1[64] z2[64] h2[64] z3[64] h3[64]
     float *h0 = A, *z1 = A + 20, *h1 = A + 84, *z2 = A + 148, *h2 = A + 212, *z3 = A + 276, *h3 = A + 340;
-    for (int k = 0; k < kNearFeat; ++k) h0[k] = (X[i * kNearFeat + k] - prm[O.mu + k]) / prm[O.sd + k];
-    for (int o = 0; o < 64; ++o) {
-        float a = prm[O.b1 + o];
-        for (int k = 0; k < kNearFeat; ++k) a = fmaf(h0[k], prm[O.W1 + k * 64 + o], a);
-        z1[o] = a;
-        h1[o] = gelu_f(a);
+    if (lane < kNearFeat) {
+        const float v = (X[i * kNearFeat + lane] - prm[O.mu + lane]) / prm[O.sd + lane];
+        h0[lane] = v;
+        row[lane] = v;
     }
-    for (int o = 0; o < 64; ++o) {
-        float a = prm[O.b2 + o];
-        for (int k = 0; k < 64; ++k) a = fmaf(h1[k], prm[O.W2 + k * 64 + o], a);
-        z2[o] = a;
-        h2[o] = gelu_f(a);
+    mlp_wave_sync();
+    mlp_fwd_layer(kNearFeat, prm + O.W1, prm + O.b1, row, lane, z1, h1);
+    mlp_fwd_layer(64, prm + O.W2, prm + O.b2, row, lane, z2, h2);
+    mlp_fwd_layer(64, prm + O.W3, prm + O.b3, row, lane, z3, h3);
+    float r = 0.f;
+    if (lane < 2) {
+        float a = prm[O.b4 + lane];
+        for (int k = 0; k < 64; ++k) a = fmaf(row[k], prm[O.W4 + k * 2 + lane], a);
+        r = a - T[i * 2 + lane];
+        dY[s * 2 + lane] = r / (float)B;
     }
-    for (int o = 0; o < 64; ++o) {
-        float a = prm[O.b3 + o];
-        for (int k = 0; k < 64; ++k) a = fmaf(h2[k], prm[O.W3 + k * 64 + o], a);
-        z3[o] = a;
-        h3[o] = gelu_f(a);
-    }
-    float l = 0.f;
-    for (int o = 0; o < 2; ++o) {
-        float a = prm[O.b4 + o];
-        for (int k = 0; k < 64; ++k) a = fmaf(h3[k], prm[O.W4 + k * 2 + o], a);
-        const float r = a - T[i * 2 + o];
-        dY[s * 2 + o] = r / (float)B;
-        l += r * r;
-    }
-    lossv[s] = 0.5f * l / (float)B;
+    const float r1 = __shfl(r, 1, kWave);
+    if (lane == 0) lossv[s] = 0.5f * (r * r + r1 * r1) / (float)B;
 }
 
-// per sample: deltas d3, d2, d1 (stored over z3, z2, z1)
+// per sample: the deltas of the three hidden layers, written over z3, z2, z1
 __global__ __launch_bounds__(256) void mlp_bwd(int32_t B, const float *__restrict__ prm, float *__restrict__ act,
                                                const float *__restrict__ dY) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= B) return;
+    __shared__ float rows[kBlock / kWave][64];
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int s = blockIdx.x * (kBlock / kWave) + wv;
+    if (s >= B) return;                  // wave-uniform
+    float *row = rows[wv];
     const MlpOffsets O;
     float *A = act + (int64_t)s * kActStride;
     float *z1 = A + 20, *z2 = A + 148, *z3 = A + 276;
     const float g0 = dY[2 * s], g1 = dY[2 * s + 1];
-    for (int k = 0; k < 64; ++k)
-        z3[k] = (prm[O.W4 + k * 2] * g0 + prm[O.W4 + k * 2 + 1] * g1) * gelu_grad_f(z3[k]);
-    for (int k = 0; k < 64; ++k) {
-        float a = 0.f;
-        for (int o = 0; o < 64; ++o) a = fmaf(prm[O.W3 + k * 64 + o], z3[o], a);
-        z2[k] = a * gelu_grad_f(z2[k]);
-    }
-    for (int k = 0; k < 64; ++k) {
-        float a = 0.f;
-        for (int o = 0; o < 64; ++o) a = fmaf(prm[O.W2 + k * 64 + o], z2[o], a);
-        z1[k] = a * gelu_grad_f(z1[k]);
-    }
+    const float d3 = (prm[O.W4 + lane * 2] * g0 + prm[O.W4 + lane * 2 + 1] * g1) * gelu_grad_f(z3[lane]);
+    z3[lane] = d3;
+    row[lane] = d3;
+    mlp_wave_sync();
+    float a = 0.f;
+    for (int o = 0; o < 64; ++o) a = fmaf(prm[O.W3 + lane * 64 + o], row[o], a);
+    const float d2 = a * gelu_grad_f(z2[lane]);
+    z2[lane] = d2;
+    mlp_wave_sync();
+    row[lane] = d2;
+    mlp_wave_sync();
+    a = 0.f;
+    for (int o = 0; o < 64; ++o) a = fmaf(prm[O.W2 + lane * 64 + o], row[o], a);
+    z1[lane] = a * gelu_grad_f(z1[lane]);
 }
 
-// one thread per parameter: gradient summed over the batch in sample order;
-// thread 0 also sums the per-sample losses in sample order.
+// gradient of every parameter: the sum over the batch of (input activation x
+// delta), in kGradChunks contiguous runs of samples, each summed in sample
+// order, then the runs added in order (fixed order: deterministic); a block
+// holds 256 / kGradChunks parameters.  The loss is the sum of lossv.
+constexpr int kGradChunks = 8;
 __global__ __launch_bounds__(256) void mlp_grad(int32_t B, const float *__restrict__ act,
                                                 const float *__restrict__ dY, const float *__restrict__ lossv,
                                                 float *__restrict__ grad, float *__restrict__ loss) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    constexpr int kPer = kBlock / kGradChunks;
+    __shared__ float part[kGradChunks][kPer];
+    const int pp = threadIdx.x % kPer, ch = threadIdx.x / kPer;
+    const int p = blockIdx.x * kPer + pp;
     const MlpOffsets O;
-    if (p >= O.total) return;
-    float g = 0.f;
     int hin = -1, dl = -1, dk = 0, width = 64;   // activation column, delta column
     if (p >= O.W1 && p < O.b1) { const int r = p - O.W1; hin = r / 64; dl = 20 + r % 64; }
     else if (p >= O.b1 && p < O.W2) { dl = 20 + (p - O.b1); }
@@ -795,21 +824,27 @@ __global__ __launch_bounds__(256) void mlp_grad(int32_t B, const float *__restri
     else if (p >= O.b3 && p < O.W4) { dl = 276 + (p - O.b3); }
     else if (p >= O.W4 && p < O.b4) { const int r = p - O.W4; hin = 340 + r / 2; dk = r % 2; width = 2; }
     else if (p >= O.b4 && p < O.total) { dk = p - O.b4; width = 2; }
-    if (p == 0 && loss) {
+    float g = 0.f;
+    if (p >= O.W1 && p < O.total) {              // mu_in / sd_in are not trained
+        const int s0 = (int)((int64_t)B * ch / kGradChunks), s1 = (int)((int64_t)B * (ch + 1) / kGradChunks);
+        for (int s = s0; s < s1; ++s) {
+            const float *A = act + (int64_t)s * kActStride;
+            const float d = width == 2 ? dY[2 * s + dk] : A[dl];
+            g = fmaf(hin >= 0 ? A[hin] : 1.f, d, g);
+        }
+    }
+    part[ch][pp] = g;
+    __syncthreads();
+    if (ch == 0 && p < O.total) {
+        float t = 0.f;
+        for (int c = 0; c < kGradChunks; ++c) t += part[c][pp];
+        grad[p] = t;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && loss) {
         float l = 0.f;
         for (int s = 0; s < B; ++s) l += lossv[s];
         *loss = l;
     }
-    if (p < O.W1) {                               // mu_in / sd_in are not trained
-        grad[p] = 0.f;
-        return;
-    }
-    for (int s = 0; s < B; ++s) {
-        const float *A = act + (int64_t)s * kActStride;
-        const float d = width == 2 ? dY[2 * s + dk] : A[dl];
-        g = fmaf(hin >= 0 ? A[hin] : 1.f, d, g);
-    }
-    grad[p] = g;
 }
 
 __global__ __launch_bounds__(256) void mlp_adam(float *__restrict__ prm, const float *__restrict__ grad,
@@ -932,9 +967,11 @@ hipError_t near_launch_train_step(int32_t B, const int32_t *idx, const float *X,
                                   float *m, float *v, int32_t step, float lr, float *grad, float *act, float *dY,
                                   float *lossv, float *loss, int update, hipStream_t st) {
     const MlpOffsets O;
-    hipLaunchKernelGGL(mlp_fwd, dim3(grid_for(B)), dim3(256), 0, st, B, idx, X, T, prm, act, dY, lossv);
-    hipLaunchKernelGGL(mlp_bwd, dim3(grid_for(B)), dim3(256), 0, st, B, prm, act, dY);
-    hipLaunchKernelGGL(mlp_grad, dim3(grid_for(O.total)), dim3(256), 0, st, B, act, dY, lossv, grad, loss);
+    const unsigned wave_blocks = (unsigned)((B + kBlock / kWave - 1) / (kBlock / kWave));   // a wave per sample
+    hipLaunchKernelGGL(mlp_fwd, dim3(wave_blocks), dim3(kBlock), 0, st, B, idx, X, T, prm, act, dY, lossv);
+    hipLaunchKernelGGL(mlp_bwd, dim3(wave_blocks), dim3(kBlock), 0, st, B, prm, act, dY);
+    hipLaunchKernelGGL(mlp_grad, dim3((unsigned)((O.total + kBlock / kGradChunks - 1) / (kBlock / kGradChunks))),
+                       dim3(kBlock), 0, st, B, act, dY, lossv, grad, loss);
     if (update)
         hipLaunchKernelGGL(mlp_adam, dim3(grid_for(O.total)), dim3(256), 0, st, prm, grad, m, v, step, lr, 0.9f,
                            0.999f, 1e-8f);
