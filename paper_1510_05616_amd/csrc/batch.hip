@@ -130,6 +130,8 @@ __global__ __launch_bounds__(256) void batch_kress_table(BatchTables t) {
 }
 
 __global__ __launch_bounds__(256) void batch_kress_self(BatchTables t) {
+    __shared__ __attribute__((aligned(16))) double ltab[kLogTabWords];
+    fill_log_table(ltab);                           // before any thread returns
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= t.trg_off[t.n_inst]) return;
     const int k = find_inst(t.trg_off, t.n_inst, g);
@@ -139,7 +141,7 @@ __global__ __launch_bounds__(256) void batch_kress_self(BatchTables t) {
     const s2d_curves &s = I.src[0];
     double sx, sy;
     kress_self_one(i, s.n_nodes, I.trg[0].on_curve, I.trg[0].on_node, s.curve_off, s.n_curves, s.x, s.y, s.nx,
-                   s.ny, s.w, s.fx, s.fy, I.kress, sx, sy);
+                   s.ny, s.w, s.fx, s.fy, I.kress, ltab, sx, sy);
     I.self[i] = sx;
     I.self[I.trg[0].n + i] = sy;
 }

@@ -62,15 +62,19 @@ __global__ __launch_bounds__(256) void near_upsample(const int32_t *__restrict__
         st[j] = s;
     }
     __syncthreads();
+    // angle indices advance by a fixed step modulo M (no division per term)
     const double *sig[4] = {x + lo, y + lo, fx + lo, fy + lo};
     for (int q = threadIdx.x; q < 4 * (H + 1); q += blockDim.x) {
         const int s = q / (H + 1), m = q % (H + 1);
         const double *v = sig[s];
+        const int step = (m * P) % M;                            // angle 2 pi m k / N
         double a = 0.0, b = 0.0;
+        int idx = 0;
         for (int k = 0; k < N; ++k) {
-            const int idx = (int)(((int64_t)m * k * P) % M);     // angle 2 pi m k / N
             a += v[k] * ct[idx];
             b += v[k] * st[idx];
+            idx += step;
+            idx -= idx >= M ? M : 0;
         }
         A[q] = a;
         B[q] = b;
@@ -80,20 +84,27 @@ __global__ __launch_bounds__(256) void near_upsample(const int32_t *__restrict__
     const int64_t base = (int64_t)lo * P;
     const int64_t plane = (int64_t)n_src * P;
     for (int j = threadIdx.x; j < M; j += blockDim.x) {
-        double val[4], der[2];
-        for (int s = 0; s < 4; ++s) {
-            const double *As = A + s * (H + 1), *Bs = B + s * (H + 1);
-            double v = As[0], dv = 0.0;
-            for (int m = 1; m < H; ++m) {
-                const int idx = (int)(((int64_t)m * j) % M);
-                v += 2.0 * (As[m] * ct[idx] + Bs[m] * st[idx]);
-                if (s < 2) dv += 2.0 * (double)m * (Bs[m] * ct[idx] - As[m] * st[idx]);
+        double v[4], dv[2] = {0.0, 0.0};
+        for (int s = 0; s < 4; ++s) v[s] = A[s * (H + 1)];
+        int idx = j;                                             // m j mod M
+        for (int m = 1; m < H; ++m) {
+            const double c = ct[idx], sn = st[idx];
+            for (int s = 0; s < 4; ++s) {
+                const double am = A[s * (H + 1) + m], bm = B[s * (H + 1) + m];
+                v[s] += 2.0 * (am * c + bm * sn);
+                if (s < 2) dv[s] += 2.0 * (double)m * (bm * c - am * sn);
             }
-            const int idx = (int)(((int64_t)H * j) % M);
-            v += As[H] * ct[idx];
-            if (s < 2) dv -= (double)H * As[H] * st[idx];
-            val[s] = v * inv;
-            if (s < 2) der[s] = dv * inv;
+            idx += j;
+            idx -= idx >= M ? M : 0;
+        }
+        double val[4], der[2];
+        const double cH = ct[idx], sH = st[idx];                 // idx = H j mod M
+        for (int s = 0; s < 4; ++s) {
+            const double aH = A[s * (H + 1) + H];
+            v[s] += aH * cH;
+            if (s < 2) dv[s] -= (double)H * aH * sH;
+            val[s] = v[s] * inv;
+            if (s < 2) der[s] = dv[s] * inv;
         }
         const double sp = sqrt(der[0] * der[0] + der[1] * der[1]);
         up[base + j] = val[0];

@@ -20,10 +20,12 @@ __global__ __launch_bounds__(256) void kress_self(int64_t n_trg, int64_t n_src, 
                                                   const double *__restrict__ w,
                                                   const double *__restrict__ fx, const double *__restrict__ fy,
                                                   const double *__restrict__ T, double *__restrict__ self) {
+    __shared__ __attribute__((aligned(16))) double ltab[kLogTabWords];
+    fill_log_table(ltab);                           // before any thread returns
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_trg) return;
     double sx, sy;
-    kress_self_one(i, n_src, on_curve, on_node, off, n_curves, x, y, nx, ny, w, fx, fy, T, sx, sy);
+    kress_self_one(i, n_src, on_curve, on_node, off, n_curves, x, y, nx, ny, w, fx, fy, T, ltab, sx, sy);
     self[i] = sx;
     self[n_trg + i] = sy;
 }
