@@ -42,10 +42,12 @@ __device__ __forceinline__ void kress_table_curve(const int32_t *__restrict__ of
     const int m = N / 2;
     for (int j = threadIdx.x; j < N; j += blockDim.x) {
         double acc = 0.0;
+        int idx = (int)(((int64_t)(m - 1) * j) % N);        // p j mod N, stepped down with p
         for (int p = m - 1; p >= 1; --p) {
-            const int64_t idx = ((int64_t)p * j) % N;
             const double cs = tab ? ctab[idx] : cospi(2.0 * (double)idx / (double)N);
             acc += cs / (double)p;
+            idx -= j;
+            idx += idx < 0 ? N : 0;
         }
         acc += ((j & 1) ? -1.0 : 1.0) / (double)N;
         if (j != 0) acc += log(2.0 * fabs(sinpi((double)j / (double)N)));
