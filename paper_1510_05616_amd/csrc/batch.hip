@@ -111,12 +111,12 @@ __global__ __launch_bounds__(256) void batch_prep(BatchTables t, int op) {
 }
 
 __global__ __launch_bounds__(256) void batch_sbsum(BatchTables t) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= t.sb_off[t.n_inst]) return;
+    const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;    // a wave per superblock
+    if (g >= t.sb_off[t.n_inst]) return;                                          // wave-uniform
     const int k = find_inst(t.sb_off, t.n_inst, g);
     const BatchInst &I = t.inst[k];
     const s2d_curves &s = I.src[0];
-    sbsum_one(g - t.sb_off[k], s.n_nodes, s.w, s.fx, s.fy, (double *)I.pa[0].sbsum);
+    sbsum_wave(g - t.sb_off[k], s.n_nodes, s.w, s.fx, s.fy, (double *)I.pa[0].sbsum, threadIdx.x & (kWave - 1));
 }
 
 __global__ __launch_bounds__(256) void batch_kress_table(BatchTables t) {
@@ -427,7 +427,7 @@ hipError_t record_graph(BatchPlan &P, const BatchTables &t, int n_pre_targets, i
                                st, t, op);
     }
     if (prec == S2D_FP32C && tot_sb > 0)
-        hipLaunchKernelGGL(batch_sbsum, dim3((unsigned)((tot_sb + 255) / 256)), dim3(256), 0, st, t);
+        hipLaunchKernelGGL(batch_sbsum, dim3((unsigned)((tot_sb + 3) / 4)), dim3(256), 0, st, t);
     if (any_self && tot_curves > 0) {
         hipLaunchKernelGGL(batch_kress_table, dim3((unsigned)tot_curves), dim3(256), 0, st, t);
         hipLaunchKernelGGL(batch_kress_self, dim3((unsigned)((tot_trg + 255) / 256)), dim3(256), 0, st, t);

@@ -25,9 +25,9 @@ __global__ __launch_bounds__(256) void prep_sbsum(int64_t n_src, int64_t n_sb,
                                                   const double *__restrict__ w,
                                                   const double *__restrict__ fx, const double *__restrict__ fy,
                                                   double *sbsum) {
-    const int64_t sb = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (sb >= n_sb) return;
-    sbsum_one(sb, n_src, w, fx, fy, sbsum);
+    const int64_t sb = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;   // a wave per superblock
+    if (sb >= n_sb) return;                                                           // wave-uniform
+    sbsum_wave(sb, n_src, w, fx, fy, sbsum, threadIdx.x & (kWave - 1));
 }
 
 template <int OP, int PREC>
@@ -42,7 +42,7 @@ static hipError_t prep_t(const Plan &p, const s2d_curves *s, void *ws, hipStream
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (OP == S2D_OP_SLP && PREC == S2D_FP32C) {
-        hipLaunchKernelGGL(prep_sbsum, dim3((unsigned)((p.n_sb + 255) / 256)), dim3(256), 0, st,
+        hipLaunchKernelGGL(prep_sbsum, dim3((unsigned)((p.n_sb + 3) / 4)), dim3(256), 0, st,
                            p.n_src, p.n_sb, s->w, s->fx, s->fy, (double *)((char *)ws + p.off_sbsum));
         e = hipGetLastError();
     }

@@ -71,18 +71,27 @@ __device__ __forceinline__ void prep_sub32(int64_t u, int64_t n_src, const doubl
     }
 }
 
-// Sequential FP64 sum of g = w f over superblock sb (fixed order).
-__device__ __forceinline__ void sbsum_one(int64_t sb, int64_t n_src, const double *__restrict__ w,
-                                          const double *__restrict__ fx, const double *__restrict__ fy,
-                                          double *sbsum) {
+// FP64 sum of g = w f over superblock sb, by one whole wave: lane l adds
+// sources l, l + 64, ... in order, then the lanes are added by a fixed
+// butterfly; lane 0 writes (fixed order: deterministic).
+__device__ __forceinline__ void sbsum_wave(int64_t sb, int64_t n_src, const double *__restrict__ w,
+                                           const double *__restrict__ fx, const double *__restrict__ fy,
+                                           double *sbsum, int lane) {
     double sx = 0.0, sy = 0.0;
     const int64_t j0 = sb * kSuperBlock, j1 = min(j0 + (int64_t)kSuperBlock, n_src);
-    for (int64_t j = j0; j < j1; ++j) {
+    for (int64_t j = j0 + lane; j < j1; j += kWave) {
         sx += w[j] * fx[j];
         sy += w[j] * fy[j];
     }
-    sbsum[2 * sb] = sx;
-    sbsum[2 * sb + 1] = sy;
+#pragma unroll
+    for (int m = kWave / 2; m >= 1; m >>= 1) {
+        sx += __shfl_xor(sx, m, kWave);
+        sy += __shfl_xor(sy, m, kWave);
+    }
+    if (lane == 0) {
+        sbsum[2 * sb] = sx;
+        sbsum[2 * sb + 1] = sy;
+    }
 }
 
 }  // namespace s2d
