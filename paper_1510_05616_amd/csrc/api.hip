@@ -697,7 +697,7 @@ NearLayout near_layout(int method, const s2d_curves *c, const s2d_targets *t, in
     NearLayout L{};
     size_t off = 0;
     L.up = off;
-    if (method != S2D_NEAR_MLP) off = align256(off + 5 * (size_t)P * (size_t)c->n_nodes * sizeof(double));
+    if (method != S2D_NEAR_MLP) off = align256(off + 4 * ((size_t)P + 1) * (size_t)c->n_nodes * sizeof(double));
     L.X = off;
     if (method != S2D_NEAR_UPSAMPLE) {
         off = align256(off + (size_t)t->n * s2d::kNearFeat * sizeof(float));

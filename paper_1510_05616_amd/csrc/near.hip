@@ -41,10 +41,14 @@ namespace s2d {
 // ---------------------------------------------------------------------------
 // a8: upsampling and FP64 quadrature
 // ---------------------------------------------------------------------------
+// Output: the fine curve as records {x, y, w fx, w fy} at up[4 (P lo + j)],
+// j < P N, with the fine trapezoid weight w = (2 pi / (P N)) |x'|, then the
+// given nodes as records {x, y, w fx, w fy} at up[4 (P n_src + lo + k)].
 __global__ __launch_bounds__(256) void near_upsample(const int32_t *__restrict__ off, int32_t n_curves, int64_t n_src,
                                                      const double *__restrict__ x, const double *__restrict__ y,
+                                                     const double *__restrict__ w,
                                                      const double *__restrict__ fx, const double *__restrict__ fy,
-                                                     int P, double *__restrict__ up /* [5][P n_src] */) {
+                                                     int P, double *__restrict__ up /* [4 (P + 1) n_src] */) {
     extern __shared__ double lds[];
     const int c = blockIdx.x;
     if (c >= n_curves) return;
@@ -82,7 +86,13 @@ __global__ __launch_bounds__(256) void near_upsample(const int32_t *__restrict__
     __syncthreads();
     const double inv = 1.0 / (double)N;
     const int64_t base = (int64_t)lo * P;
-    const int64_t plane = (int64_t)n_src * P;
+    double *coarse = up + 4 * ((int64_t)n_src * P + lo);
+    for (int k = threadIdx.x; k < N; k += blockDim.x) {
+        coarse[4 * k] = x[lo + k];
+        coarse[4 * k + 1] = y[lo + k];
+        coarse[4 * k + 2] = w[lo + k] * fx[lo + k];
+        coarse[4 * k + 3] = w[lo + k] * fy[lo + k];
+    }
     for (int j = threadIdx.x; j < M; j += blockDim.x) {
         double v[4], dv[2] = {0.0, 0.0};
         for (int s = 0; s < 4; ++s) v[s] = A[s * (H + 1)];
@@ -107,11 +117,12 @@ __global__ __launch_bounds__(256) void near_upsample(const int32_t *__restrict__
             if (s < 2) der[s] = dv[s] * inv;
         }
         const double sp = sqrt(der[0] * der[0] + der[1] * der[1]);
-        up[base + j] = val[0];
-        up[plane + base + j] = val[1];
-        up[2 * plane + base + j] = (2.0 * M_PI / (double)M) * sp;
-        up[3 * plane + base + j] = val[2];
-        up[4 * plane + base + j] = val[3];
+        const double ww = (2.0 * M_PI / (double)M) * sp;
+        double *rec = up + 4 * (base + j);
+        rec[0] = val[0];
+        rec[1] = val[1];
+        rec[2] = ww * val[2];
+        rec[3] = ww * val[3];
     }
 }
 
@@ -127,25 +138,24 @@ __device__ __forceinline__ void slp64_acc(double px, double py, double sx, doubl
     by = __builtin_fma(ry, t, by);
 }
 
-// coarse (N nodes) and fine (P N nodes) single-layer sums of one curve
+// coarse (N nodes) and fine (P N nodes) single-layer sums of one curve, from
+// the records {x, y, g_x, g_y} written by near_upsample
 template <bool UNIFORM>
-__device__ __forceinline__ void near_sums(double px, double py, int lo, int N, int P, int64_t plane,
-                                          const double *__restrict__ x, const double *__restrict__ y,
-                                          const double *__restrict__ w, const double *__restrict__ fx,
-                                          const double *__restrict__ fy, const double *__restrict__ up,
-                                          const double *ltab, double (&s)[8]) {
+__device__ __forceinline__ void near_sums(double px, double py, int lo, int N, int P, int64_t n_src,
+                                          const double *__restrict__ up, const double *ltab, double (&s)[8]) {
     if (UNIFORM) {
         lo = __builtin_amdgcn_readfirstlane(lo);
         N = __builtin_amdgcn_readfirstlane(N);
     }
-    for (int k = lo; k < lo + N; ++k)
-        slp64_acc(px, py, x[k], y[k], w[k] * fx[k], w[k] * fy[k], ltab, s[0], s[1], s[2], s[3]);
-    const int64_t base = (int64_t)lo * P;
-    for (int64_t k = base; k < base + (int64_t)N * P; ++k) {
-        const double ww = up[2 * plane + k];
-        slp64_acc(px, py, up[k], up[plane + k], ww * up[3 * plane + k], ww * up[4 * plane + k], ltab, s[4], s[5],
-                  s[6], s[7]);
-    }
+    const double *cr = up + 4 * ((int64_t)n_src * P + lo);
+#pragma unroll 4
+    for (int k = 0; k < N; ++k)
+        slp64_acc(px, py, cr[4 * k], cr[4 * k + 1], cr[4 * k + 2], cr[4 * k + 3], ltab, s[0], s[1], s[2], s[3]);
+    const double *fr = up + 4 * (int64_t)lo * P;
+    const int M = N * P;
+#pragma unroll 4
+    for (int k = 0; k < M; ++k)
+        slp64_acc(px, py, fr[4 * k], fr[4 * k + 1], fr[4 * k + 2], fr[4 * k + 3], ltab, s[4], s[5], s[6], s[7]);
 }
 
 // Delta for every target i (only those with mask[i] == 1 when mask != NULL;
@@ -156,10 +166,7 @@ __global__ __launch_bounds__(256) void near_quad(int64_t n_trg, const int32_t *_
                                                  const double *__restrict__ tx,
                                                  const double *__restrict__ ty, const int32_t *__restrict__ tc,
                                                  const int32_t *__restrict__ off, int32_t n_curves, int64_t n_src,
-                                                 const double *__restrict__ x, const double *__restrict__ y,
-                                                 const double *__restrict__ w, const double *__restrict__ fx,
-                                                 const double *__restrict__ fy, int P, const double *__restrict__ up,
-                                                 double pref, double *__restrict__ du, double *__restrict__ dv,
+                                                 int P, const double *__restrict__ up, double pref, double *__restrict__ du, double *__restrict__ dv,
                                                  double *__restrict__ uf, double *__restrict__ vf,
                                                  double *__restrict__ uc, double *__restrict__ vc) {
     __shared__ __attribute__((aligned(16))) double ltab[kLogTabWords];
@@ -183,15 +190,13 @@ __global__ __launch_bounds__(256) void near_quad(int64_t n_trg, const int32_t *_
         const bool any_ok = cmin != INT_MAX;
         const bool uniform = any_ok && __all(!live || (ok && c == cmin));
         double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        const int64_t plane = n_src * (int64_t)P;
         if (uniform) {
             // idle lanes follow the wave's curve (their results are dropped)
             const int cu = __builtin_amdgcn_readfirstlane(cmin);
             const int lou = off[cu], Nu = off[cu + 1] - lou;
-            near_sums<true>(live ? tx[i] : tx[0], live ? ty[i] : ty[0], lou, Nu, P, plane, x, y, w, fx, fy, up, ltab,
-                            s);
+            near_sums<true>(live ? tx[i] : tx[0], live ? ty[i] : ty[0], lou, Nu, P, n_src, up, ltab, s);
         } else if (ok) {
-            near_sums<false>(tx[i], ty[i], lo, N, P, plane, x, y, w, fx, fy, up, ltab, s);
+            near_sums<false>(tx[i], ty[i], lo, N, P, n_src, up, ltab, s);
         }
         if (!live) continue;
         if (!ok) {
@@ -914,7 +919,7 @@ hipError_t near_launch_upsample(const s2d_curves *c, int P, double *up, hipStrea
     // LDS: 2 M cos/sin + 8 (H + 1) coefficients, at the largest sizes (41 KB)
     const size_t lds = (2 * (size_t)kUpMaxM + 8 * ((size_t)kUpMaxN / 2 + 1)) * sizeof(double);
     hipLaunchKernelGGL(near_upsample, dim3((unsigned)c->n_curves), dim3(256), lds, st, c->curve_off, c->n_curves,
-                       c->n_nodes, c->x, c->y, c->fx, c->fy, P, up);
+                       c->n_nodes, c->x, c->y, c->w, c->fx, c->fy, P, up);
     return hipGetLastError();
 }
 
@@ -924,7 +929,7 @@ hipError_t near_launch_quad(const s2d_curves *c, const s2d_targets *t, const int
     if (t->n <= 0) return hipSuccess;
     const unsigned g = grid_for(t->n);
     hipLaunchKernelGGL(near_quad, dim3(g), dim3(256), 0, st, t->n, mask, t->x, t->y, tc, c->curve_off,
-                       c->n_curves, c->n_nodes, c->x, c->y, c->w, c->fx, c->fy, P, up, 1.0 / (4.0 * M_PI * mu), du,
+                       c->n_curves, c->n_nodes, P, up, 1.0 / (4.0 * M_PI * mu), du,
                        dv, uf, vf, uc, vc);
     return hipGetLastError();
 }
