@@ -21,15 +21,14 @@
 //    densities of nodes k0-3..k0+4 rotated into the frame and divided by
 //    their largest norm F.
 //  * MLP inference: 20 -> 64 -> 64 -> 64 -> 2, tanh-form GELU; weights and
-//    activations rounded to BF16, products accumulated in FP32 with the
-//    gfx950 v_dot2c_f32_bf16 instruction (weights wave-uniform, read through
-//    the scalar path).  The output is the correction in the local frame in
-//    units of h F / (4 pi mu).  A per-bin error bound (bins in the normal
-//    offset) calibrated on validation data decides the fallback to the
-//    upsampled quadrature.
-//  * training (FP32 master weights): per-sample forward, per-sample backward
-//    deltas, per-weight gradient sums over the batch in fixed order, and an
-//    Adam update; all deterministic.
+//    activations rounded to BF16, products accumulated in FP32 on the matrix
+//    cores (v_mfma_f32_32x32x8_bf16, 32 targets per wave).  The output is the
+//    correction in the local frame in units of h F / (4 pi mu).  A per-bin
+//    error bound (bins in the normal offset) calibrated on validation data
+//    decides the fallback to the upsampled quadrature.
+//  * training (FP32 master weights): forward and backward deltas with a wave
+//    per sample and a lane per neuron, per-weight gradient sums over the batch
+//    in fixed order, and an Adam update; all deterministic.
 #include "pair_impl.h"
 #include "s2d_near.h"
 
