@@ -217,6 +217,29 @@ __global__ __launch_bounds__(256) void near_quad(int64_t n_trg, const int32_t *_
 // ---------------------------------------------------------------------------
 // a9: features
 // ---------------------------------------------------------------------------
+// nearest node k* of the curve at [lo, lo + N) and the curve's weight sum;
+// UNIFORM: lo and N are the same in every lane (loads take the scalar path)
+template <bool UNIFORM>
+__device__ __forceinline__ int near_scan(double px, double py, int lo, int N, const double *__restrict__ x,
+                                         const double *__restrict__ y, const double *__restrict__ w, double &best,
+                                         double &wsum) {
+    if (UNIFORM) {
+        lo = __builtin_amdgcn_readfirstlane(lo);
+        N = __builtin_amdgcn_readfirstlane(N);
+    }
+    best = 1e300;
+    wsum = 0.0;
+    int ks = 0;
+#pragma unroll 4
+    for (int k = 0; k < N; ++k) {
+        const double dx = px - x[lo + k], dy = py - y[lo + k];
+        const double d2 = dx * dx + dy * dy;
+        if (d2 < best) { best = d2; ks = k; }
+        wsum += w[lo + k];
+    }
+    return ks;
+}
+
 __global__ __launch_bounds__(256) void near_features(int64_t n_trg, const double *__restrict__ tx,
                                                      const double *__restrict__ ty, const int32_t *__restrict__ tc,
                                                      const int32_t *__restrict__ off, int32_t n_curves, int64_t n_src,
@@ -225,26 +248,35 @@ __global__ __launch_bounds__(256) void near_features(int64_t n_trg, const double
                                                      const double *__restrict__ kap, const double *__restrict__ w,
                                                      const double *__restrict__ fx, const double *__restrict__ fy,
                                                      float *__restrict__ X, double *__restrict__ frame) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_trg) return;
-    const int c = tc[i];
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = q < n_trg;
+    const int64_t i = live ? q : 0;
+    const int c = live ? tc[i] : -1;
     const int lo = (c >= 0 && c < n_curves) ? off[c] : 0;
     const int N = (c >= 0 && c < n_curves) ? off[c + 1] - lo : 0;
+    const bool ok = c >= 0 && c < n_curves && N >= 8 && lo >= 0 && (int64_t)lo + N <= n_src;
+    // a wave is uniform when all its live lanes share one valid curve (every
+    // lane of the wave reaches this vote)
+    const int cl = ok ? c : INT_MAX;
+    const int cmin = wave_min(cl);
+    const bool uniform = cmin != INT_MAX && __all(!live || (ok && c == cmin));
+    const double px = live ? tx[i] : 0.0, py = live ? ty[i] : 0.0;
+    double best = 0.0, wsum = 0.0;
+    int ks = 0;
+    if (uniform) {
+        const int cu = __builtin_amdgcn_readfirstlane(cmin);
+        const int lou = off[cu];
+        ks = near_scan<true>(px, py, lou, off[cu + 1] - lou, x, y, w, best, wsum);
+    } else if (ok) {
+        ks = near_scan<false>(px, py, lo, N, x, y, w, best, wsum);
+    }
+    if (!live) return;
     float *xi = X + i * kNearFeat;
     double *fr = frame + i * 6;
-    if (c < 0 || c >= n_curves || N < 8 || lo < 0 || (int64_t)lo + N > n_src) {
+    if (!ok) {
         for (int k = 0; k < kNearFeat; ++k) xi[k] = __builtin_nanf("");
         for (int k = 0; k < 6; ++k) fr[k] = __builtin_nan("");
         return;
-    }
-    const double px = tx[i], py = ty[i];
-    double best = 1e300, wsum = 0.0;
-    int ks = 0;
-    for (int k = 0; k < N; ++k) {
-        const double dx = px - x[lo + k], dy = py - y[lo + k];
-        const double d2 = dx * dx + dy * dy;
-        if (d2 < best) { best = d2; ks = k; }
-        wsum += w[lo + k];
     }
     const double h = wsum / (double)N;
     const double ts0 = -ny[lo + ks], ts1 = nx[lo + ks];
