@@ -351,7 +351,7 @@ def wall_learned_section(prob, n_train=200000, n_test=1000000, epochs=40):
     d = prob.d
     t0 = time.time()
     tr = pn.WallNearData(walls, d, *synth.near_wall_dataset(walls, n_train, 42))
-    va = pn.WallNearData(walls, d, *synth.near_wall_dataset(walls, 20000, 43))
+    va = pn.WallNearData(walls, d, *synth.near_wall_dataset(walls, 100000, 43))
     te = pn.WallNearData(walls, d, *synth.near_wall_dataset(walls, n_test, 44))
     torch.cuda.synchronize()
     t_data = time.time() - t0
@@ -651,7 +651,7 @@ def near_section():
     from paper_1510_05616_amd import near
     t0 = time.time()
     tr = near.NearData(*synth.make_near_dataset(200000, 5)[:4], mu=1.0, upsample=8)
-    va = near.NearData(*synth.make_near_dataset(20000, 6)[:4], mu=1.0, upsample=8)
+    va = near.NearData(*synth.make_near_dataset(100000, 6)[:4], mu=1.0, upsample=8)
     c, tx, ty, tc, dh = synth.make_near_dataset(1000000, 7)
     te = near.NearData(c, tx, ty, tc, mu=1.0, upsample=8, labels=False)
     log(f"near: data ready ({time.time() - t0:.1f}s)")

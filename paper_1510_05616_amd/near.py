@@ -23,7 +23,7 @@ NPARAM = 9834
 # offsets in the FP32 master parameter vector
 OFF = dict(mu=0, sd=20, W1=40, b1=1320, W2=1384, b2=5480, W3=5544, b3=9640, W4=9704, b4=9832)
 SHAPES = dict(W1=(20, 64), b1=(64,), W2=(64, 64), b2=(64,), W3=(64, 64), b3=(64,), W4=(64, 2), b4=(2,))
-BIN_LO, BIN_W, N_BINS = math.log10(0.05), 0.1, 20      # bins of log10(|normal offset| / h)
+BIN_LO, BIN_W, N_BINS = math.log10(0.05), 2.0 / 64, 64   # bins of log10(|normal offset| / h)
 
 _bound = False
 
