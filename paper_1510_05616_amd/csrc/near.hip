@@ -43,48 +43,57 @@ namespace s2d {
 // Output: the fine curve as records {x, y, w fx, w fy} at up[4 (P lo + j)],
 // j < P N, with the fine trapezoid weight w = (2 pi / (P N)) |x'|, then the
 // given nodes as records {x, y, w fx, w fy} at up[4 (P n_src + lo + k)].
-__global__ __launch_bounds__(256) void near_upsample(const int32_t *__restrict__ off, int32_t n_curves, int64_t n_src,
-                                                     const double *__restrict__ x, const double *__restrict__ y,
-                                                     const double *__restrict__ w,
-                                                     const double *__restrict__ fx, const double *__restrict__ fy,
-                                                     int P, double *__restrict__ up /* [4 (P + 1) n_src] */) {
-    extern __shared__ double lds[];
+//
+// With v(t) = sum_{m=0}^{H} (a_m cos m t + b_m sin m t) (H = N/2, the weights
+// 2/N and 1/N folded into a, b), the fine nodes j, M - j, M/2 + j and M/2 - j
+// see the same cos and sin of m t_j up to signs: the sign of sin flips under
+// reflection and both flip with (-1)^m under the half turn.  One thread sums
+// the even-m and odd-m parts of the cosine and sine series separately for
+// t_j, 0 <= j <= M/4, and forms all four values from them.  The analysis sums
+// pair node k with node N - k (same cosine, opposite sine).  Both stages step
+// cos and sin of the multiple angles by rotation through the base angle (at
+// most 128 steps; the rounding error grows at most linearly, and the fine
+// nodes stay within about 1e-14 of the exact interpolant), so no table is
+// kept in LDS.
+constexpr int kUpThreads = 320;   // >= M/4 + 1 and >= 4 (H + 1) at N = 128, P = 8
+
+__device__ __forceinline__ void up_acc(const double *__restrict__ c, double co, double sn, double (&C)[4],
+                                       double (&S)[4], double (&Dc)[2], double (&Ds)[2]) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        C[s] = __builtin_fma(c[s], co, C[s]);
+        S[s] = __builtin_fma(c[4 + s], sn, S[s]);
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        Dc[s] = __builtin_fma(c[8 + s], co, Dc[s]);
+        Ds[s] = __builtin_fma(c[10 + s], sn, Ds[s]);
+    }
+}
+
+__global__ __launch_bounds__(kUpThreads) void near_upsample(const int32_t *__restrict__ off, int32_t n_curves,
+                                                            int64_t n_src, const double *__restrict__ x,
+                                                            const double *__restrict__ y,
+                                                            const double *__restrict__ w,
+                                                            const double *__restrict__ fx,
+                                                            const double *__restrict__ fy, int P,
+                                                            double *__restrict__ up /* [4 (P + 1) n_src] */) {
+    extern __shared__ __attribute__((aligned(16))) double lds[];
     const int c = blockIdx.x;
     if (c >= n_curves) return;
     const int lo = off[c], N = off[c + 1] - lo;
     if (N < 4 || (N & 1) || N > kUpMaxN || lo < 0 || (int64_t)lo + N > n_src || P * N > kUpMaxM) return;
     const int M = P * N, H = N / 2;
-    double *ct = lds;                 // cos(2 pi j / M), j < M
-    double *st = ct + M;              // sin(2 pi j / M)
-    double *A = st + M;               // [4][H + 1] cosine coefficients
-    double *B = A + 4 * (H + 1);      // [4][H + 1] sine coefficients
-    for (int j = threadIdx.x; j < M; j += blockDim.x) {
-        double s, co;
-        sincospi(2.0 * (double)j / (double)M, &s, &co);
-        ct[j] = co;
-        st[j] = s;
-    }
-    __syncthreads();
-    // angle indices advance by a fixed step modulo M (no division per term)
+    double *eo = lds;                 // [4][H] pairs: {v_0, v_H}, then {v_k + v_{N-k}, v_k - v_{N-k}}
+    double *cf = eo + 8 * H;          // [H + 1][12]: a_0..3, b_0..3, m b_0..1, m a_0..1
     const double *sig[4] = {x + lo, y + lo, fx + lo, fy + lo};
-    for (int q = threadIdx.x; q < 4 * (H + 1); q += blockDim.x) {
-        const int s = q / (H + 1), m = q % (H + 1);
+    for (int q = threadIdx.x; q < 4 * H; q += blockDim.x) {
+        const int s = q / H, k = q % H;
         const double *v = sig[s];
-        const int step = (m * P) % M;                            // angle 2 pi m k / N
-        double a = 0.0, b = 0.0;
-        int idx = 0;
-        for (int k = 0; k < N; ++k) {
-            a += v[k] * ct[idx];
-            b += v[k] * st[idx];
-            idx += step;
-            idx -= idx >= M ? M : 0;
-        }
-        A[q] = a;
-        B[q] = b;
+        const double p = v[k], r = k ? v[N - k] : v[H];
+        eo[2 * q] = k ? p + r : p;
+        eo[2 * q + 1] = k ? p - r : r;
     }
-    __syncthreads();
-    const double inv = 1.0 / (double)N;
-    const int64_t base = (int64_t)lo * P;
     double *coarse = up + 4 * ((int64_t)n_src * P + lo);
     for (int k = threadIdx.x; k < N; k += blockDim.x) {
         coarse[4 * k] = x[lo + k];
@@ -92,36 +101,75 @@ __global__ __launch_bounds__(256) void near_upsample(const int32_t *__restrict__
         coarse[4 * k + 2] = w[lo + k] * fx[lo + k];
         coarse[4 * k + 3] = w[lo + k] * fy[lo + k];
     }
-    for (int j = threadIdx.x; j < M; j += blockDim.x) {
-        double v[4], dv[2] = {0.0, 0.0};
-        for (int s = 0; s < 4; ++s) v[s] = A[s * (H + 1)];
-        int idx = j;                                             // m j mod M
-        for (int m = 1; m < H; ++m) {
-            const double c = ct[idx], sn = st[idx];
-            for (int s = 0; s < 4; ++s) {
-                const double am = A[s * (H + 1) + m], bm = B[s * (H + 1) + m];
-                v[s] += 2.0 * (am * c + bm * sn);
-                if (s < 2) dv[s] += 2.0 * (double)m * (bm * c - am * sn);
-            }
-            idx += j;
-            idx -= idx >= M ? M : 0;
+    __syncthreads();
+    const double inv = 1.0 / (double)N;
+    for (int q = threadIdx.x; q < 4 * (H + 1); q += blockDim.x) {
+        const int s = q / (H + 1), m = q % (H + 1);
+        const double *e = eo + 2 * H * s;
+        // (cos, sin)(2 pi m k / N) by rotation through 2 pi m / N
+        double c1, s1;
+        sincospi(2.0 * (double)m / (double)N, &s1, &c1);
+        double a = (m & 1) ? e[0] - e[1] : e[0] + e[1];          // k = 0 and k = H
+        double b = 0.0, co = c1, sn = s1;
+        for (int k = 1; k < H; ++k) {
+            a = __builtin_fma(e[2 * k], co, a);
+            b = __builtin_fma(e[2 * k + 1], sn, b);
+            const double r = __builtin_fma(co, c1, -sn * s1);
+            sn = __builtin_fma(sn, c1, co * s1);
+            co = r;
         }
-        double val[4], der[2];
-        const double cH = ct[idx], sH = st[idx];                 // idx = H j mod M
-        for (int s = 0; s < 4; ++s) {
-            const double aH = A[s * (H + 1) + H];
-            v[s] += aH * cH;
-            if (s < 2) dv[s] -= (double)H * aH * sH;
-            val[s] = v[s] * inv;
-            if (s < 2) der[s] = dv[s] * inv;
+        const bool edge = m == 0 || m == H;                      // no sine term, weight 1 / N
+        const double wgt = edge ? inv : 2.0 * inv;
+        a *= wgt;
+        b = edge ? 0.0 : b * wgt;
+        double *cm = cf + 12 * m;
+        cm[s] = a;
+        cm[4 + s] = b;
+        if (s < 2) {
+            cm[8 + s] = (double)m * b;
+            cm[10 + s] = (double)m * a;
         }
-        const double sp = sqrt(der[0] * der[0] + der[1] * der[1]);
-        const double ww = (2.0 * M_PI / (double)M) * sp;
-        double *rec = up + 4 * (base + j);
-        rec[0] = val[0];
-        rec[1] = val[1];
-        rec[2] = ww * val[2];
-        rec[3] = ww * val[3];
+    }
+    __syncthreads();
+    const int64_t base = (int64_t)lo * P;
+    const double hw = 2.0 * M_PI / (double)M;
+    const int G = M / 4 + 1;
+    for (int j = threadIdx.x; j < G; j += blockDim.x) {
+        double Ce[4] = {0, 0, 0, 0}, Co[4] = {0, 0, 0, 0}, Se[4] = {0, 0, 0, 0}, So[4] = {0, 0, 0, 0};
+        double Dce[2] = {0, 0}, Dco[2] = {0, 0}, Dse[2] = {0, 0}, Dso[2] = {0, 0};
+        // (cos, sin)(m t_j) by rotation through t_j: no lane-varying table reads
+        double c1, s1;
+        sincospi(2.0 * (double)j / (double)M, &s1, &c1);
+        double co = 1.0, sn = 0.0;
+        int m = 0;
+        for (; m < H; m += 2) {
+            up_acc(cf + 12 * m, co, sn, Ce, Se, Dce, Dse);
+            double t = __builtin_fma(co, c1, -sn * s1);
+            sn = __builtin_fma(sn, c1, co * s1);
+            co = t;
+            up_acc(cf + 12 * (m + 1), co, sn, Co, So, Dco, Dso);
+            t = __builtin_fma(co, c1, -sn * s1);
+            sn = __builtin_fma(sn, c1, co * s1);
+            co = t;
+        }
+        if (m == H) up_acc(cf + 12 * m, co, sn, Ce, Se, Dce, Dse);
+        // sign of the odd-m part (half turn) and of the sine part (reflection)
+        const int pts[4] = {j, j ? M - j : 0, M / 2 + j, M / 2 - j};
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            const double ho = (o & 2) ? -1.0 : 1.0, rs = (o & 1) ? -1.0 : 1.0;
+            double v[4], dv[2];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) v[s] = (Ce[s] + ho * Co[s]) + rs * (Se[s] + ho * So[s]);
+#pragma unroll
+            for (int s = 0; s < 2; ++s) dv[s] = (Dce[s] + ho * Dco[s]) - rs * (Dse[s] + ho * Dso[s]);
+            const double ww = hw * sqrt(dv[0] * dv[0] + dv[1] * dv[1]);
+            double *rec = up + 4 * (base + pts[o]);
+            rec[0] = v[0];
+            rec[1] = v[1];
+            rec[2] = ww * v[2];
+            rec[3] = ww * v[3];
+        }
     }
 }
 
@@ -947,9 +995,9 @@ static unsigned grid_for(int64_t n, int b = 256) { return (unsigned)((n + b - 1)
 
 hipError_t near_launch_upsample(const s2d_curves *c, int P, double *up, hipStream_t st) {
     if (c->n_curves <= 0) return hipSuccess;
-    // LDS: 2 M cos/sin + 8 (H + 1) coefficients, at the largest sizes (41 KB)
-    const size_t lds = (2 * (size_t)kUpMaxM + 8 * ((size_t)kUpMaxN / 2 + 1)) * sizeof(double);
-    hipLaunchKernelGGL(near_upsample, dim3((unsigned)c->n_curves), dim3(256), lds, st, c->curve_off, c->n_curves,
+    // LDS: 8 H node pairs and 12 (H + 1) coefficients at the largest N (21 KB)
+    const size_t lds = (4 * (size_t)kUpMaxN + 12 * ((size_t)kUpMaxN / 2 + 1)) * sizeof(double);
+    hipLaunchKernelGGL(near_upsample, dim3((unsigned)c->n_curves), dim3(kUpThreads), lds, st, c->curve_off, c->n_curves,
                        c->n_nodes, c->x, c->y, c->w, c->fx, c->fy, P, up);
     return hipGetLastError();
 }

@@ -49,6 +49,30 @@ def test_upsampled_quadrature_matches_oracle(small):
     assert worst < 1e-12
 
 
+@pytest.mark.parametrize("P,sizes", [(1, (66, 70)), (3, (66, 126)), (5, (64, 98)), (16, (4, 128)), (32, (64,))])
+def test_upsampled_quadrature_other_factors(P, sizes):
+    """Upsampling factors other than 8, curve sizes with N/2 odd (P N not a
+    multiple of 4) and the largest P N the kernel takes (2048)."""
+    import oracle
+    from paper_1510_05616_amd import near
+    c, tx, ty, tc, dh = synth.make_near_dataset(600, seed=40 + P, per_curve=100, sizes=sizes)
+    data = near.NearData(c, tx, ty, tc, mu=1.0, upsample=P)
+    du = data.du.cpu().numpy()
+    dv = data.dv.cpu().numpy()
+    worst = 0.0
+    for k in range(c.n_curves):
+        sel = np.where(tc == k)[0]
+        s = slice(c.curve_off[k], c.curve_off[k + 1])
+        ou, ov = onear.near_label(c.x[s], c.y[s], c.fx[s], c.fy[s], c.w[s], tx[sel], ty[sel], P=P)
+        sub = synth.CurveSet(*(getattr(c, a)[s] for a in ("x", "y", "nx", "ny", "w", "kappa", "fx", "fy")),
+                             curve_off=np.array([0, s.stop - s.start], np.int32))
+        u1, v1 = oracle.slp(sub, tx[sel], ty[sel])
+        sc = np.hypot(u1 + ou, v1 + ov).max()
+        worst = max(worst, np.hypot(du[sel] - ou, dv[sel] - ov).max() / sc)
+    print(f"P={P} sizes={sizes}: upsampled quadrature worst rel err {worst:.2e}", flush=True)
+    assert worst < 1e-12
+
+
 def test_features_match_oracle(small):
     c, tx, ty, tc, dh, data = small
     X = data.X.cpu().numpy()
