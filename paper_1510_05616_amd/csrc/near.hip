@@ -185,80 +185,103 @@ __device__ __forceinline__ void slp64_acc(double px, double py, double sx, doubl
     by = __builtin_fma(ry, t, by);
 }
 
-// coarse (N nodes) and fine (P N nodes) single-layer sums of one curve, from
-// the records {x, y, g_x, g_y} written by near_upsample
+// Part `part` of `parts` of the coarse (N nodes) and fine (P N nodes)
+// single-layer sums of one curve, from the records {x, y, g_x, g_y} written
+// by near_upsample: the sources are taken as one list, the N coarse records
+// then the P N fine ones, cut into `parts` contiguous pieces; coarse sources
+// go to s[0..3], fine ones to s[4..7].
 template <bool UNIFORM>
-__device__ __forceinline__ void near_sums(double px, double py, int lo, int N, int P, int64_t n_src,
-                                          const double *__restrict__ up, const double *ltab, double (&s)[8]) {
+__device__ __forceinline__ void near_sums(double px, double py, int lo, int N, int P, int64_t n_src, int part,
+                                          int parts, const double *__restrict__ up, const double *ltab,
+                                          double (&s)[8]) {
     if (UNIFORM) {
         lo = __builtin_amdgcn_readfirstlane(lo);
         N = __builtin_amdgcn_readfirstlane(N);
     }
+    const int L = (P + 1) * N;
+    const int a = L * part / parts, b = L * (part + 1) / parts;
     const double *cr = up + 4 * ((int64_t)n_src * P + lo);
+    const int ce = min(b, N);
 #pragma unroll 4
-    for (int k = 0; k < N; ++k)
+    for (int k = a; k < ce; ++k)
         slp64_acc(px, py, cr[4 * k], cr[4 * k + 1], cr[4 * k + 2], cr[4 * k + 3], ltab, s[0], s[1], s[2], s[3]);
     const double *fr = up + 4 * (int64_t)lo * P;
-    const int M = N * P;
+    const int fb = b - N;
 #pragma unroll 4
-    for (int k = 0; k < M; ++k)
+    for (int k = max(a, N) - N; k < fb; ++k)
         slp64_acc(px, py, fr[4 * k], fr[4 * k + 1], fr[4 * k + 2], fr[4 * k + 3], ltab, s[4], s[5], s[6], s[7]);
 }
 
-// Delta for every target i (only those with mask[i] == 1 when mask != NULL;
-// targets stay in their order, so the waves of curve-sorted targets remain
-// on one curve).  When every live target of a wave lies on the same curve the
-// source loops are wave-uniform and their loads go through the scalar path.
-__global__ __launch_bounds__(256) void near_quad(int64_t n_trg, const int32_t *__restrict__ mask,
-                                                 const double *__restrict__ tx,
-                                                 const double *__restrict__ ty, const int32_t *__restrict__ tc,
-                                                 const int32_t *__restrict__ off, int32_t n_curves, int64_t n_src,
-                                                 int P, const double *__restrict__ up, double pref, double *__restrict__ du, double *__restrict__ dv,
-                                                 double *__restrict__ uf, double *__restrict__ vf,
-                                                 double *__restrict__ uc, double *__restrict__ vc) {
+// Delta for the 64 targets q = 64 blockIdx.x + lane (only those with
+// mask[q] == 1 when mask != NULL).  The four waves of the workgroup take the
+// same targets and a quarter of the sources each; wave 0 adds the other
+// three's partial sums in fixed order.  Short workgroups keep the launch
+// balanced across curves of different sizes.  When every live target of the
+// wave lies on the same curve (targets sorted by curve), the source loops are
+// wave-uniform and their loads go through the scalar path.
+constexpr int kQuadParts = 4;
+
+__global__ __launch_bounds__(64 * kQuadParts) void near_quad(int64_t n_trg, const int32_t *__restrict__ mask,
+                                                             const double *__restrict__ tx,
+                                                             const double *__restrict__ ty,
+                                                             const int32_t *__restrict__ tc,
+                                                             const int32_t *__restrict__ off, int32_t n_curves,
+                                                             int64_t n_src, int P, const double *__restrict__ up,
+                                                             double pref, double *__restrict__ du,
+                                                             double *__restrict__ dv, double *__restrict__ uf,
+                                                             double *__restrict__ vf, double *__restrict__ uc,
+                                                             double *__restrict__ vc) {
     __shared__ __attribute__((aligned(16))) double ltab[kLogTabWords];
+    __shared__ double partial[kQuadParts - 1][8][kWave];
     fill_log_table(ltab);
-    const int64_t n = n_trg;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    // every wave runs the same number of iterations (n rounded up), so the
-    // wave-level vote below sees all 64 lanes
-    const int64_t nround = (n + stride - 1) / stride * stride;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nround; q += stride) {
-        const bool live = q < n && (!mask || mask[q] == 1);
-        const int64_t i = live ? q : 0;
-        const int c = live ? tc[i] : -1;
-        const int lo = (c >= 0 && c < n_curves) ? off[c] : 0;
-        const int N = (c >= 0 && c < n_curves) ? off[c + 1] - lo : 0;
-        const bool ok = c >= 0 && c < n_curves && N >= 4 && !(N & 1) && N <= kUpMaxN && P * N <= kUpMaxM &&
-                        lo >= 0 && (int64_t)lo + N <= n_src;
-        // a wave is uniform when all its live lanes share one valid curve
-        const int cl = ok ? c : INT_MAX;
-        const int cmin = wave_min(cl);
-        const bool any_ok = cmin != INT_MAX;
-        const bool uniform = any_ok && __all(!live || (ok && c == cmin));
-        double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (uniform) {
-            // idle lanes follow the wave's curve (their results are dropped)
-            const int cu = __builtin_amdgcn_readfirstlane(cmin);
-            const int lou = off[cu], Nu = off[cu + 1] - lou;
-            near_sums<true>(live ? tx[i] : tx[0], live ? ty[i] : ty[0], lou, Nu, P, n_src, up, ltab, s);
-        } else if (ok) {
-            near_sums<false>(tx[i], ty[i], lo, N, P, n_src, up, ltab, s);
-        }
-        if (!live) continue;
-        if (!ok) {
-            du[i] = dv[i] = __builtin_nan("");
-            if (uf) uf[i] = vf[i] = uc[i] = vc[i] = __builtin_nan("");
-            continue;
-        }
-        du[i] = pref * ((-0.5 * s[4] + s[6]) - (-0.5 * s[0] + s[2]));
-        dv[i] = pref * ((-0.5 * s[5] + s[7]) - (-0.5 * s[1] + s[3]));
-        if (uf) {
-            uf[i] = pref * (-0.5 * s[4] + s[6]);
-            vf[i] = pref * (-0.5 * s[5] + s[7]);
-            uc[i] = pref * (-0.5 * s[0] + s[2]);
-            vc[i] = pref * (-0.5 * s[1] + s[3]);
-        }
+    const int lane = threadIdx.x & (kWave - 1);
+    const int part = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    const int64_t q = (int64_t)blockIdx.x * kWave + lane;
+    const bool live = q < n_trg && (!mask || mask[q] == 1);
+    const int64_t i = live ? q : 0;
+    const int c = live ? tc[i] : -1;
+    const int lo = (c >= 0 && c < n_curves) ? off[c] : 0;
+    const int N = (c >= 0 && c < n_curves) ? off[c + 1] - lo : 0;
+    const bool ok = c >= 0 && c < n_curves && N >= 4 && !(N & 1) && N <= kUpMaxN && P * N <= kUpMaxM &&
+                    lo >= 0 && (int64_t)lo + N <= n_src;
+    // a wave is uniform when all its live lanes share one valid curve
+    const int cl = ok ? c : INT_MAX;
+    const int cmin = wave_min(cl);
+    const bool any_ok = cmin != INT_MAX;
+    const bool uniform = any_ok && __all(!live || (ok && c == cmin));
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (uniform) {
+        // idle lanes follow the wave's curve (their results are dropped)
+        const int cu = __builtin_amdgcn_readfirstlane(cmin);
+        const int lou = off[cu], Nu = off[cu + 1] - lou;
+        near_sums<true>(live ? tx[i] : tx[0], live ? ty[i] : ty[0], lou, Nu, P, n_src, part, kQuadParts, up, ltab,
+                        s);
+    } else if (ok) {
+        near_sums<false>(tx[i], ty[i], lo, N, P, n_src, part, kQuadParts, up, ltab, s);
+    }
+    if (part > 0) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) partial[part - 1][k][lane] = s[k];
+    }
+    __syncthreads();
+    if (part > 0 || !live) return;
+#pragma unroll
+    for (int p = 0; p < kQuadParts - 1; ++p) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s[k] += partial[p][k][lane];
+    }
+    if (!ok) {
+        du[i] = dv[i] = __builtin_nan("");
+        if (uf) uf[i] = vf[i] = uc[i] = vc[i] = __builtin_nan("");
+        return;
+    }
+    du[i] = pref * ((-0.5 * s[4] + s[6]) - (-0.5 * s[0] + s[2]));
+    dv[i] = pref * ((-0.5 * s[5] + s[7]) - (-0.5 * s[1] + s[3]));
+    if (uf) {
+        uf[i] = pref * (-0.5 * s[4] + s[6]);
+        vf[i] = pref * (-0.5 * s[5] + s[7]);
+        uc[i] = pref * (-0.5 * s[0] + s[2]);
+        vc[i] = pref * (-0.5 * s[1] + s[3]);
     }
 }
 
@@ -1006,8 +1029,8 @@ hipError_t near_launch_quad(const s2d_curves *c, const s2d_targets *t, const int
                             int P, const double *up, double mu, double *du, double *dv, hipStream_t st, double *uf,
                             double *vf, double *uc, double *vc) {
     if (t->n <= 0) return hipSuccess;
-    const unsigned g = grid_for(t->n);
-    hipLaunchKernelGGL(near_quad, dim3(g), dim3(256), 0, st, t->n, mask, t->x, t->y, tc, c->curve_off,
+    const unsigned g = grid_for(t->n, kWave);
+    hipLaunchKernelGGL(near_quad, dim3(g), dim3(kWave * kQuadParts), 0, st, t->n, mask, t->x, t->y, tc, c->curve_off,
                        c->n_curves, c->n_nodes, P, up, 1.0 / (4.0 * M_PI * mu), du,
                        dv, uf, vf, uc, vc);
     return hipGetLastError();
