@@ -143,58 +143,107 @@ __global__ __launch_bounds__(256) void wall_dft_sum(WallArgs a) {
     ((Coef8 *)a.coef)[g] = o;
 }
 
-// stage 2 sums over modes k = kb .. ke-1 at the fine angle 2 pi m / M:
-// acc = Re sum V_k e^{ik th}, dac = Re sum i k V_k e^{ik th} (x~ and y only)
+// stage 2 sums over modes k = kb .. ke-1 at the fine angle th = 2 pi j / M,
+// kept apart by the parity of k - kb (A: even, B: odd) and split into
+// C = sum Re V_k cos k th, S = sum Im V_k sin k th (four series) and
+// DS = sum k Re V_k sin k th, DC = sum k Im V_k cos k th (x~ and y only).
+// Then Re sum V_k e^{ik th} = C - S and Re sum i k V_k e^{ik th} = -(DS + DC);
+// at -th the sine parts change sign, and at th + pi the odd-k parts do.
+struct SynthAcc { double C[4], S[4], DS[2], DC[2]; };
+
 template <bool UNI>
-__device__ __forceinline__ void synth_sums(const Coef8 *coef, int64_t lo, int64_t kb, int64_t ke, int64_t m,
-                                           int64_t M, double acc[4], double dac[2]) {
-    double wr, wi;
-    sincospi(2.0 * (double)m / (double)M, &wi, &wr);   // e^{i th}
-    for (int64_t k0 = kb; k0 < ke; k0 += kAnchor) {
-        double zr, zi;
-        sincospi(2.0 * (double)((k0 * m) % M) / (double)M, &zi, &zr);
-        const int64_t k1 = min(k0 + (int64_t)kAnchor, ke);
-        for (int64_t k = k0; k < k1; ++k) {
-            const Coef8 V = ld<UNI>(coef, lo + k);
+__device__ __forceinline__ void synth_step(const Coef8 *coef, int64_t lo, int64_t k, double zr, double zi,
+                                           SynthAcc &X) {
+    const Coef8 V = ld<UNI>(coef, lo + k);
+    const double kd = (double)k;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) acc[q] += V.v[2 * q] * zr - V.v[2 * q + 1] * zi;
-            const double kd = (double)k;
+    for (int q = 0; q < 4; ++q) {
+        X.C[q] = __builtin_fma(V.v[2 * q], zr, X.C[q]);
+        X.S[q] = __builtin_fma(V.v[2 * q + 1], zi, X.S[q]);
+    }
 #pragma unroll
-            for (int q = 0; q < 2; ++q) dac[q] -= kd * (V.v[2 * q] * zi + V.v[2 * q + 1] * zr);
-            const double tr = zr * wr - zi * wi;
-            zi = zr * wi + zi * wr;
-            zr = tr;
-        }
+    for (int q = 0; q < 2; ++q) {
+        X.DS[q] = __builtin_fma(kd * V.v[2 * q], zi, X.DS[q]);
+        X.DC[q] = __builtin_fma(kd * V.v[2 * q + 1], zr, X.DC[q]);
     }
 }
 
-// stage 2, split over the modes 1 .. h-1: work-item g, chunk blockIdx.y ->
-// fine point m = g - P off[c] of curve c; six partial sums per chunk
+template <bool UNI>
+__device__ __forceinline__ void synth_sums(const Coef8 *coef, int64_t lo, int64_t kb, int64_t ke, int64_t j,
+                                           int64_t M, SynthAcc &A, SynthAcc &B) {
+    double wr, wi;
+    sincospi(2.0 * (double)j / (double)M, &wi, &wr);   // e^{i th}
+    for (int64_t k0 = kb; k0 < ke; k0 += kAnchor) {      // kAnchor is even: k0 - kb stays even
+        double zr, zi;
+        sincospi(2.0 * (double)((k0 * j) % M) / (double)M, &zi, &zr);
+        const int64_t k1 = min(k0 + (int64_t)kAnchor, ke);
+        int64_t k = k0;
+        for (; k + 1 < k1; k += 2) {
+            synth_step<UNI>(coef, lo, k, zr, zi, A);
+            double tr = zr * wr - zi * wi;
+            zi = zr * wi + zi * wr;
+            zr = tr;
+            synth_step<UNI>(coef, lo, k + 1, zr, zi, B);
+            tr = zr * wr - zi * wi;
+            zi = zr * wi + zi * wr;
+            zr = tr;
+        }
+        if (k < k1) synth_step<UNI>(coef, lo, k, zr, zi, A);
+    }
+}
+
+// stage 2, split over the modes 1 .. h-1: work-item g, chunk blockIdx.y.
+// Curve c owns the P N / 2 work-items from ceil(P off[c] / 2); item j <= M / 4
+// of the curve serves the fine points j, M - j, M/2 + j and M/2 - j (the
+// rest return at once).  Six partial sums per fine point and chunk.
 __global__ __launch_bounds__(256) void wall_synth_part(WallArgs a) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t P = a.P, nf = P * a.n_nodes;
-    if (g >= nf) return;
-    const int c = find_curve(a.off, a.n_curves, g, P);
-    const int64_t lo = a.off[c], hi = a.off[c + 1], N = hi - lo, M = P * N, m = g - P * lo, h = N / 2;
-    if (!curve_ok(lo, hi, a.n_nodes) || m < 0 || m >= M) return;
+    if (2 * g >= nf) return;
+    const int c = find_curve(a.off, a.n_curves, 2 * g, P);
+    const int64_t lo = a.off[c], hi = a.off[c + 1], N = hi - lo, M = P * N, h = N / 2;
+    const int64_t j = g - (P * lo + 1) / 2;
+    if (!curve_ok(lo, hi, a.n_nodes) || j < 0 || j > M / 4) return;
     const int64_t S = a.s2, sc = blockIdx.y, len = (h - 1 + S - 1) / S;
     const int64_t kb = min(1 + sc * len, h), ke = min(kb + len, h);
     const Coef8 *coef = (const Coef8 *)a.coef;
-    double acc[4] = {0, 0, 0, 0}, dac[2] = {0, 0};
+    SynthAcc A = {}, B = {};
     const int lo_u = __builtin_amdgcn_readfirstlane((int)lo);
     if (__all(lo == (int64_t)lo_u)) {
         // one curve: the mode range is wave-uniform (scalar loop, scalar
         // loads of the coefficients)
         const int kb_u = __builtin_amdgcn_readfirstlane((int)kb), ke_u = __builtin_amdgcn_readfirstlane((int)ke);
-        synth_sums<true>(coef, lo_u, kb_u, ke_u, m, M, acc, dac);
+        synth_sums<true>(coef, lo_u, kb_u, ke_u, j, M, A, B);
     } else {
-        synth_sums<false>(coef, lo, kb, ke, m, M, acc, dac);
+        synth_sums<false>(coef, lo, kb, ke, j, M, A, B);
     }
-    double *p = a.part2 + sc * 6 * nf + g;
+    const bool odd = kb & 1;                            // A holds the odd k when kb is odd
+    SynthAcc E, O;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) p[q * nf] = acc[q];
-    p[4 * nf] = dac[0];
-    p[5 * nf] = dac[1];
+    for (int q = 0; q < 4; ++q) {
+        E.C[q] = odd ? B.C[q] : A.C[q];
+        O.C[q] = odd ? A.C[q] : B.C[q];
+        E.S[q] = odd ? B.S[q] : A.S[q];
+        O.S[q] = odd ? A.S[q] : B.S[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        E.DS[q] = odd ? B.DS[q] : A.DS[q];
+        O.DS[q] = odd ? A.DS[q] : B.DS[q];
+        E.DC[q] = odd ? B.DC[q] : A.DC[q];
+        O.DC[q] = odd ? A.DC[q] : B.DC[q];
+    }
+    const int64_t pts[4] = {j, j ? M - j : 0, M / 2 + j, M / 2 - j};
+    double *base = a.part2 + sc * 6 * nf + P * lo;
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+        const double ho = (o & 2) ? -1.0 : 1.0, rs = (o & 1) ? -1.0 : 1.0;
+        double *p = base + pts[o];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) p[q * nf] = (E.C[q] + ho * O.C[q]) - rs * (E.S[q] + ho * O.S[q]);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) p[(4 + q) * nf] = -rs * (E.DS[q] + ho * O.DS[q]) - (E.DC[q] + ho * O.DC[q]);
+    }
 }
 
 // stage 2 finish: the chunks' sums in chunk order, the mean and Nyquist
@@ -325,11 +374,11 @@ hipError_t wall_upsample_launch(const WallArgs &a, hipStream_t st) {
                            a.off, a.n_curves, a.P, a.ooff);
     }
     if (a.n_nodes > 0) {
-        const unsigned g1 = grid(a.n_nodes), g2 = grid((int64_t)a.P * a.n_nodes);
+        const unsigned g1 = grid(a.n_nodes), g2 = grid(((int64_t)a.P * a.n_nodes + 1) / 2);
         hipLaunchKernelGGL(wall_dft_part, dim3(g1, (unsigned)a.s1), dim3(256), 0, st, a);
         hipLaunchKernelGGL(wall_dft_sum, dim3(g1), dim3(256), 0, st, a);
         hipLaunchKernelGGL(wall_synth_part, dim3(g2, (unsigned)a.s2), dim3(256), 0, st, a);
-        hipLaunchKernelGGL(wall_synth_fin, dim3(g2), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(wall_synth_fin, dim3(grid((int64_t)a.P * a.n_nodes)), dim3(256), 0, st, a);
     }
     return hipGetLastError();
 }
