@@ -236,7 +236,12 @@ __global__ __launch_bounds__(64 * kQuadParts) void near_quad(int64_t n_trg, cons
     fill_log_table(ltab);
     const int lane = threadIdx.x & (kWave - 1);
     const int part = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
-    const int64_t q = (int64_t)blockIdx.x * kWave + lane;
+    // workgroups are dispatched round-robin over the 8 XCDs; XCD r takes a
+    // contiguous run of target groups, so the 3-4 workgroups of one curve
+    // share that XCD's L2 copy of the curve's records
+    const unsigned nb = gridDim.x, r = blockIdx.x % 8, per = nb / 8, rem = nb % 8;
+    const unsigned blk = (r < rem ? r * (per + 1) : rem * (per + 1) + (r - rem) * per) + blockIdx.x / 8;
+    const int64_t q = (int64_t)blk * kWave + lane;
     const bool live = q < n_trg && (!mask || mask[q] == 1);
     const int64_t i = live ? q : 0;
     const int c = live ? tc[i] : -1;
