@@ -73,6 +73,33 @@ def test_upsampled_quadrature_other_factors(P, sizes):
     assert worst < 1e-12
 
 
+def test_upsampled_and_trapezoid_sums_match_oracle(small):
+    """near_upsampled_slp returns the fine (P = 8) and plain trapezoid single
+    layers separately; each against the oracle's sums over the upsampled and
+    the given nodes, and their difference against near_correct_eval."""
+    import torch
+    from paper_1510_05616_amd import near
+    c, tx, ty, tc, dh, data = small
+    n = len(tx)
+    out = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(4)]
+    near.near_upsampled_slp(data.curves, data.trg, data.tc, 8, 1.0, *out)
+    uP, vP, u1, v1 = (o.cpu().numpy() for o in out)
+    worst_f = worst_c = 0.0
+    for k in range(c.n_curves):
+        sel = np.where(tc == k)[0]
+        s = slice(c.curve_off[k], c.curve_off[k + 1])
+        xu, yu, wu, fxu, fyu = onear.upsample_curve(c.x[s], c.y[s], c.fx[s], c.fy[s], 8)
+        ouP, ovP = onear.slp_trap(xu, yu, wu, fxu, fyu, tx[sel], ty[sel])
+        ou1, ov1 = onear.slp_trap(c.x[s], c.y[s], c.w[s], c.fx[s], c.fy[s], tx[sel], ty[sel])
+        sc = np.hypot(ouP, ovP).max()
+        worst_f = max(worst_f, np.hypot(uP[sel] - ouP, vP[sel] - ovP).max() / sc)
+        worst_c = max(worst_c, np.hypot(u1[sel] - ou1, v1[sel] - ov1).max() / sc)
+    du, dv = data.du.cpu().numpy(), data.dv.cpu().numpy()
+    gap = np.hypot((uP - u1) - du, (vP - v1) - dv).max() / np.hypot(uP, vP).max()
+    print(f"fine {worst_f:.2e} trapezoid {worst_c:.2e} difference vs near_correct_eval {gap:.2e}", flush=True)
+    assert worst_f < 1e-12 and worst_c < 1e-12 and gap < 1e-14
+
+
 def test_features_match_oracle(small):
     c, tx, ty, tc, dh, data = small
     X = data.X.cpu().numpy()
