@@ -100,6 +100,41 @@ def test_upsampled_and_trapezoid_sums_match_oracle(small):
     assert worst_f < 1e-12 and worst_c < 1e-12 and gap < 1e-14
 
 
+def test_invalid_targets_and_curves_give_nan():
+    """Targets with a curve index out of range and targets of odd-sized
+    curves get NaN; the valid targets sharing their waves still match the
+    oracle (the per-lane path of the quadrature)."""
+    import oracle
+    from paper_1510_05616_amd import near
+    c, tx, ty, tc, dh = synth.make_near_dataset(700, seed=44, per_curve=70, sizes=(63, 64, 96))
+    tc = tc.copy()
+    rng = np.random.default_rng(4)
+    bad = rng.choice(len(tx), 40, replace=False)
+    tc[bad[:20]] = -1
+    tc[bad[20:]] = c.n_curves
+    data = near.NearData(c, tx, ty, tc, mu=1.0, upsample=8)
+    du, dv = data.du.cpu().numpy(), data.dv.cpu().numpy()
+    N = np.diff(c.curve_off)
+    valid = (tc >= 0) & (tc < c.n_curves)
+    valid[valid] &= N[tc[valid]] % 2 == 0
+    assert (~valid).sum() > 40 and valid.sum() > 300
+    assert np.all(np.isnan(du[~valid])) and np.all(np.isnan(dv[~valid]))
+    worst = 0.0
+    for k in range(c.n_curves):
+        if N[k] % 2:
+            continue
+        sel = np.where(tc == k)[0]
+        s = slice(c.curve_off[k], c.curve_off[k + 1])
+        ou, ov = onear.near_label(c.x[s], c.y[s], c.fx[s], c.fy[s], c.w[s], tx[sel], ty[sel], P=8)
+        sub = synth.CurveSet(*(getattr(c, a)[s] for a in ("x", "y", "nx", "ny", "w", "kappa", "fx", "fy")),
+                             curve_off=np.array([0, s.stop - s.start], np.int32))
+        u1, v1 = oracle.slp(sub, tx[sel], ty[sel])
+        sc = np.hypot(u1 + ou, v1 + ov).max()
+        worst = max(worst, np.hypot(du[sel] - ou, dv[sel] - ov).max() / sc)
+    print(f"valid targets beside invalid ones: worst rel err {worst:.2e}", flush=True)
+    assert worst < 1e-12
+
+
 def test_features_match_oracle(small):
     c, tx, ty, tc, dh, data = small
     X = data.X.cpu().numpy()
