@@ -81,6 +81,56 @@ def test_ragged_sizes(mode):
     _check(prob, mode)
 
 
+def _translated(prob, dx, dy):
+    import dataclasses
+    move = lambda cs: dataclasses.replace(cs, x=cs.x + dx, y=cs.y + dy)
+    trg = dataclasses.replace(prob.trg, x=prob.trg.x + dx, y=prob.trg.y + dy)
+    return dataclasses.replace(prob, ves=move(prob.ves), wall=move(prob.wall), trg=trg)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_translated_channel(mode):
+    """The whole channel moved far from the origin. FP32C forms differences
+    against FP64 origins per tile, so its error must not grow with the
+    coordinates' magnitude; both sides see the same translated inputs."""
+    _check(_translated(synth.make_config(2), 3.0e3, -7.0e2), mode)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_near_touching_vesicles(mode):
+    """Vesicle 1 moved towards vesicle 0 until their nearest nodes are a fifth
+    of a node spacing apart (the near sub-blocks of FP32C, r formed in FP64)."""
+    import dataclasses
+    prob = synth.make_config(2)
+    v, off = prob.ves, prob.ves.curve_off
+    s0, s1 = slice(off[0], off[1]), slice(off[1], off[2])
+    x0, y0, x1, y1 = v.x[s0], v.y[s0], v.x[s1], v.y[s1]
+    h = np.sum(v.w[s0]) / (off[1] - off[0])
+    ux, uy = x0.mean() - x1.mean(), y0.mean() - y1.mean()
+    gap = lambda a: np.sqrt(((x0[:, None] - (x1[None, :] + a * ux)) ** 2 +
+                             (y0[:, None] - (y1[None, :] + a * uy)) ** 2).min())
+    # the first approach to 0.2 h along the line of centres: scan, then bisect
+    steps = np.linspace(0.0, 1.0, 401)
+    k = int(np.argmax([gap(a) < 0.2 * h for a in steps]))
+    assert k > 0
+    lo, hi = steps[k - 1], steps[k]
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if gap(mid) > 0.2 * h else (lo, mid)
+    sx, sy = lo * ux, lo * uy
+    x, y = v.x.copy(), v.y.copy()
+    x[s1] += sx
+    y[s1] += sy
+    tx, ty = prob.trg.x.copy(), prob.trg.y.copy()
+    on1 = prob.trg.ves_curve == 1
+    tx[on1] += sx
+    ty[on1] += sy
+    prob = dataclasses.replace(prob, ves=dataclasses.replace(v, x=x, y=y),
+                               trg=dataclasses.replace(prob.trg, x=tx, y=ty))
+    print(f"nearest node gap {gap(lo) / h:.3f} h", flush=True)
+    _check(prob, mode)
+
+
 def test_single_node_sources_and_free_targets():
     import torch
     import oracle
