@@ -66,6 +66,32 @@ def test_batch_parity_small(small_batch, mode):
     assert worst <= TOL[mode]
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_batch_instances_far_from_the_origin(small_batch, mode):
+    """Instances moved to different places up to 5e4 from the origin (the
+    padding records sit far outside the coordinate range the batch accepts)."""
+    import dataclasses
+    import torch
+    import paper_1510_05616_amd as s2d
+    rng = np.random.default_rng(7)
+    moved = []
+    for p in small_batch[:6]:
+        dx, dy = rng.uniform(-5e4, 5e4, 2)
+        mv = lambda cs: dataclasses.replace(cs, x=cs.x + dx, y=cs.y + dy)
+        moved.append(dataclasses.replace(p, ves=mv(p.ves), wall=mv(p.wall),
+                                         trg=dataclasses.replace(p.trg, x=p.trg.x + dx, y=p.trg.y + dy)))
+    insts = _instances(moved)
+    ws = torch.empty(s2d.stokes2d_batch_workspace_size(mode, insts), dtype=torch.uint8, device="cuda")
+    s2d.stokes2d_batch_eval(mode, insts, ws)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for p, b in zip(moved, insts):
+        ou, ov = _oracle(p)
+        worst = max(worst, rel_err(b.u.cpu().numpy(), b.v.cpu().numpy(), ou, ov))
+    print(f"moved batch mode={mode} worst E={worst:.3e}", flush=True)
+    assert worst <= TOL[mode]
+
+
 def test_batch_replay_rereads_inputs(small_batch):
     import torch
     import paper_1510_05616_amd as s2d

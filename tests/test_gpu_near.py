@@ -49,10 +49,11 @@ def test_upsampled_quadrature_matches_oracle(small):
     assert worst < 1e-12
 
 
-@pytest.mark.parametrize("P,sizes", [(1, (66, 70)), (3, (66, 126)), (5, (64, 98)), (16, (4, 128)), (32, (64,))])
+@pytest.mark.parametrize("P,sizes", [(1, (66, 70)), (3, (66, 126)), (5, (64, 98)), (16, (4, 128)), (32, (64,)),
+                                     (8, (256,))])
 def test_upsampled_quadrature_other_factors(P, sizes):
     """Upsampling factors other than 8, curve sizes with N/2 odd (P N not a
-    multiple of 4) and the largest P N the kernel takes (2048)."""
+    multiple of 4), and the largest N (256) and P N (2048) the kernel takes."""
     import oracle
     from paper_1510_05616_amd import near
     c, tx, ty, tc, dh = synth.make_near_dataset(600, seed=40 + P, per_curve=100, sizes=sizes)
@@ -133,6 +134,19 @@ def test_invalid_targets_and_curves_give_nan():
         worst = max(worst, np.hypot(du[sel] - ou, dv[sel] - ov).max() / sc)
     print(f"valid targets beside invalid ones: worst rel err {worst:.2e}", flush=True)
     assert worst < 1e-12
+
+
+def test_curves_beyond_the_upsampling_limits_give_nan():
+    """Curves of more than 256 nodes, or with P N above 2048, are not
+    upsampled: their targets get NaN, the other curves' targets do not."""
+    from paper_1510_05616_amd import near
+    c, tx, ty, tc, dh = synth.make_near_dataset(400, seed=46, per_curve=100, sizes=(96, 258))
+    N = np.diff(c.curve_off)
+    assert (N == 258).any() and (N == 96).any()
+    for P, big in ((8, N[tc] == 258), (32, N[tc] >= 96)):
+        data = near.NearData(c, tx, ty, tc, mu=1.0, upsample=P)
+        du = data.du.cpu().numpy()
+        assert np.all(np.isnan(du[big])) and np.all(np.isfinite(du[~big])), P
 
 
 def test_features_match_oracle(small):
