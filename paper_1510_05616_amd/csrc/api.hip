@@ -690,7 +690,7 @@ S2D_API int stokes2d_batch_tuned(int mode, int32_t n_inst, const s2d_instance *i
 namespace {
 
 struct NearLayout {
-    size_t up, X, frame, list, count, total;
+    size_t up, X, frame, flag, list, count, total;
 };
 
 NearLayout near_layout(int method, const s2d_curves *c, const s2d_targets *t, int P) {
@@ -703,12 +703,16 @@ NearLayout near_layout(int method, const s2d_curves *c, const s2d_targets *t, in
         off = align256(off + (size_t)t->n * s2d::kNearFeat * sizeof(float));
         L.frame = off;
         off = align256(off + (size_t)t->n * 6 * sizeof(double));
+        // AUTO: per-target decisions, the fallback targets' list and the
+        // compaction's per-workgroup counts
+        L.flag = off;
+        off = align256(off + (size_t)t->n * sizeof(int32_t));
         L.list = off;
         off = align256(off + (size_t)t->n * sizeof(int32_t));
         L.count = off;
-        off = align256(off + sizeof(int32_t));
+        off = align256(off + ((size_t)(t->n + 255) / 256 + 1) * sizeof(int32_t));
     } else {
-        L.frame = L.list = L.count = off;
+        L.frame = L.flag = L.list = L.count = off;
     }
     L.total = std::max<size_t>(off, 256);
     return L;
@@ -760,7 +764,7 @@ S2D_API int near_correct_eval(int method, const s2d_curves *ves, const s2d_targe
         if (e != hipSuccess) return hip_fail(e, "near upsample launch");
     }
     if (method == S2D_NEAR_UPSAMPLE) {
-        e = s2d::near_launch_quad(ves, trg, trg_curve, nullptr, upsample, up, mu, du, dv, st);
+        e = s2d::near_launch_quad(ves, trg, trg_curve, nullptr, nullptr, upsample, up, mu, du, dv, st);
         if (e != hipSuccess) return hip_fail(e, "near quadrature launch");
         return S2D_OK;
     }
@@ -770,12 +774,18 @@ S2D_API int near_correct_eval(int method, const s2d_curves *ves, const s2d_targe
     if (e != hipSuccess) return hip_fail(e, "near features launch");
     const bool autom = method == S2D_NEAR_AUTO;
     // AUTO needs the per-target decisions: the caller's array or the workspace
-    int32_t *flag = used_fallback ? used_fallback : (autom ? (int32_t *)(w + L.list) : nullptr);
+    int32_t *flag = used_fallback ? used_fallback : (autom ? (int32_t *)(w + L.flag) : nullptr);
     e = s2d::near_launch_infer(trg->n, X, frame, (const s2d::NearBlob *)mlp, mu, threshold, autom ? 1 : 0, du, dv,
                                flag, st);
     if (e != hipSuccess) return hip_fail(e, "near MLP launch");
     if (autom) {
-        e = s2d::near_launch_quad(ves, trg, trg_curve, flag, upsample, up, mu, du, dv, st);
+        // the fallback targets, compacted in order, so that the quadrature's
+        // cost follows their number rather than the waves that hold one
+        int32_t *list = (int32_t *)(w + L.list), *cnt = (int32_t *)(w + L.count);
+        e = s2d::near_launch_compact(trg->n, flag, cnt, list, st);
+        if (e != hipSuccess) return hip_fail(e, "near fallback compaction launch");
+        e = s2d::near_launch_quad(ves, trg, trg_curve, list, cnt + (trg->n + 255) / 256, upsample, up, mu, du, dv,
+                                  st);
         if (e != hipSuccess) return hip_fail(e, "near fallback launch");
     }
     return S2D_OK;
@@ -801,7 +811,8 @@ S2D_API int near_upsampled_slp(const s2d_curves *ves, const s2d_targets *trg, co
     double *d = (double *)((char *)ws + L.total);
     hipError_t e = s2d::near_launch_upsample(ves, upsample, up, st);
     if (e != hipSuccess) return hip_fail(e, "near upsample launch");
-    e = s2d::near_launch_quad(ves, trg, trg_curve, nullptr, upsample, up, mu, d, d + trg->n, st, u_up, v_up, u_trap,
+    e = s2d::near_launch_quad(ves, trg, trg_curve, nullptr, nullptr, upsample, up, mu, d, d + trg->n, st, u_up, v_up,
+                              u_trap,
                               v_trap);
     return e == hipSuccess ? S2D_OK : hip_fail(e, "near quadrature launch");
 }

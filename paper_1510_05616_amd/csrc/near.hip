@@ -212,8 +212,9 @@ __device__ __forceinline__ void near_sums(double px, double py, int lo, int N, i
         slp64_acc(px, py, fr[4 * k], fr[4 * k + 1], fr[4 * k + 2], fr[4 * k + 3], ltab, s[4], s[5], s[6], s[7]);
 }
 
-// Delta for the 64 targets q = 64 blockIdx.x + lane (only those with
-// mask[q] == 1 when mask != NULL).  The four waves of the workgroup take the
+// Delta for the 64 targets q = 64 blk + lane, or, with an index list, for
+// targets list[q], q < *list_len (the list keeps the targets' order, so its
+// waves stay on one curve).  The four waves of the workgroup take the
 // same targets and a quarter of the sources each; wave 0 adds the other
 // three's partial sums in fixed order.  Short workgroups keep the launch
 // balanced across curves of different sizes.  When every live target of the
@@ -221,7 +222,8 @@ __device__ __forceinline__ void near_sums(double px, double py, int lo, int N, i
 // wave-uniform and their loads go through the scalar path.
 constexpr int kQuadParts = 4;
 
-__global__ __launch_bounds__(64 * kQuadParts) void near_quad(int64_t n_trg, const int32_t *__restrict__ mask,
+__global__ __launch_bounds__(64 * kQuadParts) void near_quad(int64_t n_trg, const int32_t *__restrict__ list,
+                                                             const int32_t *__restrict__ list_len,
                                                              const double *__restrict__ tx,
                                                              const double *__restrict__ ty,
                                                              const int32_t *__restrict__ tc,
@@ -233,17 +235,22 @@ __global__ __launch_bounds__(64 * kQuadParts) void near_quad(int64_t n_trg, cons
                                                              double *__restrict__ vc) {
     __shared__ __attribute__((aligned(16))) double ltab[kLogTabWords];
     __shared__ double partial[kQuadParts - 1][8][kWave];
+    // targets to process (the list's length is known on the device only;
+    // workgroups past it leave before any barrier)
+    const int64_t n = list ? (int64_t)*list_len : n_trg;
+    const unsigned nb = (unsigned)((n + kWave - 1) / kWave);
+    if (blockIdx.x >= nb) return;
     fill_log_table(ltab);
     const int lane = threadIdx.x & (kWave - 1);
     const int part = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
     // workgroups are dispatched round-robin over the 8 XCDs; XCD r takes a
     // contiguous run of target groups, so the 3-4 workgroups of one curve
     // share that XCD's L2 copy of the curve's records
-    const unsigned nb = gridDim.x, r = blockIdx.x % 8, per = nb / 8, rem = nb % 8;
+    const unsigned r = blockIdx.x % 8, per = nb / 8, rem = nb % 8;
     const unsigned blk = (r < rem ? r * (per + 1) : rem * (per + 1) + (r - rem) * per) + blockIdx.x / 8;
     const int64_t q = (int64_t)blk * kWave + lane;
-    const bool live = q < n_trg && (!mask || mask[q] == 1);
-    const int64_t i = live ? q : 0;
+    const bool live = q < n;
+    const int64_t i = live ? (list ? (int64_t)list[q] : q) : 0;
     const int c = live ? tc[i] : -1;
     const int lo = (c >= 0 && c < n_curves) ? off[c] : 0;
     const int N = (c >= 0 && c < n_curves) ? off[c + 1] - lo : 0;
@@ -288,6 +295,71 @@ __global__ __launch_bounds__(64 * kQuadParts) void near_quad(int64_t n_trg, cons
         uc[i] = pref * (-0.5 * s[0] + s[2]);
         vc[i] = pref * (-0.5 * s[1] + s[3]);
     }
+}
+
+// Order-keeping compaction of the targets with flag == 1 (AUTO's fallback):
+// per-workgroup counts, one exclusive scan, then each workgroup writes its
+// targets' indices at its offset in target order.
+constexpr int kCompactBlock = 256;
+
+__device__ __forceinline__ uint64_t flag_ballot(int64_t n, const int32_t *__restrict__ flag, int64_t i) {
+    return __ballot(i < n && flag[i] == 1);
+}
+
+__global__ __launch_bounds__(kCompactBlock) void near_compact_count(int64_t n, const int32_t *__restrict__ flag,
+                                                                    int32_t *__restrict__ cnt) {
+    __shared__ int wsum[kCompactBlock / kWave];
+    const int64_t i = (int64_t)blockIdx.x * kCompactBlock + threadIdx.x;
+    const uint64_t b = flag_ballot(n, flag, i);
+    if ((threadIdx.x & (kWave - 1)) == 0) wsum[threadIdx.x / kWave] = __popcll(b);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int s = 0;
+        for (int w = 0; w < kCompactBlock / kWave; ++w) s += wsum[w];
+        cnt[blockIdx.x] = s;
+    }
+}
+
+// exclusive scan of cnt[0 .. nb) in place, total in cnt[nb]; one workgroup
+// of 1024 threads, each over a contiguous segment
+__global__ __launch_bounds__(1024) void near_compact_scan(int64_t nb, int32_t *__restrict__ cnt) {
+    __shared__ int64_t part[1024];
+    const int64_t seg = (nb + 1023) / 1024;
+    const int64_t b0 = min((int64_t)threadIdx.x * seg, nb), b1 = min(b0 + seg, nb);
+    int64_t s = 0;
+    for (int64_t b = b0; b < b1; ++b) s += cnt[b];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t run = 0;
+        for (int k = 0; k < 1024; ++k) {
+            const int64_t v = part[k];
+            part[k] = run;
+            run += v;
+        }
+        cnt[nb] = (int32_t)run;
+    }
+    __syncthreads();
+    int64_t run = part[threadIdx.x];
+    for (int64_t b = b0; b < b1; ++b) {
+        const int32_t v = cnt[b];
+        cnt[b] = (int32_t)run;
+        run += v;
+    }
+}
+
+__global__ __launch_bounds__(kCompactBlock) void near_compact_scatter(int64_t n, const int32_t *__restrict__ flag,
+                                                                      const int32_t *__restrict__ cnt,
+                                                                      int32_t *__restrict__ list) {
+    __shared__ int wsum[kCompactBlock / kWave];
+    const int64_t i = (int64_t)blockIdx.x * kCompactBlock + threadIdx.x;
+    const uint64_t b = flag_ballot(n, flag, i);
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    if (lane == 0) wsum[w] = __popcll(b);
+    __syncthreads();
+    int base = cnt[blockIdx.x];
+    for (int k = 0; k < w; ++k) base += wsum[k];
+    if ((b >> lane) & 1) list[base + __popcll(b & ((1ull << lane) - 1))] = (int32_t)i;
 }
 
 // ---------------------------------------------------------------------------
@@ -1030,14 +1102,24 @@ hipError_t near_launch_upsample(const s2d_curves *c, int P, double *up, hipStrea
     return hipGetLastError();
 }
 
-hipError_t near_launch_quad(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, const int32_t *mask,
-                            int P, const double *up, double mu, double *du, double *dv, hipStream_t st, double *uf,
-                            double *vf, double *uc, double *vc) {
+hipError_t near_launch_quad(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, const int32_t *list,
+                            const int32_t *list_len, int P, const double *up, double mu, double *du, double *dv,
+                            hipStream_t st, double *uf, double *vf, double *uc, double *vc) {
     if (t->n <= 0) return hipSuccess;
     const unsigned g = grid_for(t->n, kWave);
-    hipLaunchKernelGGL(near_quad, dim3(g), dim3(kWave * kQuadParts), 0, st, t->n, mask, t->x, t->y, tc, c->curve_off,
+    hipLaunchKernelGGL(near_quad, dim3(g), dim3(kWave * kQuadParts), 0, st, t->n, list, list_len, t->x, t->y, tc,
+                       c->curve_off,
                        c->n_curves, c->n_nodes, P, up, 1.0 / (4.0 * M_PI * mu), du,
                        dv, uf, vf, uc, vc);
+    return hipGetLastError();
+}
+
+hipError_t near_launch_compact(int64_t n, const int32_t *flag, int32_t *cnt, int32_t *list, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t nb = (n + kCompactBlock - 1) / kCompactBlock;
+    hipLaunchKernelGGL(near_compact_count, dim3((unsigned)nb), dim3(kCompactBlock), 0, st, n, flag, cnt);
+    hipLaunchKernelGGL(near_compact_scan, dim3(1), dim3(1024), 0, st, nb, cnt);
+    hipLaunchKernelGGL(near_compact_scatter, dim3((unsigned)nb), dim3(kCompactBlock), 0, st, n, flag, cnt, list);
     return hipGetLastError();
 }
 

@@ -34,9 +34,15 @@ struct NearBlob {
 constexpr int kNearBlobWork = kNearFeat + 64 * kNearFeat / 2 + 2 * 64 * 32 + 2 * 32 + 64;
 
 hipError_t near_launch_upsample(const s2d_curves *c, int P, double *up, hipStream_t st);
-hipError_t near_launch_quad(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, const int32_t *mask,
-                            int P, const double *up, double mu, double *du, double *dv, hipStream_t st,
-                            double *uf = nullptr, double *vf = nullptr, double *uc = nullptr, double *vc = nullptr);
+// list / list_len (device): when list != NULL only targets list[q],
+// q < *list_len, are evaluated; list_len must be NULL otherwise.
+hipError_t near_launch_quad(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, const int32_t *list,
+                            const int32_t *list_len, int P, const double *up, double mu, double *du, double *dv,
+                            hipStream_t st, double *uf = nullptr, double *vf = nullptr, double *uc = nullptr,
+                            double *vc = nullptr);
+// the targets with flag == 1, in order, into list; their number into
+// cnt[ceil(n / 256)] (cnt: ceil(n / 256) + 1 ints of scratch)
+hipError_t near_launch_compact(int64_t n, const int32_t *flag, int32_t *cnt, int32_t *list, hipStream_t st);
 hipError_t near_launch_features(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, float *X,
                                 double *frame, hipStream_t st);
 hipError_t near_launch_scale_labels(int64_t n, const double *du, const double *dv, const double *frame, double mu,

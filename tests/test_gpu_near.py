@@ -293,6 +293,37 @@ def test_auto_with_zero_threshold_is_the_upsampled_result(small):
     assert torch.all(fb == 0)
 
 
+def test_auto_mixed_decisions_match_each_route(small):
+    """Bins alternate between the network, no correction and the fallback, so
+    the three decisions interleave within waves. Fallback targets (compacted
+    in order before the quadrature) must equal the upsampled result bit for
+    bit, network targets the MLP route's result, the rest zero."""
+    import torch
+    from paper_1510_05616_amd import near
+    c, tx, ty, tc, dh, data = small
+    p32 = torch.as_tensor(near.dict_to_params(_rand_params(3)).astype(np.float32), device="cuda")
+    k = torch.arange(near.N_BINS, device="cuda")
+    bound = torch.where(k % 3 == 0, 1e-3, 10.0).float()
+    bound_zero = torch.where(k % 3 == 1, 1e-3, 10.0).float()
+    blob = torch.zeros(near.near_mlp_blob_size(), dtype=torch.uint8, device="cuda")
+    near.near_mlp_pack(p32, bound, near.N_BINS, near.BIN_LO, near.BIN_W, blob, bound_zero=bound_zero)
+    sc = (data.frame[:, 4] * data.frame[:, 5]).max().item() / (4 * math.pi)
+    du, dv = torch.empty(data.n, dtype=torch.float64, device="cuda"), torch.empty(data.n, dtype=torch.float64,
+                                                                                   device="cuda")
+    fb = torch.full((data.n,), -1, dtype=torch.int32, device="cuda")
+    near.near_correct_eval(near.S2D_NEAR_AUTO, data.curves, data.trg, data.tc, 8, blob, 2e-3 * sc, 1.0, du, dv, fb)
+    mu_, mv_ = torch.empty_like(du), torch.empty_like(dv)
+    near.near_correct_eval(near.S2D_NEAR_MLP, data.curves, data.trg, data.tc, 8, blob, 0.0, 1.0, mu_, mv_)
+    torch.cuda.synchronize()
+    counts = [int((fb == j).sum()) for j in range(3)]
+    print(f"network/fallback/none {counts}", flush=True)
+    assert min(counts) > 100 and sum(counts) == data.n
+    f1, f0, f2 = fb == 1, fb == 0, fb == 2
+    assert torch.equal(du[f1], data.du[f1]) and torch.equal(dv[f1], data.dv[f1])
+    assert torch.equal(du[f0], mu_[f0]) and torch.equal(dv[f0], mv_[f0])
+    assert torch.all(du[f2] == 0) and torch.all(dv[f2] == 0)
+
+
 def test_training_gains_over_plain_trapezoid():
     import torch
     from paper_1510_05616_amd import near
