@@ -179,7 +179,7 @@ S2D_API int stokes2d_slp_traction_eval(int mode, const s2d_curves *src, const s2
 
 /* ---------------------------------------------------------------------------
  * Periodization system of one channel cell (Section 2.2, Eqs. (urep)-(bsys);
- * Nystrom discretisation, Section 2.3; block solve, Section 5.1).
+ * Nystrom discretisation, Section 2.3; block solve, Section 4.1).
  *
  * The velocity in the cell is the wall double layer of density tau summed
  * over the images |n| <= 1 plus M Stokeslets c_m at proxy points on a circle
@@ -290,7 +290,8 @@ S2D_API int stokes2d_batch_tuned(int mode, int32_t n_inst, const s2d_instance *i
  *
  * For a target x near closed source curve c (given by trg_curve[i]), the
  * plain N-node trapezoid single layer of curve c loses accuracy (the paper
- * notes the trapezoid rule's near-curve error band, Section 4.1).  The
+ * notes the trapezoid rule's near-curve error band: Section 5 footnote,
+ * Section 5.1 error figure).  The
  * correction is Delta(x) = u_P(x) - u_1(x): the single layer of curve c
  * evaluated on P*N nodes obtained by FFT upsampling of the curve and its
  * density (the paper represents curves in a Fourier basis), minus the N-node
@@ -372,7 +373,7 @@ S2D_API int near_mlp_pack(const float *params, const float *bound, const float *
  *
  * The paper evaluates the wall double layer at vesicles near a wall by the
  * plain trapezoid rule and leaves its close evaluation to future work
- * (Section 4.1 footnote, Conclusions).  These entry points supply the
+ * (Section 5 footnote; Section 6).  These entry points supply the
  * upsampled-quadrature correction for it, in the form the vesicles' near
  * field uses: Delta = D_P - D_1, the double layer of the P-times refined
  * wall minus that of the given one.

@@ -1,6 +1,6 @@
 /*
  * stokes2d_vesicle.h -- C ABI of libstokes2d.so for the vesicle time step
- * (Marple, Barnett, Gillman, Veerapaneni, arXiv 1510.05616, Section 3.3 and
+ * (Marple, Barnett, Gillman, Veerapaneni, arXiv 1510.05616, Section 3.2 and
  * Algorithm 1, steps 2 and 6-9; Appendices A-C).
  *
  * A vesicle set is n_curves closed curves, curve c owning the global nodes

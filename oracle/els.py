@@ -16,7 +16,7 @@ term) and the velocity and traction matching between the side walls L and R
 discretised by Nystrom (Section 2.3): the trapezoid weights w_j multiply the
 kernel, the n = 0 self term is the diagonal limit -(kappa/2 pi) t t^T w, the
 side walls carry K Gauss-Legendre collocation heights (no weights).  The
-system is solved as in Section 5.1: S = Q - C A^-1 B,
+system is solved as in Section 4.1: S = Q - C A^-1 B,
 c = S^+ (g - C A^-1 v), tau = A^-1 (v - B c), with S^+ the pseudo-inverse.
 
 Layout: every 2-vector is stored interleaved (x, y) per node; unknowns are
@@ -179,7 +179,7 @@ RCOND = 1e-8
 
 
 def solve(A, B, C, Q, v, g, rcond=RCOND):
-    """Schur-complement solve of Section 5.1; returns (tau, c)."""
+    """Schur-complement solve of Section 4.1; returns (tau, c)."""
     Ainv_v = np.linalg.solve(A, v)
     Ainv_B = np.linalg.solve(A, B)
     S = Q - C @ Ainv_B

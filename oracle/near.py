@@ -11,12 +11,13 @@ TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
   layer of one curve evaluated with the P-times upsampled trapezoid rule minus
   the plain N-node trapezoid rule (no images, no self term).  The paper
   notes that the trapezoid rule loses accuracy for targets near a curve
-  (Section 4.1 footnote and the error band of its serpentine-channel figure).
+  (Section 5 footnote, and the error band of its serpentine-channel figure in
+  Section 5.1).
 * Spectral upsampling of one period of a periodic channel wall (the same
   trigonometric interpolation applied to the wall's periodic parts), for the
   near-wall correction of the double layer: Delta = D_P - D_1 with both sums
   over the whole wall and its images, the close evaluation the paper names as
-  future work for the walls (Section 4.1 footnote, Conclusions).
+  future work for the walls (Section 5 footnote; Section 6).
 * Target features and the MLP (3 hidden layers of width 64, tanh-form GELU)
   forward and backward passes, written out plainly.
 """

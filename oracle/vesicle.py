@@ -56,7 +56,7 @@ def geometry(x, y, off):
 
 
 def d_s(v, g):
-    """Arc-length derivative D_s v = D_alpha v / |x_alpha| (Section 3.3)."""
+    """Arc-length derivative D_s v = D_alpha v / |x_alpha| (Section 3.2)."""
     return d_alpha(v, g.curve_off) / g.sp
 
 

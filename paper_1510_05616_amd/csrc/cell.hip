@@ -1,6 +1,6 @@
 // Periodization system of one channel cell on the GPU (Section 2.2,
 // Eqs. (urep)-(bsys); Nystrom discretisation, Section 2.3; block solve,
-// Section 5.1).
+// Section 4.1).
 //
 // Unknowns: the double-layer density tau at the N wall nodes (interleaved
 // (x, y) per node) and the coefficients c of M proxy Stokeslets on a circle

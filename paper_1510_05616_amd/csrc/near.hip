@@ -2,9 +2,9 @@
 // spacings of a closed curve.
 //
 // The periodic trapezoid rule loses accuracy for targets close to a curve
-// (the paper notes this for the channel walls, Section 4.1 footnote and the
-// error band of its serpentine-channel figure, and uses a dedicated close
-// evaluation scheme for near vesicle pairs, Section 3.3).  Here the
+// (the paper notes this for the channel walls in a footnote of Section 5 and
+// in the error band of its serpentine-channel figure, Section 5.1, and uses a
+// dedicated close evaluation scheme for near vesicle pairs, Section 3.2).  Here the
 // correction Delta = u_P(x) - u_1(x) of one curve's single layer is computed
 // either by FFT-upsampled quadrature (the reference and fallback) or by a
 // small MLP that predicts it from local features.

@@ -1,4 +1,4 @@
-// The vesicle time step (Section 3.3; Algorithm 1, steps 2 and 6-9;
+// The vesicle time step (Section 3.2; Algorithm 1, steps 2 and 6-9;
 // Appendices A-C): membrane forces, the semi-implicit step system with the
 // arc-length correction solved by restarted GMRES, the update, the area
 // correction and the reparameterization.

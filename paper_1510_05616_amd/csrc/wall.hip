@@ -1,6 +1,6 @@
 // Spectral upsampling of periodic channel walls, the first step of the walls'
 // close evaluation (the paper leaves close evaluation of the wall double
-// layer to future work: Section 4.1 footnote, Conclusions).
+// layer to future work: Section 5 footnote; Section 6).
 //
 // Each wall curve is one period of a d-periodic wall with N (even, >= 4)
 // nodes equispaced in its parameter t in [0, 2 pi), advancing by s d in x

@@ -313,7 +313,7 @@ def make_channel(n_wall: int, n_side: int, profile: str = "sin1", d: float = 2 *
 def poiseuille(X, Y, alpha, mu):
     """Manufactured Stokes flow u = (alpha y^2, 0), p = 2 alpha mu x, with a
     pressure gain of 2 alpha mu d per period d (the paper's periodization
-    test, Section 4.1, writes p = alpha mu x, which does not satisfy
+    test, Section 5, writes p = alpha mu x, which does not satisfy
     -mu Lap u + grad p = 0; the factor 2 is restored)."""
     return np.stack([alpha * np.asarray(Y) ** 2, np.zeros_like(np.asarray(Y, float))], -1), \
         2 * alpha * mu * np.asarray(X)

@@ -1,6 +1,6 @@
 """Shared helpers for the tests: run the GPU path through the C ABI on a
 synthetic problem, run the oracle on the same inputs, and compare them with
-the paper's relative error (Section 4.1: max over targets of the velocity
+the paper's relative error (Section 5: max over targets of the velocity
 error norm divided by the max velocity norm), per target class."""
 from __future__ import annotations
 

@@ -1,7 +1,7 @@
 """GPU checks of the periodization system of one channel cell: the four
 blocks filled on the GPU against the oracle's dense assembly, and the
 factored solve (rocSOLVER LU, rocBLAS GEMM, SVD pseudo-inverse) reproducing
-the Poiseuille flow of the paper's periodization test (Section 4.1) and the
+the Poiseuille flow of the paper's periodization test (Section 5) and the
 oracle's solution."""
 import numpy as np
 import pytest

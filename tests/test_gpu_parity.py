@@ -1,7 +1,7 @@
 """GPU parity: the HIP path through the C ABI against the FP64 oracle, element
 by element on the same seeded inputs.
 
-Tolerances (relative error E of Section 4.1, per target class and per part):
+Tolerances (relative error E of Section 5, per target class and per part):
 FP64 mode 1e-12, FP32C mode 1e-6.  Full-size (config 3, 128,064 targets x
 128,000 sources x 3 images) runs the GPU on every target in the same launch
 configuration the benchmark times, and checks a seeded sample of targets that

@@ -8,7 +8,7 @@
   * the assembled blocks act as the independently pinned pair sums of the C
     oracle (double layer with the diagonal limit and the -1/2 jump on the
     walls, Stokeslets from the proxies, the side-wall differences);
-  * the solved system reproduces a Poiseuille flow (Section 4.1 test: alpha =
+  * the solved system reproduces a Poiseuille flow (Section 5 test: alpha =
     0.2, mu = 0.7, d = 2 pi, points (0.8, 0), (3.2, 0), (4.8, 0)) to about
     1e-11, converging as N, K and M grow.
 """
