@@ -247,9 +247,6 @@ typedef struct s2d_instance {
     double d, mu;
     double *u, *v;               /* [n] outputs (written, not accumulated) */
 } s2d_instance;
-/* Batched instances keep every node and target coordinate below 1e6 in
- * magnitude (the library pads each instance's sources with zero-density
- * records at 1e7). */
 
 /* Workspace bytes for stokes2d_batch_eval over the host array inst[n_inst]
  * (0 on bad arguments).  The size covers every tile shape the tuner tries. */

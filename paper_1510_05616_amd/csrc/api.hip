@@ -89,42 +89,51 @@ s2d::Plan make_plan(int op, int mode, const s2d_curves *s, const s2d_targets *t,
     Plan p{};
     p.op = op;
     p.mode = mode;
-    // One target per lane in both modes; the grid over-decomposes the work
-    // to about 128 waves per SIMD (16x the resident waves of the FP32C
-    // kernel) so that tiles of unequal cost even out.  S2D_TPT (1, 2 or 4)
-    // and S2D_SPLITS override the shape for tuning sweeps.
-    static const int env_tpt = [] {
-        const char *e = std::getenv("S2D_TPT");
+    p.tpt = 1;
+    // Launch shape: one target tile (64 targets) per workgroup of W waves,
+    // each wave a source split, and G split groups (workgroups) per tile.
+    // G = 1 when the source records fit comfortably in one XCD's L2 (4 MB)
+    // and the tiles alone give at least two rounds of 8 waves per SIMD;
+    // otherwise G grows to fill the chip (few targets, many sources), and is
+    // a multiple of 8 when the records exceed the L2 budget, so that every
+    // XCD streams only its own groups' sources.  S2D_WAVES and S2D_GROUPS
+    // override the shape for tuning sweeps.
+    static const int env_waves = [] {
+        const char *e = std::getenv("S2D_WAVES");
         const int v = e ? std::atoi(e) : 0;
-        return (v == 1 || v == 2 || v == 4) ? v : 0;
+        return (v >= 1 && v <= kMaxPairWaves) ? v : 0;
     }();
-    static const int env_splits = [] {
-        const char *e = std::getenv("S2D_SPLITS");
+    static const int env_groups = [] {
+        const char *e = std::getenv("S2D_GROUPS");
         return e ? std::max(0, std::atoi(e)) : 0;
     }();
-    p.tpt = (env_tpt && op <= S2D_OP_DLP) ? env_tpt : 1;      // pressures and traction: one target per lane
-    constexpr int64_t kWavesPerSimd = 128;
+    constexpr size_t kL2Budget = (size_t)3 << 20;
     p.n_src = s->n_nodes;
     p.n_trg = t->n;
     p.n_sb = (p.n_src + kSuperBlock - 1) / kSuperBlock;
-    p.n_tiles = (p.n_trg + (int64_t)kWave * p.tpt - 1) / ((int64_t)kWave * p.tpt);
+    p.n_tiles = (p.n_trg + kWave - 1) / kWave;
     if (p.n_sb > 0 && p.n_tiles > 0) {
-        const int64_t want_waves = (int64_t)cus * 4 * kWavesPerSimd;
-        int64_t ns = env_splits ? env_splits : (want_waves + p.n_tiles - 1) / p.n_tiles;
-        if (ns >= 8 && p.n_sb >= 8) {
-            // XCD-aligned: a multiple of 8 splits keeps every XCD on its own
-            // eighth of the source records; trailing splits may be short or
-            // empty (an empty split writes zero partials)
-            ns = std::min<int64_t>((ns + 7) / 8 * 8, std::min<int64_t>(p.n_sb / 8 * 8, 4096));
-            p.sb_per_split = (p.n_sb + ns - 1) / ns;
-            p.n_splits = (int)ns;
-        } else {
-            ns = std::max<int64_t>(1, std::min<int64_t>(ns, p.n_sb));
-            p.sb_per_split = (p.n_sb + ns - 1) / ns;
-            p.n_splits = (int)((p.n_sb + p.sb_per_split - 1) / p.sb_per_split);
-        }
-        p.n_blocks = (int64_t)p.n_splits * ((p.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock);
+        const bool fits = (size_t)p.n_sb * kSuperBlock * rec_bytes(op, mode) <= kL2Budget;
+        const int64_t fill = (int64_t)cus * 4 * 16;
+        const int64_t gmax = std::max<int64_t>(1, (p.n_sb + 7) / 8);
+        int64_t G = 1;
+        if (!(fits && p.n_tiles * kMaxPairWaves >= fill))
+            G = std::min<int64_t>(std::max<int64_t>(1, (fill + p.n_tiles * kMaxPairWaves - 1) /
+                                                           (p.n_tiles * kMaxPairWaves)), gmax);
+        if (!fits && gmax >= 8) G = std::min<int64_t>((std::max<int64_t>(G, 8) + 7) / 8 * 8, gmax / 8 * 8);
+        G = std::min<int64_t>(G, 65536);
+        if (env_groups) G = std::min<int64_t>(env_groups, p.n_sb);
+        // W: the full width, or fewer when the group has fewer superblocks.
+        int W = (int)std::min<int64_t>(kMaxPairWaves, (p.n_sb + G - 1) / G);
+        if (env_waves) W = env_waves;
+        p.waves = W;
+        p.n_groups = (int)G;
+        p.n_splits = (int)(W * G);
+        p.sb_per_split = (p.n_sb + p.n_splits - 1) / p.n_splits;
+        p.n_blocks = p.n_tiles * G;
     } else {
+        p.waves = 1;
+        p.n_groups = 1;
         p.sb_per_split = 0;
         p.n_splits = 0;
         p.n_blocks = 0;
@@ -142,7 +151,7 @@ s2d::Plan make_plan(int op, int mode, const s2d_curves *s, const s2d_targets *t,
     p.off_sbsum = off;
     if (op == S2D_OP_SLP && mode == S2D_FP32C) off = align256(off + (size_t)p.n_sb * 2 * sizeof(double));
     p.off_part = off;
-    off = align256(off + (size_t)p.n_splits * 2 * (size_t)p.n_trg * sizeof(double));
+    if (p.n_groups > 1) off = align256(off + (size_t)p.n_groups * 2 * (size_t)p.n_trg * sizeof(double));
     p.off_self = off;
     p.off_kress = off;
     if (op == S2D_OP_SLP && t->on_curve && p.n_trg > 0) {
@@ -229,6 +238,7 @@ int eval(int op, int mode, const s2d_curves *src, const s2d_targets *trg, double
     a.n_trg = p.n_trg;
     a.n_tiles = p.n_tiles;
     a.n_splits = p.n_splits;
+    a.n_groups = p.n_groups;
     a.sb_per_split = p.sb_per_split;
     a.n_sb = p.n_sb;
     a.d = d;
@@ -238,28 +248,10 @@ int eval(int op, int mode, const s2d_curves *src, const s2d_targets *trg, double
     a.tnx = tnx;
     a.tny = tny;
     a.rec64 = (char *)ws + p.off_rec64;
-    if (p.n_blocks > 0) {
-        ProfEvent pe{op, nullptr, nullptr};
-        if (g_prof_on) {
-            std::lock_guard<std::mutex> lk(g_mu);
-            if (hipEventCreate(&pe.a) == hipSuccess && hipEventCreate(&pe.b) == hipSuccess) {
-                hipEventRecord(pe.a, st);
-            } else {
-                pe.a = pe.b = nullptr;
-            }
-        }
-        e = launch_pair(p, a, st);
-        if (e != hipSuccess) return hip_fail(e, "pair launch");
-        if (pe.a) {
-            hipEventRecord(pe.b, st);
-            std::lock_guard<std::mutex> lk(g_mu);
-            g_prof.push_back(pe);
-        }
-    }
     FinalArgs f{};
     f.part = a.part;
     f.self = p.self ? (const double *)((char *)ws + p.off_self) : nullptr;
-    f.n_splits = p.n_splits;
+    f.n_parts = p.n_blocks > 0 ? p.n_groups : 0;
     f.n_trg = p.n_trg;
     f.n_src = p.n_src;
     switch (op) {
@@ -285,6 +277,26 @@ int eval(int op, int mode, const s2d_curves *src, const s2d_targets *trg, double
     f.kappa = src->kappa;
     f.fx = src->fx;
     f.fy = src->fy;
+    if (p.n_blocks > 0) {
+        ProfEvent pe{op, nullptr, nullptr};
+        if (g_prof_on) {
+            std::lock_guard<std::mutex> lk(g_mu);
+            if (hipEventCreate(&pe.a) == hipSuccess && hipEventCreate(&pe.b) == hipSuccess) {
+                hipEventRecord(pe.a, st);
+            } else {
+                pe.a = pe.b = nullptr;
+            }
+        }
+        e = launch_pair(p, a, f, st);
+        if (e != hipSuccess) return hip_fail(e, "pair launch");
+        if (pe.a) {
+            hipEventRecord(pe.b, st);
+            std::lock_guard<std::mutex> lk(g_mu);
+            g_prof.push_back(pe);
+        }
+    }
+    // the pair kernel finishes the targets itself when it has one split group
+    if (p.n_blocks > 0 && p.n_groups == 1) return S2D_OK;
     e = launch_final(p, f, st);
     if (e != hipSuccess) return hip_fail(e, "finalize launch");
     return S2D_OK;

@@ -99,14 +99,14 @@ __global__ __launch_bounds__(256) void batch_prep(BatchTables t, int op) {
     const s2d_curves &s = I.src[op];
     void *rec = (void *)I.pa[op].rec;
     if (PREC == S2D_FP64) {
-        if (op == 0) prep_one64<S2D_OP_SLP>(j, s.n_nodes, s.x, s.y, s.nx, s.ny, s.w, s.fx, s.fy, rec, kFarPad);
-        else prep_one64<S2D_OP_DLP>(j, s.n_nodes, s.x, s.y, s.nx, s.ny, s.w, s.fx, s.fy, rec, kFarPad);
+        if (op == 0) prep_one64<S2D_OP_SLP>(j, s.n_nodes, s.x, s.y, s.nx, s.ny, s.w, s.fx, s.fy, rec);
+        else prep_one64<S2D_OP_DLP>(j, s.n_nodes, s.x, s.y, s.nx, s.ny, s.w, s.fx, s.fy, rec);
     } else {
         SubInfo *sub = (SubInfo *)I.pa[op].sub;
         if (op == 0)
-            prep_sub32<S2D_OP_SLP>(j / kSubBlock, s.n_nodes, s.x, s.y, s.nx, s.ny, s.w, s.fx, s.fy, rec, sub, kFarPad);
+            prep_sub32<S2D_OP_SLP>(j / kSubBlock, s.n_nodes, s.x, s.y, s.nx, s.ny, s.w, s.fx, s.fy, rec, sub);
         else
-            prep_sub32<S2D_OP_DLP>(j / kSubBlock, s.n_nodes, s.x, s.y, s.nx, s.ny, s.w, s.fx, s.fy, rec, sub, kFarPad);
+            prep_sub32<S2D_OP_DLP>(j / kSubBlock, s.n_nodes, s.x, s.y, s.nx, s.ny, s.w, s.fx, s.fy, rec, sub);
     }
 }
 
@@ -164,7 +164,7 @@ __global__ __launch_bounds__(kBlock) void batch_pair(BatchTables t) {
         // the tables were uploaded before the launch: read them as invariant
         const BatchItem w = load_ro<BatchItem>(t.items, first + k);
         const PairArgs a = load_ro<PairArgs>(&t.inst[w.inst].pa[OP], 0);
-        pair_tile<OP, PREC, TPT>(a, w.tile, w.split, lane, ltab);
+        pair_tile<OP, PREC, TPT, 3>(a, w.tile, w.split, lane, ltab);    // images -1, 0, 1
     }
 }
 
@@ -524,7 +524,6 @@ int build_plan(BatchPlan &P, int mode, int32_t n_inst, const s2d_instance *inst,
             a.img_lo = -1;
             a.img_hi = 1;
             a.part = (double *)(db + data + g.off_part[op]);
-            a.pad_far = 1;
             for (int64_t tl = 0; tl < g.n_tiles; ++tl) {
                 const int64_t act = std::min<int64_t>((int64_t)kWave * c.tpt, n - tl * kWave * c.tpt);
                 for (int64_t sp = 0; sp < g.n_splits[op]; ++sp) {

@@ -3,11 +3,13 @@
 // curve data into the per-source records the pair kernels stream, with the
 // trapezoid weight folded in (g = w f for the single layer, nu = w n for the
 // double layer; Section 2.3 Nystrom discretisation), zero-density records
-// padding the last superblock (at coordinate `pad`: the batched path puts them
-// at kFarPad so that they can be summed like real sources, contributing
-// exactly zero), and, for the FP32 single layer, each superblock's FP64
-// density sum (used to add back the log of the superblock's reference
-// distance).
+// padding the last superblock, and, for the FP32 single layer, each
+// superblock's FP64 density sum (used to add back the log of the superblock's
+// reference factor).  A padding record sits at the last real source (n_src
+// >= 1 whenever there is a superblock): its distance to any target is that of
+// a real source, so its terms are finite and exactly zero, and the ragged
+// superblock is summed like a full one.  (The one target it coincides with at
+// image 0 is that source's own node, whose superblock the exclusion masks.)
 #include "s2d_internal.h"
 
 namespace s2d {
@@ -18,9 +20,9 @@ __device__ __forceinline__ void prep_one64(int64_t j, int64_t n_src, const doubl
                                            const double *__restrict__ y, const double *__restrict__ nx,
                                            const double *__restrict__ ny, const double *__restrict__ w,
                                            const double *__restrict__ fx, const double *__restrict__ fy,
-                                           void *rec_out, double pad = 0.0) {
+                                           void *rec_out) {
     const bool v = j < n_src;
-    const double X = v ? x[j] : pad, Y = v ? y[j] : pad;
+    const double X = v ? x[j] : x[n_src - 1], Y = v ? y[j] : y[n_src - 1];
     const double W = v ? w[j] : 0.0;
     const double FX = v ? fx[j] : 0.0, FY = v ? fy[j] : 0.0;
     if (slp_sources(OP)) {
@@ -39,10 +41,10 @@ __device__ __forceinline__ void prep_sub32(int64_t u, int64_t n_src, const doubl
                                            const double *__restrict__ y, const double *__restrict__ nx,
                                            const double *__restrict__ ny, const double *__restrict__ w,
                                            const double *__restrict__ fx, const double *__restrict__ fy,
-                                           void *rec_out, SubInfo *sub, double pad = 0.0) {
+                                           void *rec_out, SubInfo *sub) {
     const int64_t j0 = u * kSubBlock;
     const int64_t nv = max((int64_t)0, min((int64_t)kSubBlock, n_src - j0));
-    double ox = 0.0, oy = 0.0, r2 = 0.0;
+    double ox = x[n_src - 1], oy = y[n_src - 1], r2 = 0.0;      // origin of an all-padding sub-block
     if (nv > 0) {
         const int64_t jm = j0 + nv / 2;
         ox = x[jm];
@@ -55,15 +57,12 @@ __device__ __forceinline__ void prep_sub32(int64_t u, int64_t n_src, const doubl
     sub[u] = SubInfo{ox, oy, kFarRadii * kFarRadii * r2};
     for (int64_t j = j0; j < j0 + kSubBlock; ++j) {
         const bool v = j < n_src;
-        const double X = v ? x[j] : pad, Y = v ? y[j] : pad;
+        const double X = v ? x[j] : x[n_src - 1], Y = v ? y[j] : y[n_src - 1];
         const double W = v ? w[j] : 0.0;
         const double FX = v ? fx[j] : 0.0, FY = v ? fy[j] : 0.0;
         const float xl = (float)(X - ox), yl = (float)(Y - oy);
         if (slp_sources(OP)) {
-            const double gx = W * FX, gy = W * FY;
-            const double c = -0.34657359027997264;   // -ln(2)/2: natural log from log2
-            ((RecSlp32 *)rec_out)[j] =
-                RecSlp32{X, Y, xl, yl, (float)gx, (float)gy, (float)(c * gx), (float)(c * gy)};
+            ((RecSlp32 *)rec_out)[j] = RecSlp32{X, Y, xl, yl, (float)(W * FX), (float)(W * FY)};
         } else {
             const double NX = v ? W * nx[j] : 0.0, NY = v ? W * ny[j] : 0.0;
             ((RecDlp32 *)rec_out)[j] = RecDlp32{X, Y, xl, yl, (float)NX, (float)NY, (float)FX, (float)FY};

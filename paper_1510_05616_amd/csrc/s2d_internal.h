@@ -13,8 +13,9 @@
 namespace s2d {
 
 constexpr int kWave = 64;            // CDNA wavefront width
-constexpr int kWavesPerBlock = 4;    // pair kernels: 4 independent waves per workgroup
+constexpr int kWavesPerBlock = 4;    // batched pair kernel: 4 independent waves per workgroup
 constexpr int kBlock = kWave * kWavesPerBlock;
+constexpr int kMaxPairWaves = 16;    // single-call pair kernel: up to 16 waves (splits) per target tile
 constexpr int kSuperBlock = 256;     // sources per superblock (split granularity, FP32 log reference)
 constexpr int kSubBlock = 16;        // FP32 sub-block: local origin, merged into the FP64 accumulators
 constexpr double kFarRadii = 4.0;    // a sub-block is far from a target beyond this many radii
@@ -25,7 +26,7 @@ constexpr int kMaxImages = 64;
 struct alignas(32) RecSlp64 { double x, y, gx, gy; };                 // g = w f
 // FP32C records carry the FP64 node (exact path) and its offset from the
 // sub-block origin in FP32 (far path).
-struct alignas(16) RecSlp32 { double x, y; float xl, yl, gx, gy, lx, ly; };   // l = -ln2/2 * g
+struct alignas(16) RecSlp32 { double x, y; float xl, yl, gx, gy; };
 struct alignas(16) RecDlp64 { double x, y, nx, ny, tx, ty; };         // nu = w n, tau
 struct alignas(16) RecDlp32 { double x, y; float xl, yl, nx, ny, tx, ty; };
 // per FP32C sub-block: origin and (kFarRadii * radius)^2
@@ -69,8 +70,10 @@ struct Plan {
     int op, mode, tpt;
     int64_t n_src, n_trg;
     int64_t n_sb;            // superblocks (sources padded to kSuperBlock)
-    int64_t n_tiles;         // target tiles of kWave * tpt
-    int n_splits;            // source splits (each a whole number of superblocks)
+    int64_t n_tiles;         // target tiles of kWave targets
+    int waves;               // waves (splits) per workgroup, <= kMaxPairWaves
+    int n_groups;            // split groups: workgroups per tile, partial planes when > 1
+    int n_splits;            // source splits = waves * n_groups (each a whole number of superblocks or empty)
     int64_t sb_per_split;
     int64_t n_blocks;        // workgroups of the pair kernel
     bool self;               // targets carry on_curve/on_node and image 0 is in range
@@ -89,20 +92,15 @@ struct PairArgs {
     int64_t n_trg;
     int64_t n_tiles;
     int32_t n_splits;
+    int32_t n_groups;         // single-call kernel: split groups (partial planes when > 1)
     int64_t sb_per_split;
     int64_t n_sb;
     double d;
     int32_t img_lo, img_hi;
-    double *part;             // [n_splits][2][n_trg]
+    double *part;             // single call: [n_groups][2][n_trg]; batched: [n_splits][2][n_trg]
     const double *tnx, *tny;  // target unit normals (single-layer traction) or NULL
     const void *rec64;        // FP32C pressures and traction: FP64 records for near sub-blocks
-    int32_t pad_far;          // padding records sit at kFarPad: the ragged superblock needs no mask
 };
-
-// Position of the zero-density padding records of the batched path: far
-// from every target (coordinates below 1e6 in magnitude), so that a padded
-// pair has a finite, large |r| and contributes exactly zero.
-constexpr double kFarPad = 1.0e7;
 
 // FP32C pressures and traction evaluate near sub-blocks from FP64 records.
 constexpr bool near_fp64(int op) { return op > S2D_OP_DLP; }
@@ -116,7 +114,7 @@ constexpr bool slp_sources(int op) {
 struct FinalArgs {
     const double *part;
     const double *self;       // SLP own-curve Kress sums [2][n_trg] or NULL
-    int32_t n_splits;
+    int32_t n_parts;          // partial planes of part
     int64_t n_trg;
     int64_t n_src;
     double pref;
@@ -132,7 +130,7 @@ struct FinalArgs {
 
 // launchers (return hipError_t of the launch)
 hipError_t launch_prep(const Plan &p, const s2d_curves *src, void *ws, hipStream_t st);
-hipError_t launch_pair(const Plan &p, const PairArgs &a, hipStream_t st);
+hipError_t launch_pair(const Plan &p, const PairArgs &a, const FinalArgs &f, hipStream_t st);
 hipError_t launch_kress(const Plan &p, const s2d_curves *src, const s2d_targets *trg,
                         void *ws, hipStream_t st);
 hipError_t launch_final(const Plan &p, const FinalArgs &a, hipStream_t st);

@@ -1,4 +1,5 @@
-// Own-curve terms and the final reduction of a single evaluation; the
+// Own-curve terms and the final reduction of a single evaluation (when the
+// pair kernel leaves split-group partials, or when there are no sources); the
 // per-curve and per-target device code is in self_impl.h.
 #include "self_impl.h"
 
@@ -34,20 +35,11 @@ __global__ __launch_bounds__(256) void finalize(FinalArgs a) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n_trg) return;
     double sx = 0.0, sy = 0.0;
-    for (int s = 0; s < a.n_splits; ++s) {
+    for (int s = 0; s < a.n_parts; ++s) {
         sx += a.part[(int64_t)(2 * s) * a.n_trg + i];
         sy += a.part[(int64_t)(2 * s + 1) * a.n_trg + i];
     }
-    if (a.self) {
-        sx += a.self[i];
-        sy += a.self[a.n_trg + i];
-    }
-    if (a.dlp_diag)
-        dlp_diag_one(i, a.n_src, a.on_curve, a.on_node, a.curve_off, a.n_curves, a.nx, a.ny, a.w, a.kappa,
-                     a.fx, a.fy, sx, sy);
-    const double ux = a.pref * sx, uy = a.pref * sy;
-    a.u[i] = a.accumulate ? a.u[i] + ux : ux;
-    if (a.ncomp == 2) a.v[i] = a.accumulate ? a.v[i] + uy : uy;
+    final_one(a, i, sx, sy);
 }
 hipError_t launch_kress(const Plan &p, const s2d_curves *src, const s2d_targets *trg, void *ws,
                         hipStream_t st) {

@@ -129,4 +129,20 @@ __device__ __forceinline__ void dlp_diag_one(int64_t i, int64_t n_src, const int
     sy += cc * (fy[j] - ny[j] * tn);
 }
 
+// Last step for target i, given its pair sum (sx, sy) without prefactor: the
+// own-curve Kress sums, the double layer's diagonal limit, the prefactor and
+// the accumulate flag (fixed order).
+__device__ __forceinline__ void final_one(const FinalArgs &a, int64_t i, double sx, double sy) {
+    if (a.self) {
+        sx += a.self[i];
+        sy += a.self[a.n_trg + i];
+    }
+    if (a.dlp_diag)
+        dlp_diag_one(i, a.n_src, a.on_curve, a.on_node, a.curve_off, a.n_curves, a.nx, a.ny, a.w, a.kappa,
+                     a.fx, a.fy, sx, sy);
+    const double ux = a.pref * sx, uy = a.pref * sy;
+    a.u[i] = a.accumulate ? a.u[i] + ux : ux;
+    if (a.ncomp == 2) a.v[i] = a.accumulate ? a.v[i] + uy : uy;
+}
+
 }  // namespace s2d

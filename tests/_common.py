@@ -14,8 +14,19 @@ def rel_err(u, v, ur, vr, sel=None):
     if sel is None:
         sel = slice(None)
     du = np.hypot(np.asarray(u)[sel] - ur[sel], np.asarray(v)[sel] - vr[sel])
+    if du.size and not np.all(np.isfinite(du)):
+        return float("inf")       # a NaN would compare False against every bound
     sc = np.hypot(ur[sel], vr[sel]).max()
     return float(du.max() / sc) if sc > 0 else float(du.max())
+
+
+def worse(a, b):
+    """max(a, b) that turns a NaN in either into inf (Python's max keeps its
+    first argument when a comparison with NaN is False)."""
+    a, b = float(a), float(b)
+    if a != a or b != b:
+        return float("inf")
+    return max(a, b)
 
 
 def class_errors(kind, u, v, ur, vr):

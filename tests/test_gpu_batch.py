@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import synth
-from _common import rel_err
+from _common import rel_err, worse
 
 pytestmark = pytest.mark.gpu
 
@@ -61,15 +61,16 @@ def test_batch_parity_small(small_batch, mode):
     for p, b in zip(small_batch, insts):
         ou, ov = _oracle(p)
         e = rel_err(b.u.cpu().numpy(), b.v.cpu().numpy(), ou, ov)
-        worst = max(worst, e)
+        worst = worse(worst, e)
     print(f"batch mode={mode} worst E={worst:.3e}", flush=True)
     assert worst <= TOL[mode]
 
 
 @pytest.mark.parametrize("mode", [0, 1])
 def test_batch_instances_far_from_the_origin(small_batch, mode):
-    """Instances moved to different places up to 5e4 from the origin (the
-    padding records sit far outside the coordinate range the batch accepts)."""
+    """Instances moved to different places up to 5e4 from the origin (FP32C
+    works in offsets from per-sub-block origins; the padding records of each
+    instance copy its last source)."""
     import dataclasses
     import torch
     import paper_1510_05616_amd as s2d
@@ -87,7 +88,7 @@ def test_batch_instances_far_from_the_origin(small_batch, mode):
     worst = 0.0
     for p, b in zip(moved, insts):
         ou, ov = _oracle(p)
-        worst = max(worst, rel_err(b.u.cpu().numpy(), b.v.cpu().numpy(), ou, ov))
+        worst = worse(worst, rel_err(b.u.cpu().numpy(), b.v.cpu().numpy(), ou, ov))
     print(f"moved batch mode={mode} worst E={worst:.3e}", flush=True)
     assert worst <= TOL[mode]
 
@@ -152,6 +153,6 @@ def test_batch_config4_full_size_sampled():
         idx = np.sort(rng.choice(p.trg.n, min(200, p.trg.n), replace=False))
         ou, ov = _oracle(p, idx)
         e = rel_err(b.u.cpu().numpy()[idx], b.v.cpu().numpy()[idx], ou, ov)
-        worst = max(worst, e)
+        worst = worse(worst, e)
     print(f"config4 sampled worst E={worst:.3e}", flush=True)
     assert worst <= TOL[mode]

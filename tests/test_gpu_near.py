@@ -6,6 +6,8 @@ trained network gains over the plain trapezoid rule."""
 import math
 
 import numpy as np
+
+from _common import worse
 import pytest
 
 import synth
@@ -44,7 +46,7 @@ def test_upsampled_quadrature_matches_oracle(small):
                              curve_off=np.array([0, s.stop - s.start], np.int32))
         u1, v1 = oracle.slp(sub, tx[sel], ty[sel])
         sc = np.hypot(u1 + ou, v1 + ov).max()
-        worst = max(worst, np.hypot(du[sel] - ou, dv[sel] - ov).max() / sc)
+        worst = worse(worst, np.hypot(du[sel] - ou, dv[sel] - ov).max() / sc)
     print(f"upsampled quadrature worst rel err {worst:.2e}", flush=True)
     assert worst < 1e-12
 
@@ -69,7 +71,7 @@ def test_upsampled_quadrature_other_factors(P, sizes):
                              curve_off=np.array([0, s.stop - s.start], np.int32))
         u1, v1 = oracle.slp(sub, tx[sel], ty[sel])
         sc = np.hypot(u1 + ou, v1 + ov).max()
-        worst = max(worst, np.hypot(du[sel] - ou, dv[sel] - ov).max() / sc)
+        worst = worse(worst, np.hypot(du[sel] - ou, dv[sel] - ov).max() / sc)
     print(f"P={P} sizes={sizes}: upsampled quadrature worst rel err {worst:.2e}", flush=True)
     assert worst < 1e-12
 
@@ -93,8 +95,8 @@ def test_upsampled_and_trapezoid_sums_match_oracle(small):
         ouP, ovP = onear.slp_trap(xu, yu, wu, fxu, fyu, tx[sel], ty[sel])
         ou1, ov1 = onear.slp_trap(c.x[s], c.y[s], c.w[s], c.fx[s], c.fy[s], tx[sel], ty[sel])
         sc = np.hypot(ouP, ovP).max()
-        worst_f = max(worst_f, np.hypot(uP[sel] - ouP, vP[sel] - ovP).max() / sc)
-        worst_c = max(worst_c, np.hypot(u1[sel] - ou1, v1[sel] - ov1).max() / sc)
+        worst_f = worse(worst_f, np.hypot(uP[sel] - ouP, vP[sel] - ovP).max() / sc)
+        worst_c = worse(worst_c, np.hypot(u1[sel] - ou1, v1[sel] - ov1).max() / sc)
     du, dv = data.du.cpu().numpy(), data.dv.cpu().numpy()
     gap = np.hypot((uP - u1) - du, (vP - v1) - dv).max() / np.hypot(uP, vP).max()
     print(f"fine {worst_f:.2e} trapezoid {worst_c:.2e} difference vs near_correct_eval {gap:.2e}", flush=True)
@@ -131,7 +133,7 @@ def test_invalid_targets_and_curves_give_nan():
                              curve_off=np.array([0, s.stop - s.start], np.int32))
         u1, v1 = oracle.slp(sub, tx[sel], ty[sel])
         sc = np.hypot(u1 + ou, v1 + ov).max()
-        worst = max(worst, np.hypot(du[sel] - ou, dv[sel] - ov).max() / sc)
+        worst = worse(worst, np.hypot(du[sel] - ou, dv[sel] - ov).max() / sc)
     print(f"valid targets beside invalid ones: worst rel err {worst:.2e}", flush=True)
     assert worst < 1e-12
 
