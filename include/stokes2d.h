@@ -130,6 +130,26 @@ S2D_API int stokes2d_slp_eval(int mode, const s2d_curves *src, const s2d_targets
                               double *u, double *v, int accumulate,
                               void *ws, size_t ws_bytes, void *stream);
 
+/* The same evaluation for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): no workspace argument; the scratch lives in a device array
+ * inside the library, S2D_NOALLOC_SCRATCH_BYTES (32 MiB) per device, set up
+ * by stokes2d_init and held until the process ends.  The call allocates
+ * nothing and returns S2D_EWORKSPACE, launching nothing, when the problem
+ * needs more scratch than that, i.e. when stokes2d_workspace_size(S2D_OP_SLP,
+ * ...) exceeds S2D_NOALLOC_SCRATCH_BYTES (about 34 bytes per source node,
+ * 8 more with on-curve targets, plus 16 per on-curve target: the 128k-node
+ * channel needs about 6 MB; a million source nodes do not fit).
+ * The result equals stokes2d_slp_eval's bit for bit.  Every call on one device
+ * shares that device's scratch: calls that overlap on one device (several
+ * streams, several host threads) race and must be serialised by the caller.
+ * Nothing in the scratch needs to start at zero; each call overwrites what
+ * it reads. */
+#define S2D_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+S2D_API int stokes2d_slp_eval_noalloc(int mode, const s2d_curves *src, const s2d_targets *trg,
+                                      double d, int32_t img_lo, int32_t img_hi, double mu,
+                                      double *u, double *v, int accumulate, void *stream);
+
 /* Double-layer potential (stresslet, principal value on source curves) of
  * density src->fx, fy (the paper's tau).  The double-layer velocity kernel has
  * no viscosity factor (Section 2.1, Eq. (D)). */

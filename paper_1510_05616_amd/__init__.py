@@ -22,7 +22,8 @@ import os
 __all__ = [
     "S2D_OK", "S2D_FP64", "S2D_FP32C", "S2D_OP_SLP", "S2D_OP_DLP", "S2DError",
     "Curves", "Targets", "lib", "library_path",
-    "stokes2d_init", "stokes2d_workspace_size", "stokes2d_slp_eval", "stokes2d_dlp_eval",
+    "stokes2d_init", "stokes2d_workspace_size", "stokes2d_slp_eval", "stokes2d_slp_eval_noalloc",
+    "stokes2d_dlp_eval",
     "stokes2d_last_error", "stokes2d_version", "stokes2d_profile_enable", "stokes2d_profile_read",
     "BatchInstance", "stokes2d_batch_workspace_size", "stokes2d_batch_eval", "stokes2d_batch_release",
     "stokes2d_batch_tuned", "S2D_OP_SLP_PRESSURE", "S2D_OP_DLP_PRESSURE", "S2D_OP_SLP_TRACTION",
@@ -82,6 +83,8 @@ def lib():
         L.stokes2d_workspace_size.restype = SZ
         L.stokes2d_slp_eval.argtypes = [I, P, P, D, I32, I32, D, P, P, I, P, SZ, P]
         L.stokes2d_slp_eval.restype = I
+        L.stokes2d_slp_eval_noalloc.argtypes = [I, P, P, D, I32, I32, D, P, P, I, P]
+        L.stokes2d_slp_eval_noalloc.restype = I
         L.stokes2d_dlp_eval.argtypes = [I, P, P, D, I32, I32, P, P, I, P, SZ, P]
         L.stokes2d_dlp_eval.restype = I
         L.stokes2d_slp_pressure_eval.argtypes = [I, P, P, D, I32, I32, P, I, P, SZ, P]
@@ -224,6 +227,16 @@ def stokes2d_slp_eval(mode, src: Curves, trg: Targets, d, img_lo, img_hi, mu, u,
     _check(lib().stokes2d_slp_eval(int(mode), ctypes.byref(cs), ctypes.byref(ts), float(d),
                                    int(img_lo), int(img_hi), float(mu), _ptr(u), _ptr(v),
                                    int(bool(accumulate)), _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def stokes2d_slp_eval_noalloc(mode, src: Curves, trg: Targets, d, img_lo, img_hi, mu, u, v,
+                              accumulate=0, stream=None) -> None:
+    """stokes2d_slp_eval without a workspace (the library's per-device scratch
+    memory; no allocation on this path)."""
+    cs, ts = src.struct(), trg.struct()
+    _check(lib().stokes2d_slp_eval_noalloc(int(mode), ctypes.byref(cs), ctypes.byref(ts), float(d),
+                                           int(img_lo), int(img_hi), float(mu), _ptr(u), _ptr(v),
+                                           int(bool(accumulate)), _stream(stream)))
 
 
 def stokes2d_dlp_eval(mode, src: Curves, trg: Targets, d, img_lo, img_hi, u, v,

@@ -13,6 +13,15 @@
 #include <string>
 #include <vector>
 
+// Scratch memory of stokes2d_slp_eval_noalloc: the records, Kress tables and
+// partial sums that stokes2d_slp_eval keeps in the caller's workspace.  Each
+// device the library runs on holds its own copy until the process ends.  In
+// host code `scratch` names a host-side stand-in, not device memory: kernels
+// and copies use the address hipGetSymbolAddress returns for it on each
+// device (DevState::scratch, set by stokes2d_init).
+constexpr size_t kScratchBytes = S2D_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
 
 thread_local std::string g_err;
@@ -20,6 +29,7 @@ thread_local std::string g_err;
 struct DevState {
     bool init = false;
     int cus = 256;
+    void *scratch = nullptr;     // this device's copy of `scratch`
 };
 constexpr int kMaxDev = 64;
 DevState g_dev[kMaxDev];
@@ -189,7 +199,7 @@ int hip_fail(hipError_t e, const char *what) {
 
 int eval(int op, int mode, const s2d_curves *src, const s2d_targets *trg, double d, int32_t img_lo,
          int32_t img_hi, double mu, double *u, double *v, int accumulate, void *ws, size_t ws_bytes,
-         void *stream, const double *tnx = nullptr, const double *tny = nullptr) {
+         void *stream, const double *tnx = nullptr, const double *tny = nullptr, bool may_profile = true) {
     using namespace s2d;
     int rc = check_args(op, mode, src, trg, d, img_lo, img_hi, mu);
     if (rc != S2D_OK) return rc;
@@ -279,7 +289,7 @@ int eval(int op, int mode, const s2d_curves *src, const s2d_targets *trg, double
     f.fy = src->fy;
     if (p.n_blocks > 0) {
         ProfEvent pe{op, nullptr, nullptr};
-        if (g_prof_on) {
+        if (g_prof_on && may_profile) {
             std::lock_guard<std::mutex> lk(g_mu);
             if (hipEventCreate(&pe.a) == hipSuccess && hipEventCreate(&pe.b) == hipSuccess) {
                 hipEventRecord(pe.a, st);
@@ -324,6 +334,13 @@ S2D_API int stokes2d_init(int device) {
         return fail(S2D_ENOTSUP, std::string("libstokes2d is built for gfx950, device is ") + prop.gcnArchName);
     std::lock_guard<std::mutex> lk(g_mu);
     g_dev[device].cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    if (!g_dev[device].scratch) {
+        // this device's address of the no-allocation entry point's scratch
+        void *sp = nullptr;
+        e = hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !sp) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        g_dev[device].scratch = sp;
+    }
     g_dev[device].init = true;
     return S2D_OK;
 }
@@ -341,6 +358,25 @@ S2D_API int stokes2d_slp_eval(int mode, const s2d_curves *src, const s2d_targets
                               int32_t img_hi, double mu, double *u, double *v, int accumulate, void *ws,
                               size_t ws_bytes, void *stream) {
     return eval(S2D_OP_SLP, mode, src, trg, d, img_lo, img_hi, mu, u, v, accumulate, ws, ws_bytes, stream);
+}
+
+S2D_API int stokes2d_slp_eval_noalloc(int mode, const s2d_curves *src, const s2d_targets *trg, double d,
+                                      int32_t img_lo, int32_t img_hi, double mu, double *u, double *v,
+                                      int accumulate, void *stream) {
+    int rc = check_args(S2D_OP_SLP, mode, src, trg, d, img_lo, img_hi, mu);
+    if (rc != S2D_OK) return rc;
+    int dev = 0;
+    rc = current_device(&dev);
+    if (rc != S2D_OK) return rc;
+    void *sp = g_dev[dev].scratch;
+    if (!sp) return fail(S2D_ENOINIT, "stokes2d_init() did not set up the scratch memory of this device");
+    const s2d::Plan p = make_plan(S2D_OP_SLP, mode, src, trg, g_dev[dev].cus);
+    if (p.total > kScratchBytes)
+        return fail(S2D_EWORKSPACE, "problem needs " + std::to_string(p.total) +
+                                        " bytes of scratch; stokes2d_slp_eval_noalloc holds " +
+                                        std::to_string(kScratchBytes) + " (use stokes2d_slp_eval with a workspace)");
+    return eval(S2D_OP_SLP, mode, src, trg, d, img_lo, img_hi, mu, u, v, accumulate, sp, kScratchBytes, stream,
+                nullptr, nullptr, false);
 }
 
 S2D_API int stokes2d_dlp_eval(int mode, const s2d_curves *src, const s2d_targets *trg, double d, int32_t img_lo,
