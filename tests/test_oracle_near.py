@@ -85,34 +85,129 @@ def test_upsampled_quadrature_converges_to_the_integral():
     assert errs[(0.5, 1)] > 1e-4 > errs[(0.5, 8)] * 1e3
 
 
-def test_features_reconstruct_target_and_window():
-    c = synth.make_curve(0.75, 64, K=8, seed=5, phi=0.3)
-    rng = np.random.default_rng(1)
-    N = 64
-    h = c.w.sum() / N
-    for _ in range(40):
-        th = rng.uniform(0, 2 * np.pi)
-        k = int(th / (2 * np.pi) * N) % N
-        delta = h * 10 ** rng.uniform(np.log10(0.05), np.log10(5))
-        px = np.interp(th, 2 * np.pi * np.arange(N + 1) / N, np.append(c.x, c.x[0])) + delta * c.nx[k]
-        py = np.interp(th, 2 * np.pi * np.arange(N + 1) / N, np.append(c.y, c.y[0])) + delta * c.ny[k]
-        f, t0, n0, hh, F = near.features_one(c.x, c.y, c.nx, c.ny, c.kappa, c.w, c.fx, c.fy, px, py)
-        assert abs(hh - h) < 1e-15
+def _lattice_flat(s, b, pmax, op, P=8, T=60.0):
+    """Brute force: the P-refined minus the plain trapezoid sum on the line y = 0
+    (nodes at the integers), density tau^p / p!, target (s, b), summed
+    directly with a smooth cutoff that vanishes well inside [-T, T] (the two
+    rules agree to rounding on the smooth far part)."""
+    from scipy.special import erfc
+
+    def rule(step):
+        tau = np.arange(-T, T + step / 2, step)
+        win = 0.5 * erfc((np.abs(tau) - 0.5 * T) / (0.06 * T))
+        a, q = s - tau, (s - tau) ** 2 + b * b
+        if op == "slp":
+            K = np.array([[-0.5 * np.log(q) + a * a / q, a * b / q], [a * b / q, -0.5 * np.log(q) + b * b / q]])
+        else:
+            K = np.array([[b * a * a / q ** 2, a * b * b / q ** 2], [a * b * b / q ** 2, b ** 3 / q ** 2]])
+        return np.stack([(K * (tau ** p / math.factorial(p) * win * step)).sum(-1) for p in range(pmax + 1)], 0)
+    return rule(1.0 / P) - rule(1.0)
+
+
+@pytest.mark.parametrize("op", ["slp", "dlp"])
+def test_flat_coefficients_match_lattice_sums(op):
+    pts = [(0.0, 0.05), (0.3, 0.05), (-0.4, 0.2), (0.1, 0.5), (0.45, 1.0), (-0.5, 2.0), (0.25, 3.0)]
+    for sv, bv in pts:
+        ref = _lattice_flat(sv, bv, 4, op)
+        fn = near.flat_coeffs_slp if op == "slp" else near.flat_coeffs_dlp
+        got = fn(np.array([sv]), np.array([bv]))[0]
+        scale = max(np.abs(ref).max(), 1e-300)
+        assert np.abs(got - ref).max() <= 1e-8 * max(scale, 1.0), (op, sv, bv, np.abs(got - ref).max(), scale)
+
+
+def test_flat_dlp_is_the_straight_wall_correction():
+    """On a straight periodic wall with equispaced nodes the double-layer
+    correction of the 8x refined wall (the oracle's wall upsampling and pair
+    sums over images -1..1) is the flat closed form contracted with the
+    density's node derivatives, up to the derivatives past p = 4 and the
+    ends of the summed image range."""
+    import oracle
+    N, d = 128, 2 * np.pi
+    xs = d * np.arange(N) / N
+    h = d / N
+    rng = np.random.default_rng(3)
+    dens = [sum(rng.normal() * np.cos(k * xs + rng.uniform(0, 6.3)) / k ** 2 for k in range(1, 5)) for _ in range(2)]
+    parts = [(xs, np.full(N, 1.0), np.zeros(N), np.ones(N), np.full(N, h), np.zeros(N), dens[0], dens[1])]
+    walls = synth.concat_curves(parts)
+    xu, yu, nxu, nyu, wu, fxu, fyu = near.wall_upsample(walls.x, walls.y, walls.nx, walls.ny, walls.fx, walls.fy,
+                                                        d, 8)
+    fine = synth.concat_curves([(xu, yu, nxu, nyu, wu, np.zeros_like(xu), fxu, fyu)])
+    # targets below the wall (normal +y points away from them), several offsets and phases
+    px = np.array([xs[40] + 0.3 * h, xs[41] - 0.2 * h, xs[70], xs[10] + 0.45 * h, xs[90] - 0.1 * h])
+    py = 1.0 - np.array([0.05, 0.2, 0.5, 1.0, 2.0]) * h
+    # 81 periods: the truncated image sum's end terms (a kernel decaying like
+    # 1 / r^2, 40 periods away) fall below the tolerance
+    uf, vf = oracle.dlp(fine, px, py, d=d, img_lo=-40, img_hi=40)
+    uc, vc = oracle.dlp(walls, px, py, d=d, img_lo=-40, img_hi=40)
+    X, frames, dd = near.wall_features(walls, d, px, py, np.zeros(len(px), np.int32))
+    yf = near.flat_predict(frames, dd, op="dlp")
+    du, dv = near.frame_to_velocity(yf, frames, 1.0 / np.pi)
+    err = np.hypot(du - (uf - uc), dv - (vf - vc))
+    assert err.max() <= 5e-9 * max(np.hypot(uf, vf).max(), 1.0), err
+    assert np.hypot(uf - uc, vf - vc).max() > 1e-4          # the correction itself is not small
+
+
+def test_node_derivatives_exact_on_trig_polynomials():
+    N = 32
+    t = 2 * np.pi * np.arange(N) / N
+    f = 0.3 + np.cos(3 * t) - 2.0 * np.sin(5 * t) + 0.7 * np.cos(16 * t)
+    D = near.node_derivatives(f, 4)
+    h = 2 * np.pi / N
+    # exact derivatives of the interpolant: the Nyquist term cos(16 t) keeps its even derivatives
+    ex = [f,
+          -3 * np.sin(3 * t) - 10 * np.cos(5 * t),
+          -9 * np.cos(3 * t) + 50 * np.sin(5 * t) - 0.7 * 256 * np.cos(16 * t),
+          27 * np.sin(3 * t) + 250 * np.cos(5 * t),
+          81 * np.cos(3 * t) - 1250 * np.sin(5 * t) + 0.7 * 16 ** 4 * np.cos(16 * t)]
+    for p in range(5):
+        assert np.abs(D[p] - ex[p] * h ** p).max() < 1e-12 * max(1.0, np.abs(ex[p] * h ** p).max()), p
+
+
+def test_features_reconstruct_target_and_frame():
+    cs, tx, ty, tc, dh = synth.make_near_dataset(200, 9, per_curve=200, sizes=(96,))
+    c = cs
+    N = 96
+    X, frames, dd = near.features(c, tx, ty)
+    for i in range(200):
+        px, py = tx[i], ty[i]
         d2 = (px - c.x) ** 2 + (py - c.y) ** 2
         ks = int(np.argmin(d2))
-        assert abs(f[2] - math.log(math.sqrt(d2[ks]) / h)) < 1e-12   # log distance to the nearest node
-        # the target is x_k0 + h (s t0 + n_off n0) for the node k0 whose frame it uses
-        k0 = [j for j in range(N) if abs(-c.ny[j] - t0[0]) < 1e-15 and abs(c.nx[j] - t0[1]) < 1e-15][0]
-        assert k0 in (ks, (ks - 1) % N) and f[0] >= 0.0 or k0 == (ks - 1) % N
-        assert abs(c.x[k0] + h * (f[0] * t0[0] + f[1] * n0[0]) - px) < 1e-13
-        assert abs(c.y[k0] + h * (f[0] * t0[1] + f[1] * n0[1]) - py) < 1e-13
-        # the density window k0-3 .. k0+4 comes back from (f_t, f_n) * F
-        idx = [(k0 + j) % N for j in range(-3, 5)]
-        fx = (f[4:12] * t0[0] + f[12:20] * n0[0]) * F
-        fy = (f[4:12] * t0[1] + f[12:20] * n0[1]) * F
-        assert np.abs(fx - c.fx[idx]).max() < 1e-13 and np.abs(fy - c.fy[idx]).max() < 1e-13
-        assert abs(np.hypot(f[4:12], f[12:20]).max() - 1.0) < 1e-14
-        assert abs(f[3] - c.kappa[k0] * h) < 1e-15
+        sv, b, t0, t1, nf0, nf1, hl, F, sg = frames[i]
+        assert hl == c.w[ks] and abs(t0 + c.ny[ks]) == 0.0 and abs(t1 - c.nx[ks]) == 0.0 and sg == 1.0
+        assert b >= 0.0 and abs(abs(nf0) - abs(c.nx[ks])) == 0.0
+        # the target is x_k* + hl (s t + b n_f)
+        assert abs(c.x[ks] + hl * (sv * t0 + b * nf0) - px) < 1e-13
+        assert abs(c.y[ks] + hl * (sv * t1 + b * nf1) - py) < 1e-13
+        assert X[i, 0] == sv and X[i, 1] == b and abs(X[i, 2] - math.log(math.sqrt(d2[ks]) / hl)) < 1e-12
+        # the neighbours come back from their frame coordinates
+        for q, j in enumerate((-2, -1, 1, 2)):
+            k = (ks + j) % N
+            gx = c.x[ks] + hl * (X[i, 4 + 2 * q] * t0 + X[i, 5 + 2 * q] * nf0)
+            gy = c.y[ks] + hl * (X[i, 4 + 2 * q] * t1 + X[i, 5 + 2 * q] * nf1)
+            assert abs(gx - c.x[k]) < 1e-13 and abs(gy - c.y[k]) < 1e-13
+        Q = np.exp(-2 * np.pi * (b + 1j * sv))
+        assert abs(X[i, 12] - Q.real) < 1e-15 and abs(X[i, 13] - Q.imag) < 1e-15
+        # d_0 is the density at k* in the frame, F its largest entry
+        assert abs(dd[i, 0, 0] * t0 + dd[i, 0, 1] * nf0 - c.fx[ks]) < 1e-13
+        assert abs(dd[i, 0, 0] * t1 + dd[i, 0, 1] * nf1 - c.fy[ks]) < 1e-13
+        assert F == np.abs(dd[i]).max()
+
+
+def test_flat_prediction_captures_most_of_the_label():
+    """The closed-form straight-line coefficients account for the bulk of
+    the upsampled correction near a curved vesicle (the rest is what the
+    network learns): within 20 % (median 5 %) where the correction is large.
+    A dropped term or a wrong sign in the closed form misses by O(1)."""
+    cs, tx, ty, tc, dh = synth.make_near_dataset(200, 4, per_curve=200, sizes=(64,))
+    one = synth.concat_curves([(cs.x, cs.y, cs.nx, cs.ny, cs.w, cs.kappa, cs.fx, cs.fy)])
+    X, frames, dd = near.features(one, tx, ty)
+    du, dv = near.near_label(one.x, one.y, one.fx, one.fy, one.w, tx, ty)
+    y = near.velocity_to_frame(du, dv, frames, frames[:, 6] / (4 * np.pi))
+    yf = near.flat_predict(frames, dd)
+    big = np.hypot(*y.T) > 0.1 * np.hypot(*y.T).max()
+    assert big.sum() >= 10
+    rel = np.hypot(*(y - yf).T)[big] / np.hypot(*y.T)[big]
+    assert rel.max() < 0.2 and np.median(rel) < 0.05, (rel.max(), np.median(rel))
 
 
 def test_gelu_tanh_form_close_to_exact_gelu():
@@ -127,19 +222,23 @@ def test_gelu_tanh_form_close_to_exact_gelu():
 
 def test_mlp_gradient_matches_finite_differences():
     rng = np.random.default_rng(2)
-    p = near.init_params(seed=4, mu_in=rng.normal(size=20) * 0.1, sd_in=1 + rng.random(20))
-    X = rng.normal(size=(7, 20))
-    T = rng.normal(size=(7, 2))
-    L, g = near.mlp_loss_grad(p, X, T)
+    nf = near.N_FEAT
+    p = near.init_params(seed=4, mu_in=rng.normal(size=nf) * 0.1, sd_in=1 + rng.random(nf))
+    X = rng.normal(size=(7, nf))
+    X[:, 1] = rng.uniform(0.05, 1.0, 7)              # the envelope's normal offset
+    dd = rng.normal(size=(7, near.N_DERIV, 2))
+    R = rng.normal(size=(7, 2))
+    wt = rng.uniform(0.5, 2.0, 7)
+    L, g = near.mlp_loss_grad(p, X, dd, R, wt)
     eps = 1e-6
     for name in ("W1", "b1", "W2", "b3", "W4", "b4"):
         flat = p[name].reshape(-1)
         for j in rng.choice(flat.size, min(6, flat.size), replace=False):
             old = flat[j]
             flat[j] = old + eps
-            Lp, _ = near.mlp_loss_grad(p, X, T)
+            Lp, _ = near.mlp_loss_grad(p, X, dd, R, wt)
             flat[j] = old - eps
-            Lm, _ = near.mlp_loss_grad(p, X, T)
+            Lm, _ = near.mlp_loss_grad(p, X, dd, R, wt)
             flat[j] = old
             fd = (Lp - Lm) / (2 * eps)
             gj = g[name].reshape(-1)[j]
@@ -202,34 +301,22 @@ def test_wall_correction_converges_to_the_integral(oracle_lib):
     assert e1 > 1e-3 and e8 < 1e-3 * e1, (e1, e8)
 
 
-def test_wall_features_reconstruct_target_and_window():
-    # from the features and the frame, the target is node K0 (unrolled over
-    # the period) plus h (s t0 + n_off n0), also for targets across the
-    # period boundary; the window is the wall density in the local frame
-    import math
-    from oracle import near as onear
-    walls, sy, d = synth.make_channel(64, 4)
-    w = synth.wall_densities(walls, 3)
-    rng = np.random.default_rng(4)
-    N = 64
-    s = slice(0, N)                     # the upper wall, x from 0 to d
-    h = w.w[s].sum() / N
-    for px, py in ((0.01, 0.9), (d - 0.02, 0.95), (-0.05, 0.92), (d + 0.03, 0.9), (2.0, 1.1)):
-        f, t0, n0, one, F = onear.wall_features_one(w.x[s], w.y[s], w.nx[s], w.ny[s], w.kappa[s], w.w[s],
-                                                    w.fx[s], w.fy[s], d, px, py)
-        assert one == 1.0
-        # candidate K0 positions: the node whose unrolled position + offsets gives p
-        ox, oy = h * (f[0] * t0[0] + f[1] * n0[0]), h * (f[0] * t0[1] + f[1] * n0[1])
-        qx, qy = px - ox, py - oy
-        K = np.arange(-N, 2 * N)
-        X = w.x[s][K % N] + d * np.floor_divide(K, N)
-        j = int(np.argmin((X - qx) ** 2 + (w.y[s][K % N] - qy) ** 2))
-        assert math.hypot(X[j] - qx, w.y[s][K[j] % N] - qy) < 1e-12
-        k0 = int(K[j])
-        # k0 is the nearest node or its predecessor
-        d2 = (X - px) ** 2 + (w.y[s][K % N] - py) ** 2
-        assert k0 in (int(K[np.argmin(d2)]), int(K[np.argmin(d2)]) - 1)
-        win = [(k0 + jj) % N for jj in range(-3, 5)]
-        ft = (w.fx[s][win] * t0[0] + w.fy[s][win] * t0[1]) / F
-        assert np.abs(f[4:12] - ft).max() < 1e-14
-        assert abs(f[2] - math.log(math.sqrt(d2.min()) / h)) < 1e-12
+def test_wall_features_reconstruct_target_across_periods():
+    walls, sy, d = synth.make_channel(64, 8)
+    for c in (0, 1):
+        s = slice(walls.curve_off[c], walls.curve_off[c + 1])
+        x, y, nx, ny = walls.x[s], walls.y[s], walls.nx[s], walls.ny[s]
+        for k in (0, 1, 31, 62, 63):        # 0, 63: next to the period boundary
+            for off in (-0.4, 0.3):
+                # a point in the fluid half a spacing from the wall beside node k
+                h = walls.w[s][k]
+                px = x[k] + off * h * (-ny[k]) - 0.5 * h * nx[k]
+                py = y[k] + off * h * nx[k] - 0.5 * h * ny[k]
+                X, frames, dd = near.wall_features(walls, d, np.array([px]), np.array([py]), np.array([c]))
+                sv, b, t0, t1, nf0, nf1, hl, F, sg = frames[0]
+                # the frame's tangent follows the node order: (-n_y, n_x) or its opposite
+                orient = t0 * -ny[k] + t1 * nx[k]
+                assert abs(abs(orient) - 1.0) < 1e-14
+                assert b > 0 and abs(b - 0.5) < 1e-9 and abs(sv - orient * off) < 1e-9
+                assert nf0 * nx[k] + nf1 * ny[k] < 0 and sg == -1.0      # the frame normal points into the fluid
+                assert np.abs(X[0, 4:12:2] - [-2, -1, 1, 2]).max() < 0.05   # neighbours along the tangent
