@@ -314,14 +314,32 @@ S2D_API int stokes2d_batch_tuned(int mode, int32_t n_inst, const s2d_instance *i
  * density (the paper represents curves in a Fourier basis), minus the N-node
  * trapezoid value; images and other curves are not involved.  Curves must
  * have an even node count N with 8 <= N <= 256 and P*N <= 2048.
+ *
+ * The learned route writes Delta in the frame of the target's nearest node
+ * k* (tangent t along growing node index, normal n_f turned towards the
+ * target, lengths in units of the local spacing h = w_k*, offsets (s, b)):
+ *   Delta = scale sum_{p=0..4} (Cflat_p(s, b) + exp(-2 pi b) dC_p) d_p,
+ * d_p = (2 pi / N)^p d^p f / dt^p at k* (the density's node derivatives in
+ * the frame), Cflat_p the exact correction of a straight line with
+ * equispaced nodes (closed form by Poisson summation), dC_p (2 x 2 each) the
+ * output of a 14-64-64-64-20 network (BF16 weights, MFMA inference), scale =
+ * h / (4 pi mu) for the single layer and 1 / pi for the double layer.
  * ------------------------------------------------------------------------- */
-#define S2D_NEAR_NFEAT 20            /* features per target */
-#define S2D_MLP_NPARAM 9834          /* FP32 master parameters of the 20-64-64-64-2 network */
+#define S2D_NEAR_NFEAT 14            /* geometry features per target */
+#define S2D_NEAR_NFRAME 20           /* FP64 frame words per target */
+#define S2D_NEAR_NDERIV 10           /* FP64 derivative-table words per node */
+#define S2D_NEAR_TSTRIDE 14          /* FP32 training-record words per sample */
+#define S2D_NEAR_NOUT 20             /* network outputs dC[p][out][in] */
+#define S2D_NEAR_NBINS 64            /* AUTO's largest number of bins of log10 b */
+#define S2D_NEAR_SBINS 4             /* AUTO's bins of |s| per b bin: width 1/8, the last open */
+#define S2D_NEAR_KBINS 8             /* AUTO's bins of log10 |kappa h|: width 3/16 from -2, ends open */
+#define S2D_NEAR_CELL (S2D_NEAR_SBINS * S2D_NEAR_KBINS)   /* table entries per b bin */
+#define S2D_MLP_NPARAM 10608         /* FP32 master parameters of the 14-64-64-64-20 network */
 
 typedef enum {
     S2D_NEAR_UPSAMPLE = 0,           /* FP64 upsampled quadrature for every target */
-    S2D_NEAR_MLP = 1,                /* BF16 MLP for every target, no fallback */
-    S2D_NEAR_AUTO = 2                /* MLP where its calibrated bound <= threshold, else upsampled */
+    S2D_NEAR_MLP = 1,                /* straight-line part plus BF16 network for every target, no fallback */
+    S2D_NEAR_AUTO = 2                /* per target: none, learned or upsampled by calibrated bounds */
 } s2d_near_method;
 
 /* Workspace bytes for near_correct_eval. */
@@ -329,17 +347,27 @@ S2D_API size_t near_workspace_size(int method, const s2d_curves *ves, const s2d_
 
 /* Delta at every target (du, dv: [n] device FP64, written).  trg->on_curve /
  * on_node are ignored; trg_curve[i] names the curve of `ves` the correction
- * is for.  upsample = P (1..32).  mlp: device blob from near_mlp_pack (MLP,
- * AUTO).  AUTO decides per target from the calibrated bounds of its bin
- * (scaled by h F / (4 pi mu) into velocity units): Delta = 0 where the plain
- * rule's bound is <= threshold, the network where its bound is, the
- * upsampled quadrature otherwise.  used_fallback: [n] device int32 or NULL,
- * set (AUTO) to 0 network, 1 upsampled quadrature, 2 no correction.
- * Targets of invalid curves get NaN. */
+ * is for.  upsample = P (1..32) of the quadrature (UPSAMPLE, and AUTO's
+ * fallback); the learned route's straight-line part uses the P stored in
+ * the blob (the one the network was trained for), so AUTO callers pass the
+ * same P.  mlp: device blob from near_mlp_pack (MLP, AUTO).
+ * AUTO decides per target against its tolerance: curve_tol[trg_curve[i]]
+ * when curve_tol ([n_curves] device FP64, absolute velocity tolerances per
+ * curve) is not NULL, else threshold.  Its bin is (log10 b, |s|,
+ * log10 |kappa h|) in FP32 (near_calibrate):
+ * b < the blob's b_min, a target inside its vesicle (against the outward
+ * normal), NaN or a b bin below the first go to the quadrature; otherwise
+ * Delta = 0 where the bin's largest correction times scale F (F = sum_p
+ * |d_p|, both components) is within the tolerance, the learned value where
+ * the bin's network bound times scale F is, the quadrature otherwise (past
+ * the last b bin: 0 or the quadrature).  used_fallback: [n] device int32 or
+ * NULL, set (MLP, AUTO) to 0 learned, 1 upsampled quadrature, 2 no
+ * correction.  Targets of invalid curves get NaN. */
 S2D_API int near_correct_eval(int method, const s2d_curves *ves, const s2d_targets *trg,
                               const int32_t *trg_curve, int32_t upsample, const void *mlp,
-                              double threshold, double mu, double *du, double *dv,
-                              int32_t *used_fallback, void *ws, size_t ws_bytes, void *stream);
+                              double threshold, const double *curve_tol, double mu, double *du,
+                              double *dv, int32_t *used_fallback, void *ws, size_t ws_bytes,
+                              void *stream);
 
 /* The single layer of each target's own curve by the P-times upsampled
  * trapezoid rule (u_up, v_up) and by the plain N-node rule (u_trap, v_trap),
@@ -349,42 +377,94 @@ S2D_API int near_upsampled_slp(const s2d_curves *ves, const s2d_targets *trg, co
                                int32_t upsample, double mu, double *u_up, double *v_up, double *u_trap,
                                double *v_trap, void *ws, size_t ws_bytes, void *stream);
 
-/* Target features X ([n][20] FP32: tangential and normal offset from node
- * k0 in units of h, distance to the nearest node / h, kappa h, and the
- * densities of nodes k0-3..k0+4 in the local frame divided by their largest
- * norm F) and frames ([n][6] FP64: t0, n0, h, F). */
-S2D_API int near_features_eval(const s2d_curves *ves, const s2d_targets *trg, const int32_t *trg_curve,
-                               float *X, double *frame, void *stream);
+/* The density's node derivatives d_p = (2 pi / N)^p d^p f / dt^p, p = 0..4,
+ * of every curve's trigonometric interpolant (N even and >= 4; other curves
+ * get NaN), the Nyquist mode split evenly (its odd derivatives vanish at the
+ * nodes): dtab [n_nodes][10] device FP64, d_p of fx at 2p and of fy at
+ * 2p + 1.  Direct sums in FP64: one workgroup per curve up to 256 nodes,
+ * a wave per coefficient and per node above (O(N^2) work per curve).  Serves
+ * closed curves and wall periods alike (curves needs fx, fy and curve_off).
+ * ws: near_derivs_workspace_size(curves) bytes, 256-byte aligned (needed
+ * only when n_nodes > 256; NULL otherwise). */
+S2D_API size_t near_derivs_workspace_size(const s2d_curves *curves);
+S2D_API int near_derivs_eval(const s2d_curves *curves, double *dtab, void *ws, size_t ws_bytes, void *stream);
 
-/* Training labels in the local frame: Y = (Delta . t0, Delta . n0) 4 pi mu / (h F). */
-S2D_API int near_scale_labels(int64_t n, const double *du, const double *dv, const double *frame,
-                              double mu, float *Y, void *stream);
+/* Per target, relative to curve trg_curve[i] of `ves`: the nearest node k*
+ * (smallest index on ties), the geometry features X [n][14] FP32 =
+ * (s, b, log(|x - x_k*| / h), sg kappa h, the nodes k*-2, k*-1, k*+1, k*+2
+ * in the frame (units h), Re Q, Im Q with Q = exp(-2 pi (b + i s))) and the
+ * frame [n][20] FP64 = (s, b, t_x, t_y, n_x, n_y, h, F, sg, d_0t, d_0n, ...,
+ * d_4t, d_4n, sg kappa h): sg the sign of the offset along the node normal,
+ * d_p from dtab (near_derivs_eval) in the frame, F = sum_p (|d_pt| + |d_pn|)
+ * (1 if all vanish). */
+S2D_API int near_features_eval(const s2d_curves *ves, const s2d_targets *trg, const int32_t *trg_curve,
+                               const double *dtab, float *X, double *frame, void *stream);
+
+/* Training records T [n][14] FP32 from labels (du, dv: the upsampled
+ * quadrature's Delta) and frames: (d_0t, d_0n, ..., d_4t, d_4n, R_t, R_n,
+ * wt, exp(-2 pi b)), R the label over scale minus the straight-line part
+ * (op S2D_OP_SLP: single layer, scale h / 4 pi mu; S2D_OP_DLP: double
+ * layer, scale 1 / pi, straight-line part times sg), wt = weight_gain
+ * scale / (the largest |(u_ref, v_ref)| over the targets of the same
+ * curve), so that the loss weighs errors as the normalised error measure
+ * does (weight_gain > 0, a constant factor that keeps the gradients well
+ * above Adam's eps).  curve_scale: [n_curves] device float, written with
+ * those largest norms; targets of other curves get wt = 0.  upsample: the
+ * P of the labels. */
+S2D_API int near_train_targets(int op, int64_t n, const double *frame, const double *du, const double *dv,
+                               const int32_t *trg_curve, int32_t n_curves, const double *u_ref,
+                               const double *v_ref, double mu, int32_t upsample, float weight_gain,
+                               float *curve_scale, float *T, void *stream);
 
 /* Workspace bytes for a training step with `batch` samples. */
 S2D_API size_t near_mlp_train_workspace_size(int32_t batch);
 
-/* One minibatch step of MSE training, L = 1/(2B) sum ||net(X_idx) - Y_idx||^2:
- * forward, backward and per-parameter gradient sums over the batch in fixed
- * sample order, then an Adam update (beta 0.9, 0.999, eps 1e-8) at
- * step >= 1; step == 0 computes grad and loss only.  params, adam_m,
- * adam_v, grad: [S2D_MLP_NPARAM] device FP32 (the first 40 entries are the
- * input standardisation mean and scale, not trained).  loss: device float
- * or NULL.  idx: [batch] sample indices into X / Y, or NULL for 0..batch-1. */
-S2D_API int near_mlp_train_step(int32_t batch, const int32_t *idx, const float *X, const float *Y,
+/* One minibatch step of weighted least squares on the learned part:
+ * L = 1/(2B) sum_i |wt_i (exp(-2 pi b_i) sum_p dC_p(X_i) d_p,i - R_i)|^2 over
+ * the records T (near_train_targets): forward, backward and per-parameter
+ * gradient sums over the batch in fixed sample order, then an Adam update
+ * (beta 0.9, 0.999, eps 1e-8) at step >= 1; step == 0 computes grad and
+ * loss only.  params, adam_m, adam_v, grad: [S2D_MLP_NPARAM] device FP32
+ * (the first 28 entries are the input standardisation mean and scale, not
+ * trained).  loss: device float or NULL.  idx: [batch] sample indices into
+ * X / T, or NULL for 0..batch-1. */
+S2D_API int near_mlp_train_step(int32_t batch, const int32_t *idx, const float *X, const float *T,
                                 float *params, float *adam_m, float *adam_v, int32_t step, float lr,
                                 float *grad, float *loss, void *ws, size_t ws_bytes, void *stream);
 
-/* FP32 forward pass of the master parameters: Y [n][2]. */
+/* FP32 forward pass of the master parameters: Y [n][20] = dC[p][out][in]
+ * at 4p + 2 out + in. */
 S2D_API int near_mlp_forward(int64_t n, const float *X, const float *params, float *Y, void *stream);
 
-/* Bytes of the BF16 inference blob; near_mlp_pack fills it from FP32 master
- * parameters and two calibrated error bounds per bin of
- * log10(|normal offset| / h) (n_bins <= 64 bins of width bin_w starting at
- * bin_lo), in the scaled output units of near_scale_labels: `bound` for the
- * network and `bound_zero` for no correction at all (NULL: never skip). */
+/* The input standardisation: mean and population standard deviation (1
+ * where it vanishes) of each feature over X [n][14], written into params'
+ * first 28 entries (FP64 sums in a fixed order). */
+S2D_API int near_feature_stats(int64_t n, const float *X, float *params, void *stream);
+
+/* Calibration of AUTO's rule on held-out targets: per bin (k, j, m), all
+ * in FP32: k the bin of log10 b ([bin_lo + k bin_w, bin_lo + (k + 1)
+ * bin_w), k < n_bins <= 64), j = min(floor(8 |s|), 3) the bin of |s| and m
+ * = clamp(floor((log10 |kappa h| + 2) 16 / 3), 0, 7) the bin of the
+ * curvature over the spacing (kappa h = frame[19]), over targets with b >=
+ * b_min on the expected side (sg > 0 for the single layer, sg < 0 for the
+ * double layer), the largest |(du_pred, dv_pred) - (du, dv)| and the largest
+ * |(du, dv)|, both over scale F, times margin (>= 1): bound, bound_zero
+ * [n_bins * S2D_NEAR_CELL] device float at S2D_NEAR_CELL k + 8 j + m; empty
+ * bins get 3e38.  count: [n_bins * S2D_NEAR_CELL] device int32, the targets
+ * per bin. */
+S2D_API int near_calibrate(int op, int64_t n, const double *frame, const double *du_pred, const double *dv_pred,
+                           const double *du, const double *dv, double mu, int32_t n_bins, float bin_lo,
+                           float bin_w, float b_min, float margin, float *bound, float *bound_zero,
+                           int32_t *count, void *stream);
+
+/* Bytes of the BF16 inference blob; near_mlp_pack fills it (device, 256-byte
+ * aligned) from FP32 master parameters, the calibrated bounds ([n_bins *
+ * S2D_NEAR_CELL] as near_calibrate writes them; bound: NULL only with n_bins == 0;
+ * bound_zero NULL: never skip), the bins, b_min and the upsampling factor P
+ * the network was trained for. */
 S2D_API size_t near_mlp_blob_size(void);
 S2D_API int near_mlp_pack(const float *params, const float *bound, const float *bound_zero, int32_t n_bins,
-                          float bin_lo, float bin_w, void *blob, void *stream);
+                          float bin_lo, float bin_w, float b_min, int32_t upsample, void *blob, void *stream);
 
 /* ---- walls: spectral upsampling and the near-wall correction ------------
  *
@@ -422,22 +502,15 @@ S2D_API int stokes2d_wall_upsample(const s2d_curves *walls, double d, int32_t up
 S2D_API size_t near_wall_workspace_size(int method, const s2d_curves *walls, const s2d_targets *trg,
                                         int32_t upsample);
 
-/* The learned route for the walls (the vesicles' near-field network applied
- * to the double layer).  Features of target i relative to wall curve
- * trg_curve[i], the wall unrolled over three periods so that the nearest
- * node and the 8-node density window may lie across the period boundary:
- * X [n][20] FP32 as for near_features_eval (offsets in units of
- * h = sum w / N, log distance, kappa h, the window's densities in the local
- * frame over their largest norm F); frame [n][6] FP64 = (t0, n0, 1, F).
- * Needs the walls' w and kappa; curves with fewer than 8 nodes give NaN. */
+/* The learned route for the walls: features and frames as for
+ * near_features_eval, of target i relative to wall curve trg_curve[i], the
+ * wall unrolled over three periods so that the nearest node and its
+ * neighbours may lie across the period boundary (h = w_k*).  dtab: the
+ * walls' node derivatives (near_derivs_eval).  Needs the walls' w and kappa;
+ * curves with fewer than 8 nodes give NaN. */
 S2D_API int near_wall_features_eval(const s2d_curves *walls, const s2d_targets *trg,
-                                    const int32_t *trg_curve, double d, float *X, double *frame,
-                                    void *stream);
-
-/* Training labels for the walls: Y = (Delta . t0, Delta . n0) pi / F (the
- * double layer's correction scales with F / pi). */
-S2D_API int near_wall_scale_labels(int64_t n, const double *du, const double *dv,
-                                   const double *frame, float *Y, void *stream);
+                                    const int32_t *trg_curve, double d, const double *dtab, float *X,
+                                    double *frame, void *stream);
 
 /* Delta = D_P - D_1 of the wall double layer (Section 2.1 Eq. (D)) summed over
  * images img_lo..img_hi, at free targets (trg->on_curve must be NULL), FP64:
@@ -445,20 +518,22 @@ S2D_API int near_wall_scale_labels(int64_t n, const double *du, const double *dv
  * accumulate != 0 (so a caller adds it to the plain double layer it holds).
  * method (s2d_near_method as for near_correct_eval):
  *   UPSAMPLE: the refined-wall quadrature at every target;
- *   MLP:      the network (mlp: a blob from near_mlp_pack trained on wall
- *             labels) at every target, relative to wall trg_curve[i];
+ *   MLP:      the straight-line part and the network (mlp: a blob from
+ *             near_mlp_pack trained on wall labels with S2D_OP_DLP) at
+ *             every target, relative to wall trg_curve[i];
  *   AUTO:     per target as near_correct_eval decides (no correction, the
- *             network, or the refined quadrature, against threshold), the
- *             quadrature only at the fallback targets.  AUTO reads the
- *             fallback count back to the host (it waits for `stream`).
+ *             learned route, or the refined quadrature, against
+ *             curve_tol[trg_curve[i]] or threshold), the quadrature only at
+ *             the fallback targets.  AUTO reads the fallback count back to
+ *             the host (it waits for `stream`).
  * used_fallback: [n] device int32 or NULL, set (MLP, AUTO) to 0 network,
  * 1 quadrature, 2 no correction.  Same image and period rules as
  * stokes2d_dlp_eval. */
 S2D_API int near_wall_correct_eval(int method, const s2d_curves *walls, const s2d_targets *trg,
                                    const int32_t *trg_curve, double d, int32_t img_lo,
                                    int32_t img_hi, int32_t upsample, const void *mlp,
-                                   double threshold, double *du, double *dv,
-                                   int32_t *used_fallback, int accumulate, void *ws,
+                                   double threshold, const double *curve_tol, double *du,
+                                   double *dv, int32_t *used_fallback, int accumulate, void *ws,
                                    size_t ws_bytes, void *stream);
 
 /* Benchmarking aid (not capturable, not for production loops): while

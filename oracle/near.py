@@ -276,11 +276,12 @@ def features_one(x, y, nx, ny, kappa, w, px, py):
 
 def head_data(D, ks, fr):
     """d[p][in] in the frame (in = t, n_f) from the node-derivative table D
-    ([pmax + 1, N] per component: (Dx, Dy)), and the scale F = max |d|."""
+    ([pmax + 1, N] per component: (Dx, Dy)), and the scale F = sum |d| over
+    p and both components (1 if zero; the unit of the calibrated bounds)."""
     Dx, Dy = D
     tx, ty, nfx, nfy = fr[2], fr[3], fr[4], fr[5]
     d = np.stack([Dx[:, ks] * tx + Dy[:, ks] * ty, Dx[:, ks] * nfx + Dy[:, ks] * nfy], 1)
-    F = np.abs(d).max()
+    F = np.abs(d).sum()
     return d, (F if F > 0 else 1.0)
 
 

@@ -737,8 +737,16 @@ S2D_API int stokes2d_batch_tuned(int mode, int32_t n_inst, const s2d_instance *i
 // ---------------------------------------------------------------------------
 namespace {
 
+static_assert(S2D_NEAR_NBINS == s2d::kNearMaxBins && S2D_NEAR_SBINS == s2d::kNearSBins &&
+                  S2D_NEAR_KBINS == s2d::kNearKBins && S2D_NEAR_CELL == s2d::kNearCell,
+              "the public bin counts match the kernels'");
+static_assert(S2D_NEAR_NFEAT == s2d::kNearFeat && S2D_NEAR_NFRAME == s2d::kNearFrame &&
+                  S2D_NEAR_NDERIV == 2 * s2d::kNearDeriv && S2D_NEAR_TSTRIDE == s2d::kNearTStride &&
+                  S2D_NEAR_NOUT == s2d::kNearOut && S2D_MLP_NPARAM == s2d::MlpOffsets::total,
+              "the public near-field sizes match the kernels'");
+
 struct NearLayout {
-    size_t up, X, frame, flag, list, count, total;
+    size_t up, dtab, dscr, X, frame, flag, list, count, total;
 };
 
 NearLayout near_layout(int method, const s2d_curves *c, const s2d_targets *t, int P) {
@@ -746,11 +754,15 @@ NearLayout near_layout(int method, const s2d_curves *c, const s2d_targets *t, in
     size_t off = 0;
     L.up = off;
     if (method != S2D_NEAR_MLP) off = align256(off + 4 * ((size_t)P + 1) * (size_t)c->n_nodes * sizeof(double));
-    L.X = off;
+    L.dtab = L.dscr = L.X = off;
     if (method != S2D_NEAR_UPSAMPLE) {
+        off = align256(off + (size_t)c->n_nodes * 2 * s2d::kNearDeriv * sizeof(double));
+        L.dscr = off;
+        off = align256(off + s2d::near_derivs_scratch(c));
+        L.X = off;
         off = align256(off + (size_t)t->n * s2d::kNearFeat * sizeof(float));
         L.frame = off;
-        off = align256(off + (size_t)t->n * 6 * sizeof(double));
+        off = align256(off + (size_t)t->n * s2d::kNearFrame * sizeof(double));
         // AUTO: per-target decisions, the fallback targets' list and the
         // compaction's per-workgroup counts
         L.flag = off;
@@ -780,6 +792,15 @@ int check_near(int method, const s2d_curves *c, const s2d_targets *t, const int3
     return S2D_OK;
 }
 
+int check_curves_derivs(const s2d_curves *c) {
+    if (!c || c->n_nodes < 0 || c->n_curves < 0 || c->n_nodes > INT32_MAX / 16) return fail(S2D_EINVAL, "bad curves");
+    if (c->n_nodes > 0 && (!c->fx || !c->fy || !c->curve_off))
+        return fail(S2D_EINVAL, "curves fx, fy and curve_off must not be NULL");
+    return S2D_OK;
+}
+
+bool valid_op(int op) { return op == S2D_OP_SLP || op == S2D_OP_DLP; }
+
 }  // namespace
 
 S2D_API size_t near_workspace_size(int method, const s2d_curves *ves, const s2d_targets *trg, int32_t upsample) {
@@ -788,12 +809,14 @@ S2D_API size_t near_workspace_size(int method, const s2d_curves *ves, const s2d_
 }
 
 S2D_API int near_correct_eval(int method, const s2d_curves *ves, const s2d_targets *trg, const int32_t *trg_curve,
-                              int32_t upsample, const void *mlp, double threshold, double mu, double *du,
-                              double *dv, int32_t *used_fallback, void *ws, size_t ws_bytes, void *stream) {
+                              int32_t upsample, const void *mlp, double threshold, const double *curve_tol,
+                              double mu, double *du, double *dv, int32_t *used_fallback, void *ws, size_t ws_bytes,
+                              void *stream) {
     int rc = check_near(method, ves, trg, trg_curve, upsample, mu);
     if (rc != S2D_OK) return rc;
     if (method != S2D_NEAR_UPSAMPLE && !mlp) return fail(S2D_EINVAL, "MLP methods need the packed network");
-    if (method == S2D_NEAR_AUTO && !(threshold >= 0.0)) return fail(S2D_EINVAL, "threshold must be >= 0");
+    if (method == S2D_NEAR_AUTO && !curve_tol && !(threshold >= 0.0))
+        return fail(S2D_EINVAL, "threshold must be >= 0");
     int dev = 0;
     rc = current_device(&dev);
     if (rc != S2D_OK) return rc;
@@ -816,15 +839,18 @@ S2D_API int near_correct_eval(int method, const s2d_curves *ves, const s2d_targe
         if (e != hipSuccess) return hip_fail(e, "near quadrature launch");
         return S2D_OK;
     }
+    double *dtab = (double *)(w + L.dtab);
     float *X = (float *)(w + L.X);
     double *frame = (double *)(w + L.frame);
-    e = s2d::near_launch_features(ves, trg, trg_curve, X, frame, st);
+    e = s2d::near_launch_derivs(ves, dtab, (double *)(w + L.dscr), st);
+    if (e != hipSuccess) return hip_fail(e, "near derivative launch");
+    e = s2d::near_launch_features(ves, trg, trg_curve, dtab, X, frame, st);
     if (e != hipSuccess) return hip_fail(e, "near features launch");
     const bool autom = method == S2D_NEAR_AUTO;
     // AUTO needs the per-target decisions: the caller's array or the workspace
     int32_t *flag = used_fallback ? used_fallback : (autom ? (int32_t *)(w + L.flag) : nullptr);
-    e = s2d::near_launch_infer(trg->n, X, frame, (const s2d::NearBlob *)mlp, mu, threshold, autom ? 1 : 0, du, dv,
-                               flag, st);
+    e = s2d::near_launch_infer(S2D_OP_SLP, trg->n, X, frame, (const s2d::NearBlob *)mlp, mu, threshold, trg_curve,
+                               ves->n_curves, curve_tol, autom ? 1 : 0, du, dv, flag, st);
     if (e != hipSuccess) return hip_fail(e, "near MLP launch");
     if (autom) {
         // the fallback targets, compacted in order, so that the quadrature's
@@ -860,8 +886,7 @@ S2D_API int near_upsampled_slp(const s2d_curves *ves, const s2d_targets *trg, co
     hipError_t e = s2d::near_launch_upsample(ves, upsample, up, st);
     if (e != hipSuccess) return hip_fail(e, "near upsample launch");
     e = s2d::near_launch_quad(ves, trg, trg_curve, nullptr, nullptr, upsample, up, mu, d, d + trg->n, st, u_up, v_up,
-                              u_trap,
-                              v_trap);
+                              u_trap, v_trap);
     return e == hipSuccess ? S2D_OK : hip_fail(e, "near quadrature launch");
 }
 
@@ -870,42 +895,71 @@ S2D_API size_t near_upsampled_slp_workspace_size(const s2d_curves *ves, const s2
     return near_layout(S2D_NEAR_UPSAMPLE, ves, trg, upsample).total + align256(2 * (size_t)trg->n * sizeof(double));
 }
 
-S2D_API int near_features_eval(const s2d_curves *ves, const s2d_targets *trg, const int32_t *trg_curve, float *X,
-                               double *frame, void *stream) {
+S2D_API size_t near_derivs_workspace_size(const s2d_curves *curves) {
+    if (!curves || curves->n_nodes < 0 || curves->n_nodes > INT32_MAX / 16) return 0;
+    return std::max<size_t>(align256(s2d::near_derivs_scratch(curves)), 256);
+}
+
+S2D_API int near_derivs_eval(const s2d_curves *curves, double *dtab, void *ws, size_t ws_bytes, void *stream) {
+    int rc = check_curves_derivs(curves);
+    if (rc != S2D_OK) return rc;
+    if (curves->n_nodes > 0 && !dtab) return fail(S2D_EINVAL, "dtab must not be NULL");
+    const size_t need = s2d::near_derivs_scratch(curves);
+    if (need > 0 && (!ws || ws_bytes < need))
+        return fail(S2D_EWORKSPACE, "derivative workspace too small: need " + std::to_string(need) + " bytes");
+    if (need > 0 && ((uintptr_t)ws & 255) != 0) return fail(S2D_EWORKSPACE, "workspace must be 256-byte aligned");
+    int dev = 0;
+    rc = current_device(&dev);
+    if (rc != S2D_OK) return rc;
+    const hipError_t e = s2d::near_launch_derivs(curves, dtab, (double *)ws, (hipStream_t)stream);
+    return e == hipSuccess ? S2D_OK : hip_fail(e, "near derivative launch");
+}
+
+S2D_API int near_features_eval(const s2d_curves *ves, const s2d_targets *trg, const int32_t *trg_curve,
+                               const double *dtab, float *X, double *frame, void *stream) {
     int rc = check_near(S2D_NEAR_MLP, ves, trg, trg_curve, 1, 1.0);
     if (rc != S2D_OK) return rc;
     int dev = 0;
     rc = current_device(&dev);
     if (rc != S2D_OK) return rc;
     if (trg->n == 0) return S2D_OK;
-    if (!X || !frame) return fail(S2D_EINVAL, "X and frame must not be NULL");
-    hipError_t e = s2d::near_launch_features(ves, trg, trg_curve, X, frame, (hipStream_t)stream);
+    if (!X || !frame || (ves->n_nodes > 0 && !dtab)) return fail(S2D_EINVAL, "dtab, X and frame must not be NULL");
+    hipError_t e = s2d::near_launch_features(ves, trg, trg_curve, dtab, X, frame, (hipStream_t)stream);
     return e == hipSuccess ? S2D_OK : hip_fail(e, "near features launch");
 }
 
-S2D_API int near_scale_labels(int64_t n, const double *du, const double *dv, const double *frame, double mu,
-                              float *Y, void *stream) {
-    if (n < 0) return fail(S2D_EINVAL, "n < 0");
-    if (n > 0 && (!du || !dv || !frame || !Y)) return fail(S2D_EINVAL, "arrays must not be NULL");
+S2D_API int near_train_targets(int op, int64_t n, const double *frame, const double *du, const double *dv,
+                               const int32_t *trg_curve, int32_t n_curves, const double *u_ref,
+                               const double *v_ref, double mu, int32_t upsample, float weight_gain,
+                               float *curve_scale, float *T, void *stream) {
+    if (!valid_op(op)) return fail(S2D_EINVAL, "op must be S2D_OP_SLP or S2D_OP_DLP");
+    if (n < 0 || n > INT32_MAX || n_curves < 0) return fail(S2D_EINVAL, "sizes out of range");
+    if (n > 0 && (!frame || !du || !dv || !trg_curve || !u_ref || !v_ref || !T))
+        return fail(S2D_EINVAL, "arrays must not be NULL");
+    if (n_curves > 0 && !curve_scale) return fail(S2D_EINVAL, "curve_scale must not be NULL");
     if (!(std::isfinite(mu) && mu > 0.0)) return fail(S2D_EINVAL, "mu must be finite and > 0");
+    if (upsample < 1 || upsample > 32) return fail(S2D_EINVAL, "upsample factor must be in 1..32");
+    if (!(weight_gain > 0.f) || !std::isfinite(weight_gain)) return fail(S2D_EINVAL, "weight_gain must be > 0");
     int dev = 0;
     int rc = current_device(&dev);
     if (rc != S2D_OK) return rc;
-    hipError_t e = s2d::near_launch_scale_labels(n, du, dv, frame, mu, Y, (hipStream_t)stream);
-    return e == hipSuccess ? S2D_OK : hip_fail(e, "label scaling launch");
+    const hipError_t e =
+        s2d::near_launch_train_targets(op, n, frame, du, dv, trg_curve, n_curves, u_ref, v_ref, mu, upsample,
+                                       weight_gain, (uint32_t *)curve_scale, T, (hipStream_t)stream);
+    return e == hipSuccess ? S2D_OK : hip_fail(e, "training targets launch");
 }
 
 S2D_API size_t near_mlp_train_workspace_size(int32_t batch) {
     if (batch <= 0) return 0;
-    return align256((size_t)batch * s2d::kActStride * sizeof(float)) + align256((size_t)batch * 2 * sizeof(float)) +
-           align256((size_t)batch * sizeof(float));
+    return align256((size_t)batch * s2d::kActStride * sizeof(float)) +
+           align256((size_t)batch * s2d::kNearOut * sizeof(float)) + align256((size_t)batch * sizeof(float));
 }
 
-S2D_API int near_mlp_train_step(int32_t batch, const int32_t *idx, const float *X, const float *Y, float *params,
+S2D_API int near_mlp_train_step(int32_t batch, const int32_t *idx, const float *X, const float *T, float *params,
                                 float *adam_m, float *adam_v, int32_t step, float lr, float *grad, float *loss,
                                 void *ws, size_t ws_bytes, void *stream) {
     if (batch <= 0 || batch > (1 << 22)) return fail(S2D_EINVAL, "batch must be in 1..4194304");
-    if (!X || !Y || !params || !grad) return fail(S2D_EINVAL, "X, Y, params, grad must not be NULL");
+    if (!X || !T || !params || !grad) return fail(S2D_EINVAL, "X, T, params, grad must not be NULL");
     if (step > 0 && (!adam_m || !adam_v)) return fail(S2D_EINVAL, "Adam state must not be NULL when step > 0");
     if (step < 0) return fail(S2D_EINVAL, "step < 0");
     if (!(std::isfinite(lr) && lr >= 0.f)) return fail(S2D_EINVAL, "lr must be finite and >= 0");
@@ -918,8 +972,8 @@ S2D_API int near_mlp_train_step(int32_t batch, const int32_t *idx, const float *
     char *w = (char *)ws;
     float *act = (float *)w;
     float *dY = (float *)(w + align256((size_t)batch * s2d::kActStride * sizeof(float)));
-    float *lossv = (float *)((char *)dY + align256((size_t)batch * 2 * sizeof(float)));
-    hipError_t e = s2d::near_launch_train_step(batch, idx, X, Y, params, adam_m, adam_v, step, lr, grad, act, dY,
+    float *lossv = (float *)((char *)dY + align256((size_t)batch * s2d::kNearOut * sizeof(float)));
+    hipError_t e = s2d::near_launch_train_step(batch, idx, X, T, params, adam_m, adam_v, step, lr, grad, act, dY,
                                                lossv, loss, step > 0 ? 1 : 0, (hipStream_t)stream);
     return e == hipSuccess ? S2D_OK : hip_fail(e, "train step launch");
 }
@@ -934,19 +988,56 @@ S2D_API int near_mlp_forward(int64_t n, const float *X, const float *params, flo
     return e == hipSuccess ? S2D_OK : hip_fail(e, "MLP forward launch");
 }
 
-S2D_API size_t near_mlp_blob_size(void) { return align256(sizeof(s2d::NearBlob)); }
-
-S2D_API int near_mlp_pack(const float *params, const float *bound, const float *bound_zero, int32_t n_bins,
-                          float bin_lo, float bin_w, void *blob, void *stream) {
-    if (!params || !blob) return fail(S2D_EINVAL, "params and blob must not be NULL");
-    if (n_bins < 0 || n_bins > s2d::kNearMaxBins) return fail(S2D_EINVAL, "n_bins must be in 0..64");
-    if (n_bins > 0 && !bound) return fail(S2D_EINVAL, "bound must not be NULL when n_bins > 0");
-    if (!(bin_w > 0.f) || !std::isfinite(bin_lo)) return fail(S2D_EINVAL, "bin_w must be > 0");
+S2D_API int near_feature_stats(int64_t n, const float *X, float *params, void *stream) {
+    if (n < 0) return fail(S2D_EINVAL, "n < 0");
+    if (!params || (n > 0 && !X)) return fail(S2D_EINVAL, "X and params must not be NULL");
     int dev = 0;
     int rc = current_device(&dev);
     if (rc != S2D_OK) return rc;
-    hipError_t e = s2d::near_launch_pack(params, bound, bound_zero, n_bins, bin_lo, bin_w, (s2d::NearBlob *)blob,
-                                         (hipStream_t)stream);
+    hipError_t e = s2d::near_launch_feature_stats(n, X, params, (hipStream_t)stream);
+    return e == hipSuccess ? S2D_OK : hip_fail(e, "feature statistics launch");
+}
+
+S2D_API int near_calibrate(int op, int64_t n, const double *frame, const double *du_pred, const double *dv_pred,
+                           const double *du, const double *dv, double mu, int32_t n_bins, float bin_lo, float bin_w,
+                           float b_min, float margin, float *bound, float *bound_zero, int32_t *count,
+                           void *stream) {
+    if (!valid_op(op)) return fail(S2D_EINVAL, "op must be S2D_OP_SLP or S2D_OP_DLP");
+    if (n < 0 || n > INT32_MAX) return fail(S2D_EINVAL, "n out of range");
+    if (n > 0 && (!frame || !du_pred || !dv_pred || !du || !dv)) return fail(S2D_EINVAL, "arrays must not be NULL");
+    if (n_bins < 1 || n_bins > s2d::kNearMaxBins) return fail(S2D_EINVAL, "n_bins must be in 1..64");
+    if (!bound || !bound_zero || !count) return fail(S2D_EINVAL, "bound, bound_zero and count must not be NULL");
+    if (!(bin_w > 0.f) || !std::isfinite(bin_lo) || !std::isfinite(bin_w))
+        return fail(S2D_EINVAL, "bins: bin_w must be finite and > 0, bin_lo finite");
+    if (!(b_min >= 0.f) || !(margin >= 1.f) || !std::isfinite(margin))
+        return fail(S2D_EINVAL, "b_min must be >= 0 and margin finite and >= 1");
+    if (!(std::isfinite(mu) && mu > 0.0)) return fail(S2D_EINVAL, "mu must be finite and > 0");
+    int dev = 0;
+    int rc = current_device(&dev);
+    if (rc != S2D_OK) return rc;
+    hipError_t e = s2d::near_launch_calibrate(op, n, frame, du_pred, dv_pred, du, dv, mu, n_bins, bin_lo, bin_w, b_min,
+                                              margin, (uint32_t *)bound, (uint32_t *)bound_zero, count,
+                                              (hipStream_t)stream);
+    return e == hipSuccess ? S2D_OK : hip_fail(e, "calibration launch");
+}
+
+S2D_API size_t near_mlp_blob_size(void) { return align256(sizeof(s2d::NearBlob)); }
+
+S2D_API int near_mlp_pack(const float *params, const float *bound, const float *bound_zero, int32_t n_bins,
+                          float bin_lo, float bin_w, float b_min, int32_t upsample, void *blob, void *stream) {
+    if (!params || !blob) return fail(S2D_EINVAL, "params and blob must not be NULL");
+    if (n_bins < 0 || n_bins > s2d::kNearMaxBins) return fail(S2D_EINVAL, "n_bins must be in 0..64");
+    if (n_bins > 0 && !bound) return fail(S2D_EINVAL, "bound must not be NULL when n_bins > 0");
+    if (!(bin_w > 0.f) || !std::isfinite(bin_lo) || !std::isfinite(bin_w))
+        return fail(S2D_EINVAL, "bins: bin_w must be finite and > 0, bin_lo finite");
+    if (!(b_min >= 0.f)) return fail(S2D_EINVAL, "b_min must be >= 0");
+    if (upsample < 1 || upsample > 32) return fail(S2D_EINVAL, "upsample factor must be in 1..32");
+    if (((uintptr_t)blob & 255) != 0) return fail(S2D_EINVAL, "blob must be 256-byte aligned");
+    int dev = 0;
+    int rc = current_device(&dev);
+    if (rc != S2D_OK) return rc;
+    hipError_t e = s2d::near_launch_pack(params, bound, bound_zero, n_bins, bin_lo, bin_w, b_min, upsample,
+                                         (s2d::NearBlob *)blob, (hipStream_t)stream);
     return e == hipSuccess ? S2D_OK : hip_fail(e, "MLP pack launch");
 }
 
@@ -1018,7 +1109,7 @@ s2d::WallArgs wall_args(const s2d_curves *w, double d, int P, void *scratch, dou
 // the fallback list (MLP, AUTO), pair sums
 struct NearWallLayout {
     WallLayout up;
-    size_t t4, X, frame, flag, list, count, cxy, pair, pair_bytes, total;
+    size_t t4, dtab, dscr, X, frame, flag, list, count, cxy, pair, pair_bytes, total;
 };
 
 NearWallLayout near_wall_layout(int method, const s2d_curves *w, const s2d_targets *t, int P,
@@ -1033,10 +1124,14 @@ NearWallLayout near_wall_layout(int method, const s2d_curves *w, const s2d_targe
     L.t4 = o;
     o += align256(4 * n * sizeof(double));
     if (method != S2D_NEAR_UPSAMPLE) {
+        L.dtab = o;
+        o += align256((size_t)w->n_nodes * 2 * s2d::kNearDeriv * sizeof(double));
+        L.dscr = o;
+        o += align256(s2d::near_derivs_scratch(w));
         L.X = o;
         o += align256(n * s2d::kNearFeat * sizeof(float));
         L.frame = o;
-        o += align256(n * 6 * sizeof(double));
+        o += align256(n * s2d::kNearFrame * sizeof(double));
         L.flag = o;
         o += align256(n * sizeof(int32_t));
         L.list = o;
@@ -1111,37 +1206,27 @@ S2D_API size_t near_wall_workspace_size(int method, const s2d_curves *walls, con
 }
 
 S2D_API int near_wall_features_eval(const s2d_curves *walls, const s2d_targets *trg, const int32_t *trg_curve,
-                                    double d, float *X, double *frame, void *stream) {
+                                    double d, const double *dtab, float *X, double *frame, void *stream) {
     int rc = check_walls(walls, d, 1);
     if (rc != S2D_OK) return rc;
-    if (!trg || trg->n < 0 || (trg->n > 0 && (!trg->x || !trg->y || !trg_curve)))
+    if (!trg || trg->n < 0 || trg->n > INT32_MAX || (trg->n > 0 && (!trg->x || !trg->y || !trg_curve)))
         return fail(S2D_EINVAL, "trg x, y and trg_curve must not be NULL");
-    if (walls->n_nodes > 0 && (!walls->w || !walls->kappa))
-        return fail(S2D_EINVAL, "the features need the walls' w and kappa");
+    if (walls->n_nodes > 0 && (!walls->w || !walls->kappa || !dtab))
+        return fail(S2D_EINVAL, "the features need the walls' w, kappa and derivative table");
     if (trg->n > 0 && (!X || !frame)) return fail(S2D_EINVAL, "X and frame must not be NULL");
     int dev = 0;
     rc = current_device(&dev);
     if (rc != S2D_OK || trg->n == 0) return rc;
-    const hipError_t e = s2d::near_launch_wall_features(walls, trg, trg_curve, d, X, frame, (hipStream_t)stream);
-    return e == hipSuccess ? S2D_OK : hip_fail(e, "near-wall features launch");
-}
-
-S2D_API int near_wall_scale_labels(int64_t n, const double *du, const double *dv, const double *frame, float *Y,
-                                   void *stream) {
-    if (n < 0 || (n > 0 && (!du || !dv || !frame || !Y))) return fail(S2D_EINVAL, "bad label arguments");
-    int dev = 0;
-    int rc = current_device(&dev);
-    if (rc != S2D_OK || n == 0) return rc;
     const hipError_t e =
-        s2d::near_launch_scale_labels(n, du, dv, frame, s2d::kWallMuScale, Y, (hipStream_t)stream);
-    return e == hipSuccess ? S2D_OK : hip_fail(e, "near-wall labels launch");
+        s2d::near_launch_wall_features(walls, trg, trg_curve, d, dtab, X, frame, (hipStream_t)stream);
+    return e == hipSuccess ? S2D_OK : hip_fail(e, "near-wall features launch");
 }
 
 S2D_API int near_wall_correct_eval(int method, const s2d_curves *walls, const s2d_targets *trg,
                                    const int32_t *trg_curve, double d, int32_t img_lo, int32_t img_hi,
-                                   int32_t upsample, const void *mlp, double threshold, double *du, double *dv,
-                                   int32_t *used_fallback, int accumulate, void *ws, size_t ws_bytes,
-                                   void *stream) {
+                                   int32_t upsample, const void *mlp, double threshold, const double *curve_tol,
+                                   double *du, double *dv, int32_t *used_fallback, int accumulate, void *ws,
+                                   size_t ws_bytes, void *stream) {
     if (method < S2D_NEAR_UPSAMPLE || method > S2D_NEAR_AUTO) return fail(S2D_EINVAL, "unknown near method");
     int rc = check_walls(walls, d, upsample);
     if (rc != S2D_OK) return rc;
@@ -1155,7 +1240,8 @@ S2D_API int near_wall_correct_eval(int method, const s2d_curves *walls, const s2
         if (walls->n_nodes > 0 && (!walls->w || !walls->kappa))
             return fail(S2D_EINVAL, "MLP methods need the walls' w and kappa");
     }
-    if (method == S2D_NEAR_AUTO && !(threshold >= 0.0)) return fail(S2D_EINVAL, "threshold must be >= 0");
+    if (method == S2D_NEAR_AUTO && !curve_tol && !(threshold >= 0.0))
+        return fail(S2D_EINVAL, "threshold must be >= 0");
     int dev = 0;
     rc = current_device(&dev);
     if (rc != S2D_OK) return rc;
@@ -1206,16 +1292,20 @@ S2D_API int near_wall_correct_eval(int method, const s2d_curves *walls, const s2
         e = s2d::delta_combine_launch(n, accumulate, du, dv, t4, st);
         return e == hipSuccess ? S2D_OK : hip_fail(e, "near-wall combine launch");
     }
-    // MLP, AUTO: features, then the network (AUTO: with the per-bin decision)
+    // MLP, AUTO: density derivatives, features, then the straight-line
+    // coefficients and the network (AUTO: with the per-bin decision)
+    double *dtab = (double *)(base + L.dtab);
     float *X = (float *)(base + L.X);
     double *frame = (double *)(base + L.frame);
-    e = s2d::near_launch_wall_features(walls, trg, trg_curve, d, X, frame, st);
+    e = s2d::near_launch_derivs(walls, dtab, (double *)(base + L.dscr), st);
+    if (e != hipSuccess) return hip_fail(e, "near-wall derivative launch");
+    e = s2d::near_launch_wall_features(walls, trg, trg_curve, d, dtab, X, frame, st);
     if (e != hipSuccess) return hip_fail(e, "near-wall features launch");
     const bool autom = method == S2D_NEAR_AUTO;
     int32_t *flag = used_fallback ? used_fallback : (autom ? (int32_t *)(base + L.flag) : nullptr);
     double *tu = t4, *tv = t4 + n;
-    e = s2d::near_launch_infer(n, X, frame, (const s2d::NearBlob *)mlp, s2d::kWallMuScale, threshold, autom ? 1 : 0,
-                               tu, tv, flag, st);
+    e = s2d::near_launch_infer(S2D_OP_DLP, n, X, frame, (const s2d::NearBlob *)mlp, 1.0, threshold, trg_curve,
+                               walls->n_curves, curve_tol, autom ? 1 : 0, tu, tv, flag, st);
     if (e != hipSuccess) return hip_fail(e, "near-wall MLP launch");
     if (autom) {
         // the fallback targets: the refined quadrature at a compacted list
@@ -1231,8 +1321,8 @@ S2D_API int near_wall_correct_eval(int method, const s2d_curves *walls, const s2
             if ((rc = refine()) != S2D_OK) return rc;
             // fine and coarse sums of the m targets into the feature area
             // (the features are no longer needed)
-            static_assert(s2d::kNearFeat * sizeof(float) >= 4 * sizeof(double), "four doubles per target fit in X");
-            double *f4 = (double *)(base + L.X);
+            static_assert(s2d::kNearFrame * sizeof(double) >= 4 * sizeof(double), "four doubles per target fit");
+            double *f4 = (double *)(base + L.frame);
             const s2d_targets tl{m, cx, cy, nullptr, nullptr};
             rc = eval(S2D_OP_DLP, S2D_FP64, &fine, &tl, d, img_lo, img_hi, 1.0, f4, f4 + m, 0, base + L.pair,
                       L.pair_bytes, stream);

@@ -15,17 +15,18 @@
 //    from the spectral derivative, weights (2 pi / (P N)) |x'|.  FP64.
 //  * quadrature: per target, the fine trapezoid sum minus the coarse one,
 //    FP64, over the target's own curve.
-//  * features: per target, nearest node k* by a scan of the curve, k0 = k* or
-//    k* - 1 so that the target lies over [k0, k0+1), the local frame of k0,
-//    offsets in units of h = (sum w) / N, ln(distance / h), kappa h, and the
-//    densities of nodes k0-3..k0+4 rotated into the frame and divided by
-//    their largest norm F.
-//  * MLP inference: 20 -> 64 -> 64 -> 64 -> 2, tanh-form GELU; weights and
-//    activations rounded to BF16, products accumulated in FP32 on the matrix
-//    cores (v_mfma_f32_32x32x8_bf16, 32 targets per wave).  The output is the
-//    correction in the local frame in units of h F / (4 pi mu).  A per-bin
-//    error bound (bins in the normal offset) calibrated on validation data
-//    decides the fallback to the upsampled quadrature.
+//  * learned correction: the density's node derivatives d_p (p = 0..4) per
+//    curve; per target its nearest node k*, the frame of k* (tangent along
+//    the node order, normal towards the target), offsets (s, b) in units of
+//    the local spacing and 14 geometry features; the correction is
+//    Delta = scale sum_p (Cflat_p(s, b) + exp(-2 pi b) dC_p) d_p, with Cflat
+//    the exact correction of a straight line with equispaced nodes (closed
+//    form, by Poisson summation) and dC the output of a 14 -> 64 -> 64 -> 64
+//    -> 20 tanh-form GELU network, weights and activations rounded to BF16,
+//    products accumulated in FP32 on the matrix cores
+//    (v_mfma_f32_32x32x8_bf16, 32 targets per wave).  A per-bin error bound
+//    (bins in log10 b) calibrated on held-out data decides between no
+//    correction, the network and the upsampled quadrature.
 //  * training (FP32 master weights): forward and backward deltas with a wave
 //    per sample and a lane per neuron, per-weight gradient sums over the batch
 //    in fixed order, and an Adam update; all deterministic.
@@ -363,27 +364,277 @@ __global__ __launch_bounds__(kCompactBlock) void near_compact_scatter(int64_t n,
 }
 
 // ---------------------------------------------------------------------------
-// a9: features
+// a9: the learned correction's inputs
 // ---------------------------------------------------------------------------
-// nearest node k* of the curve at [lo, lo + N) and the curve's weight sum;
+// The correction Delta is linear in the density, and the trapezoid rules see
+// the density only through its trigonometric interpolant.  Near the target's
+// nearest node k* the interpolant is summarised by its derivatives there,
+// d_p = (2 pi / N)^p d^p f / dt^p (p = 0..4, per-node units), and
+//   Delta = scale * sum_p (Cflat_p(s, b) + exp(-2 pi b) dC_p) d_p
+// in the frame (t, n) of k*: t along growing node index, n the normal turned
+// towards the target, lengths in units of the local spacing hl = w_k*,
+// (s, b) the target's offsets, scale = hl / 4 pi mu (single layer) or 1 / pi
+// (double layer).  Cflat_p is the exact correction of a straight line with
+// equispaced nodes (closed form, flat_* below), dC_p the network's output.
+
+// Node derivatives of the density, one workgroup per curve (even N, 4 <= N <=
+// kUpMaxN; larger even curves go to the kernels below): the interpolant's coefficients a_m, b_m (m = 0..N/2, the Nyquist
+// mode's weight split evenly), then at each node sum_m (m h)^p times the p-th
+// derivative of a_m cos(m t) + b_m sin(m t) at t_k (h = 2 pi / N; the
+// Nyquist term keeps its even derivatives only: the odd ones vanish at the
+// nodes).  Angles come from a table of cos, sin(2 pi j / N) indexed by
+// (m k) mod N.  Invalid curves get NaN.
+__global__ __launch_bounds__(256) void near_derivs(const int32_t *__restrict__ off, int32_t n_curves, int64_t n_src,
+                                                   const double *__restrict__ fx, const double *__restrict__ fy,
+                                                   double *__restrict__ dtab) {
+    __shared__ double cs[kUpMaxN], sn[kUpMaxN];
+    __shared__ double co[2][kUpMaxN / 2 + 1][2];
+    const int c = blockIdx.x;
+    if (c >= n_curves) return;
+    const int lo = off[c], N = off[c + 1] - lo;
+    if (lo < 0 || N <= 0 || (int64_t)lo + N > n_src) return;          // no rows of its own to fill
+    if (N > kUpMaxN && !(N & 1)) return;                              // the large-curve kernels' work
+    if (N < 4 || (N & 1)) {
+        for (int q = threadIdx.x; q < N * 2 * kNearDeriv; q += blockDim.x)
+            dtab[(int64_t)lo * 2 * kNearDeriv + q] = __builtin_nan("");
+        return;
+    }
+    const int H = N / 2;
+    for (int j = threadIdx.x; j < N; j += blockDim.x) sincospi(2.0 * (double)j / (double)N, &sn[j], &cs[j]);
+    __syncthreads();
+    for (int q = threadIdx.x; q < 2 * (H + 1); q += blockDim.x) {
+        const int comp = q / (H + 1), m = q % (H + 1);
+        const double *f = (comp ? fy : fx) + lo;
+        double a = 0.0, b = 0.0;
+        for (int k = 0; k < N; ++k) {
+            const int j = (int)(((int64_t)m * k) % N);
+            a = __builtin_fma(f[k], cs[j], a);
+            b = __builtin_fma(f[k], sn[j], b);
+        }
+        const double sc = (m == 0 || m == H) ? 1.0 / N : 2.0 / N;
+        co[comp][m][0] = a * sc;
+        co[comp][m][1] = (m == 0 || m == H) ? 0.0 : b * sc;
+    }
+    __syncthreads();
+    const double h = 2.0 * M_PI / (double)N;
+    for (int q = threadIdx.x; q < N * 2 * kNearDeriv; q += blockDim.x) {
+        const int k = q / (2 * kNearDeriv), r = q % (2 * kNearDeriv), p = r / 2, comp = r % 2;
+        double v = p == 0 ? co[comp][0][0] : 0.0;
+        for (int m = 1; m <= H; ++m) {
+            if (m == H && (p & 1)) break;
+            const int j = (int)(((int64_t)m * k) % N);
+            // p-th derivatives of cos and sin: cos(x + p pi / 2), sin(x + p pi / 2)
+            double dc, ds;
+            switch (p & 3) {
+            case 0: dc = cs[j]; ds = sn[j]; break;
+            case 1: dc = -sn[j]; ds = cs[j]; break;
+            case 2: dc = -cs[j]; ds = -sn[j]; break;
+            default: dc = sn[j]; ds = -cs[j]; break;
+            }
+            double mp = 1.0;
+            for (int e = 0; e < p; ++e) mp *= (double)m * h;
+            v = __builtin_fma(mp, __builtin_fma(co[comp][m][0], dc, co[comp][m][1] * ds), v);
+        }
+        dtab[((int64_t)lo + k) * 2 * kNearDeriv + r] = v;
+    }
+}
+
+// The same derivatives for curves of more than kUpMaxN nodes (walls of
+// thousands of nodes), spread over the chip: the table of cos, sin(2 pi j /
+// N) (row lo + j), then one wave per coefficient m (row lo + m, m <= N/2 <
+// N) summing over the nodes in lane-strided order, then one wave per node
+// summing over the modes.  Wave partial sums are added by a fixed butterfly.
+__device__ __forceinline__ int curve_of(const int32_t *__restrict__ off, int n_curves, int64_t q) {
+    int lo = 0, hi = n_curves - 1;                       // last c with off[c] <= q
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((int64_t)off[mid] <= q) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// the curve of row q and its range, if it is a valid curve of more than
+// kUpMaxN (even) nodes
+__device__ __forceinline__ bool big_curve(const int32_t *__restrict__ off, int32_t n_curves, int64_t n_src, int64_t q,
+                                          int &lo, int &N) {
+    if (n_curves <= 0 || q >= n_src) return false;
+    const int c = curve_of(off, n_curves, q);
+    lo = off[c];
+    N = off[c + 1] - lo;
+    return lo >= 0 && (int64_t)lo + N <= n_src && q >= lo && q < (int64_t)lo + N && N > kUpMaxN && !(N & 1);
+}
+
+__global__ __launch_bounds__(256) void near_derivs_table(const int32_t *__restrict__ off, int32_t n_curves,
+                                                         int64_t n_src, double *__restrict__ tab) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int lo, N;
+    if (!big_curve(off, n_curves, n_src, q, lo, N)) return;
+    double sv, cv;
+    sincospi(2.0 * (double)(q - lo) / (double)N, &sv, &cv);
+    tab[2 * q] = cv;
+    tab[2 * q + 1] = sv;
+}
+
+// coefficients {a_x, b_x, a_y, b_y} of mode m at coef[4 (lo + m)]
+__global__ __launch_bounds__(256) void near_derivs_coef(const int32_t *__restrict__ off, int32_t n_curves,
+                                                        int64_t n_src, const double *__restrict__ fx,
+                                                        const double *__restrict__ fy,
+                                                        const double *__restrict__ tab, double *__restrict__ coef) {
+    const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;      // wave-uniform
+    const int lane = threadIdx.x & (kWave - 1);
+    int lo, N;
+    if (!big_curve(off, n_curves, n_src, q, lo, N)) return;
+    const int H = N / 2, m = (int)(q - lo);
+    if (m > H) return;
+    double ax = 0.0, bx = 0.0, ay = 0.0, by = 0.0;
+    for (int k = lane; k < N; k += kWave) {
+        const int64_t j = lo + ((int64_t)m * k) % N;
+        const double c = tab[2 * j], sn = tab[2 * j + 1];
+        ax = __builtin_fma(fx[lo + k], c, ax);
+        bx = __builtin_fma(fx[lo + k], sn, bx);
+        ay = __builtin_fma(fy[lo + k], c, ay);
+        by = __builtin_fma(fy[lo + k], sn, by);
+    }
+    ax = wave_sum_d(ax);
+    bx = wave_sum_d(bx);
+    ay = wave_sum_d(ay);
+    by = wave_sum_d(by);
+    if (lane == 0) {
+        const bool edge = m == 0 || m == H;
+        const double sc = edge ? 1.0 / N : 2.0 / N;
+        coef[4 * q] = ax * sc;
+        coef[4 * q + 1] = edge ? 0.0 : bx * sc;
+        coef[4 * q + 2] = ay * sc;
+        coef[4 * q + 3] = edge ? 0.0 : by * sc;
+    }
+}
+
+__global__ __launch_bounds__(256) void near_derivs_nodes(const int32_t *__restrict__ off, int32_t n_curves,
+                                                         int64_t n_src, const double *__restrict__ tab,
+                                                         const double *__restrict__ coef, double *__restrict__ dtab) {
+    const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;      // wave-uniform
+    const int lane = threadIdx.x & (kWave - 1);
+    int lo, N;
+    if (!big_curve(off, n_curves, n_src, q, lo, N)) return;
+    const int H = N / 2, k = (int)(q - lo);
+    const double h = 2.0 * M_PI / (double)N;
+    double acc[2 * kNearDeriv];
+#pragma unroll
+    for (int r = 0; r < 2 * kNearDeriv; ++r) acc[r] = 0.0;
+    for (int m = 1 + lane; m <= H; m += kWave) {
+        const int64_t j = lo + ((int64_t)m * k) % N;
+        const double c = tab[2 * j], sn = tab[2 * j + 1];
+        const double *co = coef + 4 * ((int64_t)lo + m);
+        // (m h)^p times the p-th derivative of a cos + b sin: the derivatives
+        // cycle through (c, s), (-s, c), (-c, -s), (s, -c)
+        const double gx0 = __builtin_fma(co[0], c, co[1] * sn), gx1 = __builtin_fma(-co[0], sn, co[1] * c);
+        const double gy0 = __builtin_fma(co[2], c, co[3] * sn), gy1 = __builtin_fma(-co[2], sn, co[3] * c);
+        const double mh = (double)m * h;
+        double mp = 1.0;
+#pragma unroll
+        for (int p = 0; p < kNearDeriv; ++p) {
+            if (!(m == H && (p & 1))) {
+                const double sg = (p & 2) ? -1.0 : 1.0;
+                acc[2 * p] = __builtin_fma(mp, sg * ((p & 1) ? gx1 : gx0), acc[2 * p]);
+                acc[2 * p + 1] = __builtin_fma(mp, sg * ((p & 1) ? gy1 : gy0), acc[2 * p + 1]);
+            }
+            mp *= mh;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 2 * kNearDeriv; ++r) acc[r] = wave_sum_d(acc[r]);
+    if (lane == 0) {
+        acc[0] += coef[4 * (int64_t)lo];
+        acc[1] += coef[4 * (int64_t)lo + 2];
+#pragma unroll
+        for (int r = 0; r < 2 * kNearDeriv; ++r) dtab[q * 2 * kNearDeriv + r] = acc[r];
+    }
+}
+
+// Geometry features and frame of a target p whose nearest node is at (X, Y)
+// with unit normal (NX, NY), curvature kap and spacing hl, nb[j] the nodes
+// k* - 2, k* - 1, k* + 1, k* + 2: xi = [s, b, ln(|p - x_k*| / hl), sg kap hl,
+// the four nodes in the frame (units hl), Re Q, Im Q], Q = exp(-2 pi (b + i s));
+// fr[0..8] = s, b, t, n_f, hl, (F later), sg; fr[19] = sg kap hl.
+__device__ void near_frame_features(double px, double py, double X, double Y, double NX, double NY, double kap,
+                                    double hl, const double (&nb)[4][2], float *__restrict__ xi,
+                                    double *__restrict__ fr) {
+    const double st = ((nb[2][0] - nb[1][0]) * -NY + (nb[2][1] - nb[1][1]) * NX) >= 0.0 ? 1.0 : -1.0;
+    const double tx = -st * NY, ty = st * NX;
+    const double ox = px - X, oy = py - Y;
+    const double sv = (ox * tx + oy * ty) / hl;
+    const double nv = (ox * NX + oy * NY) / hl;
+    const double sg = nv >= 0.0 ? 1.0 : -1.0;
+    const double nfx = sg * NX, nfy = sg * NY;
+    const double b = sg * nv;
+    xi[0] = (float)sv;
+    xi[1] = (float)b;
+    xi[2] = (float)log(sqrt(ox * ox + oy * oy) / hl);
+    xi[3] = (float)(sg * kap * hl);
+    for (int j = 0; j < 4; ++j) {
+        const double gx = nb[j][0] - X, gy = nb[j][1] - Y;
+        xi[4 + 2 * j] = (float)((gx * tx + gy * ty) / hl);
+        xi[5 + 2 * j] = (float)((gx * nfx + gy * nfy) / hl);
+    }
+    double sq, cq;
+    sincospi(-2.0 * sv, &sq, &cq);
+    const double aq = exp(-2.0 * M_PI * b);
+    xi[12] = (float)(aq * cq);
+    xi[13] = (float)(aq * sq);
+    fr[0] = sv;
+    fr[1] = b;
+    fr[2] = tx;
+    fr[3] = ty;
+    fr[4] = nfx;
+    fr[5] = nfy;
+    fr[6] = hl;
+    fr[8] = sg;
+    fr[kNearFrame - 1] = sg * kap * hl;
+}
+
+// the density's derivatives at the node (row of the derivative table) in
+// the frame, and F = sum |d| over p and both components (1 if zero): the
+// unit of AUTO's calibrated bounds
+__device__ void near_frame_head(const double *__restrict__ drow, double *__restrict__ fr) {
+    double F = 0.0;
+#pragma unroll
+    for (int p = 0; p < kNearDeriv; ++p) {
+        const double dx = drow[2 * p], dy = drow[2 * p + 1];
+        const double dt = dx * fr[2] + dy * fr[3], dn = dx * fr[4] + dy * fr[5];
+        fr[9 + 2 * p] = dt;
+        fr[10 + 2 * p] = dn;
+        F += fabs(dt) + fabs(dn);
+    }
+    fr[7] = F > 0.0 ? F : 1.0;
+}
+
+__device__ void near_invalid(float *__restrict__ xi, double *__restrict__ fr) {
+    for (int k = 0; k < kNearFeat; ++k) xi[k] = __builtin_nanf("");
+    for (int k = 0; k < kNearFrame; ++k) fr[k] = __builtin_nan("");
+}
+
+// nearest node k* (smallest index on ties) of the curve at [lo, lo + N);
 // UNIFORM: lo and N are the same in every lane (loads take the scalar path)
 template <bool UNIFORM>
 __device__ __forceinline__ int near_scan(double px, double py, int lo, int N, const double *__restrict__ x,
-                                         const double *__restrict__ y, const double *__restrict__ w, double &best,
-                                         double &wsum) {
+                                         const double *__restrict__ y, double &best) {
     if (UNIFORM) {
         lo = __builtin_amdgcn_readfirstlane(lo);
         N = __builtin_amdgcn_readfirstlane(N);
     }
     best = 1e300;
-    wsum = 0.0;
     int ks = 0;
 #pragma unroll 4
     for (int k = 0; k < N; ++k) {
         const double dx = px - x[lo + k], dy = py - y[lo + k];
         const double d2 = dx * dx + dy * dy;
         if (d2 < best) { best = d2; ks = k; }
-        wsum += w[lo + k];
     }
     return ks;
 }
@@ -394,8 +645,8 @@ __global__ __launch_bounds__(256) void near_features(int64_t n_trg, const double
                                                      const double *__restrict__ x, const double *__restrict__ y,
                                                      const double *__restrict__ nx, const double *__restrict__ ny,
                                                      const double *__restrict__ kap, const double *__restrict__ w,
-                                                     const double *__restrict__ fx, const double *__restrict__ fy,
-                                                     float *__restrict__ X, double *__restrict__ frame) {
+                                                     const double *__restrict__ dtab, float *__restrict__ X,
+                                                     double *__restrict__ frame) {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = q < n_trg;
     const int64_t i = live ? q : 0;
@@ -409,59 +660,35 @@ __global__ __launch_bounds__(256) void near_features(int64_t n_trg, const double
     const int cmin = wave_min(cl);
     const bool uniform = cmin != INT_MAX && __all(!live || (ok && c == cmin));
     const double px = live ? tx[i] : 0.0, py = live ? ty[i] : 0.0;
-    double best = 0.0, wsum = 0.0;
+    double best = 0.0;
     int ks = 0;
     if (uniform) {
         const int cu = __builtin_amdgcn_readfirstlane(cmin);
         const int lou = off[cu];
-        ks = near_scan<true>(px, py, lou, off[cu + 1] - lou, x, y, w, best, wsum);
+        ks = near_scan<true>(px, py, lou, off[cu + 1] - lou, x, y, best);
     } else if (ok) {
-        ks = near_scan<false>(px, py, lo, N, x, y, w, best, wsum);
+        ks = near_scan<false>(px, py, lo, N, x, y, best);
     }
     if (!live) return;
     float *xi = X + i * kNearFeat;
-    double *fr = frame + i * 6;
+    double *fr = frame + i * kNearFrame;
     if (!ok) {
-        for (int k = 0; k < kNearFeat; ++k) xi[k] = __builtin_nanf("");
-        for (int k = 0; k < 6; ++k) fr[k] = __builtin_nan("");
+        near_invalid(xi, fr);
         return;
     }
-    const double h = wsum / (double)N;
-    const double ts0 = -ny[lo + ks], ts1 = nx[lo + ks];
-    const int k0 = ((px - x[lo + ks]) * ts0 + (py - y[lo + ks]) * ts1 >= 0.0) ? ks : (ks + N - 1) % N;
-    const double t0 = -ny[lo + k0], t1 = nx[lo + k0];
-    const double n0 = nx[lo + k0], n1 = ny[lo + k0];
-    const double ox = px - x[lo + k0], oy = py - y[lo + k0];
-    double ft[8], fn[8], F = 0.0;
-    for (int j = 0; j < 8; ++j) {
-        const int k = lo + (k0 + j - 3 + N) % N;
-        ft[j] = fx[k] * t0 + fy[k] * t1;
-        fn[j] = fx[k] * n0 + fy[k] * n1;
-        F = fmax(F, sqrt(ft[j] * ft[j] + fn[j] * fn[j]));
+    double nb[4][2];
+    const int js[4] = {-2, -1, 1, 2};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int k = lo + (ks + js[j] + N) % N;
+        nb[j][0] = x[k];
+        nb[j][1] = y[k];
     }
-    if (F == 0.0) F = 1.0;
-    xi[0] = (float)((ox * t0 + oy * t1) / h);
-    xi[1] = (float)((ox * n0 + oy * n1) / h);
-    xi[2] = (float)log(sqrt(best) / h);
-    xi[3] = (float)(kap[lo + k0] * h);
-    for (int j = 0; j < 8; ++j) {
-        xi[4 + j] = (float)(ft[j] / F);
-        xi[12 + j] = (float)(fn[j] / F);
-    }
-    fr[0] = t0;
-    fr[1] = t1;
-    fr[2] = n0;
-    fr[3] = n1;
-    fr[4] = h;
-    fr[5] = F;
+    const int k = lo + ks;
+    near_frame_features(px, py, x[k], y[k], nx[k], ny[k], kap[k], w[k], nb, xi, fr);
+    near_frame_head(dtab + (int64_t)k * 2 * kNearDeriv, fr);
 }
 
-// a9 for the walls: target i near one period of wall curve tc[i] (N >= 8
-// nodes advancing by sg d in x), the wall unrolled over three periods (node
-// K in [-N, 2N) at (x_{K mod N} + sg d floor(K / N), y_{K mod N})); nearest
-// unrolled node with the smallest K on ties, then the same features as for
-// closed curves; frame (t0, n0, 1, F): the double layer's correction scales
-// with F alone
 // Nearest-node search over the three periods of a wall.  Nodes are grouped in
 // cells of kWallCell consecutive nodes; a cell's centre is its middle node and
 // its radius the largest distance of its nodes from that centre.  The search is
@@ -607,8 +834,13 @@ __device__ int wall_nearest(const WallCells &W, bool cells, int c, int lo, int N
     return ks;
 }
 
+
 // Features of targets near periodic walls (grid-stride over targets; the cell
-// table is built once per block in LDS).
+// table is built once per block in LDS): one period of wall curve tc[i] (N >=
+// 8 nodes advancing by sgd d in x), unrolled over three periods (node K in
+// [-N, 2N) at (x_{K mod N} + sgd d floor(K / N), y_{K mod N})); the nearest
+// unrolled node k* (smallest K on ties) and its unrolled neighbours give the
+// features as for closed curves.
 __global__ __launch_bounds__(256) void near_wall_features(int64_t n_trg, const double *__restrict__ tx,
                                                           const double *__restrict__ ty,
                                                           const int32_t *__restrict__ tc,
@@ -618,10 +850,9 @@ __global__ __launch_bounds__(256) void near_wall_features(int64_t n_trg, const d
                                                           const double *__restrict__ nx,
                                                           const double *__restrict__ ny,
                                                           const double *__restrict__ kap,
-                                                          const double *__restrict__ w,
-                                                          const double *__restrict__ fx,
-                                                          const double *__restrict__ fy, double d,
-                                                          float *__restrict__ X, double *__restrict__ frame) {
+                                                          const double *__restrict__ w, double d,
+                                                          const double *__restrict__ dtab, float *__restrict__ X,
+                                                          double *__restrict__ frame) {
     __shared__ WallCells W;
     wall_cells_build(W, off, n_curves, n_src, x, y, w);
     const bool cells = W.ok != 0;
@@ -630,68 +861,161 @@ __global__ __launch_bounds__(256) void near_wall_features(int64_t n_trg, const d
         const int lo = (c >= 0 && c < n_curves) ? off[c] : 0;
         const int N = (c >= 0 && c < n_curves) ? off[c + 1] - lo : 0;
         float *xi = X + i * kNearFeat;
-        double *fr = frame + i * 6;
+        double *fr = frame + i * kNearFrame;
         if (c < 0 || c >= n_curves || N < 8 || lo < 0 || (int64_t)lo + N > n_src) {
-            for (int k = 0; k < kNearFeat; ++k) xi[k] = __builtin_nanf("");
-            for (int k = 0; k < 6; ++k) fr[k] = __builtin_nan("");
+            near_invalid(xi, fr);
             continue;
         }
-        const double sg = x[lo + 1] > x[lo] ? 1.0 : -1.0;
+        const double sgd = x[lo + 1] > x[lo] ? 1.0 : -1.0;
         const double px = tx[i], py = ty[i];
-        double best = 0.0, h = 0.0;
-        if (cells) {
-            h = W.h[c];
-        } else {
-            for (int k = 0; k < N; ++k) h += w[lo + k];
-            h /= (double)N;
-        }
-        const int ks = wall_nearest(W, cells, c, lo, N, sg, d, px, py, x, y, best);
+        double best = 0.0;
+        const int ks = wall_nearest(W, cells, c, lo, N, sgd, d, px, py, x, y, best);
         const auto md = [N](int K) { return ((K % N) + N) % N; };
         const auto fl = [N](int K) { return K >= 0 ? K / N : -((-K + N - 1) / N); };
-        const int ms = md(ks);
-        const double xs = x[lo + ms] + sg * d * (double)fl(ks), ys = y[lo + ms];
-        const double ts0 = -ny[lo + ms], ts1 = nx[lo + ms];
-        const int k0 = ((px - xs) * ts0 + (py - ys) * ts1 >= 0.0) ? ks : ks - 1;
-        const int m0 = md(k0);
-        const double t0 = -ny[lo + m0], t1 = nx[lo + m0];
-        const double n0 = nx[lo + m0], n1 = ny[lo + m0];
-        const double ox = px - (x[lo + m0] + sg * d * (double)fl(k0)), oy = py - y[lo + m0];
-        double ft[8], fn[8], F = 0.0;
-        for (int j = 0; j < 8; ++j) {
-            const int k = lo + md(k0 + j - 3);
-            ft[j] = fx[k] * t0 + fy[k] * t1;
-            fn[j] = fx[k] * n0 + fy[k] * n1;
-            F = fmax(F, sqrt(ft[j] * ft[j] + fn[j] * fn[j]));
+        double nb[4][2];
+        const int js[4] = {-2, -1, 1, 2};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int K = ks + js[j];
+            nb[j][0] = x[lo + md(K)] + sgd * d * (double)fl(K);
+            nb[j][1] = y[lo + md(K)];
         }
-        if (F == 0.0) F = 1.0;
-        xi[0] = (float)((ox * t0 + oy * t1) / h);
-        xi[1] = (float)((ox * n0 + oy * n1) / h);
-        xi[2] = (float)log(sqrt(best) / h);
-        xi[3] = (float)(kap[lo + m0] * h);
-        for (int j = 0; j < 8; ++j) {
-            xi[4 + j] = (float)(ft[j] / F);
-            xi[12 + j] = (float)(fn[j] / F);
-        }
-        fr[0] = t0;
-        fr[1] = t1;
-        fr[2] = n0;
-        fr[3] = n1;
-        fr[4] = 1.0;
-        fr[5] = F;
+        const int m = lo + md(ks);
+        near_frame_features(px, py, x[m] + sgd * d * (double)fl(ks), y[m], nx[m], ny[m], kap[m], w[m], nb, xi, fr);
+        near_frame_head(dtab + (int64_t)m * 2 * kNearDeriv, fr);
     }
 }
 
-// scaled labels in the local frame: (Delta . t0, Delta . n0) * 4 pi mu / (h F)
-__global__ __launch_bounds__(256) void near_scale_labels_k(int64_t n, const double *__restrict__ du,
-                                                           const double *__restrict__ dv,
-                                                           const double *__restrict__ frame, double mu,
-                                                           float *__restrict__ Y) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double *fr = frame + 6 * i;
-    const double sc = 4.0 * M_PI * mu / (fr[4] * fr[5]);
-    Y[2 * i] = (float)((du[i] * fr[0] + dv[i] * fr[1]) * sc);
-    Y[2 * i + 1] = (float)((du[i] * fr[2] + dv[i] * fr[3]) * sc);
+// ---------------------------------------------------------------------------
+// the straight-line coefficients (closed form)
+// ---------------------------------------------------------------------------
+// On the line y = 0 with nodes at the integers (weight 1), density tau^p / p!,
+// target (s, b), b > 0, the error of the trapezoid rule of spacing D is, by
+// Poisson summation, sum_{l != 0} g^(2 pi l / D).  For the single-layer
+// kernel (-1/2 log q + a^2/q, a b/q, -1/2 log q + b^2/q with a = s - tau,
+// q = a^2 + b^2) the transforms are e^{-i w s - b |w|} times pi/|w| - pi b,
+// i pi b sgn(w), pi/|w| + pi b; multiplying by tau^p is (i d/dw)^p, pairs
+// l, -l are complex conjugates, and the sums over l are polylogarithms of
+// Q = exp(-c z), c = 2 pi / D, z = b + i s:
+//   S1_p = pi sum_j C(p, j) (-z)^(p-j) (-1)^j j! c^-(j+1) Li_{j+1}(Q),
+//   S0_p = (-z)^p Li_0(Q),
+//   E_TT = (2/p!) Re[i^p (S1_p - pi b S0_p)], E_NN = (2/p!) Re[i^p (S1_p + pi b S0_p)],
+//   E_TN = (2/p!) Re[i^(p+1) pi b S0_p].
+// Li_0 = Q / (1 - Q) and Li_1 = -log(1 - Q) are closed; Li_2..Li_5 are their
+// series, truncated after L terms (|Q| = exp(-2 pi b / D)).  The double
+// layer's kernel b r r^T / q^2 has the transforms (pi/2)(1 - b|w|),
+// i (pi/2) b w, (pi/2)(1 + b|w|) times the same phase, polynomial in w: its
+// sums need only Li_0 and Li_-1 = Q / (1 - Q)^2.  Each rule's coefficients
+// are returned contracted with the density derivatives d[p][in] (frame).
+struct Cx {
+    double re, im;
+};
+__device__ __forceinline__ Cx cx_mul(Cx a, Cx b) {
+    return {__builtin_fma(a.re, b.re, -a.im * b.im), __builtin_fma(a.re, b.im, a.im * b.re)};
+}
+__device__ __forceinline__ Cx cx_add(Cx a, Cx b) { return {a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ Cx cx_scale(Cx a, double s) { return {a.re * s, a.im * s}; }
+__device__ __forceinline__ Cx cx_div(Cx a, Cx b) {
+    const double d = __builtin_fma(b.re, b.re, b.im * b.im);
+    return {__builtin_fma(a.re, b.re, a.im * b.im) / d, __builtin_fma(a.im, b.re, -a.re * b.im) / d};
+}
+// i^p c for p = 0..3 (mod 4)
+__device__ __forceinline__ Cx cx_ipow(int p, Cx c) {
+    switch (p & 3) {
+    case 0: return c;
+    case 1: return {-c.im, c.re};
+    case 2: return {-c.re, -c.im};
+    default: return {c.im, -c.re};
+    }
+}
+
+// 1 / l^k for l = 1..64, k = 2..5 (the polylogarithm series)
+struct InvPowTab {
+    double v[65][4];
+    constexpr InvPowTab() : v() {
+        for (int l = 1; l <= 64; ++l) {
+            const double r = 1.0 / (double)l;
+            double q = r * r;
+            for (int k = 0; k < 4; ++k) {
+                v[l][k] = q;
+                q *= r;
+            }
+        }
+    }
+};
+__constant__ InvPowTab kInvPow = InvPowTab();
+constexpr int kPolyCoarse = 64, kPolyFine = 16;
+
+// sum_p E_p(rule of spacing D) d_p for the single (OP = S2D_OP_SLP) or double
+// layer; out = (t, n) components
+template <int OP>
+__device__ void flat_rule(double s, double b, double D, int L, const double *__restrict__ dfr, double (&out)[2]) {
+    const double c = 2.0 * M_PI / D;
+    double sq, cq;
+    sincospi(-2.0 * s / D, &sq, &cq);
+    const double aq = exp(-c * b);
+    const Cx Q = {aq * cq, aq * sq};
+    const Cx om = {1.0 - Q.re, -Q.im};                       // 1 - Q
+    const Cx L0 = cx_div(Q, om);
+    Cx zp[kNearDeriv];                                       // (-z)^k
+    zp[0] = {1.0, 0.0};
+    for (int k = 1; k < kNearDeriv; ++k) zp[k] = cx_mul(zp[k - 1], {-b, -s});
+    out[0] = out[1] = 0.0;
+    double fact = 1.0;                                       // p!
+    if constexpr (OP == S2D_OP_SLP) {
+        Cx Li[kNearDeriv + 1];
+        Li[0] = L0;
+        Li[1] = {-0.5 * log(om.re * om.re + om.im * om.im), -atan2(om.im, om.re)};   // -log(1 - Q)
+        Cx acc[kNearDeriv - 1] = {};
+        Cx ql = {1.0, 0.0};
+        for (int l = 1; l <= L; ++l) {
+            ql = cx_mul(ql, Q);
+#pragma unroll
+            for (int k = 0; k < kNearDeriv - 1; ++k) acc[k] = cx_add(acc[k], cx_scale(ql, kInvPow.v[l][k]));
+        }
+        for (int k = 2; k <= kNearDeriv; ++k) Li[k] = acc[k - 2];
+        const double ic = 1.0 / c;
+        for (int p = 0; p < kNearDeriv; ++p) {
+            if (p > 0) fact *= (double)p;
+            Cx S1 = {0.0, 0.0};
+            double binom = 1.0, jf = 1.0, icj = ic;              // C(p, j), j!, c^-(j+1)
+            for (int j = 0; j <= p; ++j) {
+                if (j > 0) {
+                    binom = binom * (double)(p - j + 1) / (double)j;
+                    jf *= (double)j;
+                    icj *= ic;
+                }
+                const double coef = binom * ((j & 1) ? -jf : jf) * icj;
+                S1 = cx_add(S1, cx_scale(cx_mul(zp[p - j], Li[j + 1]), coef));
+            }
+            S1 = cx_scale(S1, M_PI);
+            const Cx S0 = cx_mul(zp[p], L0);
+            const double f = 2.0 / fact;
+            const double ett = f * cx_ipow(p, {S1.re - M_PI * b * S0.re, S1.im - M_PI * b * S0.im}).re;
+            const double enn = f * cx_ipow(p, {S1.re + M_PI * b * S0.re, S1.im + M_PI * b * S0.im}).re;
+            const double etn = f * cx_ipow(p + 1, cx_scale(S0, M_PI * b)).re;
+            const double dt = dfr[2 * p], dn = dfr[2 * p + 1];
+            out[0] = __builtin_fma(ett, dt, __builtin_fma(etn, dn, out[0]));
+            out[1] = __builtin_fma(etn, dt, __builtin_fma(enn, dn, out[1]));
+        }
+    } else {
+        const Cx Lm1 = cx_div(L0, om);                       // Q / (1 - Q)^2
+        for (int p = 0; p < kNearDeriv; ++p) {
+            if (p > 0) fact *= (double)p;
+            // sum_l d^p/dw^p [e^{-wz} (alpha + beta w)] = alpha (-z)^p L0 + beta ((-z)^p c Lm1 + p (-z)^(p-1) L0)
+            const Cx base = cx_mul(zp[p], L0);
+            Cx lin = cx_scale(cx_mul(zp[p], Lm1), c);
+            if (p > 0) lin = cx_add(lin, cx_scale(cx_mul(zp[p - 1], L0), (double)p));
+            const double f = 2.0 / fact;
+            const double h = 0.5 * M_PI;
+            const double ett = f * cx_ipow(p, {h * (base.re - b * lin.re), h * (base.im - b * lin.im)}).re;
+            const double enn = f * cx_ipow(p, {h * (base.re + b * lin.re), h * (base.im + b * lin.im)}).re;
+            const double etn = f * cx_ipow(p + 1, cx_scale(lin, h * b)).re;
+            const double dt = dfr[2 * p], dn = dfr[2 * p + 1];
+            out[0] = __builtin_fma(ett, dt, __builtin_fma(etn, dn, out[0]));
+            out[1] = __builtin_fma(etn, dt, __builtin_fma(enn, dn, out[1]));
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -723,26 +1047,15 @@ __device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
     return __builtin_bit_cast(uint32_t, v);
 }
 
-__device__ __forceinline__ float dot2_bf16(uint32_t a, uint32_t b, float c) {
-    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a), __builtin_bit_cast(bf16x2_t, b), c,
-                                           false);
-}
-
-// MLP inference, with the fallback decision taken first (from the target's
-// bin of |normal offset| / h and the calibrated bounds, scaled into velocity
-// units by h F / (4 pi mu)): no correction, the network, or the upsampled
-// quadrature (the target joins the fallback list).  nb: the packed BF16
-// network.  The network runs on the matrix cores: a wave takes one group of
-// 32 targets and evaluates each layer as out^T = W in^T with
-// v_mfma_f32_32x32x8_bf16: A = 32 output features x 8 inputs of W (read from
-// the blob's [out][in/2] pairs), B = 8 inputs x the 32 targets, C = 32
-// features x 32 targets in FP32, started at the bias.  Lane l holds target
-// l % 32; in C it holds features 8 (r / 4) + 4 (l / 32) + r % 4 of each
-// 32-feature tile (r = 0..15), which are exactly the inputs 8 s + 4 (l / 32) +
-// 0..3 of K-step s of the next layer's B: the activations stay in their
-// lanes between layers.  GELU in FP32 and rounding to BF16 between layers; the
-// last 64 -> 2 layer is a dot2 over the lane's 32 features plus the partner
-// lane's half.
+// MLP inference on the matrix cores: a wave takes one group of 32 targets and
+// evaluates each layer as out^T = W in^T with v_mfma_f32_32x32x8_bf16: A = 32
+// output features x 8 inputs of W (read from the blob's [out][in/2] pairs),
+// B = 8 inputs x the 32 targets, C = 32 features x 32 targets in FP32,
+// started at the bias.  Lane l holds target l % 32; in C it holds features
+// 8 (r / 4) + 4 (l / 32) + r % 4 of each 32-feature tile (r = 0..15), which
+// are exactly the inputs 8 s + 4 (l / 32) + 0..3 of K-step s of the next
+// layer's B: the activations stay in their lanes between layers.  GELU in
+// FP32 and rounding to BF16 between layers.
 typedef short bf16x4v_t __attribute__((ext_vector_type(4)));
 typedef float f32x16v_t __attribute__((ext_vector_type(16)));
 
@@ -756,19 +1069,18 @@ __device__ __forceinline__ bf16x4v_t mfma_pack4(float a, float b, float c, float
     return __builtin_bit_cast(bf16x4v_t, ((uint64_t)pack_bf16(c, d) << 32) | pack_bf16(a, b));
 }
 
-template <int KSTEPS, int IN2>
+// TILES 32-feature output tiles of a layer with KSTEPS K-steps (IN2 input pairs per row)
+template <int TILES, int KSTEPS, int IN2>
 __device__ __forceinline__ void mfma_layer(const uint32_t *W, const float *b, const bf16x4v_t (&in)[KSTEPS],
-                                           int c, int h, f32x16v_t (&acc)[2]) {
+                                           int c, int h, f32x16v_t (&acc)[TILES]) {
 #pragma unroll
-    for (int T = 0; T < 2; ++T) {
+    for (int T = 0; T < TILES; ++T) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[T][r] = b[32 * T + 8 * (r / 4) + 4 * h + (r % 4)];
 #pragma unroll
-        for (int s = 0; s < KSTEPS; ++s) {
-            const int k0 = 8 * s + 4 * h;
-            const bf16x4v_t a = (2 * IN2 > k0) ? mfma_wrow(W, IN2, 32 * T + c, k0) : bf16x4v_t{0, 0, 0, 0};
-            acc[T] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, in[s], acc[T], 0, 0, 0);
-        }
+        for (int s = 0; s < KSTEPS; ++s)
+            acc[T] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(mfma_wrow(W, IN2, 32 * T + c, 8 * s + 4 * h), in[s],
+                                                             acc[T], 0, 0, 0);
     }
 }
 
@@ -781,126 +1093,337 @@ __device__ __forceinline__ void mfma_act(const f32x16v_t (&acc)[2], bf16x4v_t (&
     }
 }
 
+// AUTO's bins: the FP32 position of log10 b among bins of width bin_w from
+// bin_lo (NaN for NaN b); within a b bin, the cell of |s| (width 1/8, the
+// last one open) and of log10 |kappa h| (width 3/16 from -2, both ends
+// open; NaN goes to the last cells)
+__device__ __forceinline__ float near_bpos(float bf, float bin_lo, float bin_w) {
+    return floorf((log10f(bf) - bin_lo) / bin_w);
+}
+__device__ __forceinline__ int near_cell(float sf, float khf) {
+    const float a = fabsf(sf) * 8.f;
+    const int j = a < (float)(kNearSBins - 1) ? (int)a : kNearSBins - 1;
+    const float k = (log10f(fabsf(khf)) + 2.f) * (16.f / 3.f);
+    const int m = k < 1.f ? 0 : (k < (float)(kNearKBins - 1) ? (int)k : kNearKBins - 1);
+    return j * kNearKBins + m;
+}
+
+// MLP and AUTO inference.  Per target, the decision first (AUTO): bins of
+// log10(b) and |s| in FP32 (the calibration bins them the same way); b below
+// the blob's b_min, NaN, a target on the unexpected side of the curve (inside
+// a vesicle, whose normals point outwards; beyond a wall, whose normals point
+// out of the fluid) or a b bin below the first go to the quadrature (flag 1);
+// past the last b bin only "no correction" (if the last b bin's largest
+// correction is within the target's tolerance) or the quadrature; inside, no
+// correction, the network or the quadrature by the bin's calibrated bounds
+// (scaled by scale * F into velocity units) against the tolerance (the
+// target's curve's entry of curve_tol, else threshold).  Then
+// the network (only if some target of the wave uses it), the straight-line
+// coefficients (half-wave h = 0 the plain rule, h = 1 the refined one, each
+// contracted with the density derivatives and exchanged), and
+//   Delta = scale [t n_f] (sum_p Cflat_p d_p + exp(-2 pi b) sum_p dC_p d_p)
+// in FP64 (the double layer's flat part times sg).
+template <int OP>
 __global__ __launch_bounds__(256) void near_mlp_infer_mfma(int64_t n_trg, const float *__restrict__ X,
                                                            const double *__restrict__ frame,
                                                            const NearBlob *__restrict__ nb, double mu,
-                                                           double threshold, int use_bound,
-                                                           double *__restrict__ du, double *__restrict__ dv,
-                                                           int32_t *__restrict__ flag) {
-    static_assert(kNearFeat <= 24, "three K-steps of the first layer");
+                                                           double threshold, const int32_t *__restrict__ tc,
+                                                           int32_t n_curves, const double *__restrict__ curve_tol,
+                                                           int use_bound, double *__restrict__ du,
+                                                           double *__restrict__ dv, int32_t *__restrict__ flag) {
+    static_assert(kNearFeat <= 16, "two K-steps of the first layer");
     const int lane = threadIdx.x & (kWave - 1), h = lane >> 5, c = lane & 31;
     const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;   // this wave's group
-    if (g * 32 < n_trg) {                                            // wave-uniform
-        const int64_t i = g * 32 + c;
-        const bool valid = i < n_trg;
-        const float *xi = X + (valid ? i : 0) * kNearFeat;
-        const double *fr = frame + 6 * (valid ? i : 0);
-        int dec = 0;                                                 // 0 network, 1 quadrature, 2 none
-        double sc = 0.0;
-        if (valid) {
-            sc = fr[4] * fr[5] / (4.0 * M_PI * mu);
-            if (use_bound) {
-                const float noff = fabsf(xi[1]);
-                int bin = (int)floorf((log10f(fmaxf(noff, 1e-30f)) - nb->bin_lo) / nb->bin_w);
-                bin = bin < 0 ? 0 : (bin >= nb->n_bins ? nb->n_bins - 1 : bin);
-                const bool bad = !(noff == noff);
-                if (!bad && (double)nb->bound_zero[bin] * sc <= threshold) dec = 2;
-                else if (bad || (double)nb->bound[bin] * sc > threshold) dec = 1;
+    if (g * 32 >= n_trg) return;                                                   // wave-uniform
+    const int64_t i = g * 32 + c;
+    const bool valid = i < n_trg;
+    const float *xi = X + (valid ? i : 0) * kNearFeat;
+    const double *fr = frame + kNearFrame * (valid ? i : 0);
+    const double b = fr[1], sg = fr[8], F = fr[7];
+    const double scale = OP == S2D_OP_SLP ? fr[6] / (4.0 * M_PI * mu) : 1.0 / M_PI;
+    int dec = 0;                                                 // 0 network, 1 quadrature, 2 none
+    if (valid && use_bound) {
+        const float bf = (float)b;
+        const bool side = OP == S2D_OP_SLP ? sg > 0.0 : sg < 0.0;
+        const double sF = scale * F;
+        const int nbins = nb->n_bins;
+        const float pos = near_bpos(bf, nb->bin_lo, nb->bin_w);
+        double tol = threshold;
+        if (curve_tol) {
+            const int cc = tc[i];
+            tol = (cc >= 0 && cc < n_curves) ? curve_tol[cc] : -1.0;
+        }
+        if (!(bf >= nb->b_min) || !side || !(sF == sF) || !(pos >= 0.f) || nbins <= 0) {
+            dec = 1;
+        } else {
+            const bool past = !(pos < (float)nbins);
+            const int bin = (past ? nbins - 1 : (int)pos) * kNearCell + near_cell((float)fr[0], (float)fr[19]);
+            if ((double)nb->bound_zero[bin] * sF <= tol) dec = 2;
+            else if (past) dec = 1;
+            else dec = (double)nb->bound[bin] * sF <= tol ? 0 : 1;
+        }
+    }
+    double net[2] = {0.0, 0.0};
+    if (__any(valid && dec == 0)) {                              // wave-uniform
+        bf16x4v_t in1[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            float v[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int k = 8 * s + 4 * h + e;
+                v[e] = (valid && k < kNearFeat) ? (xi[k] - nb->mu_in[k]) * nb->isd_in[k] : 0.f;
+            }
+            in1[s] = mfma_pack4(v[0], v[1], v[2], v[3]);
+        }
+        f32x16v_t acc[2];
+        bf16x4v_t hb[8];
+        mfma_layer<2, 2, 8>(nb->W1, nb->b1, in1, c, h, acc);
+        mfma_act(acc, hb);
+        mfma_layer<2, 8, 32>(nb->W2, nb->b2, hb, c, h, acc);
+        mfma_act(acc, hb);
+        mfma_layer<2, 8, 32>(nb->W3, nb->b3, hb, c, h, acc);
+        mfma_act(acc, hb);
+        f32x16v_t y[1];
+        mfma_layer<1, 8, 32>(nb->W4, nb->b4, hb, c, h, y);
+        // the lane's outputs o = 8 (r / 4) + 4 h + r % 4 < 20: dC[p][out][in] with
+        // p = o / 4, out = (o % 4) / 2, in = o % 2, contracted with d[p][in]
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int o = 8 * (r / 4) + 4 * h + (r % 4);
+            if (o < kNearOut) {
+                const int p = o / 4, out = (o % 4) / 2, in = o % 2;
+                net[out] = __builtin_fma((double)y[0][r], fr[9 + 2 * p + in], net[out]);
             }
         }
-        // the network runs only if some target of the group needs it
-        float y0 = 0.f, y1 = 0.f;
-        if (__any(valid && dec == 0)) {                              // wave-uniform
-            // first layer: the standardised features of the lane's target
-            bf16x4v_t in1[3];
-#pragma unroll
-            for (int s = 0; s < 3; ++s) {
-                float v[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int k = 8 * s + 4 * h + e;
-                    v[e] = (valid && k < kNearFeat) ? (xi[k] - nb->mu_in[k]) * nb->isd_in[k] : 0.f;
-                }
-                in1[s] = mfma_pack4(v[0], v[1], v[2], v[3]);
-            }
-            f32x16v_t acc[2];
-            bf16x4v_t hb[8];
-            mfma_layer<3, kNearFeat / 2>(nb->W1, nb->b1, in1, c, h, acc);
-            mfma_act(acc, hb);
-            mfma_layer<8, 32>(nb->W2, nb->b2, hb, c, h, acc);
-            mfma_act(acc, hb);
-            mfma_layer<8, 32>(nb->W3, nb->b3, hb, c, h, acc);
-#pragma unroll
-            for (int T = 0; T < 2; ++T) {
-#pragma unroll
-                for (int r = 0; r < 16; r += 2) {
-                    const int f = 32 * T + 8 * (r / 4) + 4 * h + (r % 4);
-                    const uint32_t p = pack_bf16(gelu_f(acc[T][r]), gelu_f(acc[T][r + 1]));
-                    y0 = dot2_bf16(nb->W4[f / 2], p, y0);
-                    y1 = dot2_bf16(nb->W4[32 + f / 2], p, y1);
-                }
-            }
-            y0 += __shfl_xor(y0, 32, kWave);
-            y1 += __shfl_xor(y1, 32, kWave);
-            y0 += nb->b4[0];
-            y1 += nb->b4[1];
+        net[0] += __shfl_xor(net[0], 32, kWave);
+        net[1] += __shfl_xor(net[1], 32, kWave);
+        const double env = exp(-2.0 * M_PI * b);
+        net[0] *= env;
+        net[1] *= env;
+    }
+    // straight-line part: lanes h = 0 the plain rule (subtracted), h = 1 the refined one
+    double flat[2] = {0.0, 0.0};
+    if (valid && b > 0.0) {
+        const double D = h ? 1.0 / (double)nb->P : 1.0;
+        flat_rule<OP>(fr[0], b, D, h ? kPolyFine : kPolyCoarse, fr + 9, flat);
+        if (!h) {
+            flat[0] = -flat[0];
+            flat[1] = -flat[1];
         }
-        if (valid && h == 0) {
-            if (dec == 2) {
-                if (flag) flag[i] = 2;
-                du[i] = 0.0;
-                dv[i] = 0.0;
-            } else if (dec == 1) {
-                flag[i] = 1;               // the quadrature kernel writes du, dv
-            } else {
-                if (flag) flag[i] = 0;
-                du[i] = sc * ((double)y0 * fr[0] + (double)y1 * fr[2]);
-                dv[i] = sc * ((double)y0 * fr[1] + (double)y1 * fr[3]);
+    }
+    const double ot = __shfl_xor(flat[0], 32, kWave), on = __shfl_xor(flat[1], 32, kWave);
+    if (!valid || h != 0) return;
+    // the refined rule's part plus the plain rule's (negated) part, in a fixed order
+    double yt = ot + flat[0], yn = on + flat[1];
+    if (OP != S2D_OP_SLP) {
+        yt *= sg;
+        yn *= sg;
+    }
+    if (dec == 2) {
+        if (flag) flag[i] = 2;
+        du[i] = 0.0;
+        dv[i] = 0.0;
+    } else if (dec == 1) {
+        flag[i] = 1;                     // the quadrature fills du, dv
+    } else {
+        if (flag) flag[i] = 0;
+        yt += net[0];
+        yn += net[1];
+        du[i] = scale * (yt * fr[2] + yn * fr[4]);
+        dv[i] = scale * (yt * fr[3] + yn * fr[5]);
+    }
+}
+
+// Pack FP32 master parameters into the BF16 inference blob (first layer rows
+// padded to 8 input pairs, the last layer to 32 output rows, with zeros).
+__global__ __launch_bounds__(256) void near_pack(const float *__restrict__ prm, const float *__restrict__ bound,
+                                                 const float *__restrict__ bound_zero, int32_t n_bins, float bin_lo,
+                                                 float bin_w, float b_min, int32_t P, NearBlob *__restrict__ nb) {
+    using O = MlpOffsets;
+    constexpr int r0 = kNearFeat;                  // W1 pairs
+    constexpr int r1 = r0 + 64 * 8;                // W2
+    constexpr int r2 = r1 + 64 * 32;               // W3
+    constexpr int r3 = r2 + 64 * 32;               // W4
+    constexpr int r4 = r3 + 32 * 32;               // biases, bounds
+    constexpr int total = r4 + kNearTable;
+    static_assert(kNearTable >= 64, "the bias pass rides on the bound pass");
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < total; q += gridDim.x * blockDim.x) {
+        if (q < r0) {
+            nb->mu_in[q] = prm[O::mu + q];
+            nb->isd_in[q] = 1.f / prm[O::sd + q];
+        } else if (q < r1) {
+            const int r = q - r0, o = r / 8, k = r % 8;
+            const float a = 2 * k < kNearFeat ? prm[O::W1 + (2 * k) * 64 + o] : 0.f;
+            const float bq = 2 * k + 1 < kNearFeat ? prm[O::W1 + (2 * k + 1) * 64 + o] : 0.f;
+            nb->W1[r] = pack_bf16(a, bq);
+        } else if (q < r2) {
+            const int r = q - r1, o = r / 32, k = r % 32;
+            nb->W2[r] = pack_bf16(prm[O::W2 + (2 * k) * 64 + o], prm[O::W2 + (2 * k + 1) * 64 + o]);
+        } else if (q < r3) {
+            const int r = q - r2, o = r / 32, k = r % 32;
+            nb->W3[r] = pack_bf16(prm[O::W3 + (2 * k) * 64 + o], prm[O::W3 + (2 * k + 1) * 64 + o]);
+        } else if (q < r4) {
+            const int r = q - r3, o = r / 32, k = r % 32;
+            nb->W4[r] = o < kNearOut ? pack_bf16(prm[O::W4 + (2 * k) * kNearOut + o],
+                                                 prm[O::W4 + (2 * k + 1) * kNearOut + o])
+                                     : 0u;
+        } else {
+            const int o = q - r4;                  // 0 .. kNearTable - 1
+            if (o < 64) {
+                nb->b1[o] = prm[O::b1 + o];
+                nb->b2[o] = prm[O::b2 + o];
+                nb->b3[o] = prm[O::b3 + o];
+            }
+            if (o < 32) nb->b4[o] = o < kNearOut ? prm[O::b4 + o] : 0.f;
+            nb->bound[o] = o < n_bins * kNearCell ? bound[o] : 3e38f;
+            nb->bound_zero[o] = (o < n_bins * kNearCell && bound_zero) ? bound_zero[o] : 3e38f;
+            if (o == 0) {
+                nb->n_bins = n_bins;
+                nb->bin_lo = bin_lo;
+                nb->bin_w = bin_w;
+                nb->b_min = b_min;
+                nb->P = P;
             }
         }
     }
 }
 
-// Pack FP32 master parameters into the BF16 inference blob.
-__global__ __launch_bounds__(256) void near_pack(const float *__restrict__ prm, const float *__restrict__ bound,
-                                                 const float *__restrict__ bound_zero, int32_t n_bins, float bin_lo,
-                                                 float bin_w, NearBlob *__restrict__ nb) {
-    const MlpOffsets O;
-    constexpr int r0 = kNearFeat;                  // W1 pairs
-    constexpr int r1 = r0 + 64 * kNearFeat / 2;    // W2
-    constexpr int r2 = r1 + 64 * 32;               // W3
-    constexpr int r3 = r2 + 64 * 32;               // W4
-    constexpr int r4 = r3 + 2 * 32;                // biases, bounds
-    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < kNearBlobWork; q += gridDim.x * blockDim.x) {
-        if (q < r0) {
-            nb->mu_in[q] = prm[O.mu + q];
-            nb->isd_in[q] = 1.f / prm[O.sd + q];
-        } else if (q < r1) {
-            const int r = q - r0, o = r / (kNearFeat / 2), k = r % (kNearFeat / 2);
-            nb->W1[r] = pack_bf16(prm[O.W1 + (2 * k) * 64 + o], prm[O.W1 + (2 * k + 1) * 64 + o]);
-        } else if (q < r2) {
-            const int r = q - r1, o = r / 32, k = r % 32;
-            nb->W2[r] = pack_bf16(prm[O.W2 + (2 * k) * 64 + o], prm[O.W2 + (2 * k + 1) * 64 + o]);
-        } else if (q < r3) {
-            const int r = q - r2, o = r / 32, k = r % 32;
-            nb->W3[r] = pack_bf16(prm[O.W3 + (2 * k) * 64 + o], prm[O.W3 + (2 * k + 1) * 64 + o]);
-        } else if (q < r4) {
-            const int r = q - r3, o = r / 32, k = r % 32;
-            nb->W4[r] = pack_bf16(prm[O.W4 + (2 * k) * 2 + o], prm[O.W4 + (2 * k + 1) * 2 + o]);
-        } else {
-            const int o = q - r4;                  // 0 .. 63
-            nb->b1[o] = prm[O.b1 + o];
-            nb->b2[o] = prm[O.b2 + o];
-            nb->b3[o] = prm[O.b3 + o];
-            if (o < 2) nb->b4[o] = prm[O.b4 + o];
-            nb->bound[o] = o < n_bins ? bound[o] : 3e38f;
-            nb->bound_zero[o] = (o < n_bins && bound_zero) ? bound_zero[o] : 3e38f;
-            if (o == 0) {
-                nb->n_bins = n_bins;
-                nb->bin_lo = bin_lo;
-                nb->bin_w = bin_w;
-            }
-        }
+// ---------------------------------------------------------------------------
+// training data: the flat prediction's residual and the per-sample weight
+// ---------------------------------------------------------------------------
+// largest |(ur, vr)| of each curve's targets (non-negative floats order like
+// their bit patterns, so an atomic max on the bits is exact and order-free)
+__global__ __launch_bounds__(256) void near_curve_scale(int64_t n, const int32_t *__restrict__ tc, int32_t n_curves,
+                                                        const double *__restrict__ ur, const double *__restrict__ vr,
+                                                        uint32_t *__restrict__ cscale) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int c = tc[i];
+    if (c < 0 || c >= n_curves) return;
+    const float v = (float)sqrt(ur[i] * ur[i] + vr[i] * vr[i]);
+    if (v == v) atomicMax(cscale + c, __builtin_bit_cast(uint32_t, v));
+}
+
+// per sample: T = [d (10, frame), R (2) = label / scale - flat prediction
+// (frame), weight = gain scale / curve scale, exp(-2 pi b)]; the labels are the
+// quadrature's corrections (du, dv), the curve scale is its curve's largest
+// |(ur, vr)| (the error measure's normalisation)
+template <int OP>
+__global__ __launch_bounds__(256) void near_train_targets_k(int64_t n, const double *__restrict__ frame,
+                                                            const double *__restrict__ du,
+                                                            const double *__restrict__ dv,
+                                                            const int32_t *__restrict__ tc, int32_t n_curves,
+                                                            double mu, int32_t P, float gain,
+                                                            const uint32_t *__restrict__ cscale,
+                                                            float *__restrict__ T) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double *fr = frame + kNearFrame * i;
+    const double b = fr[1];
+    const double scale = OP == S2D_OP_SLP ? fr[6] / (4.0 * M_PI * mu) : 1.0 / M_PI;
+    double y0 = (du[i] * fr[2] + dv[i] * fr[3]) / scale, y1 = (du[i] * fr[4] + dv[i] * fr[5]) / scale;
+    double fc[2] = {0.0, 0.0}, ff[2] = {0.0, 0.0};
+    if (b > 0.0) {
+        flat_rule<OP>(fr[0], b, 1.0, kPolyCoarse, fr + 9, fc);
+        flat_rule<OP>(fr[0], b, 1.0 / (double)P, kPolyFine, fr + 9, ff);
+    }
+    const double sgn = OP == S2D_OP_SLP ? 1.0 : fr[8];
+    y0 -= sgn * (ff[0] - fc[0]);
+    y1 -= sgn * (ff[1] - fc[1]);
+    const int c = tc[i];
+    const float cs = (c >= 0 && c < n_curves) ? __builtin_bit_cast(float, cscale[c]) : 0.f;
+    float *t = T + kNearTStride * i;
+    for (int k = 0; k < 2 * kNearDeriv; ++k) t[k] = (float)fr[9 + k];
+    t[10] = (float)y0;
+    t[11] = (float)y1;
+    t[12] = cs > 0.f ? (float)((double)gain * scale / (double)cs) : 0.f;
+    t[13] = (float)exp(-2.0 * M_PI * b);
+}
+
+// per-feature mean and standard deviation (population) over n samples into
+// the parameter vector's standardisation slots: one workgroup per feature,
+// strided FP64 partial sums added in a fixed tree order (deterministic)
+__global__ __launch_bounds__(256) void near_feature_stats_k(int64_t n, const float *__restrict__ X,
+                                                            float *__restrict__ prm) {
+    __shared__ double red[256];
+    const int k = blockIdx.x;
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += (double)X[i * kNearFeat + k];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    const double mean = red[0] / (double)(n > 0 ? n : 1);
+    __syncthreads();
+    s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const double e = (double)X[i * kNearFeat + k] - mean;
+        s = __builtin_fma(e, e, s);
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double sd = sqrt(red[0] / (double)(n > 0 ? n : 1));
+        prm[MlpOffsets::mu + k] = (float)mean;
+        prm[MlpOffsets::sd + k] = sd > 1e-30 ? (float)sd : 1.f;
+    }
+}
+
+// Calibration of AUTO's rule: per bin of log10(b) and |s| (FP32, as the
+// inference bins them), the largest network error |pred - label| and the largest
+// correction |label|, both over scale * F; targets that AUTO would not trust
+// the network with (b < b_min, the wrong side, NaN) are skipped.  bound and
+// bound_zero hold float bits (atomic max); empty bins become 3e38 and the
+// others are multiplied by margin in the finishing pass.
+template <int OP>
+__global__ __launch_bounds__(256) void near_calib_acc(int64_t n, const double *__restrict__ frame,
+                                                      const double *__restrict__ dup, const double *__restrict__ dvp,
+                                                      const double *__restrict__ du, const double *__restrict__ dv,
+                                                      double mu, int32_t n_bins, float bin_lo, float bin_w,
+                                                      float b_min, uint32_t *__restrict__ bound,
+                                                      uint32_t *__restrict__ bound_zero, int32_t *__restrict__ count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double *fr = frame + kNearFrame * i;
+    const float bf = (float)fr[1];
+    const bool side = OP == S2D_OP_SLP ? fr[8] > 0.0 : fr[8] < 0.0;
+    if (!(bf >= b_min) || !side) return;
+    const float pos = near_bpos(bf, bin_lo, bin_w);
+    if (!(pos >= 0.f && pos < (float)n_bins)) return;
+    const int bin = (int)pos * kNearCell + near_cell((float)fr[0], (float)fr[19]);
+    const double scale = OP == S2D_OP_SLP ? fr[6] / (4.0 * M_PI * mu) : 1.0 / M_PI;
+    const double sF = scale * fr[7];
+    const float e = (float)(sqrt((dup[i] - du[i]) * (dup[i] - du[i]) + (dvp[i] - dv[i]) * (dvp[i] - dv[i])) / sF);
+    const float z = (float)(sqrt(du[i] * du[i] + dv[i] * dv[i]) / sF);
+    if (!(e == e) || !(z == z)) return;
+    atomicMax(bound + bin, __builtin_bit_cast(uint32_t, e));
+    atomicMax(bound_zero + bin, __builtin_bit_cast(uint32_t, z));
+    atomicAdd(count + bin, 1);
+}
+
+__global__ __launch_bounds__(256) void near_calib_init(int32_t n_bins, uint32_t *bound, uint32_t *bound_zero,
+                                                       int32_t *count) {
+    for (int b = threadIdx.x; b < n_bins * kNearCell; b += blockDim.x) {
+        bound[b] = 0u;
+        bound_zero[b] = 0u;
+        count[b] = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void near_calib_finish(int32_t n_bins, float margin, uint32_t *bound,
+                                                         uint32_t *bound_zero, const int32_t *count) {
+    for (int b = threadIdx.x; b < n_bins * kNearCell; b += blockDim.x) {
+        const float e = count[b] > 0 ? __builtin_bit_cast(float, bound[b]) * margin : 3e38f;
+        const float z = count[b] > 0 ? __builtin_bit_cast(float, bound_zero[b]) * margin : 3e38f;
+        bound[b] = __builtin_bit_cast(uint32_t, e);
+        bound_zero[b] = __builtin_bit_cast(uint32_t, z);
     }
 }
 
@@ -920,6 +1443,10 @@ __device__ __forceinline__ void mlp_wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// activation columns of a training sample's record
+constexpr int kA_h0 = 0, kA_z1 = kNearFeat, kA_h1 = kA_z1 + 64, kA_z2 = kA_h1 + 64, kA_h2 = kA_z2 + 64,
+              kA_z3 = kA_h2 + 64, kA_h3 = kA_z3 + 64;
+
 // one 64-neuron layer of sample's forward pass: lane o; in: the wave's LDS row
 // (n_in values), written over by the layer's activations on return
 __device__ __forceinline__ void mlp_fwd_layer(int n_in, const float *__restrict__ W, const float *__restrict__ b,
@@ -934,67 +1461,83 @@ __device__ __forceinline__ void mlp_fwd_layer(int n_in, const float *__restrict_
     mlp_wave_sync();
 }
 
-// per sample: forward, loss term, output delta dY = (Y - T) / B, and the
-// pre-activations z1..z3 and activations h0..h3 kept for the backward pass
+// per sample: forward, the head (the 20 outputs dC contracted with the
+// sample's d, times exp(-2 pi b)), the weighted residual e = wt (head - R),
+// its loss term |e|^2 / 2B, the output deltas dY[o] = wt e_out(o) env d[p][in] / B,
+// and the pre-activations z1..z3 and activations h0..h3 for the backward pass
 __global__ __launch_bounds__(256) void mlp_fwd(int32_t B, const int32_t *__restrict__ idx,
                                                const float *__restrict__ X, const float *__restrict__ T,
                                                const float *__restrict__ prm, float *__restrict__ act,
                                                float *__restrict__ dY, float *__restrict__ lossv) {
     __shared__ float rows[kBlock / kWave][64];
+    using O = MlpOffsets;
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     const int s = blockIdx.x * (kBlock / kWave) + wv;
     if (s >= B) return;                  // wave-uniform; no block barrier below
     float *row = rows[wv];
-    const MlpOffsets O;
     const int64_t i = idx ? idx[s] : s;
-    float *A = act + (int64_t)s * kActStride;   // h0[20] z1[64] h1[64] z2[64] h2[64] z3[64] h3[64]
-    float *h0 = A, *z1 = A + 20, *h1 = A + 84, *z2 = A + 148, *h2 = A + 212, *z3 = A + 276, *h3 = A + 340;
+    float *A = act + (int64_t)s * kActStride;
     if (lane < kNearFeat) {
-        const float v = (X[i * kNearFeat + lane] - prm[O.mu + lane]) / prm[O.sd + lane];
-        h0[lane] = v;
+        const float v = (X[i * kNearFeat + lane] - prm[O::mu + lane]) / prm[O::sd + lane];
+        A[kA_h0 + lane] = v;
         row[lane] = v;
     }
     mlp_wave_sync();
-    mlp_fwd_layer(kNearFeat, prm + O.W1, prm + O.b1, row, lane, z1, h1);
-    mlp_fwd_layer(64, prm + O.W2, prm + O.b2, row, lane, z2, h2);
-    mlp_fwd_layer(64, prm + O.W3, prm + O.b3, row, lane, z3, h3);
-    float r = 0.f;
-    if (lane < 2) {
-        float a = prm[O.b4 + lane];
-        for (int k = 0; k < 64; ++k) a = fmaf(row[k], prm[O.W4 + k * 2 + lane], a);
-        r = a - T[i * 2 + lane];
-        dY[s * 2 + lane] = r / (float)B;
+    mlp_fwd_layer(kNearFeat, prm + O::W1, prm + O::b1, row, lane, A + kA_z1, A + kA_h1);
+    mlp_fwd_layer(64, prm + O::W2, prm + O::b2, row, lane, A + kA_z2, A + kA_h2);
+    mlp_fwd_layer(64, prm + O::W3, prm + O::b3, row, lane, A + kA_z3, A + kA_h3);
+    float yo = 0.f;
+    if (lane < kNearOut) {
+        float a = prm[O::b4 + lane];
+        for (int k = 0; k < 64; ++k) a = fmaf(row[k], prm[O::W4 + k * kNearOut + lane], a);
+        yo = a;
     }
-    const float r1 = __shfl(r, 1, kWave);
-    if (lane == 0) lossv[s] = 0.5f * (r * r + r1 * r1) / (float)B;
+    mlp_wave_sync();
+    if (lane < kNearOut) row[lane] = yo;
+    mlp_wave_sync();
+    // every lane contracts the 20 outputs in the same order
+    const float *t = T + (int64_t)kNearTStride * i;
+    float hd[2] = {0.f, 0.f};
+    for (int o = 0; o < kNearOut; ++o) {
+        const int p = o / 4, out = (o % 4) / 2, in = o % 2;
+        hd[out] = fmaf(row[o], t[2 * p + in], hd[out]);
+    }
+    const float wt = t[12], env = t[13];
+    const float e0 = wt * (env * hd[0] - t[10]), e1 = wt * (env * hd[1] - t[11]);
+    if (lane < kNearOut) {
+        const int p = lane / 4, out = (lane % 4) / 2, in = lane % 2;
+        dY[(int64_t)s * kNearOut + lane] = wt * (out ? e1 : e0) * env * t[2 * p + in] / (float)B;
+    }
+    if (lane == 0) lossv[s] = 0.5f * (e0 * e0 + e1 * e1) / (float)B;
 }
 
 // per sample: the deltas of the three hidden layers, written over z3, z2, z1
 __global__ __launch_bounds__(256) void mlp_bwd(int32_t B, const float *__restrict__ prm, float *__restrict__ act,
                                                const float *__restrict__ dY) {
     __shared__ float rows[kBlock / kWave][64];
+    using O = MlpOffsets;
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     const int s = blockIdx.x * (kBlock / kWave) + wv;
     if (s >= B) return;                  // wave-uniform
     float *row = rows[wv];
-    const MlpOffsets O;
     float *A = act + (int64_t)s * kActStride;
-    float *z1 = A + 20, *z2 = A + 148, *z3 = A + 276;
-    const float g0 = dY[2 * s], g1 = dY[2 * s + 1];
-    const float d3 = (prm[O.W4 + lane * 2] * g0 + prm[O.W4 + lane * 2 + 1] * g1) * gelu_grad_f(z3[lane]);
-    z3[lane] = d3;
+    const float *g = dY + (int64_t)s * kNearOut;
+    float a = 0.f;
+    for (int o = 0; o < kNearOut; ++o) a = fmaf(prm[O::W4 + lane * kNearOut + o], g[o], a);
+    const float d3 = a * gelu_grad_f(A[kA_z3 + lane]);
+    A[kA_z3 + lane] = d3;
     row[lane] = d3;
     mlp_wave_sync();
-    float a = 0.f;
-    for (int o = 0; o < 64; ++o) a = fmaf(prm[O.W3 + lane * 64 + o], row[o], a);
-    const float d2 = a * gelu_grad_f(z2[lane]);
-    z2[lane] = d2;
+    a = 0.f;
+    for (int o = 0; o < 64; ++o) a = fmaf(prm[O::W3 + lane * 64 + o], row[o], a);
+    const float d2 = a * gelu_grad_f(A[kA_z2 + lane]);
+    A[kA_z2 + lane] = d2;
     mlp_wave_sync();
     row[lane] = d2;
     mlp_wave_sync();
     a = 0.f;
-    for (int o = 0; o < 64; ++o) a = fmaf(prm[O.W2 + lane * 64 + o], row[o], a);
-    z1[lane] = a * gelu_grad_f(z1[lane]);
+    for (int o = 0; o < 64; ++o) a = fmaf(prm[O::W2 + lane * 64 + o], row[o], a);
+    A[kA_z1 + lane] = a * gelu_grad_f(A[kA_z1 + lane]);
 }
 
 // gradient of every parameter: the sum over the batch of (input activation x
@@ -1007,30 +1550,31 @@ __global__ __launch_bounds__(256) void mlp_grad(int32_t B, const float *__restri
                                                 float *__restrict__ grad, float *__restrict__ loss) {
     constexpr int kPer = kBlock / kGradChunks;
     __shared__ float part[kGradChunks][kPer];
+    using O = MlpOffsets;
     const int pp = threadIdx.x % kPer, ch = threadIdx.x / kPer;
     const int p = blockIdx.x * kPer + pp;
-    const MlpOffsets O;
-    int hin = -1, dl = -1, dk = 0, width = 64;   // activation column, delta column
-    if (p >= O.W1 && p < O.b1) { const int r = p - O.W1; hin = r / 64; dl = 20 + r % 64; }
-    else if (p >= O.b1 && p < O.W2) { dl = 20 + (p - O.b1); }
-    else if (p >= O.W2 && p < O.b2) { const int r = p - O.W2; hin = 84 + r / 64; dl = 148 + r % 64; }
-    else if (p >= O.b2 && p < O.W3) { dl = 148 + (p - O.b2); }
-    else if (p >= O.W3 && p < O.b3) { const int r = p - O.W3; hin = 212 + r / 64; dl = 276 + r % 64; }
-    else if (p >= O.b3 && p < O.W4) { dl = 276 + (p - O.b3); }
-    else if (p >= O.W4 && p < O.b4) { const int r = p - O.W4; hin = 340 + r / 2; dk = r % 2; width = 2; }
-    else if (p >= O.b4 && p < O.total) { dk = p - O.b4; width = 2; }
+    int hin = -1, dl = -1, dk = 0;               // activation column, delta column (act) or output (dY)
+    bool outd = false;
+    if (p >= O::W1 && p < O::b1) { const int r = p - O::W1; hin = kA_h0 + r / 64; dl = kA_z1 + r % 64; }
+    else if (p >= O::b1 && p < O::W2) { dl = kA_z1 + (p - O::b1); }
+    else if (p >= O::W2 && p < O::b2) { const int r = p - O::W2; hin = kA_h1 + r / 64; dl = kA_z2 + r % 64; }
+    else if (p >= O::b2 && p < O::W3) { dl = kA_z2 + (p - O::b2); }
+    else if (p >= O::W3 && p < O::b3) { const int r = p - O::W3; hin = kA_h2 + r / 64; dl = kA_z3 + r % 64; }
+    else if (p >= O::b3 && p < O::W4) { dl = kA_z3 + (p - O::b3); }
+    else if (p >= O::W4 && p < O::b4) { const int r = p - O::W4; hin = kA_h3 + r / kNearOut; dk = r % kNearOut; outd = true; }
+    else if (p >= O::b4 && p < O::total) { dk = p - O::b4; outd = true; }
     float g = 0.f;
-    if (p >= O.W1 && p < O.total) {              // mu_in / sd_in are not trained
+    if (p >= O::W1 && p < O::total) {            // mu_in / sd_in are not trained
         const int s0 = (int)((int64_t)B * ch / kGradChunks), s1 = (int)((int64_t)B * (ch + 1) / kGradChunks);
         for (int s = s0; s < s1; ++s) {
             const float *A = act + (int64_t)s * kActStride;
-            const float d = width == 2 ? dY[2 * s + dk] : A[dl];
+            const float d = outd ? dY[(int64_t)s * kNearOut + dk] : A[dl];
             g = fmaf(hin >= 0 ? A[hin] : 1.f, d, g);
         }
     }
     part[ch][pp] = g;
     __syncthreads();
-    if (ch == 0 && p < O.total) {
+    if (ch == 0 && p < O::total) {
         float t = 0.f;
         for (int c = 0; c < kGradChunks; ++c) t += part[c][pp];
         grad[p] = t;
@@ -1046,8 +1590,8 @@ __global__ __launch_bounds__(256) void mlp_adam(float *__restrict__ prm, const f
                                                 float *__restrict__ m, float *__restrict__ v, int32_t step, float lr,
                                                 float b1, float b2, float eps) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    const MlpOffsets O;
-    if (p >= O.total || p < O.W1) return;
+    using O = MlpOffsets;
+    if (p >= O::total || p < O::W1) return;
     const float g = grad[p];
     const float mm = b1 * m[p] + (1.f - b1) * g;
     const float vv = b2 * v[p] + (1.f - b2) * g * g;
@@ -1058,33 +1602,34 @@ __global__ __launch_bounds__(256) void mlp_adam(float *__restrict__ prm, const f
     prm[p] -= lr * mh / (sqrtf(vh) + eps);
 }
 
-// FP32 forward only (reference-precision inference, gradient checks)
+// FP32 forward only: the 20 raw outputs dC (reference-precision inference,
+// gradient checks)
 __global__ __launch_bounds__(256) void mlp_fwd_only(int64_t n, const float *__restrict__ X,
                                                     const float *__restrict__ prm, float *__restrict__ Y) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const MlpOffsets O;
+    using O = MlpOffsets;
     float h0[kNearFeat], h1[64], h2[64];
-    for (int k = 0; k < kNearFeat; ++k) h0[k] = (X[i * kNearFeat + k] - prm[O.mu + k]) / prm[O.sd + k];
+    for (int k = 0; k < kNearFeat; ++k) h0[k] = (X[i * kNearFeat + k] - prm[O::mu + k]) / prm[O::sd + k];
     for (int o = 0; o < 64; ++o) {
-        float a = prm[O.b1 + o];
-        for (int k = 0; k < kNearFeat; ++k) a = fmaf(h0[k], prm[O.W1 + k * 64 + o], a);
+        float a = prm[O::b1 + o];
+        for (int k = 0; k < kNearFeat; ++k) a = fmaf(h0[k], prm[O::W1 + k * 64 + o], a);
         h1[o] = gelu_f(a);
     }
     for (int o = 0; o < 64; ++o) {
-        float a = prm[O.b2 + o];
-        for (int k = 0; k < 64; ++k) a = fmaf(h1[k], prm[O.W2 + k * 64 + o], a);
+        float a = prm[O::b2 + o];
+        for (int k = 0; k < 64; ++k) a = fmaf(h1[k], prm[O::W2 + k * 64 + o], a);
         h2[o] = gelu_f(a);
     }
     for (int o = 0; o < 64; ++o) {
-        float a = prm[O.b3 + o];
-        for (int k = 0; k < 64; ++k) a = fmaf(h2[k], prm[O.W3 + k * 64 + o], a);
+        float a = prm[O::b3 + o];
+        for (int k = 0; k < 64; ++k) a = fmaf(h2[k], prm[O::W3 + k * 64 + o], a);
         h1[o] = gelu_f(a);
     }
-    for (int o = 0; o < 2; ++o) {
-        float a = prm[O.b4 + o];
-        for (int k = 0; k < 64; ++k) a = fmaf(h1[k], prm[O.W4 + k * 2 + o], a);
-        Y[i * 2 + o] = a;
+    for (int o = 0; o < kNearOut; ++o) {
+        float a = prm[O::b4 + o];
+        for (int k = 0; k < 64; ++k) a = fmaf(h1[k], prm[O::W4 + k * kNearOut + o], a);
+        Y[i * kNearOut + o] = a;
     }
 }
 
@@ -1123,62 +1668,103 @@ hipError_t near_launch_compact(int64_t n, const int32_t *flag, int32_t *cnt, int
     return hipGetLastError();
 }
 
-hipError_t near_launch_features(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, float *X,
-                                double *frame, hipStream_t st) {
+
+size_t near_derivs_scratch(const s2d_curves *c) {
+    // cos / sin table and mode coefficients for curves above kUpMaxN nodes
+    return c->n_nodes > kUpMaxN ? (size_t)c->n_nodes * 6 * sizeof(double) : 0;
+}
+
+hipError_t near_launch_derivs(const s2d_curves *c, double *dtab, double *scratch, hipStream_t st) {
+    if (c->n_curves <= 0 || c->n_nodes <= 0) return hipSuccess;
+    hipLaunchKernelGGL(near_derivs, dim3((unsigned)c->n_curves), dim3(256), 0, st, c->curve_off, c->n_curves,
+                       c->n_nodes, c->fx, c->fy, dtab);
+    if (c->n_nodes > kUpMaxN) {
+        // some curve may exceed kUpMaxN nodes: rows of smaller curves return at once
+        double *tab = scratch, *coef = scratch + 2 * c->n_nodes;
+        hipLaunchKernelGGL(near_derivs_table, dim3(grid_for(c->n_nodes)), dim3(256), 0, st, c->curve_off,
+                           c->n_curves, c->n_nodes, tab);
+        const unsigned wb = grid_for(c->n_nodes, 256 / kWave);
+        hipLaunchKernelGGL(near_derivs_coef, dim3(wb), dim3(256), 0, st, c->curve_off, c->n_curves, c->n_nodes, c->fx,
+                           c->fy, tab, coef);
+        hipLaunchKernelGGL(near_derivs_nodes, dim3(wb), dim3(256), 0, st, c->curve_off, c->n_curves, c->n_nodes, tab,
+                           coef, dtab);
+    }
+    return hipGetLastError();
+}
+
+hipError_t near_launch_features(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, const double *dtab,
+                                float *X, double *frame, hipStream_t st) {
     if (t->n <= 0) return hipSuccess;
     hipLaunchKernelGGL(near_features, dim3(grid_for(t->n)), dim3(256), 0, st, t->n, t->x, t->y, tc, c->curve_off,
-                       c->n_curves, c->n_nodes, c->x, c->y, c->nx, c->ny, c->kappa, c->w, c->fx, c->fy, X, frame);
+                       c->n_curves, c->n_nodes, c->x, c->y, c->nx, c->ny, c->kappa, c->w, dtab, X, frame);
     return hipGetLastError();
 }
 
 hipError_t near_launch_wall_features(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, double d,
-                                     float *X, double *frame, hipStream_t st) {
+                                     const double *dtab, float *X, double *frame, hipStream_t st) {
     if (t->n <= 0) return hipSuccess;
     // grid-stride: each block builds the cell table once for up to a few
     // thousand targets
     const int64_t blocks = std::min<int64_t>((t->n + 255) / 256, 1024);
-    hipLaunchKernelGGL(near_wall_features, dim3((unsigned)blocks), dim3(256), 0, st, t->n, t->x, t->y,
-                       tc, c->curve_off, c->n_curves, c->n_nodes, c->x, c->y, c->nx, c->ny, c->kappa, c->w, c->fx,
-                       c->fy, d, X, frame);
+    hipLaunchKernelGGL(near_wall_features, dim3((unsigned)blocks), dim3(256), 0, st, t->n, t->x, t->y, tc,
+                       c->curve_off, c->n_curves, c->n_nodes, c->x, c->y, c->nx, c->ny, c->kappa, c->w, d, dtab, X,
+                       frame);
     return hipGetLastError();
 }
 
-hipError_t near_launch_scale_labels(int64_t n, const double *du, const double *dv, const double *frame, double mu,
-                                    float *Y, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(near_scale_labels_k, dim3(grid_for(n)), dim3(256), 0, st, n, du, dv, frame, mu, Y);
-    return hipGetLastError();
-}
-
-hipError_t near_launch_infer(int64_t n, const float *X, const double *frame, const NearBlob *nb, double mu,
-                             double threshold, int use_bound, double *du, double *dv, int32_t *flag, hipStream_t st) {
+hipError_t near_launch_infer(int op, int64_t n, const float *X, const double *frame, const NearBlob *nb, double mu,
+                             double threshold, const int32_t *tc, int32_t n_curves, const double *curve_tol,
+                             int use_bound, double *du, double *dv, int32_t *flag, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     // 32 targets per wave, 4 waves per block
     const int64_t groups = (n + 31) / 32;
     const int64_t blocks = (groups + 3) / 4;
-    hipLaunchKernelGGL(near_mlp_infer_mfma, dim3((unsigned)blocks), dim3(256), 0, st, n, X, frame, nb, mu, threshold,
-                       use_bound, du, dv, flag);
+    if (op == S2D_OP_SLP)
+        hipLaunchKernelGGL(near_mlp_infer_mfma<S2D_OP_SLP>, dim3((unsigned)blocks), dim3(256), 0, st, n, X, frame, nb,
+                           mu, threshold, tc, n_curves, curve_tol, use_bound, du, dv, flag);
+    else
+        hipLaunchKernelGGL(near_mlp_infer_mfma<S2D_OP_DLP>, dim3((unsigned)blocks), dim3(256), 0, st, n, X, frame, nb,
+                           mu, threshold, tc, n_curves, curve_tol, use_bound, du, dv, flag);
     return hipGetLastError();
 }
 
 hipError_t near_launch_pack(const float *prm, const float *bound, const float *bound_zero, int32_t n_bins,
-                            float bin_lo, float bin_w, NearBlob *nb, hipStream_t st) {
-    hipLaunchKernelGGL(near_pack, dim3(grid_for(kNearBlobWork)), dim3(256), 0, st, prm, bound, bound_zero, n_bins,
-                       bin_lo, bin_w, nb);
+                            float bin_lo, float bin_w, float b_min, int32_t P, NearBlob *nb, hipStream_t st) {
+    hipLaunchKernelGGL(near_pack, dim3(32), dim3(256), 0, st, prm, bound, bound_zero, n_bins, bin_lo, bin_w, b_min, P,
+                       nb);
+    return hipGetLastError();
+}
+
+hipError_t near_launch_train_targets(int op, int64_t n, const double *frame, const double *du, const double *dv,
+                                     const int32_t *tc, int32_t n_curves, const double *ur, const double *vr,
+                                     double mu, int32_t P, float gain, uint32_t *cscale, float *T,
+                                     hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    if (n_curves > 0) {
+        hipError_t e = zero_int_launch((int32_t *)cscale, n_curves, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(near_curve_scale, dim3(grid_for(n)), dim3(256), 0, st, n, tc, n_curves, ur, vr, cscale);
+    }
+    if (op == S2D_OP_SLP)
+        hipLaunchKernelGGL(near_train_targets_k<S2D_OP_SLP>, dim3(grid_for(n)), dim3(256), 0, st, n, frame, du, dv, tc,
+                           n_curves, mu, P, gain, cscale, T);
+    else
+        hipLaunchKernelGGL(near_train_targets_k<S2D_OP_DLP>, dim3(grid_for(n)), dim3(256), 0, st, n, frame, du, dv, tc,
+                           n_curves, mu, P, gain, cscale, T);
     return hipGetLastError();
 }
 
 hipError_t near_launch_train_step(int32_t B, const int32_t *idx, const float *X, const float *T, float *prm,
                                   float *m, float *v, int32_t step, float lr, float *grad, float *act, float *dY,
                                   float *lossv, float *loss, int update, hipStream_t st) {
-    const MlpOffsets O;
+    using O = MlpOffsets;
     const unsigned wave_blocks = (unsigned)((B + kBlock / kWave - 1) / (kBlock / kWave));   // a wave per sample
     hipLaunchKernelGGL(mlp_fwd, dim3(wave_blocks), dim3(kBlock), 0, st, B, idx, X, T, prm, act, dY, lossv);
     hipLaunchKernelGGL(mlp_bwd, dim3(wave_blocks), dim3(kBlock), 0, st, B, prm, act, dY);
-    hipLaunchKernelGGL(mlp_grad, dim3((unsigned)((O.total + kBlock / kGradChunks - 1) / (kBlock / kGradChunks))),
+    hipLaunchKernelGGL(mlp_grad, dim3((unsigned)((O::total + kBlock / kGradChunks - 1) / (kBlock / kGradChunks))),
                        dim3(kBlock), 0, st, B, act, dY, lossv, grad, loss);
     if (update)
-        hipLaunchKernelGGL(mlp_adam, dim3(grid_for(O.total)), dim3(256), 0, st, prm, grad, m, v, step, lr, 0.9f,
+        hipLaunchKernelGGL(mlp_adam, dim3(grid_for(O::total)), dim3(256), 0, st, prm, grad, m, v, step, lr, 0.9f,
                            0.999f, 1e-8f);
     return hipGetLastError();
 }
@@ -1186,6 +1772,28 @@ hipError_t near_launch_train_step(int32_t B, const int32_t *idx, const float *X,
 hipError_t near_launch_fwd(int64_t n, const float *X, const float *prm, float *Y, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(mlp_fwd_only, dim3(grid_for(n)), dim3(256), 0, st, n, X, prm, Y);
+    return hipGetLastError();
+}
+
+hipError_t near_launch_feature_stats(int64_t n, const float *X, float *prm, hipStream_t st) {
+    hipLaunchKernelGGL(near_feature_stats_k, dim3(kNearFeat), dim3(256), 0, st, n, X, prm);
+    return hipGetLastError();
+}
+
+hipError_t near_launch_calibrate(int op, int64_t n, const double *frame, const double *dup, const double *dvp,
+                                 const double *du, const double *dv, double mu, int32_t n_bins, float bin_lo,
+                                 float bin_w, float b_min, float margin, uint32_t *bound, uint32_t *bound_zero,
+                                 int32_t *count, hipStream_t st) {
+    hipLaunchKernelGGL(near_calib_init, dim3(1), dim3(256), 0, st, n_bins, bound, bound_zero, count);
+    if (n > 0) {
+        if (op == S2D_OP_SLP)
+            hipLaunchKernelGGL(near_calib_acc<S2D_OP_SLP>, dim3(grid_for(n)), dim3(256), 0, st, n, frame, dup, dvp, du,
+                               dv, mu, n_bins, bin_lo, bin_w, b_min, bound, bound_zero, count);
+        else
+            hipLaunchKernelGGL(near_calib_acc<S2D_OP_DLP>, dim3(grid_for(n)), dim3(256), 0, st, n, frame, dup, dvp, du,
+                               dv, mu, n_bins, bin_lo, bin_w, b_min, bound, bound_zero, count);
+    }
+    hipLaunchKernelGGL(near_calib_finish, dim3(1), dim3(256), 0, st, n_bins, margin, bound, bound_zero, count);
     return hipGetLastError();
 }
 

@@ -4,34 +4,57 @@
 
 namespace s2d {
 
-constexpr int kNearFeat = 20;
-constexpr int kNearMaxBins = 64;
-constexpr int kActStride = 20 + 6 * 64;      // h0 z1 h1 z2 h2 z3 h3 per training sample
+// Learned correction (see near.hip): 14 geometry features per target, a
+// frame record of kNearFrame doubles {s, b, t_x, t_y, n_x, n_y, hl, F, sg,
+// d_0t, d_0n, ..., d_4t, d_4n, sg kappa hl} (offsets in units of hl, n the normal
+// towards the target, sg the sign of the offset along the node normal, d the
+// density's node derivatives in the frame, F = sum |d|), and a 64-64-64
+// network with 20 outputs dC[p][out][in].
+constexpr int kNearFeat = 14;
+constexpr int kNearDeriv = 5;
+constexpr int kNearOut = 4 * kNearDeriv;
+constexpr int kNearFrame = 20;
+constexpr int kNearMaxBins = 64;                // bins of log10 b
+constexpr int kNearSBins = 4;                   // bins of |s|: width 1/8, the last open
+constexpr int kNearKBins = 8;                   // bins of log10 |kappa h| from -2, width 3/16, both ends open
+constexpr int kNearCell = kNearSBins * kNearKBins;
+constexpr int kNearTable = kNearMaxBins * kNearCell;
+constexpr int kActStride = kNearFeat + 6 * 64;   // h0 z1 h1 z2 h2 z3 h3 per training sample
+// training sample record (floats): d[10] (frame, d_pt at 2p, d_pn at 2p + 1),
+// the flat prediction's residual R[2] (frame, units of the layer's scale),
+// the loss weight, exp(-2 pi b)
+constexpr int kNearTStride = 14;
 
 // FP32 master parameter vector: standardisation, then W (in x out, row
 // major) and b of each layer.
 struct MlpOffsets {
-    int mu = 0, sd = 20, W1 = 40, b1 = 40 + 1280, W2 = 1384, b2 = 1384 + 4096, W3 = 5544, b3 = 5544 + 4096,
-        W4 = 9704, b4 = 9704 + 128, total = 9834;
+    static constexpr int mu = 0, sd = kNearFeat, W1 = 2 * kNearFeat, b1 = W1 + kNearFeat * 64, W2 = b1 + 64,
+                         b2 = W2 + 4096, W3 = b2 + 64, b3 = W3 + 4096, W4 = b3 + 64, b4 = W4 + 64 * kNearOut,
+                         total = b4 + kNearOut;
 };
 
-// BF16 inference blob (device): weights as [out][in / 2] bf16 pairs.
+// BF16 inference blob (device): weights as [out][in / 2] bf16 pairs; the
+// last layer padded to 32 output rows.
 struct NearBlob {
     float mu_in[kNearFeat], isd_in[kNearFeat];
-    uint32_t W1[64 * kNearFeat / 2];
+    uint32_t W1[64 * 8];              // first layer: rows padded to 8 input pairs
     float b1[64];
     uint32_t W2[64 * 32];
     float b2[64];
     uint32_t W3[64 * 32];
     float b3[64];
-    uint32_t W4[2 * 32];
-    float b4[2];
+    uint32_t W4[32 * 32];
+    float b4[32];
     int32_t n_bins;
-    float bin_lo, bin_w;
-    float bound[kNearMaxBins];        // network error bound per bin (scaled units)
-    float bound_zero[kNearMaxBins];   // plain-rule error bound per bin (scaled units)
+    float bin_lo, bin_w;              // bins of log10(b)
+    float b_min;                      // smaller normal offsets go to the quadrature
+    int32_t P;                        // upsampling factor of the quadrature the network was trained on
+    // per bin (log10 b bin k, |s| bin j, |kappa h| bin m at kNearCell k +
+    // kNearKBins j + m): the network's error bound and the largest
+    // correction, in units of the layer's scale times F
+    float bound[kNearTable];
+    float bound_zero[kNearTable];
 };
-constexpr int kNearBlobWork = kNearFeat + 64 * kNearFeat / 2 + 2 * 64 * 32 + 2 * 32 + 64;
 
 hipError_t near_launch_upsample(const s2d_curves *c, int P, double *up, hipStream_t st);
 // list / list_len (device): when list != NULL only targets list[q],
@@ -43,24 +66,38 @@ hipError_t near_launch_quad(const s2d_curves *c, const s2d_targets *t, const int
 // the targets with flag == 1, in order, into list; their number into
 // cnt[ceil(n / 256)] (cnt: ceil(n / 256) + 1 ints of scratch)
 hipError_t near_launch_compact(int64_t n, const int32_t *flag, int32_t *cnt, int32_t *list, hipStream_t st);
-hipError_t near_launch_features(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, float *X,
-                                double *frame, hipStream_t st);
-hipError_t near_launch_scale_labels(int64_t n, const double *du, const double *dv, const double *frame, double mu,
-                                    float *Y, hipStream_t st);
+// the density's node derivatives (kNearDeriv x 2 doubles per node, d_p of x
+// then y at 2p, 2p + 1), per-node units
+// scratch: near_derivs_scratch(c) bytes (8-byte aligned), used when some
+// curve has more than kUpMaxN nodes
+size_t near_derivs_scratch(const s2d_curves *c);
+hipError_t near_launch_derivs(const s2d_curves *c, double *dtab, double *scratch, hipStream_t st);
+hipError_t near_launch_features(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, const double *dtab,
+                                float *X, double *frame, hipStream_t st);
 hipError_t near_launch_wall_features(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, double d,
-                                     float *X, double *frame, hipStream_t st);
-// The walls' labels and inference reuse the single layer's scale
-// h F / (4 pi mu): with the frame's length factor 1 and mu = 1/4 it is the
-// double layer's F / pi.
-constexpr double kWallMuScale = 0.25;
-hipError_t near_launch_infer(int64_t n, const float *X, const double *frame, const NearBlob *nb, double mu,
-                             double threshold, int use_bound, double *du, double *dv, int32_t *flag, hipStream_t st);
+                                     const double *dtab, float *X, double *frame, hipStream_t st);
+// op: S2D_OP_SLP (vesicles, scale hl / 4 pi mu, side +1) or S2D_OP_DLP
+// (walls, scale 1 / pi, side -1)
+// tolerance of target i: curve_tol[tc[i]] when curve_tol != NULL (and tc[i]
+// names a curve), else threshold
+hipError_t near_launch_infer(int op, int64_t n, const float *X, const double *frame, const NearBlob *nb, double mu,
+                             double threshold, const int32_t *tc, int32_t n_curves, const double *curve_tol,
+                             int use_bound, double *du, double *dv, int32_t *flag, hipStream_t st);
 hipError_t near_launch_pack(const float *prm, const float *bound, const float *bound_zero, int32_t n_bins,
-                            float bin_lo, float bin_w, NearBlob *nb, hipStream_t st);
+                            float bin_lo, float bin_w, float b_min, int32_t P, NearBlob *nb, hipStream_t st);
+hipError_t near_launch_train_targets(int op, int64_t n, const double *frame, const double *du, const double *dv,
+                                     const int32_t *tc, int32_t n_curves, const double *ur, const double *vr,
+                                     double mu, int32_t P, float gain, uint32_t *cscale, float *T,
+                                     hipStream_t st);
 hipError_t near_launch_train_step(int32_t B, const int32_t *idx, const float *X, const float *T, float *prm,
                                   float *m, float *v, int32_t step, float lr, float *grad, float *act, float *dY,
                                   float *lossv, float *loss, int update, hipStream_t st);
 hipError_t near_launch_fwd(int64_t n, const float *X, const float *prm, float *Y, hipStream_t st);
+hipError_t near_launch_feature_stats(int64_t n, const float *X, float *prm, hipStream_t st);
+hipError_t near_launch_calibrate(int op, int64_t n, const double *frame, const double *dup, const double *dvp,
+                                 const double *du, const double *dv, double mu, int32_t n_bins, float bin_lo,
+                                 float bin_w, float b_min, float margin, uint32_t *bound, uint32_t *bound_zero,
+                                 int32_t *count, hipStream_t st);
 
 constexpr int kUpMaxN = 256;      // coarse nodes per curve for upsampling
 constexpr int kUpMaxM = 2048;     // fine nodes per curve

@@ -187,8 +187,8 @@ def test_wall_argument_checks(L):
     assert L.stokes2d_wall_upsample(by(none), 1.0, 4, *o, fake, 1 << 20, None) == s2d.S2D_EINVAL
     # the correction: free targets only, outputs, images, method, network
     def corr(method, trg, lo, hi, du, mlp=None, tc=fake):
-        return L.near_wall_correct_eval(method, by(walls), by(trg), tc, 1.0, lo, hi, 8, mlp, 0.0, du, fake, None,
-                                        0, fake, 1 << 30, None)
+        return L.near_wall_correct_eval(method, by(walls), by(trg), tc, 1.0, lo, hi, 8, mlp, 0.0, None, du, fake,
+                                        None, 0, fake, 1 << 30, None)
     assert corr(0, ts_on, -1, 1, fake) == s2d.S2D_EINVAL
     assert corr(0, ts, -1, 1, None) == s2d.S2D_EINVAL
     assert corr(0, ts, 1, -1, fake) == s2d.S2D_EINVAL
@@ -196,7 +196,50 @@ def test_wall_argument_checks(L):
     assert corr(1, ts, -1, 1, fake, mlp=None) == s2d.S2D_EINVAL            # MLP needs the network
     assert corr(2, ts, -1, 1, fake, mlp=fake, tc=None) == s2d.S2D_EINVAL   # and trg_curve
     assert corr(1, ts, -1, 1, fake, mlp=fake) == s2d.S2D_EINVAL            # and the walls' w, kappa
-    assert L.near_wall_features_eval(by(walls), by(ts), None, 1.0, fake, fake, None) == s2d.S2D_EINVAL
+    assert L.near_wall_features_eval(by(walls), by(ts), None, 1.0, fake, fake, fake, None) == s2d.S2D_EINVAL
+    assert L.near_wall_features_eval(by(walls), by(ts), fake, 1.0, None, fake, fake, None) == s2d.S2D_EINVAL
+
+
+def test_learned_near_argument_checks(L):
+    """Argument checks of the learned correction's entry points (all fail
+    before any device call)."""
+    import paper_1510_05616_amd as s2d
+    from paper_1510_05616_amd import near as pn
+    pn._bind()
+    fake = ctypes.c_void_p(0x1000)
+    odd = ctypes.c_void_p(0x1004)
+    by = ctypes.byref
+    small = s2d._Curves(200, 2, fake, fake, fake, fake, fake, fake, fake, fake, fake)
+    big = s2d._Curves(4000, 2, fake, fake, fake, fake, fake, fake, fake, fake, fake)
+    assert L.near_derivs_workspace_size(by(small)) == 256
+    need = L.near_derivs_workspace_size(by(big))
+    assert need >= 4000 * 6 * 8
+    assert L.near_derivs_eval(by(big), fake, fake, need - 256, None) == s2d.S2D_EWORKSPACE
+    assert L.near_derivs_eval(by(big), None, fake, need, None) == s2d.S2D_EINVAL
+    nof = s2d._Curves(200, 2, fake, fake, fake, fake, fake, fake, fake, None, fake)     # no fx
+    assert L.near_derivs_eval(by(nof), fake, None, 0, None) == s2d.S2D_EINVAL
+    # training records: op, weight gain, mu, upsample, NULL arrays
+    tt = lambda op=0, n=10, gain=1.0, mu=1.0, P=8, cs=fake: L.near_train_targets(
+        op, n, fake, fake, fake, fake, 2, fake, fake, mu, P, gain, cs, fake, None)
+    assert tt(op=2) == s2d.S2D_EINVAL and tt(op=4) == s2d.S2D_EINVAL
+    assert tt(gain=0.0) == s2d.S2D_EINVAL and tt(gain=float("nan")) == s2d.S2D_EINVAL
+    assert tt(mu=0.0) == s2d.S2D_EINVAL and tt(P=0) == s2d.S2D_EINVAL and tt(n=-1) == s2d.S2D_EINVAL
+    assert tt(cs=None) == s2d.S2D_EINVAL
+    # calibration: bins, margin, b_min
+    cal = lambda nb=64, w=0.03, bmin=0.05, margin=1.25, op=0: L.near_calibrate(
+        op, 10, fake, fake, fake, fake, fake, 1.0, nb, -1.3, w, bmin, margin, fake, fake, fake, None)
+    assert cal(nb=0) == s2d.S2D_EINVAL and cal(nb=65) == s2d.S2D_EINVAL
+    assert cal(w=0.0) == s2d.S2D_EINVAL and cal(margin=0.9) == s2d.S2D_EINVAL
+    assert cal(bmin=-1.0) == s2d.S2D_EINVAL and cal(op=3) == s2d.S2D_EINVAL
+    # packing: bins, bounds, b_min, upsample, blob alignment
+    pk = lambda nb=64, bound=fake, bmin=0.05, P=8, blob=fake: L.near_mlp_pack(
+        fake, bound, None, nb, -1.3, 0.03, bmin, P, blob, None)
+    assert pk(nb=65) == s2d.S2D_EINVAL and pk(bound=None) == s2d.S2D_EINVAL
+    assert pk(bmin=-0.1) == s2d.S2D_EINVAL and pk(P=33) == s2d.S2D_EINVAL
+    assert pk(blob=odd) == s2d.S2D_EINVAL
+    assert L.near_feature_stats(10, fake, None, None) == s2d.S2D_EINVAL
+    assert L.near_feature_stats(-1, fake, fake, None) == s2d.S2D_EINVAL
+    assert L.near_mlp_blob_size() >= 4 * (64 * 8 + 2 * 64 * 32 + 32 * 32)
 
 
 def test_vesicle_argument_checks(L):

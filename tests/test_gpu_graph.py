@@ -101,12 +101,14 @@ def test_near_correction_replays_in_a_graph():
     from oracle import near as onear
     c, tx, ty, tc, dh = synth.make_near_dataset(3000, seed=23, per_curve=150)
     data = near.NearData(c, tx, ty, tc, mu=1.0, upsample=8, labels=False)
-    p = onear.init_params(seed=4, mu_in=np.zeros(20), sd_in=np.ones(20))
+    p = onear.init_params(seed=4, mu_in=np.zeros(14), sd_in=np.ones(14))
     prm = torch.as_tensor(near.dict_to_params(p).astype(np.float32), device="cuda")
-    # bins below 0.5 h fall back to the upsampled quadrature, the others use
-    # the network: both branches and the fallback mask are exercised
-    bound = torch.tensor([1.0] * 10 + [1e-9] * 10, dtype=torch.float32, device="cuda")
-    bound0 = torch.ones(near.N_BINS, dtype=torch.float32, device="cuda")
+    # bins below b = 0.5 fall back to the upsampled quadrature, the others use
+    # the learned route: both branches and the fallback mask are exercised
+    half = int(round((math.log10(0.5) - near.BIN_LO) / near.BIN_W))
+    bound = torch.tensor([1.0] * half + [1e-9] * (near.N_BINS - half), dtype=torch.float32,
+                         device="cuda").repeat_interleave(near.CELL)
+    bound0 = torch.ones(near.N_BINS * near.CELL, dtype=torch.float32, device="cuda")
     blob = torch.zeros(near.near_mlp_blob_size(), dtype=torch.uint8, device="cuda")
     near.near_mlp_pack(prm, bound, near.N_BINS, near.BIN_LO, near.BIN_W, blob, bound_zero=bound0)
     n = data.n

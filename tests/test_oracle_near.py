@@ -187,10 +187,10 @@ def test_features_reconstruct_target_and_frame():
             assert abs(gx - c.x[k]) < 1e-13 and abs(gy - c.y[k]) < 1e-13
         Q = np.exp(-2 * np.pi * (b + 1j * sv))
         assert abs(X[i, 12] - Q.real) < 1e-15 and abs(X[i, 13] - Q.imag) < 1e-15
-        # d_0 is the density at k* in the frame, F its largest entry
+        # d_0 is the density at k* in the frame, F the sum of |d| over p and components
         assert abs(dd[i, 0, 0] * t0 + dd[i, 0, 1] * nf0 - c.fx[ks]) < 1e-13
         assert abs(dd[i, 0, 0] * t1 + dd[i, 0, 1] * nf1 - c.fy[ks]) < 1e-13
-        assert F == np.abs(dd[i]).max()
+        assert F == np.abs(dd[i]).sum()
 
 
 def test_flat_prediction_captures_most_of_the_label():
