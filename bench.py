@@ -336,14 +336,15 @@ def wall_section(prob, n_trg=20000, P=8, reps=5):
                                        "given double layers by direct FP64 sums"}}
 
 
-def wall_learned_section(prob, n_train=200000, n_test=1000000, epochs=40):
+def wall_learned_section(prob, n_train=200000, n_test=1000000, steps=200000):
     """The learned route for the walls on the 128k channel's walls (2 x
     16,000 nodes, smooth densities, images -1..1): the network trained on
     200,000 targets at log-uniform distances 0.05..5 spacings (labels from
-    the 8x refined walls), calibrated on 20,000, then on 1,000,000 test
-    targets the refined quadrature (every target against all 256,000 refined
-    nodes), the network alone, and AUTO at a threshold of 1e-3 of the
-    largest correction.  Errors in the labels' units (Delta pi / F)."""
+    the 8x refined walls) for 200,000 steps, calibrated on 1,000,000, then on
+    1,000,000 test targets the refined quadrature (every target against all
+    256,000 refined nodes), the learned route alone, and AUTO at per-wall
+    tolerances of 1e-4 and 1e-3 of each wall's largest |D_P|.  Errors are
+    normalised per wall by that largest |D_P|."""
     import torch
     import synth
     from paper_1510_05616_amd import near as pn
@@ -351,50 +352,57 @@ def wall_learned_section(prob, n_train=200000, n_test=1000000, epochs=40):
     d = prob.d
     t0 = time.time()
     tr = pn.WallNearData(walls, d, *synth.near_wall_dataset(walls, n_train, 42))
-    va = pn.WallNearData(walls, d, *synth.near_wall_dataset(walls, 100000, 43))
-    te = pn.WallNearData(walls, d, *synth.near_wall_dataset(walls, n_test, 44))
     torch.cuda.synchronize()
     t_data = time.time() - t0
     t0 = time.time()
-    params, hist = pn.train(tr, epochs=epochs, batch=512, lr=3e-3)
+    params, hist = pn.train(tr, steps=steps, batch=1024, lr=2e-3, log_every=steps)
     torch.cuda.synchronize()
     t_train = time.time() - t0
-    blob, bound, bound0 = pn.calibrate(va, params)
+    del tr
+    va = pn.WallNearData(walls, d, *synth.near_wall_dataset(walls, 1000000, 43))
+    blob, bound, bound0, count = pn.calibrate(va, params, margin=1.5)
+    del va
+    te = pn.WallNearData(walls, d, *synth.near_wall_dataset(walls, n_test, 44))
     du = torch.empty(te.n, dtype=torch.float64, device="cuda")
     dv = torch.empty_like(du)
     fb = torch.zeros(te.n, dtype=torch.int32, device="cuda")
-    thr = 1e-3 * te.du.abs().max().item()
     ws = {m: torch.empty(pn.near_wall_workspace_size(te.curves, te.trg, 8, m), dtype=torch.uint8, device="cuda")
           for m in (pn.S2D_NEAR_UPSAMPLE, pn.S2D_NEAR_MLP, pn.S2D_NEAR_AUTO)}
+    tols = {rel: te.curve_tolerance(rel) for rel in (1e-4, 1e-3)}
     run = {
         "upsampled": lambda: pn.near_wall_correct_eval(te.curves, te.trg, d, -1, 1, 8, du, dv,
                                                        ws=ws[pn.S2D_NEAR_UPSAMPLE]),
-        "mlp": lambda: pn.near_wall_correct_eval(te.curves, te.trg, d, -1, 1, 8, du, dv, method=pn.S2D_NEAR_MLP,
-                                                 trg_curve=te.tc, blob=blob, ws=ws[pn.S2D_NEAR_MLP]),
-        "auto": lambda: pn.near_wall_correct_eval(te.curves, te.trg, d, -1, 1, 8, du, dv, method=pn.S2D_NEAR_AUTO,
-                                                  trg_curve=te.tc, blob=blob, threshold=thr, used_fallback=fb,
-                                                  ws=ws[pn.S2D_NEAR_AUTO]),
+        "learned": lambda: pn.near_wall_correct_eval(te.curves, te.trg, d, -1, 1, 8, du, dv,
+                                                     method=pn.S2D_NEAR_MLP, trg_curve=te.tc, blob=blob,
+                                                     ws=ws[pn.S2D_NEAR_MLP]),
     }
+    for rel, tol in tols.items():
+        run[f"auto_{rel:g}"] = (lambda tol=tol: pn.near_wall_correct_eval(
+            te.curves, te.trg, d, -1, 1, 8, du, dv, method=pn.S2D_NEAR_AUTO, trg_curve=te.tc, blob=blob,
+            used_fallback=fb, ws=ws[pn.S2D_NEAR_AUTO], curve_tol=tol))
     out = {"workload": "learned wall correction: 128k channel walls (2 x 16,000 nodes), 1,000,000 test targets "
-                       "at 0.05..5 spacings, images -1..1, refined 8x",
-           "train_s": t_train, "data_s": t_data, "loss": [hist[0], hist[-1]]}
+                       "at 0.05..5 spacings, images -1..1, refined 8x; trained on 200,000 targets, calibrated on "
+                       "1,000,000",
+           "train_s": t_train, "data_s": t_data, "train_steps": steps, "loss": [hist[0][1], hist[-1][1]]}
     for name, fn in run.items():
         ms = _time(fn, reps=2)
+        fn()
         torch.cuda.synchronize()
-        e = (torch.hypot(du - te.du, dv - te.dv) * math.pi / te.frame[:, 5]).max().item()
-        out[name] = {"ms": ms, "max_scaled_error": e}
-        if name == "auto":
-            out[name]["threshold"] = thr
-            out[name]["fractions_network_quadrature_none"] = [(fb == k).float().mean().item() for k in range(3)]
-            out[name]["max_error"] = torch.hypot(du - te.du, dv - te.dv).max().item()
+        e = te.scaled_errors(du, dv)
+        out[name] = {"ms": ms, "max_normalised_error": e.max().item(),
+                     "max_scaled_error_pi_over_d0": (torch.hypot(du - te.du, dv - te.dv) * math.pi
+                                                     / te.frame[:, 9:11].abs().sum(1)).max().item()}
+        if name.startswith("auto"):
+            out[name]["fractions_learned_quadrature_none"] = [(fb == k).float().mean().item() for k in range(3)]
     base = out["upsampled"]["ms"]
-    for name in ("mlp", "auto"):
-        out[name]["speedup_vs_upsampled"] = base / out[name]["ms"]
-    log(f"walls learned: train {t_train:.1f}s (loss {hist[0]:.3e} -> {hist[-1]:.3e}); upsampled {base:.1f} ms, "
-        f"mlp {out['mlp']['ms']:.2f} ms ({out['mlp']['speedup_vs_upsampled']:.0f}x, max scaled error "
-        f"{out['mlp']['max_scaled_error']:.2e}), auto {out['auto']['ms']:.1f} ms "
-        f"({out['auto']['speedup_vs_upsampled']:.2f}x, max error {out['auto']['max_error']:.2e} <= {thr:.2e}, "
-        f"fractions {out['auto']['fractions_network_quadrature_none']})")
+    for name in out:
+        if isinstance(out[name], dict) and name != "upsampled":
+            out[name]["speedup_vs_upsampled"] = base / out[name]["ms"]
+    log(f"walls learned: train {t_train:.1f}s; upsampled {base:.1f} ms; learned {out['learned']['ms']:.2f} ms "
+        f"(E={out['learned']['max_normalised_error']:.2e}); " + "; ".join(
+            f"{k}: {v['ms']:.2f} ms E={v['max_normalised_error']:.2e} fractions "
+            + "/".join(f"{x:.2f}" for x in v["fractions_learned_quadrature_none"])
+            for k, v in out.items() if k.startswith("auto")))
     return out
 
 
@@ -640,101 +648,95 @@ def batch_section():
     return res
 
 
-def near_section():
+def near_section(steps=200000):
     """Learned near-field correction on the near-target workload: train on
-    200k targets, calibrate on 100k, test on 1M (targets at log-uniform
-    normal distances 0.05 h .. 5 h from ellipses of 64-128 nodes).  Errors are
-    normalised per curve by the largest |u| of the 8x upsampled single layer
-    over that curve's test targets."""
+    200k targets (200,000 steps of 1024 on the GPU), calibrate on 1M, test on
+    1M (targets at log-uniform normal distances 0.05 h .. 5 h from ellipses
+    of 64-128 nodes).  Errors are normalised per curve by the largest |u| of
+    the 8x upsampled single layer over that curve's test targets; AUTO takes
+    per-curve tolerances of rel times that scale."""
     import torch
     import synth
     from paper_1510_05616_amd import near
     t0 = time.time()
     tr = near.NearData(*synth.make_near_dataset(200000, 5)[:4], mu=1.0, upsample=8)
-    va = near.NearData(*synth.make_near_dataset(100000, 6)[:4], mu=1.0, upsample=8)
-    c, tx, ty, tc, dh = synth.make_near_dataset(1000000, 7)
-    te = near.NearData(c, tx, ty, tc, mu=1.0, upsample=8, labels=False)
-    log(f"near: data ready ({time.time() - t0:.1f}s)")
+    torch.cuda.synchronize()
+    log(f"near: training data ready ({time.time() - t0:.1f}s)")
     t0 = time.time()
-    params, hist = near.train(tr, epochs=40, batch=512, lr=3e-3)
+    params, hist = near.train(tr, steps=steps, batch=1024, lr=2e-3, log_every=steps)
     torch.cuda.synchronize()
     t_train = time.time() - t0
-    blob, bound, bound0 = near.calibrate(va, params)
-    log(f"near: trained 40 epochs in {t_train:.1f}s, loss {hist[0]:.3e} -> {hist[-1]:.3e}")
+    del tr
+    va = near.NearData(*synth.make_near_dataset(1000000, 6)[:4], mu=1.0, upsample=8)
+    blob, bound, bound0, count = near.calibrate(va, params, margin=1.5)
+    del va
+    log(f"near: trained {steps} steps in {t_train:.1f}s, loss {hist[0][1]:.3e} -> {hist[-1][1]:.3e}")
+    te = near.NearData(*synth.make_near_dataset(1000000, 7)[:4], mu=1.0, upsample=8)
     n = te.n
-    dev = "cuda"
-    uP = torch.empty(n, dtype=torch.float64, device=dev)
-    vP, u1, v1 = torch.empty_like(uP), torch.empty_like(uP), torch.empty_like(uP)
-    near.near_upsampled_slp(te.curves, te.trg, te.tc, 8, 1.0, uP, vP, u1, v1)
-    d_up, e_up = uP - u1, vP - v1
-    tcl = te.tc.long()
-    mag = torch.hypot(uP, vP)
-    scale_c = torch.zeros(te.curves.n_curves, dtype=torch.float64, device=dev).scatter_reduce(
-        0, tcl, mag, reduce="amax", include_self=False)
-    scale = scale_c[tcl]
-    thr = 1e-5 * float(scale_c.min())
-    du, dv = torch.empty_like(uP), torch.empty_like(uP)
-    fb = torch.zeros(n, dtype=torch.int32, device=dev)
-    ws_up = near._empty(near.near_workspace_size(0, te.curves, te.trg, 8))
-    ws_ml = near._empty(near.near_workspace_size(2, te.curves, te.trg, 8))
-    run = lambda m, th=0.0, flag=None, ws=ws_ml: near.near_correct_eval(m, te.curves, te.trg, te.tc, 8, blob, th,
-                                                                      1.0, du, dv, flag, ws)
+    du, dv = (torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(2))
+    fb = torch.zeros(n, dtype=torch.int32, device="cuda")
+    ws_up = near._empty(near.near_workspace_size(near.S2D_NEAR_UPSAMPLE, te.curves, te.trg, 8))
+    ws_ml = near._empty(near.near_workspace_size(near.S2D_NEAR_AUTO, te.curves, te.trg, 8))
+    run = lambda m, th=0.0, flag=None, ws=ws_ml, tol=None: near.near_correct_eval(
+        m, te.curves, te.trg, te.tc, 8, blob, th, 1.0, du, dv, flag, ws, curve_tol=tol)
+    err = lambda: te.scaled_errors(du, dv).max().item()
     ms_up = _time(lambda: run(near.S2D_NEAR_UPSAMPLE, ws=ws_up))
     ms_mlp = _time(lambda: run(near.S2D_NEAR_MLP))
-    err = lambda: float((torch.hypot(du - d_up, dv - e_up) / scale).max())
     run(near.S2D_NEAR_MLP)
+    torch.cuda.synchronize()
     e_mlp = err()
-    ms_auto = _time(lambda: run(near.S2D_NEAR_AUTO, thr, fb))
+    err_mlp = te.scaled_errors(du, dv).cpu().numpy()
+    auto = {}
+    for rel in (1e-5, 3e-5, 1e-4):
+        tol = te.curve_tolerance(rel)
+        ms = _time(lambda: run(near.S2D_NEAR_AUTO, 0.0, fb, tol=tol))
+        run(near.S2D_NEAR_AUTO, 0.0, fb, tol=tol)
+        torch.cuda.synchronize()
+        auto[f"{rel:g}"] = {"ms": ms, "speedup_vs_upsampled8": ms_up / ms, "err": err(),
+                            "fractions_learned_quadrature_none": [float((fb == k).double().mean()) for k in range(3)]}
+    # one scalar tolerance for every curve: 1e-5 of the smallest curve scale
+    thr = 1e-5 * te.curve_scale.min().item()
+    ms_s = _time(lambda: run(near.S2D_NEAR_AUTO, thr, fb))
     run(near.S2D_NEAR_AUTO, thr, fb)
-    e_auto = err()
-    frac_fb = float((fb == 1).double().mean())
-    frac_zero = float((fb == 2).double().mean())
-    e_plain = float((torch.hypot(d_up, e_up) / scale).max())
-    # AUTO at looser thresholds (relative to the smallest per-curve scale, as above)
-    sweep = {}
-    for rel in (1e-4, 1e-3, 1e-2):
-        th = rel * float(scale_c.min())
-        ms = _time(lambda: run(near.S2D_NEAR_AUTO, th, fb))
-        run(near.S2D_NEAR_AUTO, th, fb)
-        sweep[f"{rel:g}"] = {"ms": ms, "speedup_vs_upsampled8": ms_up / ms, "err": err(),
-                             "fractions_network_quadrature_none": [float((fb == k).double().mean()) for k in range(3)]}
-    log("near: auto at looser thresholds: " + "; ".join(
-        f"{k}: {v['ms']:.2f} ms ({v['speedup_vs_upsampled8']:.2f}x, E={v['err']:.1e}, network/quadrature/none "
-        + "/".join(f"{x:.2f}" for x in v["fractions_network_quadrature_none"]) + ")" for k, v in sweep.items()))
+    torch.cuda.synchronize()
+    auto_scalar = {"threshold": thr, "ms": ms_s, "speedup_vs_upsampled8": ms_up / ms_s, "err": err(),
+                   "fractions_learned_quadrature_none": [float((fb == k).double().mean()) for k in range(3)]}
+    e_plain = te.scaled_errors(torch.zeros_like(du), torch.zeros_like(dv))
+    err_plain = e_plain.cpu().numpy()
     # 32x upsampled quadrature as context for the 8x reference (64-node curves,
     # the largest that 32x upsampling supports)
     c64 = synth.make_near_dataset(100000, 8, sizes=(64,))
     d64 = near.NearData(*c64[:4], mu=1.0, upsample=8, labels=False)
-    a8, b8, a1, b1 = (torch.empty(d64.n, dtype=torch.float64, device=dev) for _ in range(4))
+    a8, b8, a1, b1 = (torch.empty(d64.n, dtype=torch.float64, device="cuda") for _ in range(4))
     a32, b32 = torch.empty_like(a8), torch.empty_like(a8)
     near.near_upsampled_slp(d64.curves, d64.trg, d64.tc, 8, 1.0, a8, b8, a1, b1)
     near.near_upsampled_slp(d64.curves, d64.trg, d64.tc, 32, 1.0, a32, b32, a1, b1)
     t64 = d64.tc.long()
-    s64 = torch.zeros(d64.curves.n_curves, dtype=torch.float64, device=dev).scatter_reduce(
+    s64 = torch.zeros(d64.curves.n_curves, dtype=torch.float64, device="cuda").scatter_reduce(
         0, t64, torch.hypot(a32, b32), reduce="amax", include_self=False)[t64]
     e_8v32 = float((torch.hypot(a8 - a32, b8 - b32) / s64).max())
-    # what the network gains: median errors per band of normal offset / h
-    run(near.S2D_NEAR_MLP)
-    err_mlp = (torch.hypot(du - d_up, dv - e_up) / scale).cpu().numpy()
-    err_plain = (torch.hypot(d_up, e_up) / scale).cpu().numpy()
-    noff = np.abs(te.X[:, 1].double().cpu().numpy())
+    b = te.b.cpu().numpy()
     gain = {}
     for lo, hi in ((0.05, 0.2), (0.2, 0.5), (0.5, 1.0), (1.0, 2.0), (2.0, 5.1)):
-        m = (noff >= lo) & (noff < hi)
-        gain[f"{lo}-{hi}h"] = {"plain_median": float(np.median(err_plain[m])),
-                               "mlp_median": float(np.median(err_mlp[m])), "mlp_max": float(err_mlp[m].max())}
-    res = {"workload": "1e6 targets at 0.05h..5h from 5000 ellipses of 64/96/128 nodes; MLP 20-64-64-64-2 "
-                       "trained on 2e5 8x-upsampled labels, calibrated on 1e5",
-           "threshold_abs": thr, "err_vs_upsampled8": {"mlp": e_mlp, "auto": e_auto, "no_correction": e_plain},
-           "err_upsampled8_vs_32_on_64_node_curves": e_8v32, "error_by_offset_band": gain,
-           "auto_fraction_fallback": frac_fb, "auto_fraction_no_correction":
-               frac_zero, "ms": {"upsampled8": ms_up, "mlp": ms_mlp, "auto": ms_auto},
-           "speedup_vs_upsampled8": {"mlp": ms_up / ms_mlp, "auto": ms_up / ms_auto},
-           "auto_looser_thresholds": sweep,
-           "train_s": t_train, "epochs": 40, "final_loss": hist[-1]}
-    log(f"near: upsampled {ms_up:.2f} ms, mlp {ms_mlp:.2f} ms (E={e_mlp:.2e}), auto {ms_auto:.2f} ms "
-        f"(E={e_auto:.2e}, fallback {frac_fb:.3f}, no-correction {frac_zero:.3f}); plain E={e_plain:.2e}, "
-        f"8x vs 32x {e_8v32:.2e}")
+        m = (b >= lo) & (b < hi)
+        gain[f"b {lo}-{hi}"] = {"plain_median": float(np.median(err_plain[m])),
+                                "learned_median": float(np.median(err_mlp[m])),
+                                "learned_q999": float(np.quantile(err_mlp[m], 0.999)),
+                                "learned_max": float(err_mlp[m].max())}
+    a5 = auto["1e-05"]
+    res = {"workload": "1e6 targets at 0.05h..5h from 5000 ellipses of 64/96/128 nodes; network 14-64-64-64-20 "
+                       "trained on the GPU on 2e5 8x-upsampled labels (200,000 steps of 1024), calibrated on 1e6",
+           "err_vs_upsampled8": {"learned": e_mlp, "auto_1e-5_per_curve": a5["err"],
+                                 "no_correction": float(err_plain.max())},
+           "err_upsampled8_vs_32_on_64_node_curves": e_8v32, "error_by_normal_offset": gain,
+           "ms": {"upsampled8": ms_up, "learned": ms_mlp, "auto_1e-5_per_curve": a5["ms"]},
+           "speedup_vs_upsampled8": {"learned": ms_up / ms_mlp, "auto_1e-5_per_curve": a5["speedup_vs_upsampled8"]},
+           "auto_per_curve": auto, "auto_scalar_1e-5_of_smallest_curve_scale": auto_scalar,
+           "train_s": t_train, "train_steps": steps, "loss": [hist[0][1], hist[-1][1]]}
+    log(f"near: upsampled {ms_up:.3f} ms, learned {ms_mlp:.3f} ms (E={e_mlp:.2e}); AUTO per curve " + "; ".join(
+        f"{k}: {v['ms']:.3f} ms ({v['speedup_vs_upsampled8']:.2f}x, E={v['err']:.2e}, learned/quadrature/none "
+        + "/".join(f"{x:.3f}" for x in v["fractions_learned_quadrature_none"]) + ")" for k, v in auto.items())
+        + f"; scalar {ms_s:.3f} ms (E={auto_scalar['err']:.2e}); plain E={err_plain.max():.2e}, 8x vs 32x {e_8v32:.2e}")
     return res
 
 

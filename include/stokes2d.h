@@ -384,8 +384,8 @@ S2D_API int near_upsampled_slp(const s2d_curves *ves, const s2d_targets *trg, co
  * 2p + 1.  Direct sums in FP64: one workgroup per curve up to 256 nodes,
  * a wave per coefficient and per node above (O(N^2) work per curve).  Serves
  * closed curves and wall periods alike (curves needs fx, fy and curve_off).
- * ws: near_derivs_workspace_size(curves) bytes, 256-byte aligned (needed
- * only when n_nodes > 256; NULL otherwise). */
+ * ws: near_derivs_workspace_size(curves) bytes of device scratch, 256-byte
+ * aligned (256 bytes when n_nodes <= 256). */
 S2D_API size_t near_derivs_workspace_size(const s2d_curves *curves);
 S2D_API int near_derivs_eval(const s2d_curves *curves, double *dtab, void *ws, size_t ws_bytes, void *stream);
 

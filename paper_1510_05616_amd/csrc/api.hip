@@ -746,7 +746,7 @@ static_assert(S2D_NEAR_NFEAT == s2d::kNearFeat && S2D_NEAR_NFRAME == s2d::kNearF
               "the public near-field sizes match the kernels'");
 
 struct NearLayout {
-    size_t up, dtab, dscr, X, frame, flag, list, count, total;
+    size_t up, dtab, dscr, X, frame, flag, list, count, llist, lcount, total;
 };
 
 NearLayout near_layout(int method, const s2d_curves *c, const s2d_targets *t, int P) {
@@ -771,8 +771,13 @@ NearLayout near_layout(int method, const s2d_curves *c, const s2d_targets *t, in
         off = align256(off + (size_t)t->n * sizeof(int32_t));
         L.count = off;
         off = align256(off + ((size_t)(t->n + 255) / 256 + 1) * sizeof(int32_t));
+        // the learned targets' list and its compaction counts
+        L.llist = off;
+        off = align256(off + (size_t)t->n * sizeof(int32_t));
+        L.lcount = off;
+        off = align256(off + ((size_t)(t->n + 255) / 256 + 1) * sizeof(int32_t));
     } else {
-        L.frame = L.flag = L.list = L.count = off;
+        L.frame = L.flag = L.list = L.count = L.llist = L.lcount = off;
     }
     L.total = std::max<size_t>(off, 256);
     return L;
@@ -842,21 +847,22 @@ S2D_API int near_correct_eval(int method, const s2d_curves *ves, const s2d_targe
     double *dtab = (double *)(w + L.dtab);
     float *X = (float *)(w + L.X);
     double *frame = (double *)(w + L.frame);
-    e = s2d::near_launch_derivs(ves, dtab, (double *)(w + L.dscr), st);
+    e = s2d::near_launch_derivs(ves, dtab, w + L.dscr, st);
     if (e != hipSuccess) return hip_fail(e, "near derivative launch");
     e = s2d::near_launch_features(ves, trg, trg_curve, dtab, X, frame, st);
     if (e != hipSuccess) return hip_fail(e, "near features launch");
     const bool autom = method == S2D_NEAR_AUTO;
-    // AUTO needs the per-target decisions: the caller's array or the workspace
-    int32_t *flag = used_fallback ? used_fallback : (autom ? (int32_t *)(w + L.flag) : nullptr);
+    // the per-target decisions: the caller's array or the workspace
+    int32_t *flag = used_fallback ? used_fallback : (int32_t *)(w + L.flag);
     e = s2d::near_launch_infer(S2D_OP_SLP, trg->n, X, frame, (const s2d::NearBlob *)mlp, mu, threshold, trg_curve,
-                               ves->n_curves, curve_tol, autom ? 1 : 0, du, dv, flag, st);
+                               ves->n_curves, curve_tol, autom ? 1 : 0, du, dv, flag, (int32_t *)(w + L.lcount),
+                               (int32_t *)(w + L.llist), st);
     if (e != hipSuccess) return hip_fail(e, "near MLP launch");
     if (autom) {
         // the fallback targets, compacted in order, so that the quadrature's
         // cost follows their number rather than the waves that hold one
         int32_t *list = (int32_t *)(w + L.list), *cnt = (int32_t *)(w + L.count);
-        e = s2d::near_launch_compact(trg->n, flag, cnt, list, st);
+        e = s2d::near_launch_compact(trg->n, flag, 1, cnt, list, st);
         if (e != hipSuccess) return hip_fail(e, "near fallback compaction launch");
         e = s2d::near_launch_quad(ves, trg, trg_curve, list, cnt + (trg->n + 255) / 256, upsample, up, mu, du, dv,
                                   st);
@@ -905,13 +911,13 @@ S2D_API int near_derivs_eval(const s2d_curves *curves, double *dtab, void *ws, s
     if (rc != S2D_OK) return rc;
     if (curves->n_nodes > 0 && !dtab) return fail(S2D_EINVAL, "dtab must not be NULL");
     const size_t need = s2d::near_derivs_scratch(curves);
-    if (need > 0 && (!ws || ws_bytes < need))
+    if (!ws || ws_bytes < need)
         return fail(S2D_EWORKSPACE, "derivative workspace too small: need " + std::to_string(need) + " bytes");
-    if (need > 0 && ((uintptr_t)ws & 255) != 0) return fail(S2D_EWORKSPACE, "workspace must be 256-byte aligned");
+    if (((uintptr_t)ws & 255) != 0) return fail(S2D_EWORKSPACE, "workspace must be 256-byte aligned");
     int dev = 0;
     rc = current_device(&dev);
     if (rc != S2D_OK) return rc;
-    const hipError_t e = s2d::near_launch_derivs(curves, dtab, (double *)ws, (hipStream_t)stream);
+    const hipError_t e = s2d::near_launch_derivs(curves, dtab, ws, (hipStream_t)stream);
     return e == hipSuccess ? S2D_OK : hip_fail(e, "near derivative launch");
 }
 
@@ -1109,7 +1115,7 @@ s2d::WallArgs wall_args(const s2d_curves *w, double d, int P, void *scratch, dou
 // the fallback list (MLP, AUTO), pair sums
 struct NearWallLayout {
     WallLayout up;
-    size_t t4, dtab, dscr, X, frame, flag, list, count, cxy, pair, pair_bytes, total;
+    size_t t4, dtab, dscr, X, frame, flag, list, count, llist, lcount, cxy, pair, pair_bytes, total;
 };
 
 NearWallLayout near_wall_layout(int method, const s2d_curves *w, const s2d_targets *t, int P,
@@ -1138,6 +1144,10 @@ NearWallLayout near_wall_layout(int method, const s2d_curves *w, const s2d_targe
         o += align256(n * sizeof(int32_t));
         L.count = o;
         o += 256;
+        L.llist = o;
+        o += align256(n * sizeof(int32_t));
+        L.lcount = o;
+        o += align256((n + 255) / 256 * sizeof(int32_t) + sizeof(int32_t));
         L.cxy = o;
         o += align256(2 * n * sizeof(double));
     }
@@ -1297,15 +1307,16 @@ S2D_API int near_wall_correct_eval(int method, const s2d_curves *walls, const s2
     double *dtab = (double *)(base + L.dtab);
     float *X = (float *)(base + L.X);
     double *frame = (double *)(base + L.frame);
-    e = s2d::near_launch_derivs(walls, dtab, (double *)(base + L.dscr), st);
+    e = s2d::near_launch_derivs(walls, dtab, base + L.dscr, st);
     if (e != hipSuccess) return hip_fail(e, "near-wall derivative launch");
     e = s2d::near_launch_wall_features(walls, trg, trg_curve, d, dtab, X, frame, st);
     if (e != hipSuccess) return hip_fail(e, "near-wall features launch");
     const bool autom = method == S2D_NEAR_AUTO;
-    int32_t *flag = used_fallback ? used_fallback : (autom ? (int32_t *)(base + L.flag) : nullptr);
+    int32_t *flag = used_fallback ? used_fallback : (int32_t *)(base + L.flag);
     double *tu = t4, *tv = t4 + n;
     e = s2d::near_launch_infer(S2D_OP_DLP, n, X, frame, (const s2d::NearBlob *)mlp, 1.0, threshold, trg_curve,
-                               walls->n_curves, curve_tol, autom ? 1 : 0, tu, tv, flag, st);
+                               walls->n_curves, curve_tol, autom ? 1 : 0, tu, tv, flag,
+                               (int32_t *)(base + L.lcount), (int32_t *)(base + L.llist), st);
     if (e != hipSuccess) return hip_fail(e, "near-wall MLP launch");
     if (autom) {
         // the fallback targets: the refined quadrature at a compacted list

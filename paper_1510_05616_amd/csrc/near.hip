@@ -298,20 +298,21 @@ __global__ __launch_bounds__(64 * kQuadParts) void near_quad(int64_t n_trg, cons
     }
 }
 
-// Order-keeping compaction of the targets with flag == 1 (AUTO's fallback):
-// per-workgroup counts, one exclusive scan, then each workgroup writes its
-// targets' indices at its offset in target order.
+// Order-keeping compaction of the targets with flag == value (AUTO's
+// learned and fallback targets): per-workgroup counts, one exclusive scan,
+// then each workgroup writes its targets' indices at its offset in target
+// order.
 constexpr int kCompactBlock = 256;
 
-__device__ __forceinline__ uint64_t flag_ballot(int64_t n, const int32_t *__restrict__ flag, int64_t i) {
-    return __ballot(i < n && flag[i] == 1);
+__device__ __forceinline__ uint64_t flag_ballot(int64_t n, const int32_t *__restrict__ flag, int64_t i, int value) {
+    return __ballot(i < n && flag[i] == value);
 }
 
 __global__ __launch_bounds__(kCompactBlock) void near_compact_count(int64_t n, const int32_t *__restrict__ flag,
-                                                                    int32_t *__restrict__ cnt) {
+                                                                    int value, int32_t *__restrict__ cnt) {
     __shared__ int wsum[kCompactBlock / kWave];
     const int64_t i = (int64_t)blockIdx.x * kCompactBlock + threadIdx.x;
-    const uint64_t b = flag_ballot(n, flag, i);
+    const uint64_t b = flag_ballot(n, flag, i, value);
     if ((threadIdx.x & (kWave - 1)) == 0) wsum[threadIdx.x / kWave] = __popcll(b);
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -350,11 +351,11 @@ __global__ __launch_bounds__(1024) void near_compact_scan(int64_t nb, int32_t *_
 }
 
 __global__ __launch_bounds__(kCompactBlock) void near_compact_scatter(int64_t n, const int32_t *__restrict__ flag,
-                                                                      const int32_t *__restrict__ cnt,
+                                                                      int value, const int32_t *__restrict__ cnt,
                                                                       int32_t *__restrict__ list) {
     __shared__ int wsum[kCompactBlock / kWave];
     const int64_t i = (int64_t)blockIdx.x * kCompactBlock + threadIdx.x;
-    const uint64_t b = flag_ballot(n, flag, i);
+    const uint64_t b = flag_ballot(n, flag, i, value);
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     if (lane == 0) wsum[w] = __popcll(b);
     __syncthreads();
@@ -378,38 +379,47 @@ __global__ __launch_bounds__(kCompactBlock) void near_compact_scatter(int64_t n,
 // equispaced nodes (closed form, flat_* below), dC_p the network's output.
 
 // Node derivatives of the density, one workgroup per curve (even N, 4 <= N <=
-// kUpMaxN; larger even curves go to the kernels below): the interpolant's coefficients a_m, b_m (m = 0..N/2, the Nyquist
-// mode's weight split evenly), then at each node sum_m (m h)^p times the p-th
-// derivative of a_m cos(m t) + b_m sin(m t) at t_k (h = 2 pi / N; the
-// Nyquist term keeps its even derivatives only: the odd ones vanish at the
-// nodes).  Angles come from a table of cos, sin(2 pi j / N) indexed by
-// (m k) mod N.  Invalid curves get NaN.
+// kUpMaxN; larger even curves go to the kernels below): the interpolant's
+// coefficients a_m, b_m (m = 0..N/2, the Nyquist mode's weight split evenly),
+// then at each node sum_m (m h)^p times the p-th derivative of a_m cos(m t) +
+// b_m sin(m t) at t_k (h = 2 pi / N; the Nyquist term keeps its even
+// derivatives only: the odd ones vanish at the nodes).  A thread takes one
+// coefficient (mode, component) in the first stage and one (node, component)
+// with all five p in the second; each steps cos and sin of the multiple
+// angles by rotation through its base angle (at most 256 steps, rounding
+// growing at most linearly), so no lane gathers from a table.  Invalid
+// curves get NaN.
 __global__ __launch_bounds__(256) void near_derivs(const int32_t *__restrict__ off, int32_t n_curves, int64_t n_src,
                                                    const double *__restrict__ fx, const double *__restrict__ fy,
-                                                   double *__restrict__ dtab) {
-    __shared__ double cs[kUpMaxN], sn[kUpMaxN];
+                                                   double *__restrict__ dtab, int32_t *__restrict__ big) {
     __shared__ double co[2][kUpMaxN / 2 + 1][2];
     const int c = blockIdx.x;
     if (c >= n_curves) return;
     const int lo = off[c], N = off[c + 1] - lo;
     if (lo < 0 || N <= 0 || (int64_t)lo + N > n_src) return;          // no rows of its own to fill
-    if (N > kUpMaxN && !(N & 1)) return;                              // the large-curve kernels' work
+    if (N > kUpMaxN && !(N & 1)) {                                     // the large-curve kernels' work
+        if (threadIdx.x == 0) big[0] = 1;
+        return;
+    }
     if (N < 4 || (N & 1)) {
         for (int q = threadIdx.x; q < N * 2 * kNearDeriv; q += blockDim.x)
             dtab[(int64_t)lo * 2 * kNearDeriv + q] = __builtin_nan("");
         return;
     }
     const int H = N / 2;
-    for (int j = threadIdx.x; j < N; j += blockDim.x) sincospi(2.0 * (double)j / (double)N, &sn[j], &cs[j]);
-    __syncthreads();
     for (int q = threadIdx.x; q < 2 * (H + 1); q += blockDim.x) {
         const int comp = q / (H + 1), m = q % (H + 1);
         const double *f = (comp ? fy : fx) + lo;
+        double cb, sb;                                                 // cos, sin(2 pi m / N)
+        sincospi(2.0 * (double)m / (double)N, &sb, &cb);
+        double cm = 1.0, sm = 0.0;                                     // cos, sin(2 pi m k / N)
         double a = 0.0, b = 0.0;
         for (int k = 0; k < N; ++k) {
-            const int j = (int)(((int64_t)m * k) % N);
-            a = __builtin_fma(f[k], cs[j], a);
-            b = __builtin_fma(f[k], sn[j], b);
+            a = __builtin_fma(f[k], cm, a);
+            b = __builtin_fma(f[k], sm, b);
+            const double cn = __builtin_fma(cm, cb, -sm * sb);
+            sm = __builtin_fma(sm, cb, cm * sb);
+            cm = cn;
         }
         const double sc = (m == 0 || m == H) ? 1.0 / N : 2.0 / N;
         co[comp][m][0] = a * sc;
@@ -417,25 +427,35 @@ __global__ __launch_bounds__(256) void near_derivs(const int32_t *__restrict__ o
     }
     __syncthreads();
     const double h = 2.0 * M_PI / (double)N;
-    for (int q = threadIdx.x; q < N * 2 * kNearDeriv; q += blockDim.x) {
-        const int k = q / (2 * kNearDeriv), r = q % (2 * kNearDeriv), p = r / 2, comp = r % 2;
-        double v = p == 0 ? co[comp][0][0] : 0.0;
+    for (int q = threadIdx.x; q < 2 * N; q += blockDim.x) {
+        const int k = q >> 1, comp = q & 1;
+        double cb, sb;                                                 // cos, sin(2 pi k / N)
+        sincospi(2.0 * (double)k / (double)N, &sb, &cb);
+        double cm = 1.0, sm = 0.0;                                     // cos, sin(2 pi m k / N)
+        double acc[kNearDeriv];
+        acc[0] = co[comp][0][0];
+#pragma unroll
+        for (int p = 1; p < kNearDeriv; ++p) acc[p] = 0.0;
         for (int m = 1; m <= H; ++m) {
-            if (m == H && (p & 1)) break;
-            const int j = (int)(((int64_t)m * k) % N);
-            // p-th derivatives of cos and sin: cos(x + p pi / 2), sin(x + p pi / 2)
-            double dc, ds;
-            switch (p & 3) {
-            case 0: dc = cs[j]; ds = sn[j]; break;
-            case 1: dc = -sn[j]; ds = cs[j]; break;
-            case 2: dc = -cs[j]; ds = -sn[j]; break;
-            default: dc = sn[j]; ds = -cs[j]; break;
+            const double cn = __builtin_fma(cm, cb, -sm * sb);
+            sm = __builtin_fma(sm, cb, cm * sb);
+            cm = cn;
+            const double a = co[comp][m][0], b = co[comp][m][1];
+            // (m h)^p times the p-th derivative of a cos + b sin: the
+            // derivatives cycle through g0, g1, -g0, -g1
+            const double g0 = __builtin_fma(a, cm, b * sm), g1 = __builtin_fma(-a, sm, b * cm);
+            const double mh = (double)m * h, mh2 = mh * mh;
+            acc[0] += g0;
+            if (m < H) {
+                acc[1] = __builtin_fma(mh, g1, acc[1]);
+                acc[3] = __builtin_fma(-mh * mh2, g1, acc[3]);
             }
-            double mp = 1.0;
-            for (int e = 0; e < p; ++e) mp *= (double)m * h;
-            v = __builtin_fma(mp, __builtin_fma(co[comp][m][0], dc, co[comp][m][1] * ds), v);
+            acc[2] = __builtin_fma(-mh2, g0, acc[2]);
+            acc[4] = __builtin_fma(mh2 * mh2, g0, acc[4]);
         }
-        dtab[((int64_t)lo + k) * 2 * kNearDeriv + r] = v;
+        double *row = dtab + ((int64_t)lo + k) * 2 * kNearDeriv + comp;
+#pragma unroll
+        for (int p = 0; p < kNearDeriv; ++p) row[2 * p] = acc[p];
     }
 }
 
@@ -444,6 +464,8 @@ __global__ __launch_bounds__(256) void near_derivs(const int32_t *__restrict__ o
 // N) (row lo + j), then one wave per coefficient m (row lo + m, m <= N/2 <
 // N) summing over the nodes in lane-strided order, then one wave per node
 // summing over the modes.  Wave partial sums are added by a fixed butterfly.
+// The kernels stride over the rows with a fixed grid and return at once
+// unless near_derivs flagged a large curve (big[0] != 0).
 __device__ __forceinline__ int curve_of(const int32_t *__restrict__ off, int n_curves, int64_t q) {
     int lo = 0, hi = n_curves - 1;                       // last c with off[c] <= q
     while (lo < hi) {
@@ -470,90 +492,109 @@ __device__ __forceinline__ bool big_curve(const int32_t *__restrict__ off, int32
     return lo >= 0 && (int64_t)lo + N <= n_src && q >= lo && q < (int64_t)lo + N && N > kUpMaxN && !(N & 1);
 }
 
+constexpr int kBigBlocks = 1024;
+constexpr int kInferCUs = 256;
+
 __global__ __launch_bounds__(256) void near_derivs_table(const int32_t *__restrict__ off, int32_t n_curves,
-                                                         int64_t n_src, double *__restrict__ tab) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int lo, N;
-    if (!big_curve(off, n_curves, n_src, q, lo, N)) return;
-    double sv, cv;
-    sincospi(2.0 * (double)(q - lo) / (double)N, &sv, &cv);
-    tab[2 * q] = cv;
-    tab[2 * q + 1] = sv;
+                                                         int64_t n_src, const int32_t *__restrict__ big,
+                                                         double *__restrict__ tab) {
+    if (big[0] == 0) return;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n_src; q += (int64_t)gridDim.x * blockDim.x) {
+        int lo, N;
+        if (!big_curve(off, n_curves, n_src, q, lo, N)) continue;
+        double sv, cv;
+        sincospi(2.0 * (double)(q - lo) / (double)N, &sv, &cv);
+        tab[2 * q] = cv;
+        tab[2 * q + 1] = sv;
+    }
 }
 
 // coefficients {a_x, b_x, a_y, b_y} of mode m at coef[4 (lo + m)]
 __global__ __launch_bounds__(256) void near_derivs_coef(const int32_t *__restrict__ off, int32_t n_curves,
-                                                        int64_t n_src, const double *__restrict__ fx,
-                                                        const double *__restrict__ fy,
+                                                        int64_t n_src, const int32_t *__restrict__ big,
+                                                        const double *__restrict__ fx, const double *__restrict__ fy,
                                                         const double *__restrict__ tab, double *__restrict__ coef) {
-    const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;      // wave-uniform
+    if (big[0] == 0) return;
     const int lane = threadIdx.x & (kWave - 1);
-    int lo, N;
-    if (!big_curve(off, n_curves, n_src, q, lo, N)) return;
-    const int H = N / 2, m = (int)(q - lo);
-    if (m > H) return;
-    double ax = 0.0, bx = 0.0, ay = 0.0, by = 0.0;
-    for (int k = lane; k < N; k += kWave) {
-        const int64_t j = lo + ((int64_t)m * k) % N;
-        const double c = tab[2 * j], sn = tab[2 * j + 1];
-        ax = __builtin_fma(fx[lo + k], c, ax);
-        bx = __builtin_fma(fx[lo + k], sn, bx);
-        ay = __builtin_fma(fy[lo + k], c, ay);
-        by = __builtin_fma(fy[lo + k], sn, by);
-    }
-    ax = wave_sum_d(ax);
-    bx = wave_sum_d(bx);
-    ay = wave_sum_d(ay);
-    by = wave_sum_d(by);
-    if (lane == 0) {
-        const bool edge = m == 0 || m == H;
-        const double sc = edge ? 1.0 / N : 2.0 / N;
-        coef[4 * q] = ax * sc;
-        coef[4 * q + 1] = edge ? 0.0 : bx * sc;
-        coef[4 * q + 2] = ay * sc;
-        coef[4 * q + 3] = edge ? 0.0 : by * sc;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    for (int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; q < n_src; q += waves) {
+        int lo, N;
+        if (!big_curve(off, n_curves, n_src, q, lo, N)) continue;       // wave-uniform
+        const int H = N / 2, m = (int)(q - lo);
+        if (m > H) continue;
+        double ax = 0.0, bx = 0.0, ay = 0.0, by = 0.0;
+        int j = (int)(((int64_t)m * lane) % N);                         // (m k) mod N, stepped by 64 m
+        const int step = (int)(((int64_t)m * kWave) % N);
+        for (int k = lane; k < N; k += kWave) {
+            const double c = tab[2 * ((int64_t)lo + j)], sn = tab[2 * ((int64_t)lo + j) + 1];
+            ax = __builtin_fma(fx[lo + k], c, ax);
+            bx = __builtin_fma(fx[lo + k], sn, bx);
+            ay = __builtin_fma(fy[lo + k], c, ay);
+            by = __builtin_fma(fy[lo + k], sn, by);
+            j += step;
+            j = j >= N ? j - N : j;
+        }
+        ax = wave_sum_d(ax);
+        bx = wave_sum_d(bx);
+        ay = wave_sum_d(ay);
+        by = wave_sum_d(by);
+        if (lane == 0) {
+            const bool edge = m == 0 || m == H;
+            const double sc = edge ? 1.0 / N : 2.0 / N;
+            coef[4 * q] = ax * sc;
+            coef[4 * q + 1] = edge ? 0.0 : bx * sc;
+            coef[4 * q + 2] = ay * sc;
+            coef[4 * q + 3] = edge ? 0.0 : by * sc;
+        }
     }
 }
 
 __global__ __launch_bounds__(256) void near_derivs_nodes(const int32_t *__restrict__ off, int32_t n_curves,
-                                                         int64_t n_src, const double *__restrict__ tab,
+                                                         int64_t n_src, const int32_t *__restrict__ big,
+                                                         const double *__restrict__ tab,
                                                          const double *__restrict__ coef, double *__restrict__ dtab) {
-    const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;      // wave-uniform
+    if (big[0] == 0) return;
     const int lane = threadIdx.x & (kWave - 1);
-    int lo, N;
-    if (!big_curve(off, n_curves, n_src, q, lo, N)) return;
-    const int H = N / 2, k = (int)(q - lo);
-    const double h = 2.0 * M_PI / (double)N;
-    double acc[2 * kNearDeriv];
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    for (int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; q < n_src; q += waves) {
+        int lo, N;
+        if (!big_curve(off, n_curves, n_src, q, lo, N)) continue;       // wave-uniform
+        const int H = N / 2, k = (int)(q - lo);
+        const double h = 2.0 * M_PI / (double)N;
+        double acc[2 * kNearDeriv];
 #pragma unroll
-    for (int r = 0; r < 2 * kNearDeriv; ++r) acc[r] = 0.0;
-    for (int m = 1 + lane; m <= H; m += kWave) {
-        const int64_t j = lo + ((int64_t)m * k) % N;
-        const double c = tab[2 * j], sn = tab[2 * j + 1];
-        const double *co = coef + 4 * ((int64_t)lo + m);
-        // (m h)^p times the p-th derivative of a cos + b sin: the derivatives
-        // cycle through (c, s), (-s, c), (-c, -s), (s, -c)
-        const double gx0 = __builtin_fma(co[0], c, co[1] * sn), gx1 = __builtin_fma(-co[0], sn, co[1] * c);
-        const double gy0 = __builtin_fma(co[2], c, co[3] * sn), gy1 = __builtin_fma(-co[2], sn, co[3] * c);
-        const double mh = (double)m * h;
-        double mp = 1.0;
+        for (int r = 0; r < 2 * kNearDeriv; ++r) acc[r] = 0.0;
+        int j = (int)(((int64_t)(1 + lane) * k) % N);                   // (m k) mod N, stepped by 64 k
+        const int step = (int)(((int64_t)kWave * k) % N);
+        for (int m = 1 + lane; m <= H; m += kWave) {
+            const double c = tab[2 * ((int64_t)lo + j)], sn = tab[2 * ((int64_t)lo + j) + 1];
+            j += step;
+            j = j >= N ? j - N : j;
+            const double *co = coef + 4 * ((int64_t)lo + m);
+            // (m h)^p times the p-th derivative of a cos + b sin: the derivatives
+            // cycle through g0, g1, -g0, -g1
+            const double gx0 = __builtin_fma(co[0], c, co[1] * sn), gx1 = __builtin_fma(-co[0], sn, co[1] * c);
+            const double gy0 = __builtin_fma(co[2], c, co[3] * sn), gy1 = __builtin_fma(-co[2], sn, co[3] * c);
+            const double mh = (double)m * h;
+            double mp = 1.0;
 #pragma unroll
-        for (int p = 0; p < kNearDeriv; ++p) {
-            if (!(m == H && (p & 1))) {
-                const double sg = (p & 2) ? -1.0 : 1.0;
-                acc[2 * p] = __builtin_fma(mp, sg * ((p & 1) ? gx1 : gx0), acc[2 * p]);
-                acc[2 * p + 1] = __builtin_fma(mp, sg * ((p & 1) ? gy1 : gy0), acc[2 * p + 1]);
+            for (int p = 0; p < kNearDeriv; ++p) {
+                if (!(m == H && (p & 1))) {
+                    const double sg = (p & 2) ? -1.0 : 1.0;
+                    acc[2 * p] = __builtin_fma(mp, sg * ((p & 1) ? gx1 : gx0), acc[2 * p]);
+                    acc[2 * p + 1] = __builtin_fma(mp, sg * ((p & 1) ? gy1 : gy0), acc[2 * p + 1]);
+                }
+                mp *= mh;
             }
-            mp *= mh;
         }
-    }
 #pragma unroll
-    for (int r = 0; r < 2 * kNearDeriv; ++r) acc[r] = wave_sum_d(acc[r]);
-    if (lane == 0) {
-        acc[0] += coef[4 * (int64_t)lo];
-        acc[1] += coef[4 * (int64_t)lo + 2];
+        for (int r = 0; r < 2 * kNearDeriv; ++r) acc[r] = wave_sum_d(acc[r]);
+        if (lane == 0) {
+            acc[0] += coef[4 * (int64_t)lo];
+            acc[1] += coef[4 * (int64_t)lo + 2];
 #pragma unroll
-        for (int r = 0; r < 2 * kNearDeriv; ++r) dtab[q * 2 * kNearDeriv + r] = acc[r];
+            for (int r = 0; r < 2 * kNearDeriv; ++r) dtab[q * 2 * kNearDeriv + r] = acc[r];
+        }
     }
 }
 
@@ -946,13 +987,36 @@ struct InvPowTab {
 __constant__ InvPowTab kInvPow = InvPowTab();
 constexpr int kPolyCoarse = 64, kPolyFine = 16;
 
-// sum_p E_p(rule of spacing D) d_p for the single (OP = S2D_OP_SLP) or double
-// layer; out = (t, n) components
+// C(p, j) (-1)^j j! and 2 / p! (the coefficients of S1_p and of E_p)
+struct FlatCoef {
+    double bj[kNearDeriv][kNearDeriv];
+    double f[kNearDeriv];
+    constexpr FlatCoef() : bj(), f() {
+        double fact = 1.0;
+        for (int p = 0; p < kNearDeriv; ++p) {
+            if (p > 0) fact *= (double)p;
+            f[p] = 2.0 / fact;
+            double binom = 1.0, jf = 1.0;
+            for (int j = 0; j <= p; ++j) {
+                if (j > 0) {
+                    binom = binom * (double)(p - j + 1) / (double)j;
+                    jf *= (double)j;
+                }
+                bj[p][j] = binom * ((j & 1) ? -jf : jf);
+            }
+        }
+    }
+};
+__constant__ FlatCoef kFlat = FlatCoef();
+
+// sum_p E_p(rule of spacing D = 1 / inv_d) d_p for the single (OP =
+// S2D_OP_SLP) or double layer; out = (t, n) components
 template <int OP>
-__device__ void flat_rule(double s, double b, double D, int L, const double *__restrict__ dfr, double (&out)[2]) {
-    const double c = 2.0 * M_PI / D;
+__device__ void flat_rule(double s, double b, double inv_d, int L, const double *__restrict__ dfr,
+                          double (&out)[2]) {
+    const double c = 2.0 * M_PI * inv_d;
     double sq, cq;
-    sincospi(-2.0 * s / D, &sq, &cq);
+    sincospi(-2.0 * s * inv_d, &sq, &cq);
     const double aq = exp(-c * b);
     const Cx Q = {aq * cq, aq * sq};
     const Cx om = {1.0 - Q.re, -Q.im};                       // 1 - Q
@@ -961,7 +1025,6 @@ __device__ void flat_rule(double s, double b, double D, int L, const double *__r
     zp[0] = {1.0, 0.0};
     for (int k = 1; k < kNearDeriv; ++k) zp[k] = cx_mul(zp[k - 1], {-b, -s});
     out[0] = out[1] = 0.0;
-    double fact = 1.0;                                       // p!
     if constexpr (OP == S2D_OP_SLP) {
         Cx Li[kNearDeriv + 1];
         Li[0] = L0;
@@ -974,23 +1037,19 @@ __device__ void flat_rule(double s, double b, double D, int L, const double *__r
             for (int k = 0; k < kNearDeriv - 1; ++k) acc[k] = cx_add(acc[k], cx_scale(ql, kInvPow.v[l][k]));
         }
         for (int k = 2; k <= kNearDeriv; ++k) Li[k] = acc[k - 2];
-        const double ic = 1.0 / c;
+        const double ic = (0.5 / M_PI) / inv_d;              // 1 / c
+#pragma unroll
         for (int p = 0; p < kNearDeriv; ++p) {
-            if (p > 0) fact *= (double)p;
             Cx S1 = {0.0, 0.0};
-            double binom = 1.0, jf = 1.0, icj = ic;              // C(p, j), j!, c^-(j+1)
+            double icj = ic;                                 // c^-(j+1)
+#pragma unroll
             for (int j = 0; j <= p; ++j) {
-                if (j > 0) {
-                    binom = binom * (double)(p - j + 1) / (double)j;
-                    jf *= (double)j;
-                    icj *= ic;
-                }
-                const double coef = binom * ((j & 1) ? -jf : jf) * icj;
-                S1 = cx_add(S1, cx_scale(cx_mul(zp[p - j], Li[j + 1]), coef));
+                if (j > 0) icj *= ic;
+                S1 = cx_add(S1, cx_scale(cx_mul(zp[p - j], Li[j + 1]), kFlat.bj[p][j] * icj));
             }
             S1 = cx_scale(S1, M_PI);
             const Cx S0 = cx_mul(zp[p], L0);
-            const double f = 2.0 / fact;
+            const double f = kFlat.f[p];
             const double ett = f * cx_ipow(p, {S1.re - M_PI * b * S0.re, S1.im - M_PI * b * S0.im}).re;
             const double enn = f * cx_ipow(p, {S1.re + M_PI * b * S0.re, S1.im + M_PI * b * S0.im}).re;
             const double etn = f * cx_ipow(p + 1, cx_scale(S0, M_PI * b)).re;
@@ -1000,13 +1059,13 @@ __device__ void flat_rule(double s, double b, double D, int L, const double *__r
         }
     } else {
         const Cx Lm1 = cx_div(L0, om);                       // Q / (1 - Q)^2
+#pragma unroll
         for (int p = 0; p < kNearDeriv; ++p) {
-            if (p > 0) fact *= (double)p;
             // sum_l d^p/dw^p [e^{-wz} (alpha + beta w)] = alpha (-z)^p L0 + beta ((-z)^p c Lm1 + p (-z)^(p-1) L0)
             const Cx base = cx_mul(zp[p], L0);
             Cx lin = cx_scale(cx_mul(zp[p], Lm1), c);
             if (p > 0) lin = cx_add(lin, cx_scale(cx_mul(zp[p - 1], L0), (double)p));
-            const double f = 2.0 / fact;
+            const double f = kFlat.f[p];
             const double h = 0.5 * M_PI;
             const double ett = f * cx_ipow(p, {h * (base.re - b * lin.re), h * (base.im - b * lin.im)}).re;
             const double enn = f * cx_ipow(p, {h * (base.re + b * lin.re), h * (base.im + b * lin.im)}).re;
@@ -1047,7 +1106,7 @@ __device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
     return __builtin_bit_cast(uint32_t, v);
 }
 
-// MLP inference on the matrix cores: a wave takes one group of 32 targets and
+// MLP inference on the matrix cores: a pass of a wave takes 32 targets and
 // evaluates each layer as out^T = W in^T with v_mfma_f32_32x32x8_bf16: A = 32
 // output features x 8 inputs of W (read from the blob's [out][in/2] pairs),
 // B = 8 inputs x the 32 targets, C = 32 features x 32 targets in FP32,
@@ -1059,9 +1118,10 @@ __device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
 typedef short bf16x4v_t __attribute__((ext_vector_type(4)));
 typedef float f32x16v_t __attribute__((ext_vector_type(16)));
 
-// 4 bf16 of row `row` of a [out][in2] pair array, inputs k0..k0+3 (k0 % 4 == 0)
-__device__ __forceinline__ bf16x4v_t mfma_wrow(const uint32_t *W, int in2, int row, int k0) {
-    const uint32_t *q = W + row * in2 + k0 / 2;
+// 4 bf16 of row `row` of a pair array with rows of `stride` words, inputs
+// k0..k0+3 (k0 % 4 == 0)
+__device__ __forceinline__ bf16x4v_t mfma_wrow(const uint32_t *W, int stride, int row, int k0) {
+    const uint32_t *q = W + row * stride + k0 / 2;
     const uint32_t lo = q[0], hi = q[1];
     return __builtin_bit_cast(bf16x4v_t, ((uint64_t)hi << 32) | lo);
 }
@@ -1069,7 +1129,8 @@ __device__ __forceinline__ bf16x4v_t mfma_pack4(float a, float b, float c, float
     return __builtin_bit_cast(bf16x4v_t, ((uint64_t)pack_bf16(c, d) << 32) | pack_bf16(a, b));
 }
 
-// TILES 32-feature output tiles of a layer with KSTEPS K-steps (IN2 input pairs per row)
+// TILES 32-feature output tiles of a layer with KSTEPS K-steps (weight rows
+// of IN2 words)
 template <int TILES, int KSTEPS, int IN2>
 __device__ __forceinline__ void mfma_layer(const uint32_t *W, const float *b, const bf16x4v_t (&in)[KSTEPS],
                                            int c, int h, f32x16v_t (&acc)[TILES]) {
@@ -1117,32 +1178,54 @@ __device__ __forceinline__ int near_cell(float sf, float khf) {
 // correction is within the target's tolerance) or the quadrature; inside, no
 // correction, the network or the quadrature by the bin's calibrated bounds
 // (scaled by scale * F into velocity units) against the tolerance (the
-// target's curve's entry of curve_tol, else threshold).  Then
-// the network (only if some target of the wave uses it), the straight-line
-// coefficients (half-wave h = 0 the plain rule, h = 1 the refined one, each
-// contracted with the density derivatives and exchanged), and
+// target's curve's entry of curve_tol, else threshold).  A wave takes 64
+// targets, one per lane: the straight-line coefficients of both rules in
+// FP64, contracted with the density derivatives (only for targets that take
+// the learned route), then the network in two MFMA passes of 32 targets (a
+// pass only if one of its targets needs it), and
 //   Delta = scale [t n_f] (sum_p Cflat_p d_p + exp(-2 pi b) sum_p dC_p d_p)
 // in FP64 (the double layer's flat part times sg).
+// The network's weights and biases staged in LDS once per workgroup.  Rows
+// are padded by two words (strides 10 and 34) so that the 32 rows a wave's
+// lanes read for one MFMA fall in distinct LDS banks.
+constexpr int kS1 = 10, kS2 = 34;
+struct NetLds {
+    uint32_t W1[64 * kS1], W2[64 * kS2], W3[64 * kS2], W4[32 * kS2];
+    float b1[64], b2[64], b3[64], b4[32];
+};
+
+__device__ void net_stage(const NearBlob *__restrict__ nb, NetLds &L) {
+    for (int q = threadIdx.x; q < 64 * 32; q += blockDim.x) {
+        const int r = q / 32, k = q % 32;
+        if (k < 8) L.W1[r * kS1 + k] = nb->W1[r * 8 + k];
+        L.W2[r * kS2 + k] = nb->W2[q];
+        L.W3[r * kS2 + k] = nb->W3[q];
+        if (r < 32) L.W4[r * kS2 + k] = nb->W4[q];
+    }
+    for (int q = threadIdx.x; q < 64; q += blockDim.x) {
+        L.b1[q] = nb->b1[q];
+        L.b2[q] = nb->b2[q];
+        L.b3[q] = nb->b3[q];
+        if (q < 32) L.b4[q] = nb->b4[q];
+    }
+}
+
+// AUTO's decision per target (flag[i] = dec: 0 learned, 1 quadrature, 2 no
+// correction; all 0 when use_bound == 0); du = dv = 0 for dec 2.
 template <int OP>
-__global__ __launch_bounds__(256) void near_mlp_infer_mfma(int64_t n_trg, const float *__restrict__ X,
-                                                           const double *__restrict__ frame,
-                                                           const NearBlob *__restrict__ nb, double mu,
-                                                           double threshold, const int32_t *__restrict__ tc,
-                                                           int32_t n_curves, const double *__restrict__ curve_tol,
-                                                           int use_bound, double *__restrict__ du,
-                                                           double *__restrict__ dv, int32_t *__restrict__ flag) {
-    static_assert(kNearFeat <= 16, "two K-steps of the first layer");
-    const int lane = threadIdx.x & (kWave - 1), h = lane >> 5, c = lane & 31;
-    const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;   // this wave's group
-    if (g * 32 >= n_trg) return;                                                   // wave-uniform
-    const int64_t i = g * 32 + c;
-    const bool valid = i < n_trg;
-    const float *xi = X + (valid ? i : 0) * kNearFeat;
-    const double *fr = frame + kNearFrame * (valid ? i : 0);
-    const double b = fr[1], sg = fr[8], F = fr[7];
-    const double scale = OP == S2D_OP_SLP ? fr[6] / (4.0 * M_PI * mu) : 1.0 / M_PI;
-    int dec = 0;                                                 // 0 network, 1 quadrature, 2 none
-    if (valid && use_bound) {
+__global__ __launch_bounds__(256) void near_decide(int64_t n_trg, const double *__restrict__ frame,
+                                                   const NearBlob *__restrict__ nb, double mu, double threshold,
+                                                   const int32_t *__restrict__ tc, int32_t n_curves,
+                                                   const double *__restrict__ curve_tol, int use_bound,
+                                                   double *__restrict__ du, double *__restrict__ dv,
+                                                   int32_t *__restrict__ flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_trg) return;
+    int dec = 0;
+    if (use_bound) {
+        const double *fr = frame + kNearFrame * i;
+        const double b = fr[1], sg = fr[8], F = fr[7];
+        const double scale = OP == S2D_OP_SLP ? fr[6] / (4.0 * M_PI * mu) : 1.0 / M_PI;
         const float bf = (float)b;
         const bool side = OP == S2D_OP_SLP ? sg > 0.0 : sg < 0.0;
         const double sF = scale * F;
@@ -1163,75 +1246,120 @@ __global__ __launch_bounds__(256) void near_mlp_infer_mfma(int64_t n_trg, const 
             else dec = (double)nb->bound[bin] * sF <= tol ? 0 : 1;
         }
     }
-    double net[2] = {0.0, 0.0};
-    if (__any(valid && dec == 0)) {                              // wave-uniform
-        bf16x4v_t in1[2];
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            float v[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int k = 8 * s + 4 * h + e;
-                v[e] = (valid && k < kNearFeat) ? (xi[k] - nb->mu_in[k]) * nb->isd_in[k] : 0.f;
-            }
-            in1[s] = mfma_pack4(v[0], v[1], v[2], v[3]);
-        }
-        f32x16v_t acc[2];
-        bf16x4v_t hb[8];
-        mfma_layer<2, 2, 8>(nb->W1, nb->b1, in1, c, h, acc);
-        mfma_act(acc, hb);
-        mfma_layer<2, 8, 32>(nb->W2, nb->b2, hb, c, h, acc);
-        mfma_act(acc, hb);
-        mfma_layer<2, 8, 32>(nb->W3, nb->b3, hb, c, h, acc);
-        mfma_act(acc, hb);
-        f32x16v_t y[1];
-        mfma_layer<1, 8, 32>(nb->W4, nb->b4, hb, c, h, y);
-        // the lane's outputs o = 8 (r / 4) + 4 h + r % 4 < 20: dC[p][out][in] with
-        // p = o / 4, out = (o % 4) / 2, in = o % 2, contracted with d[p][in]
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int o = 8 * (r / 4) + 4 * h + (r % 4);
-            if (o < kNearOut) {
-                const int p = o / 4, out = (o % 4) / 2, in = o % 2;
-                net[out] = __builtin_fma((double)y[0][r], fr[9 + 2 * p + in], net[out]);
-            }
-        }
-        net[0] += __shfl_xor(net[0], 32, kWave);
-        net[1] += __shfl_xor(net[1], 32, kWave);
-        const double env = exp(-2.0 * M_PI * b);
-        net[0] *= env;
-        net[1] *= env;
-    }
-    // straight-line part: lanes h = 0 the plain rule (subtracted), h = 1 the refined one
-    double flat[2] = {0.0, 0.0};
-    if (valid && b > 0.0) {
-        const double D = h ? 1.0 / (double)nb->P : 1.0;
-        flat_rule<OP>(fr[0], b, D, h ? kPolyFine : kPolyCoarse, fr + 9, flat);
-        if (!h) {
-            flat[0] = -flat[0];
-            flat[1] = -flat[1];
-        }
-    }
-    const double ot = __shfl_xor(flat[0], 32, kWave), on = __shfl_xor(flat[1], 32, kWave);
-    if (!valid || h != 0) return;
-    // the refined rule's part plus the plain rule's (negated) part, in a fixed order
-    double yt = ot + flat[0], yn = on + flat[1];
-    if (OP != S2D_OP_SLP) {
-        yt *= sg;
-        yn *= sg;
-    }
+    flag[i] = dec;
     if (dec == 2) {
-        if (flag) flag[i] = 2;
         du[i] = 0.0;
         dv[i] = 0.0;
-    } else if (dec == 1) {
-        flag[i] = 1;                     // the quadrature fills du, dv
-    } else {
-        if (flag) flag[i] = 0;
-        yt += net[0];
-        yn += net[1];
-        du[i] = scale * (yt * fr[2] + yn * fr[4]);
-        dv[i] = scale * (yt * fr[3] + yn * fr[5]);
+    }
+}
+
+// The straight-line part of the learned targets, one per lane (target
+// list[q], q < *list_len, or q itself when list is NULL): du, dv =
+// scale [t n_f] sum_p Cflat_p d_p, the refined rule minus the plain one.
+template <int OP>
+__global__ __launch_bounds__(256) void near_flat(int64_t n_trg, const int32_t *__restrict__ list,
+                                                 const int32_t *__restrict__ list_len,
+                                                 const double *__restrict__ frame, const NearBlob *__restrict__ nb,
+                                                 double mu, double *__restrict__ du, double *__restrict__ dv) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = list ? (int64_t)*list_len : n_trg;
+    if (q >= n) return;
+    const int64_t i = list ? (int64_t)list[q] : q;
+    const double *fr = frame + kNearFrame * i;
+    const double b = fr[1];
+    const double scale = OP == S2D_OP_SLP ? fr[6] / (4.0 * M_PI * mu) : 1.0 / M_PI;
+    double yt = 0.0, yn = 0.0;
+    if (b > 0.0) {
+        double ff[2], fc[2];
+        flat_rule<OP>(fr[0], b, (double)nb->P, kPolyFine, fr + 9, ff);
+        flat_rule<OP>(fr[0], b, 1.0, kPolyCoarse, fr + 9, fc);
+        yt = ff[0] - fc[0];
+        yn = ff[1] - fc[1];
+        if (OP != S2D_OP_SLP) {
+            yt *= fr[8];
+            yn *= fr[8];
+        }
+    }
+    du[i] = scale * (yt * fr[2] + yn * fr[4]);                   // NaN for an invalid frame
+    dv[i] = scale * (yt * fr[3] + yn * fr[5]);
+}
+
+// The network's part of the learned route, added to du, dv of the listed
+// targets (list[q], q < *list_len, or all when list is NULL): a wave takes
+// 64 of them in two MFMA passes of 32; pass h2 feeds target 32 h2 + c from
+// lanes c and c + 32, and after the exchange lane 32 h2 + c holds it.
+// Persistent workgroups stage the network in LDS once; 4 waves per SIMD (128
+// registers) keep the LDS and MFMA latencies covered.
+template <int OP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) void near_net(
+    int64_t n_trg, const int32_t *__restrict__ list, const int32_t *__restrict__ list_len,
+    const float *__restrict__ X, const double *__restrict__ frame, const NearBlob *__restrict__ nb, double mu,
+    double *__restrict__ du, double *__restrict__ dv) {
+    static_assert(kNearFeat <= 16, "two K-steps of the first layer");
+    __shared__ NetLds L;
+    net_stage(nb, L);
+    __syncthreads();
+    const int64_t n = list ? (int64_t)*list_len : n_trg;
+    const int lane = threadIdx.x & (kWave - 1), h = lane >> 5, c = lane & 31;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    for (int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; g * kWave < n; g += waves) {
+        const int64_t q0 = g * kWave + lane;
+        const bool mine = q0 < n;
+        const int64_t i = mine ? (list ? (int64_t)list[q0] : q0) : 0;
+        double net[2] = {0.0, 0.0};
+#pragma unroll 1
+        for (int h2 = 0; h2 < 2; ++h2) {
+            const int64_t qt = g * kWave + 32 * h2 + c;
+            if (g * kWave + 32 * h2 >= n) break;                 // wave-uniform
+            const bool vt = qt < n;
+            const int64_t it = vt ? (list ? (int64_t)list[qt] : qt) : 0;
+            const float *xi = X + it * kNearFeat;
+            const double *ft = frame + kNearFrame * it;
+            bf16x4v_t in1[2];
+#pragma unroll
+            for (int s2 = 0; s2 < 2; ++s2) {
+                float v[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int k = 8 * s2 + 4 * h + e;
+                    v[e] = (vt && k < kNearFeat) ? (xi[k] - nb->mu_in[k]) * nb->isd_in[k] : 0.f;
+                }
+                in1[s2] = mfma_pack4(v[0], v[1], v[2], v[3]);
+            }
+            f32x16v_t acc[2];
+            bf16x4v_t hb[8];
+            mfma_layer<2, 2, kS1>(L.W1, L.b1, in1, c, h, acc);
+            mfma_act(acc, hb);
+            mfma_layer<2, 8, kS2>(L.W2, L.b2, hb, c, h, acc);
+            mfma_act(acc, hb);
+            mfma_layer<2, 8, kS2>(L.W3, L.b3, hb, c, h, acc);
+            mfma_act(acc, hb);
+            f32x16v_t y[1];
+            mfma_layer<1, 8, kS2>(L.W4, L.b4, hb, c, h, y);
+            // the lane's outputs o = 8 (r / 4) + 4 h + r % 4 < 20: dC[p][out][in] with
+            // p = o / 4, out = (o % 4) / 2, in = o % 2, contracted with d[p][in]
+            double nt[2] = {0.0, 0.0};
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int o = 8 * (r / 4) + 4 * h + (r % 4);
+                if (o < kNearOut) {
+                    const int p = o / 4, out = (o % 4) / 2, in = o % 2;
+                    nt[out] = __builtin_fma((double)y[0][r], ft[9 + 2 * p + in], nt[out]);
+                }
+            }
+            nt[0] += __shfl_xor(nt[0], 32, kWave);
+            nt[1] += __shfl_xor(nt[1], 32, kWave);
+            if (h == h2) {
+                net[0] = nt[0];
+                net[1] = nt[1];
+            }
+        }
+        if (!mine) continue;
+        const double *fr = frame + kNearFrame * i;
+        const double scale = OP == S2D_OP_SLP ? fr[6] / (4.0 * M_PI * mu) : 1.0 / M_PI;
+        const double se = scale * exp(-2.0 * M_PI * fr[1]);
+        du[i] = __builtin_fma(se, net[0] * fr[2] + net[1] * fr[4], du[i]);
+        dv[i] = __builtin_fma(se, net[0] * fr[3] + net[1] * fr[5], dv[i]);
     }
 }
 
@@ -1326,7 +1454,7 @@ __global__ __launch_bounds__(256) void near_train_targets_k(int64_t n, const dou
     double fc[2] = {0.0, 0.0}, ff[2] = {0.0, 0.0};
     if (b > 0.0) {
         flat_rule<OP>(fr[0], b, 1.0, kPolyCoarse, fr + 9, fc);
-        flat_rule<OP>(fr[0], b, 1.0 / (double)P, kPolyFine, fr + 9, ff);
+        flat_rule<OP>(fr[0], b, (double)P, kPolyFine, fr + 9, ff);
     }
     const double sgn = OP == S2D_OP_SLP ? 1.0 : fr[8];
     y0 -= sgn * (ff[0] - fc[0]);
@@ -1659,35 +1787,42 @@ hipError_t near_launch_quad(const s2d_curves *c, const s2d_targets *t, const int
     return hipGetLastError();
 }
 
-hipError_t near_launch_compact(int64_t n, const int32_t *flag, int32_t *cnt, int32_t *list, hipStream_t st) {
+hipError_t near_launch_compact(int64_t n, const int32_t *flag, int value, int32_t *cnt, int32_t *list,
+                               hipStream_t st) {
     if (n <= 0) return hipSuccess;
     const int64_t nb = (n + kCompactBlock - 1) / kCompactBlock;
-    hipLaunchKernelGGL(near_compact_count, dim3((unsigned)nb), dim3(kCompactBlock), 0, st, n, flag, cnt);
+    hipLaunchKernelGGL(near_compact_count, dim3((unsigned)nb), dim3(kCompactBlock), 0, st, n, flag, value, cnt);
     hipLaunchKernelGGL(near_compact_scan, dim3(1), dim3(1024), 0, st, nb, cnt);
-    hipLaunchKernelGGL(near_compact_scatter, dim3((unsigned)nb), dim3(kCompactBlock), 0, st, n, flag, cnt, list);
+    hipLaunchKernelGGL(near_compact_scatter, dim3((unsigned)nb), dim3(kCompactBlock), 0, st, n, flag, value, cnt,
+                       list);
     return hipGetLastError();
 }
 
 
 size_t near_derivs_scratch(const s2d_curves *c) {
-    // cos / sin table and mode coefficients for curves above kUpMaxN nodes
-    return c->n_nodes > kUpMaxN ? (size_t)c->n_nodes * 6 * sizeof(double) : 0;
+    // a flag (256 bytes), then for curves above kUpMaxN nodes the cos / sin
+    // table and the mode coefficients
+    return 256 + (c->n_nodes > kUpMaxN ? (size_t)c->n_nodes * 6 * sizeof(double) : 0);
 }
 
-hipError_t near_launch_derivs(const s2d_curves *c, double *dtab, double *scratch, hipStream_t st) {
+hipError_t near_launch_derivs(const s2d_curves *c, double *dtab, void *scratch, hipStream_t st) {
     if (c->n_curves <= 0 || c->n_nodes <= 0) return hipSuccess;
+    int32_t *big = (int32_t *)scratch;
+    hipError_t e = zero_int_launch(big, 1, st);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(near_derivs, dim3((unsigned)c->n_curves), dim3(256), 0, st, c->curve_off, c->n_curves,
-                       c->n_nodes, c->fx, c->fy, dtab);
+                       c->n_nodes, c->fx, c->fy, dtab, big);
     if (c->n_nodes > kUpMaxN) {
-        // some curve may exceed kUpMaxN nodes: rows of smaller curves return at once
-        double *tab = scratch, *coef = scratch + 2 * c->n_nodes;
-        hipLaunchKernelGGL(near_derivs_table, dim3(grid_for(c->n_nodes)), dim3(256), 0, st, c->curve_off,
-                           c->n_curves, c->n_nodes, tab);
-        const unsigned wb = grid_for(c->n_nodes, 256 / kWave);
-        hipLaunchKernelGGL(near_derivs_coef, dim3(wb), dim3(256), 0, st, c->curve_off, c->n_curves, c->n_nodes, c->fx,
-                           c->fy, tab, coef);
-        hipLaunchKernelGGL(near_derivs_nodes, dim3(wb), dim3(256), 0, st, c->curve_off, c->n_curves, c->n_nodes, tab,
-                           coef, dtab);
+        // some curve may exceed kUpMaxN nodes: the kernels return at once
+        // unless near_derivs found one
+        double *tab = (double *)((char *)scratch + 256), *coef = tab + 2 * c->n_nodes;
+        const unsigned g = (unsigned)std::min<int64_t>(kBigBlocks, (c->n_nodes + 255) / 256 * 4);
+        hipLaunchKernelGGL(near_derivs_table, dim3(g), dim3(256), 0, st, c->curve_off, c->n_curves, c->n_nodes, big,
+                           tab);
+        hipLaunchKernelGGL(near_derivs_coef, dim3(g), dim3(256), 0, st, c->curve_off, c->n_curves, c->n_nodes, big,
+                           c->fx, c->fy, tab, coef);
+        hipLaunchKernelGGL(near_derivs_nodes, dim3(g), dim3(256), 0, st, c->curve_off, c->n_curves, c->n_nodes, big,
+                           tab, coef, dtab);
     }
     return hipGetLastError();
 }
@@ -1714,17 +1849,37 @@ hipError_t near_launch_wall_features(const s2d_curves *c, const s2d_targets *t, 
 
 hipError_t near_launch_infer(int op, int64_t n, const float *X, const double *frame, const NearBlob *nb, double mu,
                              double threshold, const int32_t *tc, int32_t n_curves, const double *curve_tol,
-                             int use_bound, double *du, double *dv, int32_t *flag, hipStream_t st) {
+                             int use_bound, double *du, double *dv, int32_t *flag, int32_t *lcnt, int32_t *llist,
+                             hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    // 32 targets per wave, 4 waves per block
-    const int64_t groups = (n + 31) / 32;
-    const int64_t blocks = (groups + 3) / 4;
-    if (op == S2D_OP_SLP)
-        hipLaunchKernelGGL(near_mlp_infer_mfma<S2D_OP_SLP>, dim3((unsigned)blocks), dim3(256), 0, st, n, X, frame, nb,
-                           mu, threshold, tc, n_curves, curve_tol, use_bound, du, dv, flag);
+    // the decisions; with bounds, the learned targets compacted in order; the
+    // straight-line part a target per lane; the network 64 targets per wave
+    // (4 waves per block, persistent blocks that stage the network in LDS
+    // once, four per compute unit at most)
+    const unsigned fb = grid_for(n);
+    const int64_t groups = (n + kWave - 1) / kWave;
+    const unsigned nbk = (unsigned)std::min<int64_t>((groups + 3) / 4, 4 * kInferCUs);
+    const int32_t *list = nullptr, *len = nullptr;
+    const bool slp = op == S2D_OP_SLP;
+    if (slp)
+        hipLaunchKernelGGL(near_decide<S2D_OP_SLP>, dim3(fb), dim3(256), 0, st, n, frame, nb, mu, threshold, tc,
+                           n_curves, curve_tol, use_bound, du, dv, flag);
     else
-        hipLaunchKernelGGL(near_mlp_infer_mfma<S2D_OP_DLP>, dim3((unsigned)blocks), dim3(256), 0, st, n, X, frame, nb,
-                           mu, threshold, tc, n_curves, curve_tol, use_bound, du, dv, flag);
+        hipLaunchKernelGGL(near_decide<S2D_OP_DLP>, dim3(fb), dim3(256), 0, st, n, frame, nb, mu, threshold, tc,
+                           n_curves, curve_tol, use_bound, du, dv, flag);
+    if (use_bound) {
+        hipError_t e = near_launch_compact(n, flag, 0, lcnt, llist, st);
+        if (e != hipSuccess) return e;
+        list = llist;
+        len = lcnt + (n + 255) / 256;
+    }
+    if (slp) {
+        hipLaunchKernelGGL(near_flat<S2D_OP_SLP>, dim3(fb), dim3(256), 0, st, n, list, len, frame, nb, mu, du, dv);
+        hipLaunchKernelGGL(near_net<S2D_OP_SLP>, dim3(nbk), dim3(256), 0, st, n, list, len, X, frame, nb, mu, du, dv);
+    } else {
+        hipLaunchKernelGGL(near_flat<S2D_OP_DLP>, dim3(fb), dim3(256), 0, st, n, list, len, frame, nb, mu, du, dv);
+        hipLaunchKernelGGL(near_net<S2D_OP_DLP>, dim3(nbk), dim3(256), 0, st, n, list, len, X, frame, nb, mu, du, dv);
+    }
     return hipGetLastError();
 }
 

@@ -63,15 +63,16 @@ hipError_t near_launch_quad(const s2d_curves *c, const s2d_targets *t, const int
                             const int32_t *list_len, int P, const double *up, double mu, double *du, double *dv,
                             hipStream_t st, double *uf = nullptr, double *vf = nullptr, double *uc = nullptr,
                             double *vc = nullptr);
-// the targets with flag == 1, in order, into list; their number into
+// the targets with flag == value, in order, into list; their number into
 // cnt[ceil(n / 256)] (cnt: ceil(n / 256) + 1 ints of scratch)
-hipError_t near_launch_compact(int64_t n, const int32_t *flag, int32_t *cnt, int32_t *list, hipStream_t st);
+hipError_t near_launch_compact(int64_t n, const int32_t *flag, int value, int32_t *cnt, int32_t *list,
+                               hipStream_t st);
 // the density's node derivatives (kNearDeriv x 2 doubles per node, d_p of x
 // then y at 2p, 2p + 1), per-node units
-// scratch: near_derivs_scratch(c) bytes (8-byte aligned), used when some
-// curve has more than kUpMaxN nodes
+// scratch: near_derivs_scratch(c) bytes (256-byte aligned): a flag, and
+// when n_nodes > kUpMaxN the large-curve tables
 size_t near_derivs_scratch(const s2d_curves *c);
-hipError_t near_launch_derivs(const s2d_curves *c, double *dtab, double *scratch, hipStream_t st);
+hipError_t near_launch_derivs(const s2d_curves *c, double *dtab, void *scratch, hipStream_t st);
 hipError_t near_launch_features(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, const double *dtab,
                                 float *X, double *frame, hipStream_t st);
 hipError_t near_launch_wall_features(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, double d,
@@ -79,10 +80,13 @@ hipError_t near_launch_wall_features(const s2d_curves *c, const s2d_targets *t, 
 // op: S2D_OP_SLP (vesicles, scale hl / 4 pi mu, side +1) or S2D_OP_DLP
 // (walls, scale 1 / pi, side -1)
 // tolerance of target i: curve_tol[tc[i]] when curve_tol != NULL (and tc[i]
-// names a curve), else threshold
+// names a curve), else threshold; flag (device, [n], not NULL) receives the
+// decisions (all 0 when use_bound == 0); lcnt, llist: compaction scratch as
+// for near_launch_compact (used when use_bound != 0)
 hipError_t near_launch_infer(int op, int64_t n, const float *X, const double *frame, const NearBlob *nb, double mu,
                              double threshold, const int32_t *tc, int32_t n_curves, const double *curve_tol,
-                             int use_bound, double *du, double *dv, int32_t *flag, hipStream_t st);
+                             int use_bound, double *du, double *dv, int32_t *flag, int32_t *lcnt, int32_t *llist,
+                             hipStream_t st);
 hipError_t near_launch_pack(const float *prm, const float *bound, const float *bound_zero, int32_t n_bins,
                             float bin_lo, float bin_w, float b_min, int32_t P, NearBlob *nb, hipStream_t st);
 hipError_t near_launch_train_targets(int op, int64_t n, const double *frame, const double *du, const double *dv,
