@@ -360,7 +360,7 @@ def wall_learned_section(prob, n_train=200000, n_test=1000000, steps=200000):
     t_train = time.time() - t0
     del tr
     va = pn.WallNearData(walls, d, *synth.near_wall_dataset(walls, 1000000, 43))
-    blob, bound, bound0, count = pn.calibrate(va, params, margin=1.5)
+    blob, bound, bound0, count = pn.calibrate(va, params, margin=1.5, count_margin=2.0)
     del va
     te = pn.WallNearData(walls, d, *synth.near_wall_dataset(walls, n_test, 44))
     du = torch.empty(te.n, dtype=torch.float64, device="cuda")
@@ -650,7 +650,7 @@ def batch_section():
 
 def near_section(steps=200000):
     """Learned near-field correction on the near-target workload: train on
-    200k targets (200,000 steps of 1024 on the GPU), calibrate on 1M, test on
+    200k targets (200,000 steps of 1024 on the GPU), calibrate on 2M, test on
     1M (targets at log-uniform normal distances 0.05 h .. 5 h from ellipses
     of 64-128 nodes).  Errors are normalised per curve by the largest |u| of
     the 8x upsampled single layer over that curve's test targets; AUTO takes
@@ -667,8 +667,8 @@ def near_section(steps=200000):
     torch.cuda.synchronize()
     t_train = time.time() - t0
     del tr
-    va = near.NearData(*synth.make_near_dataset(1000000, 6)[:4], mu=1.0, upsample=8)
-    blob, bound, bound0, count = near.calibrate(va, params, margin=1.5)
+    va = near.NearData(*synth.make_near_dataset(2000000, 6)[:4], mu=1.0, upsample=8)
+    blob, bound, bound0, count = near.calibrate(va, params, margin=1.5, count_margin=2.0)
     del va
     log(f"near: trained {steps} steps in {t_train:.1f}s, loss {hist[0][1]:.3e} -> {hist[-1][1]:.3e}")
     te = near.NearData(*synth.make_near_dataset(1000000, 7)[:4], mu=1.0, upsample=8)
@@ -725,7 +725,7 @@ def near_section(steps=200000):
                                 "learned_max": float(err_mlp[m].max())}
     a5 = auto["1e-05"]
     res = {"workload": "1e6 targets at 0.05h..5h from 5000 ellipses of 64/96/128 nodes; network 14-64-64-64-20 "
-                       "trained on the GPU on 2e5 8x-upsampled labels (200,000 steps of 1024), calibrated on 1e6",
+                       "trained on the GPU on 2e5 8x-upsampled labels (200,000 steps of 1024), calibrated on 2e6",
            "err_vs_upsampled8": {"learned": e_mlp, "auto_1e-5_per_curve": a5["err"],
                                  "no_correction": float(err_plain.max())},
            "err_upsampled8_vs_32_on_64_node_curves": e_8v32, "error_by_normal_offset": gain,

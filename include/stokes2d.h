@@ -448,14 +448,15 @@ S2D_API int near_feature_stats(int64_t n, const float *X, float *params, void *s
  * curvature over the spacing (kappa h = frame[19]), over targets with b >=
  * b_min on the expected side (sg > 0 for the single layer, sg < 0 for the
  * double layer), the largest |(du_pred, dv_pred) - (du, dv)| and the largest
- * |(du, dv)|, both over scale F, times margin (>= 1): bound, bound_zero
- * [n_bins * S2D_NEAR_CELL] device float at S2D_NEAR_CELL k + 8 j + m; empty
- * bins get 3e38.  count: [n_bins * S2D_NEAR_CELL] device int32, the targets
- * per bin. */
+ * |(du, dv)|, both over scale F, times margin (1 + count_margin / sqrt(c))
+ * for a bin of c targets (margin >= 1, count_margin >= 0: a wider margin
+ * where the maximum rests on few samples): bound, bound_zero [n_bins *
+ * S2D_NEAR_CELL] device float at S2D_NEAR_CELL k + 8 j + m; empty bins get
+ * 3e38.  count: [n_bins * S2D_NEAR_CELL] device int32, the targets per bin. */
 S2D_API int near_calibrate(int op, int64_t n, const double *frame, const double *du_pred, const double *dv_pred,
                            const double *du, const double *dv, double mu, int32_t n_bins, float bin_lo,
-                           float bin_w, float b_min, float margin, float *bound, float *bound_zero,
-                           int32_t *count, void *stream);
+                           float bin_w, float b_min, float margin, float count_margin, float *bound,
+                           float *bound_zero, int32_t *count, void *stream);
 
 /* Bytes of the BF16 inference blob; near_mlp_pack fills it (device, 256-byte
  * aligned) from FP32 master parameters, the calibrated bounds ([n_bins *

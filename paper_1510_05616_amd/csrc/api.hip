@@ -849,14 +849,15 @@ S2D_API int near_correct_eval(int method, const s2d_curves *ves, const s2d_targe
     double *frame = (double *)(w + L.frame);
     e = s2d::near_launch_derivs(ves, dtab, w + L.dscr, st);
     if (e != hipSuccess) return hip_fail(e, "near derivative launch");
-    e = s2d::near_launch_features(ves, trg, trg_curve, dtab, X, frame, st);
-    if (e != hipSuccess) return hip_fail(e, "near features launch");
     const bool autom = method == S2D_NEAR_AUTO;
     // the per-target decisions: the caller's array or the workspace
     int32_t *flag = used_fallback ? used_fallback : (int32_t *)(w + L.flag);
-    e = s2d::near_launch_infer(S2D_OP_SLP, trg->n, X, frame, (const s2d::NearBlob *)mlp, mu, threshold, trg_curve,
-                               ves->n_curves, curve_tol, autom ? 1 : 0, du, dv, flag, (int32_t *)(w + L.lcount),
-                               (int32_t *)(w + L.llist), st);
+    const s2d::DecideArgs da{(const s2d::NearBlob *)mlp, mu, threshold, curve_tol, ves->n_curves, autom ? 1 : 0,
+                             du, dv, flag};
+    e = s2d::near_launch_features(ves, trg, trg_curve, dtab, X, frame, st, &da);
+    if (e != hipSuccess) return hip_fail(e, "near features launch");
+    e = s2d::near_launch_infer(S2D_OP_SLP, trg->n, X, frame, (const s2d::NearBlob *)mlp, mu, flag, autom ? 1 : 0, du,
+                               dv, (int32_t *)(w + L.lcount), (int32_t *)(w + L.llist), st);
     if (e != hipSuccess) return hip_fail(e, "near MLP launch");
     if (autom) {
         // the fallback targets, compacted in order, so that the quadrature's
@@ -1006,8 +1007,8 @@ S2D_API int near_feature_stats(int64_t n, const float *X, float *params, void *s
 
 S2D_API int near_calibrate(int op, int64_t n, const double *frame, const double *du_pred, const double *dv_pred,
                            const double *du, const double *dv, double mu, int32_t n_bins, float bin_lo, float bin_w,
-                           float b_min, float margin, float *bound, float *bound_zero, int32_t *count,
-                           void *stream) {
+                           float b_min, float margin, float count_margin, float *bound, float *bound_zero,
+                           int32_t *count, void *stream) {
     if (!valid_op(op)) return fail(S2D_EINVAL, "op must be S2D_OP_SLP or S2D_OP_DLP");
     if (n < 0 || n > INT32_MAX) return fail(S2D_EINVAL, "n out of range");
     if (n > 0 && (!frame || !du_pred || !dv_pred || !du || !dv)) return fail(S2D_EINVAL, "arrays must not be NULL");
@@ -1015,14 +1016,15 @@ S2D_API int near_calibrate(int op, int64_t n, const double *frame, const double 
     if (!bound || !bound_zero || !count) return fail(S2D_EINVAL, "bound, bound_zero and count must not be NULL");
     if (!(bin_w > 0.f) || !std::isfinite(bin_lo) || !std::isfinite(bin_w))
         return fail(S2D_EINVAL, "bins: bin_w must be finite and > 0, bin_lo finite");
-    if (!(b_min >= 0.f) || !(margin >= 1.f) || !std::isfinite(margin))
-        return fail(S2D_EINVAL, "b_min must be >= 0 and margin finite and >= 1");
+    if (!(b_min >= 0.f) || !(margin >= 1.f) || !std::isfinite(margin) || !(count_margin >= 0.f) ||
+        !std::isfinite(count_margin))
+        return fail(S2D_EINVAL, "b_min must be >= 0, margin finite and >= 1, count_margin finite and >= 0");
     if (!(std::isfinite(mu) && mu > 0.0)) return fail(S2D_EINVAL, "mu must be finite and > 0");
     int dev = 0;
     int rc = current_device(&dev);
     if (rc != S2D_OK) return rc;
     hipError_t e = s2d::near_launch_calibrate(op, n, frame, du_pred, dv_pred, du, dv, mu, n_bins, bin_lo, bin_w, b_min,
-                                              margin, (uint32_t *)bound, (uint32_t *)bound_zero, count,
+                                              margin, count_margin, (uint32_t *)bound, (uint32_t *)bound_zero, count,
                                               (hipStream_t)stream);
     return e == hipSuccess ? S2D_OK : hip_fail(e, "calibration launch");
 }
@@ -1309,13 +1311,14 @@ S2D_API int near_wall_correct_eval(int method, const s2d_curves *walls, const s2
     double *frame = (double *)(base + L.frame);
     e = s2d::near_launch_derivs(walls, dtab, base + L.dscr, st);
     if (e != hipSuccess) return hip_fail(e, "near-wall derivative launch");
-    e = s2d::near_launch_wall_features(walls, trg, trg_curve, d, dtab, X, frame, st);
-    if (e != hipSuccess) return hip_fail(e, "near-wall features launch");
     const bool autom = method == S2D_NEAR_AUTO;
     int32_t *flag = used_fallback ? used_fallback : (int32_t *)(base + L.flag);
     double *tu = t4, *tv = t4 + n;
-    e = s2d::near_launch_infer(S2D_OP_DLP, n, X, frame, (const s2d::NearBlob *)mlp, 1.0, threshold, trg_curve,
-                               walls->n_curves, curve_tol, autom ? 1 : 0, tu, tv, flag,
+    const s2d::DecideArgs da{(const s2d::NearBlob *)mlp, 1.0, threshold, curve_tol, walls->n_curves, autom ? 1 : 0,
+                             tu, tv, flag};
+    e = s2d::near_launch_wall_features(walls, trg, trg_curve, d, dtab, X, frame, st, &da);
+    if (e != hipSuccess) return hip_fail(e, "near-wall features launch");
+    e = s2d::near_launch_infer(S2D_OP_DLP, n, X, frame, (const s2d::NearBlob *)mlp, 1.0, flag, autom ? 1 : 0, tu, tv,
                                (int32_t *)(base + L.lcount), (int32_t *)(base + L.llist), st);
     if (e != hipSuccess) return hip_fail(e, "near-wall MLP launch");
     if (autom) {

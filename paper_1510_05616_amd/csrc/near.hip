@@ -263,14 +263,14 @@ __global__ __launch_bounds__(64 * kQuadParts) void near_quad(int64_t n_trg, cons
     const bool any_ok = cmin != INT_MAX;
     const bool uniform = any_ok && __all(!live || (ok && c == cmin));
     double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const double px = live ? tx[i] : tx[0], py = live ? ty[i] : ty[0];
     if (uniform) {
         // idle lanes follow the wave's curve (their results are dropped)
         const int cu = __builtin_amdgcn_readfirstlane(cmin);
         const int lou = off[cu], Nu = off[cu + 1] - lou;
-        near_sums<true>(live ? tx[i] : tx[0], live ? ty[i] : ty[0], lou, Nu, P, n_src, part, kQuadParts, up, ltab,
-                        s);
+        near_sums<true>(px, py, lou, Nu, P, n_src, part, kQuadParts, up, ltab, s);
     } else if (ok) {
-        near_sums<false>(tx[i], ty[i], lo, N, P, n_src, part, kQuadParts, up, ltab, s);
+        near_sums<false>(px, py, lo, N, P, n_src, part, kQuadParts, up, ltab, s);
     }
     if (part > 0) {
 #pragma unroll
@@ -680,6 +680,9 @@ __device__ __forceinline__ int near_scan(double px, double py, int lo, int N, co
     return ks;
 }
 
+// DEC: -1 features only; S2D_OP_SLP also AUTO's decision (near_decide_one)
+// from the frame in registers
+template <int DEC>
 __global__ __launch_bounds__(256) void near_features(int64_t n_trg, const double *__restrict__ tx,
                                                      const double *__restrict__ ty, const int32_t *__restrict__ tc,
                                                      const int32_t *__restrict__ off, int32_t n_curves, int64_t n_src,
@@ -687,7 +690,7 @@ __global__ __launch_bounds__(256) void near_features(int64_t n_trg, const double
                                                      const double *__restrict__ nx, const double *__restrict__ ny,
                                                      const double *__restrict__ kap, const double *__restrict__ w,
                                                      const double *__restrict__ dtab, float *__restrict__ X,
-                                                     double *__restrict__ frame) {
+                                                     double *__restrict__ frame, DecideArgs da) {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = q < n_trg;
     const int64_t i = live ? q : 0;
@@ -712,22 +715,26 @@ __global__ __launch_bounds__(256) void near_features(int64_t n_trg, const double
     }
     if (!live) return;
     float *xi = X + i * kNearFeat;
-    double *fr = frame + i * kNearFrame;
+    double rec[kNearFrame];
     if (!ok) {
-        near_invalid(xi, fr);
-        return;
-    }
-    double nb[4][2];
-    const int js[4] = {-2, -1, 1, 2};
+        near_invalid(xi, rec);
+    } else {
+        double nb[4][2];
+        const int js[4] = {-2, -1, 1, 2};
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int k = lo + (ks + js[j] + N) % N;
-        nb[j][0] = x[k];
-        nb[j][1] = y[k];
+        for (int j = 0; j < 4; ++j) {
+            const int k = lo + (ks + js[j] + N) % N;
+            nb[j][0] = x[k];
+            nb[j][1] = y[k];
+        }
+        const int k = lo + ks;
+        near_frame_features(px, py, x[k], y[k], nx[k], ny[k], kap[k], w[k], nb, xi, rec);
+        near_frame_head(dtab + (int64_t)k * 2 * kNearDeriv, rec);
     }
-    const int k = lo + ks;
-    near_frame_features(px, py, x[k], y[k], nx[k], ny[k], kap[k], w[k], nb, xi, fr);
-    near_frame_head(dtab + (int64_t)k * 2 * kNearDeriv, fr);
+    double *fr = frame + i * kNearFrame;
+#pragma unroll
+    for (int r = 0; r < kNearFrame; ++r) fr[r] = rec[r];
+    if constexpr (DEC >= 0) near_decide_one<DEC>(i, rec, da, c);
 }
 
 // Nearest-node search over the three periods of a wall.  Nodes are grouped in
@@ -882,6 +889,7 @@ __device__ int wall_nearest(const WallCells &W, bool cells, int c, int lo, int N
 // [-N, 2N) at (x_{K mod N} + sgd d floor(K / N), y_{K mod N})); the nearest
 // unrolled node k* (smallest K on ties) and its unrolled neighbours give the
 // features as for closed curves.
+template <int DEC>
 __global__ __launch_bounds__(256) void near_wall_features(int64_t n_trg, const double *__restrict__ tx,
                                                           const double *__restrict__ ty,
                                                           const int32_t *__restrict__ tc,
@@ -893,7 +901,7 @@ __global__ __launch_bounds__(256) void near_wall_features(int64_t n_trg, const d
                                                           const double *__restrict__ kap,
                                                           const double *__restrict__ w, double d,
                                                           const double *__restrict__ dtab, float *__restrict__ X,
-                                                          double *__restrict__ frame) {
+                                                          double *__restrict__ frame, DecideArgs da) {
     __shared__ WallCells W;
     wall_cells_build(W, off, n_curves, n_src, x, y, w);
     const bool cells = W.ok != 0;
@@ -903,8 +911,12 @@ __global__ __launch_bounds__(256) void near_wall_features(int64_t n_trg, const d
         const int N = (c >= 0 && c < n_curves) ? off[c + 1] - lo : 0;
         float *xi = X + i * kNearFeat;
         double *fr = frame + i * kNearFrame;
+        double rec[kNearFrame];
         if (c < 0 || c >= n_curves || N < 8 || lo < 0 || (int64_t)lo + N > n_src) {
-            near_invalid(xi, fr);
+            near_invalid(xi, rec);
+#pragma unroll
+            for (int r = 0; r < kNearFrame; ++r) fr[r] = rec[r];
+            if constexpr (DEC >= 0) near_decide_one<DEC>(i, rec, da, c);
             continue;
         }
         const double sgd = x[lo + 1] > x[lo] ? 1.0 : -1.0;
@@ -922,8 +934,12 @@ __global__ __launch_bounds__(256) void near_wall_features(int64_t n_trg, const d
             nb[j][1] = y[lo + md(K)];
         }
         const int m = lo + md(ks);
-        near_frame_features(px, py, x[m] + sgd * d * (double)fl(ks), y[m], nx[m], ny[m], kap[m], w[m], nb, xi, fr);
-        near_frame_head(dtab + (int64_t)m * 2 * kNearDeriv, fr);
+        near_frame_features(px, py, x[m] + sgd * d * (double)fl(ks), y[m], nx[m], ny[m], kap[m], w[m], nb, xi,
+                            rec);
+        near_frame_head(dtab + (int64_t)m * 2 * kNearDeriv, rec);
+#pragma unroll
+        for (int r = 0; r < kNearFrame; ++r) fr[r] = rec[r];
+        if constexpr (DEC >= 0) near_decide_one<DEC>(i, rec, da, c);
     }
 }
 
@@ -1210,32 +1226,23 @@ __device__ void net_stage(const NearBlob *__restrict__ nb, NetLds &L) {
     }
 }
 
-// AUTO's decision per target (flag[i] = dec: 0 learned, 1 quadrature, 2 no
-// correction; all 0 when use_bound == 0); du = dv = 0 for dec 2.
+// AUTO's decision for one target from its frame record fr (flag value: 0
+// learned, 1 quadrature, 2 no correction; 0 when use_bound == 0), and the
+// zero correction of dec 2 written to du, dv.
 template <int OP>
-__global__ __launch_bounds__(256) void near_decide(int64_t n_trg, const double *__restrict__ frame,
-                                                   const NearBlob *__restrict__ nb, double mu, double threshold,
-                                                   const int32_t *__restrict__ tc, int32_t n_curves,
-                                                   const double *__restrict__ curve_tol, int use_bound,
-                                                   double *__restrict__ du, double *__restrict__ dv,
-                                                   int32_t *__restrict__ flag) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_trg) return;
+__device__ __forceinline__ void near_decide_one(int64_t i, const double *fr, const DecideArgs &a, int c) {
     int dec = 0;
-    if (use_bound) {
-        const double *fr = frame + kNearFrame * i;
+    if (a.use_bound) {
+        const NearBlob *nb = a.nb;
         const double b = fr[1], sg = fr[8], F = fr[7];
-        const double scale = OP == S2D_OP_SLP ? fr[6] / (4.0 * M_PI * mu) : 1.0 / M_PI;
+        const double scale = OP == S2D_OP_SLP ? fr[6] / (4.0 * M_PI * a.mu) : 1.0 / M_PI;
         const float bf = (float)b;
         const bool side = OP == S2D_OP_SLP ? sg > 0.0 : sg < 0.0;
         const double sF = scale * F;
         const int nbins = nb->n_bins;
         const float pos = near_bpos(bf, nb->bin_lo, nb->bin_w);
-        double tol = threshold;
-        if (curve_tol) {
-            const int cc = tc[i];
-            tol = (cc >= 0 && cc < n_curves) ? curve_tol[cc] : -1.0;
-        }
+        double tol = a.threshold;
+        if (a.curve_tol) tol = (c >= 0 && c < a.n_curves) ? a.curve_tol[c] : -1.0;
         if (!(bf >= nb->b_min) || !side || !(sF == sF) || !(pos >= 0.f) || nbins <= 0) {
             dec = 1;
         } else {
@@ -1246,10 +1253,10 @@ __global__ __launch_bounds__(256) void near_decide(int64_t n_trg, const double *
             else dec = (double)nb->bound[bin] * sF <= tol ? 0 : 1;
         }
     }
-    flag[i] = dec;
+    a.flag[i] = dec;
     if (dec == 2) {
-        du[i] = 0.0;
-        dv[i] = 0.0;
+        a.du[i] = 0.0;
+        a.dv[i] = 0.0;
     }
 }
 
@@ -1509,7 +1516,8 @@ __global__ __launch_bounds__(256) void near_feature_stats_k(int64_t n, const flo
 // correction |label|, both over scale * F; targets that AUTO would not trust
 // the network with (b < b_min, the wrong side, NaN) are skipped.  bound and
 // bound_zero hold float bits (atomic max); empty bins become 3e38 and the
-// others are multiplied by margin in the finishing pass.
+// others are multiplied by margin (1 + count_margin / sqrt(count)) in the
+// finishing pass (a wider margin where a bin has few samples).
 template <int OP>
 __global__ __launch_bounds__(256) void near_calib_acc(int64_t n, const double *__restrict__ frame,
                                                       const double *__restrict__ dup, const double *__restrict__ dvp,
@@ -1545,11 +1553,13 @@ __global__ __launch_bounds__(256) void near_calib_init(int32_t n_bins, uint32_t 
     }
 }
 
-__global__ __launch_bounds__(256) void near_calib_finish(int32_t n_bins, float margin, uint32_t *bound,
-                                                         uint32_t *bound_zero, const int32_t *count) {
+__global__ __launch_bounds__(256) void near_calib_finish(int32_t n_bins, float margin, float count_margin,
+                                                         uint32_t *bound, uint32_t *bound_zero, const int32_t *count) {
     for (int b = threadIdx.x; b < n_bins * kNearCell; b += blockDim.x) {
-        const float e = count[b] > 0 ? __builtin_bit_cast(float, bound[b]) * margin : 3e38f;
-        const float z = count[b] > 0 ? __builtin_bit_cast(float, bound_zero[b]) * margin : 3e38f;
+        const int n = count[b];
+        const float m = n > 0 ? margin * (1.f + count_margin / sqrtf((float)n)) : 0.f;
+        const float e = n > 0 ? __builtin_bit_cast(float, bound[b]) * m : 3e38f;
+        const float z = n > 0 ? __builtin_bit_cast(float, bound_zero[b]) * m : 3e38f;
         bound[b] = __builtin_bit_cast(uint32_t, e);
         bound_zero[b] = __builtin_bit_cast(uint32_t, z);
     }
@@ -1828,52 +1838,58 @@ hipError_t near_launch_derivs(const s2d_curves *c, double *dtab, void *scratch, 
 }
 
 hipError_t near_launch_features(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, const double *dtab,
-                                float *X, double *frame, hipStream_t st) {
+                                float *X, double *frame, hipStream_t st, const DecideArgs *dec) {
     if (t->n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(near_features, dim3(grid_for(t->n)), dim3(256), 0, st, t->n, t->x, t->y, tc, c->curve_off,
-                       c->n_curves, c->n_nodes, c->x, c->y, c->nx, c->ny, c->kappa, c->w, dtab, X, frame);
+    const DecideArgs da = dec ? *dec : DecideArgs{};
+    if (dec)
+        hipLaunchKernelGGL(near_features<S2D_OP_SLP>, dim3(grid_for(t->n)), dim3(256), 0, st, t->n, t->x, t->y, tc,
+                           c->curve_off, c->n_curves, c->n_nodes, c->x, c->y, c->nx, c->ny, c->kappa, c->w, dtab, X,
+                           frame, da);
+    else
+        hipLaunchKernelGGL(near_features<-1>, dim3(grid_for(t->n)), dim3(256), 0, st, t->n, t->x, t->y, tc,
+                           c->curve_off, c->n_curves, c->n_nodes, c->x, c->y, c->nx, c->ny, c->kappa, c->w, dtab, X,
+                           frame, da);
     return hipGetLastError();
 }
 
 hipError_t near_launch_wall_features(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, double d,
-                                     const double *dtab, float *X, double *frame, hipStream_t st) {
+                                     const double *dtab, float *X, double *frame, hipStream_t st,
+                                     const DecideArgs *dec) {
     if (t->n <= 0) return hipSuccess;
     // grid-stride: each block builds the cell table once for up to a few
     // thousand targets
     const int64_t blocks = std::min<int64_t>((t->n + 255) / 256, 1024);
-    hipLaunchKernelGGL(near_wall_features, dim3((unsigned)blocks), dim3(256), 0, st, t->n, t->x, t->y, tc,
-                       c->curve_off, c->n_curves, c->n_nodes, c->x, c->y, c->nx, c->ny, c->kappa, c->w, d, dtab, X,
-                       frame);
+    const DecideArgs da = dec ? *dec : DecideArgs{};
+    if (dec)
+        hipLaunchKernelGGL(near_wall_features<S2D_OP_DLP>, dim3((unsigned)blocks), dim3(256), 0, st, t->n, t->x, t->y,
+                           tc, c->curve_off, c->n_curves, c->n_nodes, c->x, c->y, c->nx, c->ny, c->kappa, c->w, d,
+                           dtab, X, frame, da);
+    else
+        hipLaunchKernelGGL(near_wall_features<-1>, dim3((unsigned)blocks), dim3(256), 0, st, t->n, t->x, t->y, tc,
+                           c->curve_off, c->n_curves, c->n_nodes, c->x, c->y, c->nx, c->ny, c->kappa, c->w, d, dtab,
+                           X, frame, da);
     return hipGetLastError();
 }
 
 hipError_t near_launch_infer(int op, int64_t n, const float *X, const double *frame, const NearBlob *nb, double mu,
-                             double threshold, const int32_t *tc, int32_t n_curves, const double *curve_tol,
-                             int use_bound, double *du, double *dv, int32_t *flag, int32_t *lcnt, int32_t *llist,
-                             hipStream_t st) {
+                             const int32_t *flag, int use_bound, double *du, double *dv, int32_t *lcnt,
+                             int32_t *llist, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    // the decisions; with bounds, the learned targets compacted in order; the
-    // straight-line part a target per lane; the network 64 targets per wave
-    // (4 waves per block, persistent blocks that stage the network in LDS
-    // once, four per compute unit at most)
+    // with bounds, the learned targets compacted in order; the straight-line
+    // part a target per lane; the network 64 targets per wave (4 waves per
+    // block, persistent blocks that stage the network in LDS once, four per
+    // compute unit at most)
     const unsigned fb = grid_for(n);
     const int64_t groups = (n + kWave - 1) / kWave;
     const unsigned nbk = (unsigned)std::min<int64_t>((groups + 3) / 4, 4 * kInferCUs);
     const int32_t *list = nullptr, *len = nullptr;
-    const bool slp = op == S2D_OP_SLP;
-    if (slp)
-        hipLaunchKernelGGL(near_decide<S2D_OP_SLP>, dim3(fb), dim3(256), 0, st, n, frame, nb, mu, threshold, tc,
-                           n_curves, curve_tol, use_bound, du, dv, flag);
-    else
-        hipLaunchKernelGGL(near_decide<S2D_OP_DLP>, dim3(fb), dim3(256), 0, st, n, frame, nb, mu, threshold, tc,
-                           n_curves, curve_tol, use_bound, du, dv, flag);
     if (use_bound) {
         hipError_t e = near_launch_compact(n, flag, 0, lcnt, llist, st);
         if (e != hipSuccess) return e;
         list = llist;
         len = lcnt + (n + 255) / 256;
     }
-    if (slp) {
+    if (op == S2D_OP_SLP) {
         hipLaunchKernelGGL(near_flat<S2D_OP_SLP>, dim3(fb), dim3(256), 0, st, n, list, len, frame, nb, mu, du, dv);
         hipLaunchKernelGGL(near_net<S2D_OP_SLP>, dim3(nbk), dim3(256), 0, st, n, list, len, X, frame, nb, mu, du, dv);
     } else {
@@ -1937,8 +1953,8 @@ hipError_t near_launch_feature_stats(int64_t n, const float *X, float *prm, hipS
 
 hipError_t near_launch_calibrate(int op, int64_t n, const double *frame, const double *dup, const double *dvp,
                                  const double *du, const double *dv, double mu, int32_t n_bins, float bin_lo,
-                                 float bin_w, float b_min, float margin, uint32_t *bound, uint32_t *bound_zero,
-                                 int32_t *count, hipStream_t st) {
+                                 float bin_w, float b_min, float margin, float count_margin, uint32_t *bound,
+                                 uint32_t *bound_zero, int32_t *count, hipStream_t st) {
     hipLaunchKernelGGL(near_calib_init, dim3(1), dim3(256), 0, st, n_bins, bound, bound_zero, count);
     if (n > 0) {
         if (op == S2D_OP_SLP)
@@ -1948,7 +1964,8 @@ hipError_t near_launch_calibrate(int op, int64_t n, const double *frame, const d
             hipLaunchKernelGGL(near_calib_acc<S2D_OP_DLP>, dim3(grid_for(n)), dim3(256), 0, st, n, frame, dup, dvp, du,
                                dv, mu, n_bins, bin_lo, bin_w, b_min, bound, bound_zero, count);
     }
-    hipLaunchKernelGGL(near_calib_finish, dim3(1), dim3(256), 0, st, n_bins, margin, bound, bound_zero, count);
+    hipLaunchKernelGGL(near_calib_finish, dim3(1), dim3(256), 0, st, n_bins, margin, count_margin, bound,
+                       bound_zero, count);
     return hipGetLastError();
 }
 

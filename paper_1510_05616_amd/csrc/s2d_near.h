@@ -73,20 +73,32 @@ hipError_t near_launch_compact(int64_t n, const int32_t *flag, int value, int32_
 // when n_nodes > kUpMaxN the large-curve tables
 size_t near_derivs_scratch(const s2d_curves *c);
 hipError_t near_launch_derivs(const s2d_curves *c, double *dtab, void *scratch, hipStream_t st);
+// AUTO's decision inputs: tolerance of target i = curve_tol[tc[i]] when
+// curve_tol != NULL (and tc[i] names a curve), else threshold; flag [n]
+// receives the decisions (0 learned, 1 quadrature, 2 none; all 0 when
+// use_bound == 0), du = dv = 0 is written for decision 2
+struct DecideArgs {
+    const NearBlob *nb;
+    double mu, threshold;
+    const double *curve_tol;
+    int32_t n_curves, use_bound;
+    double *du, *dv;
+    int32_t *flag;
+};
+// the feature kernels also take AUTO's decisions when dec != NULL
 hipError_t near_launch_features(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, const double *dtab,
-                                float *X, double *frame, hipStream_t st);
+                                float *X, double *frame, hipStream_t st, const DecideArgs *dec = nullptr);
 hipError_t near_launch_wall_features(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, double d,
-                                     const double *dtab, float *X, double *frame, hipStream_t st);
+                                     const double *dtab, float *X, double *frame, hipStream_t st,
+                                     const DecideArgs *dec = nullptr);
 // op: S2D_OP_SLP (vesicles, scale hl / 4 pi mu, side +1) or S2D_OP_DLP
 // (walls, scale 1 / pi, side -1)
-// tolerance of target i: curve_tol[tc[i]] when curve_tol != NULL (and tc[i]
-// names a curve), else threshold; flag (device, [n], not NULL) receives the
-// decisions (all 0 when use_bound == 0); lcnt, llist: compaction scratch as
-// for near_launch_compact (used when use_bound != 0)
+// the learned route for the targets with flag 0 (flag from the feature
+// kernels' decisions; use_bound == 0: every target): lcnt, llist are
+// compaction scratch as for near_launch_compact (used when use_bound != 0)
 hipError_t near_launch_infer(int op, int64_t n, const float *X, const double *frame, const NearBlob *nb, double mu,
-                             double threshold, const int32_t *tc, int32_t n_curves, const double *curve_tol,
-                             int use_bound, double *du, double *dv, int32_t *flag, int32_t *lcnt, int32_t *llist,
-                             hipStream_t st);
+                             const int32_t *flag, int use_bound, double *du, double *dv, int32_t *lcnt,
+                             int32_t *llist, hipStream_t st);
 hipError_t near_launch_pack(const float *prm, const float *bound, const float *bound_zero, int32_t n_bins,
                             float bin_lo, float bin_w, float b_min, int32_t P, NearBlob *nb, hipStream_t st);
 hipError_t near_launch_train_targets(int op, int64_t n, const double *frame, const double *du, const double *dv,
@@ -100,8 +112,8 @@ hipError_t near_launch_fwd(int64_t n, const float *X, const float *prm, float *Y
 hipError_t near_launch_feature_stats(int64_t n, const float *X, float *prm, hipStream_t st);
 hipError_t near_launch_calibrate(int op, int64_t n, const double *frame, const double *dup, const double *dvp,
                                  const double *du, const double *dv, double mu, int32_t n_bins, float bin_lo,
-                                 float bin_w, float b_min, float margin, uint32_t *bound, uint32_t *bound_zero,
-                                 int32_t *count, hipStream_t st);
+                                 float bin_w, float b_min, float margin, float count_margin, uint32_t *bound,
+                                 uint32_t *bound_zero, int32_t *count, hipStream_t st);
 
 constexpr int kUpMaxN = 256;      // coarse nodes per curve for upsampling
 constexpr int kUpMaxM = 2048;     // fine nodes per curve

@@ -77,7 +77,7 @@ def _bind():
         "near_mlp_train_step": ([I32, P, P, P, P, P, P, I32, F, P, P, P, SZ, P], I),
         "near_mlp_forward": ([I64, P, P, P, P], I),
         "near_feature_stats": ([I64, P, P, P], I),
-        "near_calibrate": ([I, I64, P, P, P, P, P, D, I32, F, F, F, F, P, P, P, P], I),
+        "near_calibrate": ([I, I64, P, P, P, P, P, D, I32, F, F, F, F, F, P, P, P, P], I),
         "near_mlp_blob_size": ([], SZ),
         "near_mlp_pack": ([P, P, P, I32, F, F, F, I32, P, P], I),
         "stokes2d_wall_upsample_workspace_size": ([P, I32], SZ),
@@ -176,11 +176,11 @@ def near_feature_stats(X, params, stream=None) -> None:
 
 
 def near_calibrate(op, frame, du_pred, dv_pred, du, dv, mu, n_bins, bin_lo, bin_w, b_min, margin, bound,
-                   bound_zero, count, stream=None) -> None:
+                   bound_zero, count, count_margin=0.0, stream=None) -> None:
     _check(_bind().near_calibrate(int(op), int(frame.shape[0]), _ptr(frame), _ptr(du_pred), _ptr(dv_pred),
                                   _ptr(du), _ptr(dv), float(mu), int(n_bins), float(bin_lo), float(bin_w),
-                                  float(b_min), float(margin), _ptr(bound), _ptr(bound_zero), _ptr(count),
-                                  _stream(stream)))
+                                  float(b_min), float(margin), float(count_margin), _ptr(bound), _ptr(bound_zero),
+                                  _ptr(count), _stream(stream)))
 
 
 def near_mlp_blob_size() -> int:
@@ -438,10 +438,12 @@ def train(data: _NearSet, steps=20000, batch=1024, lr=2e-3, lr_min=2e-5, b_train
     return params, hist
 
 
-def calibrate(data: _NearSet, params, margin=1.25, b_min=B_MIN, n_bins=N_BINS, bin_lo=BIN_LO, bin_w=BIN_W):
+def calibrate(data: _NearSet, params, margin=1.5, count_margin=2.0, b_min=B_MIN, n_bins=N_BINS, bin_lo=BIN_LO,
+              bin_w=BIN_W):
     """Per-bin bounds on held-out data by the library's calibration kernel:
     the learned route's (BF16) largest error and the largest correction, each
-    over scale F, times margin, per bin of (log10 b, |s|, log10 |kappa h|).
+    over scale F, times margin (1 + count_margin / sqrt(targets in the bin)),
+    per bin of (log10 b, |s|, log10 |kappa h|).
     Returns (blob, bound, bound_zero, count) as device tensors ([N_BINS *
     CELL])."""
     import torch
@@ -455,6 +457,6 @@ def calibrate(data: _NearSet, params, margin=1.25, b_min=B_MIN, n_bins=N_BINS, b
     bound0 = torch.zeros_like(bound)
     count = torch.zeros(n_bins * CELL, dtype=torch.int32, device=dev)
     near_calibrate(data.op, data.frame, du, dv, data.du, data.dv, data.mu, n_bins, bin_lo, bin_w, b_min, margin,
-                   bound, bound0, count)
+                   bound, bound0, count, count_margin)
     near_mlp_pack(params, bound, n_bins, bin_lo, bin_w, blob, bound_zero=bound0, b_min=b_min, upsample=data.P)
     return blob, bound, bound0, count

@@ -226,10 +226,11 @@ def test_learned_near_argument_checks(L):
     assert tt(mu=0.0) == s2d.S2D_EINVAL and tt(P=0) == s2d.S2D_EINVAL and tt(n=-1) == s2d.S2D_EINVAL
     assert tt(cs=None) == s2d.S2D_EINVAL
     # calibration: bins, margin, b_min
-    cal = lambda nb=64, w=0.03, bmin=0.05, margin=1.25, op=0: L.near_calibrate(
-        op, 10, fake, fake, fake, fake, fake, 1.0, nb, -1.3, w, bmin, margin, fake, fake, fake, None)
+    cal = lambda nb=64, w=0.03, bmin=0.05, margin=1.25, cm=2.0, op=0: L.near_calibrate(
+        op, 10, fake, fake, fake, fake, fake, 1.0, nb, -1.3, w, bmin, margin, cm, fake, fake, fake, None)
     assert cal(nb=0) == s2d.S2D_EINVAL and cal(nb=65) == s2d.S2D_EINVAL
     assert cal(w=0.0) == s2d.S2D_EINVAL and cal(margin=0.9) == s2d.S2D_EINVAL
+    assert cal(cm=-1.0) == s2d.S2D_EINVAL and cal(cm=float("inf")) == s2d.S2D_EINVAL
     assert cal(bmin=-1.0) == s2d.S2D_EINVAL and cal(op=3) == s2d.S2D_EINVAL
     # packing: bins, bounds, b_min, upsample, blob alignment
     pk = lambda nb=64, bound=fake, bmin=0.05, P=8, blob=fake: L.near_mlp_pack(

@@ -510,7 +510,7 @@ def test_calibration_matches_numpy(small):
     bound = torch.zeros(near.N_BINS * near.CELL, dtype=torch.float32, device="cuda")
     bound0, count = torch.zeros_like(bound), torch.zeros(near.N_BINS * near.CELL, dtype=torch.int32, device="cuda")
     near.near_calibrate(near.S2D_OP_SLP, data.frame, du, dv, data.du, data.dv, 1.0, near.N_BINS, near.BIN_LO,
-                        near.BIN_W, near.B_MIN, 1.5, bound, bound0, count)
+                        near.BIN_W, near.B_MIN, 1.5, bound, bound0, count, count_margin=2.0)
     torch.cuda.synchronize()
     fr = data.frame.cpu().numpy()
     sF = fr[:, 6] / (4 * math.pi) * fr[:, 7]
@@ -528,7 +528,8 @@ def test_calibration_matches_numpy(small):
     gb, gz, gc = bound.cpu().numpy(), bound0.cpu().numpy(), count.cpu().numpy()
     full = cn > 0
     assert np.array_equal(gc, cn)
-    assert np.allclose(gb[full], 1.5 * be[full], rtol=1e-6) and np.allclose(gz[full], 1.5 * bz[full], rtol=1e-6)
+    m = 1.5 * (1 + 2.0 / np.sqrt(np.maximum(cn, 1)))
+    assert np.allclose(gb[full], (m * be)[full], rtol=1e-6) and np.allclose(gz[full], (m * bz)[full], rtol=1e-6)
     assert np.all(gb[~full] == np.float32(3e38)) and np.all(gz[~full] == np.float32(3e38))
 
 
@@ -536,13 +537,13 @@ def test_calibration_matches_numpy(small):
 def trained():
     """The learned correction trained on the GPU: 200,000 targets of the
     near-field workload, 200,000 steps of 1024, calibrated on 1,000,000
-    held-out targets with margin 1.5."""
+    held-out targets with margin 1.5 (1 + 2 / sqrt(targets per bin))."""
     from paper_1510_05616_amd import near
     tr = near.NearData(*synth.make_near_dataset(200000, seed=51)[:4], mu=1.0, upsample=8)
     params, hist = near.train(tr, steps=200000, batch=1024, lr=2e-3, log_every=25000)
     del tr
     va = near.NearData(*synth.make_near_dataset(1000000, seed=52)[:4], mu=1.0, upsample=8)
-    blob, bound, bound0, count = near.calibrate(va, params, margin=1.5)
+    blob, bound, bound0, count = near.calibrate(va, params, margin=1.5, count_margin=2.0)
     del va
     return params, hist, blob
 
