@@ -44,7 +44,8 @@ PEAK = {"f32": 157.3e12, "f64": 78.6e12}
 
 
 PAIR_SOURCES = ("paper_1510_05616_amd/csrc/pair_impl.h", "paper_1510_05616_amd/csrc/pair.hip",
-                "paper_1510_05616_amd/csrc/s2d_internal.h", "paper_1510_05616_amd/csrc/api.hip")
+                "paper_1510_05616_amd/csrc/s2d_internal.h", "paper_1510_05616_amd/csrc/plan.hip")
+SLP_KERNEL = {"f32": "pair_kernel<0,1,3>", "f64": "pair_kernel<0,0,3>"}
 PROFILE = "profiles/pair_kernels_config3.md"
 VALU_PROFILE = "profiles/pair_kernels_valu_config3.md"
 
@@ -86,11 +87,45 @@ def measured_valu(kernel):
     m = re.search(r"pair-kernel source sha1: ([0-9a-f]{40})", txt)
     if not m or m.group(1) != pair_source_sha1():
         return None
-    m = re.search(r"valu_busy " + re.escape(kernel) + r" ([\d.]+) issuing ([\d.]+) dual ([\d.]+) ghz ([\d.]+)", txt)
+    m = re.search(r"valu_busy " + re.escape(kernel) + r" ([\d.]+) issuing ([\d.]+) dual ([\d.]+) ghz ([\d.]+)"
+                  r" valu_per_pair ([\d.]+)", txt)
     if not m:
         return None
     return {"valu_busy_pct": float(m.group(1)), "valu_issuing_pct": float(m.group(2)),
-            "dual_issue_pct": float(m.group(3)), "clock_ghz": float(m.group(4)), "source": VALU_PROFILE}
+            "dual_issue_pct": float(m.group(3)), "clock_ghz": float(m.group(4)),
+            "valu_per_pair": float(m.group(5)), "source": VALU_PROFILE}
+
+
+def issue_probe(blocks=2048, iters=20000, reps=3):
+    """The VALU issue ceiling: stokes2d_valu_probe's rate (wave-instructions
+    per second, 8 waves per SIMD of independent FMA chains) for FP32 with
+    VGPR operands, FP32 with an SGPR operand, and FP64, timed with HIP events
+    on the launch stream."""
+    import ctypes
+    import torch
+    import paper_1510_05616_amd as s2d
+    L = s2d.lib()
+    L.stokes2d_valu_probe.argtypes = [ctypes.c_int, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+    L.stokes2d_valu_probe.restype = ctypes.c_int
+    sink = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+    st = torch.cuda.current_stream()
+    out = {}
+    for form, name in ((0, "f32_vgpr"), (1, "f32_sgpr"), (2, "f64")):
+        best = None
+        for _ in range(reps + 1):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(st)
+            rc = L.stokes2d_valu_probe(form, blocks, iters, ctypes.c_void_p(sink.data_ptr()),
+                                       ctypes.c_void_p(st.cuda_stream))
+            b.record(st)
+            assert rc == 0, s2d.stokes2d_last_error()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b)
+            best = ms if best is None else min(best, ms)
+        winstr = blocks * 4 * iters * 8                      # wave-instructions (4 waves per block)
+        out[name] = {"wave_instr_per_s": winstr / (best * 1e-3), "ms": best,
+                     "tflops": 2 * 64 * winstr / (best * 1e-3) / 1e12}
+    return out
 
 
 def copy_probe():
@@ -759,9 +794,17 @@ def main():
     ap.add_argument("--channel", type=int, default=1,
                     help="run Algorithm 1 in the channel, with the cell factored once (0: skip)")
     ap.add_argument("--copy-probe", action="store_true", help="only copy 1 GiB on the device and exit")
+    ap.add_argument("--issue-probe", action="store_true",
+                    help="only run the VALU issue-rate probes, print their rates and exit")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
+        return
+    if args.issue_probe:
+        import torch
+        import paper_1510_05616_amd as s2d
+        s2d.stokes2d_init(0)
+        print(json.dumps(issue_probe()), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path; a single-GPU run "
@@ -779,20 +822,30 @@ def main():
     pairs_dlp = n_trg * n_w * n_img
     pairs = pairs_slp + pairs_dlp
 
+    probe = issue_probe()
+    log("VALU issue probe: " + ", ".join(f"{k} {v['wave_instr_per_s']:.3e} wave-instr/s ({v['tflops']:.1f} TFLOP/s)"
+                                         for k, v in probe.items()))
     res = {}
     for name, mode in (("f32", s2d.S2D_FP32C), ("f64", s2d.S2D_FP64)):
         r = run_mode(prob, mode, args.steps, args.warmup)
         ms_step = r["ms_total"] / args.steps
         ach = FLOPS_PER_PAIR * pairs_slp / (r["slp_ms"] * 1e-3)
+        kern = SLP_KERNEL[name]
+        valu = measured_valu(kern)
+        # the kernel's VALU wave-instruction rate (instructions per pair from
+        # the committed counters) over the probe's all-VGPR rate of its type
+        ceiling = probe["f32_vgpr" if name == "f32" else "f64"]["wave_instr_per_s"]
+        rate = valu["valu_per_pair"] * pairs_slp / 64 / (r["slp_ms"] * 1e-3) if valu else None
         res[name] = dict(ms_per_step=ms_step, value=pairs / (ms_step * 1e-3),
                          slp_pair_ms=r["slp_ms"], dlp_pair_ms=r["dlp_ms"],
-                         roofline={"bound": "alu", "kernel": "pair_kernel<SLP>",
+                         roofline={"bound": "alu", "kernel": kern,
                                    "achieved": ach / 1e12, "peak": PEAK[name] / 1e12,
                                    "unit": "TFLOP/s", "frac": ach / PEAK[name],
-                                   "traffic": measured_traffic(
-                                       "pair_kernel<0,1,1>" if name == "f32" else "pair_kernel<0,0,1>"),
-                                   "valu_counters": measured_valu(
-                                       "pair_kernel<0,1,1>" if name == "f32" else "pair_kernel<0,0,1>"),
+                                   "traffic": measured_traffic(kern),
+                                   "valu_counters": valu,
+                                   "issue_ceiling_wave_instr_per_s": ceiling,
+                                   "issue_ceiling_frac": rate / ceiling if rate else None,
+                                   "issue_probe": probe,
                                    "flops_per_pair": FLOPS_PER_PAIR, "pairs_per_launch": pairs_slp},
                          u=r["u"], v=r["v"])
         log(f"{name}: {ms_step:.3f} ms/step, {pairs / (ms_step * 1e-3):.4e} pairs/s, "

@@ -537,6 +537,15 @@ S2D_API int near_wall_correct_eval(int method, const s2d_curves *walls, const s2
                                    double *dv, int32_t *used_fallback, int accumulate, void *ws,
                                    size_t ws_bytes, void *stream);
 
+/* Benchmarking aid: the VALU instruction issue rate reachable on this chip.
+ * Launches blocks x 256 threads on `stream`, each running 8 independent
+ * fused multiply-add chains of `iters` steps and writing their sum to
+ * sink[thread] ([blocks * 256] device floats): form 0 FP32 with every
+ * operand in a VGPR, form 1 FP32 with the multiplier a wave-uniform SGPR
+ * value, form 2 FP64.  The caller times the launch (8 FMA per thread and
+ * step). */
+S2D_API int stokes2d_valu_probe(int form, int32_t blocks, int32_t iters, float *sink, void *stream);
+
 /* Benchmarking aid (not capturable, not for production loops): while
  * enabled, each evaluation records a HIP event pair around its pair-sum
  * kernel launch on the caller's stream.  stokes2d_profile_read() waits for

@@ -52,10 +52,7 @@ int fail(int code, const std::string &msg) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-size_t rec_bytes(int op, int mode) {
-    if (s2d::slp_sources(op)) return mode == S2D_FP64 ? sizeof(s2d::RecSlp64) : sizeof(s2d::RecSlp32);
-    return mode == S2D_FP64 ? sizeof(s2d::RecDlp64) : sizeof(s2d::RecDlp32);
-}
+using s2d::rec_bytes;
 
 // Checks that do not depend on the device; returns S2D_OK or an error code
 // with g_err set.
@@ -92,85 +89,6 @@ int check_args(int op, int mode, const s2d_curves *s, const s2d_targets *t, doub
     if ((op == S2D_OP_SLP || op == S2D_OP_DLP_PRESSURE) && !(std::isfinite(mu) && mu > 0.0))
         return fail(S2D_EINVAL, "mu must be finite and > 0");
     return S2D_OK;
-}
-
-s2d::Plan make_plan(int op, int mode, const s2d_curves *s, const s2d_targets *t, int cus) {
-    using namespace s2d;
-    Plan p{};
-    p.op = op;
-    p.mode = mode;
-    p.tpt = 1;
-    // Launch shape: one target tile (64 targets) per workgroup of W waves,
-    // each wave a source split, and G split groups (workgroups) per tile.
-    // G = 1 when the source records fit comfortably in one XCD's L2 (4 MB)
-    // and the tiles alone give at least two rounds of 8 waves per SIMD;
-    // otherwise G grows to fill the chip (few targets, many sources), and is
-    // a multiple of 8 when the records exceed the L2 budget, so that every
-    // XCD streams only its own groups' sources.  S2D_WAVES and S2D_GROUPS
-    // override the shape for tuning sweeps.
-    static const int env_waves = [] {
-        const char *e = std::getenv("S2D_WAVES");
-        const int v = e ? std::atoi(e) : 0;
-        return (v >= 1 && v <= kMaxPairWaves) ? v : 0;
-    }();
-    static const int env_groups = [] {
-        const char *e = std::getenv("S2D_GROUPS");
-        return e ? std::max(0, std::atoi(e)) : 0;
-    }();
-    constexpr size_t kL2Budget = (size_t)3 << 20;
-    p.n_src = s->n_nodes;
-    p.n_trg = t->n;
-    p.n_sb = (p.n_src + kSuperBlock - 1) / kSuperBlock;
-    p.n_tiles = (p.n_trg + kWave - 1) / kWave;
-    if (p.n_sb > 0 && p.n_tiles > 0) {
-        const bool fits = (size_t)p.n_sb * kSuperBlock * rec_bytes(op, mode) <= kL2Budget;
-        const int64_t fill = (int64_t)cus * 4 * 16;
-        const int64_t gmax = std::max<int64_t>(1, (p.n_sb + 7) / 8);
-        int64_t G = 1;
-        if (!(fits && p.n_tiles * kMaxPairWaves >= fill))
-            G = std::min<int64_t>(std::max<int64_t>(1, (fill + p.n_tiles * kMaxPairWaves - 1) /
-                                                           (p.n_tiles * kMaxPairWaves)), gmax);
-        if (!fits && gmax >= 8) G = std::min<int64_t>((std::max<int64_t>(G, 8) + 7) / 8 * 8, gmax / 8 * 8);
-        G = std::min<int64_t>(G, 65536);
-        if (env_groups) G = std::min<int64_t>(env_groups, p.n_sb);
-        // W: the full width, or fewer when the group has fewer superblocks.
-        int W = (int)std::min<int64_t>(kMaxPairWaves, (p.n_sb + G - 1) / G);
-        if (env_waves) W = env_waves;
-        p.waves = W;
-        p.n_groups = (int)G;
-        p.n_splits = (int)(W * G);
-        p.sb_per_split = (p.n_sb + p.n_splits - 1) / p.n_splits;
-        p.n_blocks = p.n_tiles * G;
-    } else {
-        p.waves = 1;
-        p.n_groups = 1;
-        p.sb_per_split = 0;
-        p.n_splits = 0;
-        p.n_blocks = 0;
-    }
-    p.self = false;    // set by the caller once images are known
-    size_t off = 0;
-    p.off_rec = off;
-    off = align256(off + (size_t)p.n_sb * kSuperBlock * rec_bytes(op, mode));
-    p.off_rec64 = off;
-    if (mode == S2D_FP32C && s2d::near_fp64(op))
-        off = align256(off + (size_t)p.n_sb * kSuperBlock * rec_bytes(op, S2D_FP64));
-    p.off_sub = off;
-    if (mode == S2D_FP32C)
-        off = align256(off + (size_t)p.n_sb * (kSuperBlock / kSubBlock) * sizeof(s2d::SubInfo));
-    p.off_sbsum = off;
-    if (op == S2D_OP_SLP && mode == S2D_FP32C) off = align256(off + (size_t)p.n_sb * 2 * sizeof(double));
-    p.off_part = off;
-    if (p.n_groups > 1) off = align256(off + (size_t)p.n_groups * 2 * (size_t)p.n_trg * sizeof(double));
-    p.off_self = off;
-    p.off_kress = off;
-    if (op == S2D_OP_SLP && t->on_curve && p.n_trg > 0) {
-        off = align256(off + 2 * (size_t)p.n_trg * sizeof(double));
-        p.off_kress = off;
-        off = align256(off + (size_t)p.n_src * sizeof(double));
-    }
-    p.total = off;
-    return p;
 }
 
 int check_batch_inst(int mode, const s2d_instance &I, int32_t k) {
@@ -212,7 +130,7 @@ int eval(int op, int mode, const s2d_curves *src, const s2d_targets *trg, double
     rc = current_device(&dev);
     if (rc != S2D_OK) return rc;
     if (trg->n == 0) return S2D_OK;
-    Plan p = make_plan(op, mode, src, trg, g_dev[dev].cus);
+    Plan p = s2d::make_plan(op, mode, src, trg, g_dev[dev].cus);
     if (p.n_blocks > (int64_t)INT32_MAX)
         return fail(S2D_EINVAL, "too many target tiles x source splits for one launch (" +
                                     std::to_string(p.n_blocks) + " workgroups)");
@@ -350,7 +268,7 @@ S2D_API size_t stokes2d_workspace_size(int op, int mode, const s2d_curves *src, 
     int dev = 0;
     int cus = 256;
     if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < kMaxDev && g_dev[dev].init) cus = g_dev[dev].cus;
-    s2d::Plan p = make_plan(op, mode, src, trg, cus);
+    s2d::Plan p = s2d::make_plan(op, mode, src, trg, cus);
     return p.total > 0 ? p.total : 256;
 }
 
@@ -370,7 +288,7 @@ S2D_API int stokes2d_slp_eval_noalloc(int mode, const s2d_curves *src, const s2d
     if (rc != S2D_OK) return rc;
     void *sp = g_dev[dev].scratch;
     if (!sp) return fail(S2D_ENOINIT, "stokes2d_init() did not set up the scratch memory of this device");
-    const s2d::Plan p = make_plan(S2D_OP_SLP, mode, src, trg, g_dev[dev].cus);
+    const s2d::Plan p = s2d::make_plan(S2D_OP_SLP, mode, src, trg, g_dev[dev].cus);
     if (p.total > kScratchBytes)
         return fail(S2D_EWORKSPACE, "problem needs " + std::to_string(p.total) +
                                         " bytes of scratch; stokes2d_slp_eval_noalloc holds " +
@@ -651,6 +569,17 @@ S2D_API int ves_channel_response(const s2d_cell *cell, void *cell_ws, size_t cel
         return rc;
     const s2d_curves prx{(int64_t)M, 1, poff, px, py, nullptr, nullptr, pw, nullptr, cx, cy};
     return eval(S2D_OP_SLP, mode, &prx, &tv, d, 0, 0, mu, u_resp_x, u_resp_y, 1, ew, eb, stream);
+}
+
+S2D_API int stokes2d_valu_probe(int form, int32_t blocks, int32_t iters, float *sink, void *stream) {
+    if (form < 0 || form > 2) return fail(S2D_EINVAL, "form must be 0, 1 or 2");
+    if (blocks < 1 || blocks > (1 << 20) || iters < 1) return fail(S2D_EINVAL, "blocks in 1..2^20, iters >= 1");
+    if (!sink) return fail(S2D_EINVAL, "sink must not be NULL");
+    int dev = 0;
+    int rc = current_device(&dev);
+    if (rc != S2D_OK) return rc;
+    const hipError_t e = s2d::valu_probe_launch(form, blocks, iters, sink, (hipStream_t)stream);
+    return e == hipSuccess ? S2D_OK : hip_fail(e, "VALU probe launch");
 }
 
 S2D_API int stokes2d_profile_enable(int on) {
@@ -1159,8 +1088,8 @@ NearWallLayout near_wall_layout(int method, const s2d_curves *w, const s2d_targe
     if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < kMaxDev && g_dev[dev].init) cus = g_dev[dev].cus;
     size_t pb = 256;
     if (method == S2D_NEAR_UPSAMPLE) {
-        pb = std::max(pb, make_plan(S2D_OP_DLP, S2D_FP64, &f, t, cus).total);
-        pb = std::max(pb, make_plan(S2D_OP_DLP, S2D_FP64, w, t, cus).total);
+        pb = std::max(pb, s2d::make_plan(S2D_OP_DLP, S2D_FP64, &f, t, cus).total);
+        pb = std::max(pb, s2d::make_plan(S2D_OP_DLP, S2D_FP64, w, t, cus).total);
     } else if (method == S2D_NEAR_AUTO) {
         // the fallback targets are known only at run time: the largest plan
         // over every tile count up to all targets (the plan depends on the
@@ -1169,8 +1098,8 @@ NearWallLayout near_wall_layout(int method, const s2d_curves *w, const s2d_targe
         const int64_t tiles = ((int64_t)n + s2d::kWave - 1) / s2d::kWave;
         for (int64_t k = 1; k <= tiles; ++k) {
             tm.n = std::min<int64_t>(k * s2d::kWave, (int64_t)n);
-            pb = std::max(pb, make_plan(S2D_OP_DLP, S2D_FP64, &f, &tm, cus).total);
-            pb = std::max(pb, make_plan(S2D_OP_DLP, S2D_FP64, w, &tm, cus).total);
+            pb = std::max(pb, s2d::make_plan(S2D_OP_DLP, S2D_FP64, &f, &tm, cus).total);
+            pb = std::max(pb, s2d::make_plan(S2D_OP_DLP, S2D_FP64, w, &tm, cus).total);
         }
     }
     L.pair = o;

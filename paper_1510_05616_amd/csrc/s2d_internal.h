@@ -105,6 +105,15 @@ struct PairArgs {
 // FP32C pressures and traction evaluate near sub-blocks from FP64 records.
 constexpr bool near_fp64(int op) { return op > S2D_OP_DLP; }
 
+// bytes of one source record of (op, mode), and the launch plan of an
+// evaluation with `cus` compute units (plan.hip)
+size_t rec_bytes(int op, int mode);
+Plan make_plan(int op, int mode, const s2d_curves *s, const s2d_targets *t, int cus);
+
+// VALU issue-rate probe (probe.hip): blocks x 256 threads, each 8 FMA chains
+// of `iters` steps; sink: [blocks * 256] floats
+hipError_t valu_probe_launch(int form, int32_t blocks, int32_t iters, float *sink, hipStream_t st);
+
 // Operators whose sources are force densities g = w f (single-layer records)
 // rather than double-layer densities (nu = w n, tau).
 constexpr bool slp_sources(int op) {
