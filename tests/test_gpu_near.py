@@ -437,6 +437,16 @@ def test_auto_extremes(small):
     high = data.b >= near.B_MAX * (1 + 1e-6)
     mid = ~low & (data.b < near.B_MAX * (1 - 1e-6))
     assert high.any() and torch.all(fb[mid] == 0) and torch.all(fb[high] == 1)
+    # targets at 1e-3 h, far below the trained and calibrated range, always
+    # take the quadrature, whatever the tolerance
+    close = near.NearData(*synth.make_near_dataset(640, seed=27, per_curve=160, delta_range=(1e-3, 1.2e-3))[:4])
+    du2, dv2 = torch.empty(close.n, dtype=torch.float64, device="cuda"), torch.empty(close.n, dtype=torch.float64,
+                                                                                      device="cuda")
+    fb2 = torch.zeros(close.n, dtype=torch.int32, device="cuda")
+    for tol in (0.0, thr, 1e30):
+        close.correct(near.S2D_NEAR_AUTO, blob, tol, du2, dv2, fb2)
+        torch.cuda.synchronize()
+        assert torch.all(fb2 == 1) and torch.equal(du2, close.du) and torch.equal(dv2, close.dv)
 
 
 def test_auto_mixed_decisions_match_each_route(small):
