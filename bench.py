@@ -515,16 +515,15 @@ def step_section(prob, steps=3, dt=1e-4, kappa_b=1.0):
     return out
 
 
-def channel_section(prob, steps=2, dt=1e-4, kappa_b=1.0, p_drive=10.0, n_proxy=128, wall_nodes=8000):
-    """Algorithm 1 in the 128k channel: its walls at 2 x 8,000 nodes (the
-    dense cell system is limited to (2N)^2 < 2^31 elements; 8,000 per wall
-    still resolves every vesicle, all at least 3 wall spacings away)
-    with the 32 Gauss-Legendre side heights and 128 proxies factored once
-    (step 1, the dense 32,256-unknown periodization system), then time steps of the
-    1,000 vesicles: total membrane force (step 2), the channel's response
-    (steps 3-5: single layer on the walls and side walls, cell solve, wall
-    double layer and proxies at the 96,000 vesicle nodes), the preconditioned
-    step, update, area correction and reparameterization (steps 6-9); FP64."""
+def channel_section(prob, steps=2, dt=1e-4, kappa_b=1.0, p_drive=10.0, n_proxy=128, wall_nodes=16000):
+    """Algorithm 1 in the 128k channel: its walls at 2 x 16,000 nodes with
+    the 32 Gauss-Legendre side heights and 128 proxies factored once
+    (step 1: the dense 64,256-unknown periodization system, a blocked LU in
+    four panels), then time steps of the 1,000 vesicles: total membrane force
+    (step 2), the channel's response (steps 3-5: single layer on the walls
+    and side walls, cell solve, wall double layer and proxies at the 96,000
+    vesicle nodes), the preconditioned step, update, area correction and
+    reparameterization (steps 6-9); FP64."""
     import torch
     import synth
     from paper_1510_05616_amd import vesicle as pv
@@ -540,7 +539,7 @@ def channel_section(prob, steps=2, dt=1e-4, kappa_b=1.0, p_drive=10.0, n_proxy=1
     torch.cuda.synchronize()
     t_factor = time.time() - t0
     ves = prob.ves
-    out = {"workload": "Algorithm 1 in the 128k channel: walls at 2 x 8,000 nodes, K = 32, M = 128 (cell factored "
+    out = {"workload": f"Algorithm 1 in the 128k channel: walls at 2 x {wall_nodes:,} nodes, K = 32, M = 128 (cell factored "
                        "once), 1,000 vesicles x 96 nodes, dt = %g, kappa_B = %g, p_drive = %g per period; "
                        "response in FP64, the step solved to 1e-10 with FP64 sums (f64) or by FP32C corrections "
                        "with FP64 residuals (f32)" % (dt, kappa_b, p_drive),
@@ -568,7 +567,7 @@ def channel_section(prob, steps=2, dt=1e-4, kappa_b=1.0, p_drive=10.0, n_proxy=1
                 resp_ms.append(ev[0].elapsed_time(ev[1]))
                 its.append((it, res))
         ms = sum(step_ms) / len(step_ms)
-        log(f"channel {name}: cell factor {t_factor:.1f} s (32,256 unknowns); Algorithm 1 step {ms:.1f} ms "
+        log(f"channel {name}: cell factor {t_factor:.1f} s ({4 * wall_nodes + 2 * n_proxy:,} unknowns); Algorithm 1 step {ms:.1f} ms "
             f"(response {sum(resp_ms) / len(resp_ms):.1f} ms), GMRES {its}")
         out[name] = {"ms_per_step": ms, "value": 1e3 / ms, "unit": "time steps/s",
                      "response_ms": sum(resp_ms) / len(resp_ms), "gmres": its}
@@ -578,8 +577,8 @@ def channel_section(prob, steps=2, dt=1e-4, kappa_b=1.0, p_drive=10.0, n_proxy=1
 def cell_section(n_wall=4000, K=32, M=128, reps=5):
     """Periodization system of an empty channel cell at the paper's sizes
     (y = +-(1 + 0.3 sin x), d = 2 pi, 4000 nodes per wall, K = 32 side
-    heights, M = 128 proxies, mu = 0.7): factor (block fill, LU of the
-    16,000 x 16,000 wall block, A^-1 B, Schur complement, SVD) and solve
+    heights, M = 128 proxies, mu = 0.7): factor (block fill, blocked LU of
+    the 16,000 x 16,000 wall block, A^-1 B, Schur complement, SVD) and solve
     times, the Poiseuille test errors at (0.8, 0), (3.2, 0), (4.8, 0), and
     the FP64 oracle's dense solve at 500 nodes per wall for scale."""
     import torch
@@ -606,15 +605,15 @@ def cell_section(n_wall=4000, K=32, M=128, reps=5):
     eu = float(np.abs(un - ue).max() / (alpha * 1.3 ** 2))
     ep = float(np.abs((pn - pn[0]) - (pe - pe[0])).max() / (2 * alpha * mu * d))
     n, nc, mr = 4 * n_wall, 2 * M, 4 * K
-    # LU (2/3 n^3) + inverse from the LU (4/3 n^3) + A^-1 B + C A^-1 B
-    flops = 2.0 * n ** 3 + 2.0 * n * n * nc + 2.0 * mr * n * nc
+    # LU (2/3 n^3) + A^-1 B (two triangular sweeps) + C A^-1 B
+    flops = 2.0 / 3.0 * n ** 3 + 2.0 * n * n * nc + 2.0 * mr * n * nc
     tf = flops / t_factor / 1e12
     res = {"workload": f"empty channel y = +-(1 + 0.3 sin x), d = 2 pi, {n_wall} nodes per wall "
                        f"(system {n} + {nc} unknowns), K = {K}, M = {M}, Poiseuille data",
            "factor_s": t_factor, "solve_ms": ms_solve,
            "factor_flops": flops, "factor_tflops": tf, "peak_tflops": 78.6, "frac": tf / 78.6,
            "poiseuille_error": {"velocity": eu, "pressure": ep}}
-    log(f"cell: factor {t_factor * 1e3:.1f} ms ({tf:.1f} TFLOP/s FP64: LU and inverse), solve {ms_solve:.3f} ms, "
+    log(f"cell: factor {t_factor * 1e3:.1f} ms ({tf:.1f} TFLOP/s FP64: blocked LU), solve {ms_solve:.3f} ms, "
         f"Poiseuille error velocity {eu:.2e} pressure {ep:.2e}")
     return res
 

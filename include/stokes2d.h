@@ -214,28 +214,37 @@ S2D_API int stokes2d_slp_traction_eval(int mode, const s2d_curves *src, const s2
  * velocity differences, then the K traction differences), c [2M].  Matrices
  * are column-major with leading dimension = rows: A 2N x 2N, B 2N x 2M,
  * C 4K x 2N, Q 4K x 2M.  The pair kernels of Eqs. (D), (S), (K) and the
- * double-layer traction of Eq. (T) fill them on the GPU; LU, GEMM and SVD run
- * in rocSOLVER / rocBLAS (LU, explicit inverse, GEMM, SVD), which may
- * allocate their own device scratch.
+ * double-layer traction of Eq. (T) fill them on the GPU.  A is factored by a
+ * blocked LU with partial pivoting: column panels of lu_panel columns
+ * (rocSOLVER getrf), their row interchanges on the other columns, and
+ * rocBLAS TRSM / GEMM updates of the columns to their right; each solve
+ * permutes its right-hand side and runs the forward and backward triangular
+ * sweeps.  No library call is given an operand that spans more than 2^30
+ * elements, which bounds the panel width: at most 16,640 columns at
+ * N = 32,128, 8,192 at N = 65,536.  The libraries may allocate their own
+ * device scratch.
  * ------------------------------------------------------------------------- */
 typedef struct s2d_cell {
     s2d_curves walls;             /* the wall nodes of one period (x, y, nx, ny, w, kappa; the
-                                     densities are not used); normals point out of the fluid */
+                                     densities are not used); normals point out of the fluid;
+                                     1 <= N <= 65,536 */
     int32_t n_side;               /* K >= 1 collocation heights on each side wall */
     const double *side_y;         /* [K] device */
     double x_left;                /* L at x = x_left, R at x = x_left + d */
     int32_t n_proxy;              /* M >= 1 proxy Stokeslets, equispaced from angle 0 */
     double proxy_cx, proxy_cy, proxy_r;
     double d, mu;                 /* period > 0, viscosity > 0 */
+    int32_t lu_panel;             /* LU panel width in columns: 0 for the widest within the
+                                     2^30-element bound (a single panel when (2N)^2 fits it),
+                                     else 1 .. that width */
 } s2d_cell;
 
-/* The walls may hold at most 23,170 nodes: the dense (2N)^2 system is
- * factored through 32-bit solver interfaces whose offsets stay below 2^31
- * elements (S2D_EINVAL beyond).
+/* Limits: N <= 65,536 wall nodes, and 4K * 2N and 2M * 2N at most 2^30
+ * (S2D_EINVAL beyond).
  *
- * Workspace bytes of a factored cell (0 on bad arguments): A^-1 (formed
- * once, so that each solve is matrix-vector products), B, A^-1 B, C, the
- * pseudo-inverse of S and scratch, about (2N)^2 * 8 bytes. */
+ * Workspace bytes of a factored cell (0 on bad arguments): the LU factors of
+ * A (2N)^2 * 8 bytes, B, A^-1 B, C, the pseudo-inverse of S, the pivots, the
+ * solves' row permutation and scratch. */
 S2D_API size_t stokes2d_cell_workspace_size(const s2d_cell *cell);
 
 /* Fills the four blocks into caller buffers (any may be NULL to skip). */

@@ -20,7 +20,7 @@ class _Cell(ctypes.Structure):
     _fields_ = [("walls", _Curves), ("n_side", ctypes.c_int32), ("side_y", ctypes.c_void_p),
                 ("x_left", ctypes.c_double), ("n_proxy", ctypes.c_int32), ("proxy_cx", ctypes.c_double),
                 ("proxy_cy", ctypes.c_double), ("proxy_r", ctypes.c_double), ("d", ctypes.c_double),
-                ("mu", ctypes.c_double)]
+                ("mu", ctypes.c_double), ("lu_panel", ctypes.c_int32)]
 
 
 _bound = False
@@ -47,9 +47,10 @@ class Cell:
     """One period of a channel: wall curves (a CurveSet, or anything with x,
     y, nx, ny, w, kappa, curve_off), the K side-wall heights, period d, M
     proxy Stokeslets on the circle of radius proxy_r (default d) around the
-    cell centre, viscosity mu.  Holds the factored system after factor()."""
+    cell centre, viscosity mu; lu_panel: columns per LU panel (0: the widest
+    the library calls allow).  Holds the factored system after factor()."""
 
-    def __init__(self, walls, side_y, d, n_proxy, mu, x_left=0.0, proxy_r=None, device="cuda"):
+    def __init__(self, walls, side_y, d, n_proxy, mu, x_left=0.0, proxy_r=None, device="cuda", lu_panel=0):
         self.walls = Curves(walls, device)
         self.side_y = _dev_f64(side_y, device)
         sy = np.asarray(side_y, dtype=np.float64)
@@ -60,6 +61,7 @@ class Cell:
         self.proxy_cy = 0.5 * (float(sy.min()) + float(sy.max()))
         self.proxy_r = self.d if proxy_r is None else float(proxy_r)
         self.device = device
+        self.lu_panel = int(lu_panel)
         self.ws = None
 
     @property
@@ -68,7 +70,7 @@ class Cell:
 
     def struct(self):
         return _Cell(self.walls.struct(), self.K, _ptr(self.side_y), self.x_left, self.M, self.proxy_cx,
-                     self.proxy_cy, self.proxy_r, self.d, self.mu)
+                     self.proxy_cy, self.proxy_r, self.d, self.mu, self.lu_panel)
 
     def workspace_size(self) -> int:
         s = self.struct()

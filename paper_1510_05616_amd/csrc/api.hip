@@ -1,6 +1,7 @@
 // C ABI of libstokes2d: argument checks, launch planning, workspace carve-up
 // and the launch sequence for each evaluation.  No allocation happens here:
 // all scratch lives in the caller's workspace.
+#include "lu_plan.h"
 #include "s2d_internal.h"
 #include "s2d_near.h"
 #include "../../include/stokes2d_vesicle.h"
@@ -333,12 +334,7 @@ namespace {
 int check_cell(const s2d_cell *c, s2d::CellArgs *g) {
     if (!c) return fail(S2D_EINVAL, "cell must not be NULL");
     const s2d_curves &w = c->walls;
-    // the dense factor and solve go through rocSOLVER's and rocBLAS's 32-bit
-    // (rocblas_int) interfaces, whose matrix offsets must stay below 2^31
-    // elements: (2N)^2 < 2^31, N <= 23,170 wall nodes
-    if (w.n_nodes < 1 || w.n_nodes > 23170)
-        return fail(S2D_EINVAL, "cell walls: n_nodes must be in 1..23170 (the dense (2N)^2 system must stay below "
-                                "2^31 elements for the 32-bit solver interface)");
+    if (w.n_nodes < 1 || w.n_nodes > 65536) return fail(S2D_EINVAL, "cell walls: n_nodes must be in 1..65536");
     if (!w.x || !w.y || !w.nx || !w.ny || !w.w || !w.kappa)
         return fail(S2D_EINVAL, "cell walls need x, y, nx, ny, w and kappa");
     if (c->n_side < 1 || c->n_side > 4096 || !c->side_y) return fail(S2D_EINVAL, "cell: n_side in 1..4096 and side_y set");
@@ -364,6 +360,16 @@ int check_cell(const s2d_cell *c, s2d::CellArgs *g) {
     g->R = c->proxy_r;
     g->d = c->d;
     g->mu = c->mu;
+    // the blocked LU keeps every library operand within lu::kMaxSpan
+    // elements; the blocks C (4K x 2N) and X (2N x 2M) go to the libraries
+    // whole and must fit it too
+    const int64_t n = 2 * w.n_nodes;
+    if (4 * (int64_t)c->n_side * n > s2d::lu::kMaxSpan || 2 * (int64_t)c->n_proxy * n > s2d::lu::kMaxSpan)
+        return fail(S2D_EINVAL, "cell: 4 n_side * 2 n_nodes and 2 n_proxy * 2 n_nodes must be at most 2^30");
+    g->panel = s2d::lu::panel_width(n, s2d::lu::kMaxSpan, c->lu_panel);
+    if (g->panel < 1)
+        return fail(S2D_EINVAL, "cell: lu_panel must be 0 or in 1.." +
+                                    std::to_string(s2d::lu::panel_width(n, s2d::lu::kMaxSpan, 0)));
     return S2D_OK;
 }
 

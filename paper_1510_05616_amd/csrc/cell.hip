@@ -13,10 +13,14 @@
 // (BIEgT)).
 //
 // The four blocks are filled by one kernel each (one thread per 2 x 2 node
-// block, column-major for the solver).  Factor: LU of A^T and the explicit
-// inverse (A^-1)^T (rocSOLVER), X = A^-1 B, S = Q - C X (rocBLAS GEMM), SVD of the
-// small S and its truncated pseudo-inverse.  Solve (matrix-vector products
-// only): y = A^-1 v, c = S^+ (g - C y), tau = y - X c.
+// block, column-major for the solver).  Factor: blocked LU of A with partial
+// pivoting (rocSOLVER panels, rocBLAS TRSM / GEMM updates, row interchanges
+// by a kernel of its own; the call schedule in lu_plan.h keeps every library
+// operand within 2^30 elements), X = A^-1 B by the triangular sweeps,
+// S = Q - C X (GEMM), SVD of the small S and its truncated pseudo-inverse.
+// Solve: y = A^-1 v (row permutation, forward and backward sweeps),
+// c = S^+ (g - C y), tau = y - X c.
+#include "lu_plan.h"
 #include "s2d_internal.h"
 
 #include <rocblas/rocblas.h>
@@ -26,6 +30,7 @@
 #include <cmath>
 #include <mutex>
 #include <string>
+#include <vector>
 
 namespace s2d {
 
@@ -98,7 +103,7 @@ __device__ __forceinline__ void put(double *A, int64_t ld, int64_t row0, int64_t
 }
 
 // A: -1/2 I + sum_{|n| <= 1} D(x_i, y_j + n d) w_j, diagonal limit at n = 0
-__global__ __launch_bounds__(256) void cell_fill_A(CellArgs g, double *A, int transpose) {
+__global__ __launch_bounds__(256) void cell_fill_A(CellArgs g, double *A) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t N = g.n_wall;
     if (t >= N * N) return;
@@ -124,12 +129,7 @@ __global__ __launch_bounds__(256) void cell_fill_A(CellArgs g, double *A, int tr
         acc[0] -= 0.5;
         acc[3] -= 0.5;
     }
-    if (transpose) {
-        const double tr[4] = {acc[0], acc[2], acc[1], acc[3]};
-        put(A, 2 * N, 2 * j, 2 * i, tr);
-    } else {
-        put(A, 2 * N, 2 * i, 2 * j, acc);
-    }
+    put(A, 2 * N, 2 * i, 2 * j, acc);
 }
 
 // B: the proxy Stokeslets at the wall nodes
@@ -203,9 +203,46 @@ __global__ __launch_bounds__(256) void cell_pinv(int m, int n, int r, const doub
     P[j + (int64_t)i * n] = acc;
 }
 
+// the row interchanges of one LU panel on columns of T (column c at
+// T + c ld): for i < k in order, rows i and ipiv[i] - 1 (1-based, relative to
+// T's first row), skipping pivots outside the m rows; one thread per column,
+// the pivots staged through LDS
+__global__ __launch_bounds__(64) void lu_laswp(double *T, int64_t ld, int64_t cols, int64_t m, const int32_t *ipiv,
+                                               int64_t k) {
+    __shared__ int32_t sp[1024];
+    const int64_t c = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    double *col = T + (c < cols ? c : 0) * ld;
+    for (int64_t i0 = 0; i0 < k; i0 += 1024) {
+        const int cnt = (int)(k - i0 < 1024 ? k - i0 : 1024);
+        __syncthreads();
+        for (int t = threadIdx.x; t < cnt; t += 64) sp[t] = ipiv[i0 + t] - 1;
+        __syncthreads();
+        if (c >= cols) continue;
+        for (int t = 0; t < cnt; ++t) {
+            const int64_t i = i0 + t, r = sp[t];
+            if (r == i || r < 0 || r >= m) continue;
+            const double a = col[i];
+            col[i] = col[r];
+            col[r] = a;
+        }
+    }
+}
+
+// out[i + j ldo] = in[perm[i] + j ldi], i < n, j < nrhs (NaN for an index
+// outside 0..n-1, as in a workspace that was never factored)
+__global__ __launch_bounds__(256) void lu_gather(int64_t n, int64_t nrhs, const double *in, int64_t ldi,
+                                                 const int32_t *perm, double *out, int64_t ldo) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * nrhs) return;
+    const int64_t i = t % n, j = t / n, p = perm[i];
+    out[i + j * ldo] = p >= 0 && p < n ? in[p + j * ldi] : __builtin_nan("");
+}
+
 unsigned grid(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
+
+int64_t cell_panels(const CellArgs &g) { return g.panel < 1 ? 0 : (2 * g.n_wall + g.panel - 1) / g.panel; }
 
 CellLayout cell_layout(const CellArgs &g) {
     CellLayout L{};
@@ -226,14 +263,15 @@ CellLayout cell_layout(const CellArgs &g) {
     L.y = off;    off = al(off + (size_t)n * 8);
     L.rr = off;   off = al(off + (size_t)mr * 8);
     L.ipiv = off; off = al(off + (size_t)n * 4);
-    L.info = off; off = al(off + 3 * 4);
+    L.perm = off; off = al(off + (size_t)n * 4);
+    L.info = off; off = al(off + (size_t)(cell_panels(g) + 1) * 4);
     L.total = off;
     return L;
 }
 
-hipError_t cell_fill(const CellArgs &g, double *A, double *B, double *C, double *Q, hipStream_t st, bool a_transposed) {
+hipError_t cell_fill(const CellArgs &g, double *A, double *B, double *C, double *Q, hipStream_t st) {
     const int64_t N = g.n_wall;
-    if (A && N > 0) hipLaunchKernelGGL(cell_fill_A, dim3(grid(N * N)), dim3(256), 0, st, g, A, a_transposed ? 1 : 0);
+    if (A && N > 0) hipLaunchKernelGGL(cell_fill_A, dim3(grid(N * N)), dim3(256), 0, st, g, A);
     if (B && N > 0 && g.M > 0) hipLaunchKernelGGL(cell_fill_B, dim3(grid(N * g.M)), dim3(256), 0, st, g, B);
     if (C && N > 0 && g.K > 0) hipLaunchKernelGGL(cell_fill_C, dim3(grid(g.K * N)), dim3(256), 0, st, g, C);
     if (Q && g.K > 0 && g.M > 0) hipLaunchKernelGGL(cell_fill_Q, dim3(grid((int64_t)g.K * g.M)), dim3(256), 0, st, g, Q);
@@ -372,6 +410,71 @@ std::mutex &blas_mutex() { return g_hmu; }
 
 void *blas_handle(hipStream_t st, std::string &err) { return (void *)handle_for(st, err); }
 
+namespace {
+
+// rows of a single right-hand side's sweep blocks (TRSV + GEMV per block)
+constexpr int64_t kSolveBlock = 8192;
+
+// the calls of an LU schedule (lu_plan.h): F is the n x n factored matrix
+// (ld n), T the target (F itself when factoring), ldt its leading dimension
+std::string lu_run(rocblas_handle h, const std::vector<lu::Call> &plan, double *F, int64_t n, double *T,
+                   int64_t ldt, int32_t *ipiv, int32_t *info, hipStream_t st) {
+    const double one = 1.0, minus_one = -1.0;
+    const rocblas_int ld = (rocblas_int)n, lt = (rocblas_int)ldt;
+    for (const lu::Call &c : plan) {
+        rocblas_status s = rocblas_status_success;
+        const rocblas_int m = (rocblas_int)c.m, nn = (rocblas_int)c.n, k = (rocblas_int)c.k;
+        switch (c.op) {
+            case lu::kGetrf:
+                s = rocsolver_dgetrf(h, m, nn, F + c.a, ld, ipiv + c.piv, info + c.slot);
+                if (s != rocblas_status_success) return rb_err("rocsolver_dgetrf", s);
+                break;
+            case lu::kLaswp: {
+                hipLaunchKernelGGL(lu_laswp, dim3((unsigned)((c.n + 63) / 64)), dim3(64), 0, st, T + c.b, ldt, c.n,
+                                   c.m, ipiv + c.piv, c.k);
+                const hipError_t e = hipGetLastError();
+                if (e != hipSuccess) return std::string("lu_laswp: ") + hipGetErrorString(e);
+                break;
+            }
+            case lu::kTrsm: {
+                const rocblas_fill fill = c.upper ? rocblas_fill_upper : rocblas_fill_lower;
+                const rocblas_diagonal diag = c.upper ? rocblas_diagonal_non_unit : rocblas_diagonal_unit;
+                if (c.n == 1) {
+                    s = rocblas_dtrsv(h, fill, rocblas_operation_none, diag, m, F + c.a, ld, T + c.b, 1);
+                    if (s != rocblas_status_success) return rb_err("rocblas_dtrsv", s);
+                } else {
+                    s = rocblas_dtrsm(h, rocblas_side_left, fill, rocblas_operation_none, diag, m, nn, &one, F + c.a,
+                                      ld, T + c.b, lt);
+                    if (s != rocblas_status_success) return rb_err("rocblas_dtrsm", s);
+                }
+                break;
+            }
+            case lu::kGemm:
+                if (c.n == 1) {
+                    s = rocblas_dgemv(h, rocblas_operation_none, m, k, &minus_one, F + c.a, ld, T + c.b, 1, &one,
+                                      T + c.c, 1);
+                    if (s != rocblas_status_success) return rb_err("rocblas_dgemv", s);
+                } else {
+                    s = rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, m, nn, k, &minus_one,
+                                      F + c.a, ld, T + c.b, lt, &one, T + c.c, lt);
+                    if (s != rocblas_status_success) return rb_err("rocblas_dgemm", s);
+                }
+                break;
+            default:
+                return "unknown LU call";
+        }
+    }
+    return "";
+}
+
+hipError_t gather_launch(int64_t n, int64_t nrhs, const double *in, int64_t ldi, const int32_t *perm, double *out,
+                         int64_t ldo, hipStream_t st) {
+    hipLaunchKernelGGL(lu_gather, dim3(grid(n * nrhs)), dim3(256), 0, st, n, nrhs, in, ldi, perm, out, ldo);
+    return hipGetLastError();
+}
+
+}  // namespace
+
 std::string cell_factor(const CellArgs &g, double rcond, void *ws, hipStream_t st) {
     const CellLayout L = cell_layout(g);
     char *b = (char *)ws;
@@ -379,41 +482,56 @@ std::string cell_factor(const CellArgs &g, double rcond, void *ws, hipStream_t s
     double *S = (double *)(b + L.S);
     double *U = (double *)(b + L.U), *Vt = (double *)(b + L.Vt), *sv = (double *)(b + L.sv), *E = (double *)(b + L.E);
     double *P = (double *)(b + L.P);
-    rocblas_int *ipiv = (rocblas_int *)(b + L.ipiv), *info = (rocblas_int *)(b + L.info);
-    const rocblas_int n = (rocblas_int)(2 * g.n_wall), nc = 2 * g.M, mr = 4 * g.K, r = std::min(mr, nc);
-    hipError_t e = cell_fill(g, A, B, C, S, st, true);    // A^T, and Q into S
+    int32_t *ipiv = (int32_t *)(b + L.ipiv), *perm = (int32_t *)(b + L.perm), *info = (int32_t *)(b + L.info);
+    const int64_t n = 2 * g.n_wall, np = cell_panels(g);
+    const rocblas_int nc = 2 * g.M, mr = 4 * g.K, r = std::min(mr, nc);
+    if (g.panel < 1 || lu::panel_width(n, lu::kMaxSpan, g.panel) != g.panel) return "cell: bad LU panel width";
+    hipError_t e = cell_fill(g, A, B, C, S, st);    // Q into S
     if (e != hipSuccess) return std::string("cell fill: ") + hipGetErrorString(e);
     std::lock_guard<std::mutex> lk(g_hmu);
     std::string err;
     rocblas_handle h = handle_for(st, err);
     if (!h) return err;
-    // (A^T)^-1 = (A^-1)^T is formed once from the LU of A^T: every later
-    // solve is then matrix-vector products, and with the inverse stored
-    // transposed they read its rows contiguously (a triangular solve per
-    // right-hand side is latency-bound at this size)
-    rocblas_status s = rocsolver_dgetrf(h, n, n, A, n, ipiv, info);
-    if (s != rocblas_status_success) return rb_err("rocsolver_dgetrf", s);
-    s = rocsolver_dgetri(h, n, A, n, ipiv, info + 2);
-    if (s != rocblas_status_success) return rb_err("rocsolver_dgetri", s);
-    const double one = 1.0, minus_one = -1.0, zero = 0.0;
-    s = rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, n, nc, n, &one, A, n, B, n, &zero, X,
-                      n);                                                             // X = A^-1 B
-    if (s != rocblas_status_success) return rb_err("rocblas_dgemm", s);
-    s = rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, mr, nc, n, &minus_one, C, mr, X, n, &one, S,
-                      mr);                                                            // S = Q - C X
+    err = lu_run(h, lu::factor_plan(n, g.panel, lu::kMaxSpan), A, n, A, n, ipiv, info, st);
+    if (!err.empty()) return err;
+    // the solves' row permutation: the panels' interchanges in order
+    std::vector<int32_t> hp((size_t)n), hinfo((size_t)np + 1, 0);
+    e = hipMemcpyAsync(hp.data(), ipiv, (size_t)n * 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(hinfo.data(), info, (size_t)np * 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return std::string("cell factor: ") + hipGetErrorString(e);
+    for (int64_t p = 0; p < np; ++p)
+        if (hinfo[(size_t)p] != 0)
+            return "the wall block A is singular (LU pivot " + std::to_string(p * g.panel + hinfo[(size_t)p]) +
+                   " is zero)";
+    std::vector<int32_t> pm((size_t)n);
+    for (int64_t i = 0; i < n; ++i) pm[(size_t)i] = (int32_t)i;
+    for (int64_t k = 0; k < n; k += g.panel)
+        for (int64_t i = k; i < std::min(n, k + g.panel); ++i) {
+            const int64_t q = k + hp[(size_t)i] - 1;
+            if (q < k || q >= n) return "cell factor: pivot out of range";
+            std::swap(pm[(size_t)i], pm[(size_t)q]);
+        }
+    e = hipMemcpyAsync(perm, pm.data(), (size_t)n * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = gather_launch(n, nc, B, n, perm, X, n, st);            // P B
+    if (e != hipSuccess) return std::string("cell factor: ") + hipGetErrorString(e);
+    err = lu_run(h, lu::solve_plan(n, nc, n, g.panel, lu::kMaxSpan), A, n, X, n, ipiv, info, st);  // X = A^-1 B
+    if (!err.empty()) return err;
+    const double one = 1.0, minus_one = -1.0;
+    rocblas_status s = rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, mr, nc, (rocblas_int)n,
+                                     &minus_one, C, mr, X, (rocblas_int)n, &one, S, mr);    // S = Q - C X
     if (s != rocblas_status_success) return rb_err("rocblas_dgemm", s);
     s = rocsolver_dgesvd(h, rocblas_svect_singular, rocblas_svect_singular, mr, nc, S, mr, sv, U, mr, Vt, r, E,
-                         rocblas_outofplace, info + 1);
+                         rocblas_outofplace, info + np);
     if (s != rocblas_status_success) return rb_err("rocsolver_dgesvd", s);
     e = cell_pinv_launch(mr, nc, sv, U, Vt, rcond, P, st);
     if (e != hipSuccess) return std::string("cell pinv: ") + hipGetErrorString(e);
-    rocblas_int hinfo[3] = {0, 0, 0};
-    e = hipMemcpyAsync(hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, st);
+    int32_t svd_info = 0;
+    e = hipMemcpyAsync(&svd_info, info + np, 4, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return std::string("cell factor: ") + hipGetErrorString(e);
-    if (hinfo[0] != 0 || hinfo[2] != 0)
-        return "the wall block A is singular (LU pivot " + std::to_string(std::max(hinfo[0], hinfo[2])) + " is zero)";
-    if (hinfo[1] != 0) return "the SVD of the Schur complement did not converge";
+    if (svd_info != 0) return "the SVD of the Schur complement did not converge";
     return "";
 }
 
@@ -423,23 +541,29 @@ std::string cell_solve(const CellArgs &g, const double *v, const double *gv, dou
     char *b = (char *)ws;
     double *A = (double *)(b + L.A), *X = (double *)(b + L.X), *C = (double *)(b + L.C), *P = (double *)(b + L.P);
     double *y = (double *)(b + L.y), *rr = (double *)(b + L.rr);
-    const rocblas_int n = (rocblas_int)(2 * g.n_wall), nc = 2 * g.M, mr = 4 * g.K;
+    int32_t *ipiv = (int32_t *)(b + L.ipiv), *perm = (int32_t *)(b + L.perm), *info = (int32_t *)(b + L.info);
+    const int64_t n = 2 * g.n_wall;
+    const rocblas_int nc = 2 * g.M, mr = 4 * g.K;
     hipError_t e = hipMemcpyAsync(rr, gv, (size_t)mr * 8, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = gather_launch(n, 1, v, n, perm, y, n, st);                 // P v
     if (e != hipSuccess) return std::string("cell solve: ") + hipGetErrorString(e);
     std::lock_guard<std::mutex> lk(g_hmu);
     std::string err;
     rocblas_handle h = handle_for(st, err);
     if (!h) return err;
+    err = lu_run(h, lu::solve_plan(n, 1, n, std::min(kSolveBlock, g.panel), lu::kMaxSpan), A, n, y, n, ipiv, info,
+                 st);                                                                    // y = A^-1 v
+    if (!err.empty()) return err;
     const double one = 1.0, minus_one = -1.0, zero = 0.0;
-    rocblas_status s = rocblas_dgemv(h, rocblas_operation_transpose, n, n, &one, A, n, v, 1, &zero, y, 1);  // A^-1 v
-    if (s != rocblas_status_success) return rb_err("rocblas_dgemv", s);
-    s = rocblas_dgemv(h, rocblas_operation_none, mr, n, &minus_one, C, mr, y, 1, &one, rr, 1);     // g - C y
+    rocblas_status s = rocblas_dgemv(h, rocblas_operation_none, mr, (rocblas_int)n, &minus_one, C, mr, y, 1, &one,
+                                     rr, 1);                                             // g - C y
     if (s != rocblas_status_success) return rb_err("rocblas_dgemv", s);
     s = rocblas_dgemv(h, rocblas_operation_none, nc, mr, &one, P, nc, rr, 1, &zero, c, 1);         // c = S^+ (.)
     if (s != rocblas_status_success) return rb_err("rocblas_dgemv", s);
     e = hipMemcpyAsync(tau, y, (size_t)n * 8, hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return std::string("cell solve: ") + hipGetErrorString(e);
-    s = rocblas_dgemv(h, rocblas_operation_none, n, nc, &minus_one, X, n, c, 1, &one, tau, 1);     // y - X c
+    s = rocblas_dgemv(h, rocblas_operation_none, (rocblas_int)n, nc, &minus_one, X, (rocblas_int)n, c, 1, &one, tau,
+                      1);                                                                // y - X c
     if (s != rocblas_status_success) return rb_err("rocblas_dgemv", s);
     return "";
 }

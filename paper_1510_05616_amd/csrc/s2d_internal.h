@@ -42,14 +42,17 @@ struct CellArgs {
     int32_t M;                                        // proxy Stokeslets
     double cx, cy, R;                                 // proxy circle
     double d, mu;
+    int64_t panel;                                    // LU panel width (columns)
 };
-// workspace of a factored cell (byte offsets)
+// workspace of a factored cell (byte offsets): A holds the LU factors, ipiv
+// the panels' pivots, perm the row permutation of the solves, info the
+// panels' LU status then the SVD's
 struct CellLayout {
-    size_t A, B, X, C, S, U, Vt, sv, E, P, y, rr, ipiv, info, total;
+    size_t A, B, X, C, S, U, Vt, sv, E, P, y, rr, ipiv, perm, info, total;
 };
 CellLayout cell_layout(const CellArgs &g);
-hipError_t cell_fill(const CellArgs &g, double *A, double *B, double *C, double *Q, hipStream_t st,
-                     bool a_transposed = false);
+int64_t cell_panels(const CellArgs &g);
+hipError_t cell_fill(const CellArgs &g, double *A, double *B, double *C, double *Q, hipStream_t st);
 hipError_t cell_pinv_launch(int m, int n, const double *sv, const double *U, const double *Vt, double rcond,
                             double *P, hipStream_t st);
 // data of the channel's response to vesicles (cell.hip)

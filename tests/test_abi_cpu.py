@@ -2,6 +2,7 @@
 every entry point declared in include/stokes2d.h, and rejects bad arguments
 (before touching the device) with the documented status codes."""
 import ctypes
+from pathlib import Path
 import os
 import re
 
@@ -148,16 +149,93 @@ def test_cell_argument_checks(L):
         setattr(bad, field, value)
         assert L.stokes2d_cell_workspace_size(by(bad)) == 0, field
         assert L.stokes2d_cell_factor(by(bad), 1e-8, fake, 1 << 30, None) == s2d.S2D_EINVAL, field
-    big = s2d._Curves(23171, 2, fake, fake, fake, fake, fake, fake, fake, fake, fake)   # (2N)^2 >= 2^31
+    big = s2d._Curves(65537, 2, fake, fake, fake, fake, fake, fake, fake, fake, fake)
     assert L.stokes2d_cell_workspace_size(by(pc._Cell(big, 8, fake, 0.0, 32, 3.0, 0.0, 6.0, 6.0, 0.7))) == 0
     assert L.stokes2d_cell_factor(by(pc._Cell(big, 8, fake, 0.0, 32, 3.0, 0.0, 6.0, 6.0, 0.7)), 1e-8, fake,
                                   1 << 40, None) == s2d.S2D_EINVAL
-    assert "23170" in s2d.stokes2d_last_error()
+    assert "65536" in s2d.stokes2d_last_error()
+    # LU panel width: 0 (widest), 1 .. widest; C and X within 2^30 elements
+    for panel, ok in ((0, True), (1, True), (128, True), (128 + 1, False), (-1, False)):
+        c = pc._Cell(walls, 8, fake, 0.0, 32, 3.0, 0.0, 6.0, 6.0, 0.7, panel)
+        assert (L.stokes2d_cell_workspace_size(by(c)) > 0) == ok, panel
+    wide = s2d._Curves(65536, 2, fake, fake, fake, fake, fake, fake, fake, fake, fake)
+    for K, M, ok in ((8, 32, True), (4096, 32, False), (8, 8192, False)):
+        c = pc._Cell(wide, K, fake, 0.0, M, 3.0, 0.0, 6.0, 6.0, 0.7)
+        assert (L.stokes2d_cell_workspace_size(by(c)) > 0) == ok, (K, M)
     nok = s2d._Curves(64, 2, fake, fake, fake, fake, fake, fake, None, fake, fake)     # no kappa
     assert L.stokes2d_cell_workspace_size(by(pc._Cell(nok, 8, fake, 0.0, 32, 3.0, 0.0, 6.0, 6.0, 0.7))) == 0
     assert L.stokes2d_cell_factor(by(good), 1.5, fake, 1 << 30, None) == s2d.S2D_EINVAL     # rcond
     assert L.stokes2d_cell_factor(by(good), 1e-8, fake, 16, None) == s2d.S2D_EWORKSPACE
     assert L.stokes2d_cell_solve(by(good), None, fake, fake, fake, fake, 1 << 30, None) == s2d.S2D_EINVAL
+
+
+def _cell_layout_bytes(N, K, M, panel):
+    """The cell workspace written out in 64-bit integers: each block rounded
+    up to 256 bytes, in the order A, B, X, C, S, U, Vt, sv, E, P, y, rr,
+    pivots, permutation, LU status per panel + the SVD's."""
+    n, nc, mr = 2 * N, 2 * M, 4 * K
+    r = min(mr, nc)
+    sizes = [n * n * 8, n * nc * 8, n * nc * 8, mr * n * 8, mr * nc * 8, mr * r * 8, r * nc * 8, r * 8, r * 8,
+             nc * mr * 8, n * 8, mr * 8, n * 4, n * 4, (-(-n // panel) + 1) * 4]
+    return sum(-(-b // 256) * 256 for b in sizes)
+
+
+@pytest.mark.parametrize("N,panel", [(32128, 16640), (65536, 8192), (4000, 8000), (23171, 23040)])
+def test_cell_workspace_at_the_largest_walls(L, N, panel):
+    """The workspace of cells whose dense block has more than 2^31 elements
+    (2 x 16,064 and 2 x 32,768 wall nodes): sizes and offsets in 64 bits, and
+    the widest LU panel is the one the plan check below uses."""
+    import paper_1510_05616_amd as s2d
+    from paper_1510_05616_amd import cell as pc
+    pc._bind()
+    fake = ctypes.c_void_p(0x1000)
+    walls = s2d._Curves(N, 2, fake, fake, fake, fake, fake, fake, fake, fake, fake)
+    c = pc._Cell(walls, 32, fake, 0.0, 128, 3.0, 0.0, 6.0, 6.0, 0.7)
+    assert L.stokes2d_cell_workspace_size(ctypes.byref(c)) == _cell_layout_bytes(N, 32, 128, panel)
+    c.lu_panel = panel
+    assert L.stokes2d_cell_workspace_size(ctypes.byref(c)) == _cell_layout_bytes(N, 32, 128, panel)
+    c.lu_panel = panel + 1
+    assert L.stokes2d_cell_workspace_size(ctypes.byref(c)) == 0
+
+
+@pytest.fixture(scope="module")
+def lu_check(tmp_path_factory):
+    """The host check of the blocked LU schedule, compiled with g++."""
+    import shutil
+    import subprocess
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not found")
+    exe = tmp_path_factory.mktemp("lu") / "lu_plan_check"
+    src = Path(__file__).with_name("lu_plan_check.cpp")
+    subprocess.run([gxx, "-O2", "-std=c++17", "-Wall", "-Werror", "-o", str(exe), str(src)], check=True)
+
+    def run(*args):
+        p = subprocess.run([str(exe), *map(str, args)], capture_output=True, text=True, timeout=120)
+        assert p.returncode == 0 and p.stdout.startswith("OK"), p.stdout + p.stderr
+        return p.stdout
+    return run
+
+
+@pytest.mark.parametrize("n,S,nrhs", [(64256, 16640, 256), (64256, 8192, 1), (131072, 8192, 256),
+                                       (131072, 8192, 1), (46340, 8192, 1)])
+def test_lu_schedule_offsets_at_full_size(lu_check, n, S, nrhs):
+    """Every call of the factor and solve schedules of a 64,256^2 and a
+    131,072^2 system (config-3 and the largest walls) addresses at most 2^30
+    elements from its operand's base and stays inside its buffer."""
+    out = lu_check("check", n, 1 << 30, 0, S, nrhs)
+    if n > 46340:
+        assert int(out.split(" W ")[1].split()[0]) < n          # several panels
+
+
+@pytest.mark.parametrize("n,lim,W,S,nrhs,seed", [(60, 1000, 0, 7, 1, 1), (60, 1000, 0, 7, 5, 2),
+                                                 (97, 2500, 0, 9, 3, 3), (200, 1 << 31, 0, 50, 2, 4),
+                                                 (200, 1 << 31, 64, 50, 2, 5), (150, 4000, 13, 11, 1, 6),
+                                                 (301, 40000, 0, 40, 4, 7), (1, 1, 0, 1, 1, 8)])
+def test_lu_schedule_solves(lu_check, n, lim, W, S, nrhs, seed):
+    """The schedule at small bounds (narrow panels, chunked operands) run with
+    plain loops: the same pivots and solution as unblocked elimination."""
+    lu_check("run", n, lim, W, S, nrhs, seed)
 
 
 def test_wall_argument_checks(L):

@@ -37,11 +37,11 @@ def test_blocks_match_the_oracle():
         assert e < 1e-13, name
 
 
-def _solve(Nw, K, M, alpha=ALPHA):
+def _solve(Nw, K, M, alpha=ALPHA, lu_panel=0):
     import torch
     from paper_1510_05616_amd.cell import Cell
     walls, sy, d = synth.make_channel(Nw, K)
-    cell = Cell(walls, sy, d, M, MU)
+    cell = Cell(walls, sy, d, M, MU, lu_panel=lu_panel)
     cell.factor()
     v, g = synth.poiseuille_cell_data(walls, sy, d, alpha, MU)
     f64 = dict(dtype=torch.float64, device="cuda")
@@ -109,3 +109,54 @@ def test_larger_channel_both_evaluation_modes(mode):
     eu, ep = _errors(u, v, p, d)
     print(f"N=2x1000 mode={mode}: velocity {eu:.2e}, pressure {ep:.2e}", flush=True)
     assert max(eu, ep) < (1e-10 if mode == 0 else 1e-6)
+
+
+def test_narrow_lu_panels_give_the_same_flow():
+    """The blocked LU with narrow panels (many rocSOLVER panels, row
+    interchanges across panels, TRSM / GEMM updates cut into column chunks)
+    against the single-panel factorisation and the oracle's dense solve."""
+    import torch
+    from oracle import els
+    fields = {}
+    for panel in (0, 100, 37):
+        walls, sy, d, cell, tau, c = _solve(300, 16, 64, lu_panel=panel)
+        u, v, p = cell.flow(tau, c, *PTS)
+        eu, ep = _errors(u, v, p, d)
+        # the first block row holds to rounding: tau = A^-1 (v - B c)
+        A, B, _, _ = cell.assemble()
+        vv, _ = synth.poiseuille_cell_data(walls, sy, d, ALPHA, MU)
+        vt = torch.as_tensor(vv, dtype=torch.float64, device="cuda")
+        res = (A @ tau + B @ c - vt).abs().max().item()
+        scale = (A.abs().sum(1).max() * tau.abs().max() + B.abs().sum(1).max() * c.abs().max()).item()
+        print(f"lu_panel {panel}: velocity {eu:.2e}, pressure {ep:.2e}, A tau + B c - v {res / scale:.2e}",
+              flush=True)
+        assert eu < 1e-10 and ep < 1e-10, panel
+        assert res < 1e-14 * scale, panel
+        fields[panel] = np.stack([u.cpu().numpy(), v.cpu().numpy()], 1)
+    # the truncated pseudo-inverse passes rounding differences of S on to c
+    # (the dropped directions), so the fields agree to the method's accuracy
+    for panel in (100, 37):
+        assert np.abs(fields[panel] - fields[0]).max() < 1e-10 * ALPHA, panel
+    A, B, C, Q, (px, py) = els.assemble(walls, sy, d, 64, MU)
+    vv, gg = synth.poiseuille_cell_data(walls, sy, d, ALPHA, MU)
+    t_o, c_o = els.solve(A, B, C, Q, vv, gg)
+    uo, _ = els.field(walls, t_o, px, py, c_o, d, MU, *PTS)
+    assert np.abs(fields[37] - uo).max() < 1e-10 * ALPHA
+
+
+def test_poiseuille_at_16000_nodes_per_wall():
+    """The cell at 2 x 16,000 wall nodes (a 64,000^2 dense block, 4.1e9
+    elements, factored in four panels of at most 16,640 columns): the
+    Poiseuille flow at the test points."""
+    import time
+    import torch
+    t0 = time.time()
+    walls, sy, d, cell, tau, c = _solve(16000, 32, 128)
+    torch.cuda.synchronize()
+    t1 = time.time()
+    u, v, p = cell.flow(tau, c, *PTS)
+    eu, ep = _errors(u, v, p, d)
+    print(f"N=2x16000: factor + solve {t1 - t0:.1f} s, velocity {eu:.2e}, pressure {ep:.2e}", flush=True)
+    assert eu < 1e-9 and ep < 1e-9
+    del cell
+    torch.cuda.empty_cache()
