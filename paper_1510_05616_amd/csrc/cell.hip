@@ -238,6 +238,111 @@ __global__ __launch_bounds__(256) void lu_gather(int64_t n, int64_t nrhs, const 
     out[i + j * ldo] = p >= 0 && p < n ? in[p + j * ldi] : __builtin_nan("");
 }
 
+// Rows per block of the one-right-hand-side sweeps.  Each sweep keeps, per
+// block t, a row-major tile of 2 kTb doubles per row (n rows in all, block t
+// at rows t kTb..): [D_t | -G_t], D_t the inverse of the diagonal block of L
+// (forward) or U (backward), G_t = D_t F[t rows, s columns] with s the block
+// the sweep finishes t from (forward s = t - 1, backward s = t + 1); zeros
+// past the blocks' sizes.
+constexpr int kTb = 256;
+constexpr int kTileW = 2 * kTb;
+
+// identity in the D_t part of every tile, zeros elsewhere
+__global__ __launch_bounds__(256) void tri_tile_init(int64_t n, double *T) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * kTileW) return;
+    const int64_t r = t / kTileW, e = t % kTileW;
+    T[t] = e == r % kTb ? 1.0 : 0.0;
+}
+
+// sum_j col[j n] v[j], j < jn <= NJ, in order; all NJ loads in flight at once
+// when the block is whole
+template <int NJ>
+__device__ __forceinline__ double dot_cols(const double *col, int64_t n, const double *v, int jn) {
+    double acc = 0.0;
+    if (jn == NJ) {
+        double a[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) a[j] = col[j * n];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) acc += a[j] * v[j];
+    } else {
+        for (int j = 0; j < jn; ++j) acc += col[j * n] * v[j];
+    }
+    return acc;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+// One step of a triangular sweep of one right-hand side: y is the working
+// vector (the right-hand side less the finished blocks' contributions), x
+// receives the finished blocks.  Block s is finished (x_s final) when the
+// step runs; the step finishes block t and updates the rows [r0, r1):
+//   x_t = [D_t | -G_t] [y_t; x_s]  (y_t alone when s0 < 0: the first block),
+//   y_r -= F[r, s columns] x_s     for r in [r0, r1), outside blocks s and t.
+// y_t is complete, since every block before s updated it in an earlier
+// step.  Forward (unit lower L): t = s + 1, r0 = the row after t; backward
+// (U): t = s - 1, [r0, r1) = the rows above t.
+// Workgroups of 8 waves: the first ceil(bt / 32) finish block t, 4 rows per
+// wave, each row's tile read contiguously across the lanes and summed over
+// the wave; the others update 64 rows each, every wave an eighth of the kTb
+// columns of F.
+constexpr int kTriThreads = 512;
+__global__ __launch_bounds__(kTriThreads) void tri_step(const double *__restrict__ F, const double *__restrict__ T,
+                                                        int64_t n, double *__restrict__ y, double *__restrict__ x,
+                                                        int64_t s0, int bs, int64_t t0, int bt, int64_t r0,
+                                                        int64_t r1) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nfin = (bt + 31) / 32;
+    if ((int)blockIdx.x < nfin) {
+        constexpr int KE = kTileW / 64;
+        double in[KE];
+#pragma unroll
+        for (int k = 0; k < KE; ++k) {
+            const int e = lane + 64 * k;
+            in[k] = e < kTb ? (e < bt ? y[t0 + e] : 0.0) : (e - kTb < bs ? x[s0 + e - kTb] : 0.0);
+        }
+        const int i0 = (int)blockIdx.x * 32 + w * 4;
+        double acc[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            acc[q] = 0.0;
+            if (i0 + q < bt) {
+                const double *row = T + (t0 + i0 + q) * kTileW + lane;
+                double a[KE];
+#pragma unroll
+                for (int k = 0; k < KE; ++k) a[k] = row[64 * k];
+#pragma unroll
+                for (int k = 0; k < KE; ++k) acc[q] += a[k] * in[k];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double v = wave_sum(acc[q]);
+            if (lane == 0 && i0 + q < bt) x[t0 + i0 + q] = v;
+        }
+        return;
+    }
+    __shared__ double red[kTriThreads];
+    constexpr int NJ = kTb / 8;
+    const int64_t r = r0 + (int64_t)((int)blockIdx.x - nfin) * 64 + lane;
+    const bool live = r < r1;
+    double acc = 0.0;
+    if (live) acc = dot_cols<NJ>(F + r + (s0 + w * NJ) * n, n, x + s0 + w * NJ, min(NJ, bs - w * NJ));
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    if (w == 0 && live) {
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) t += red[k * 64 + lane];
+        y[r] -= t;
+    }
+}
+
 unsigned grid(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
@@ -264,6 +369,9 @@ CellLayout cell_layout(const CellArgs &g) {
     L.rr = off;   off = al(off + (size_t)mr * 8);
     L.ipiv = off; off = al(off + (size_t)n * 4);
     L.perm = off; off = al(off + (size_t)n * 4);
+    L.Tf = off;   off = al(off + (size_t)n * kTileW * 8);
+    L.Tb = off;   off = al(off + (size_t)n * kTileW * 8);
+    L.w = off;    off = al(off + (size_t)n * 8);
     L.info = off; off = al(off + (size_t)(cell_panels(g) + 1) * 4);
     L.total = off;
     return L;
@@ -412,9 +520,6 @@ void *blas_handle(hipStream_t st, std::string &err) { return (void *)handle_for(
 
 namespace {
 
-// rows of a single right-hand side's sweep blocks (TRSV + GEMV per block)
-constexpr int64_t kSolveBlock = 8192;
-
 // the calls of an LU schedule (lu_plan.h): F is the n x n factored matrix
 // (ld n), T the target (F itself when factoring), ldt its leading dimension
 std::string lu_run(rocblas_handle h, const std::vector<lu::Call> &plan, double *F, int64_t n, double *T,
@@ -439,26 +544,15 @@ std::string lu_run(rocblas_handle h, const std::vector<lu::Call> &plan, double *
             case lu::kTrsm: {
                 const rocblas_fill fill = c.upper ? rocblas_fill_upper : rocblas_fill_lower;
                 const rocblas_diagonal diag = c.upper ? rocblas_diagonal_non_unit : rocblas_diagonal_unit;
-                if (c.n == 1) {
-                    s = rocblas_dtrsv(h, fill, rocblas_operation_none, diag, m, F + c.a, ld, T + c.b, 1);
-                    if (s != rocblas_status_success) return rb_err("rocblas_dtrsv", s);
-                } else {
-                    s = rocblas_dtrsm(h, rocblas_side_left, fill, rocblas_operation_none, diag, m, nn, &one, F + c.a,
-                                      ld, T + c.b, lt);
-                    if (s != rocblas_status_success) return rb_err("rocblas_dtrsm", s);
-                }
+                s = rocblas_dtrsm(h, rocblas_side_left, fill, rocblas_operation_none, diag, m, nn, &one, F + c.a, ld,
+                                  T + c.b, lt);
+                if (s != rocblas_status_success) return rb_err("rocblas_dtrsm", s);
                 break;
             }
             case lu::kGemm:
-                if (c.n == 1) {
-                    s = rocblas_dgemv(h, rocblas_operation_none, m, k, &minus_one, F + c.a, ld, T + c.b, 1, &one,
-                                      T + c.c, 1);
-                    if (s != rocblas_status_success) return rb_err("rocblas_dgemv", s);
-                } else {
-                    s = rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, m, nn, k, &minus_one,
-                                      F + c.a, ld, T + c.b, lt, &one, T + c.c, lt);
-                    if (s != rocblas_status_success) return rb_err("rocblas_dgemm", s);
-                }
+                s = rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, m, nn, k, &minus_one, F + c.a,
+                                  ld, T + c.b, lt, &one, T + c.c, lt);
+                if (s != rocblas_status_success) return rb_err("rocblas_dgemm", s);
                 break;
             default:
                 return "unknown LU call";
@@ -470,6 +564,61 @@ std::string lu_run(rocblas_handle h, const std::vector<lu::Call> &plan, double *
 hipError_t gather_launch(int64_t n, int64_t nrhs, const double *in, int64_t ldi, const int32_t *perm, double *out,
                          int64_t ldo, hipStream_t st) {
     hipLaunchKernelGGL(lu_gather, dim3(grid(n * nrhs)), dim3(256), 0, st, n, nrhs, in, ldi, perm, out, ldo);
+    return hipGetLastError();
+}
+
+// the sweeps' tiles.  Viewed column-major with leading dimension kTileW,
+// block t's tile holds D_t^T in rows 0..bt-1 and -G_t^T in rows kTb..:
+// D^T = L^-T (U^-T) by TRSM from the right with the transposed triangle on
+// an identity, -G^T = -F[t rows, s columns]^T D^T by GEMM.
+std::string tri_prepare(rocblas_handle h, const double *F, int64_t n, double *Tf, double *Tb, hipStream_t st) {
+    hipLaunchKernelGGL(tri_tile_init, dim3(grid(n * kTileW)), dim3(256), 0, st, n, Tf);
+    hipLaunchKernelGGL(tri_tile_init, dim3(grid(n * kTileW)), dim3(256), 0, st, n, Tb);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return std::string("tri_tile_init: ") + hipGetErrorString(e);
+    const double one = 1.0, minus_one = -1.0, zero = 0.0;
+    const rocblas_int ld = (rocblas_int)n, lt = kTileW;
+    auto bsz = [&](int64_t q) { return (rocblas_int)std::min<int64_t>(kTb, n - q); };
+    for (int64_t q = 0; q < n; q += kTb) {
+        const rocblas_int b = bsz(q);
+        const double *Fq = F + q + q * n;
+        double *tf = Tf + q * kTileW, *tb = Tb + q * kTileW;
+        rocblas_status s = rocblas_dtrsm(h, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
+                                         rocblas_diagonal_unit, b, b, &one, Fq, ld, tf, lt);
+        if (s == rocblas_status_success)
+            s = rocblas_dtrsm(h, rocblas_side_right, rocblas_fill_upper, rocblas_operation_transpose,
+                              rocblas_diagonal_non_unit, b, b, &one, Fq, ld, tb, lt);
+        if (s != rocblas_status_success) return rb_err("rocblas_dtrsm", s);
+        if (q > 0) {                                  // forward: block q from q - kTb
+            const int64_t p = q - kTb;
+            s = rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, bsz(p), b, b, &minus_one,
+                              F + q + p * n, ld, tf, lt, &zero, tf + kTb, lt);
+        }
+        if (s == rocblas_status_success && q + kTb < n) {   // backward: block q from q + kTb
+            const int64_t p = q + kTb;
+            s = rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, bsz(p), b, b, &minus_one,
+                              F + q + p * n, ld, tb, lt, &zero, tb + kTb, lt);
+        }
+        if (s != rocblas_status_success) return rb_err("rocblas_dgemm", s);
+    }
+    return "";
+}
+
+// x = U^-1 L^-1 y, y and w scratch (both overwritten): the forward sweep
+// from y into w, then the backward sweep from w into x; one launch per block
+hipError_t tri_solve(const double *F, const double *Tf, const double *Tb, int64_t n, double *y, double *w, double *x,
+                     hipStream_t st) {
+    const int64_t nq = (n + kTb - 1) / kTb;
+    auto bsz = [&](int64_t q) { return (int)std::min<int64_t>(kTb, n - q * kTb); };
+    auto step = [&](const double *T, double *yy, double *xx, int64_t s, int64_t t, int64_t r0, int64_t r1) {
+        const unsigned g = (unsigned)((bsz(t) + 31) / 32 + (r1 - r0 + 63) / 64);
+        hipLaunchKernelGGL(tri_step, dim3(g), dim3(kTriThreads), 0, st, F, T, n, yy, xx, s < 0 ? -1 : s * kTb,
+                           s < 0 ? 0 : bsz(s), t * kTb, bsz(t), r0, r1);
+    };
+    step(Tf, y, w, -1, 0, 0, 0);
+    for (int64_t q = 0; q + 1 < nq; ++q) step(Tf, y, w, q, q + 1, std::min(n, (q + 2) * kTb), n);
+    step(Tb, w, x, -1, nq - 1, 0, 0);
+    for (int64_t q = nq - 1; q >= 1; --q) step(Tb, w, x, q, q - 1, 0, (q - 1) * kTb);
     return hipGetLastError();
 }
 
@@ -493,6 +642,8 @@ std::string cell_factor(const CellArgs &g, double rcond, void *ws, hipStream_t s
     rocblas_handle h = handle_for(st, err);
     if (!h) return err;
     err = lu_run(h, lu::factor_plan(n, g.panel, lu::kMaxSpan), A, n, A, n, ipiv, info, st);
+    if (err.empty())
+        err = tri_prepare(h, A, n, (double *)(b + L.Tf), (double *)(b + L.Tb), st);
     if (!err.empty()) return err;
     // the solves' row permutation: the panels' interchanges in order
     std::vector<int32_t> hp((size_t)n), hinfo((size_t)np + 1, 0);
@@ -541,19 +692,18 @@ std::string cell_solve(const CellArgs &g, const double *v, const double *gv, dou
     char *b = (char *)ws;
     double *A = (double *)(b + L.A), *X = (double *)(b + L.X), *C = (double *)(b + L.C), *P = (double *)(b + L.P);
     double *y = (double *)(b + L.y), *rr = (double *)(b + L.rr);
-    int32_t *ipiv = (int32_t *)(b + L.ipiv), *perm = (int32_t *)(b + L.perm), *info = (int32_t *)(b + L.info);
+    const int32_t *perm = (const int32_t *)(b + L.perm);
     const int64_t n = 2 * g.n_wall;
     const rocblas_int nc = 2 * g.M, mr = 4 * g.K;
     hipError_t e = hipMemcpyAsync(rr, gv, (size_t)mr * 8, hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess) e = gather_launch(n, 1, v, n, perm, y, n, st);                 // P v
+    if (e == hipSuccess)                                                                 // y = A^-1 v
+        e = tri_solve(A, (const double *)(b + L.Tf), (const double *)(b + L.Tb), n, y, (double *)(b + L.w), y, st);
     if (e != hipSuccess) return std::string("cell solve: ") + hipGetErrorString(e);
     std::lock_guard<std::mutex> lk(g_hmu);
     std::string err;
     rocblas_handle h = handle_for(st, err);
     if (!h) return err;
-    err = lu_run(h, lu::solve_plan(n, 1, n, std::min(kSolveBlock, g.panel), lu::kMaxSpan), A, n, y, n, ipiv, info,
-                 st);                                                                    // y = A^-1 v
-    if (!err.empty()) return err;
     const double one = 1.0, minus_one = -1.0, zero = 0.0;
     rocblas_status s = rocblas_dgemv(h, rocblas_operation_none, mr, (rocblas_int)n, &minus_one, C, mr, y, 1, &one,
                                      rr, 1);                                             // g - C y

@@ -45,10 +45,11 @@ struct CellArgs {
     int64_t panel;                                    // LU panel width (columns)
 };
 // workspace of a factored cell (byte offsets): A holds the LU factors, ipiv
-// the panels' pivots, perm the row permutation of the solves, info the
-// panels' LU status then the SVD's
+// the panels' pivots, perm the row permutation of the solves, Tf / Tb the
+// forward and backward sweeps' block tiles, w sweep scratch, info the panels'
+// LU status then the SVD's
 struct CellLayout {
-    size_t A, B, X, C, S, U, Vt, sv, E, P, y, rr, ipiv, perm, info, total;
+    size_t A, B, X, C, S, U, Vt, sv, E, P, y, rr, ipiv, perm, Tf, Tb, w, info, total;
 };
 CellLayout cell_layout(const CellArgs &g);
 int64_t cell_panels(const CellArgs &g);

@@ -172,11 +172,12 @@ def test_cell_argument_checks(L):
 def _cell_layout_bytes(N, K, M, panel):
     """The cell workspace written out in 64-bit integers: each block rounded
     up to 256 bytes, in the order A, B, X, C, S, U, Vt, sv, E, P, y, rr,
-    pivots, permutation, LU status per panel + the SVD's."""
+    pivots, permutation, the two sweeps' tiles (512 doubles per row), the
+    sweep scratch vector, LU status per panel + the SVD's."""
     n, nc, mr = 2 * N, 2 * M, 4 * K
     r = min(mr, nc)
     sizes = [n * n * 8, n * nc * 8, n * nc * 8, mr * n * 8, mr * nc * 8, mr * r * 8, r * nc * 8, r * 8, r * 8,
-             nc * mr * 8, n * 8, mr * 8, n * 4, n * 4, (-(-n // panel) + 1) * 4]
+             nc * mr * 8, n * 8, mr * 8, n * 4, n * 4, n * 512 * 8, n * 512 * 8, n * 8, (-(-n // panel) + 1) * 4]
     return sum(-(-b // 256) * 256 for b in sizes)
 
 
