@@ -90,6 +90,20 @@ typedef struct ves_step_params {
                               rebuilt every solve; 0: none */
     int32_t nmax;          /* largest node count of any curve (>= the actual one;
                               sizes the preconditioner's workspace) */
+    int32_t near;          /* close evaluation between vesicles (Section 3.2): 0 none, the
+                              trapezoid rule for every pair of distinct vesicles; 1 upsampled:
+                              a node closer than near_band h_c to another vesicle c, or to an
+                              image of one (h_c the largest trapezoid weight of c, the
+                              distance to c's nearest node), gets the difference between
+                              c's single layer by the near_P-times upsampled quadrature and
+                              by the trapezoid rule (near_correct_eval's
+                              S2D_NEAR_UPSAMPLE), in S and in b.  The pairs are found once
+                              per call (one read-back: ves_step_apply then waits for the
+                              stream too).  Needs nmax in 4..256. */
+    int32_t near_P;        /* upsampling factor: near_P >= 2, near_P nmax <= 2048 */
+    double near_band;      /* > 0, in units of h_c */
+    int32_t near_max;      /* capacity for the (node, vesicle, image) pairs (>= 1; sizes the
+                              workspace); a call that finds more returns S2D_EINVAL */
 } ves_step_params;
 
 /* Workspace bytes for ves_step_apply / ves_step_solve / ves_time_step. */

@@ -12,7 +12,7 @@ every parity test use them):
   * D_alpha is the spectral derivative of the trigonometric interpolant
     (the Nyquist mode's derivative is zero at the nodes);
   * D_s = diag(1 / |x_alpha|) D_alpha, the arc-length derivative (Section
-    3.3), with |x_alpha| from D_alpha of the node coordinates; higher
+    3.1), with |x_alpha| from D_alpha of the node coordinates; higher
     derivatives apply D_s repeatedly (x_ssss = D_s D_s D_s D_s x);
   * the trapezoid weights are w_j = (2 pi / N) |x_alpha|_j, the outward
     normal (y_alpha, -x_alpha) / |x_alpha|.
@@ -107,6 +107,59 @@ def slp_matrix(g, d, img_lo, img_hi, mu):
             S[:n, comp * n + j] = u
             S[n:, comp * n + j] = v
     return S
+
+
+def near_pairs(g, d, img_lo, img_hi, band):
+    """The vesicle-vesicle interactions that take close evaluation (Section
+    3.2, the paragraph on suspensions): every (node i, curve c, image k) with
+    c other than the node's own curve or k != 0, for which the node moved to
+    (x_i - k d, y_i) lies closer than band h_c to a node of c, h_c the largest
+    trapezoid weight on c.  The squared distance is formed as the sum of two
+    rounded squares, and (band h_c)^2 as the square of the rounded product.
+    Returns [(i, c, k)] ordered by node, then curve, then image."""
+    curves = _curves(g.curve_off)
+    n = g.x.shape[0]
+    own = np.empty(n, np.int64)
+    for c, s in enumerate(curves):
+        own[s] = c
+    out = []
+    for i in range(n):
+        for c, s in enumerate(curves):
+            R = band * g.w[s].max()
+            R2 = R * R
+            for k in range(img_lo, img_hi + 1):
+                if c == own[i] and k == 0:
+                    continue
+                dx = (g.x[i] - k * d) - g.x[s]
+                dy = g.y[i] - g.y[s]
+                if (dx * dx + dy * dy).min() < R2:
+                    out.append((i, c, k))
+    return out
+
+
+def near_slp_matrix(g, pairs, d, P, mu):
+    """The close-evaluation correction of S^near_{gamma,gamma} as a dense
+    (2n x 2n) matrix: for a pair (i, c, k), rows i and n + i gain the map from
+    the density on curve c to u_P - u_1 at (x_i - k d, y_i), the P-times
+    upsampled quadrature of c's single layer less its trapezoid rule
+    (oracle.near.near_label), column by column for unit densities."""
+    from .near import near_label
+    curves = _curves(g.curve_off)
+    n = g.x.shape[0]
+    dS = np.zeros((2 * n, 2 * n))
+    for i, c, k in pairs:
+        s = curves[c]
+        N = s.stop - s.start
+        tx, ty = np.array([g.x[i] - k * d]), np.array([g.y[i]])
+        for comp in range(2):
+            for j in range(N):
+                f = np.zeros(N)
+                f[j] = 1.0
+                fx, fy = (f, np.zeros(N)) if comp == 0 else (np.zeros(N), f)
+                du, dv = near_label(g.x[s], g.y[s], fx, fy, g.w[s], tx, ty, P, mu)
+                dS[i, comp * n + s.start + j] += du[0]
+                dS[n + i, comp * n + s.start + j] += dv[0]
+    return dS
 
 
 def ds_matrix(g):
@@ -242,13 +295,17 @@ def reparameterize(x, y, sigma, off):
 # one time step
 # ---------------------------------------------------------------------------
 def time_step(x, y, sigma, off, dt, kappa_b, mu, L0=None, A0=None, u_resp=None, d=0.0, img_lo=0, img_hi=0,
-              reparam=True):
+              reparam=True, near=None):
     """Steps 6-9 of Algorithm 1 for all curves: solve Eq. (tsteplinsys)
     (constraint per Eq. (ALC) when L0 is given) exactly, x <- x + dt u,
     area correction to A0 (when given), reparameterization (when asked).
+    near = (P, band): S with the close-evaluation correction of the pairs
+    near_pairs(.., band) (near_slp_matrix, P-times upsampled).
     Returns (x, y, sigma, u, v) with sigma = sigma^{k+1}."""
     g = geometry(x, y, off)
     S = slp_matrix(g, d, img_lo, img_hi, mu)
+    if near is not None:
+        S = S + near_slp_matrix(g, near_pairs(g, d, img_lo, img_hi, near[1]), d, near[0], mu)
     A = step_system(g, S, dt, kappa_b)
     b = step_rhs(g, S, dt, kappa_b, L0, u_resp)
     z = np.linalg.solve(A, b)

@@ -14,6 +14,7 @@
 // fixed order (reproducible bit for bit), the small Hessenberg least-squares
 // problem by Givens rotations on the host.
 #include "self_impl.h"
+#include "s2d_near.h"
 #include "../../include/stokes2d_vesicle.h"
 
 #include <rocblas/rocblas.h>
@@ -710,6 +711,140 @@ __global__ __launch_bounds__(256) void vec_axpby_kernel(int64_t len, double a, c
     out[i] = b == 0.0 ? a * x[i] : a * x[i] + b * y[i];
 }
 
+// ---------------------------------------------------------------------------
+// close evaluation between vesicles (Section 3.2): a node closer than
+// band h_c to another vesicle c, or to an image of one (h_c the largest
+// trapezoid weight of c), gets the difference between the upsampled
+// quadrature of c's single layer and its trapezoid rule at that node
+// ---------------------------------------------------------------------------
+// per curve: box[5 c ..] = x min, x max, y min, y max, h_c; NaN for a curve
+// of invalid size (never near)
+__global__ __launch_bounds__(256) void ves_near_box(int64_t n, const int32_t *off, const double *x, const double *y,
+                                                    const double *w, double *box) {
+    __shared__ double red[5][256];
+    const CurveRange r = curve_range(off, n);
+    const double inf = __builtin_inf();
+    double v[5] = {inf, -inf, inf, -inf, 0.0};
+    if (r.ok)
+        for (int64_t i = r.lo + threadIdx.x; i < r.hi; i += blockDim.x) {
+            v[0] = fmin(v[0], x[i]);
+            v[1] = fmax(v[1], x[i]);
+            v[2] = fmin(v[2], y[i]);
+            v[3] = fmax(v[3], y[i]);
+            v[4] = fmax(v[4], w[i]);
+        }
+    for (int k = 0; k < 5; ++k) red[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            const int o = threadIdx.x + h;
+            red[0][threadIdx.x] = fmin(red[0][threadIdx.x], red[0][o]);
+            red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][o]);
+            red[2][threadIdx.x] = fmin(red[2][threadIdx.x], red[2][o]);
+            red[3][threadIdx.x] = fmax(red[3][threadIdx.x], red[3][o]);
+            red[4][threadIdx.x] = fmax(red[4][threadIdx.x], red[4][o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 5) box[5 * blockIdx.x + threadIdx.x] = r.ok ? red[threadIdx.x][0] : __builtin_nan("");
+}
+
+// The near test of the point (tx, ty) against curve c: the squared distance
+// to c's nearest node below (band h_c)^2, every product and sum rounded on
+// its own (no fused multiply-add), as the host-side reference computes it.
+__device__ bool ves_near_hit(double tx, double ty, const double *x, const double *y, int64_t lo, int64_t hi,
+                             double R2) {
+#pragma clang fp contract(off)
+    double q = __builtin_inf();
+    for (int64_t j = lo; j < hi; ++j) {
+        const double dx = tx - x[j], dy = ty - y[j];
+        q = fmin(q, dx * dx + dy * dy);
+    }
+    return q < R2;
+}
+
+// Per node i (on curve ci), the (curve c, image k) pairs with c != ci or
+// k != 0 for which the node, shifted by -k d, is near c: counted (WRITE
+// false, cnt[i]) or written from pos[i] on in the order c, then k (WRITE
+// true): the node, the curve and the shifted coordinates.
+template <bool WRITE>
+__global__ __launch_bounds__(256) void ves_near_pairs(int64_t n, int32_t nc, const int32_t *off, const int32_t *oc,
+                                                      const double *x, const double *y, const double *box, double d,
+                                                      int img_lo, int img_hi, double band, int32_t *cnt,
+                                                      const int64_t *pos, int32_t *pnode, int32_t *pcurve,
+                                                      double *px, double *py) {
+#pragma clang fp contract(off)
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int ci = oc[i];
+    const double xi = x[i], yi = y[i];
+    int32_t m = 0;
+    int64_t at = WRITE ? pos[i] : 0;
+    for (int c = 0; c < nc; ++c) {
+        const double *b = box + 5 * c;
+        const double R = band * b[4], R2 = R * R, Rb = 1.01 * R;   // the box test only pre-selects
+        for (int k = img_lo; k <= img_hi; ++k) {
+            if (c == ci && k == 0) continue;
+            const double tx = xi - (double)k * d;
+            if (!(tx >= b[0] - Rb && tx <= b[1] + Rb && yi >= b[2] - Rb && yi <= b[3] + Rb)) continue;
+            if (!ves_near_hit(tx, yi, x, y, off[c], off[c + 1], R2)) continue;
+            if (WRITE) {
+                pnode[at] = (int32_t)i;
+                pcurve[at] = c;
+                px[at] = tx;
+                py[at] = yi;
+                ++at;
+            } else {
+                ++m;
+            }
+        }
+    }
+    if (!WRITE) cnt[i] = m;
+}
+
+// exclusive scan of cnt[0 .. n) into pos[0 .. n], pos[n] the total; one
+// workgroup, each thread over a contiguous segment
+__global__ __launch_bounds__(1024) void ves_near_scan(int64_t n, const int32_t *cnt, int64_t *pos) {
+    __shared__ int64_t part[1024];
+    const int64_t seg = (n + 1023) / 1024;
+    const int64_t b0 = min((int64_t)threadIdx.x * seg, n), b1 = min(b0 + seg, n);
+    int64_t s = 0;
+    for (int64_t i = b0; i < b1; ++i) s += cnt[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t acc = 0;
+        for (int t = 0; t < 1024; ++t) {
+            const int64_t v = part[t];
+            part[t] = acc;
+            acc += v;
+        }
+        pos[n] = acc;
+    }
+    __syncthreads();
+    int64_t acc = part[threadIdx.x];
+    for (int64_t i = b0; i < b1; ++i) {
+        pos[i] = acc;
+        acc += cnt[i];
+    }
+}
+
+// out[i] += the node's corrections, out[n + i] likewise, summed in list order
+__global__ __launch_bounds__(256) void ves_near_add(int64_t n, const int64_t *pos, const double *du, const double *dv,
+                                                    double *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t a = pos[i], b = pos[i + 1];
+    if (b <= a) return;
+    double su = 0.0, sv = 0.0;
+    for (int64_t p = a; p < b; ++p) {
+        su += du[p];
+        sv += dv[p];
+    }
+    out[i] += su;
+    out[n + i] += sv;
+}
+
 unsigned g256(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
@@ -727,6 +862,10 @@ struct StepLayout {
     // S_cc, B, S_cc B, P (LU), pivots, info, padded right-hand sides, two
     // [3n] vectors
     size_t T, Dm, D2, D4, Sm, Bm, Top, Pm, ipiv, info, rhs, t1, t2;
+    // close evaluation (near != 0): curve boxes, per-node counts and list
+    // offsets, the near pairs (node, curve, shifted coordinates, corrections),
+    // the upsampled records
+    size_t nbox, ncnt, npos, pnode, pcurve, px, py, pdu, pdv, up;
     size_t total;
 };
 
@@ -813,6 +952,29 @@ StepLayout step_layout(int64_t n, int32_t nc, const ves_step_params *p) {
         L.t2 = o;
         o += al256(n3 * d);
     }
+    if (p->near) {
+        const size_t cap = (size_t)std::max(p->near_max, 1);
+        L.nbox = o;
+        o += al256((size_t)nc * 5 * d);
+        L.ncnt = o;
+        o += al256((size_t)n * sizeof(int32_t));
+        L.npos = o;
+        o += al256(((size_t)n + 1) * sizeof(int64_t));
+        L.pnode = o;
+        o += al256(cap * sizeof(int32_t));
+        L.pcurve = o;
+        o += al256(cap * sizeof(int32_t));
+        L.px = o;
+        o += al256(cap * d);
+        L.py = o;
+        o += al256(cap * d);
+        L.pdu = o;
+        o += al256(cap * d);
+        L.pdv = o;
+        o += al256(cap * d);
+        L.up = o;
+        o += al256(4 * ((size_t)p->near_P + 1) * (size_t)n * d);
+    }
     L.total = o;
     return L;
 }
@@ -832,6 +994,7 @@ struct StepCtx {
     double *geo;
     bool pc;
     rocblas_handle h;        // set while the preconditioner is in use (blas_mutex held)
+    int64_t nm;              // near pairs (close evaluation)
 };
 
 int ves_fail(int code, const std::string &m) { return set_error(code, m); }
@@ -859,6 +1022,16 @@ int check_params(const ves_step_params *p) {
         return ves_fail(S2D_EINVAL, "the preconditioner needs nmax in 4..512");
     if (!p->precond && p->nmax != 0 && (p->nmax < 4 || p->nmax > kVesMaxN))
         return ves_fail(S2D_EINVAL, "nmax must be 0 or in 4..512");
+    if (p->near != 0 && p->near != 1) return ves_fail(S2D_EINVAL, "near must be 0 or 1");
+    if (p->near) {
+        if (p->nmax < 4 || p->nmax > kUpMaxN)
+            return ves_fail(S2D_EINVAL, "close evaluation needs nmax in 4..256");
+        if (p->near_P < 2 || (int64_t)p->near_P * p->nmax > kUpMaxM)
+            return ves_fail(S2D_EINVAL, "close evaluation needs near_P >= 2 and near_P * nmax <= 2048");
+        if (!(std::isfinite(p->near_band) && p->near_band > 0.0))
+            return ves_fail(S2D_EINVAL, "near_band must be finite and > 0");
+        if (p->near_max < 1) return ves_fail(S2D_EINVAL, "near_max must be >= 1");
+    }
     if (p->max_iter < 1) return ves_fail(S2D_EINVAL, "max_iter must be >= 1");
     if (!(p->tol >= 0.0)) return ves_fail(S2D_EINVAL, "tol must be >= 0");
     return S2D_OK;
@@ -902,8 +1075,42 @@ int setup_ctx(StepCtx &C, int64_t n, int32_t nc, const int32_t *off, const doubl
     C.trg.y = y;
     C.trg.on_curve = oc;
     C.trg.on_node = on;
+    C.nm = 0;
+    if (p->near && n > 0) {
+        char *b = C.ws;
+        double *box = (double *)(b + C.L.nbox);
+        int32_t *cnt = (int32_t *)(b + C.L.ncnt);
+        int64_t *pos = (int64_t *)(b + C.L.npos);
+        int32_t *pn = (int32_t *)(b + C.L.pnode), *pc = (int32_t *)(b + C.L.pcurve);
+        double *px = (double *)(b + C.L.px), *py = (double *)(b + C.L.py);
+        hipLaunchKernelGGL(ves_near_box, dim3(nc), dim3(256), 0, C.st, n, off, x, y, g.w, box);
+        hipLaunchKernelGGL(ves_near_pairs<false>, dim3(g256(n)), dim3(256), 0, C.st, n, nc, off, oc, x, y, box, p->d,
+                           p->img_lo, p->img_hi, p->near_band, cnt, pos, pn, pc, px, py);
+        hipLaunchKernelGGL(ves_near_scan, dim3(1), dim3(1024), 0, C.st, n, cnt, pos);
+        int64_t total = 0;
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(&total, pos + n, sizeof(int64_t), hipMemcpyDeviceToHost, C.st);
+        if (e == hipSuccess) e = hipStreamSynchronize(C.st);
+        if (e != hipSuccess) return hipf(e, "near pairs");
+        if (total > p->near_max)
+            return ves_fail(S2D_EINVAL, std::to_string(total) + " near pairs exceed near_max = " +
+                                            std::to_string(p->near_max));
+        if (total > 0) {
+            hipLaunchKernelGGL(ves_near_pairs<true>, dim3(g256(n)), dim3(256), 0, C.st, n, nc, off, oc, x, y, box,
+                               p->d, p->img_lo, p->img_hi, p->near_band, cnt, pos, pn, pc, px, py);
+            e = hipGetLastError();
+            if (e != hipSuccess) return hipf(e, "near pairs");
+        }
+        C.nm = total;
+    }
     return S2D_OK;
 }
+
+#define S2D_TRY(x)                          \
+    do {                                    \
+        const int rc_ = (x);                \
+        if (rc_ != S2D_OK) return rc_;      \
+    } while (0)
 
 // out = A z (RHS = false) or out = b (RHS = true, z unused), single-layer
 // sums in `mode`
@@ -926,8 +1133,29 @@ int apply(StepCtx &C, const double *z, double *out, int mode) {
     hipLaunchKernelGGL(ves_op_kernel<RHS>, dim3(C.nc), dim3(kVesBlock), 0, C.st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hipf(e, "vesicle operator launch");
-    return stokes2d_slp_eval(mode, &C.src, &C.trg, C.p->d, C.p->img_lo, C.p->img_hi, C.p->mu, out,
-                             out + C.n, 1, C.ws + C.L.slp, C.L.slp_bytes, C.st);
+    S2D_TRY(stokes2d_slp_eval(mode, &C.src, &C.trg, C.p->d, C.p->img_lo, C.p->img_hi, C.p->mu, out, out + C.n, 1,
+                              C.ws + C.L.slp, C.L.slp_bytes, C.st));
+    if (C.nm > 0) {
+        // close evaluation: the upsampled records of every vesicle's layer
+        // for this density, the corrections at the near pairs, summed per node
+        char *b = C.ws;
+        double *up = (double *)(b + C.L.up), *du = (double *)(b + C.L.pdu), *dv = (double *)(b + C.L.pdv);
+        s2d_targets nt{};
+        nt.n = C.nm;
+        nt.x = (const double *)(b + C.L.px);
+        nt.y = (const double *)(b + C.L.py);
+        e = near_launch_upsample(&C.src, C.p->near_P, up, C.st);
+        if (e == hipSuccess)
+            e = near_launch_quad(&C.src, &nt, (const int32_t *)(b + C.L.pcurve), nullptr, nullptr, C.p->near_P, up,
+                                 C.p->mu, du, dv, C.st);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(ves_near_add, dim3(g256(C.n)), dim3(256), 0, C.st, C.n,
+                               (const int64_t *)(b + C.L.npos), du, dv, out);
+            e = hipGetLastError();
+        }
+        if (e != hipSuccess) return hipf(e, "close evaluation");
+    }
+    return S2D_OK;
 }
 
 // dots[j] = V_j . w, j < k1, read back to the host
@@ -957,12 +1185,6 @@ int axpby(StepCtx &C, double a, const double *x, double b, const double *y, doub
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? S2D_OK : hipf(e, "GMRES vector update");
 }
-
-#define S2D_TRY(x)                          \
-    do {                                    \
-        const int rc_ = (x);                \
-        if (rc_ != S2D_OK) return rc_;      \
-    } while (0)
 
 int rbf(rocblas_status s, const char *what) {
     return s == rocblas_status_success ? S2D_OK

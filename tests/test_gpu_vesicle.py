@@ -111,6 +111,97 @@ def test_step_operator_and_rhs(img):
     assert e_op < 1e-10 and e_b < 1e-10
 
 
+def _close_set():
+    """Three ellipses 0.05 apart along x (0.7 node spacings), the third's
+    image at -d as close to the first: nodes near other vesicles and near
+    images of them."""
+    xs, ys, off = [], [], [0]
+    for cx, cy, N in ((0.0, 0.0, 32), (0.95, 0.04, 48), (1.9, -0.03, 32)):
+        x, y = synth._ellipse(cx, cy, 0.45, 0.3, 0.0, N)[:2]
+        xs.append(x)
+        ys.append(y)
+        off.append(off[-1] + N)
+    return np.concatenate(xs), np.concatenate(ys), np.array(off, np.int32), 2.85
+
+
+def _near_oracle(g, d, img, band=5.0, P=8, mu=0.7):
+    """The oracle's close-evaluation correction of S, and the pairs, checked
+    to lie clear of the band's edge (decisions both sides must share)."""
+    from oracle import vesicle as ov
+    pairs = ov.near_pairs(g, d, img[0], img[1], band)
+    for b2 in (band * (1 - 1e-9), band * (1 + 1e-9)):
+        assert ov.near_pairs(g, d, img[0], img[1], b2) == pairs, "a node sits on the band's edge"
+    return pairs, ov.near_slp_matrix(g, pairs, d, P, mu)
+
+
+@pytest.mark.parametrize("img", [(0, 0), (-1, 1)])
+def test_step_operator_with_close_evaluation(img):
+    """The step operator and right-hand side with close evaluation between
+    vesicles (8x upsampled, band 5 spacings) against the oracle's matrix
+    with the same correction; the correction itself is far above the
+    tolerance."""
+    from oracle import vesicle as ov
+    from paper_1510_05616_amd import vesicle as pv
+    import torch
+    x, y, off, d = _close_set()
+    n = x.shape[0]
+    g = ov.geometry(x, y, off)
+    pairs, dS = _near_oracle(g, d, img)
+    assert len(pairs) > 20 and (img == (0, 0) or any(k != 0 for _, _, k in pairs))
+    L0 = ov.arc_lengths(g)
+    f64 = dict(dtype=torch.float64, device="cuda")
+    V = pv.Vesicles(x, y, off)
+    al = np.concatenate([2 * math.pi * np.arange(off[c + 1] - off[c]) / (off[c + 1] - off[c]) for c in range(3)])
+    z = np.concatenate([np.cos(al) + 0.3 * np.sin(3 * al), np.sin(2 * al) - 0.1, 0.5 * np.cos(al) + 1.0])
+    kw = dict(dt=0.002, kappa_b=0.8, mu=0.7, d=d, img_lo=img[0], img_hi=img[1], L0=torch.as_tensor(L0, **f64),
+              nmax=48, precond=False)
+    out, b = V.step_apply(pv.params(near=1, near_P=8, near_band=5.0, near_max=4096, **kw), torch.as_tensor(z, **f64))
+    out0, b0 = V.step_apply(pv.params(**kw), torch.as_tensor(z, **f64))
+    torch.cuda.synchronize()
+    S = ov.slp_matrix(g, d, img[0], img[1], 0.7) + dS
+    A = ov.step_system(g, S, 0.002, 0.8)
+    bo = ov.step_rhs(g, S, 0.002, 0.8, L0)
+    e_op, e_b = _rel(_np(out), A @ z), _rel(_np(b), bo)
+    c_op, c_b = _rel(_np(out0), A @ z), _rel(_np(b0), bo)
+    print(f"img={img} pairs {len(pairs)}: operator {e_op:.2e} rhs {e_b:.2e} (without the correction "
+          f"{c_op:.2e}, {c_b:.2e})", flush=True)
+    assert e_op < 1e-10 and e_b < 1e-10
+    assert c_op > 1e-6 and c_b > 1e-6
+    # a capacity below the pair count is an error, not a silent truncation
+    import paper_1510_05616_amd as s2d
+    with pytest.raises(s2d.S2DError):
+        V.step_apply(pv.params(near=1, near_P=8, near_band=5.0, near_max=len(pairs) - 1, **kw),
+                     torch.as_tensor(z, **f64))
+
+
+def test_time_steps_with_close_evaluation_match_the_oracle():
+    """Three time steps of the close set with close evaluation (images
+    -1..1; the pairs are found anew at every step) against the oracle's
+    steps with the same correction."""
+    from oracle import vesicle as ov
+    from paper_1510_05616_amd import vesicle as pv
+    import torch
+    x, y, off, d = _close_set()
+    g = ov.geometry(x, y, off)
+    L0, A0 = ov.arc_lengths(g), ov.areas(x, y, off)
+    f64 = dict(dtype=torch.float64, device="cuda")
+    p = pv.params(mode=0, dt=0.002, kappa_b=1.0, mu=0.7, d=d, img_lo=-1, img_hi=1, L0=torch.as_tensor(L0, **f64),
+                  tol=1e-13, restart=64, max_iter=4000, nmax=48, near=1, near_P=8, near_band=5.0, near_max=4096)
+    V = pv.Vesicles(x, y, off)
+    A0d = torch.as_tensor(A0, **f64)
+    xo, yo, so = x.copy(), y.copy(), np.zeros_like(x)
+    for k in range(3):
+        _near_oracle(ov.geometry(xo, yo, off), d, (-1, 1))
+        it, res = V.time_step(p, A0=A0d, reparam=True)
+        xo, yo, so, _, _ = ov.time_step(xo, yo, so, off, 0.002, 1.0, 0.7, L0=L0, A0=A0, d=d, img_lo=-1, img_hi=1,
+                                        near=(8, 5.0))
+        torch.cuda.synchronize()
+        ex = max(_rel(_np(V.x), xo), _rel(_np(V.y), yo))
+        es = _rel(_np(V.sigma), so)
+        print(f"close set step {k}: {it} iterations, residual {res:.1e}, x {ex:.2e}, sigma {es:.2e}", flush=True)
+        assert res <= 1e-13 and ex < 1e-11 and es < 1e-7
+
+
 def test_refined_fp32c_solve_matches_dense_solve():
     # FP32C corrections with FP64 residuals reach the FP64 tolerance
     from oracle import vesicle as ov
