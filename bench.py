@@ -461,11 +461,14 @@ def step_section(prob, steps=3, dt=1e-4, kappa_b=1.0):
                        f"dt = {dt}, kappa_B = {kappa_b}, mu = {prob.mu}: one step = GMRES solve of the "
                        "288,000-unknown step system + update + area correction + reparameterization",
            "n_nodes": n}
-    for name, mode, tol in (("f64", s2d.S2D_FP64, 1e-10), ("f32", s2d.S2D_FP32C, 1e-10)):
+    out["near_pairs"] = _near_pair_count(ves, prob.d, 5.0)
+    for name, mode, tol, near in (("f64", s2d.S2D_FP64, 1e-10, 0), ("f32", s2d.S2D_FP32C, 1e-10, 0),
+                                  ("f32_near", s2d.S2D_FP32C, 1e-10, 1)):
         V = pv.Vesicles(ves.x, ves.y, ves.curve_off)
         L0, A0 = V.measure()
         p = pv.params(mode=mode, dt=dt, kappa_b=kappa_b, mu=prob.mu, d=prob.d, img_lo=-1, img_hi=1, L0=L0,
-                      tol=tol, restart=64, max_iter=500, nmax=96)
+                      tol=tol, restart=64, max_iter=500, nmax=96, near=near, near_P=8, near_band=5.0,
+                      near_max=1 << 22)
         ws = V.workspace(p)
         V.time_step(p, A0=A0, ws=ws)                     # warm-up
         torch.cuda.synchronize()
@@ -483,7 +486,7 @@ def step_section(prob, steps=3, dt=1e-4, kappa_b=1.0):
         pairs = n * n * 3
         avg = kms / max(kn, 1)
         tf = FLOPS_PER_PAIR * pairs / (avg * 1e-3) / 1e12
-        peak = PEAK[name]
+        peak = PEAK["f64" if mode == s2d.S2D_FP64 else "f32"]
         out[name] = {"ms_per_step": ms, "value": 1e3 / ms, "unit": "time steps/s", "gmres": its,
                      "single_layer_launches_per_step": kn / steps, "slp_ms_per_step": kms / steps}
         if name == "f64":
@@ -496,7 +499,8 @@ def step_section(prob, steps=3, dt=1e-4, kappa_b=1.0):
         else:
             # FP64 right-hand side and residuals, FP32C corrections: the
             # launches are of both precisions
-            log(f"step {name} (FP32C corrections, FP64 residuals): {ms:.1f} ms per time step, GMRES {its}, "
+            what = ("close evaluation of %d near pairs (8x), " % out["near_pairs"]) if near else ""
+            log(f"step {name} ({what}FP32C corrections, FP64 residuals): {ms:.1f} ms per time step, GMRES {its}, "
                 f"{kn / steps:.1f} single-layer launches per step ({kms / steps:.1f} ms)")
     # the oracle: one step of 4 vesicles (dense solve of the 1,152-unknown system)
     off = ves.curve_off
@@ -513,6 +517,44 @@ def step_section(prob, steps=3, dt=1e-4, kappa_b=1.0):
                            "sample": "one step of 4 of the 1,000 vesicles (384 nodes, dense FP64 solve)"}
     log(f"step oracle: {t_or:.2f} s for one step of 4 vesicles")
     return out
+
+
+def _near_pair_count(ves, d, band):
+    """(node, vesicle, image) pairs of the close evaluation: nodes within band
+    times the vesicle's largest spacing of one of its nodes (images -1..1,
+    the own vesicle at image 0 excluded), counted on the host with a k-d tree."""
+    from scipy.spatial import cKDTree
+    off = np.asarray(ves.curve_off)
+    x, y = np.asarray(ves.x), np.asarray(ves.y)
+    n, nc = x.shape[0], off.shape[0] - 1
+    own = np.repeat(np.arange(nc), np.diff(off))
+    h = np.zeros(nc)
+    for c in range(nc):
+        xs, ys = x[off[c]:off[c + 1]], y[off[c]:off[c + 1]]
+        # the largest trapezoid weight, from the spectral speed of the node curve
+        N = xs.shape[0]
+        k = np.fft.fftfreq(N, 1.0 / N)
+        k[N // 2] = 0.0
+        xa = np.fft.ifft(1j * k * np.fft.fft(xs)).real
+        ya = np.fft.ifft(1j * k * np.fft.fft(ys)).real
+        h[c] = (2 * np.pi / N) * np.hypot(xa, ya).max()
+    tree = cKDTree(np.stack([x, y], 1))
+    count = 0
+    for kimg in (-1, 0, 1):
+        pts = np.stack([x - kimg * d, y], 1)
+        hits = tree.query_ball_point(pts, band * h.max())
+        for i, js in enumerate(hits):
+            if not js:
+                continue
+            js = np.asarray(js)
+            cs = own[js]
+            r2 = (pts[i, 0] - x[js]) ** 2 + (pts[i, 1] - y[js]) ** 2
+            ok = r2 < (band * h[cs]) ** 2
+            near = set(cs[ok].tolist())
+            if kimg == 0:
+                near.discard(own[i])
+            count += len(near)
+    return count
 
 
 def channel_section(prob, steps=2, dt=1e-4, kappa_b=1.0, p_drive=10.0, n_proxy=128, wall_nodes=16000):
