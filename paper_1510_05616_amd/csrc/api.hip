@@ -681,7 +681,7 @@ static_assert(S2D_NEAR_NFEAT == s2d::kNearFeat && S2D_NEAR_NFRAME == s2d::kNearF
               "the public near-field sizes match the kernels'");
 
 struct NearLayout {
-    size_t up, dtab, dscr, X, frame, flag, list, count, llist, lcount, total;
+    size_t up, dtab, dscr, X, nrec, flag, list, count, llist, lcount, total;
 };
 
 NearLayout near_layout(int method, const s2d_curves *c, const s2d_targets *t, int P) {
@@ -696,8 +696,8 @@ NearLayout near_layout(int method, const s2d_curves *c, const s2d_targets *t, in
         off = align256(off + s2d::near_derivs_scratch(c));
         L.X = off;
         off = align256(off + (size_t)t->n * s2d::kNearFeat * sizeof(float));
-        L.frame = off;
-        off = align256(off + (size_t)t->n * s2d::kNearFrame * sizeof(double));
+        L.nrec = off;
+        off = align256(off + (size_t)t->n * s2d::kNetRec * sizeof(float));
         // AUTO: per-target decisions, the fallback targets' list and the
         // compaction's per-workgroup counts
         L.flag = off;
@@ -712,7 +712,7 @@ NearLayout near_layout(int method, const s2d_curves *c, const s2d_targets *t, in
         L.lcount = off;
         off = align256(off + ((size_t)(t->n + 255) / 256 + 1) * sizeof(int32_t));
     } else {
-        L.frame = L.flag = L.list = L.count = L.llist = L.lcount = off;
+        L.nrec = L.flag = L.list = L.count = L.llist = L.lcount = off;
     }
     L.total = std::max<size_t>(off, 256);
     return L;
@@ -780,8 +780,7 @@ S2D_API int near_correct_eval(int method, const s2d_curves *ves, const s2d_targe
         return S2D_OK;
     }
     double *dtab = (double *)(w + L.dtab);
-    float *X = (float *)(w + L.X);
-    double *frame = (double *)(w + L.frame);
+    float *X = (float *)(w + L.X), *nrec = (float *)(w + L.nrec);
     e = s2d::near_launch_derivs(ves, dtab, w + L.dscr, st);
     if (e != hipSuccess) return hip_fail(e, "near derivative launch");
     const bool autom = method == S2D_NEAR_AUTO;
@@ -789,10 +788,10 @@ S2D_API int near_correct_eval(int method, const s2d_curves *ves, const s2d_targe
     int32_t *flag = used_fallback ? used_fallback : (int32_t *)(w + L.flag);
     const s2d::DecideArgs da{(const s2d::NearBlob *)mlp, mu, threshold, curve_tol, ves->n_curves, autom ? 1 : 0,
                              du, dv, flag};
-    e = s2d::near_launch_features(ves, trg, trg_curve, dtab, X, frame, st, &da);
+    e = s2d::near_launch_features(ves, trg, trg_curve, dtab, X, nullptr, st, &da, nrec);
     if (e != hipSuccess) return hip_fail(e, "near features launch");
-    e = s2d::near_launch_infer(S2D_OP_SLP, trg->n, X, frame, (const s2d::NearBlob *)mlp, mu, flag, autom ? 1 : 0, du,
-                               dv, (int32_t *)(w + L.lcount), (int32_t *)(w + L.llist), st);
+    e = s2d::near_launch_infer(S2D_OP_SLP, trg->n, X, nrec, (const s2d::NearBlob *)mlp, flag, autom ? 1 : 0, du, dv,
+                               (int32_t *)(w + L.lcount), (int32_t *)(w + L.llist), st);
     if (e != hipSuccess) return hip_fail(e, "near MLP launch");
     if (autom) {
         // the fallback targets, compacted in order, so that the quadrature's
@@ -1052,7 +1051,7 @@ s2d::WallArgs wall_args(const s2d_curves *w, double d, int P, void *scratch, dou
 // the fallback list (MLP, AUTO), pair sums
 struct NearWallLayout {
     WallLayout up;
-    size_t t4, dtab, dscr, X, frame, flag, list, count, llist, lcount, cxy, pair, pair_bytes, total;
+    size_t t4, dtab, dscr, X, nrec, flag, list, count, llist, lcount, cxy, pair, pair_bytes, total;
 };
 
 NearWallLayout near_wall_layout(int method, const s2d_curves *w, const s2d_targets *t, int P,
@@ -1073,8 +1072,8 @@ NearWallLayout near_wall_layout(int method, const s2d_curves *w, const s2d_targe
         o += align256(s2d::near_derivs_scratch(w));
         L.X = o;
         o += align256(n * s2d::kNearFeat * sizeof(float));
-        L.frame = o;
-        o += align256(n * s2d::kNearFrame * sizeof(double));
+        L.nrec = o;
+        o += align256(n * s2d::kNetRec * sizeof(float));
         L.flag = o;
         o += align256(n * sizeof(int32_t));
         L.list = o;
@@ -1242,8 +1241,7 @@ S2D_API int near_wall_correct_eval(int method, const s2d_curves *walls, const s2
     // MLP, AUTO: density derivatives, features, then the straight-line
     // coefficients and the network (AUTO: with the per-bin decision)
     double *dtab = (double *)(base + L.dtab);
-    float *X = (float *)(base + L.X);
-    double *frame = (double *)(base + L.frame);
+    float *X = (float *)(base + L.X), *nrec = (float *)(base + L.nrec);
     e = s2d::near_launch_derivs(walls, dtab, base + L.dscr, st);
     if (e != hipSuccess) return hip_fail(e, "near-wall derivative launch");
     const bool autom = method == S2D_NEAR_AUTO;
@@ -1251,9 +1249,9 @@ S2D_API int near_wall_correct_eval(int method, const s2d_curves *walls, const s2
     double *tu = t4, *tv = t4 + n;
     const s2d::DecideArgs da{(const s2d::NearBlob *)mlp, 1.0, threshold, curve_tol, walls->n_curves, autom ? 1 : 0,
                              tu, tv, flag};
-    e = s2d::near_launch_wall_features(walls, trg, trg_curve, d, dtab, X, frame, st, &da);
+    e = s2d::near_launch_wall_features(walls, trg, trg_curve, d, dtab, X, nullptr, st, &da, nrec);
     if (e != hipSuccess) return hip_fail(e, "near-wall features launch");
-    e = s2d::near_launch_infer(S2D_OP_DLP, n, X, frame, (const s2d::NearBlob *)mlp, 1.0, flag, autom ? 1 : 0, tu, tv,
+    e = s2d::near_launch_infer(S2D_OP_DLP, n, X, nrec, (const s2d::NearBlob *)mlp, flag, autom ? 1 : 0, tu, tv,
                                (int32_t *)(base + L.lcount), (int32_t *)(base + L.llist), st);
     if (e != hipSuccess) return hip_fail(e, "near-wall MLP launch");
     if (autom) {
@@ -1270,8 +1268,8 @@ S2D_API int near_wall_correct_eval(int method, const s2d_curves *walls, const s2
             if ((rc = refine()) != S2D_OK) return rc;
             // fine and coarse sums of the m targets into the feature area
             // (the features are no longer needed)
-            static_assert(s2d::kNearFrame * sizeof(double) >= 4 * sizeof(double), "four doubles per target fit");
-            double *f4 = (double *)(base + L.frame);
+            static_assert(s2d::kNetRec * sizeof(float) >= 4 * sizeof(double), "four doubles per target fit");
+            double *f4 = (double *)(base + L.nrec);
             const s2d_targets tl{m, cx, cy, nullptr, nullptr};
             rc = eval(S2D_OP_DLP, S2D_FP64, &fine, &tl, d, img_lo, img_hi, 1.0, f4, f4 + m, 0, base + L.pair,
                       L.pair_bytes, stream);

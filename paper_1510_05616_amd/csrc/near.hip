@@ -680,9 +680,16 @@ __device__ __forceinline__ int near_scan(double px, double py, int lo, int N, co
     return ks;
 }
 
-// DEC: -1 features only; S2D_OP_SLP also AUTO's decision (near_decide_one)
-// from the frame in registers
-template <int DEC>
+template <int OP>
+__device__ __forceinline__ int near_decide_one(int64_t i, const double *fr, const DecideArgs &a, int c);
+template <int OP>
+__device__ void near_learned_head(int64_t i, const double *rec, const DecideArgs &a, float *__restrict__ nrec);
+
+// FUSE false: the features X and frame records; FUSE true (the learned and
+// AUTO routes): the features, AUTO's decision (near_decide_one) and, for a
+// learned target, its straight-line part and network record
+// (near_learned_head), all from the frame in registers (frame unused)
+template <bool FUSE>
 __global__ __launch_bounds__(256) void near_features(int64_t n_trg, const double *__restrict__ tx,
                                                      const double *__restrict__ ty, const int32_t *__restrict__ tc,
                                                      const int32_t *__restrict__ off, int32_t n_curves, int64_t n_src,
@@ -690,7 +697,8 @@ __global__ __launch_bounds__(256) void near_features(int64_t n_trg, const double
                                                      const double *__restrict__ nx, const double *__restrict__ ny,
                                                      const double *__restrict__ kap, const double *__restrict__ w,
                                                      const double *__restrict__ dtab, float *__restrict__ X,
-                                                     double *__restrict__ frame, DecideArgs da) {
+                                                     double *__restrict__ frame, float *__restrict__ nrec,
+                                                     DecideArgs da) {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = q < n_trg;
     const int64_t i = live ? q : 0;
@@ -731,10 +739,13 @@ __global__ __launch_bounds__(256) void near_features(int64_t n_trg, const double
         near_frame_features(px, py, x[k], y[k], nx[k], ny[k], kap[k], w[k], nb, xi, rec);
         near_frame_head(dtab + (int64_t)k * 2 * kNearDeriv, rec);
     }
-    double *fr = frame + i * kNearFrame;
+    if constexpr (FUSE) {
+        if (near_decide_one<S2D_OP_SLP>(i, rec, da, c) == 0) near_learned_head<S2D_OP_SLP>(i, rec, da, nrec);
+    } else {
+        double *fr = frame + i * kNearFrame;
 #pragma unroll
-    for (int r = 0; r < kNearFrame; ++r) fr[r] = rec[r];
-    if constexpr (DEC >= 0) near_decide_one<DEC>(i, rec, da, c);
+        for (int r = 0; r < kNearFrame; ++r) fr[r] = rec[r];
+    }
 }
 
 // Nearest-node search over the three periods of a wall.  Nodes are grouped in
@@ -889,7 +900,8 @@ __device__ int wall_nearest(const WallCells &W, bool cells, int c, int lo, int N
 // [-N, 2N) at (x_{K mod N} + sgd d floor(K / N), y_{K mod N})); the nearest
 // unrolled node k* (smallest K on ties) and its unrolled neighbours give the
 // features as for closed curves.
-template <int DEC>
+// FUSE as for near_features (the double layer's straight-line part)
+template <bool FUSE>
 __global__ __launch_bounds__(256) void near_wall_features(int64_t n_trg, const double *__restrict__ tx,
                                                           const double *__restrict__ ty,
                                                           const int32_t *__restrict__ tc,
@@ -901,7 +913,8 @@ __global__ __launch_bounds__(256) void near_wall_features(int64_t n_trg, const d
                                                           const double *__restrict__ kap,
                                                           const double *__restrict__ w, double d,
                                                           const double *__restrict__ dtab, float *__restrict__ X,
-                                                          double *__restrict__ frame, DecideArgs da) {
+                                                          double *__restrict__ frame, float *__restrict__ nrec,
+                                                          DecideArgs da) {
     __shared__ WallCells W;
     wall_cells_build(W, off, n_curves, n_src, x, y, w);
     const bool cells = W.ok != 0;
@@ -910,13 +923,21 @@ __global__ __launch_bounds__(256) void near_wall_features(int64_t n_trg, const d
         const int lo = (c >= 0 && c < n_curves) ? off[c] : 0;
         const int N = (c >= 0 && c < n_curves) ? off[c + 1] - lo : 0;
         float *xi = X + i * kNearFeat;
-        double *fr = frame + i * kNearFrame;
         double rec[kNearFrame];
+        // the frame record's destination: the frame array, or the fused
+        // decision and learned head
+        const auto emit = [&]() {
+            if constexpr (FUSE) {
+                if (near_decide_one<S2D_OP_DLP>(i, rec, da, c) == 0) near_learned_head<S2D_OP_DLP>(i, rec, da, nrec);
+            } else {
+                double *fr = frame + i * kNearFrame;
+#pragma unroll
+                for (int r = 0; r < kNearFrame; ++r) fr[r] = rec[r];
+            }
+        };
         if (c < 0 || c >= n_curves || N < 8 || lo < 0 || (int64_t)lo + N > n_src) {
             near_invalid(xi, rec);
-#pragma unroll
-            for (int r = 0; r < kNearFrame; ++r) fr[r] = rec[r];
-            if constexpr (DEC >= 0) near_decide_one<DEC>(i, rec, da, c);
+            emit();
             continue;
         }
         const double sgd = x[lo + 1] > x[lo] ? 1.0 : -1.0;
@@ -937,9 +958,7 @@ __global__ __launch_bounds__(256) void near_wall_features(int64_t n_trg, const d
         near_frame_features(px, py, x[m] + sgd * d * (double)fl(ks), y[m], nx[m], ny[m], kap[m], w[m], nb, xi,
                             rec);
         near_frame_head(dtab + (int64_t)m * 2 * kNearDeriv, rec);
-#pragma unroll
-        for (int r = 0; r < kNearFrame; ++r) fr[r] = rec[r];
-        if constexpr (DEC >= 0) near_decide_one<DEC>(i, rec, da, c);
+        emit();
     }
 }
 
@@ -1230,7 +1249,7 @@ __device__ void net_stage(const NearBlob *__restrict__ nb, NetLds &L) {
 // learned, 1 quadrature, 2 no correction; 0 when use_bound == 0), and the
 // zero correction of dec 2 written to du, dv.
 template <int OP>
-__device__ __forceinline__ void near_decide_one(int64_t i, const double *fr, const DecideArgs &a, int c) {
+__device__ __forceinline__ int near_decide_one(int64_t i, const double *fr, const DecideArgs &a, int c) {
     int dec = 0;
     if (a.use_bound) {
         const NearBlob *nb = a.nb;
@@ -1258,41 +1277,43 @@ __device__ __forceinline__ void near_decide_one(int64_t i, const double *fr, con
         a.du[i] = 0.0;
         a.dv[i] = 0.0;
     }
+    return dec;
 }
 
-// The straight-line part of the learned targets, one per lane (target
-// list[q], q < *list_len, or q itself when list is NULL): du, dv =
-// scale [t n_f] sum_p Cflat_p d_p, the refined rule minus the plain one.
+// The learned route's part that needs the frame, for one target: the
+// straight-line part (the refined rule of spacing 1 / P minus the plain one,
+// FP64) written to du, dv, and the network's record nrec[kNetRec]: the
+// derivatives d_p in the frame, t, n_f, and scale exp(-2 pi b) (FP32).
 template <int OP>
-__global__ __launch_bounds__(256) void near_flat(int64_t n_trg, const int32_t *__restrict__ list,
-                                                 const int32_t *__restrict__ list_len,
-                                                 const double *__restrict__ frame, const NearBlob *__restrict__ nb,
-                                                 double mu, double *__restrict__ du, double *__restrict__ dv) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t n = list ? (int64_t)*list_len : n_trg;
-    if (q >= n) return;
-    const int64_t i = list ? (int64_t)list[q] : q;
-    const double *fr = frame + kNearFrame * i;
-    const double b = fr[1];
-    const double scale = OP == S2D_OP_SLP ? fr[6] / (4.0 * M_PI * mu) : 1.0 / M_PI;
+__device__ void near_learned_head(int64_t i, const double *rec, const DecideArgs &a, float *__restrict__ nrec) {
+    const double b = rec[1];
+    const double scale = OP == S2D_OP_SLP ? rec[6] / (4.0 * M_PI * a.mu) : 1.0 / M_PI;
     double yt = 0.0, yn = 0.0;
     if (b > 0.0) {
         double ff[2], fc[2];
-        flat_rule<OP>(fr[0], b, (double)nb->P, kPolyFine, fr + 9, ff);
-        flat_rule<OP>(fr[0], b, 1.0, kPolyCoarse, fr + 9, fc);
+        flat_rule<OP>(rec[0], b, (double)a.nb->P, kPolyFine, rec + 9, ff);
+        flat_rule<OP>(rec[0], b, 1.0, kPolyCoarse, rec + 9, fc);
         yt = ff[0] - fc[0];
         yn = ff[1] - fc[1];
         if (OP != S2D_OP_SLP) {
-            yt *= fr[8];
-            yn *= fr[8];
+            yt *= rec[8];
+            yn *= rec[8];
         }
     }
-    du[i] = scale * (yt * fr[2] + yn * fr[4]);                   // NaN for an invalid frame
-    dv[i] = scale * (yt * fr[3] + yn * fr[5]);
+    a.du[i] = scale * (yt * rec[2] + yn * rec[4]);               // NaN for an invalid frame
+    a.dv[i] = scale * (yt * rec[3] + yn * rec[5]);
+    float *r = nrec + i * kNetRec;
+#pragma unroll
+    for (int k = 0; k < 2 * kNearDeriv; ++k) r[k] = (float)rec[9 + k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r[2 * kNearDeriv + k] = (float)rec[2 + k];
+    r[2 * kNearDeriv + 4] = (float)(scale * exp(-2.0 * M_PI * b));
+    r[2 * kNearDeriv + 5] = 0.f;
 }
 
 // The network's part of the learned route, added to du, dv of the listed
-// targets (list[q], q < *list_len, or all when list is NULL): a wave takes
+// targets (list[q], q < *list_len, or all when list is NULL) from their
+// features X and records nrec (near_learned_head): a wave takes
 // 64 of them in two MFMA passes of 32; pass h2 feeds target 32 h2 + c from
 // lanes c and c + 32, and after the exchange lane 32 h2 + c holds it.
 // Persistent workgroups stage the network in LDS once; 4 waves per SIMD (128
@@ -1300,7 +1321,7 @@ __global__ __launch_bounds__(256) void near_flat(int64_t n_trg, const int32_t *_
 template <int OP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) void near_net(
     int64_t n_trg, const int32_t *__restrict__ list, const int32_t *__restrict__ list_len,
-    const float *__restrict__ X, const double *__restrict__ frame, const NearBlob *__restrict__ nb, double mu,
+    const float *__restrict__ X, const float *__restrict__ nrec, const NearBlob *__restrict__ nb,
     double *__restrict__ du, double *__restrict__ dv) {
     static_assert(kNearFeat <= 16, "two K-steps of the first layer");
     __shared__ NetLds L;
@@ -1321,7 +1342,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
             const bool vt = qt < n;
             const int64_t it = vt ? (list ? (int64_t)list[qt] : qt) : 0;
             const float *xi = X + it * kNearFeat;
-            const double *ft = frame + kNearFrame * it;
+            const float *ft = nrec + kNetRec * it;
             bf16x4v_t in1[2];
 #pragma unroll
             for (int s2 = 0; s2 < 2; ++s2) {
@@ -1351,7 +1372,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
                 const int o = 8 * (r / 4) + 4 * h + (r % 4);
                 if (o < kNearOut) {
                     const int p = o / 4, out = (o % 4) / 2, in = o % 2;
-                    nt[out] = __builtin_fma((double)y[0][r], ft[9 + 2 * p + in], nt[out]);
+                    nt[out] = __builtin_fma((double)y[0][r], (double)ft[2 * p + in], nt[out]);
                 }
             }
             nt[0] += __shfl_xor(nt[0], 32, kWave);
@@ -1362,11 +1383,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
             }
         }
         if (!mine) continue;
-        const double *fr = frame + kNearFrame * i;
-        const double scale = OP == S2D_OP_SLP ? fr[6] / (4.0 * M_PI * mu) : 1.0 / M_PI;
-        const double se = scale * exp(-2.0 * M_PI * fr[1]);
-        du[i] = __builtin_fma(se, net[0] * fr[2] + net[1] * fr[4], du[i]);
-        dv[i] = __builtin_fma(se, net[0] * fr[3] + net[1] * fr[5], dv[i]);
+        const float *fr = nrec + kNetRec * i + 2 * kNearDeriv;      // t, n_f, scale exp(-2 pi b)
+        const double se = fr[4];
+        du[i] = __builtin_fma(se, net[0] * (double)fr[0] + net[1] * (double)fr[2], du[i]);
+        dv[i] = __builtin_fma(se, net[0] * (double)fr[1] + net[1] * (double)fr[3], dv[i]);
     }
 }
 
@@ -1838,48 +1858,46 @@ hipError_t near_launch_derivs(const s2d_curves *c, double *dtab, void *scratch, 
 }
 
 hipError_t near_launch_features(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, const double *dtab,
-                                float *X, double *frame, hipStream_t st, const DecideArgs *dec) {
+                                float *X, double *frame, hipStream_t st, const DecideArgs *fused, float *nrec) {
     if (t->n <= 0) return hipSuccess;
-    const DecideArgs da = dec ? *dec : DecideArgs{};
-    if (dec)
-        hipLaunchKernelGGL(near_features<S2D_OP_SLP>, dim3(grid_for(t->n)), dim3(256), 0, st, t->n, t->x, t->y, tc,
+    const DecideArgs da = fused ? *fused : DecideArgs{};
+    if (fused)
+        hipLaunchKernelGGL(near_features<true>, dim3(grid_for(t->n)), dim3(256), 0, st, t->n, t->x, t->y, tc,
                            c->curve_off, c->n_curves, c->n_nodes, c->x, c->y, c->nx, c->ny, c->kappa, c->w, dtab, X,
-                           frame, da);
+                           nullptr, nrec, da);
     else
-        hipLaunchKernelGGL(near_features<-1>, dim3(grid_for(t->n)), dim3(256), 0, st, t->n, t->x, t->y, tc,
+        hipLaunchKernelGGL(near_features<false>, dim3(grid_for(t->n)), dim3(256), 0, st, t->n, t->x, t->y, tc,
                            c->curve_off, c->n_curves, c->n_nodes, c->x, c->y, c->nx, c->ny, c->kappa, c->w, dtab, X,
-                           frame, da);
+                           frame, nullptr, da);
     return hipGetLastError();
 }
 
 hipError_t near_launch_wall_features(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, double d,
                                      const double *dtab, float *X, double *frame, hipStream_t st,
-                                     const DecideArgs *dec) {
+                                     const DecideArgs *fused, float *nrec) {
     if (t->n <= 0) return hipSuccess;
     // grid-stride: each block builds the cell table once for up to a few
     // thousand targets
     const int64_t blocks = std::min<int64_t>((t->n + 255) / 256, 1024);
-    const DecideArgs da = dec ? *dec : DecideArgs{};
-    if (dec)
-        hipLaunchKernelGGL(near_wall_features<S2D_OP_DLP>, dim3((unsigned)blocks), dim3(256), 0, st, t->n, t->x, t->y,
-                           tc, c->curve_off, c->n_curves, c->n_nodes, c->x, c->y, c->nx, c->ny, c->kappa, c->w, d,
-                           dtab, X, frame, da);
-    else
-        hipLaunchKernelGGL(near_wall_features<-1>, dim3((unsigned)blocks), dim3(256), 0, st, t->n, t->x, t->y, tc,
+    const DecideArgs da = fused ? *fused : DecideArgs{};
+    if (fused)
+        hipLaunchKernelGGL(near_wall_features<true>, dim3((unsigned)blocks), dim3(256), 0, st, t->n, t->x, t->y, tc,
                            c->curve_off, c->n_curves, c->n_nodes, c->x, c->y, c->nx, c->ny, c->kappa, c->w, d, dtab,
-                           X, frame, da);
+                           X, nullptr, nrec, da);
+    else
+        hipLaunchKernelGGL(near_wall_features<false>, dim3((unsigned)blocks), dim3(256), 0, st, t->n, t->x, t->y, tc,
+                           c->curve_off, c->n_curves, c->n_nodes, c->x, c->y, c->nx, c->ny, c->kappa, c->w, d, dtab,
+                           X, frame, nullptr, da);
     return hipGetLastError();
 }
 
-hipError_t near_launch_infer(int op, int64_t n, const float *X, const double *frame, const NearBlob *nb, double mu,
+hipError_t near_launch_infer(int op, int64_t n, const float *X, const float *nrec, const NearBlob *nb,
                              const int32_t *flag, int use_bound, double *du, double *dv, int32_t *lcnt,
                              int32_t *llist, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    // with bounds, the learned targets compacted in order; the straight-line
-    // part a target per lane; the network 64 targets per wave (4 waves per
-    // block, persistent blocks that stage the network in LDS once, four per
-    // compute unit at most)
-    const unsigned fb = grid_for(n);
+    // with bounds, the learned targets compacted in order; the network 64
+    // targets per wave (4 waves per block, persistent blocks that stage the
+    // network in LDS once, four per compute unit at most)
     const int64_t groups = (n + kWave - 1) / kWave;
     const unsigned nbk = (unsigned)std::min<int64_t>((groups + 3) / 4, 4 * kInferCUs);
     const int32_t *list = nullptr, *len = nullptr;
@@ -1889,13 +1907,10 @@ hipError_t near_launch_infer(int op, int64_t n, const float *X, const double *fr
         list = llist;
         len = lcnt + (n + 255) / 256;
     }
-    if (op == S2D_OP_SLP) {
-        hipLaunchKernelGGL(near_flat<S2D_OP_SLP>, dim3(fb), dim3(256), 0, st, n, list, len, frame, nb, mu, du, dv);
-        hipLaunchKernelGGL(near_net<S2D_OP_SLP>, dim3(nbk), dim3(256), 0, st, n, list, len, X, frame, nb, mu, du, dv);
-    } else {
-        hipLaunchKernelGGL(near_flat<S2D_OP_DLP>, dim3(fb), dim3(256), 0, st, n, list, len, frame, nb, mu, du, dv);
-        hipLaunchKernelGGL(near_net<S2D_OP_DLP>, dim3(nbk), dim3(256), 0, st, n, list, len, X, frame, nb, mu, du, dv);
-    }
+    if (op == S2D_OP_SLP)
+        hipLaunchKernelGGL(near_net<S2D_OP_SLP>, dim3(nbk), dim3(256), 0, st, n, list, len, X, nrec, nb, du, dv);
+    else
+        hipLaunchKernelGGL(near_net<S2D_OP_DLP>, dim3(nbk), dim3(256), 0, st, n, list, len, X, nrec, nb, du, dv);
     return hipGetLastError();
 }
 

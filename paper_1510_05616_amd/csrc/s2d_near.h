@@ -85,18 +85,26 @@ struct DecideArgs {
     double *du, *dv;
     int32_t *flag;
 };
-// the feature kernels also take AUTO's decisions when dec != NULL
+// The feature kernels write X and the frame records (fused == NULL), or,
+// for the learned and AUTO routes (fused != NULL), X, AUTO's decisions and,
+// for every target decided learned (all when use_bound == 0), the
+// straight-line part into du, dv and the network's record into nrec
+// [kNetRec floats per target: d_p in the frame (2 p, 2 p + 1), t, n_f,
+// scale exp(-2 pi b)]; frame is not used then.
+constexpr int kNetRec = 16;
 hipError_t near_launch_features(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, const double *dtab,
-                                float *X, double *frame, hipStream_t st, const DecideArgs *dec = nullptr);
+                                float *X, double *frame, hipStream_t st, const DecideArgs *fused = nullptr,
+                                float *nrec = nullptr);
 hipError_t near_launch_wall_features(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, double d,
                                      const double *dtab, float *X, double *frame, hipStream_t st,
-                                     const DecideArgs *dec = nullptr);
+                                     const DecideArgs *fused = nullptr, float *nrec = nullptr);
 // op: S2D_OP_SLP (vesicles, scale hl / 4 pi mu, side +1) or S2D_OP_DLP
 // (walls, scale 1 / pi, side -1)
-// the learned route for the targets with flag 0 (flag from the feature
-// kernels' decisions; use_bound == 0: every target): lcnt, llist are
-// compaction scratch as for near_launch_compact (used when use_bound != 0)
-hipError_t near_launch_infer(int op, int64_t n, const float *X, const double *frame, const NearBlob *nb, double mu,
+// the network's part of the learned route, added to du, dv of the targets
+// with flag 0 (flag from the fused feature kernels; use_bound == 0: every
+// target): lcnt, llist are compaction scratch as for near_launch_compact
+// (used when use_bound != 0)
+hipError_t near_launch_infer(int op, int64_t n, const float *X, const float *nrec, const NearBlob *nb,
                              const int32_t *flag, int use_bound, double *du, double *dv, int32_t *lcnt,
                              int32_t *llist, hipStream_t st);
 hipError_t near_launch_pack(const float *prm, const float *bound, const float *bound_zero, int32_t n_bins,
