@@ -186,11 +186,33 @@ __device__ __forceinline__ void slp64_acc(double px, double py, double sx, doubl
     by = __builtin_fma(ry, t, by);
 }
 
+// The coarse node k and the fine node k P are the same point (the
+// interpolant passes through the nodes): one squared distance, log and
+// reciprocal serve both rules, with the fine record's weight (gfx, gfy) and
+// the coarse one's (gcx, gcy); the node's FP64 coordinates are the coarse
+// record's.
+__device__ __forceinline__ void slp64_acc2(double px, double py, double sx, double sy, double gfx, double gfy,
+                                           double gcx, double gcy, const double *ltab, double (&s)[8]) {
+    const double rx = px - sx, ry = py - sy;
+    const double q = __builtin_fma(rx, rx, ry * ry);
+    const double lq = log64_tab(q, ltab);
+    const double iq = rcp64(q);
+    const double tf = __builtin_fma(rx, gfx, ry * gfy) * iq, tc = __builtin_fma(rx, gcx, ry * gcy) * iq;
+    s[4] = __builtin_fma(gfx, lq, s[4]);
+    s[5] = __builtin_fma(gfy, lq, s[5]);
+    s[6] = __builtin_fma(rx, tf, s[6]);
+    s[7] = __builtin_fma(ry, tf, s[7]);
+    s[0] = __builtin_fma(gcx, lq, s[0]);
+    s[1] = __builtin_fma(gcy, lq, s[1]);
+    s[2] = __builtin_fma(rx, tc, s[2]);
+    s[3] = __builtin_fma(ry, tc, s[3]);
+}
+
 // Part `part` of `parts` of the coarse (N nodes) and fine (P N nodes)
 // single-layer sums of one curve, from the records {x, y, g_x, g_y} written
-// by near_upsample: the sources are taken as one list, the N coarse records
-// then the P N fine ones, cut into `parts` contiguous pieces; coarse sources
-// go to s[0..3], fine ones to s[4..7].
+// by near_upsample: the coarse nodes k of the part (N part / parts <= k <
+// N (part + 1) / parts) with the fine nodes k P .. k P + P - 1 that follow
+// each; coarse sums go to s[0..3], fine ones to s[4..7].
 template <bool UNIFORM>
 __device__ __forceinline__ void near_sums(double px, double py, int lo, int N, int P, int64_t n_src, int part,
                                           int parts, const double *__restrict__ up, const double *ltab,
@@ -199,18 +221,25 @@ __device__ __forceinline__ void near_sums(double px, double py, int lo, int N, i
         lo = __builtin_amdgcn_readfirstlane(lo);
         N = __builtin_amdgcn_readfirstlane(N);
     }
-    const int L = (P + 1) * N;
-    const int a = L * part / parts, b = L * (part + 1) / parts;
+    const int ka = N * part / parts, kb = N * (part + 1) / parts;
     const double *cr = up + 4 * ((int64_t)n_src * P + lo);
-    const int ce = min(b, N);
-#pragma unroll 4
-    for (int k = a; k < ce; ++k)
-        slp64_acc(px, py, cr[4 * k], cr[4 * k + 1], cr[4 * k + 2], cr[4 * k + 3], ltab, s[0], s[1], s[2], s[3]);
     const double *fr = up + 4 * (int64_t)lo * P;
-    const int fb = b - N;
-#pragma unroll 4
-    for (int k = max(a, N) - N; k < fb; ++k)
-        slp64_acc(px, py, fr[4 * k], fr[4 * k + 1], fr[4 * k + 2], fr[4 * k + 3], ltab, s[4], s[5], s[6], s[7]);
+    // the fine nodes between coarse ones alternate between two accumulator
+    // sets (t), added at the end: two independent chains
+    double t[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = ka; k < kb; ++k) {
+        const double *c = cr + 4 * k, *f = fr + 4 * (int64_t)k * P;
+        slp64_acc2(px, py, c[0], c[1], f[2], f[3], c[2], c[3], ltab, s);
+        int j = 1;
+        for (; j + 1 < P; j += 2) {
+            slp64_acc(px, py, f[4 * j], f[4 * j + 1], f[4 * j + 2], f[4 * j + 3], ltab, t[0], t[1], t[2], t[3]);
+            slp64_acc(px, py, f[4 * j + 4], f[4 * j + 5], f[4 * j + 6], f[4 * j + 7], ltab, s[4], s[5], s[6], s[7]);
+        }
+        if (j < P)
+            slp64_acc(px, py, f[4 * j], f[4 * j + 1], f[4 * j + 2], f[4 * j + 3], ltab, t[0], t[1], t[2], t[3]);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) s[4 + e] += t[e];
 }
 
 // Delta for the 64 targets q = 64 blk + lane, or, with an index list, for
@@ -383,16 +412,22 @@ __global__ __launch_bounds__(kCompactBlock) void near_compact_scatter(int64_t n,
 // coefficients a_m, b_m (m = 0..N/2, the Nyquist mode's weight split evenly),
 // then at each node sum_m (m h)^p times the p-th derivative of a_m cos(m t) +
 // b_m sin(m t) at t_k (h = 2 pi / N; the Nyquist term keeps its even
-// derivatives only: the odd ones vanish at the nodes).  A thread takes one
-// coefficient (mode, component) in the first stage and one (node, component)
-// with all five p in the second; each steps cos and sin of the multiple
-// angles by rotation through its base angle (at most 256 steps, rounding
-// growing at most linearly), so no lane gathers from a table.  Invalid
-// curves get NaN.
+// derivatives only: the odd ones vanish at the nodes).  Both stages use the
+// reflection k -> N - k: the coefficients sum the even and odd parts
+// f_k +- f_{N-k} over k < N/2, and a thread of the second stage evaluates the
+// nodes k and N - k together (cos(m t) the same, sin(m t) of opposite sign).
+// A thread takes one coefficient (mode, component) in the first stage and one
+// node pair and component, all five p, in the second; each steps cos and sin
+// of the multiple angles by rotation through its base angle (at most 128
+// steps, rounding growing at most linearly), so no lane gathers from a
+// table; the powers of m h come from a per-mode table in LDS (read as a
+// broadcast).  Invalid curves get NaN.
 __global__ __launch_bounds__(256) void near_derivs(const int32_t *__restrict__ off, int32_t n_curves, int64_t n_src,
                                                    const double *__restrict__ fx, const double *__restrict__ fy,
                                                    double *__restrict__ dtab, int32_t *__restrict__ big) {
     __shared__ double co[2][kUpMaxN / 2 + 1][2];
+    __shared__ double eo[2][kUpMaxN / 2 + 1][2];      // {f_k + f_{N-k}, f_k - f_{N-k}}; k = 0, N/2: {f_k, 0}
+    __shared__ double mp[kUpMaxN / 2 + 1][4];         // m h, -(m h)^2, -(m h)^3, (m h)^4
     const int c = blockIdx.x;
     if (c >= n_curves) return;
     const int lo = off[c], N = off[c + 1] - lo;
@@ -407,16 +442,34 @@ __global__ __launch_bounds__(256) void near_derivs(const int32_t *__restrict__ o
         return;
     }
     const int H = N / 2;
+    const double h = 2.0 * M_PI / (double)N;
+    for (int q = threadIdx.x; q < 2 * (H + 1); q += blockDim.x) {
+        const int comp = q / (H + 1), k = q % (H + 1);
+        const double *f = (comp ? fy : fx) + lo;
+        const bool edge = k == 0 || k == H;
+        const double p = f[k], r = edge ? 0.0 : f[N - k];
+        eo[comp][k][0] = p + r;
+        eo[comp][k][1] = p - r;
+    }
+    for (int m = threadIdx.x; m <= H; m += blockDim.x) {
+        const double mh = (double)m * h, mh2 = mh * mh;
+        mp[m][0] = mh;
+        mp[m][1] = -mh2;
+        mp[m][2] = -mh * mh2;
+        mp[m][3] = mh2 * mh2;
+    }
+    __syncthreads();
     for (int q = threadIdx.x; q < 2 * (H + 1); q += blockDim.x) {
         const int comp = q / (H + 1), m = q % (H + 1);
-        const double *f = (comp ? fy : fx) + lo;
         double cb, sb;                                                 // cos, sin(2 pi m / N)
         sincospi(2.0 * (double)m / (double)N, &sb, &cb);
-        double cm = 1.0, sm = 0.0;                                     // cos, sin(2 pi m k / N)
-        double a = 0.0, b = 0.0;
-        for (int k = 0; k < N; ++k) {
-            a = __builtin_fma(f[k], cm, a);
-            b = __builtin_fma(f[k], sm, b);
+        double cm = cb, sm = sb;                                       // cos, sin(2 pi m k / N), k = 1
+        // k = 0 and k = N/2 (cos = (-1)^m, sin = 0)
+        double a = (m & 1) ? eo[comp][0][0] - eo[comp][H][0] : eo[comp][0][0] + eo[comp][H][0];
+        double b = 0.0;
+        for (int k = 1; k < H; ++k) {
+            a = __builtin_fma(eo[comp][k][0], cm, a);
+            b = __builtin_fma(eo[comp][k][1], sm, b);
             const double cn = __builtin_fma(cm, cb, -sm * sb);
             sm = __builtin_fma(sm, cb, cm * sb);
             cm = cn;
@@ -426,36 +479,50 @@ __global__ __launch_bounds__(256) void near_derivs(const int32_t *__restrict__ o
         co[comp][m][1] = (m == 0 || m == H) ? 0.0 : b * sc;
     }
     __syncthreads();
-    const double h = 2.0 * M_PI / (double)N;
-    for (int q = threadIdx.x; q < 2 * N; q += blockDim.x) {
-        const int k = q >> 1, comp = q & 1;
+    for (int q = threadIdx.x; q < 2 * (H + 1); q += blockDim.x) {
+        const int comp = q / (H + 1), k = q % (H + 1);
+        const bool pair = k != 0 && k != H;                            // node N - k is another node
         double cb, sb;                                                 // cos, sin(2 pi k / N)
         sincospi(2.0 * (double)k / (double)N, &sb, &cb);
         double cm = 1.0, sm = 0.0;                                     // cos, sin(2 pi m k / N)
-        double acc[kNearDeriv];
-        acc[0] = co[comp][0][0];
+        double acc[kNearDeriv], acr[kNearDeriv];                       // node k, node N - k
+        acc[0] = acr[0] = co[comp][0][0];
 #pragma unroll
-        for (int p = 1; p < kNearDeriv; ++p) acc[p] = 0.0;
+        for (int p = 1; p < kNearDeriv; ++p) acc[p] = acr[p] = 0.0;
         for (int m = 1; m <= H; ++m) {
             const double cn = __builtin_fma(cm, cb, -sm * sb);
             sm = __builtin_fma(sm, cb, cm * sb);
             cm = cn;
             const double a = co[comp][m][0], b = co[comp][m][1];
             // (m h)^p times the p-th derivative of a cos + b sin: the
-            // derivatives cycle through g0, g1, -g0, -g1
-            const double g0 = __builtin_fma(a, cm, b * sm), g1 = __builtin_fma(-a, sm, b * cm);
-            const double mh = (double)m * h, mh2 = mh * mh;
+            // derivatives cycle through g0, g1, -g0, -g1; at N - k the sine
+            // changes sign
+            const double bs = b * sm, ac = a * cm;
+            const double g0 = ac + bs, r0 = ac - bs;
+            const double bc = b * cm;
+            const double g1 = __builtin_fma(-a, sm, bc), r1 = __builtin_fma(a, sm, bc);
+            const double p1 = mp[m][0], p2 = mp[m][1], p3 = mp[m][2], p4 = mp[m][3];
             acc[0] += g0;
+            acr[0] += r0;
             if (m < H) {
-                acc[1] = __builtin_fma(mh, g1, acc[1]);
-                acc[3] = __builtin_fma(-mh * mh2, g1, acc[3]);
+                acc[1] = __builtin_fma(p1, g1, acc[1]);
+                acr[1] = __builtin_fma(p1, r1, acr[1]);
+                acc[3] = __builtin_fma(p3, g1, acc[3]);
+                acr[3] = __builtin_fma(p3, r1, acr[3]);
             }
-            acc[2] = __builtin_fma(-mh2, g0, acc[2]);
-            acc[4] = __builtin_fma(mh2 * mh2, g0, acc[4]);
+            acc[2] = __builtin_fma(p2, g0, acc[2]);
+            acr[2] = __builtin_fma(p2, r0, acr[2]);
+            acc[4] = __builtin_fma(p4, g0, acc[4]);
+            acr[4] = __builtin_fma(p4, r0, acr[4]);
         }
         double *row = dtab + ((int64_t)lo + k) * 2 * kNearDeriv + comp;
 #pragma unroll
         for (int p = 0; p < kNearDeriv; ++p) row[2 * p] = acc[p];
+        if (pair) {
+            double *rr = dtab + ((int64_t)lo + N - k) * 2 * kNearDeriv + comp;
+#pragma unroll
+            for (int p = 0; p < kNearDeriv; ++p) rr[2 * p] = acr[p];
+        }
     }
 }
 
