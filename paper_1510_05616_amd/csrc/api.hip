@@ -2,6 +2,7 @@
 // and the launch sequence for each evaluation.  No allocation happens here:
 // all scratch lives in the caller's workspace.
 #include "lu_plan.h"
+#include "s2d_cell.h"
 #include "s2d_internal.h"
 #include "s2d_near.h"
 #include "../../include/stokes2d_vesicle.h"

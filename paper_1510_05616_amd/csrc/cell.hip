@@ -21,6 +21,7 @@
 // Solve: y = A^-1 v (row permutation, forward and backward sweeps),
 // c = S^+ (g - C y), tau = y - X c.
 #include "lu_plan.h"
+#include "s2d_cell.h"
 #include "s2d_internal.h"
 
 #include <rocblas/rocblas.h>
