@@ -212,8 +212,9 @@ __device__ __forceinline__ void slp64_acc2(double px, double py, double sx, doub
 // single-layer sums of one curve, from the records {x, y, g_x, g_y} written
 // by near_upsample: the coarse nodes k of the part (N part / parts <= k <
 // N (part + 1) / parts) with the fine nodes k P .. k P + P - 1 that follow
-// each; coarse sums go to s[0..3], fine ones to s[4..7].
-template <bool UNIFORM>
+// each; coarse sums go to s[0..3], fine ones to s[4..7].  PK: P known at
+// compile time (its fine nodes unrolled), or 0.
+template <bool UNIFORM, int PK>
 __device__ __forceinline__ void near_sums(double px, double py, int lo, int N, int P, int64_t n_src, int part,
                                           int parts, const double *__restrict__ up, const double *ltab,
                                           double (&s)[8]) {
@@ -221,6 +222,7 @@ __device__ __forceinline__ void near_sums(double px, double py, int lo, int N, i
         lo = __builtin_amdgcn_readfirstlane(lo);
         N = __builtin_amdgcn_readfirstlane(N);
     }
+    if (PK > 0) P = PK;
     const int ka = N * part / parts, kb = N * (part + 1) / parts;
     const double *cr = up + 4 * ((int64_t)n_src * P + lo);
     const double *fr = up + 4 * (int64_t)lo * P;
@@ -230,13 +232,26 @@ __device__ __forceinline__ void near_sums(double px, double py, int lo, int N, i
     for (int k = ka; k < kb; ++k) {
         const double *c = cr + 4 * k, *f = fr + 4 * (int64_t)k * P;
         slp64_acc2(px, py, c[0], c[1], f[2], f[3], c[2], c[3], ltab, s);
-        int j = 1;
-        for (; j + 1 < P; j += 2) {
-            slp64_acc(px, py, f[4 * j], f[4 * j + 1], f[4 * j + 2], f[4 * j + 3], ltab, t[0], t[1], t[2], t[3]);
-            slp64_acc(px, py, f[4 * j + 4], f[4 * j + 5], f[4 * j + 6], f[4 * j + 7], ltab, s[4], s[5], s[6], s[7]);
+        if constexpr (PK > 0) {
+#pragma unroll
+            for (int j = 1; j < PK; ++j) {
+                if (j & 1)
+                    slp64_acc(px, py, f[4 * j], f[4 * j + 1], f[4 * j + 2], f[4 * j + 3], ltab, t[0], t[1], t[2],
+                              t[3]);
+                else
+                    slp64_acc(px, py, f[4 * j], f[4 * j + 1], f[4 * j + 2], f[4 * j + 3], ltab, s[4], s[5], s[6],
+                              s[7]);
+            }
+        } else {
+            int j = 1;
+            for (; j + 1 < P; j += 2) {
+                slp64_acc(px, py, f[4 * j], f[4 * j + 1], f[4 * j + 2], f[4 * j + 3], ltab, t[0], t[1], t[2], t[3]);
+                slp64_acc(px, py, f[4 * j + 4], f[4 * j + 5], f[4 * j + 6], f[4 * j + 7], ltab, s[4], s[5], s[6],
+                          s[7]);
+            }
+            if (j < P)
+                slp64_acc(px, py, f[4 * j], f[4 * j + 1], f[4 * j + 2], f[4 * j + 3], ltab, t[0], t[1], t[2], t[3]);
         }
-        if (j < P)
-            slp64_acc(px, py, f[4 * j], f[4 * j + 1], f[4 * j + 2], f[4 * j + 3], ltab, t[0], t[1], t[2], t[3]);
     }
 #pragma unroll
     for (int e = 0; e < 4; ++e) s[4 + e] += t[e];
@@ -297,9 +312,11 @@ __global__ __launch_bounds__(64 * kQuadParts) void near_quad(int64_t n_trg, cons
         // idle lanes follow the wave's curve (their results are dropped)
         const int cu = __builtin_amdgcn_readfirstlane(cmin);
         const int lou = off[cu], Nu = off[cu + 1] - lou;
-        near_sums<true>(px, py, lou, Nu, P, n_src, part, kQuadParts, up, ltab, s);
+        if (P == 8) near_sums<true, 8>(px, py, lou, Nu, P, n_src, part, kQuadParts, up, ltab, s);
+        else near_sums<true, 0>(px, py, lou, Nu, P, n_src, part, kQuadParts, up, ltab, s);
     } else if (ok) {
-        near_sums<false>(px, py, lo, N, P, n_src, part, kQuadParts, up, ltab, s);
+        if (P == 8) near_sums<false, 8>(px, py, lo, N, P, n_src, part, kQuadParts, up, ltab, s);
+        else near_sums<false, 0>(px, py, lo, N, P, n_src, part, kQuadParts, up, ltab, s);
     }
     if (part > 0) {
 #pragma unroll
