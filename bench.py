@@ -142,6 +142,32 @@ def copy_probe():
     print(f"copied 3 x {4 * n} bytes", flush=True)
 
 
+def near_probe(reps=3):
+    """The near-field routes alone, for kernel traces and counters: the
+    upsampled route and the learned route (every target) on the 1e6-target
+    test set, with an untrained packed network (the kernels' work does not
+    depend on the weights), reps times each."""
+    import torch
+    import synth
+    import paper_1510_05616_amd as s2d
+    from paper_1510_05616_amd import near
+    s2d.stokes2d_init(0)
+    te = near.NearData(*synth.make_near_dataset(1000000, 7)[:4], mu=1.0, upsample=8, labels=False)
+    prm = torch.as_tensor(near.init_weights(0), dtype=torch.float32, device="cuda")
+    blob = torch.empty(near.near_mlp_blob_size(), dtype=torch.uint8, device="cuda")
+    near.near_mlp_pack(prm, torch.zeros(64 * near.CELL, dtype=torch.float32, device="cuda"), near.N_BINS,
+                       near.BIN_LO, near.BIN_W, blob)
+    du = torch.empty(te.n, dtype=torch.float64, device="cuda")
+    dv = torch.empty_like(du)
+    for name, m in (("upsampled", near.S2D_NEAR_UPSAMPLE), ("learned", near.S2D_NEAR_MLP)):
+        for r in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            te.correct(m, blob, 0.0, du, dv)
+            torch.cuda.synchronize()
+            print(f"{name} route {r}: {(time.perf_counter() - t0) * 1e3:.3f} ms", flush=True)
+
+
 def load_problem(cfg: int):
     import synth
     t0 = time.time()
@@ -837,9 +863,14 @@ def main():
     ap.add_argument("--copy-probe", action="store_true", help="only copy 1 GiB on the device and exit")
     ap.add_argument("--issue-probe", action="store_true",
                     help="only run the VALU issue-rate probes, print their rates and exit")
+    ap.add_argument("--near-probe", action="store_true",
+                    help="only run the upsampled and learned near-field routes on 1e6 targets and exit")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
+        return
+    if args.near_probe:
+        near_probe()
         return
     if args.issue_probe:
         import torch
