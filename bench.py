@@ -610,9 +610,10 @@ def channel_section(prob, steps=2, dt=1e-4, kappa_b=1.0, p_drive=10.0, n_proxy=1
     out = {"workload": f"Algorithm 1 in the 128k channel: walls at 2 x {wall_nodes:,} nodes, K = 32, M = 128 (cell factored "
                        "once), 1,000 vesicles x 96 nodes, dt = %g, kappa_B = %g, p_drive = %g per period; "
                        "response in FP64, the step solved to 1e-10 with FP64 sums (f64) or by FP32C corrections "
-                       "with FP64 residuals (f32)" % (dt, kappa_b, p_drive),
+                       "with FP64 residuals (f32; f32_near: with close evaluation of near vesicle pairs, 8x "
+                       "upsampled, band 5 spacings)" % (dt, kappa_b, p_drive),
            "cell_factor_s": t_factor}
-    for name, mode in (("f64", 0), ("f32", 1)):
+    for name, mode, near in (("f64", 0, 0), ("f32", 1, 0), ("f32_near", 1, 1)):
         V = pv.Vesicles(ves.x, ves.y, ves.curve_off)
         L0, A0 = V.measure()
         ws = None
@@ -626,7 +627,7 @@ def channel_section(prob, steps=2, dt=1e-4, kappa_b=1.0, p_drive=10.0, n_proxy=1
             ur = V.channel_response(cell, fx, fy, p_drive)
             ev[1].record()
             p = pv.params(mode=mode, dt=dt, kappa_b=kappa_b, mu=prob.mu, d=prob.d, img_lo=-1, img_hi=1, L0=L0,
-                          u_resp=ur, tol=1e-10, nmax=96)
+                          u_resp=ur, tol=1e-10, nmax=96, near=near, near_P=8, near_band=5.0, near_max=1 << 22)
             ws = V.workspace(p) if ws is None else ws
             it, res = V.time_step(p, A0=A0, ws=ws)
             torch.cuda.synchronize()
