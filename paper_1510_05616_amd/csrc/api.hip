@@ -32,6 +32,13 @@ struct DevState {
     bool init = false;
     int cus = 256;
     void *scratch = nullptr;     // this device's copy of `scratch`
+    // AUTO's second stream (default priority) and its fork / join events:
+    // the upsampling runs beside the learned route's first kernels and the
+    // fallback quadrature beside the network; side_mu orders the calls that
+    // use them
+    hipStream_t side = nullptr;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    std::mutex side_mu;
 };
 constexpr int kMaxDev = 64;
 DevState g_dev[kMaxDev];
@@ -260,6 +267,12 @@ S2D_API int stokes2d_init(int device) {
         e = hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch));
         if (e != hipSuccess || !sp) return hip_fail(e, "hipGetSymbolAddress(scratch)");
         g_dev[device].scratch = sp;
+    }
+    if (!g_dev[device].side) {
+        e = hipStreamCreateWithFlags(&g_dev[device].side, hipStreamNonBlocking);
+        for (int k = 0; k < 3 && e == hipSuccess; ++k)
+            e = hipEventCreateWithFlags(&g_dev[device].ev[k], hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "AUTO side stream");
     }
     g_dev[device].init = true;
     return S2D_OK;
@@ -771,38 +784,73 @@ S2D_API int near_correct_eval(int method, const s2d_curves *ves, const s2d_targe
     char *w = (char *)ws;
     double *up = (double *)(w + L.up);
     hipError_t e = hipSuccess;
-    if (method != S2D_NEAR_MLP) {
+    if (method == S2D_NEAR_UPSAMPLE) {
         e = s2d::near_launch_upsample(ves, upsample, up, st);
         if (e != hipSuccess) return hip_fail(e, "near upsample launch");
-    }
-    if (method == S2D_NEAR_UPSAMPLE) {
         e = s2d::near_launch_quad(ves, trg, trg_curve, nullptr, nullptr, upsample, up, mu, du, dv, st);
         if (e != hipSuccess) return hip_fail(e, "near quadrature launch");
         return S2D_OK;
     }
     double *dtab = (double *)(w + L.dtab);
     float *X = (float *)(w + L.X), *nrec = (float *)(w + L.nrec);
-    e = s2d::near_launch_derivs(ves, dtab, w + L.dscr, st);
-    if (e != hipSuccess) return hip_fail(e, "near derivative launch");
     const bool autom = method == S2D_NEAR_AUTO;
     // the per-target decisions: the caller's array or the workspace
     int32_t *flag = used_fallback ? used_fallback : (int32_t *)(w + L.flag);
     const s2d::DecideArgs da{(const s2d::NearBlob *)mlp, mu, threshold, curve_tol, ves->n_curves, autom ? 1 : 0,
                              du, dv, flag};
+    const int64_t nb = (trg->n + 255) / 256;
+    int32_t *lcnt = (int32_t *)(w + L.lcount), *llist = (int32_t *)(w + L.llist);
+    int32_t *fcnt = (int32_t *)(w + L.count), *flist = (int32_t *)(w + L.list);
+    // AUTO outside stream capture: the upsampling and the fallback
+    // quadrature on the device's second stream (fork / join by events)
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (autom) {
+        e = hipStreamIsCapturing(st, &cap);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
+    }
+    DevState &D = g_dev[dev];
+    const bool two = autom && cap == hipStreamCaptureStatusNone && D.side;
+    std::unique_lock<std::mutex> lk(D.side_mu, std::defer_lock);
+    hipStream_t sd = st;
+    if (two) {
+        lk.lock();
+        sd = D.side;
+        e = hipEventRecord(D.ev[0], st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(sd, D.ev[0], 0);
+        if (e != hipSuccess) return hip_fail(e, "near AUTO fork");
+    }
+    if (autom) {
+        e = s2d::near_launch_upsample(ves, upsample, up, sd);
+        if (e != hipSuccess) return hip_fail(e, "near upsample launch");
+    }
+    e = s2d::near_launch_derivs(ves, dtab, w + L.dscr, st);
+    if (e != hipSuccess) return hip_fail(e, "near derivative launch");
     e = s2d::near_launch_features(ves, trg, trg_curve, dtab, X, nullptr, st, &da, nrec);
     if (e != hipSuccess) return hip_fail(e, "near features launch");
-    e = s2d::near_launch_infer(S2D_OP_SLP, trg->n, X, nrec, (const s2d::NearBlob *)mlp, flag, autom ? 1 : 0, du, dv,
-                               (int32_t *)(w + L.lcount), (int32_t *)(w + L.llist), st);
+    if (!autom) {
+        e = s2d::near_launch_infer(S2D_OP_SLP, trg->n, X, nrec, (const s2d::NearBlob *)mlp, nullptr, nullptr, du,
+                                   dv, st);
+        return e == hipSuccess ? S2D_OK : hip_fail(e, "near MLP launch");
+    }
+    // the learned and the fallback targets, each compacted in order (the
+    // quadrature's cost follows the fallback targets' number rather than the
+    // waves that hold one)
+    e = s2d::near_launch_compact(trg->n, flag, 0, lcnt, llist, st, 1, fcnt, flist);
+    if (e != hipSuccess) return hip_fail(e, "near compaction launch");
+    if (two) {
+        e = hipEventRecord(D.ev[1], st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(sd, D.ev[1], 0);
+        if (e != hipSuccess) return hip_fail(e, "near AUTO fallback fork");
+    }
+    e = s2d::near_launch_quad(ves, trg, trg_curve, flist, fcnt + nb, upsample, up, mu, du, dv, sd);
+    if (e != hipSuccess) return hip_fail(e, "near fallback launch");
+    e = s2d::near_launch_infer(S2D_OP_SLP, trg->n, X, nrec, (const s2d::NearBlob *)mlp, llist, lcnt + nb, du, dv,
+                               st);
     if (e != hipSuccess) return hip_fail(e, "near MLP launch");
-    if (autom) {
-        // the fallback targets, compacted in order, so that the quadrature's
-        // cost follows their number rather than the waves that hold one
-        int32_t *list = (int32_t *)(w + L.list), *cnt = (int32_t *)(w + L.count);
-        e = s2d::near_launch_compact(trg->n, flag, 1, cnt, list, st);
-        if (e != hipSuccess) return hip_fail(e, "near fallback compaction launch");
-        e = s2d::near_launch_quad(ves, trg, trg_curve, list, cnt + (trg->n + 255) / 256, upsample, up, mu, du, dv,
-                                  st);
-        if (e != hipSuccess) return hip_fail(e, "near fallback launch");
+    if (two) {
+        e = hipEventRecord(D.ev[2], sd);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, D.ev[2], 0);
+        if (e != hipSuccess) return hip_fail(e, "near AUTO join");
     }
     return S2D_OK;
 }
@@ -1252,8 +1300,15 @@ S2D_API int near_wall_correct_eval(int method, const s2d_curves *walls, const s2
                              tu, tv, flag};
     e = s2d::near_launch_wall_features(walls, trg, trg_curve, d, dtab, X, nullptr, st, &da, nrec);
     if (e != hipSuccess) return hip_fail(e, "near-wall features launch");
-    e = s2d::near_launch_infer(S2D_OP_DLP, n, X, nrec, (const s2d::NearBlob *)mlp, flag, autom ? 1 : 0, tu, tv,
-                               (int32_t *)(base + L.lcount), (int32_t *)(base + L.llist), st);
+    const int32_t *llist = nullptr, *llen = nullptr;
+    if (autom) {
+        int32_t *lcnt = (int32_t *)(base + L.lcount);
+        e = s2d::near_launch_compact(n, flag, 0, lcnt, (int32_t *)(base + L.llist), st);
+        if (e != hipSuccess) return hip_fail(e, "near-wall compaction launch");
+        llist = (const int32_t *)(base + L.llist);
+        llen = lcnt + (n + 255) / 256;
+    }
+    e = s2d::near_launch_infer(S2D_OP_DLP, n, X, nrec, (const s2d::NearBlob *)mlp, llist, llen, tu, tv, st);
     if (e != hipSuccess) return hip_fail(e, "near-wall MLP launch");
     if (autom) {
         // the fallback targets: the refined quadrature at a compacted list

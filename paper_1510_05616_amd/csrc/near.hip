@@ -345,69 +345,107 @@ __global__ __launch_bounds__(64 * kQuadParts) void near_quad(int64_t n_trg, cons
 }
 
 // Order-keeping compaction of the targets with flag == value (AUTO's
-// learned and fallback targets): per-workgroup counts, one exclusive scan,
-// then each workgroup writes its targets' indices at its offset in target
-// order.
+// learned and fallback targets, one or both in the same pass): per-workgroup
+// counts, one exclusive scan per value, then each workgroup writes its
+// targets' indices at its offset in target order.
 constexpr int kCompactBlock = 256;
+constexpr int kScanThreads = 1024;
 
-__device__ __forceinline__ uint64_t flag_ballot(int64_t n, const int32_t *__restrict__ flag, int64_t i, int value) {
-    return __ballot(i < n && flag[i] == value);
+// one compaction: targets with flag == value into list, per-workgroup
+// counts (then their exclusive scan and the total) in cnt; list == NULL
+// switches it off
+struct CompactOut {
+    int value;
+    int32_t *cnt, *list;
+};
+
+__device__ __forceinline__ int compact_flag(int64_t n, const int32_t *__restrict__ flag, int64_t i) {
+    return i < n ? flag[i] : -1;
 }
 
 __global__ __launch_bounds__(kCompactBlock) void near_compact_count(int64_t n, const int32_t *__restrict__ flag,
-                                                                    int value, int32_t *__restrict__ cnt) {
-    __shared__ int wsum[kCompactBlock / kWave];
+                                                                    CompactOut a, CompactOut b) {
+    __shared__ int wsum[2][kCompactBlock / kWave];
     const int64_t i = (int64_t)blockIdx.x * kCompactBlock + threadIdx.x;
-    const uint64_t b = flag_ballot(n, flag, i, value);
-    if ((threadIdx.x & (kWave - 1)) == 0) wsum[threadIdx.x / kWave] = __popcll(b);
+    const int f = compact_flag(n, flag, i);
+    const uint64_t ba = __ballot(f == a.value), bb = __ballot(f == b.value);
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        wsum[0][threadIdx.x / kWave] = __popcll(ba);
+        wsum[1][threadIdx.x / kWave] = __popcll(bb);
+    }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < 2) {
+        const CompactOut &o = threadIdx.x == 0 ? a : b;
         int s = 0;
-        for (int w = 0; w < kCompactBlock / kWave; ++w) s += wsum[w];
-        cnt[blockIdx.x] = s;
+        for (int w = 0; w < kCompactBlock / kWave; ++w) s += wsum[threadIdx.x][w];
+        if (o.list) o.cnt[blockIdx.x] = s;
     }
 }
 
-// exclusive scan of cnt[0 .. nb) in place, total in cnt[nb]; one workgroup
-// of 1024 threads, each over a contiguous segment
-__global__ __launch_bounds__(1024) void near_compact_scan(int64_t nb, int32_t *__restrict__ cnt) {
-    __shared__ int64_t part[1024];
-    const int64_t seg = (nb + 1023) / 1024;
+// exclusive scan of cnt[0 .. nb) in place, total in cnt[nb]: workgroup 0
+// scans a's counts, workgroup 1 b's; each thread sums a contiguous segment,
+// the segment sums are scanned by wave prefix sums and the waves' totals,
+// then each thread writes its segment's prefixes
+__global__ __launch_bounds__(kScanThreads) void near_compact_scan(int64_t nb, CompactOut a, CompactOut b) {
+    __shared__ int wtot[kScanThreads / kWave];
+    const CompactOut &o = blockIdx.x == 0 ? a : b;
+    if (!o.list) return;                                   // workgroup-uniform
+    int32_t *cnt = o.cnt;
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int64_t seg = (nb + kScanThreads - 1) / kScanThreads;
     const int64_t b0 = min((int64_t)threadIdx.x * seg, nb), b1 = min(b0 + seg, nb);
-    int64_t s = 0;
-    for (int64_t b = b0; b < b1; ++b) s += cnt[b];
-    part[threadIdx.x] = s;
+    int s = 0;
+    for (int64_t k = b0; k < b1; ++k) s += cnt[k];
+    int x = s;                                             // inclusive prefix within the wave
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int y = __shfl_up(x, d, kWave);
+        if (lane >= d) x += y;
+    }
+    if (lane == kWave - 1) wtot[wv] = x;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t run = 0;
-        for (int k = 0; k < 1024; ++k) {
-            const int64_t v = part[k];
-            part[k] = run;
-            run += v;
+    if (wv == 0) {
+        int t = lane < kScanThreads / kWave ? wtot[lane] : 0;
+#pragma unroll
+        for (int d = 1; d < kScanThreads / kWave; d <<= 1) {
+            const int y = __shfl_up(t, d, kWave);
+            if (lane >= d) t += y;
         }
-        cnt[nb] = (int32_t)run;
+        if (lane < kScanThreads / kWave) wtot[lane] = t;   // inclusive totals
     }
     __syncthreads();
-    int64_t run = part[threadIdx.x];
-    for (int64_t b = b0; b < b1; ++b) {
-        const int32_t v = cnt[b];
-        cnt[b] = (int32_t)run;
+    int run = x - s + (wv > 0 ? wtot[wv - 1] : 0);
+    for (int64_t k = b0; k < b1; ++k) {
+        const int v = cnt[k];
+        cnt[k] = run;
         run += v;
     }
+    if (threadIdx.x == kScanThreads - 1) cnt[nb] = wtot[kScanThreads / kWave - 1];
 }
 
 __global__ __launch_bounds__(kCompactBlock) void near_compact_scatter(int64_t n, const int32_t *__restrict__ flag,
-                                                                      int value, const int32_t *__restrict__ cnt,
-                                                                      int32_t *__restrict__ list) {
-    __shared__ int wsum[kCompactBlock / kWave];
+                                                                      CompactOut a, CompactOut b) {
+    __shared__ int wsum[2][kCompactBlock / kWave];
     const int64_t i = (int64_t)blockIdx.x * kCompactBlock + threadIdx.x;
-    const uint64_t b = flag_ballot(n, flag, i, value);
+    const int f = compact_flag(n, flag, i);
+    const uint64_t ba = __ballot(f == a.value), bb = __ballot(f == b.value);
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    if (lane == 0) wsum[w] = __popcll(b);
+    if (lane == 0) {
+        wsum[0][w] = __popcll(ba);
+        wsum[1][w] = __popcll(bb);
+    }
     __syncthreads();
-    int base = cnt[blockIdx.x];
-    for (int k = 0; k < w; ++k) base += wsum[k];
-    if ((b >> lane) & 1) list[base + __popcll(b & ((1ull << lane) - 1))] = (int32_t)i;
+    const uint64_t below = (1ull << lane) - 1;
+    if (a.list && ((ba >> lane) & 1)) {
+        int base = a.cnt[blockIdx.x];
+        for (int k = 0; k < w; ++k) base += wsum[0][k];
+        a.list[base + __popcll(ba & below)] = (int32_t)i;
+    }
+    if (b.list && ((bb >> lane) & 1)) {
+        int base = b.cnt[blockIdx.x];
+        for (int k = 0; k < w; ++k) base += wsum[1][k];
+        b.list[base + __popcll(bb & below)] = (int32_t)i;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1902,13 +1940,13 @@ hipError_t near_launch_quad(const s2d_curves *c, const s2d_targets *t, const int
 }
 
 hipError_t near_launch_compact(int64_t n, const int32_t *flag, int value, int32_t *cnt, int32_t *list,
-                               hipStream_t st) {
+                               hipStream_t st, int value2, int32_t *cnt2, int32_t *list2) {
     if (n <= 0) return hipSuccess;
     const int64_t nb = (n + kCompactBlock - 1) / kCompactBlock;
-    hipLaunchKernelGGL(near_compact_count, dim3((unsigned)nb), dim3(kCompactBlock), 0, st, n, flag, value, cnt);
-    hipLaunchKernelGGL(near_compact_scan, dim3(1), dim3(1024), 0, st, nb, cnt);
-    hipLaunchKernelGGL(near_compact_scatter, dim3((unsigned)nb), dim3(kCompactBlock), 0, st, n, flag, value, cnt,
-                       list);
+    const CompactOut a{value, cnt, list}, b{list2 ? value2 : -2, list2 ? cnt2 : nullptr, list2};
+    hipLaunchKernelGGL(near_compact_count, dim3((unsigned)nb), dim3(kCompactBlock), 0, st, n, flag, a, b);
+    hipLaunchKernelGGL(near_compact_scan, dim3(list2 ? 2 : 1), dim3(kScanThreads), 0, st, nb, a, b);
+    hipLaunchKernelGGL(near_compact_scatter, dim3((unsigned)nb), dim3(kCompactBlock), 0, st, n, flag, a, b);
     return hipGetLastError();
 }
 
@@ -1976,25 +2014,16 @@ hipError_t near_launch_wall_features(const s2d_curves *c, const s2d_targets *t, 
 }
 
 hipError_t near_launch_infer(int op, int64_t n, const float *X, const float *nrec, const NearBlob *nb,
-                             const int32_t *flag, int use_bound, double *du, double *dv, int32_t *lcnt,
-                             int32_t *llist, hipStream_t st) {
+                             const int32_t *list, const int32_t *list_len, double *du, double *dv, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    // with bounds, the learned targets compacted in order; the network 64
-    // targets per wave (4 waves per block, persistent blocks that stage the
-    // network in LDS once, four per compute unit at most)
+    // the network 64 targets per wave (4 waves per block, persistent blocks
+    // that stage the network in LDS once, four per compute unit at most)
     const int64_t groups = (n + kWave - 1) / kWave;
     const unsigned nbk = (unsigned)std::min<int64_t>((groups + 3) / 4, 4 * kInferCUs);
-    const int32_t *list = nullptr, *len = nullptr;
-    if (use_bound) {
-        hipError_t e = near_launch_compact(n, flag, 0, lcnt, llist, st);
-        if (e != hipSuccess) return e;
-        list = llist;
-        len = lcnt + (n + 255) / 256;
-    }
     if (op == S2D_OP_SLP)
-        hipLaunchKernelGGL(near_net<S2D_OP_SLP>, dim3(nbk), dim3(256), 0, st, n, list, len, X, nrec, nb, du, dv);
+        hipLaunchKernelGGL(near_net<S2D_OP_SLP>, dim3(nbk), dim3(256), 0, st, n, list, list_len, X, nrec, nb, du, dv);
     else
-        hipLaunchKernelGGL(near_net<S2D_OP_DLP>, dim3(nbk), dim3(256), 0, st, n, list, len, X, nrec, nb, du, dv);
+        hipLaunchKernelGGL(near_net<S2D_OP_DLP>, dim3(nbk), dim3(256), 0, st, n, list, list_len, X, nrec, nb, du, dv);
     return hipGetLastError();
 }
 

@@ -64,9 +64,11 @@ hipError_t near_launch_quad(const s2d_curves *c, const s2d_targets *t, const int
                             hipStream_t st, double *uf = nullptr, double *vf = nullptr, double *uc = nullptr,
                             double *vc = nullptr);
 // the targets with flag == value, in order, into list; their number into
-// cnt[ceil(n / 256)] (cnt: ceil(n / 256) + 1 ints of scratch)
+// cnt[ceil(n / 256)] (cnt: ceil(n / 256) + 1 ints of scratch); with list2,
+// in the same pass the targets with flag == value2 into list2 (count in
+// cnt2 likewise)
 hipError_t near_launch_compact(int64_t n, const int32_t *flag, int value, int32_t *cnt, int32_t *list,
-                               hipStream_t st);
+                               hipStream_t st, int value2 = 0, int32_t *cnt2 = nullptr, int32_t *list2 = nullptr);
 // the density's node derivatives (kNearDeriv x 2 doubles per node, d_p of x
 // then y at 2p, 2p + 1), per-node units
 // scratch: near_derivs_scratch(c) bytes (256-byte aligned): a flag, and
@@ -101,12 +103,10 @@ hipError_t near_launch_wall_features(const s2d_curves *c, const s2d_targets *t, 
 // op: S2D_OP_SLP (vesicles, scale hl / 4 pi mu, side +1) or S2D_OP_DLP
 // (walls, scale 1 / pi, side -1)
 // the network's part of the learned route, added to du, dv of the targets
-// with flag 0 (flag from the fused feature kernels; use_bound == 0: every
-// target): lcnt, llist are compaction scratch as for near_launch_compact
-// (used when use_bound != 0)
+// list[q], q < *list_len (device; the learned targets of AUTO compacted by
+// near_launch_compact), or of every target when list is NULL
 hipError_t near_launch_infer(int op, int64_t n, const float *X, const float *nrec, const NearBlob *nb,
-                             const int32_t *flag, int use_bound, double *du, double *dv, int32_t *lcnt,
-                             int32_t *llist, hipStream_t st);
+                             const int32_t *list, const int32_t *list_len, double *du, double *dv, hipStream_t st);
 hipError_t near_launch_pack(const float *prm, const float *bound, const float *bound_zero, int32_t n_bins,
                             float bin_lo, float bin_w, float b_min, int32_t P, NearBlob *nb, hipStream_t st);
 hipError_t near_launch_train_targets(int op, int64_t n, const double *frame, const double *du, const double *dv,
