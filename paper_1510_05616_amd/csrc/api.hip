@@ -32,10 +32,9 @@ struct DevState {
     bool init = false;
     int cus = 256;
     void *scratch = nullptr;     // this device's copy of `scratch`
-    // AUTO's second stream (default priority) and its fork / join events:
-    // the upsampling runs beside the learned route's first kernels and the
-    // fallback quadrature beside the network; side_mu orders the calls that
-    // use them
+    // AUTO's second stream (default priority) and its events: the
+    // derivatives run beside the nearest-node search and the upsampling
+    // beside the head kernel; side_mu orders the calls that use them
     hipStream_t side = nullptr;
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     std::mutex side_mu;
@@ -801,15 +800,29 @@ S2D_API int near_correct_eval(int method, const s2d_curves *ves, const s2d_targe
     const int64_t nb = (trg->n + 255) / 256;
     int32_t *lcnt = (int32_t *)(w + L.lcount), *llist = (int32_t *)(w + L.llist);
     int32_t *fcnt = (int32_t *)(w + L.count), *flist = (int32_t *)(w + L.list);
-    // AUTO outside stream capture: the upsampling and the fallback
-    // quadrature on the device's second stream (fork / join by events)
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    if (autom) {
-        e = hipStreamIsCapturing(st, &cap);
-        if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
+    // the nearest nodes, from the search to the head kernel, in the fallback
+    // list's area (the compaction writes it only after the head kernel)
+    int32_t *kstar = flist;
+    if (!autom) {
+        // the learned route: derivatives, then the search, features and head
+        // in one launch, then the network
+        e = s2d::near_launch_derivs(ves, dtab, w + L.dscr, st);
+        if (e != hipSuccess) return hip_fail(e, "near derivative launch");
+        e = s2d::near_launch_head(ves, trg, trg_curve, dtab, nullptr, da, nrec, st, X);
+        if (e != hipSuccess) return hip_fail(e, "near features launch");
+        e = s2d::near_launch_infer(S2D_OP_SLP, trg->n, X, nrec, (const s2d::NearBlob *)mlp, nullptr, nullptr, du,
+                                   dv, st);
+        return e == hipSuccess ? S2D_OK : hip_fail(e, "near MLP launch");
     }
+    // AUTO outside stream capture: the derivatives and the upsampling on the
+    // device's second stream, beside the nearest-node search and the head
+    // kernel (fork / join by events); under capture every kernel stays on
+    // the caller's stream in the same order, with the same results
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    e = hipStreamIsCapturing(st, &cap);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
     DevState &D = g_dev[dev];
-    const bool two = autom && cap == hipStreamCaptureStatusNone && D.side;
+    const bool two = cap == hipStreamCaptureStatusNone && D.side;
     std::unique_lock<std::mutex> lk(D.side_mu, std::defer_lock);
     hipStream_t sd = st;
     if (two) {
@@ -817,41 +830,33 @@ S2D_API int near_correct_eval(int method, const s2d_curves *ves, const s2d_targe
         sd = D.side;
         e = hipEventRecord(D.ev[0], st);
         if (e == hipSuccess) e = hipStreamWaitEvent(sd, D.ev[0], 0);
-        if (e != hipSuccess) return hip_fail(e, "near AUTO fork");
+        if (e != hipSuccess) return hip_fail(e, "near fork");
     }
-    if (autom) {
-        e = s2d::near_launch_upsample(ves, upsample, up, sd);
-        if (e != hipSuccess) return hip_fail(e, "near upsample launch");
-    }
-    e = s2d::near_launch_derivs(ves, dtab, w + L.dscr, st);
+    // the derivatives (the longer of the two chains) first, then the search
+    e = s2d::near_launch_derivs(ves, dtab, w + L.dscr, sd);
     if (e != hipSuccess) return hip_fail(e, "near derivative launch");
-    e = s2d::near_launch_features(ves, trg, trg_curve, dtab, X, nullptr, st, &da, nrec);
-    if (e != hipSuccess) return hip_fail(e, "near features launch");
-    if (!autom) {
-        e = s2d::near_launch_infer(S2D_OP_SLP, trg->n, X, nrec, (const s2d::NearBlob *)mlp, nullptr, nullptr, du,
-                                   dv, st);
-        return e == hipSuccess ? S2D_OK : hip_fail(e, "near MLP launch");
-    }
+    if (two && (e = hipEventRecord(D.ev[1], sd)) != hipSuccess) return hip_fail(e, "near derivative event");
+    e = s2d::near_launch_scan(ves, trg, trg_curve, X, kstar, st);
+    if (e != hipSuccess) return hip_fail(e, "near nearest-node launch");
+    e = s2d::near_launch_upsample(ves, upsample, up, sd);
+    if (e != hipSuccess) return hip_fail(e, "near upsample launch");
+    if (two && (e = hipEventRecord(D.ev[2], sd)) != hipSuccess) return hip_fail(e, "near upsample event");
+    if (two && (e = hipStreamWaitEvent(st, D.ev[1], 0)) != hipSuccess) return hip_fail(e, "near derivative wait");
+    e = s2d::near_launch_head(ves, trg, trg_curve, dtab, kstar, da, nrec, st);
+    if (e != hipSuccess) return hip_fail(e, "near head launch");
     // the learned and the fallback targets, each compacted in order (the
     // quadrature's cost follows the fallback targets' number rather than the
-    // waves that hold one)
+    // waves that hold one); the network, then the quadrature once the
+    // upsampling is done (the network's persistent workgroups hold every
+    // SIMD's registers, so the two would not overlap anyway)
     e = s2d::near_launch_compact(trg->n, flag, 0, lcnt, llist, st, 1, fcnt, flist);
     if (e != hipSuccess) return hip_fail(e, "near compaction launch");
-    if (two) {
-        e = hipEventRecord(D.ev[1], st);
-        if (e == hipSuccess) e = hipStreamWaitEvent(sd, D.ev[1], 0);
-        if (e != hipSuccess) return hip_fail(e, "near AUTO fallback fork");
-    }
-    e = s2d::near_launch_quad(ves, trg, trg_curve, flist, fcnt + nb, upsample, up, mu, du, dv, sd);
-    if (e != hipSuccess) return hip_fail(e, "near fallback launch");
     e = s2d::near_launch_infer(S2D_OP_SLP, trg->n, X, nrec, (const s2d::NearBlob *)mlp, llist, lcnt + nb, du, dv,
                                st);
     if (e != hipSuccess) return hip_fail(e, "near MLP launch");
-    if (two) {
-        e = hipEventRecord(D.ev[2], sd);
-        if (e == hipSuccess) e = hipStreamWaitEvent(st, D.ev[2], 0);
-        if (e != hipSuccess) return hip_fail(e, "near AUTO join");
-    }
+    if (two && (e = hipStreamWaitEvent(st, D.ev[2], 0)) != hipSuccess) return hip_fail(e, "near upsample wait");
+    e = s2d::near_launch_quad(ves, trg, trg_curve, flist, fcnt + nb, upsample, up, mu, du, dv, st);
+    if (e != hipSuccess) return hip_fail(e, "near fallback launch");
     return S2D_OK;
 }
 

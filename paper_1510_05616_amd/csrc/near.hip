@@ -259,10 +259,10 @@ __device__ __forceinline__ void near_sums(double px, double py, int lo, int N, i
 
 // Delta for the 64 targets q = 64 blk + lane, or, with an index list, for
 // targets list[q], q < *list_len (the list keeps the targets' order, so its
-// waves stay on one curve).  The four waves of the workgroup take the
-// same targets and a quarter of the sources each; wave 0 adds the other
-// three's partial sums in fixed order.  Short workgroups keep the launch
-// balanced across curves of different sizes.  When every live target of the
+// waves stay on one curve).  The kQuadParts waves of the workgroup take the
+// same targets and an equal share of the coarse nodes (with their fine
+// nodes) each; wave 0 adds the others' partial sums in fixed order.  Short
+// workgroups keep the launch balanced across curves of different sizes.  When every live target of the
 // wave lies on the same curve (targets sorted by curve), the source loops are
 // wave-uniform and their loads go through the scalar path.
 constexpr int kQuadParts = 4;
@@ -725,9 +725,9 @@ __global__ __launch_bounds__(256) void near_derivs_nodes(const int32_t *__restri
 // k* - 2, k* - 1, k* + 1, k* + 2: xi = [s, b, ln(|p - x_k*| / hl), sg kap hl,
 // the four nodes in the frame (units hl), Re Q, Im Q], Q = exp(-2 pi (b + i s));
 // fr[0..8] = s, b, t, n_f, hl, (F later), sg; fr[19] = sg kap hl.
-__device__ void near_frame_features(double px, double py, double X, double Y, double NX, double NY, double kap,
-                                    double hl, const double (&nb)[4][2], float *__restrict__ xi,
-                                    double *__restrict__ fr) {
+__device__ __forceinline__ void near_frame_features(double px, double py, double X, double Y, double NX,
+                                                    double NY, double kap, double hl, const double (&nb)[4][2],
+                                                    float *__restrict__ xi, double *__restrict__ fr) {
     const double st = ((nb[2][0] - nb[1][0]) * -NY + (nb[2][1] - nb[1][1]) * NX) >= 0.0 ? 1.0 : -1.0;
     const double tx = -st * NY, ty = st * NX;
     const double ox = px - X, oy = py - Y;
@@ -764,7 +764,7 @@ __device__ void near_frame_features(double px, double py, double X, double Y, do
 // the density's derivatives at the node (row of the derivative table) in
 // the frame, and F = sum |d| over p and both components (1 if zero): the
 // unit of AUTO's calibrated bounds
-__device__ void near_frame_head(const double *__restrict__ drow, double *__restrict__ fr) {
+__device__ __forceinline__ void near_frame_head(const double *__restrict__ drow, double *__restrict__ fr) {
     double F = 0.0;
 #pragma unroll
     for (int p = 0; p < kNearDeriv; ++p) {
@@ -777,7 +777,7 @@ __device__ void near_frame_head(const double *__restrict__ drow, double *__restr
     fr[7] = F > 0.0 ? F : 1.0;
 }
 
-__device__ void near_invalid(float *__restrict__ xi, double *__restrict__ fr) {
+__device__ __forceinline__ void near_invalid(float *__restrict__ xi, double *__restrict__ fr) {
     for (int k = 0; k < kNearFeat; ++k) xi[k] = __builtin_nanf("");
     for (int k = 0; k < kNearFrame; ++k) fr[k] = __builtin_nan("");
 }
@@ -807,11 +807,20 @@ __device__ __forceinline__ int near_decide_one(int64_t i, const double *fr, cons
 template <int OP>
 __device__ void near_learned_head(int64_t i, const double *rec, const DecideArgs &a, float *__restrict__ nrec);
 
-// FUSE false: the features X and frame records; FUSE true (the learned and
-// AUTO routes): the features, AUTO's decision (near_decide_one) and, for a
-// learned target, its straight-line part and network record
-// (near_learned_head), all from the frame in registers (frame unused)
-template <bool FUSE>
+// What a launch of near_features computes:
+// - kFeatFrame: the features X and the frame records (training, calibration);
+// - kFeatScan: the features X and the nearest node k* (kstar, -1 for an
+//   invalid target), without the density: it can run beside near_derivs;
+// - kFeatHead: from kstar and the derivative table, the frame in registers,
+//   AUTO's decision (near_decide_one) and, for a learned target, its
+//   straight-line part and network record (near_learned_head);
+// - kFeatFused: kFeatScan and kFeatHead in one launch (the frame stays in
+//   registers; no kstar).
+// The frames of kFeatHead and kFeatFused are the one kFeatFrame writes, bit
+// for bit (the same code from the same nearest node).
+constexpr int kFeatFrame = 0, kFeatScan = 1, kFeatHead = 2, kFeatFused = 3;
+
+template <int MODE>
 __global__ __launch_bounds__(256) void near_features(int64_t n_trg, const double *__restrict__ tx,
                                                      const double *__restrict__ ty, const int32_t *__restrict__ tc,
                                                      const int32_t *__restrict__ off, int32_t n_curves, int64_t n_src,
@@ -819,32 +828,40 @@ __global__ __launch_bounds__(256) void near_features(int64_t n_trg, const double
                                                      const double *__restrict__ nx, const double *__restrict__ ny,
                                                      const double *__restrict__ kap, const double *__restrict__ w,
                                                      const double *__restrict__ dtab, float *__restrict__ X,
-                                                     double *__restrict__ frame, float *__restrict__ nrec,
-                                                     DecideArgs da) {
+                                                     double *__restrict__ frame, int32_t *__restrict__ kstar,
+                                                     float *__restrict__ nrec, DecideArgs da) {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = q < n_trg;
     const int64_t i = live ? q : 0;
     const int c = live ? tc[i] : -1;
     const int lo = (c >= 0 && c < n_curves) ? off[c] : 0;
     const int N = (c >= 0 && c < n_curves) ? off[c + 1] - lo : 0;
-    const bool ok = c >= 0 && c < n_curves && N >= 8 && lo >= 0 && (int64_t)lo + N <= n_src;
-    // a wave is uniform when all its live lanes share one valid curve (every
-    // lane of the wave reaches this vote)
-    const int cl = ok ? c : INT_MAX;
-    const int cmin = wave_min(cl);
-    const bool uniform = cmin != INT_MAX && __all(!live || (ok && c == cmin));
+    bool ok = c >= 0 && c < n_curves && N >= 8 && lo >= 0 && (int64_t)lo + N <= n_src;
     const double px = live ? tx[i] : 0.0, py = live ? ty[i] : 0.0;
-    double best = 0.0;
     int ks = 0;
-    if (uniform) {
-        const int cu = __builtin_amdgcn_readfirstlane(cmin);
-        const int lou = off[cu];
-        ks = near_scan<true>(px, py, lou, off[cu + 1] - lou, x, y, best);
-    } else if (ok) {
-        ks = near_scan<false>(px, py, lo, N, x, y, best);
+    if constexpr (MODE == kFeatHead) {
+        if (!live) return;
+        ks = kstar[i];
+        ok = ok && ks >= 0 && ks < N;
+    } else {
+        // a wave is uniform when all its live lanes share one valid curve
+        // (every lane of the wave reaches this vote)
+        const int cl = ok ? c : INT_MAX;
+        const int cmin = wave_min(cl);
+        const bool uniform = cmin != INT_MAX && __all(!live || (ok && c == cmin));
+        double best = 0.0;
+        if (uniform) {
+            const int cu = __builtin_amdgcn_readfirstlane(cmin);
+            const int lou = off[cu];
+            ks = near_scan<true>(px, py, lou, off[cu + 1] - lou, x, y, best);
+        } else if (ok) {
+            ks = near_scan<false>(px, py, lo, N, x, y, best);
+        }
+        if (!live) return;
+        if constexpr (MODE == kFeatScan) kstar[i] = ok ? ks : -1;
     }
-    if (!live) return;
-    float *xi = X + i * kNearFeat;
+    float xl[kNearFeat];
+    float *xi = MODE == kFeatHead ? xl : X + i * kNearFeat;
     double rec[kNearFrame];
     if (!ok) {
         near_invalid(xi, rec);
@@ -859,11 +876,11 @@ __global__ __launch_bounds__(256) void near_features(int64_t n_trg, const double
         }
         const int k = lo + ks;
         near_frame_features(px, py, x[k], y[k], nx[k], ny[k], kap[k], w[k], nb, xi, rec);
-        near_frame_head(dtab + (int64_t)k * 2 * kNearDeriv, rec);
+        if constexpr (MODE != kFeatScan) near_frame_head(dtab + (int64_t)k * 2 * kNearDeriv, rec);
     }
-    if constexpr (FUSE) {
+    if constexpr (MODE == kFeatHead || MODE == kFeatFused) {
         if (near_decide_one<S2D_OP_SLP>(i, rec, da, c) == 0) near_learned_head<S2D_OP_SLP>(i, rec, da, nrec);
-    } else {
+    } else if constexpr (MODE == kFeatFrame) {
         double *fr = frame + i * kNearFrame;
 #pragma unroll
         for (int r = 0; r < kNearFrame; ++r) fr[r] = rec[r];
@@ -1980,17 +1997,34 @@ hipError_t near_launch_derivs(const s2d_curves *c, double *dtab, void *scratch, 
 }
 
 hipError_t near_launch_features(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, const double *dtab,
-                                float *X, double *frame, hipStream_t st, const DecideArgs *fused, float *nrec) {
+                                float *X, double *frame, hipStream_t st) {
     if (t->n <= 0) return hipSuccess;
-    const DecideArgs da = fused ? *fused : DecideArgs{};
-    if (fused)
-        hipLaunchKernelGGL(near_features<true>, dim3(grid_for(t->n)), dim3(256), 0, st, t->n, t->x, t->y, tc,
-                           c->curve_off, c->n_curves, c->n_nodes, c->x, c->y, c->nx, c->ny, c->kappa, c->w, dtab, X,
-                           nullptr, nrec, da);
+    hipLaunchKernelGGL(near_features<kFeatFrame>, dim3(grid_for(t->n)), dim3(256), 0, st, t->n, t->x, t->y, tc,
+                       c->curve_off, c->n_curves, c->n_nodes, c->x, c->y, c->nx, c->ny, c->kappa, c->w, dtab, X,
+                       frame, nullptr, nullptr, DecideArgs{});
+    return hipGetLastError();
+}
+
+hipError_t near_launch_scan(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, float *X, int32_t *kstar,
+                            hipStream_t st) {
+    if (t->n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(near_features<kFeatScan>, dim3(grid_for(t->n)), dim3(256), 0, st, t->n, t->x, t->y, tc,
+                       c->curve_off, c->n_curves, c->n_nodes, c->x, c->y, c->nx, c->ny, c->kappa, c->w, nullptr, X,
+                       nullptr, kstar, nullptr, DecideArgs{});
+    return hipGetLastError();
+}
+
+hipError_t near_launch_head(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, const double *dtab,
+                            const int32_t *kstar, const DecideArgs &da, float *nrec, hipStream_t st, float *X) {
+    if (t->n <= 0) return hipSuccess;
+    if (kstar)
+        hipLaunchKernelGGL(near_features<kFeatHead>, dim3(grid_for(t->n)), dim3(256), 0, st, t->n, t->x, t->y, tc,
+                           c->curve_off, c->n_curves, c->n_nodes, c->x, c->y, c->nx, c->ny, c->kappa, c->w, dtab,
+                           nullptr, nullptr, (int32_t *)kstar, nrec, da);
     else
-        hipLaunchKernelGGL(near_features<false>, dim3(grid_for(t->n)), dim3(256), 0, st, t->n, t->x, t->y, tc,
+        hipLaunchKernelGGL(near_features<kFeatFused>, dim3(grid_for(t->n)), dim3(256), 0, st, t->n, t->x, t->y, tc,
                            c->curve_off, c->n_curves, c->n_nodes, c->x, c->y, c->nx, c->ny, c->kappa, c->w, dtab, X,
-                           frame, nullptr, da);
+                           nullptr, nullptr, nrec, da);
     return hipGetLastError();
 }
 

@@ -87,16 +87,25 @@ struct DecideArgs {
     double *du, *dv;
     int32_t *flag;
 };
-// The feature kernels write X and the frame records (fused == NULL), or,
-// for the learned and AUTO routes (fused != NULL), X, AUTO's decisions and,
-// for every target decided learned (all when use_bound == 0), the
+// near_launch_features writes X and the frame records (training and
+// calibration).  The learned and AUTO routes of the vesicles take two
+// launches instead: near_launch_scan writes X and the nearest node kstar [n]
+// (-1: invalid target) without the density, so it can run beside the
+// derivatives; near_launch_head then takes AUTO's decisions and, for every
+// target decided learned (all when use_bound == 0), writes the
 // straight-line part into du, dv and the network's record into nrec
 // [kNetRec floats per target: d_p in the frame (2 p, 2 p + 1), t, n_f,
-// scale exp(-2 pi b)]; frame is not used then.
+// scale exp(-2 pi b)].  near_launch_head with kstar == NULL does the search
+// as well and writes X (one launch, after the derivatives).  The wall
+// feature kernel does both in one launch (fused != NULL; frame unused then).
 constexpr int kNetRec = 16;
 hipError_t near_launch_features(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, const double *dtab,
-                                float *X, double *frame, hipStream_t st, const DecideArgs *fused = nullptr,
-                                float *nrec = nullptr);
+                                float *X, double *frame, hipStream_t st);
+hipError_t near_launch_scan(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, float *X, int32_t *kstar,
+                            hipStream_t st);
+hipError_t near_launch_head(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, const double *dtab,
+                            const int32_t *kstar, const DecideArgs &da, float *nrec, hipStream_t st,
+                            float *X = nullptr);
 hipError_t near_launch_wall_features(const s2d_curves *c, const s2d_targets *t, const int32_t *tc, double d,
                                      const double *dtab, float *X, double *frame, hipStream_t st,
                                      const DecideArgs *fused = nullptr, float *nrec = nullptr);
