@@ -340,7 +340,7 @@ S2D_API int stokes2d_batch_tuned(int mode, int32_t n_inst, const s2d_instance *i
 #define S2D_NEAR_TSTRIDE 14          /* FP32 training-record words per sample */
 #define S2D_NEAR_NOUT 20             /* network outputs dC[p][out][in] */
 #define S2D_NEAR_NBINS 64            /* AUTO's largest number of bins of log10 b */
-#define S2D_NEAR_SBINS 4             /* AUTO's bins of |s| per b bin: width 1/8, the last open */
+#define S2D_NEAR_SBINS 5             /* AUTO's bins of |s| per b bin: width 1/8, the last (|s| >= 1/2) open */
 #define S2D_NEAR_KBINS 8             /* AUTO's bins of log10 |kappa h|: width 3/16 from -2, ends open */
 #define S2D_NEAR_CELL (S2D_NEAR_SBINS * S2D_NEAR_KBINS)   /* table entries per b bin */
 #define S2D_MLP_NPARAM 10608         /* FP32 master parameters of the 14-64-64-64-20 network */
@@ -452,7 +452,7 @@ S2D_API int near_feature_stats(int64_t n, const float *X, float *params, void *s
 
 /* Calibration of AUTO's rule on held-out targets: per bin (k, j, m), all
  * in FP32: k the bin of log10 b ([bin_lo + k bin_w, bin_lo + (k + 1)
- * bin_w), k < n_bins <= 64), j = min(floor(8 |s|), 3) the bin of |s| and m
+ * bin_w), k < n_bins <= 64), j = min(floor(8 |s|), 4) the bin of |s| and m
  * = clamp(floor((log10 |kappa h| + 2) 16 / 3), 0, 7) the bin of the
  * curvature over the spacing (kappa h = frame[19]), over targets with b >=
  * b_min on the expected side (sg > 0 for the single layer, sg < 0 for the
@@ -461,7 +461,10 @@ S2D_API int near_feature_stats(int64_t n, const float *X, float *params, void *s
  * for a bin of c targets (margin >= 1, count_margin >= 0: a wider margin
  * where the maximum rests on few samples): bound, bound_zero [n_bins *
  * S2D_NEAR_CELL] device float at S2D_NEAR_CELL k + 8 j + m; empty bins get
- * 3e38.  count: [n_bins * S2D_NEAR_CELL] device int32, the targets per bin. */
+ * 3e38, and so does bound in the bins of j = 4 (|s| >= 1/2: past the
+ * midpoint between two nodes the network's held-out errors underestimate
+ * its errors on new targets, so the learned route is never admitted there).
+ * count: [n_bins * S2D_NEAR_CELL] device int32, the targets per bin. */
 S2D_API int near_calibrate(int op, int64_t n, const double *frame, const double *du_pred, const double *dv_pred,
                            const double *du, const double *dv, double mu, int32_t n_bins, float bin_lo,
                            float bin_w, float b_min, float margin, float count_margin, float *bound,

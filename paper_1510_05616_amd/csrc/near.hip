@@ -1254,20 +1254,27 @@ __device__ void flat_rule(double s, double b, double inv_d, int L, const double 
 // ---------------------------------------------------------------------------
 // MLP pieces
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float gelu_f(float z) {
-    const float u = 0.7978845608028654f * (z + 0.044715f * z * z * z);
-    // tanh(u) = 1 - 2 / (exp(2u) + 1); exp via the hardware exp2
-    const float e = __builtin_amdgcn_exp2f(fminf(2.8853900817779268f * u, 126.f));
-    const float th = 1.f - 2.f * __builtin_amdgcn_rcpf(e + 1.f);
-    return 0.5f * z * (1.f + th);
+// tanh-form GELU, 0.5 z (1 + tanh u) with u = sqrt(2/pi) (z + 0.044715 z^3),
+// taken as z / (1 + exp(-2u)) (the same function: 1 + tanh u = 2 / (1 +
+// exp(-2u))): one exponential, one reciprocal and six other instructions
+// per neuron; exp via the hardware exp2, its argument clamped so that the
+// sum stays finite
+constexpr float kGeluK = -2.0f * 0.7978845608028654f * 1.4426950408889634f;   // -2 sqrt(2/pi) log2(e)
+
+__device__ __forceinline__ float gelu_sig(float z) {
+    // 1 / (1 + exp(-2u)) = (1 + tanh u) / 2
+    const float t = z * __builtin_fmaf(0.044715f * kGeluK, z * z, kGeluK);
+    return __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(fminf(t, 126.f)) + 1.f);
 }
 
+__device__ __forceinline__ float gelu_f(float z) { return z * gelu_sig(z); }
+
+// d/dz: s + 2 z s (1 - s) du/dz with s = (1 + tanh u) / 2 (the tanh form's
+// derivative 0.5 (1 + tanh u) + 0.5 z (1 - tanh^2 u) du/dz, rewritten)
 __device__ __forceinline__ float gelu_grad_f(float z) {
-    const float u = 0.7978845608028654f * (z + 0.044715f * z * z * z);
-    const float e = __builtin_amdgcn_exp2f(fminf(2.8853900817779268f * u, 126.f));
-    const float th = 1.f - 2.f * __builtin_amdgcn_rcpf(e + 1.f);
+    const float sg = gelu_sig(z);
     const float du = 0.7978845608028654f * (1.f + 3.f * 0.044715f * z * z);
-    return 0.5f * (1.f + th) + 0.5f * z * (1.f - th * th) * du;
+    return __builtin_fmaf(2.f * z * sg * (1.f - sg), du, sg);
 }
 
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
@@ -1712,12 +1719,18 @@ __global__ __launch_bounds__(256) void near_calib_init(int32_t n_bins, uint32_t 
     }
 }
 
+// Targets past the midpoint between two nodes (|s| >= 1/2, where the
+// nearest node by distance is not the nearest by arc) never take the learned
+// route: the network's held-out errors there underestimate its errors on new
+// targets by up to three times (heavy tails), so their cells keep the
+// no-correction bound only.
 __global__ __launch_bounds__(256) void near_calib_finish(int32_t n_bins, float margin, float count_margin,
                                                          uint32_t *bound, uint32_t *bound_zero, const int32_t *count) {
     for (int b = threadIdx.x; b < n_bins * kNearCell; b += blockDim.x) {
         const int n = count[b];
+        const bool past_mid = (b % kNearCell) / kNearKBins == kNearSBins - 1;
         const float m = n > 0 ? margin * (1.f + count_margin / sqrtf((float)n)) : 0.f;
-        const float e = n > 0 ? __builtin_bit_cast(float, bound[b]) * m : 3e38f;
+        const float e = n > 0 && !past_mid ? __builtin_bit_cast(float, bound[b]) * m : 3e38f;
         const float z = n > 0 ? __builtin_bit_cast(float, bound_zero[b]) * m : 3e38f;
         bound[b] = __builtin_bit_cast(uint32_t, e);
         bound_zero[b] = __builtin_bit_cast(uint32_t, z);

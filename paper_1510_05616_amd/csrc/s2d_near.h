@@ -15,7 +15,7 @@ constexpr int kNearDeriv = 5;
 constexpr int kNearOut = 4 * kNearDeriv;
 constexpr int kNearFrame = 20;
 constexpr int kNearMaxBins = 64;                // bins of log10 b
-constexpr int kNearSBins = 4;                   // bins of |s|: width 1/8, the last open
+constexpr int kNearSBins = 5;                   // bins of |s|: width 1/8, the last (|s| >= 1/2) open
 constexpr int kNearKBins = 8;                   // bins of log10 |kappa h| from -2, width 3/16, both ends open
 constexpr int kNearCell = kNearSBins * kNearKBins;
 constexpr int kNearTable = kNearMaxBins * kNearCell;

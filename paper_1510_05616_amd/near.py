@@ -31,12 +31,13 @@ NPARAM = 10608
 OFF = dict(mu=0, sd=14, W1=28, b1=924, W2=988, b2=5084, W3=5148, b3=9244, W4=9308, b4=10588)
 SHAPES = dict(W1=(14, 64), b1=(64,), W2=(64, 64), b2=(64,), W3=(64, 64), b3=(64,), W4=(64, 20), b4=(20,))
 # AUTO's bins: log10 b (b the normal offset in units of the local spacing),
-# each split into CELL cells of |s| (S_BINS of width 1/8, the last open) and
+# each split into CELL cells of |s| (S_BINS of width 1/8, the last, |s| >= 1/2,
+# open: calibration never admits the learned route there) and
 # log10 |kappa h| (K_BINS of width 3/16 from -2, both ends open): tables of
 # N_BINS * CELL entries
 B_MIN = 0.05
 BIN_LO, BIN_W, N_BINS = math.log10(B_MIN), 2.0 / 32, 32
-S_BINS, K_BINS = 4, 8
+S_BINS, K_BINS = 5, 8
 CELL = S_BINS * K_BINS
 B_MAX = 10.0 ** (BIN_LO + N_BINS * BIN_W)    # the last bin's upper edge (5.0)
 
