@@ -720,36 +720,51 @@ __global__ __launch_bounds__(256) void near_derivs_nodes(const int32_t *__restri
     }
 }
 
+// The frame in registers: the kNearFrame words of the frame record, then
+// exp(-2 pi b), cos(-2 pi s) and sin(-2 pi s) (Q of the plain rule, kept for
+// the straight-line part; not part of the stored record).
+constexpr int kNearRec = kNearFrame + 3;
+
+// exp(-2 pi b) and (cos, sin)(-2 pi s) (the one expression every caller uses)
+__device__ __forceinline__ void flat_q(double s, double b, double &aq, double &cq, double &sq) {
+    sincospi(-2.0 * s, &sq, &cq);
+    aq = exp(-2.0 * M_PI * b);
+}
+
 // Geometry features and frame of a target p whose nearest node is at (X, Y)
 // with unit normal (NX, NY), curvature kap and spacing hl, nb[j] the nodes
 // k* - 2, k* - 1, k* + 1, k* + 2: xi = [s, b, ln(|p - x_k*| / hl), sg kap hl,
 // the four nodes in the frame (units hl), Re Q, Im Q], Q = exp(-2 pi (b + i s));
-// fr[0..8] = s, b, t, n_f, hl, (F later), sg; fr[19] = sg kap hl.
+// fr[0..8] = s, b, t, n_f, hl, (F later), sg; fr[19] = sg kap hl; fr[20..22]
+// = exp(-2 pi b), cos(-2 pi s), sin(-2 pi s).
 __device__ __forceinline__ void near_frame_features(double px, double py, double X, double Y, double NX,
                                                     double NY, double kap, double hl, const double (&nb)[4][2],
                                                     float *__restrict__ xi, double *__restrict__ fr) {
     const double st = ((nb[2][0] - nb[1][0]) * -NY + (nb[2][1] - nb[1][1]) * NX) >= 0.0 ? 1.0 : -1.0;
     const double tx = -st * NY, ty = st * NX;
     const double ox = px - X, oy = py - Y;
-    const double sv = (ox * tx + oy * ty) / hl;
-    const double nv = (ox * NX + oy * NY) / hl;
+    const double ih = 1.0 / hl;
+    const double sv = (ox * tx + oy * ty) * ih;
+    const double nv = (ox * NX + oy * NY) * ih;
     const double sg = nv >= 0.0 ? 1.0 : -1.0;
     const double nfx = sg * NX, nfy = sg * NY;
     const double b = sg * nv;
     xi[0] = (float)sv;
     xi[1] = (float)b;
-    xi[2] = (float)log(sqrt(ox * ox + oy * oy) / hl);
+    xi[2] = (float)log(sqrt(ox * ox + oy * oy) * ih);
     xi[3] = (float)(sg * kap * hl);
     for (int j = 0; j < 4; ++j) {
         const double gx = nb[j][0] - X, gy = nb[j][1] - Y;
-        xi[4 + 2 * j] = (float)((gx * tx + gy * ty) / hl);
-        xi[5 + 2 * j] = (float)((gx * nfx + gy * nfy) / hl);
+        xi[4 + 2 * j] = (float)((gx * tx + gy * ty) * ih);
+        xi[5 + 2 * j] = (float)((gx * nfx + gy * nfy) * ih);
     }
-    double sq, cq;
-    sincospi(-2.0 * sv, &sq, &cq);
-    const double aq = exp(-2.0 * M_PI * b);
+    double aq, cq, sq;
+    flat_q(sv, b, aq, cq, sq);
     xi[12] = (float)(aq * cq);
     xi[13] = (float)(aq * sq);
+    fr[kNearFrame] = aq;
+    fr[kNearFrame + 1] = cq;
+    fr[kNearFrame + 2] = sq;
     fr[0] = sv;
     fr[1] = b;
     fr[2] = tx;
@@ -779,7 +794,7 @@ __device__ __forceinline__ void near_frame_head(const double *__restrict__ drow,
 
 __device__ __forceinline__ void near_invalid(float *__restrict__ xi, double *__restrict__ fr) {
     for (int k = 0; k < kNearFeat; ++k) xi[k] = __builtin_nanf("");
-    for (int k = 0; k < kNearFrame; ++k) fr[k] = __builtin_nan("");
+    for (int k = 0; k < kNearRec; ++k) fr[k] = __builtin_nan("");
 }
 
 // nearest node k* (smallest index on ties) of the curve at [lo, lo + N);
@@ -862,7 +877,7 @@ __global__ __launch_bounds__(256) void near_features(int64_t n_trg, const double
     }
     float xl[kNearFeat];
     float *xi = MODE == kFeatHead ? xl : X + i * kNearFeat;
-    double rec[kNearFrame];
+    double rec[kNearRec];
     if (!ok) {
         near_invalid(xi, rec);
     } else {
@@ -1062,7 +1077,7 @@ __global__ __launch_bounds__(256) void near_wall_features(int64_t n_trg, const d
         const int lo = (c >= 0 && c < n_curves) ? off[c] : 0;
         const int N = (c >= 0 && c < n_curves) ? off[c + 1] - lo : 0;
         float *xi = X + i * kNearFeat;
-        double rec[kNearFrame];
+        double rec[kNearRec];
         // the frame record's destination: the frame array, or the fused
         // decision and learned head
         const auto emit = [&]() {
@@ -1185,14 +1200,11 @@ __constant__ FlatCoef kFlat = FlatCoef();
 
 // sum_p E_p(rule of spacing D = 1 / inv_d) d_p for the single (OP =
 // S2D_OP_SLP) or double layer; out = (t, n) components
+// Q = exp(-2 pi inv_d (b + i s)) is passed in (flat_pair)
 template <int OP>
-__device__ void flat_rule(double s, double b, double inv_d, int L, const double *__restrict__ dfr,
+__device__ void flat_rule(double s, double b, double inv_d, Cx Q, int L, const double *__restrict__ dfr,
                           double (&out)[2]) {
     const double c = 2.0 * M_PI * inv_d;
-    double sq, cq;
-    sincospi(-2.0 * s * inv_d, &sq, &cq);
-    const double aq = exp(-c * b);
-    const Cx Q = {aq * cq, aq * sq};
     const Cx om = {1.0 - Q.re, -Q.im};                       // 1 - Q
     const Cx L0 = cx_div(Q, om);
     Cx zp[kNearDeriv];                                       // (-z)^k
@@ -1249,6 +1261,22 @@ __device__ void flat_rule(double s, double b, double inv_d, int L, const double 
             out[1] = __builtin_fma(etn, dt, __builtin_fma(enn, dn, out[1]));
         }
     }
+}
+
+// The straight-line parts of the refined rule (spacing 1 / P: Q^P, by
+// repeated squaring) and of the plain one (Q = aq (cq + i sq)), the refined
+// with L = kPolyFine polylogarithm terms and the plain with kPolyCoarse.
+template <int OP>
+__device__ __forceinline__ void flat_pair(double s, double b, int P, double aq, double cq, double sq,
+                                          const double *__restrict__ dfr, double (&ff)[2], double (&fc)[2]) {
+    const Cx Q = {aq * cq, aq * sq};
+    Cx QP = {1.0, 0.0}, base = Q;
+    for (int e = P; e > 0; e >>= 1) {
+        if (e & 1) QP = cx_mul(QP, base);
+        if (e > 1) base = cx_mul(base, base);
+    }
+    flat_rule<OP>(s, b, (double)P, QP, kPolyFine, dfr, ff);
+    flat_rule<OP>(s, b, 1.0, Q, kPolyCoarse, dfr, fc);
 }
 
 // ---------------------------------------------------------------------------
@@ -1437,8 +1465,8 @@ __device__ void near_learned_head(int64_t i, const double *rec, const DecideArgs
     double yt = 0.0, yn = 0.0;
     if (b > 0.0) {
         double ff[2], fc[2];
-        flat_rule<OP>(rec[0], b, (double)a.nb->P, kPolyFine, rec + 9, ff);
-        flat_rule<OP>(rec[0], b, 1.0, kPolyCoarse, rec + 9, fc);
+        flat_pair<OP>(rec[0], b, a.nb->P, rec[kNearFrame], rec[kNearFrame + 1], rec[kNearFrame + 2], rec + 9, ff,
+                      fc);
         yt = ff[0] - fc[0];
         yn = ff[1] - fc[1];
         if (OP != S2D_OP_SLP) {
@@ -1453,7 +1481,7 @@ __device__ void near_learned_head(int64_t i, const double *rec, const DecideArgs
     for (int k = 0; k < 2 * kNearDeriv; ++k) r[k] = (float)rec[9 + k];
 #pragma unroll
     for (int k = 0; k < 4; ++k) r[2 * kNearDeriv + k] = (float)rec[2 + k];
-    r[2 * kNearDeriv + 4] = (float)(scale * exp(-2.0 * M_PI * b));
+    r[2 * kNearDeriv + 4] = (float)(scale * rec[kNearFrame]);           // scale exp(-2 pi b)
     r[2 * kNearDeriv + 5] = 0.f;
 }
 
@@ -1625,10 +1653,9 @@ __global__ __launch_bounds__(256) void near_train_targets_k(int64_t n, const dou
     const double scale = OP == S2D_OP_SLP ? fr[6] / (4.0 * M_PI * mu) : 1.0 / M_PI;
     double y0 = (du[i] * fr[2] + dv[i] * fr[3]) / scale, y1 = (du[i] * fr[4] + dv[i] * fr[5]) / scale;
     double fc[2] = {0.0, 0.0}, ff[2] = {0.0, 0.0};
-    if (b > 0.0) {
-        flat_rule<OP>(fr[0], b, 1.0, kPolyCoarse, fr + 9, fc);
-        flat_rule<OP>(fr[0], b, (double)P, kPolyFine, fr + 9, ff);
-    }
+    double aq, cq, sq;
+    flat_q(fr[0], b, aq, cq, sq);
+    if (b > 0.0) flat_pair<OP>(fr[0], b, P, aq, cq, sq, fr + 9, ff, fc);
     const double sgn = OP == S2D_OP_SLP ? 1.0 : fr[8];
     y0 -= sgn * (ff[0] - fc[0]);
     y1 -= sgn * (ff[1] - fc[1]);
@@ -1639,7 +1666,7 @@ __global__ __launch_bounds__(256) void near_train_targets_k(int64_t n, const dou
     t[10] = (float)y0;
     t[11] = (float)y1;
     t[12] = cs > 0.f ? (float)((double)gain * scale / (double)cs) : 0.f;
-    t[13] = (float)exp(-2.0 * M_PI * b);
+    t[13] = (float)aq;
 }
 
 // per-feature mean and standard deviation (population) over n samples into
