@@ -1903,11 +1903,21 @@ __global__ __launch_bounds__(256) void mlp_grad(int32_t B, const float *__restri
     float g = 0.f;
     if (p >= O::W1 && p < O::total) {            // mu_in / sd_in are not trained
         const int s0 = (int)((int64_t)B * ch / kGradChunks), s1 = (int)((int64_t)B * (ch + 1) / kGradChunks);
-        for (int s = s0; s < s1; ++s) {
-            const float *A = act + (int64_t)s * kActStride;
-            const float d = outd ? dY[(int64_t)s * kNearOut + dk] : A[dl];
-            g = fmaf(hin >= 0 ? A[hin] : 1.f, d, g);
+        // the loads of 8 samples are issued before their (ordered) FMAs
+        const float *dsrc = outd ? dY + dk : act + dl;
+        const int64_t dstr = outd ? kNearOut : kActStride;
+        int s = s0;
+        for (; s + 8 <= s1; s += 8) {
+            float dv[8], hv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                dv[u] = dsrc[(int64_t)(s + u) * dstr];
+                hv[u] = hin >= 0 ? act[(int64_t)(s + u) * kActStride + hin] : 1.f;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) g = fmaf(hv[u], dv[u], g);
         }
+        for (; s < s1; ++s) g = fmaf(hin >= 0 ? act[(int64_t)s * kActStride + hin] : 1.f, dsrc[(int64_t)s * dstr], g);
     }
     part[ch][pp] = g;
     __syncthreads();
