@@ -111,8 +111,10 @@ typedef struct s2d_targets {
 } s2d_targets;
 
 /* Selects the device for the calling thread's later calls and sets up the
- * library's per-device state (device properties, launch tuning table).
- * Not capturable; call once per device before any evaluation. */
+ * library's per-device state (device properties, launch tuning table, the
+ * no-allocation entry point's scratch address, and the second stream and
+ * events near_correct_eval's AUTO method uses).  Not capturable; call once
+ * per device before any evaluation. */
 S2D_API int stokes2d_init(int device);
 
 /* Bytes of workspace an evaluation with these arguments needs (0 on bad
@@ -371,7 +373,14 @@ S2D_API size_t near_workspace_size(int method, const s2d_curves *ves, const s2d_
  * the bin's network bound times scale F is, the quadrature otherwise (past
  * the last b bin: 0 or the quadrature).  used_fallback: [n] device int32 or
  * NULL, set (MLP, AUTO) to 0 learned, 1 upsampled quadrature, 2 no
- * correction.  Targets of invalid curves get NaN. */
+ * correction.  Targets of invalid curves get NaN.
+ * Streams: every kernel is ordered after the caller's earlier work on
+ * `stream`, and the call's last kernel runs on `stream`.  Outside stream
+ * capture AUTO runs its derivatives and upsampling on a second stream of
+ * the device (created by stokes2d_init, default priority), forked from and
+ * joined back into `stream` by events; AUTO calls on one device take a
+ * library lock while they enqueue.  Under capture everything stays on
+ * `stream`; the results are the same either way. */
 S2D_API int near_correct_eval(int method, const s2d_curves *ves, const s2d_targets *trg,
                               const int32_t *trg_curve, int32_t upsample, const void *mlp,
                               double threshold, const double *curve_tol, double mu, double *du,
