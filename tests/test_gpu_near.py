@@ -487,6 +487,52 @@ def test_auto_mixed_decisions_match_each_route(small):
     assert agree > 0.999, agree
 
 
+def test_auto_on_a_side_stream_sees_the_callers_prior_work(small):
+    """AUTO forks work to a second stream of the device: it must wait for
+    what the caller queued on its own stream just before the call (here the
+    density, rewritten on that stream) and finish there. The result on a
+    user stream equals the default-stream result for the same density."""
+    import torch
+    from paper_1510_05616_amd import near
+    c, tx, ty, tc, dh, data = small
+    k = torch.arange(near.N_BINS * near.CELL, device="cuda") // near.CELL
+    bound = torch.where(k % 2 == 0, 1e-3, 10.0).float()
+    blob = _auto_blob(_rand_params(5), bound, torch.full_like(bound, 10.0))
+    sF = (data.frame[:, 6] / (4 * math.pi) * data.frame[:, 7])
+    thr = 2e-3 * sF.max().item()
+    fx0, fy0 = data.curves.fx.clone(), data.curves.fy.clone()
+    ref = [torch.empty(data.n, dtype=torch.float64, device="cuda") for _ in range(2)]
+    fr = torch.full((data.n,), -1, dtype=torch.int32, device="cuda")
+    data.curves.fx.mul_(-2.0)
+    data.curves.fy.mul_(0.5)
+    data.correct(near.S2D_NEAR_AUTO, blob, thr, ref[0], ref[1], fr)
+    torch.cuda.synchronize()
+    assert bool((fr == 0).any()) and bool((fr == 1).any())
+    data.curves.fx.copy_(fx0)
+    data.curves.fy.copy_(fy0)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    du, dv = (torch.full((data.n,), float("nan"), dtype=torch.float64, device="cuda") for _ in range(2))
+    fb = torch.full((data.n,), -1, dtype=torch.int32, device="cuda")
+    ws = near._empty(near.near_workspace_size(near.S2D_NEAR_AUTO, data.curves, data.trg, 8))
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        # queued on the side stream right before the call: a long chain of
+        # kernels ending with the density the call must see
+        for _ in range(20):
+            data.curves.fx.mul_(1.0)
+        data.curves.fx.mul_(-2.0)
+        data.curves.fy.mul_(0.5)
+        near.near_correct_eval(near.S2D_NEAR_AUTO, data.curves, data.trg, data.tc, 8, blob, thr, 1.0, du, dv, fb,
+                               ws, stream=side)
+    side.synchronize()
+    data.curves.fx.copy_(fx0)
+    data.curves.fy.copy_(fy0)
+    torch.cuda.synchronize()
+    assert torch.equal(fb, fr)
+    assert torch.equal(du, ref[0]) and torch.equal(dv, ref[1])
+
+
 def test_auto_per_curve_tolerances(small):
     """With curve_tol, each target is held to its own curve's tolerance: a
     zero tolerance sends every target of those curves to the quadrature, a
