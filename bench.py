@@ -421,7 +421,7 @@ def wall_learned_section(prob, n_train=200000, n_test=1000000, steps=200000):
     t_train = time.time() - t0
     del tr
     va = pn.WallNearData(walls, d, *synth.near_wall_dataset(walls, 1000000, 43))
-    blob, bound, bound0, count = pn.calibrate(va, params, margin=1.75, count_margin=2.0)
+    blob, bound, bound0, count = pn.calibrate(va, params, margin=1.5, count_margin=2.0)
     del va
     te = pn.WallNearData(walls, d, *synth.near_wall_dataset(walls, n_test, 44))
     du = torch.empty(te.n, dtype=torch.float64, device="cuda")
@@ -771,7 +771,7 @@ def near_section(steps=200000):
     t_train = time.time() - t0
     del tr
     va = near.NearData(*synth.make_near_dataset(2000000, 6)[:4], mu=1.0, upsample=8)
-    blob, bound, bound0, count = near.calibrate(va, params, margin=1.75, count_margin=2.0)
+    blob, bound, bound0, count = near.calibrate(va, params, margin=1.5, count_margin=2.0)
     del va
     log(f"near: trained {steps} steps in {t_train:.1f}s, loss {hist[0][1]:.3e} -> {hist[-1][1]:.3e}")
     te = near.NearData(*synth.make_near_dataset(1000000, 7)[:4], mu=1.0, upsample=8)

@@ -439,7 +439,7 @@ def train(data: _NearSet, steps=20000, batch=1024, lr=2e-3, lr_min=2e-5, b_train
     return params, hist
 
 
-def calibrate(data: _NearSet, params, margin=1.75, count_margin=2.0, b_min=B_MIN, n_bins=N_BINS, bin_lo=BIN_LO,
+def calibrate(data: _NearSet, params, margin=1.5, count_margin=2.0, b_min=B_MIN, n_bins=N_BINS, bin_lo=BIN_LO,
               bin_w=BIN_W):
     """Per-bin bounds on held-out data by the library's calibration kernel:
     the learned route's (BF16) largest error and the largest correction, each

@@ -597,13 +597,13 @@ def test_calibration_matches_numpy(small):
 def trained():
     """The learned correction trained on the GPU: 200,000 targets of the
     near-field workload, 200,000 steps of 1024, calibrated on 1,000,000
-    held-out targets with margin 1.75 (1 + 2 / sqrt(targets per bin))."""
+    held-out targets with margin 1.5 (1 + 2 / sqrt(targets per bin))."""
     from paper_1510_05616_amd import near
     tr = near.NearData(*synth.make_near_dataset(200000, seed=51)[:4], mu=1.0, upsample=8)
     params, hist = near.train(tr, steps=200000, batch=1024, lr=2e-3, log_every=25000)
     del tr
     va = near.NearData(*synth.make_near_dataset(1000000, seed=52)[:4], mu=1.0, upsample=8)
-    blob, bound, bound0, count = near.calibrate(va, params, margin=1.75, count_margin=2.0)
+    blob, bound, bound0, count = near.calibrate(va, params, margin=1.5, count_margin=2.0)
     del va
     return params, hist, blob
 
