@@ -751,9 +751,9 @@ def batch_section():
     return res
 
 
-def near_section(steps=200000):
+def near_section(steps=400000):
     """Learned near-field correction on the near-target workload: train on
-    200k targets (200,000 steps of 1024 on the GPU), calibrate on 2M, test on
+    200k targets (400,000 steps of 1024 on the GPU), calibrate on 2M, test on
     1M (targets at log-uniform normal distances 0.05 h .. 5 h from ellipses
     of 64-128 nodes).  Errors are normalised per curve by the largest |u| of
     the 8x upsampled single layer over that curve's test targets; AUTO takes
@@ -828,7 +828,7 @@ def near_section(steps=200000):
                                 "learned_max": float(err_mlp[m].max())}
     a5 = auto["1e-05"]
     res = {"workload": "1e6 targets at 0.05h..5h from 5000 ellipses of 64/96/128 nodes; network 14-64-64-64-20 "
-                       "trained on the GPU on 2e5 8x-upsampled labels (200,000 steps of 1024), calibrated on 2e6",
+                       "trained on the GPU on 2e5 8x-upsampled labels (400,000 steps of 1024), calibrated on 2e6",
            "err_vs_upsampled8": {"learned": e_mlp, "auto_1e-5_per_curve": a5["err"],
                                  "no_correction": float(err_plain.max())},
            "err_upsampled8_vs_32_on_64_node_curves": e_8v32, "error_by_normal_offset": gain,
