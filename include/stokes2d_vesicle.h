@@ -104,6 +104,11 @@ typedef struct ves_step_params {
     double near_band;      /* > 0, in units of h_c */
     int32_t near_max;      /* capacity for the (node, vesicle, image) pairs (>= 1; sizes the
                               workspace); a call that finds more returns S2D_EINVAL */
+    int32_t warm;          /* 0: GMRES starts from z = 0; 1: from a given z (ves_step_solve:
+                              the z passed in; ves_time_step: (u, v, sigma), u and v holding
+                              the previous step's velocity), GMRES then solves for the
+                              correction of the FP64 residual b - A z; the same tolerance
+                              relative to ||b|| */
 } ves_step_params;
 
 /* Workspace bytes for ves_step_apply / ves_step_solve / ves_time_step. */
@@ -116,9 +121,9 @@ S2D_API int ves_step_apply(int64_t n_nodes, int32_t n_curves, const int32_t *cur
                            const double *z, double *out, double *b,
                            void *ws, size_t ws_bytes, void *stream);
 
-/* Solves the step system by restarted GMRES from z = 0 (classical
- * Gram-Schmidt applied twice, fixed-order reductions: bitwise
- * reproducible).  z: [3 n_nodes] solution.  iters, rel_res: host pointers
+/* Solves the step system by restarted GMRES from z = 0, or from the z
+ * passed in when p->warm (classical Gram-Schmidt applied twice, fixed-order
+ * reductions: bitwise reproducible).  z: [3 n_nodes] solution.  iters, rel_res: host pointers
  * (may be NULL) for the iteration count and the final ||b - A z|| / ||b||.
  * Returns S2D_OK also when max_iter is reached; check rel_res.  iters
  * counts the GMRES iterations of all corrections in S2D_FP32C mode. */
@@ -142,7 +147,9 @@ S2D_API int ves_reparameterize(int64_t n_nodes, int32_t n_curves, const int32_t 
 /* One time step (Algorithm 1, steps 6-9): solve the step system, then
  * x <- x + dt u, area correction to A0 (if not NULL), reparameterization of
  * x, y and sigma (if reparam != 0).  sigma: [n_nodes] in/out, receives
- * sigma^{k+1}.  u, v: [n_nodes] outputs (may be NULL). */
+ * sigma^{k+1}.  u, v: [n_nodes] outputs (may be NULL unless p->warm; with
+ * p->warm they are also inputs: the starting guess of the velocity, such as
+ * the last step's output). */
 S2D_API int ves_time_step(int64_t n_nodes, int32_t n_curves, const int32_t *curve_off,
                           double *x, double *y, double *sigma, const ves_step_params *p,
                           const double *A0, int reparam, double *u, double *v,

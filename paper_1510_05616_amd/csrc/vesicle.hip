@@ -1034,6 +1034,7 @@ int check_params(const ves_step_params *p) {
     }
     if (p->max_iter < 1) return ves_fail(S2D_EINVAL, "max_iter must be >= 1");
     if (!(p->tol >= 0.0)) return ves_fail(S2D_EINVAL, "tol must be >= 0");
+    if (p->warm != 0 && p->warm != 1) return ves_fail(S2D_EINVAL, "warm must be 0 or 1");
     return S2D_OK;
 }
 
@@ -1386,7 +1387,9 @@ constexpr int kMaxRefine = 30;
 // FP32C: iterative refinement; b and every residual b - A z in FP64, each
 // correction A dz = r solved by GMRES with FP32C sums to a relative
 // kInnerTol (or to what the tolerance still asks), z += dz.
-int gmres_run(StepCtx &C, double *z, int32_t *iters_out, double *res_out) {
+// The solve from z = 0, or (warm) from the z passed in: then GMRES works on
+// the residual r = b - A z (FP64) and adds its correction.
+int gmres_run(StepCtx &C, double *z, bool warm, int32_t *iters_out, double *res_out) {
     double *b = (double *)(C.ws + C.L.b), *r = (double *)(C.ws + C.L.r), *w = (double *)(C.ws + C.L.w);
     double *dz = (double *)(C.ws + C.L.dz);
     S2D_TRY(apply<true>(C, nullptr, b, S2D_FP64));
@@ -1395,13 +1398,31 @@ int gmres_run(StepCtx &C, double *z, int32_t *iters_out, double *res_out) {
     const double bnorm = std::sqrt(nb2);
     int iters = 0;
     double rel = 0.0;
-    if (C.p->mode == S2D_FP64) {
+    // the starting residual and its norm
+    double rnorm = bnorm;
+    if (warm) {
+        S2D_TRY(apply<false>(C, z, w, S2D_FP64));
+        S2D_TRY(axpby(C, 1.0, b, -1.0, w, r));
+        double rr2 = 0.0;
+        S2D_TRY(dots(C, 1, r, r, &rr2));
+        rnorm = std::sqrt(rr2);
+    }
+    if (C.p->mode == S2D_FP64 && !warm) {
         S2D_TRY(krylov(C, b, bnorm, z, C.p->tol, S2D_FP64, C.p->max_iter, iters, rel));
+    } else if (C.p->mode == S2D_FP64) {
+        rel = bnorm == 0.0 ? 0.0 : rnorm / bnorm;
+        if (bnorm > 0.0 && std::isfinite(rnorm) && rel > C.p->tol) {
+            double irel = 0.0;
+            S2D_TRY(krylov(C, r, rnorm, dz, C.p->tol * bnorm / rnorm, S2D_FP64, C.p->max_iter, iters, irel));
+            S2D_TRY(axpby(C, 1.0, z, 1.0, dz, z));
+            rel = irel * rnorm / bnorm;
+        }
     } else {
-        S2D_TRY(axpby(C, 0.0, b, 0.0, nullptr, z));
-        S2D_TRY(axpby(C, 1.0, b, 0.0, nullptr, r));
-        double rnorm = bnorm;
-        rel = bnorm == 0.0 ? 0.0 : 1.0;
+        if (!warm) {
+            S2D_TRY(axpby(C, 0.0, b, 0.0, nullptr, z));
+            S2D_TRY(axpby(C, 1.0, b, 0.0, nullptr, r));
+        }
+        rel = bnorm == 0.0 ? 0.0 : rnorm / bnorm;
         for (int o = 0; o < kMaxRefine && bnorm > 0.0 && std::isfinite(rnorm); ++o) {
             if (rel <= C.p->tol || iters >= C.p->max_iter) break;
             const double itol = std::max(C.p->tol * bnorm / rnorm, kInnerTol);
@@ -1429,13 +1450,14 @@ int gmres_run(StepCtx &C, double *z, int32_t *iters_out, double *res_out) {
 // the step system, right-preconditioned when asked
 int gmres(StepCtx &C, double *z, int32_t *iters_out, double *res_out) {
     C.pc = C.p->precond != 0;
-    if (!C.pc) return gmres_run(C, z, iters_out, res_out);
+    const bool warm = C.p->warm != 0;
+    if (!C.pc) return gmres_run(C, z, warm, iters_out, res_out);
     std::lock_guard<std::mutex> lk(blas_mutex());
     std::string err;
     C.h = (rocblas_handle)blas_handle(C.st, err);
     if (!C.h) return ves_fail(S2D_EHIP, err);
     S2D_TRY(pc_build(C));
-    return gmres_run(C, z, iters_out, res_out);
+    return gmres_run(C, z, warm, iters_out, res_out);
 }
 
 }  // namespace
@@ -1593,9 +1615,19 @@ S2D_API int ves_time_step(int64_t n_nodes, int32_t n_curves, const int32_t *curv
         if (rel_res) *rel_res = 0.0;
         return S2D_OK;
     }
+    if (p->warm && (!u || !v)) return ves_fail(S2D_EINVAL, "a warm start needs u and v (the previous velocity)");
     StepCtx C{};
     S2D_TRY(setup_ctx(C, n_nodes, n_curves, curve_off, x, y, p, ws, ws_bytes, stream));
     double *z = (double *)(C.ws + C.L.z);
+    if (p->warm) {
+        // the starting guess (u, v, sigma): the previous step's velocity and
+        // the current tension
+        const size_t nb = (size_t)n_nodes * sizeof(double);
+        hipError_t e = hipMemcpyAsync(z, u, nb, hipMemcpyDeviceToDevice, C.st);
+        if (e == hipSuccess) e = hipMemcpyAsync(z + n_nodes, v, nb, hipMemcpyDeviceToDevice, C.st);
+        if (e == hipSuccess) e = hipMemcpyAsync(z + 2 * n_nodes, sigma, nb, hipMemcpyDeviceToDevice, C.st);
+        if (e != hipSuccess) return hipf(e, "warm start copy");
+    }
     S2D_TRY(gmres(C, z, iters, rel_res));
     hipStream_t st = (hipStream_t)stream;
     hipLaunchKernelGGL(ves_update_kernel, dim3(g256(n_nodes)), dim3(256), 0, st, n_nodes, z, p->dt, x, y, sigma, u,

@@ -17,7 +17,7 @@ class StepParams(ctypes.Structure):
                 ("u_resp_y", ctypes.c_void_p), ("tol", ctypes.c_double), ("restart", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("precond", ctypes.c_int32), ("nmax", ctypes.c_int32),
                 ("near", ctypes.c_int32), ("near_P", ctypes.c_int32), ("near_band", ctypes.c_double),
-                ("near_max", ctypes.c_int32)]
+                ("near_max", ctypes.c_int32), ("warm", ctypes.c_int32)]
 
 
 def _bind():
@@ -57,19 +57,20 @@ def _bind():
 
 def params(mode=0, dt=1e-3, kappa_b=1.0, mu=1.0, d=0.0, img_lo=0, img_hi=0, L0=None, u_resp=None, tol=1e-12,
            restart=64, max_iter=2000, precond=None, nmax=0, near=0, near_P=8, near_band=5.0,
-           near_max=1 << 20) -> StepParams:
+           near_max=1 << 20, warm=0) -> StepParams:
     """L0: device float64 [n_curves] or None; u_resp: (ux, uy) device tensors
     or None; nmax: largest curve size; precond (default: when nmax is given)
     selects the block-diagonal preconditioner; near = 1 turns on the close
     evaluation between vesicles (near_P-times upsampled quadrature for the
     nodes within near_band spacings of another vesicle, at most near_max
-    such pairs).  The returned structure keeps the tensors it points to
-    alive."""
+    such pairs); warm = 1 starts GMRES from the given solution (the z of
+    step_solve, or the velocity uv and sigma of time_step).  The returned
+    structure keeps the tensors it points to alive."""
     ux, uy = (None, None) if u_resp is None else u_resp
     precond = nmax > 0 if precond is None else precond
     p = StepParams(int(mode), float(dt), float(kappa_b), float(mu), float(d), int(img_lo), int(img_hi),
                    _ptr(L0), _ptr(ux), _ptr(uy), float(tol), int(restart), int(max_iter), int(bool(precond)),
-                   int(nmax), int(near), int(near_P), float(near_band), int(near_max))
+                   int(nmax), int(near), int(near_P), float(near_band), int(near_max), int(bool(warm)))
     p._keep = (L0, ux, uy)
     return p
 

@@ -312,6 +312,45 @@ def test_time_steps_match_the_oracle(img, mode):
         assert res <= tol and ex < 1e-11 and es < 1e-7
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_warm_started_steps_match_the_oracle_in_fewer_iterations(mode):
+    """GMRES started from the previous step's velocity and the current
+    tension (warm = 1) reaches the same tolerance, so the steps still match
+    the oracle's dense solves, and needs fewer iterations than from zero."""
+    from oracle import vesicle as ov
+    from paper_1510_05616_amd import vesicle as pv
+    import torch
+    x, y, off = _set(sizes=(32, 32, 48), seed=4)
+    d = 4.0
+    g = ov.geometry(x, y, off)
+    L0, A0 = ov.arc_lengths(g), ov.areas(x, y, off)
+    f64 = dict(dtype=torch.float64, device="cuda")
+    tol = 1e-13 if mode == 0 else 1e-12
+    kw = dict(mode=mode, dt=0.005, kappa_b=1.0, mu=1.0, d=d, img_lo=-1, img_hi=1, L0=torch.as_tensor(L0, **f64),
+              tol=tol, restart=64, max_iter=4000, nmax=48)
+    cold, warm = pv.params(**kw), pv.params(warm=1, **kw)
+    A0d = torch.as_tensor(A0, **f64)
+    Vc, Vw = pv.Vesicles(x, y, off), pv.Vesicles(x, y, off)
+    n = Vw.n
+    uc, vc = torch.zeros(n, **f64), torch.zeros(n, **f64)
+    uw, vw = torch.zeros(n, **f64), torch.zeros(n, **f64)
+    xo, yo, so = x.copy(), y.copy(), np.zeros_like(x)
+    saved = 0
+    for k in range(4):
+        itc, rc = Vc.time_step(cold, A0=A0d, reparam=True, uv=(uc, vc))
+        itw, rw = Vw.time_step(warm, A0=A0d, reparam=True, uv=(uw, vw))
+        xo, yo, so, _, _ = ov.time_step(xo, yo, so, off, 0.005, 1.0, 1.0, L0=L0, A0=A0, d=d, img_lo=-1, img_hi=1)
+        torch.cuda.synchronize()
+        ex = max(_rel(_np(Vw.x), xo), _rel(_np(Vw.y), yo))
+        es = _rel(_np(Vw.sigma), so)
+        print(f"mode={mode} step {k}: cold {itc} iterations ({rc:.1e}), warm {itw} ({rw:.1e}), "
+              f"x {ex:.2e}, sigma {es:.2e}", flush=True)
+        assert rw <= tol and ex < 1e-11 and es < 1e-7
+        if k > 0:
+            saved += itc - itw
+    assert saved > 0
+
+
 def test_invalid_curves_and_empty_set():
     from paper_1510_05616_amd.vesicle import Vesicles
     import torch
