@@ -1387,11 +1387,11 @@ __device__ __forceinline__ int near_cell(float sf, float khf) {
 // correction is within the target's tolerance) or the quadrature; inside, no
 // correction, the network or the quadrature by the bin's calibrated bounds
 // (scaled by scale * F into velocity units) against the tolerance (the
-// target's curve's entry of curve_tol, else threshold).  A wave takes 64
-// targets, one per lane: the straight-line coefficients of both rules in
-// FP64, contracted with the density derivatives (only for targets that take
-// the learned route), then the network in two MFMA passes of 32 targets (a
-// pass only if one of its targets needs it), and
+// target's curve's entry of curve_tol, else threshold); the bins of |s| >=
+// 1/2 hold no network bound (near_calib_finish).  For a learned target the
+// feature kernel's head writes the straight-line part of both rules (FP64,
+// contracted with the density derivatives) to du, dv and the network's
+// record; near_net then adds the network's part, so that
 //   Delta = scale [t n_f] (sum_p Cflat_p d_p + exp(-2 pi b) sum_p dC_p d_p)
 // in FP64 (the double layer's flat part times sg).
 // The network's weights and biases staged in LDS once per workgroup.  Rows
