@@ -487,6 +487,37 @@ def test_auto_mixed_decisions_match_each_route(small):
     assert agree > 0.999, agree
 
 
+def test_auto_lists_beyond_one_scan_segment():
+    """300,000 targets: 1,172 compaction workgroups, more than the scan's
+    1,024 threads, so each scan thread sums two counts. Both lists must still
+    be complete and in order: fallback targets equal the upsampled route bit
+    for bit, learned ones the MLP route, the rest zero."""
+    import torch
+    from paper_1510_05616_amd import near
+    c, tx, ty, tc, dh = synth.make_near_dataset(300000, seed=29)
+    data = near.NearData(c, tx, ty, tc, mu=1.0, upsample=8)
+    assert (data.n + 255) // 256 > 1024
+    k = torch.arange(near.N_BINS * near.CELL, device="cuda") // near.CELL
+    bound = torch.where(k % 3 == 0, 1e-3, 10.0).float()
+    bound_zero = torch.where(k % 3 == 1, 1e-3, 10.0).float()
+    blob = _auto_blob(_rand_params(7), bound, bound_zero)
+    sF = (data.frame[:, 6] / (4 * math.pi) * data.frame[:, 7])
+    thr = 2e-3 * sF.max().item()
+    du, dv = (torch.empty(data.n, dtype=torch.float64, device="cuda") for _ in range(2))
+    fb = torch.full((data.n,), -1, dtype=torch.int32, device="cuda")
+    data.correct(near.S2D_NEAR_AUTO, blob, thr, du, dv, fb)
+    mu_, mv_ = torch.empty_like(du), torch.empty_like(dv)
+    data.correct(near.S2D_NEAR_MLP, blob, 0.0, mu_, mv_)
+    torch.cuda.synchronize()
+    counts = [int((fb == j).sum()) for j in range(3)]
+    print(f"network/fallback/none {counts}", flush=True)
+    assert min(counts) > 10000 and sum(counts) == data.n
+    f1, f0, f2 = fb == 1, fb == 0, fb == 2
+    assert torch.equal(du[f1], data.du[f1]) and torch.equal(dv[f1], data.dv[f1])
+    assert torch.equal(du[f0], mu_[f0]) and torch.equal(dv[f0], mv_[f0])
+    assert torch.all(du[f2] == 0) and torch.all(dv[f2] == 0)
+
+
 def test_auto_on_a_side_stream_sees_the_callers_prior_work(small):
     """AUTO forks work to a second stream of the device: it must wait for
     what the caller queued on its own stream just before the call (here the
